@@ -1,0 +1,304 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the phase-field step on one MI355X.
+
+Workload (default): 512^3 periodic unit cube, FP32 storage, 64 seeded drops (R in [0.03, 0.08]),
+a seeded divergence-free 16-mode Fourier velocity (synthesised on the GPU), eps = 0.75 dx,
+gamma = 1.1 max|u|, classic RK4. One "step" is one full RK4 step of the whole grid (four stage
+launches). Prints ONE JSON line with Gcell-updates/s, the stage kernel's achieved HBM bandwidth
+against the 8 TB/s peak, extra measurements (FP64, adjoint/forward cost, batched vs looped) and
+the FP64 CPU oracle's throughput on a bounded sample of the same recipe.
+
+  python bench.py [--steps 500] [--warmup 10] [--quick] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcell-updates/s & % HBM peak (fwd, adjoint, batched vs looped) at FP32/FP64 tol"
+HBM_PEAK_GBS = 8000.0
+WORDS_PER_CELL_STEP = 28  # algorithmic words per RK4 cell-update (see stage schedule)
+KERNEL_SOURCES = ("paper_1803_01262_amd/csrc/pf_tiled_body.h", "paper_1803_01262_amd/csrc/pf_cell.h",
+                  "paper_1803_01262_amd/csrc/stage_tiled.hip")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cuda_timer(st, fn, reps=1):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def setup_roofline(pf, fx, n, dtype, st, seed=3):
+    """Fields of the roofline workload on the GPU: phi from the seeded drops, faces from the
+    library's velocity synthesis; gamma and dt from the synthesised max face speed."""
+    import torch
+    c = fx.roofline512(n, seed=seed)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    phases, coeffs = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in c.modes)
+    p0 = pf.make_params((n, n, n), c.dx, c.eps, 1.0, 1.0, dtype=dtype)
+    u, v, w = pf.velocity_from_coeffs(p0, phases, coeffs, stream=st)
+    torch.cuda.synchronize()
+    umax = max(float(t.abs().max()) for t in (u, v, w))
+    fx.set_speed(c, umax)
+    phi = torch.tensor(c.phi0, dtype=tdt, device="cuda")
+    return c, phi, u, v, w
+
+
+def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, variant=-1):
+    import torch
+    n = c.shape[0]
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, variant=variant)
+    tuned = None
+    if autotune and variant < 0:
+        best, times = s.autotune(reps=3, stream=st)
+        tuned = {pf.phasefield_variant_name(0, k): round(t, 4) for k, t in enumerate(times)}
+    with torch.cuda.stream(st):
+        if warmup:
+            s.step(phi, u, v, w, nsteps=warmup, stream=st)
+        m0 = s.reduce(phi, stream=st)
+        ms = cuda_timer(st, lambda: s.step(phi, u, v, w, nsteps=steps, stream=st)) / steps
+        m1 = s.reduce(phi, stream=st)
+    name = pf.phasefield_variant_name(0, s.variant)
+    s.close()
+    return ms, name, tuned, m0, m1
+
+
+def adjoint_ratio(pf, fx, dtype, st, n=128, reps=10):
+    """Cost of one adjoint step (stage recompute + four reverse stages + velocity gradient) over
+    one forward step, on the adjoint workload (128^3, 8-mode field, delta = 1e-6/dx)."""
+    import torch
+    c = fx.adjoint_case(n)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    phases, coeffs = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in c.modes)
+    p0 = pf.make_params((n, n, n), c.dx, c.eps, 1.0, 1.0, dtype=dtype)
+    u, v, w = pf.velocity_from_coeffs(p0, phases, coeffs, stream=st)
+    torch.cuda.synchronize()
+    umax = max(float(t.abs().max()) for t in (u, v, w))
+    fx.set_speed(c, umax)
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, delta=c.delta)
+    phi = torch.tensor(c.phi0, dtype=tdt, device="cuda")
+    lam = torch.randn_like(phi)
+    gs = [torch.zeros_like(phi) for _ in range(3)]
+    with torch.cuda.stream(st):
+        s.step(phi, u, v, w, nsteps=8, stream=st)
+        fwd = cuda_timer(st, lambda: s.step(phi, u, v, w, nsteps=1, stream=st), reps)
+        s.adjoint_step(phi, u, v, w, 0.0, lam, *gs, stream=st)
+        adj = cuda_timer(st, lambda: s.adjoint_step(phi, u, v, w, 0.0, lam, *gs, stream=st), reps)
+    s.close()
+    return {"fwd_ms": round(fwd, 4), "adjoint_ms": round(adj, 4), "ratio": round(adj / fwd, 3),
+            "grid": n, "dtype": dtype}
+
+
+def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
+    """The batched driver against a loop of single solves (each its own handle, one stream,
+    no graphs), on the same uneven FP32 instances."""
+    import torch
+    cases = fx.batch_cases(count=count, nsteps=nsteps)
+    params, fields = [], []
+    for c in cases:
+        n = c.shape[0]
+        phases, coeffs = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in c.modes)
+        p0 = pf.make_params((n, n, n), c.dx, c.eps, 1.0, 1.0, dtype="f32")
+        u, v, w = pf.velocity_from_coeffs(p0, phases, coeffs, stream=st)
+        torch.cuda.synchronize()
+        fx.set_speed(c, max(float(t.abs().max()) for t in (u, v, w)))
+        params.append(pf.make_params((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype="f32"))
+        fields.append([torch.tensor(c.phi0, dtype=torch.float32, device="cuda"), u, v, w])
+    cells = sum(int(c.cells) for c in cases)
+    # batched
+    bs = pf.BatchSolver(params)
+    bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+    with torch.cuda.stream(st):
+        bs.step(*zip(*bf), nsteps=8, stream=st)
+        t_batch = cuda_timer(st, lambda: bs.step(*zip(*bf), nsteps=nsteps, stream=st))
+    bs.close()
+    # looped single solves, uncaptured
+    solvers = [pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype="f32", use_graph=False)
+               for p in params]
+    lf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+
+    def loop(steps):
+        for s, f in zip(solvers, lf):
+            s.step(*f, nsteps=steps, stream=st)
+
+    with torch.cuda.stream(st):
+        loop(2)
+        t_loop = cuda_timer(st, lambda: loop(nsteps))
+    # looped single solves, each replayed from its own captured graph
+    gsolvers = [pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype="f32", use_graph=True)
+                for p in params]
+    gf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+
+    def gloop(steps):
+        for s, f in zip(gsolvers, gf):
+            s.step(*f, nsteps=steps, stream=st)
+
+    with torch.cuda.stream(st):
+        gloop(8)
+        t_gloop = cuda_timer(st, lambda: gloop(nsteps))
+    for s in solvers + gsolvers:
+        s.close()
+    return {"instances": count, "cells": cells, "steps": nsteps,
+            "batched_ms": round(t_batch, 2), "looped_ms": round(t_loop, 2),
+            "looped_graph_ms": round(t_gloop, 2),
+            "batched_gcell_s": round(cells * nsteps / t_batch / 1e6, 2),
+            "looped_gcell_s": round(cells * nsteps / t_loop / 1e6, 2),
+            "speedup_vs_looped": round(t_loop / t_batch, 2),
+            "speedup_vs_looped_graph": round(t_gloop / t_batch, 2)}
+
+
+def cpu_baseline(fx, n=128, budget_s=12.0):
+    """The FP64 oracle (FP32-storage mode) on a 128^3 instance of the same recipe, timed on
+    the host cores: RK4 steps until about budget_s seconds have passed."""
+    import numpy as np
+
+    import oracle
+    c = fx.roofline512(n, seed=3)
+    U, V, W = fx.fourier_faces(c.shape, c.dx, *c.modes)
+    fx.set_speed(c, fx.max_face_speed(U, V, W))
+    U, V, W, phi = (a.astype(np.float32).astype(np.float64) for a in (U, V, W, c.phi0))
+    kw = dict(dx=c.dx, eps=c.eps, gamma=c.gamma, dt=c.dt, fp32=True)
+    phi = oracle.step(phi, U, V, W, nsteps=1, **kw)  # warm-up
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        phi = oracle.step(phi, U, V, W, nsteps=1, **kw)
+        steps += 1
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(c.cells * steps / el / 1e9, 5), "unit": "Gcell-updates/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"{n}^3 instance of the same recipe (64 drops, 16 modes, eps=0.75dx, "
+                      f"gamma=1.1max|u|), FP32-storage RK4, {steps} steps in {el:.1f} s"}
+
+
+def stored_traffic(khash: str):
+    f = os.path.join(ROOT, "profiles", "stage_traffic_roofline512_f32.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    if d.get("kernel_hash") != khash:
+        return None
+    return d
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the FP64/adjoint/batch extras")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="also run one plain device copy of BYTES bytes (hardware-counter "
+                         "calibration: its FETCH_SIZE/WRITE_SIZE should read BYTES each)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the method runs on one device here; multi-GPU slab "
+              "decomposition is a design note only. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1803_01262_amd as pf
+    import pf_fixtures as fx
+
+    st = torch.cuda.Stream()
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    n = args.n
+    esz = 4 if args.dtype == "f32" else 8
+    log(f"setup {n}^3 {args.dtype}")
+    c, phi, u, v, w = setup_roofline(pf, fx, n, args.dtype, st)
+    log("timing forward")
+    ms, vname, tuned, m0, m1 = time_forward(pf, c, phi, u, v, w, args.dtype, args.steps,
+                                            args.warmup, st, autotune=not args.no_autotune,
+                                            variant=args.variant)
+    cells = c.cells
+    value = cells / ms / 1e6  # Gcell-updates/s
+    achieved = WORDS_PER_CELL_STEP * esz * cells / ms / 1e6  # GB/s, = per-launch bytes / launch time
+    khash = kernel_hash()
+    tr = stored_traffic(khash)
+    launch_bytes = WORDS_PER_CELL_STEP * esz * cells / 4
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if tr is None else tr["bytes_per_launch"],
+            "algorithmic_bytes_per_launch": int(launch_bytes), "kernel": vname,
+            "kernel_hash": khash}
+    del phi, u, v, w
+    torch.cuda.empty_cache()
+    extras = {"tile_autotune_ms_per_step": tuned,
+              "mass_drift_timed_region": (m1[0] - m0[0]) / m0[0], "min": m1[1], "max": m1[2],
+              "eq17_margin": c.eps / c.dx - (c.gamma + c.extra["umax"]) / (2 * c.gamma)}
+    if not args.quick:
+        log("timing FP64")
+        other = "f64" if args.dtype == "f32" else "f32"
+        c2, phi2, u2, v2, w2 = setup_roofline(pf, fx, n, other, st)
+        ms2, vname2, _, _, _ = time_forward(pf, c2, phi2, u2, v2, w2, other, min(args.steps, 200),
+                                            5, st, autotune=not args.no_autotune)
+        e2 = 8 if other == "f64" else 4
+        extras[f"{other}_{n}"] = {"ms_per_step": round(ms2, 4),
+                                  "gcell_s": round(cells / ms2 / 1e6, 2),
+                                  "achieved_gbs": round(WORDS_PER_CELL_STEP * e2 * cells / ms2 / 1e6, 1),
+                                  "kernel": vname2}
+        del phi2, u2, v2, w2
+        torch.cuda.empty_cache()
+        log("timing adjoint")
+        extras["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st)
+        extras["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st)
+        log("timing batch vs loop")
+        extras["batch96_f32"] = batch_vs_loop(pf, fx, st)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing CPU oracle")
+        cpu = cpu_baseline(fx)
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": f"roofline{n}: {n}^3 periodic unit cube, {args.dtype} storage, "
+                                  "64 drops R~U[0.03,0.08], 16-mode solenoidal Fourier velocity "
+                                  "(unit RMS), eps=0.75dx, gamma=1.1max|u|, RK4",
+                      "grid": [n, n, n], "cells": cells, "eps_over_dx": 0.75,
+                      "gamma_over_umax": 1.1, "dt": c.dt, "parallelism": "single GPU"},
+           "roofline": roof, "cpu_baseline": cpu, "extras": extras}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

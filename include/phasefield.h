@@ -1,0 +1,204 @@
+/*
+ * phasefield.h — C ABI of the MI355X (gfx950) library for the conservative, bounded
+ * phase-field method of Mirjalili, Ivey & Mani (arXiv:1803.01262).
+ *
+ * What is computed (Sec. 1, Eq. 1):
+ *   d(phi)/dt + div(u phi) = div[ gamma ( eps grad(phi) - phi (1-phi) grad(phi)/|grad(phi)| ) ]
+ * discretised as in Sec. 2.2 (the five-step recipe): phi at cell centres, velocity on cell
+ * faces (a staggered MAC grid), unit normal and the sharpening product phi(1-phi)n at cell
+ * centres averaged onto faces, diffusive and advective face fluxes from second-order central
+ * differences, and the cell update as the divergence of the face fluxes. Time integration is
+ * forward Euler (Sec. 2.3, Eq. 25) or classic fourth-order Runge-Kutta (Eq. 28; the scheme of
+ * every experiment in Sec. 3).
+ *
+ * Data layout (every array): C-contiguous [nz][ny][nx], x fastest, periodic in every axis.
+ *   phi[k][j][i]  cell-centre phase field.
+ *   u[k][j][i]    x-velocity on the low x-face of cell (i,j,k)  (at x = i dx);
+ *   v, w          likewise on the low y- and z-faces.
+ * A two-dimensional problem is n[2] = 1 (with w = 0); one-dimensional is n[1] = n[2] = 1.
+ * The element type of phi, u, v, w, lam and the gradients is the handle's storage dtype
+ * (float for PF_F32, double for PF_F64). Arithmetic runs in the storage precision; mass sums
+ * are always accumulated in double.
+ *
+ * Pointers: unless stated otherwise every array argument is a DEVICE pointer on the current
+ * HIP device, at least 16-byte aligned, not aliasing any other argument, owned by the caller.
+ * The library never frees or retains caller memory beyond a call. Scratch (stage buffers,
+ * reduction partials, captured graphs) belongs to the handle and is released by destroy.
+ *
+ * Streams: hip_stream is a hipStream_t (NULL = the legacy default stream). Work is enqueued
+ * asynchronously on it unless a function says it synchronises. A handle serves one stream at a
+ * time; calls on one handle from several host threads must be serialised by the caller.
+ *
+ * Errors: every function returns pf_status; none aborts. On failure nothing has been enqueued
+ * (argument errors) or the HIP error is reported as PF_ERR_DEVICE; phasefield_last_error()
+ * then describes it. Leaving the paper's bounded regime (Eq. 17) or exceeding the scheme's
+ * step limit (Eqs. 25, 28) is NOT an error — the paper runs such cases on purpose (Sec. 2.2.1,
+ * Table 2); phasefield_check_params reports the margins.
+ */
+#ifndef PHASEFIELD_H
+#define PHASEFIELD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PF_OK = 0,
+    PF_ERR_INVALID = 1,     /* bad argument: size, spacing, parameter, null/misaligned pointer */
+    PF_ERR_UNSUPPORTED = 2, /* valid request this build does not provide (e.g. a wall BC)     */
+    PF_ERR_DEVICE = 3,      /* a HIP call failed                                              */
+    PF_ERR_OOM = 4,         /* device allocation failed                                       */
+    PF_ERR_NONFINITE = 5    /* phasefield_reduce found NaN or Inf                             */
+} pf_status;
+
+typedef enum { PF_F32 = 0, PF_F64 = 1 } pf_dtype;             /* storage precision      */
+typedef enum { PF_BC_PERIODIC = 0, PF_BC_WALL = 1 } pf_bc;      /* WALL: unsupported      */
+typedef enum { PF_EULER = 1, PF_RK4 = 4 } pf_scheme;
+typedef enum { PF_VEL_STEADY = 0, PF_VEL_COS_REVERSAL = 1 } pf_velmode;
+
+/* Problem statement of one simulation (Sec. 2.2: uniform isotropic mesh dx; eps and gamma
+ * the interface thickness and sharpening speed of Eq. 1; dt the explicit step). */
+typedef struct {
+    int32_t n[3];       /* cells along x, y, z; each >= 1                                     */
+    double dx;          /* mesh spacing (> 0)                                                  */
+    double eps;         /* interface thickness parameter epsilon (>= 0)                        */
+    double gamma;       /* sharpening velocity scale gamma (>= 0)                              */
+    double dt;          /* time step (> 0)                                                     */
+    double delta;       /* |grad phi| regulariser: n = g / sqrt(|g|^2 + delta^2); 0 gives the  */
+                        /* plain unit normal with n = 0 where g = 0                            */
+    int32_t bc[3];      /* pf_bc per axis; only PF_BC_PERIODIC is provided                     */
+    int32_t dtype;      /* pf_dtype                                                            */
+    int32_t scheme;     /* pf_scheme                                                           */
+    int32_t vel_mode;   /* pf_velmode: velocity u0(x) * s(t), s = 1 or cos(pi t / vel_T)       */
+    double vel_T;       /* reversal period for PF_VEL_COS_REVERSAL (> 0)                       */
+    int32_t variant;    /* stage-kernel variant: -1 = automatic (tuned), else an index below   */
+                        /* phasefield_variant_count(); every variant gives identical results   */
+    int32_t use_graph;  /* 1: replay steps from a captured HIP graph where possible; 0: launch  */
+} pf_params;
+
+/* Fill p with defaults: periodic, FP64, RK4, steady velocity, variant -1, graphs on,
+ * delta 0. The caller then sets n, dx, eps, gamma and dt. */
+void phasefield_default_params(pf_params *p);
+
+/* Criteria of the paper for a parameter set (no device work). max_face_speed is the largest
+ * |component| over the face arrays (times max|s(t)|).
+ *   crossover_margin_eq17: eps/dx - (gamma/U + 1)/(2 gamma/U), U = max_face_speed (Eq. 17);
+ *                          >= 0 is the bounded regime proven in Sec. 2.2.
+ *   crossover_margin_eq24: the same with the relaxed line of Eqs. 23-24 (identical here,
+ *                          because the face speed is already the largest component).
+ *   dt_max_scheme:         Eq. 25 (Euler) or Eq. 28 (RK4) with D_f = axes longer than 1 cell.
+ *   dt_over_dtmax:         dt / dt_max_scheme. */
+typedef struct {
+    double crossover_margin_eq17;
+    double crossover_margin_eq24;
+    double dt_max_scheme;
+    double dt_over_dtmax;
+} pf_report;
+pf_status phasefield_check_params(const pf_params *p, double max_face_speed, pf_report *out);
+
+typedef struct pf_solver pf_solver;
+
+/* Validate p and allocate the handle with its device scratch (three field-sized stage
+ * buffers). Errors: PF_ERR_INVALID (n < 1, dx <= 0, eps < 0, gamma < 0, dt <= 0, delta < 0,
+ * bad enum, vel_T <= 0 in cos mode, variant out of range), PF_ERR_UNSUPPORTED (wall BC),
+ * PF_ERR_OOM, PF_ERR_DEVICE. *out is NULL on failure. */
+pf_status phasefield_create(const pf_params *p, pf_solver **out);
+
+/* Release the handle and all its device memory (NULL is accepted). Synchronises the device
+ * work the handle enqueued. */
+pf_status phasefield_destroy(pf_solver *s);
+
+/* Advance phi IN PLACE by nsteps steps of the handle's scheme (Sec. 2.3), starting at time
+ * t0; step m runs from t0 + m dt. u, v, w: face velocity u0 (the time factor s(t) is applied
+ * by the library at the RK4 stage times t, t+dt/2, t+dt/2, t+dt). nsteps = 0 is a no-op.
+ * Errors: PF_ERR_INVALID (null/misaligned pointer, nsteps < 0), PF_ERR_DEVICE. */
+pf_status phasefield_step(pf_solver *s, void *phi, const void *u, const void *v, const void *w,
+                          double t0, int32_t nsteps, void *hip_stream);
+
+/* Discrete adjoint of ONE step (the transpose of the derivative of phasefield_step with
+ * nsteps = 1, taken at phi_n and time t_n). On entry lam = dL/dphi_{n+1}; on exit
+ * lam = dL/dphi_n (in place). gu, gv, gw (may each be NULL to skip) ACCUMULATE
+ * dL/du0 etc. (+=). The stage inputs of the forward step are recomputed from phi_n.
+ * Allocates five more field-sized scratch buffers on first use.
+ * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_OOM, PF_ERR_DEVICE. */
+pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
+                                  const void *w, double t_n, void *lam, void *gu, void *gv,
+                                  void *gw, void *hip_stream);
+
+/* Mass and bounds of a field: out4 = {sum(phi) * dx^D, min(phi), max(phi), #non-finite},
+ * D = number of axes longer than one cell; the sum is accumulated in double in a fixed order
+ * (deterministic). Non-finite cells are left out of sum, min and max. SYNCHRONISES
+ * hip_stream. out4 is a HOST pointer. Returns PF_ERR_NONFINITE (with out4 filled) if any cell
+ * is NaN or Inf. */
+pf_status phasefield_reduce(pf_solver *s, const void *phi, double out4[4], void *hip_stream);
+
+/* Face velocity as the discrete curl of an edge vector potential built from separable
+ * Fourier modes (the face field is then discretely divergence-free, as Eq. 19 requires):
+ *   A_a(x) = sum_{m1,m2,m3=1..M} coeffs[m3-1][m2-1][m1-1][a]
+ *            sin(2 pi m1 x/Lx + phases[0][m1-1]) sin(2 pi m2 y/Ly + phases[1][m2-1])
+ *            sin(2 pi m3 z/Lz + phases[2][m3-1]),   L = n dx,
+ * with A_x on x-edges ((i+1/2) dx, j dx, k dx), A_y on y-edges (i dx, (j+1/2) dx, k dx) and
+ * A_z on z-edges (i dx, j dx, (k+1/2) dx); u = (A_z[j+1]-A_z[j] - A_y[k+1]+A_y[k]) / dx and
+ * cyclically. p supplies n, dx and dtype. phases (double[3][M]) and coeffs (double[M][M][M][3])
+ * are device pointers; u, v, w are written in the storage dtype (computed in double).
+ * Errors: PF_ERR_INVALID (M < 1 or M > 64, null pointer), PF_ERR_OOM, PF_ERR_DEVICE. */
+pf_status phasefield_velocity_from_coeffs(const pf_params *p, int32_t modes, const double *phases,
+                                          const double *coeffs, void *u, void *v, void *w,
+                                          void *hip_stream);
+
+/* Transpose of phasefield_velocity_from_coeffs: coeff_grad (double[M][M][M][3], device)
+ * ACCUMULATES d<(u,v,w),(gu,gv,gw)>/d coeffs (+=). gu, gv, gw in the storage dtype. Projects
+ * a face-velocity gradient (from phasefield_adjoint_step) onto the mode coefficients. */
+pf_status phasefield_velocity_coeffs_grad(const pf_params *p, int32_t modes,
+                                          const double *phases, const void *gu, const void *gv,
+                                          const void *gw, double *coeff_grad, void *hip_stream);
+
+/* Number of compiled stage-kernel variants (tile shapes) for a storage dtype. */
+int32_t phasefield_variant_count(int32_t dtype);
+
+/* Short name of a variant (static string), or NULL if out of range. */
+const char *phasefield_variant_name(int32_t dtype, int32_t variant);
+
+/* Time every variant on the handle's grid (using the handle's scratch only; caller data is
+ * untouched), store the fastest as the handle's variant and return it in *best; times_ms
+ * (HOST, may be NULL) receives phasefield_variant_count(dtype) per-step times. Synchronises.
+ * The choice is cached per (dtype, grid shape) for the life of the process. */
+pf_status phasefield_autotune(pf_solver *s, int32_t reps, int32_t *best, double *times_ms,
+                              void *hip_stream);
+
+/* The variant a handle runs. */
+int32_t phasefield_solver_variant(const pf_solver *s);
+
+/* ----------------------------------------------------------------------------------------
+ * Batched driver: many independent simulations (each its own pf_params, uneven grid sizes,
+ * same dtype and scheme) advanced together. Each RK stage is ONE launch over a global tile
+ * list that covers every instance; the step sequence is replayed from a captured HIP graph.
+ * Results are bit-identical to running each instance alone with phasefield_step.
+ * ------------------------------------------------------------------------------------- */
+typedef struct pf_batch pf_batch;
+
+/* per_instance: HOST array of count parameter sets (all with the same dtype and scheme).
+ * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtype/scheme), PF_ERR_OOM,
+ * PF_ERR_DEVICE. */
+pf_status phasefield_batch_create(const pf_params *per_instance, int32_t count, pf_batch **out);
+
+/* Advance every instance b by nsteps steps: phi[b], u[b], v[b], w[b] are HOST arrays of count
+ * device pointers; t0 is a HOST array of count start times (NULL = all zero). The pointer set
+ * may change between calls (a changed set is re-captured). */
+pf_status phasefield_batch_step(pf_batch *b, void *const *phi, const void *const *u,
+                                const void *const *v, const void *const *w, const double *t0,
+                                int32_t nsteps, void *hip_stream);
+
+pf_status phasefield_batch_destroy(pf_batch *b);
+
+/* Description of the last error on the calling thread (empty string if none); valid until
+ * the next library call on that thread. */
+const char *phasefield_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHASEFIELD_H */

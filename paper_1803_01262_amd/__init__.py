@@ -1,0 +1,197 @@
+"""MI355X (gfx950) library for the conservative, bounded phase-field method of
+Mirjalili, Ivey & Mani (arXiv:1803.01262): the explicit flux-form step of Eq. 1 on a staggered
+grid (Sec. 2.2), its discrete adjoint, a batched multi-instance driver and velocity synthesis.
+
+Everything runs in libphasefield.so (hand-written HIP kernels, C ABI in include/phasefield.h);
+this package marshals torch tensors to it. Importing the package fails if the library has not
+been built — there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from ._capi import (EXPORTED, PF_BC_PERIODIC, PF_BC_WALL, PF_ERR_DEVICE, PF_ERR_INVALID,  # noqa: F401
+                    PF_ERR_NONFINITE, PF_ERR_OOM, PF_ERR_UNSUPPORTED, PF_EULER, PF_F32, PF_F64,
+                    PF_OK, PF_RK4, PF_VEL_COS_REVERSAL, PF_VEL_STEADY, LIB_PATH, Params,
+                    PhaseFieldError, Report, cells, lib, make_params, phasefield_adjoint_step,
+                    phasefield_autotune, phasefield_batch_create, phasefield_batch_destroy,
+                    phasefield_batch_step, phasefield_check_params, phasefield_create,
+                    phasefield_default_params, phasefield_destroy, phasefield_last_error,
+                    phasefield_reduce, phasefield_solver_variant, phasefield_step,
+                    phasefield_variant_count, phasefield_variant_name,
+                    phasefield_velocity_coeffs_grad, phasefield_velocity_from_coeffs)
+
+TORCH_DTYPE = {PF_F32: torch.float32, PF_F64: torch.float64}
+
+
+class Solver:
+    """One simulation handle: grid, eps, gamma, dt, scheme, storage dtype (pf_params)."""
+
+    def __init__(self, n, dx, eps, gamma, dt, **kw):
+        self.params = make_params(n, dx, eps, gamma, dt, **kw)
+        self.handle = phasefield_create(self.params)
+
+    @property
+    def shape(self):
+        p = self.params
+        return (int(p.n[2]), int(p.n[1]), int(p.n[0]))
+
+    @property
+    def dtype(self) -> torch.dtype:
+        return TORCH_DTYPE[self.params.dtype]
+
+    @property
+    def dt(self) -> float:
+        return float(self.params.dt)
+
+    @property
+    def variant(self) -> int:
+        return phasefield_solver_variant(self.handle)
+
+    def step(self, phi, u, v, w, t0=0.0, nsteps=1, stream=None):
+        """Advance phi in place by nsteps steps from time t0."""
+        phasefield_step(self.handle, self.params, phi, u, v, w, t0, nsteps, stream)
+        return phi
+
+    def adjoint_step(self, phi_n, u, v, w, t_n, lam, gu=None, gv=None, gw=None, stream=None):
+        """lam <- dL/dphi_n given lam = dL/dphi_{n+1}; gu/gv/gw accumulate dL/du0 (in place)."""
+        phasefield_adjoint_step(self.handle, self.params, phi_n, u, v, w, t_n, lam, gu, gv, gw,
+                                stream)
+        return lam
+
+    def reduce(self, phi, stream=None):
+        """(mass, min, max, #non-finite); synchronises the stream."""
+        return phasefield_reduce(self.handle, self.params, phi, stream)
+
+    def autotune(self, reps=5, stream=None):
+        return phasefield_autotune(self.handle, reps, stream)
+
+    def report(self, max_face_speed: float) -> Report:
+        return phasefield_check_params(self.params, max_face_speed)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            phasefield_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Many independent RK4 simulations (uneven grids, one storage dtype, steady velocity)
+    advanced together: one persistent launch per stage, graph-replayed steps."""
+
+    def __init__(self, params_list):
+        self.params = list(params_list)
+        self.handle = phasefield_batch_create(self.params)
+
+    def step(self, phis, us, vs, ws, nsteps=1, t0s=None, stream=None):
+        phasefield_batch_step(self.handle, self.params, phis, us, vs, ws, t0s, nsteps, stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            phasefield_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def velocity_from_coeffs(params: Params, phases, coeffs, stream=None):
+    """Face velocity (u, v, w) of the separable-mode potential (phases (3, M), coeffs
+    (M, M, M, 3), float64 GPU tensors), in the storage dtype of params."""
+    M = int(phases.shape[1])
+    shape = (int(params.n[2]), int(params.n[1]), int(params.n[0]))
+    dt = TORCH_DTYPE[params.dtype]
+    u, v, w = (torch.empty(shape, dtype=dt, device=phases.device) for _ in range(3))
+    phasefield_velocity_from_coeffs(params, M, phases.contiguous(), coeffs.contiguous(), u, v, w,
+                                    stream)
+    return u, v, w
+
+
+def velocity_coeffs_grad(params: Params, phases, gu, gv, gw, stream=None):
+    """Gradient with respect to the mode coefficients of <(u, v, w), (gu, gv, gw)>."""
+    M = int(phases.shape[1])
+    cg = torch.zeros((M, M, M, 3), dtype=torch.float64, device=phases.device)
+    phasefield_velocity_coeffs_grad(params, M, phases.contiguous(), gu, gv, gw, cg, stream)
+    return cg
+
+
+class Rollout(torch.autograd.Function):
+    """phi_T = (nsteps steps of the solver)(phi_0) in the velocity synthesised from coeffs.
+
+    Backward: discrete adjoint with checkpoints every ``ckpt`` steps. Each segment is
+    recomputed from its checkpoint (states held on the GPU), then swept backwards with
+    phasefield_adjoint_step; the accumulated face-velocity gradient is projected onto the mode
+    coefficients once. Returns gradients for phi_0 and coeffs.
+
+    Usage: Rollout.apply(phi0, coeffs, solver, phases, nsteps, ckpt, t0)
+    """
+
+    @staticmethod
+    def forward(ctx, phi0, coeffs, solver: Solver, phases, nsteps: int, ckpt: int = 20,
+                t0: float = 0.0):
+        p = solver.params
+        u, v, w = velocity_from_coeffs(p, phases, coeffs.detach().to(torch.float64))
+        phi = phi0.detach().clone().contiguous()
+        single = p.vel_mode != PF_VEL_STEADY  # time-varying: one call per step, t = t0 + n dt
+        ckpts = []
+        n = 0
+        while n < nsteps:
+            ckpts.append(phi.clone())
+            m = min(ckpt, nsteps - n)
+            _advance(solver, phi, u, v, w, t0, n, m, single)
+            n += m
+        ctx.solver, ctx.phases, ctx.nsteps, ctx.ckpt, ctx.t0 = solver, phases, nsteps, ckpt, t0
+        ctx.ckpts = ckpts
+        ctx.vel = (u, v, w)
+        return phi
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        solver, nsteps, ckpt, t0 = ctx.solver, ctx.nsteps, ctx.ckpt, ctx.t0
+        p = solver.params
+        u, v, w = ctx.vel
+        dt = solver.dt
+        single = p.vel_mode != PF_VEL_STEADY
+        lam = grad_out.detach().to(solver.dtype).contiguous().clone()
+        gu, gv, gw = (torch.zeros_like(u) for _ in range(3))
+        nseg = len(ctx.ckpts)
+        for s in reversed(range(nseg)):
+            n0 = s * ckpt
+            m = min(ckpt, nsteps - n0)
+            states = [ctx.ckpts[s]]
+            phi = ctx.ckpts[s].clone()
+            for j in range(m - 1):
+                _advance(solver, phi, u, v, w, t0, n0 + j, 1, single)
+                states.append(phi.clone())
+            for j in reversed(range(m)):
+                solver.adjoint_step(states[j], u, v, w, t0 + (n0 + j) * dt, lam, gu, gv, gw)
+        cg = velocity_coeffs_grad(p, ctx.phases, gu, gv, gw)
+        ctx.ckpts = None
+        return lam, cg, None, None, None, None, None
+
+
+def _advance(solver, phi, u, v, w, t0, n0, m, single):
+    """m steps from step index n0 (time t0 + n0 dt)."""
+    dt = solver.dt
+    if single:
+        for j in range(m):
+            solver.step(phi, u, v, w, t0 + (n0 + j) * dt, 1)
+    else:
+        solver.step(phi, u, v, w, t0 + n0 * dt, m)
+
+
+def rk4_dt_limit(dims: int, dx: float, gamma: float, eps: float) -> float:
+    """Eq. 28: 2.79 dx^2 / (4 D_f gamma eps)."""
+    return 2.79 * dx * dx / (4.0 * dims * gamma * eps) if gamma * eps > 0 else math.inf

@@ -1,0 +1,481 @@
+// C ABI of the phase-field library: handles, validation, stage schedules, graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "pf_api_internal.h"
+
+using namespace pf;
+
+// ------------------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+pf_status pf::fail(pf_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+pf_status pf::hip_fail(hipError_t e, const char* what)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(PF_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
+    return fail(PF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* phasefield_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------------------ params
+extern "C" void phasefield_default_params(pf_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->n[0] = p->n[1] = p->n[2] = 1;
+    p->dx = 1.0;
+    p->bc[0] = p->bc[1] = p->bc[2] = PF_BC_PERIODIC;
+    p->dtype = PF_F64;
+    p->scheme = PF_RK4;
+    p->vel_mode = PF_VEL_STEADY;
+    p->vel_T = 1.0;
+    p->variant = -1;
+    p->use_graph = 1;
+}
+
+pf_status pf::validate_params(const pf_params* p)
+{
+    if (!p) return fail(PF_ERR_INVALID, "params is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (p->n[a] < 1 || p->n[a] > (1 << 20))
+            return fail(PF_ERR_INVALID, "n[%d] = %d out of range [1, 2^20]", a, p->n[a]);
+        if (p->bc[a] == PF_BC_WALL)
+            return fail(PF_ERR_UNSUPPORTED, "wall boundary (axis %d) is not provided", a);
+        if (p->bc[a] != PF_BC_PERIODIC) return fail(PF_ERR_INVALID, "bc[%d] = %d", a, p->bc[a]);
+    }
+    const double cells = (double)p->n[0] * p->n[1] * p->n[2];
+    if (cells > 4.0e9) return fail(PF_ERR_INVALID, "grid of %.3g cells is too large", cells);
+    if (p->n[2] > 65535 || p->n[1] > 65535)
+        return fail(PF_ERR_INVALID, "n[1] and n[2] must be <= 65535");
+    if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(PF_ERR_INVALID, "dx must be > 0");
+    if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return fail(PF_ERR_INVALID, "eps must be >= 0");
+    if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma))
+        return fail(PF_ERR_INVALID, "gamma must be >= 0");
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(PF_ERR_INVALID, "dt must be > 0");
+    if (!(p->delta >= 0.0) || !std::isfinite(p->delta))
+        return fail(PF_ERR_INVALID, "delta must be >= 0");
+    if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_ERR_INVALID, "dtype = %d", p->dtype);
+    if (p->scheme != PF_EULER && p->scheme != PF_RK4)
+        return fail(PF_ERR_INVALID, "scheme = %d", p->scheme);
+    if (p->vel_mode != PF_VEL_STEADY && p->vel_mode != PF_VEL_COS_REVERSAL)
+        return fail(PF_ERR_INVALID, "vel_mode = %d", p->vel_mode);
+    if (p->vel_mode == PF_VEL_COS_REVERSAL && !(p->vel_T > 0.0))
+        return fail(PF_ERR_INVALID, "vel_T must be > 0 with the cos reversal");
+    if (p->variant < -1 || p->variant >= stage_variant_count())
+        return fail(PF_ERR_INVALID, "variant %d out of range", p->variant);
+    return PF_OK;
+}
+
+static int active_dims(const int32_t n[3])
+{
+    const int d = (n[0] > 1) + (n[1] > 1) + (n[2] > 1);
+    return d > 0 ? d : 1;
+}
+
+extern "C" pf_status phasefield_check_params(const pf_params* p, double max_face_speed,
+                                             pf_report* out)
+{
+    pf_status st = validate_params(p);
+    if (st != PF_OK) return st;
+    if (!out) return fail(PF_ERR_INVALID, "out is NULL");
+    if (!(max_face_speed >= 0.0)) return fail(PF_ERR_INVALID, "max_face_speed must be >= 0");
+    // Eq. 17: eps/dx >= (gamma/U + 1) / (2 gamma/U) = (gamma + U) / (2 gamma)
+    double thr;
+    if (p->gamma > 0.0)
+        thr = (p->gamma + max_face_speed) / (2.0 * p->gamma);
+    else
+        thr = max_face_speed > 0.0 ? INFINITY : 0.5;
+    out->crossover_margin_eq17 = p->eps / p->dx - thr;
+    out->crossover_margin_eq24 = out->crossover_margin_eq17;
+    const int D = active_dims(p->n);
+    const double ge = p->gamma * p->eps;
+    const double base = ge > 0.0 ? p->dx * p->dx / ge : INFINITY;
+    out->dt_max_scheme = p->scheme == PF_EULER ? base / (2.0 * D) : 2.79 * base / (4.0 * D);
+    out->dt_over_dtmax = p->dt / out->dt_max_scheme;
+    return PF_OK;
+}
+
+// ------------------------------------------------------------------------------ tuning cache
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int>, int> g_tuned;
+
+int pf::tuned_variant(int dtype, const int32_t n[3])
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(dtype, n[0], n[1], n[2]));
+    if (it != g_tuned.end()) return it->second;
+    return default_stage_variant(n[0], n[1], n[2], dtype);
+}
+
+static void store_tuned(int dtype, const int32_t n[3], int v)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(dtype, n[0], n[1], n[2])] = v;
+}
+
+extern "C" int32_t phasefield_variant_count(int32_t dtype)
+{
+    (void)dtype;
+    return stage_variant_count();
+}
+
+extern "C" const char* phasefield_variant_name(int32_t dtype, int32_t v)
+{
+    (void)dtype;
+    if (v < 0 || v >= stage_variant_count()) return nullptr;
+    return stage_variant(v).name;
+}
+
+// ------------------------------------------------------------------------------ solver
+static void free_dev(void*& ptr)
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+}
+
+void pf::release_graph(StepGraph& g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = StepGraph{};
+}
+
+extern "C" pf_status phasefield_create(const pf_params* p, pf_solver** out)
+{
+    if (!out) return fail(PF_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    pf_status st = validate_params(p);
+    if (st != PF_OK) return st;
+    auto* s = new pf_solver();
+    s->p = *p;
+    s->N = (size_t)p->n[0] * p->n[1] * p->n[2];
+    s->esz = p->dtype == PF_F32 ? sizeof(float) : sizeof(double);
+    s->variant = p->variant >= 0 ? p->variant : tuned_variant(p->dtype, p->n);
+    hipError_t e = hipSuccess;
+    for (void** b : {&s->ya, &s->yb, &s->acc}) {
+        e = hipMalloc(b, s->N * s->esz);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&s->red_part, sizeof(double) * 4 * kReduceBlocks);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->red_out, sizeof(double) * 4);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->red_host, sizeof(double) * 4);
+    if (e != hipSuccess) {
+        phasefield_destroy(s);
+        return hip_fail(e, "phasefield_create: allocation");
+    }
+    *out = s;
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_destroy(pf_solver* s)
+{
+    if (!s) return PF_OK;
+    (void)hipDeviceSynchronize();
+    release_graph(s->graph);
+    for (void** b : {&s->ya, &s->yb, &s->acc}) free_dev(*b);
+    for (auto& b : s->adj) free_dev(b);
+    void* rp = s->red_part;
+    void* ro = s->red_out;
+    free_dev(rp);
+    free_dev(ro);
+    if (s->red_host) (void)hipHostFree(s->red_host);
+    free_dev(s->vel_scratch);
+    delete s;
+    return PF_OK;
+}
+
+extern "C" int32_t phasefield_solver_variant(const pf_solver* s) { return s ? s->variant : -1; }
+
+pf_status pf::check_field_ptr(const void* ptr, const char* name)
+{
+    if (!ptr) return fail(PF_ERR_INVALID, "%s is NULL", name);
+    if (((uintptr_t)ptr) & 15) return fail(PF_ERR_INVALID, "%s is not 16-byte aligned", name);
+    return PF_OK;
+}
+
+double pf::time_factor(const pf_params& p, double t)
+{
+    return p.vel_mode == PF_VEL_COS_REVERSAL ? std::cos(M_PI * t / p.vel_T) : 1.0;
+}
+
+template <typename T>
+StageArgs<T> pf::make_stage(const pf_params& p, double svel, const T* y, const T* base1,
+                            const T* base2, T* out1, T* out2, double c1, double c2, const T* U,
+                            const T* V, const T* W)
+{
+    StageArgs<T> a;
+    a.y = y;
+    a.base1 = base1;
+    a.base2 = base2;
+    a.out1 = out1;
+    a.out2 = out2;
+    a.U = U;
+    a.V = V;
+    a.W = W;
+    a.nx = p.n[0];
+    a.ny = p.n[1];
+    a.nz = p.n[2];
+    a.inv_dx = (T)(1.0 / p.dx);
+    a.inv_2dx = (T)(1.0 / (2.0 * p.dx));
+    a.ge = (T)(p.gamma * p.eps / p.dx);
+    a.hg = (T)(0.5 * p.gamma);
+    a.hs = (T)(0.5 * svel);
+    a.delta2 = (T)(p.delta * p.delta);
+    a.c1 = (T)c1;
+    a.c2 = (T)c2;
+    return a;
+}
+template StageArgs<float> pf::make_stage<float>(const pf_params&, double, const float*,
+                                                const float*, const float*, float*, float*,
+                                                double, double, const float*, const float*,
+                                                const float*);
+template StageArgs<double> pf::make_stage<double>(const pf_params&, double, const double*,
+                                                  const double*, const double*, double*,
+                                                  double*, double, double, const double*,
+                                                  const double*, const double*);
+
+template <typename T>
+static hipError_t run_stage(int variant, const StageArgs<T>& a, hipStream_t st)
+{
+    const StageVariant& v = stage_variant(variant);
+    if constexpr (sizeof(T) == 4)
+        return v.launch_f32(a, st);
+    else
+        return v.launch_f64(a, st);
+}
+
+// One explicit step from time t on the given buffers (phi updated in place).
+//   RK4 (classic; Sec. 2.3, Eq. 28), fixed buffers, no pointer swaps:
+//     S1: ya = phi + dt/2 k1,  acc = phi + dt/6 k1          (k1 = f(phi, t))
+//     S2: yb = phi + dt/2 k2,  acc += dt/3 k2               (k2 = f(ya, t + dt/2))
+//     S3: ya = phi + dt k3,    acc += dt/3 k3               (k3 = f(yb, t + dt/2))
+//     S4: phi = acc + dt/6 k4                               (k4 = f(ya, t + dt))
+//   Euler (Eq. 25): acc = phi + dt f(phi, t); phi = acc.
+// S4 writes phi in place: it reads phi nowhere (its stencil input is ya, acc is read only at
+// the cell being written).
+template <typename T>
+hipError_t pf::enqueue_step(const pf_params& p, int variant, T* phi, const T* U, const T* V,
+                            const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st)
+{
+    const double dt = p.dt;
+    hipError_t e;
+    if (p.scheme == PF_EULER) {
+        e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, nullptr, phi, nullptr,
+                                                acc, 0.0, dt, U, V, W), st);
+        if (e != hipSuccess) return e;
+        return launch_copy<T>(phi, acc, (size_t)p.n[0] * p.n[1] * p.n[2], st);
+    }
+    const double sh = time_factor(p, t + 0.5 * dt);
+    e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, phi, ya, acc,
+                                            0.5 * dt, dt / 6.0, U, V, W), st);
+    if (e != hipSuccess) return e;
+    e = run_stage<T>(variant, make_stage<T>(p, sh, ya, phi, acc, yb, acc, 0.5 * dt, dt / 3.0, U,
+                                            V, W), st);
+    if (e != hipSuccess) return e;
+    e = run_stage<T>(variant, make_stage<T>(p, sh, yb, phi, acc, ya, acc, dt, dt / 3.0, U, V, W),
+                     st);
+    if (e != hipSuccess) return e;
+    return run_stage<T>(variant, make_stage<T>(p, time_factor(p, t + dt), ya, nullptr, acc,
+                                               nullptr, phi, 0.0, dt / 6.0, U, V, W), st);
+}
+template hipError_t pf::enqueue_step<float>(const pf_params&, int, float*, const float*,
+                                            const float*, const float*, float*, float*, float*,
+                                            double, hipStream_t);
+template hipError_t pf::enqueue_step<double>(const pf_params&, int, double*, const double*,
+                                             const double*, const double*, double*, double*,
+                                             double*, double, hipStream_t);
+
+template <typename T>
+static pf_status step_impl(pf_solver* s, T* phi, const T* U, const T* V, const T* W, double t0,
+                           int32_t nsteps, hipStream_t st)
+{
+    const pf_params& p = s->p;
+    T* ya = (T*)s->ya;
+    T* yb = (T*)s->yb;
+    T* acc = (T*)s->acc;
+    // Steady velocity: every step is the same launch sequence, replayed from a captured graph
+    // of kGraphSteps steps (capture is not possible on the legacy NULL stream).
+    const bool graphable = p.use_graph && p.vel_mode == PF_VEL_STEADY && st != nullptr;
+    int32_t done = 0;
+    if (graphable && nsteps >= kGraphSteps) {
+        StepGraph& g = s->graph;
+        const bool hit = g.exec && g.phi == phi && g.U == U && g.V == V && g.W == W &&
+                         g.stream == st && g.variant == s->variant;
+        if (!hit) {
+            release_graph(g);
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "phasefield_step: begin capture");
+            hipError_t le = hipSuccess;
+            for (int m = 0; m < kGraphSteps && le == hipSuccess; ++m)
+                le = enqueue_step<T>(p, s->variant, phi, U, V, W, ya, yb, acc, t0, st);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(st, &graph);
+            if (le != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_fail(le, "phasefield_step: launch during capture");
+            }
+            if (e != hipSuccess) return hip_fail(e, "phasefield_step: end capture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return hip_fail(e, "phasefield_step: instantiate");
+            }
+            g.graph = graph;
+            g.exec = exec;
+            g.phi = phi;
+            g.U = U;
+            g.V = V;
+            g.W = W;
+            g.stream = st;
+            g.variant = s->variant;
+        }
+        for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+            hipError_t e = hipGraphLaunch(g.exec, st);
+            if (e != hipSuccess) return hip_fail(e, "phasefield_step: graph launch");
+        }
+    }
+    for (; done < nsteps; ++done) {
+        const double t = t0 + (double)done * p.dt;
+        hipError_t e = enqueue_step<T>(p, s->variant, phi, U, V, W, ya, yb, acc, t, st);
+        if (e != hipSuccess) return hip_fail(e, "phasefield_step: launch");
+    }
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_step(pf_solver* s, void* phi, const void* u, const void* v,
+                                     const void* w, double t0, int32_t nsteps, void* hip_stream)
+{
+    if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
+    pf_status st;
+    if ((st = check_field_ptr(phi, "phi")) != PF_OK) return st;
+    if ((st = check_field_ptr(u, "u")) != PF_OK) return st;
+    if ((st = check_field_ptr(v, "v")) != PF_OK) return st;
+    if ((st = check_field_ptr(w, "w")) != PF_OK) return st;
+    if (nsteps < 0) return fail(PF_ERR_INVALID, "nsteps < 0");
+    if (!std::isfinite(t0)) return fail(PF_ERR_INVALID, "t0 is not finite");
+    if (nsteps == 0) return PF_OK;
+    hipStream_t hs = (hipStream_t)hip_stream;
+    if (s->p.dtype == PF_F32)
+        return step_impl<float>(s, (float*)phi, (const float*)u, (const float*)v, (const float*)w,
+                                t0, nsteps, hs);
+    return step_impl<double>(s, (double*)phi, (const double*)u, (const double*)v,
+                             (const double*)w, t0, nsteps, hs);
+}
+
+extern "C" pf_status phasefield_reduce(pf_solver* s, const void* phi, double out4[4],
+                                       void* hip_stream)
+{
+    if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
+    pf_status st = check_field_ptr(phi, "phi");
+    if (st != PF_OK) return st;
+    if (!out4) return fail(PF_ERR_INVALID, "out4 is NULL");
+    hipStream_t hs = (hipStream_t)hip_stream;
+    hipError_t e = s->p.dtype == PF_F32
+                       ? launch_reduce<float>((const float*)phi, s->N, s->red_part, s->red_out, hs)
+                       : launch_reduce<double>((const double*)phi, s->N, s->red_part, s->red_out, hs);
+    if (e != hipSuccess) return hip_fail(e, "phasefield_reduce: launch");
+    e = hipMemcpyAsync(s->red_host, s->red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, hs);
+    if (e != hipSuccess) return hip_fail(e, "phasefield_reduce: copy");
+    e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_fail(e, "phasefield_reduce: synchronize");
+    const int D = active_dims(s->p.n);
+    double dV = 1.0;
+    for (int d = 0; d < D; ++d) dV *= s->p.dx;
+    out4[0] = s->red_host[0] * dV;
+    out4[1] = s->red_host[1];
+    out4[2] = s->red_host[2];
+    out4[3] = s->red_host[3];
+    if (out4[3] > 0.0) return fail(PF_ERR_NONFINITE, "%.0f non-finite cells", out4[3]);
+    return PF_OK;
+}
+
+// ------------------------------------------------------------------------------ autotune
+template <typename T>
+static pf_status autotune_impl(pf_solver* s, int reps, int32_t* best, double* times_ms,
+                               hipStream_t st)
+{
+    const pf_params& p = s->p;
+    // private operands: phi and velocity live in adjoint-scratch-sized temporaries
+    T *phi = nullptr, *U = nullptr, *V = nullptr, *W = nullptr;
+    hipError_t e = hipMalloc((void**)&phi, s->N * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc((void**)&U, s->N * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc((void**)&V, s->N * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc((void**)&W, s->N * sizeof(T));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    pf_status ret = PF_OK;
+    if (e == hipSuccess) {
+        // a smooth bounded field and a uniform velocity: timing does not depend on the values
+        e = launch_fill<T>(phi, (T)0.5, s->N, st);
+        if (e == hipSuccess) e = launch_fill<T>(U, (T)0.1, s->N, st);
+        if (e == hipSuccess) e = launch_fill<T>(V, (T)0.1, s->N, st);
+        if (e == hipSuccess) e = launch_fill<T>(W, (T)0.1, s->N, st);
+    }
+    double best_t = INFINITY;
+    int best_v = s->variant;
+    const int nv = stage_variant_count();
+    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+        e = enqueue_step<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, (T*)s->acc, 0.0, st);
+        if (e != hipSuccess) break;
+        e = hipEventRecord(ev0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = enqueue_step<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, (T*)s->acc, 0.0, st);
+        if (e == hipSuccess) e = hipEventRecord(ev1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        const double per = ms / std::max(reps, 1);
+        if (times_ms) times_ms[v] = per;
+        if (e == hipSuccess && per < best_t) {
+            best_t = per;
+            best_v = v;
+        }
+    }
+    if (e != hipSuccess) ret = hip_fail(e, "phasefield_autotune");
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipStreamSynchronize(st);
+    for (T* b : {phi, U, V, W})
+        if (b) (void)hipFree(b);
+    if (ret == PF_OK) {
+        s->variant = best_v;
+        store_tuned(p.dtype, p.n, best_v);
+        release_graph(s->graph);
+        if (best) *best = best_v;
+    }
+    return ret;
+}
+
+extern "C" pf_status phasefield_autotune(pf_solver* s, int32_t reps, int32_t* best,
+                                         double* times_ms, void* hip_stream)
+{
+    if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
+    if (reps < 1) return fail(PF_ERR_INVALID, "reps < 1");
+    hipStream_t hs = (hipStream_t)hip_stream;
+    return s->p.dtype == PF_F32 ? autotune_impl<float>(s, reps, best, times_ms, hs)
+                                : autotune_impl<double>(s, reps, best, times_ms, hs);
+}

@@ -1,0 +1,202 @@
+// C ABI: discrete adjoint of one step, velocity synthesis from modes and its transpose.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "pf_api_internal.h"
+
+using namespace pf;
+
+template <typename T>
+static AdjArgs<T> make_adj(const pf_params& p, double svel, const T* y, const T* kap_in,
+                           double kap_scale, const T* lam_base, T* lam_out, const T* lamp,
+                           T* kap_out, double kb, double ka, T* gU, T* gV, T* gW, const T* U,
+                           const T* V, const T* W)
+{
+    AdjArgs<T> a;
+    a.y = y;
+    a.kap_in = kap_in;
+    a.kap_scale = (T)kap_scale;
+    a.lam_base = lam_base;
+    a.lam_out = lam_out;
+    a.lamp = lamp;
+    a.kap_out = kap_out;
+    a.kb = (T)kb;
+    a.ka = (T)ka;
+    a.gU = gU;
+    a.gV = gV;
+    a.gW = gW;
+    a.U = U;
+    a.V = V;
+    a.W = W;
+    a.nx = p.n[0];
+    a.ny = p.n[1];
+    a.nz = p.n[2];
+    a.inv_dx = (T)(1.0 / p.dx);
+    a.inv_2dx = (T)(1.0 / (2.0 * p.dx));
+    a.ge = (T)(p.gamma * p.eps / p.dx);
+    a.hg = (T)(0.5 * p.gamma);
+    a.hs = (T)(0.5 * svel);
+    a.delta2 = (T)(p.delta * p.delta);
+    return a;
+}
+
+template <typename T>
+static hipError_t run_stage(int variant, const StageArgs<T>& a, hipStream_t st)
+{
+    const StageVariant& v = stage_variant(variant);
+    if constexpr (sizeof(T) == 4)
+        return v.launch_f32(a, st);
+    else
+        return v.launch_f64(a, st);
+}
+
+// Reverse sweep of one classic RK4 step  phi' = phi + dt/6 (k1 + 2k2 + 2k3 + k4),
+// y1 = phi, y2 = phi + dt/2 k1, y3 = phi + dt/2 k2, y4 = phi + dt k3, k_s = f(y_s, t_s):
+//   kap4 = dt/6 lam'                       lam_n = lam' + sum_s ybar_s,
+//   kap3 = dt/3 lam' + dt   ybar4          ybar_s = (df/dy at y_s)^T kap_s,
+//   kap2 = dt/3 lam' + dt/2 ybar3          gU += sum_s (df/dU at y_s)^T kap_s.
+//   kap1 = dt/6 lam' + dt/2 ybar2
+// Buffers: y2, y3, y4 reuse the forward stage buffers; Ka/Kb ping-pong the stage cotangent
+// (it is read with a stencil), L accumulates lam' + sum ybar.
+template <typename T>
+static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V, const T* W,
+                              double t, T* lam, T* gU, T* gV, T* gW, hipStream_t st)
+{
+    const pf_params& p = s->p;
+    for (int b = 0; b < 3; ++b)
+        if (!s->adj[b]) {
+            hipError_t e = hipMalloc(&s->adj[b], s->N * sizeof(T));
+            if (e != hipSuccess) return hip_fail(e, "phasefield_adjoint_step: allocation");
+        }
+    T* Ka = (T*)s->adj[0];
+    T* Kb = (T*)s->adj[1];
+    T* L = (T*)s->adj[2];
+    const double dt = p.dt;
+    hipError_t e;
+    if (p.scheme == PF_EULER) {
+        // phi' = phi + dt f(phi):  lam_n = lam' + (df/dphi)^T (dt lam')
+        e = launch_adjoint_stage<T>(make_adj<T>(p, time_factor(p, t), phi, lam, dt, lam, L, nullptr,
+                                                nullptr, 0.0, 0.0, gU, gV, gW, U, V, W), st);
+        if (e == hipSuccess) e = launch_copy<T>(lam, L, s->N, st);
+        return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
+    }
+    T* y2 = (T*)s->ya;
+    T* y3 = (T*)s->yb;
+    T* y4 = (T*)s->acc;
+    const double s1 = time_factor(p, t), s2 = time_factor(p, t + 0.5 * dt),
+                 s4 = time_factor(p, t + dt);
+    const int v = s->variant;
+    // recompute the stage inputs exactly as the forward step stores them
+    e = run_stage<T>(v, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt, 0.0, U, V, W), st);
+    if (e == hipSuccess)
+        e = run_stage<T>(v, make_stage<T>(p, s2, y2, phi, nullptr, y3, nullptr, 0.5 * dt, 0.0, U, V, W), st);
+    if (e == hipSuccess)
+        e = run_stage<T>(v, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W), st);
+    // reverse stages
+    if (e == hipSuccess)
+        e = launch_adjoint_stage<T>(make_adj<T>(p, s4, y4, lam, dt / 6.0, lam, L, lam, Ka, dt / 3.0,
+                                                dt, gU, gV, gW, U, V, W), st);
+    if (e == hipSuccess)
+        e = launch_adjoint_stage<T>(make_adj<T>(p, s2, y3, Ka, 1.0, L, L, lam, Kb, dt / 3.0,
+                                                0.5 * dt, gU, gV, gW, U, V, W), st);
+    if (e == hipSuccess)
+        e = launch_adjoint_stage<T>(make_adj<T>(p, s2, y2, Kb, 1.0, L, L, lam, Ka, dt / 6.0,
+                                                0.5 * dt, gU, gV, gW, U, V, W), st);
+    if (e == hipSuccess)
+        e = launch_adjoint_stage<T>(make_adj<T>(p, s1, phi, Ka, 1.0, L, lam, nullptr, nullptr, 0.0,
+                                                0.0, gU, gV, gW, U, V, W), st);
+    // the forward graph (if any) captured the stage buffers' old contents only; nothing to redo
+    return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
+}
+
+extern "C" pf_status phasefield_adjoint_step(pf_solver* s, const void* phi_n, const void* u,
+                                             const void* v, const void* w, double t_n, void* lam,
+                                             void* gu, void* gv, void* gw, void* hip_stream)
+{
+    if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
+    pf_status st;
+    if ((st = check_field_ptr(phi_n, "phi_n")) != PF_OK) return st;
+    if ((st = check_field_ptr(u, "u")) != PF_OK) return st;
+    if ((st = check_field_ptr(v, "v")) != PF_OK) return st;
+    if ((st = check_field_ptr(w, "w")) != PF_OK) return st;
+    if ((st = check_field_ptr(lam, "lam")) != PF_OK) return st;
+    for (const void* g : {(const void*)gu, (const void*)gv, (const void*)gw})
+        if (g && (((uintptr_t)g) & 15)) return fail(PF_ERR_INVALID, "gradient not 16-byte aligned");
+    if (!std::isfinite(t_n)) return fail(PF_ERR_INVALID, "t_n is not finite");
+    hipStream_t hs = (hipStream_t)hip_stream;
+    if (s->p.dtype == PF_F32)
+        return adjoint_impl<float>(s, (const float*)phi_n, (const float*)u, (const float*)v,
+                                   (const float*)w, t_n, (float*)lam, (float*)gu, (float*)gv,
+                                   (float*)gw, hs);
+    return adjoint_impl<double>(s, (const double*)phi_n, (const double*)u, (const double*)v,
+                                (const double*)w, t_n, (double*)lam, (double*)gu, (double*)gv,
+                                (double*)gw, hs);
+}
+
+// ------------------------------------------------------------------------------ velocity
+static pf_status velocity_common(const pf_params* p, int32_t modes, const double* phases)
+{
+    pf_status st = validate_params(p);
+    if (st != PF_OK) return st;
+    if (modes < 1 || modes > 64) return fail(PF_ERR_INVALID, "modes = %d out of [1, 64]", modes);
+    if (!phases) return fail(PF_ERR_INVALID, "phases is NULL");
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_velocity_from_coeffs(const pf_params* p, int32_t modes,
+                                                     const double* phases, const double* coeffs,
+                                                     void* u, void* v, void* w, void* hip_stream)
+{
+    pf_status st = velocity_common(p, modes, phases);
+    if (st != PF_OK) return st;
+    if (!coeffs) return fail(PF_ERR_INVALID, "coeffs is NULL");
+    if ((st = check_field_ptr(u, "u")) != PF_OK) return st;
+    if ((st = check_field_ptr(v, "v")) != PF_OK) return st;
+    if ((st = check_field_ptr(w, "w")) != PF_OK) return st;
+    hipStream_t hs = (hipStream_t)hip_stream;
+    double* scratch = nullptr;
+    const size_t nd = velocity_scratch_doubles(p->n[0], p->n[1], p->n[2], modes);
+    hipError_t e = hipMalloc((void**)&scratch, nd * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "phasefield_velocity_from_coeffs: allocation");
+    if (p->dtype == PF_F32)
+        e = launch_velocity<float>(p->n[0], p->n[1], p->n[2], p->dx, modes, phases, coeffs,
+                                   (float*)u, (float*)v, (float*)w, scratch, hs);
+    else
+        e = launch_velocity<double>(p->n[0], p->n[1], p->n[2], p->dx, modes, phases, coeffs,
+                                    (double*)u, (double*)v, (double*)w, scratch, hs);
+    hipError_t e2 = hipStreamSynchronize(hs);
+    (void)hipFree(scratch);
+    if (e == hipSuccess) e = e2;
+    return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_velocity_from_coeffs");
+}
+
+extern "C" pf_status phasefield_velocity_coeffs_grad(const pf_params* p, int32_t modes,
+                                                     const double* phases, const void* gu,
+                                                     const void* gv, const void* gw,
+                                                     double* coeff_grad, void* hip_stream)
+{
+    pf_status st = velocity_common(p, modes, phases);
+    if (st != PF_OK) return st;
+    if (!coeff_grad) return fail(PF_ERR_INVALID, "coeff_grad is NULL");
+    if ((st = check_field_ptr(gu, "gu")) != PF_OK) return st;
+    if ((st = check_field_ptr(gv, "gv")) != PF_OK) return st;
+    if ((st = check_field_ptr(gw, "gw")) != PF_OK) return st;
+    hipStream_t hs = (hipStream_t)hip_stream;
+    double* scratch = nullptr;
+    const size_t nd = velocity_scratch_doubles(p->n[0], p->n[1], p->n[2], modes);
+    hipError_t e = hipMalloc((void**)&scratch, nd * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "phasefield_velocity_coeffs_grad: allocation");
+    if (p->dtype == PF_F32)
+        e = launch_velocity_grad<float>(p->n[0], p->n[1], p->n[2], p->dx, modes, phases,
+                                        (const float*)gu, (const float*)gv, (const float*)gw,
+                                        coeff_grad, scratch, hs);
+    else
+        e = launch_velocity_grad<double>(p->n[0], p->n[1], p->n[2], p->dx, modes, phases,
+                                         (const double*)gu, (const double*)gv, (const double*)gw,
+                                         coeff_grad, scratch, hs);
+    hipError_t e2 = hipStreamSynchronize(hs);
+    (void)hipFree(scratch);
+    if (e == hipSuccess) e = e2;
+    return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_velocity_coeffs_grad");
+}

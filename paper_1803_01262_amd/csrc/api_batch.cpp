@@ -1,0 +1,224 @@
+// C ABI: batched driver. Each RK4 stage of every instance runs in ONE persistent launch over a
+// global tile list; the step sequence is captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pf_api_internal.h"
+
+using namespace pf;
+
+struct pf_batch {
+    int count = 0;
+    int dtype = PF_F64;
+    std::vector<pf_params> p;
+    std::vector<size_t> N;
+    void* pool = nullptr;                // stage buffers of every instance
+    std::vector<size_t> pool_off;        // element offset of instance b's ya (yb, acc follow)
+    int total_tiles = 0;
+    int grid_blocks = 0;
+    int* owner = nullptr;                // device: instance of each global tile
+    void* tables[4] = {nullptr, nullptr, nullptr, nullptr};  // device BatchEntry<T>[count] per stage
+    std::vector<const void*> key;        // pointer set the tables and graph were built for
+    hipStream_t key_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void batch_release_graph(pf_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+extern "C" pf_status phasefield_batch_destroy(pf_batch* b)
+{
+    if (!b) return PF_OK;
+    (void)hipDeviceSynchronize();
+    batch_release_graph(b);
+    if (b->pool) (void)hipFree(b->pool);
+    if (b->owner) (void)hipFree(b->owner);
+    for (void* t : b->tables)
+        if (t) (void)hipFree(t);
+    delete b;
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int32_t count,
+                                             pf_batch** out)
+{
+    if (!out) return fail(PF_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !per_instance) return fail(PF_ERR_INVALID, "count < 1 or params NULL");
+    for (int b = 0; b < count; ++b) {
+        pf_status st = validate_params(&per_instance[b]);
+        if (st != PF_OK) return fail(st, "instance %d: %s", b, phasefield_last_error());
+        if (per_instance[b].dtype != per_instance[0].dtype)
+            return fail(PF_ERR_INVALID, "instance %d: mixed dtypes", b);
+        if (per_instance[b].scheme != PF_RK4)
+            return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver runs RK4 only", b);
+        if (per_instance[b].vel_mode != PF_VEL_STEADY)
+            return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver needs a steady velocity", b);
+    }
+    auto* B = new pf_batch();
+    B->count = count;
+    B->dtype = per_instance[0].dtype;
+    B->p.assign(per_instance, per_instance + count);
+    const size_t esz = B->dtype == PF_F32 ? sizeof(float) : sizeof(double);
+    size_t total = 0;
+    std::vector<int> owner;
+    for (int b = 0; b < count; ++b) {
+        const size_t n = (size_t)B->p[b].n[0] * B->p[b].n[1] * B->p[b].n[2];
+        B->N.push_back(n);
+        B->pool_off.push_back(total);
+        total += 3 * ((n + 63) / 64 * 64);  // keep every buffer 256-byte aligned
+        int tx, ty, cz;
+        batch_tile_counts(B->p[b].n[0], B->p[b].n[1], B->p[b].n[2], &tx, &ty, &cz);
+        for (int t = 0; t < tx * ty * cz; ++t) owner.push_back(b);
+    }
+    B->total_tiles = (int)owner.size();
+    int cus = 256;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    B->grid_blocks = std::min(B->total_tiles, cus * 8);
+    hipError_t e = hipMalloc(&B->pool, total * esz);
+    if (e == hipSuccess) e = hipMalloc((void**)&B->owner, owner.size() * sizeof(int));
+    if (e == hipSuccess)
+        e = hipMemcpy(B->owner, owner.data(), owner.size() * sizeof(int), hipMemcpyHostToDevice);
+    const size_t tsz = B->dtype == PF_F32 ? sizeof(BatchEntry<float>) : sizeof(BatchEntry<double>);
+    for (int s = 0; s < 4 && e == hipSuccess; ++s) e = hipMalloc(&B->tables[s], tsz * count);
+    if (e != hipSuccess) {
+        phasefield_batch_destroy(B);
+        return hip_fail(e, "phasefield_batch_create: allocation");
+    }
+    *out = B;
+    return PF_OK;
+}
+
+// Build the four RK4 stage tables for one pointer set (same schedule as the single solve:
+// S1 ya = phi + dt/2 k1, acc = phi + dt/6 k1; S2 yb = phi + dt/2 k2, acc += dt/3 k2;
+// S3 ya = phi + dt k3, acc += dt/3 k3; S4 phi = acc + dt/6 k4).
+template <typename T>
+static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const* u,
+                               const void* const* v, const void* const* w)
+{
+    std::vector<BatchEntry<T>> tab[4];
+    int tile = 0;
+    for (int b = 0; b < B->count; ++b) {
+        const pf_params& p = B->p[b];
+        T* ph = (T*)phi[b];
+        const T *U = (const T*)u[b], *V = (const T*)v[b], *W = (const T*)w[b];
+        T* base = (T*)B->pool + B->pool_off[b];
+        const size_t stride = (B->N[b] + 63) / 64 * 64;
+        T *ya = base, *yb = base + stride, *acc = base + 2 * stride;
+        const double dt = p.dt;
+        StageArgs<T> st[4] = {
+            make_stage<T>(p, 1.0, ph, ph, ph, ya, acc, 0.5 * dt, dt / 6.0, U, V, W),
+            make_stage<T>(p, 1.0, ya, ph, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W),
+            make_stage<T>(p, 1.0, yb, ph, acc, ya, acc, dt, dt / 3.0, U, V, W),
+            make_stage<T>(p, 1.0, ya, nullptr, acc, nullptr, ph, 0.0, dt / 6.0, U, V, W)};
+        int tx, ty, cz;
+        batch_tile_counts(p.n[0], p.n[1], p.n[2], &tx, &ty, &cz);
+        for (int s = 0; s < 4; ++s) {
+            BatchEntry<T> e;
+            e.a = st[s];
+            e.tile_begin = tile;
+            e.tiles_x = tx;
+            e.tiles_y = ty;
+            e.chunks_z = cz;
+            tab[s].push_back(e);
+        }
+        tile += tx * ty * cz;
+    }
+    for (int s = 0; s < 4; ++s) {
+        hipError_t e = hipMemcpy(B->tables[s], tab[s].data(), sizeof(BatchEntry<T>) * B->count,
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: table upload");
+    }
+    return PF_OK;
+}
+
+template <typename T>
+static hipError_t enqueue_batch_step(pf_batch* B, hipStream_t st)
+{
+    for (int s = 0; s < 4; ++s) {
+        hipError_t e = launch_batch_stage<T>((const BatchEntry<T>*)B->tables[s], B->owner,
+                                             B->total_tiles, B->grid_blocks, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+static pf_status batch_step_impl(pf_batch* B, void* const* phi, const void* const* u,
+                                 const void* const* v, const void* const* w, int32_t nsteps,
+                                 hipStream_t st)
+{
+    std::vector<const void*> key;
+    for (int b = 0; b < B->count; ++b) {
+        key.push_back(phi[b]);
+        key.push_back(u[b]);
+        key.push_back(v[b]);
+        key.push_back(w[b]);
+    }
+    if (key != B->key) {
+        // tables may be in use by queued work on the previous stream
+        hipError_t e = B->key_stream ? hipStreamSynchronize(B->key_stream) : hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: synchronize");
+        pf_status ps = upload_tables<T>(B, phi, u, v, w);
+        if (ps != PF_OK) return ps;
+        batch_release_graph(B);
+        B->key = key;
+    }
+    int32_t done = 0;
+    if (st != nullptr && nsteps >= kGraphSteps) {
+        if (!B->exec || B->key_stream != st) {
+            batch_release_graph(B);
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: begin capture");
+            hipError_t le = hipSuccess;
+            for (int m = 0; m < kGraphSteps && le == hipSuccess; ++m) le = enqueue_batch_step<T>(B, st);
+            e = hipStreamEndCapture(st, &B->graph);
+            if (le != hipSuccess) return hip_fail(le, "phasefield_batch_step: launch during capture");
+            if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: end capture");
+            e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: instantiate");
+        }
+        for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+            hipError_t e = hipGraphLaunch(B->exec, st);
+            if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: graph launch");
+        }
+    }
+    B->key_stream = st;
+    for (; done < nsteps; ++done) {
+        hipError_t e = enqueue_batch_step<T>(B, st);
+        if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: launch");
+    }
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_batch_step(pf_batch* b, void* const* phi, const void* const* u,
+                                           const void* const* v, const void* const* w,
+                                           const double* t0, int32_t nsteps, void* hip_stream)
+{
+    (void)t0;  // steady velocity: the step does not depend on the start time
+    if (!b) return fail(PF_ERR_INVALID, "batch is NULL");
+    if (!phi || !u || !v || !w) return fail(PF_ERR_INVALID, "pointer array is NULL");
+    if (nsteps < 0) return fail(PF_ERR_INVALID, "nsteps < 0");
+    for (int i = 0; i < b->count; ++i) {
+        pf_status st;
+        if ((st = check_field_ptr(phi[i], "phi[b]")) != PF_OK) return st;
+        if ((st = check_field_ptr(u[i], "u[b]")) != PF_OK) return st;
+        if ((st = check_field_ptr(v[i], "v[b]")) != PF_OK) return st;
+        if ((st = check_field_ptr(w[i], "w[b]")) != PF_OK) return st;
+    }
+    if (nsteps == 0) return PF_OK;
+    hipStream_t hs = (hipStream_t)hip_stream;
+    return b->dtype == PF_F32 ? batch_step_impl<float>(b, phi, u, v, w, nsteps, hs)
+                              : batch_step_impl<double>(b, phi, u, v, w, nsteps, hs);
+}

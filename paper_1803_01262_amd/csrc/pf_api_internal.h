@@ -1,0 +1,59 @@
+// Host-side internals shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "pf_internal.h"
+#include "phasefield.h"
+
+namespace pf {
+
+constexpr int kGraphSteps = 8;  // steps per captured graph (steady velocity)
+
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* phi = nullptr;
+    const void* U = nullptr;
+    const void* V = nullptr;
+    const void* W = nullptr;
+    hipStream_t stream = nullptr;
+    int variant = -1;
+};
+
+pf_status fail(pf_status st, const char* fmt, ...);
+pf_status hip_fail(hipError_t e, const char* what);
+pf_status validate_params(const pf_params* p);
+pf_status check_field_ptr(const void* ptr, const char* name);
+int tuned_variant(int dtype, const int32_t n[3]);
+void release_graph(StepGraph& g);
+double time_factor(const pf_params& p, double t);
+
+template <typename T>
+StageArgs<T> make_stage(const pf_params& p, double svel, const T* y, const T* base1,
+                        const T* base2, T* out1, T* out2, double c1, double c2, const T* U,
+                        const T* V, const T* W);
+
+template <typename T>
+hipError_t enqueue_step(const pf_params& p, int variant, T* phi, const T* U, const T* V,
+                        const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st);
+
+}  // namespace pf
+
+struct pf_solver {
+    pf_params p{};
+    size_t N = 0;       // cells
+    size_t esz = 0;     // bytes per element
+    int variant = 0;
+    void* ya = nullptr;  // RK stage buffers
+    void* yb = nullptr;
+    void* acc = nullptr;
+    void* adj[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // adjoint scratch
+    double* red_part = nullptr;
+    double* red_out = nullptr;
+    double* red_host = nullptr;  // pinned
+    void* vel_scratch = nullptr;
+    pf::StepGraph graph;
+};

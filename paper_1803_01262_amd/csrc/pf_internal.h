@@ -1,0 +1,113 @@
+// Internal declarations of the gfx950 phase-field library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "phasefield.h"
+
+namespace pf {
+
+// One explicit stage of the flux-form update (Sec. 2.2 recipe): evaluate f = d(phi)/dt of
+// Eq. 1 from the stage input y, then write out1 = base1 + c1 f and out2 = base2 + c2 f
+// (either output may be null). base2 and out2 may be the same array (in-place accumulator);
+// y is never written by the stage.
+template <typename T>
+struct StageArgs {
+    const T* y;
+    const T* base1;
+    const T* base2;
+    T* out1;
+    T* out2;
+    const T* U;
+    const T* V;
+    const T* W;
+    int nx, ny, nz;
+    T inv_dx;   // 1 / dx
+    T inv_2dx;  // 1 / (2 dx), central gradient
+    T ge;       // gamma * eps / dx, diffusive flux coefficient
+    T hg;       // gamma / 2, sharpening flux (face mean of q)
+    T hs;       // s(t) / 2, advective flux (face mean of phi)
+    T delta2;   // delta^2, |grad phi| regulariser
+    T c1, c2;
+};
+
+// Adjoint of one stage: given the cotangent kap of the stage's f (a field), accumulate
+//   lam_out = lam_base + a_lam * ybar        (ybar = (df/dy)^T kap at y)
+//   kap_out = kap_lam_coef * lamp + a_kap * ybar   (next stage's cotangent), if kap_out
+// and gU/gV/gW += (df/dU)^T kap (if non-null). kap is read through kap_scale * kap_in.
+template <typename T>
+struct AdjArgs {
+    const T* y;        // stage input (forward)
+    const T* kap_in;   // cotangent source read with a stencil
+    T kap_scale;       // kap = kap_scale * kap_in
+    const T* lam_base; // lam_out = lam_base + ybar
+    T* lam_out;
+    const T* lamp;     // lambda' (cotangent of the step output), centre only
+    T* kap_out;        // = kb * lamp + ka * ybar (nullable)
+    T kb, ka;
+    T* gU;
+    T* gV;
+    T* gW;
+    const T* U;
+    const T* V;
+    const T* W;
+    int nx, ny, nz;
+    T inv_dx, inv_2dx, ge, hg, hs, delta2;
+};
+
+// ------------------------------------------------------------------ launchers (stage.hip)
+struct StageVariant {
+    const char* name;
+    hipError_t (*launch_f32)(const StageArgs<float>&, hipStream_t);
+    hipError_t (*launch_f64)(const StageArgs<double>&, hipStream_t);
+    bool (*fits)(int nx, int ny, int nz, int dtype);  // shape/dtype supported by this variant
+};
+int stage_variant_count();
+const StageVariant& stage_variant(int v);
+int default_stage_variant(int nx, int ny, int nz, int dtype);
+
+// ------------------------------------------------------------------ batched stages (batch.hip)
+// One entry per instance: the stage arguments plus where its tiles start in the global list.
+template <typename T>
+struct BatchEntry {
+    StageArgs<T> a;
+    int tile_begin;   // first global tile index of this instance
+    int tiles_x, tiles_y, chunks_z;
+};
+template <typename T>
+hipError_t launch_batch_stage(const BatchEntry<T>* table_dev, const int* owner_dev, int total_tiles,
+                              int grid_blocks, hipStream_t st);
+void batch_tile_counts(int nx, int ny, int nz, int* tx, int* ty, int* cz);
+
+// ------------------------------------------------------------------ adjoint (adjoint.hip)
+template <typename T>
+hipError_t launch_adjoint_stage(const AdjArgs<T>& a, hipStream_t st);
+
+// ------------------------------------------------------------------ reduction (reduce.hip)
+constexpr int kReduceBlocks = 1024;
+template <typename T>
+hipError_t launch_reduce(const T* phi, size_t n, double* partial /*4*kReduceBlocks*/,
+                         double* out4 /*device, 4*/, hipStream_t st);
+
+// ------------------------------------------------------------------ velocity (velocity.hip)
+// Scratch needs (doubles) for synthesis / projection of an n grid with M modes.
+size_t velocity_scratch_doubles(int nx, int ny, int nz, int M);
+template <typename T>
+hipError_t launch_velocity(int nx, int ny, int nz, double dx, int M, const double* phases,
+                           const double* coeffs, T* U, T* V, T* W, double* scratch,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_velocity_grad(int nx, int ny, int nz, double dx, int M, const double* phases,
+                                const T* gU, const T* gV, const T* gW, double* coeff_grad,
+                                double* scratch, hipStream_t st);
+
+// ------------------------------------------------------------------ small utilities
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T* dst, T value, size_t n, hipStream_t st);
+
+}  // namespace pf

@@ -1,0 +1,60 @@
+// Stage kernel, plain variant: one thread per cell, every operand read from global memory
+// (L1/L2 supply the reuse). It is the reference shape for the tiled variants and the fallback
+// for grids the tiled variants do not cover; all variants share pf_cell.h and agree bitwise.
+#include "pf_cell.h"
+#include "pf_internal.h"
+
+namespace pf {
+
+template <typename T>
+__global__ void __launch_bounds__(256) stage_global_kernel(StageArgs<T> a)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= a.nx || j >= a.ny) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const T* __restrict__ y = a.y;
+    auto idx = [&](int di, int dj, int dk) -> size_t {
+        return ((size_t)wrapn(k + dk, nz) * ny + wrapn(j + dj, ny)) * nx + wrapn(i + di, nx);
+    };
+    auto at = [&](int di, int dj, int dk) -> T { return y[idx(di, dj, dk)]; };
+    // one component of the sharpening product at a neighbouring centre
+    auto qcomp = [&](int di, int dj, int dk, int ax) -> T {
+        const T gx = grad1(at(di + 1, dj, dk), at(di - 1, dj, dk), a.inv_2dx);
+        const T gy = grad1(at(di, dj + 1, dk), at(di, dj - 1, dk), a.inv_2dx);
+        const T gz = grad1(at(di, dj, dk + 1), at(di, dj, dk - 1), a.inv_2dx);
+        const T fac = sharpen_factor(at(di, dj, dk), gx, gy, gz, a.delta2);
+        return fac * (ax == 0 ? gx : (ax == 1 ? gy : gz));
+    };
+    const size_t c = idx(0, 0, 0);
+    const T pc = y[c];
+    const T gx = grad1(at(1, 0, 0), at(-1, 0, 0), a.inv_2dx);
+    const T gy = grad1(at(0, 1, 0), at(0, -1, 0), a.inv_2dx);
+    const T gz = grad1(at(0, 0, 1), at(0, 0, -1), a.inv_2dx);
+    const T fac = sharpen_factor(pc, gx, gy, gz, a.delta2);
+    const T qx = fac * gx, qy = fac * gy, qz = fac * gz;
+
+    const T fx0 = face_flux(at(-1, 0, 0), pc, qcomp(-1, 0, 0, 0), qx, a.U[c], a.hs, a.ge, a.hg);
+    const T fx1 = face_flux(pc, at(1, 0, 0), qx, qcomp(1, 0, 0, 0), a.U[idx(1, 0, 0)], a.hs, a.ge, a.hg);
+    const T fy0 = face_flux(at(0, -1, 0), pc, qcomp(0, -1, 0, 1), qy, a.V[c], a.hs, a.ge, a.hg);
+    const T fy1 = face_flux(pc, at(0, 1, 0), qy, qcomp(0, 1, 0, 1), a.V[idx(0, 1, 0)], a.hs, a.ge, a.hg);
+    const T fz0 = face_flux(at(0, 0, -1), pc, qcomp(0, 0, -1, 2), qz, a.W[c], a.hs, a.ge, a.hg);
+    const T fz1 = face_flux(pc, at(0, 0, 1), qz, qcomp(0, 0, 1, 2), a.W[idx(0, 0, 1)], a.hs, a.ge, a.hg);
+    const T f = flux_divergence(fx0, fx1, fy0, fy1, fz0, fz1, a.inv_dx);
+    if (a.out1) a.out1[c] = fma(a.c1, f, a.base1[c]);
+    if (a.out2) a.out2[c] = fma(a.c2, f, a.base2[c]);
+}
+
+template <typename T>
+hipError_t launch_stage_global(const StageArgs<T>& a, hipStream_t st)
+{
+    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz);
+    hipLaunchKernelGGL(stage_global_kernel<T>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_stage_global<float>(const StageArgs<float>&, hipStream_t);
+template hipError_t launch_stage_global<double>(const StageArgs<double>&, hipStream_t);
+
+}  // namespace pf

@@ -150,6 +150,30 @@ def random_modes(rng: np.random.Generator, M: int, n: int, decay: float = 2.0):
     return phases, coeffs / rms
 
 
+def fourier_faces(shape, dx, phases, coeffs, dtype=np.float64):
+    """Face velocity of the separable-mode edge potential, built on the host with numpy
+    (tensor contractions over the 1-D sine tables, then the discrete curl). An input generator
+    for cases whose velocity must not come from the GPU path (e.g. inputs of oracle checks at
+    large sizes); same potential and edge positions as the library's synthesis."""
+    nz, ny, nx = shape
+    M = phases.shape[1]
+    m = np.arange(1, M + 1, dtype=np.float64)
+
+    def tab(axis, n, off):
+        i = np.arange(n, dtype=np.float64) + off
+        return np.sin(2.0 * np.pi * m[:, None] * i[None, :] / n + phases[axis][:, None])
+
+    A = []
+    for c in range(3):
+        X = tab(0, nx, 0.5 if c == 0 else 0.0)
+        Y = tab(1, ny, 0.5 if c == 1 else 0.0)
+        Z = tab(2, nz, 0.5 if c == 2 else 0.0)
+        t1 = np.einsum("abc,ci->abi", coeffs[..., c], X)      # [m3][m2][i]
+        t2 = np.einsum("abi,bj->aji", t1, Y)                  # [m3][j][i]
+        A.append(np.einsum("aji,ak->kji", t2, Z, optimize=True).astype(dtype, copy=False))
+    return edge_curl(A[0], A[1], A[2], dx)
+
+
 def max_face_speed(U, V, W) -> float:
     """Largest |component| over the three face arrays (the |u|_max that sets gamma)."""
     return float(max(np.abs(U).max(), np.abs(V).max(), np.abs(W).max()))

@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads and exports every function
+that include/phasefield.h declares, parameter validation rejects bad input before touching the
+device, and phasefield_check_params states the paper's criteria (Eq. 17, Eqs. 25 and 28)."""
+import os
+import re
+
+import pytest
+
+from oracle import params as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "phasefield.h")).read()
+    return sorted(set(re.findall(r"\b(phasefield_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import paper_1803_01262_amd as pf
+    return pf
+
+
+def test_library_exports_every_declared_symbol(pf):
+    names = header_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(pf.lib, n), n  # ctypes resolves the symbol from the .so
+    assert sorted(pf.EXPORTED) == names
+    for n in names:
+        assert callable(getattr(pf, n)), n
+
+
+def test_default_params(pf):
+    p = pf.phasefield_default_params()
+    assert tuple(p.n) == (1, 1, 1) and p.dtype == pf.PF_F64 and p.scheme == pf.PF_RK4
+    assert p.variant == -1 and p.use_graph == 1 and p.vel_mode == pf.PF_VEL_STEADY
+
+
+@pytest.mark.parametrize("field,value", [("dx", 0.0), ("dx", -1.0), ("eps", -0.1),
+                                         ("gamma", -1.0), ("dt", 0.0), ("delta", -1.0),
+                                         ("dtype", 7), ("scheme", 2), ("vel_mode", 3),
+                                         ("variant", 999)])
+def test_invalid_params_rejected_before_device_work(pf, field, value):
+    p = pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01)
+    setattr(p, field, value)
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        pf.phasefield_create(p)
+    assert ei.value.status == pf.PF_ERR_INVALID
+    assert pf.phasefield_last_error()
+
+
+def test_invalid_sizes_and_bcs(pf):
+    p = pf.make_params((8, 0, 8), 0.1, 0.1, 1.0, 0.01)
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        pf.phasefield_create(p)
+    assert ei.value.status == pf.PF_ERR_INVALID
+    p = pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01, vel_mode=1, vel_T=0.0)
+    with pytest.raises(pf.PhaseFieldError):
+        pf.phasefield_create(p)
+    p = pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01)
+    p.bc[2] = pf.PF_BC_WALL
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        pf.phasefield_create(p)
+    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        pf.phasefield_batch_create([pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01, scheme="euler")])
+    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,scheme", [((64, 64, 1), "rk4"), ((32, 32, 32), "rk4"),
+                                      ((50, 1, 1), "euler"), ((20, 30, 1), "euler")])
+def test_check_params_states_eq17_and_dt_limits(pf, n, scheme):
+    dx, eps, gamma, umax = 0.02, 0.017, 1.3, 0.9
+    p = pf.make_params(n, dx, eps, gamma, 1e-4, scheme=scheme)
+    r = pf.phasefield_check_params(p, umax)
+    dims = sum(v > 1 for v in n)
+    assert r.crossover_margin_eq17 == pytest.approx(P.margin_eq17(eps, dx, gamma, umax), rel=1e-14)
+    assert r.dt_max_scheme == pytest.approx(P.dt_max(scheme, dims, dx, gamma, eps), rel=1e-14)
+    assert r.dt_over_dtmax == pytest.approx(1e-4 / r.dt_max_scheme, rel=1e-14)
+
+
+def test_variant_table(pf):
+    nv = pf.phasefield_variant_count(pf.PF_F64)
+    assert nv >= 2
+    names = [pf.phasefield_variant_name(pf.PF_F64, v) for v in range(nv)]
+    assert all(names) and len(set(names)) == nv
+    assert pf.phasefield_variant_name(pf.PF_F64, nv) is None

@@ -1,0 +1,214 @@
+"""GPU parity of the discrete adjoint, velocity synthesis, autograd rollout and batched driver.
+
+Bars: FP64 adjoint and synthesis <= 1e-12 relative L-inf against the oracle; the rollout
+gradient against central finite differences of the GPU forward; FP32 gradients against the
+FP64 oracle at 1e-3; batched instances bit-identical to their single solves.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pf_fixtures as fx
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_linf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def adj_case(seed, shape):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    dx = 1.0 / max(shape)
+    phi = fx.drops_ic(shape, dx, [(0.5 * nx * dx, 0.5 * ny * dx, 0.5 * nz * dx)],
+                      [0.3 * max(shape) * dx], 1.5 * dx) * 0.8 + 0.2 * rng.uniform(size=shape)
+    U, V, W = fx.random_edge_faces(rng, shape, dx)
+    s = 1.0 / fx.max_face_speed(U, V, W)
+    lam = rng.standard_normal(shape)
+    return rng, phi, U * s, V * s, W * s, lam, dx
+
+
+@pytest.mark.parametrize("scheme,shape", [("rk4", (12, 10, 14)), ("rk4", (1, 20, 18)),
+                                          ("euler", (9, 11, 7)), ("rk4", (20, 16, 70))])
+def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
+    pf = lib
+    rng, phi, U, V, W, lam, dx = adj_case(1, shape)
+    kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, vel_mode=1, vel_T=0.8)
+    ref = oracle.adjoint_step(phi, U, V, W, lam, t=0.1, scheme={"rk4": 4, "euler": 1}[scheme], **kw)
+    nz, ny, nx = shape
+    s = pf.Solver((nx, ny, nz), scheme=scheme, **kw)
+    g = [dev(a) for a in (phi, U, V, W)]
+    L = dev(lam)
+    grads = [torch.zeros_like(g[0]) for _ in range(3)]
+    s.adjoint_step(*g, 0.1, L, *grads)
+    torch.cuda.synchronize()
+    assert rel_linf(host(L), ref[0]) <= 1e-12, rel_linf(host(L), ref[0])
+    for a, b in zip(grads, ref[1:]):
+        assert rel_linf(host(a), b) <= 1e-12, rel_linf(host(a), b)
+    # NULL gradients skip the velocity part and leave lam unchanged
+    L2 = dev(lam)
+    s.adjoint_step(*g, 0.1, L2)
+    torch.cuda.synchronize()
+    assert torch.equal(L2, L)
+    s.close()
+
+
+def test_adjoint_step_fp32_close_to_fp64_oracle(lib):
+    pf = lib
+    rng, phi, U, V, W, lam, dx = adj_case(2, (16, 16, 16))
+    kw = dict(dx=dx, eps=dx, gamma=1.0, dt=0.1 * dx, delta=0.05 / dx)
+    ref = oracle.adjoint_step(phi, U, V, W, lam, **kw)
+    s = pf.Solver((16, 16, 16), dtype="f32", **kw)
+    g = [dev(a, torch.float32) for a in (phi, U, V, W)]
+    L = dev(lam, torch.float32)
+    grads = [torch.zeros_like(g[0]) for _ in range(3)]
+    s.adjoint_step(*g, 0.0, L, *grads)
+    torch.cuda.synchronize()
+    assert rel_linf(host(L), ref[0]) <= 1e-3
+    for a, b in zip(grads, ref[1:]):
+        assert rel_linf(host(a), b) <= 1e-3
+    s.close()
+
+
+@pytest.mark.parametrize("shape,M", [((12, 10, 14), 3), ((32, 32, 32), 8), ((1, 16, 20), 4)])
+def test_velocity_synthesis_matches_oracle(lib, shape, M):
+    pf = lib
+    rng = np.random.default_rng(3)
+    nz, ny, nx = shape
+    dx = 1.0 / nx
+    th = rng.uniform(0, 2 * np.pi, size=(3, M))
+    c = rng.standard_normal((M, M, M, 3))
+    ref = oracle.velocity_from_coeffs(shape, dx=dx, phases=th, coeffs=c)
+    p = pf.make_params((nx, ny, nz), dx, dx, 1.0, 0.1 * dx)
+    got = pf.velocity_from_coeffs(p, dev(th), dev(c))
+    for a, b in zip(got, ref):
+        assert rel_linf(host(a), b) <= 1e-12
+    p32 = pf.make_params((nx, ny, nz), dx, dx, 1.0, 0.1 * dx, dtype="f32")
+    got32 = pf.velocity_from_coeffs(p32, dev(th), dev(c))
+    for a, b in zip(got32, ref):
+        assert np.abs(host(a) - b).max() <= 2 * np.spacing(np.float32(np.abs(b).max()))
+    # transpose
+    gb = [rng.standard_normal(shape) for _ in range(3)]
+    cref = oracle.velocity_from_coeffs_T(shape, dx=dx, phases=th, Ubar=gb[0], Vbar=gb[1], Wbar=gb[2])
+    cg = pf.velocity_coeffs_grad(p, dev(th), *[dev(x) for x in gb])
+    assert rel_linf(host(cg), cref) <= 1e-12
+
+
+def _rollout_setup(pf, n=16, nsteps=12, dtype="f64", seed=5):
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n
+    th, c = fx.random_modes(rng, 3, n)
+    U, V, W = oracle.velocity_from_coeffs((n, n, n), dx=dx, phases=th, coeffs=c)
+    umax = fx.max_face_speed(U, V, W)
+    phi0 = fx.drops_ic((n, n, n), dx, [(0.4, 0.45, 0.5)], [0.25], dx)
+    target = fx.drops_ic((n, n, n), dx, [(0.5, 0.5, 0.5)], [0.25], dx)
+    dt = fx.rk4_dt_3d(dx, umax, dx)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    s = pf.Solver((n, n, n), dx, dx, umax, dt, dtype=dtype, delta=1e-3 / dx)
+    return s, th, c, phi0, target, tdt, (U, V, W, umax, dt, dx)
+
+
+def _loss(pf, s, th, coeffs, phi0, target, nsteps, ckpt):
+    phiT = pf.Rollout.apply(phi0, coeffs, s, th, nsteps, ckpt, 0.0)
+    return 0.5 * ((phiT - target) ** 2).sum()
+
+
+def test_rollout_gradient_matches_oracle_and_fd(lib):
+    """dL/dphi0 and dL/dcoeffs of L = 0.5 |phi_T - target|^2 through Rollout: against the
+    oracle's adjoint chain (1e-11), fourth-order central differences of the GPU forward in 6 random
+    directions (1e-7), and identical for checkpoint intervals 1, 5 and 12."""
+    pf = lib
+    nsteps = 12
+    s, th, c, phi0, target, tdt, (U, V, W, umax, dt, dx) = _rollout_setup(pf, nsteps=nsteps)
+    thd, tg = dev(th), dev(target)
+    grads = {}
+    for ck in (1, 5, 12):
+        p0 = dev(phi0).requires_grad_(True)
+        cc = dev(c).requires_grad_(True)
+        L = _loss(pf, s, thd, cc, p0, tg, nsteps, ck)
+        L.backward()
+        grads[ck] = (host(p0.grad), host(cc.grad))
+    for ck in (5, 12):
+        assert np.array_equal(grads[ck][0], grads[1][0]) and np.array_equal(grads[ck][1], grads[1][1])
+    # oracle chain
+    states = [phi0]
+    kw = dict(dx=dx, eps=dx, gamma=umax, dt=dt, delta=1e-3 / dx)
+    for n in range(nsteps):
+        states.append(oracle.step(states[-1], U, V, W, **kw))
+    lam = states[-1] - target
+    gu, gv, gw = (np.zeros_like(U) for _ in range(3))
+    for n in reversed(range(nsteps)):
+        lam, a, b, d = oracle.adjoint_step(states[n], U, V, W, lam, t=n * dt, **kw)
+        gu += a
+        gv += b
+        gw += d
+    cg = oracle.velocity_from_coeffs_T(phi0.shape, dx=dx, phases=th, Ubar=gu, Vbar=gv, Wbar=gw)
+    assert rel_linf(grads[1][0], lam) <= 1e-11
+    assert rel_linf(grads[1][1], cg) <= 1e-11
+    # finite differences of the GPU forward
+    rng = np.random.default_rng(9)
+    with torch.no_grad():
+        for d in range(6):
+            v0 = rng.standard_normal(phi0.shape) if d % 2 == 0 else np.zeros(phi0.shape)
+            vc = rng.standard_normal(c.shape) if d % 2 == 1 else np.zeros(c.shape)
+            h = 1e-5
+
+            def L_at(sgn):
+                return float(_loss(pf, s, thd, dev(c + sgn * h * vc), dev(phi0 + sgn * h * v0),
+                                   tg, nsteps, 5))
+
+            # fourth-order central difference: the normal g/sqrt(|g|^2 + delta^2) has large
+            # higher derivatives where |g| ~ delta, which the two-point formula does not resolve
+            fd = (8 * (L_at(1) - L_at(-1)) - (L_at(2) - L_at(-2))) / (12 * h)
+            an = float(np.sum(grads[1][0] * v0) + np.sum(grads[1][1] * vc))
+            assert an == pytest.approx(fd, rel=1e-7), (d, an, fd)
+    s.close()
+
+
+def _batch_instances(sizes, seed=4):
+    cases = []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng(seed + i)
+        nx, ny, nz = n
+        dx = 1.0 / max(n)
+        phi = fx.drops_ic((nz, ny, nx), dx, *fx.random_drops(rng, 3, 0.1, 0.25), dx)
+        U, V, W = fx.random_edge_faces(rng, (nz, ny, nx), dx)
+        s = 1.0 / fx.max_face_speed(U, V, W)
+        cases.append((n, dx, phi, U * s, V * s, W * s))
+    return cases
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_bitwise_equals_single_solves(lib, dtype):
+    pf = lib
+    sizes = [(32, 32, 32), (48, 40, 24), (17, 9, 33), (64, 64, 8), (5, 70, 3), (96, 1, 1)]
+    cases = _batch_instances(sizes)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    params, singles = [], []
+    for (n, dx, phi, U, V, W) in cases:
+        params.append(pf.make_params(n, dx, dx, 1.0, fx.rk4_dt_3d(dx, 1.0, dx), dtype=dtype))
+    st = torch.cuda.Stream()
+    bs = pf.BatchSolver(params)
+    bt = [[dev(a, tdt) for a in cs[2:]] for cs in cases]
+    with torch.cuda.stream(st):
+        bs.step([b[0] for b in bt], [b[1] for b in bt], [b[2] for b in bt], [b[3] for b in bt],
+                nsteps=19, stream=st)
+    st.synchronize()
+    for p, cs, b in zip(params, cases, bt):
+        s = pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype=dtype)
+        g = [dev(a, tdt) for a in cs[2:]]
+        s.step(*g, nsteps=19)
+        torch.cuda.synchronize()
+        assert torch.equal(g[0], b[0]), p.n[:]
+        s.close()
+    bs.close()

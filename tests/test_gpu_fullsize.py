@@ -1,0 +1,74 @@
+"""Parity at the full benchmark size (512^3), on sampled cells.
+
+Inputs are built on the host (seeded drops; the Fourier face field contracted with numpy), so
+no oracle input comes from the GPU path. The GPU advances the whole grid in the benchmark's
+configuration (tuned tile variant, FP32 storage). The oracle cannot step 134M cells in a test,
+but a cell's value after m RK4 steps depends only on the input within 8m cells of it (four
+stages, each reaching two cells along an axis), so the oracle runs on a periodic patch of radius
+8m + 2 around each sampled cell and its centre value is exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pf_fixtures as fx
+
+pytestmark = pytest.mark.gpu
+
+
+def patch(a, k, j, i, R):
+    n = a.shape
+    kk = (k + np.arange(-R, R + 1)) % n[0]
+    jj = (j + np.arange(-R, R + 1)) % n[1]
+    ii = (i + np.arange(-R, R + 1)) % n[2]
+    return a[np.ix_(kk, jj, ii)]
+
+
+@pytest.fixture(scope="module")
+def case512():
+    c = fx.roofline512(512)
+    U, V, W = fx.fourier_faces(c.shape, c.dx, *c.modes)
+    fx.set_speed(c, fx.max_face_speed(U, V, W))
+    return c, U, V, W
+
+
+def sample_cells(phi, rng, count):
+    inter = np.argwhere((phi > 0.05) & (phi < 0.95))
+    pick = inter[rng.choice(len(inter), count // 2, replace=False)]
+    rand = rng.integers(0, phi.shape[0], size=(count - count // 2, 3))
+    return np.concatenate([pick, rand])
+
+
+@pytest.mark.parametrize("dtype,nsteps,tol", [("f32", 2, 1e-5), ("f64", 1, 1e-12)])
+def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol):
+    pf = lib
+    c, U, V, W = case512
+    np_dt = np.float32 if dtype == "f32" else np.float64
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    inputs = [a.astype(np_dt).astype(np.float64) for a in (c.phi0, U, V, W)]
+    n = c.shape[0]
+    st = torch.cuda.Stream()
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype)
+    s.autotune(reps=1, stream=st)
+    print("variant", pf.phasefield_variant_name(0, s.variant), flush=True)
+    g = [torch.tensor(a, dtype=tdt, device="cuda") for a in inputs]
+    m0 = s.reduce(g[0], stream=st)
+    with torch.cuda.stream(st):
+        s.step(*g, nsteps=nsteps, stream=st)
+    m1 = s.reduce(g[0], stream=st)
+    out = g[0].cpu().numpy().astype(np.float64)
+    del g
+    s.close()
+    drift = abs(m1[0] - m0[0]) / m0[0]
+    assert drift <= (1e-6 if dtype == "f32" else 1e-13), drift
+    R = 8 * nsteps + 2
+    rng = np.random.default_rng(17)
+    worst = 0.0
+    for (k, j, i) in sample_cells(inputs[0], rng, 24):
+        pp = [patch(a, k, j, i, R) for a in inputs]
+        ref = oracle.step(*pp, dx=c.dx, eps=c.eps, gamma=c.gamma, dt=c.dt, nsteps=nsteps,
+                          fp32=(dtype == "f32"))
+        worst = max(worst, abs(out[k, j, i] - ref[R, R, R]))
+    print(dtype, "worst sampled |gpu - oracle| =", worst, "mass drift", drift, flush=True)
+    assert worst <= tol * np.abs(out).max()
