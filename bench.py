@@ -77,14 +77,14 @@ def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, v
     tuned = None
     if autotune and variant < 0:
         best, times = s.autotune(reps=3, stream=st)
-        tuned = {pf.phasefield_variant_name(0, k): round(t, 4) for k, t in enumerate(times)}
+        tuned = {k: round(t, 4) for k, t in times.items()}
     with torch.cuda.stream(st):
         if warmup:
             s.step(phi, u, v, w, nsteps=warmup, stream=st)
         m0 = s.reduce(phi, stream=st)
         ms = cuda_timer(st, lambda: s.step(phi, u, v, w, nsteps=steps, stream=st)) / steps
         m1 = s.reduce(phi, stream=st)
-    name = pf.phasefield_variant_name(0, s.variant)
+    name = s.variant_name
     s.close()
     return ms, name, tuned, m0, m1
 

@@ -67,7 +67,13 @@ class Solver:
         return phasefield_reduce(self.handle, self.params, phi, stream)
 
     def autotune(self, reps=5, stream=None):
-        return phasefield_autotune(self.handle, reps, stream)
+        """Time every stage-kernel variant; returns (best, {name: ms per step})."""
+        best, times = phasefield_autotune(self.handle, reps, stream, self.params.dtype)
+        return best, {phasefield_variant_name(self.params.dtype, k): t for k, t in enumerate(times)}
+
+    @property
+    def variant_name(self) -> str:
+        return phasefield_variant_name(self.params.dtype, self.variant)
 
     def report(self, max_face_speed: float) -> Report:
         return phasefield_check_params(self.params, max_face_speed)

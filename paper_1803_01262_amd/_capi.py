@@ -219,13 +219,13 @@ def phasefield_variant_name(dtype, v) -> str | None:
     return None if r is None else r.decode()
 
 
-def phasefield_autotune(h, reps=5, stream=None):
-    """Returns (best variant, per-variant ms per step)."""
-    nv = lib.phasefield_variant_count(0)
-    times = (ctypes.c_double * nv)()
+def phasefield_autotune(h, reps=5, stream=None, dtype=PF_F64):
+    """Returns (best variant, per-variant ms per step) for a handle of storage dtype."""
+    nv = lib.phasefield_variant_count(int(dtype))
+    times = (ctypes.c_double * max(nv, 1))()
     best = ctypes.c_int32()
     _check(lib.phasefield_autotune(h, int(reps), ctypes.byref(best), times, _stream(stream)))
-    return best.value, list(times)
+    return best.value, list(times)[:nv]
 
 
 def phasefield_solver_variant(h) -> int:

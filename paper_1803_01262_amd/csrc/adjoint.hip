@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
     auto K = [&](int di, int dj, int dk) -> T { return a.kap_scale * a.kap_in[idx(di, dj, dk)]; };
     // cotangent of the flux on the low ax-face of cell (di, dj, dk)
     auto Fb = [&](int di, int dj, int dk, int ax) -> T {
-        return (K(di - (ax == 0), dj - (ax == 1), dk - (ax == 2)) - K(di, dj, dk)) * a.inv_dx;
+        return adj_face(K(di - (ax == 0), dj - (ax == 1), dk - (ax == 2)), K(di, dj, dk), a.inv_dx);
     };
     // gbar (all three components) and the local (1-2y)(n.qbar) term of cell (di, dj, dk)
     auto cell = [&](int di, int dj, int dk, T gb[3], T& local) {
@@ -38,20 +38,11 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
         g[0] = grad1(Y(di + 1, dj, dk), Y(di - 1, dj, dk), a.inv_2dx);
         g[1] = grad1(Y(di, dj + 1, dk), Y(di, dj - 1, dk), a.inv_2dx);
         g[2] = grad1(Y(di, dj, dk + 1), Y(di, dj, dk - 1), a.inv_2dx);
-        const T r = inv_mag(g[0], g[1], g[2], a.delta2);
-        const T w = p * (T(1) - p);
         T qb[3];
         qb[0] = -a.hg * (Fb(di, dj, dk, 0) + Fb(di + 1, dj, dk, 0));
         qb[1] = -a.hg * (Fb(di, dj, dk, 1) + Fb(di, dj + 1, dk, 1));
         qb[2] = -a.hg * (Fb(di, dj, dk, 2) + Fb(di, dj, dk + 1, 2));
-        T nq = T(0), gn = T(0);
-        for (int b = 0; b < 3; ++b) {
-            nq = fma(g[b] * r, qb[b], nq);
-            gn = fma(g[b], w * qb[b], gn);
-        }
-        local = (T(1) - T(2) * p) * nq;
-        const T r3gn = r * r * r * gn;
-        for (int b = 0; b < 3; ++b) gb[b] = r * (w * qb[b]) - g[b] * r3gn;
+        local = adj_cell(p, g, qb, a.delta2, gb);
     };
 
     const size_t c = idx(0, 0, 0);
@@ -81,15 +72,210 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
     if (a.kap_out) a.kap_out[c] = fma(a.ka, ybar, a.kb * a.lamp[c]);
 }
 
+// Tiled form of the same stage adjoint: a TX x TY workgroup marches KZ planes along z, with
+// three-plane LDS rings (two-cell halo) of the stage input and of the cotangent, the x- and
+// y-components of gbar of the current and next plane in LDS (one-cell halo in their own
+// direction), and the z-component of gbar, the local term and the z-face cotangent carried in
+// registers. Iteration k computes gbar at plane k+1 and finishes plane k. Same per-cell
+// arithmetic, in the same order, as the plain kernel above, so the two agree bitwise.
+template <typename T, int TX, int TY, int KZ>
+__global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int tiles_x, int tiles_y)
+{
+    constexpr int NT = TX * TY;
+    constexpr int PW = TX + 4, PH = TY + 4, PS = PW * PH;
+    constexpr int GXW = TX + 2, GXS = GXW * TY;
+    constexpr int GYS = TX * (TY + 2);
+    constexpr int NL = (PS + NT - 1) / NT;
+    static_assert(NT >= 2 * TX + 2 * TY, "halo ring needs one thread per halo cell");
+    __shared__ T sy[3 * PS];
+    __shared__ T sk[3 * PS];
+    __shared__ T sgx[2 * GXS];
+    __shared__ T sgy[2 * GYS];
+
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int ti = b % tiles_x;
+    b /= tiles_x;
+    const int tj = b % tiles_y;
+    const int tk = b / tiles_y;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const size_t plane = (size_t)nx * ny;
+    const int i0 = ti * TX, j0 = tj * TY, k0 = tk * KZ;
+    const int k1 = min(k0 + KZ, nz);
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = (i < nx) && (j < ny);
+    const int iw = wrapn(i, nx), jw = wrapn(j, ny);
+    constexpr unsigned ES = sizeof(T);  // byte offsets within a plane
+    const unsigned col = (unsigned)(jw * nx + iw) * ES;
+    const unsigned col_xp = (unsigned)(jw * nx + wrapn(i + 1, nx)) * ES;
+    const unsigned col_yp = (unsigned)(wrapn(j + 1, ny) * nx + iw) * ES;
+
+    unsigned loff[NL];
+    int lpos[NL];
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+        const int e = tid + s * NT;
+        lpos[s] = e < PS ? e : -1;
+        const int r = e / PW, c = e - r * PW;
+        loff[s] = e < PS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
+    }
+    T pre_y[NL], pre_k[NL];
+    auto fetch = [&](int kk) {
+        const size_t base = (size_t)wrapz(kk, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < NL; ++s)
+            if (lpos[s] >= 0) {
+                pre_y[s] = ldg(a.y + base, loff[s]);
+                pre_k[s] = a.kap_scale * ldg(a.kap_in + base, loff[s]);
+            }
+    };
+    auto commit = [&](int slot) {
+#pragma unroll
+        for (int s = 0; s < NL; ++s)
+            if (lpos[s] >= 0) {
+                sy[slot * PS + lpos[s]] = pre_y[s];
+                sk[slot * PS + lpos[s]] = pre_k[s];
+            }
+    };
+    int h_o = -1, h_dst = 0, h_axis = 0;
+    if (tid < 2 * TY) {
+        const int side = tid / TY, r = tid - side * TY;
+        h_o = (r + 2) * PW + (side ? TX + 2 : 1);
+        h_dst = r * GXW + (side ? TX + 1 : 0);
+        h_axis = 0;
+    } else if (tid < 2 * TY + 2 * TX) {
+        const int t2 = tid - 2 * TY;
+        const int side = t2 / TX, c = t2 - side * TX;
+        h_o = (side ? TY + 2 : 1) * PW + c + 2;
+        h_dst = (side ? TY + 1 : 0) * TX + c;
+        h_axis = 1;
+    }
+    const T inv_dx = a.inv_dx, inv_2dx = a.inv_2dx, d2 = a.delta2, hs = a.hs, hg = a.hg, ge = a.ge;
+    const int o = (ty + 2) * PW + (tx + 2);
+
+    // gbar and local term of the cell at LDS offset q of plane k+1
+    auto cell = [&](const T* Y0, const T* Y1, const T* Y2, const T* K0, const T* K1, const T* K2,
+                    int q, T gb[3]) -> T {
+        T g[3], qb[3];
+        g[0] = grad1(Y1[q + 1], Y1[q - 1], inv_2dx);
+        g[1] = grad1(Y1[q + PW], Y1[q - PW], inv_2dx);
+        g[2] = grad1(Y2[q], Y0[q], inv_2dx);
+        qb[0] = -hg * (adj_face(K1[q - 1], K1[q], inv_dx) + adj_face(K1[q], K1[q + 1], inv_dx));
+        qb[1] = -hg * (adj_face(K1[q - PW], K1[q], inv_dx) + adj_face(K1[q], K1[q + PW], inv_dx));
+        qb[2] = -hg * (adj_face(K0[q], K1[q], inv_dx) + adj_face(K1[q], K2[q], inv_dx));
+        return adj_cell(Y1[q], g, qb, d2, gb);
+    };
+
+    fetch(k0 - 2);
+    commit(0);
+    fetch(k0 - 1);
+    commit(1);
+    fetch(k0);
+    T gz_prev = T(0), gz_cur = T(0), loc_cur = T(0), fbz_cur = T(0);
+    int it = 0;
+    for (int k = k0 - 2; k < k1; ++k, ++it) {
+        __syncthreads();
+        const int s0 = it % 3, s1 = (it + 1) % 3, s2 = (it + 2) % 3;
+        commit(s2);
+        if (k + 1 < k1) fetch(k + 3);
+        const size_t pk = (size_t)(k < 0 ? 0 : k) * plane;
+        const size_t pk1 = (size_t)wrapz(k + 1, nz) * plane;
+        const bool out = k >= k0 && active;
+        const bool zface = active && k + 1 >= k0 && k + 1 < k1;  // low z-face of plane k+1
+        T u0 = T(0), u1 = T(0), v0 = T(0), v1 = T(0), w0 = T(0), w1 = T(0);
+        T gu = T(0), gv = T(0), gw = T(0), lb = T(0), lp = T(0);
+        if (out) {
+            u0 = ldg(a.U + pk, col);
+            u1 = ldg(a.U + pk, col_xp);
+            v0 = ldg(a.V + pk, col);
+            v1 = ldg(a.V + pk, col_yp);
+            w0 = ldg(a.W + pk, col);
+            w1 = ldg(a.W + pk1, col);
+            if (a.gU) gu = ldg(a.gU + pk, col);
+            if (a.gV) gv = ldg(a.gV + pk, col);
+            if (a.lam_out) lb = ldg(a.lam_base + pk, col);
+            if (a.kap_out) lp = ldg(a.lamp + pk, col);
+        }
+        if (zface && a.gW) gw = ldg(a.gW + pk1, col);
+        __syncthreads();
+
+        const T *Y0 = sy + s0 * PS, *Y1 = sy + s1 * PS, *Y2 = sy + s2 * PS;
+        const T *K0 = sk + s0 * PS, *K1 = sk + s1 * PS, *K2 = sk + s2 * PS;
+        const int q0 = it & 1, q1 = (it + 1) & 1;
+        T gb[3];
+        const T loc_next = cell(Y0, Y1, Y2, K0, K1, K2, o, gb);
+        sgx[q1 * GXS + ty * GXW + tx + 1] = gb[0];
+        sgy[q1 * GYS + (ty + 1) * TX + tx] = gb[1];
+        const T gz_next = gb[2];
+        if (h_o >= 0) {
+            T hb[3];
+            (void)cell(Y0, Y1, Y2, K0, K1, K2, h_o, hb);
+            if (h_axis == 0)
+                sgx[q1 * GXS + h_dst] = hb[0];
+            else
+                sgy[q1 * GYS + h_dst] = hb[1];
+        }
+        const T fbz_next = adj_face(K0[o], K1[o], inv_dx);  // z-face between planes k and k+1
+        if (zface && a.gW) stg(a.gW + pk1, col, fma(-hs * (Y0[o] + Y1[o]), fbz_next, gw));
+        if (out) {
+            T ybar = loc_cur;
+            // x faces
+            T lo = adj_face(K0[o - 1], K0[o], inv_dx), hi = adj_face(K0[o], K0[o + 1], inv_dx);
+            ybar = fma(lo, fma(-hs, u0, ge), ybar);
+            ybar = fma(hi, fma(-hs, u1, -ge), ybar);
+            if (a.gU) stg(a.gU + pk, col, fma(-hs * (Y0[o - 1] + Y0[o]), lo, gu));
+            const T* GX = sgx + q0 * GXS + ty * GXW + tx;
+            ybar = fma(GX[0] - GX[2], inv_2dx, ybar);
+            // y faces
+            lo = adj_face(K0[o - PW], K0[o], inv_dx);
+            hi = adj_face(K0[o], K0[o + PW], inv_dx);
+            ybar = fma(lo, fma(-hs, v0, ge), ybar);
+            ybar = fma(hi, fma(-hs, v1, -ge), ybar);
+            if (a.gV) stg(a.gV + pk, col, fma(-hs * (Y0[o - PW] + Y0[o]), lo, gv));
+            const T* GY = sgy + q0 * GYS + ty * TX + tx;
+            ybar = fma(GY[0] - GY[2 * TX], inv_2dx, ybar);
+            // z faces
+            ybar = fma(fbz_cur, fma(-hs, w0, ge), ybar);
+            ybar = fma(fbz_next, fma(-hs, w1, -ge), ybar);
+            ybar = fma(gz_prev - gz_next, inv_2dx, ybar);
+            if (a.lam_out) stg(a.lam_out + pk, col, lb + ybar);
+            if (a.kap_out) stg(a.kap_out + pk, col, fma(a.ka, ybar, a.kb * lp));
+        }
+        gz_prev = gz_cur;
+        gz_cur = gz_next;
+        loc_cur = loc_next;
+        fbz_cur = fbz_next;
+    }
+}
+
 template <typename T>
-hipError_t launch_adjoint_stage(const AdjArgs<T>& a, hipStream_t st)
+hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st)
 {
     dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz);
     hipLaunchKernelGGL(adjoint_stage_kernel<T>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_adjoint_stage(const AdjArgs<T>& a, hipStream_t st)
+{
+    constexpr int TX = 64, TY = 8, KZ = 32;
+    const int tiles_x = (a.nx + TX - 1) / TX;
+    const int tiles_y = (a.ny + TY - 1) / TY;
+    const int chunks = (a.nz + KZ - 1) / KZ;
+    const long long blocks = (long long)tiles_x * tiles_y * chunks;
+    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, KZ>), dim3((unsigned)blocks), dim3(TX * TY),
+                       0, st, a, tiles_x, tiles_y);
+    return hipGetLastError();
+}
+
 template hipError_t launch_adjoint_stage<float>(const AdjArgs<float>&, hipStream_t);
 template hipError_t launch_adjoint_stage<double>(const AdjArgs<double>&, hipStream_t);
+template hipError_t launch_adjoint_stage_global<float>(const AdjArgs<float>&, hipStream_t);
+template hipError_t launch_adjoint_stage_global<double>(const AdjArgs<double>&, hipStream_t);
 
 }  // namespace pf

@@ -69,6 +69,8 @@ pf_status pf::validate_params(const pf_params* p)
     if (cells > 4.0e9) return fail(PF_ERR_INVALID, "grid of %.3g cells is too large", cells);
     if (p->n[2] > 65535 || p->n[1] > 65535)
         return fail(PF_ERR_INVALID, "n[1] and n[2] must be <= 65535");
+    if ((double)p->n[0] * p->n[1] * 8.0 >= 2147483648.0)
+        return fail(PF_ERR_INVALID, "an xy plane must hold fewer than 2^28 cells");
     if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(PF_ERR_INVALID, "dx must be > 0");
     if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return fail(PF_ERR_INVALID, "eps must be >= 0");
     if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma))
@@ -83,8 +85,8 @@ pf_status pf::validate_params(const pf_params* p)
         return fail(PF_ERR_INVALID, "vel_mode = %d", p->vel_mode);
     if (p->vel_mode == PF_VEL_COS_REVERSAL && !(p->vel_T > 0.0))
         return fail(PF_ERR_INVALID, "vel_T must be > 0 with the cos reversal");
-    if (p->variant < -1 || p->variant >= stage_variant_count())
-        return fail(PF_ERR_INVALID, "variant %d out of range", p->variant);
+    if (p->variant < -1 || p->variant >= stage_variant_count(p->dtype))
+        return fail(PF_ERR_INVALID, "variant %d out of range for this dtype", p->variant);
     return PF_OK;
 }
 
@@ -137,15 +139,15 @@ static void store_tuned(int dtype, const int32_t n[3], int v)
 
 extern "C" int32_t phasefield_variant_count(int32_t dtype)
 {
-    (void)dtype;
-    return stage_variant_count();
+    if (dtype != PF_F32 && dtype != PF_F64) return 0;
+    return stage_variant_count(dtype);
 }
 
 extern "C" const char* phasefield_variant_name(int32_t dtype, int32_t v)
 {
-    (void)dtype;
-    if (v < 0 || v >= stage_variant_count()) return nullptr;
-    return stage_variant(v).name;
+    if (dtype != PF_F32 && dtype != PF_F64) return nullptr;
+    if (v < 0 || v >= stage_variant_count(dtype)) return nullptr;
+    return stage_variant(dtype, v).name;
 }
 
 // ------------------------------------------------------------------------------ solver
@@ -257,14 +259,18 @@ template StageArgs<double> pf::make_stage<double>(const pf_params&, double, cons
                                                   const double*, const double*);
 
 template <typename T>
-static hipError_t run_stage(int variant, const StageArgs<T>& a, hipStream_t st)
+hipError_t pf::run_stage(int variant, const StageArgs<T>& a, hipStream_t st)
 {
-    const StageVariant& v = stage_variant(variant);
+    constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
+    const int v = variant_is_fused(dtype, variant) ? 0 : variant;  // variant 0 is per-stage
+    const StageVariant& sv = stage_variant(dtype, v);
     if constexpr (sizeof(T) == 4)
-        return v.launch_f32(a, st);
+        return sv.launch_f32(a, st);
     else
-        return v.launch_f64(a, st);
+        return sv.launch_f64(a, st);
 }
+template hipError_t pf::run_stage<float>(int, const StageArgs<float>&, hipStream_t);
+template hipError_t pf::run_stage<double>(int, const StageArgs<double>&, hipStream_t);
 
 // One explicit step from time t on the given buffers (phi updated in place).
 //   RK4 (classic; Sec. 2.3, Eq. 28), fixed buffers, no pointer swaps:
@@ -307,6 +313,96 @@ template hipError_t pf::enqueue_step<double>(const pf_params&, int, double*, con
                                              const double*, const double*, double*, double*,
                                              double*, double, hipStream_t);
 
+// One RK4 step as two fused sweeps (pf_fused_body.h). phi_cur holds phi; the new phi is
+// written to phi_next (the accumulator of sweep A, overwritten in place by sweep B).
+template <typename T>
+static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* phi_cur,
+                                     T* phi_next, const T* U, const T* V, const T* W, T* yb,
+                                     double t, hipStream_t st)
+{
+    const double dt = p.dt;
+    FusedArgs<T> a;
+    a.U = U;
+    a.V = V;
+    a.W = W;
+    a.nx = p.n[0];
+    a.ny = p.n[1];
+    a.nz = p.n[2];
+    a.inv_dx = (T)(1.0 / p.dx);
+    a.inv_2dx = (T)(1.0 / (2.0 * p.dx));
+    a.ge = (T)(p.gamma * p.eps / p.dx);
+    a.hg = (T)(0.5 * p.gamma);
+    a.delta2 = (T)(p.delta * p.delta);
+    // sweep A: stages 1 and 2
+    a.y = phi_cur;
+    a.phi = phi_cur;
+    a.acc_in = nullptr;
+    a.out_y = yb;
+    a.out_acc = phi_next;
+    a.hs1 = (T)(0.5 * time_factor(p, t));
+    a.hs2 = (T)(0.5 * time_factor(p, t + 0.5 * dt));
+    a.c_mid = (T)(0.5 * dt);
+    a.c_acc1 = (T)(dt / 6.0);
+    a.c_y2 = (T)(0.5 * dt);
+    a.c_acc2 = (T)(dt / 3.0);
+    constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
+    const StageVariant& sv = stage_variant(dtype, variant);
+    hipError_t e;
+    if constexpr (sizeof(T) == 4)
+        e = sv.fused_f32(a, false, st);
+    else
+        e = sv.fused_f64(a, false, st);
+    if (e != hipSuccess) return e;
+    // sweep B: stages 3 and 4
+    a.y = yb;
+    a.phi = phi_cur;
+    a.acc_in = phi_next;
+    a.out_y = nullptr;
+    a.out_acc = phi_next;
+    a.hs1 = (T)(0.5 * time_factor(p, t + 0.5 * dt));
+    a.hs2 = (T)(0.5 * time_factor(p, t + dt));
+    a.c_mid = (T)dt;
+    a.c_acc1 = (T)(dt / 3.0);
+    a.c_y2 = (T)0;
+    a.c_acc2 = (T)(dt / 6.0);
+    if constexpr (sizeof(T) == 4)
+        return sv.fused_f32(a, true, st);
+    else
+        return sv.fused_f64(a, true, st);
+}
+
+// nsteps steps from t0 (step m at t0 + m dt), phi updated in place. A fused variant alternates
+// phi between the caller's buffer and acc and copies back after an odd count.
+template <typename T>
+hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U, const T* V,
+                             const T* W, T* ya, T* yb, T* acc, double t0, int nsteps,
+                             hipStream_t st)
+{
+    constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
+    const bool fused = p.scheme == PF_RK4 && variant_is_fused(dtype, variant);
+    T* cur = phi;
+    for (int m = 0; m < nsteps; ++m) {
+        const double t = t0 + (double)m * p.dt;
+        hipError_t e;
+        if (fused) {
+            T* next = cur == phi ? acc : phi;
+            e = enqueue_step_fused<T>(p, variant, cur, next, U, V, W, yb, t, st);
+            cur = next;
+        } else {
+            e = enqueue_step<T>(p, variant, phi, U, V, W, ya, yb, acc, t, st);
+        }
+        if (e != hipSuccess) return e;
+    }
+    if (cur != phi) return launch_copy<T>(phi, cur, (size_t)p.n[0] * p.n[1] * p.n[2], st);
+    return hipSuccess;
+}
+template hipError_t pf::enqueue_steps<float>(const pf_params&, int, float*, const float*,
+                                             const float*, const float*, float*, float*, float*,
+                                             double, int, hipStream_t);
+template hipError_t pf::enqueue_steps<double>(const pf_params&, int, double*, const double*,
+                                              const double*, const double*, double*, double*,
+                                              double*, double, int, hipStream_t);
+
 template <typename T>
 static pf_status step_impl(pf_solver* s, T* phi, const T* U, const T* V, const T* W, double t0,
                            int32_t nsteps, hipStream_t st)
@@ -328,8 +424,7 @@ static pf_status step_impl(pf_solver* s, T* phi, const T* U, const T* V, const T
             hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "phasefield_step: begin capture");
             hipError_t le = hipSuccess;
-            for (int m = 0; m < kGraphSteps && le == hipSuccess; ++m)
-                le = enqueue_step<T>(p, s->variant, phi, U, V, W, ya, yb, acc, t0, st);
+            le = enqueue_steps<T>(p, s->variant, phi, U, V, W, ya, yb, acc, t0, kGraphSteps, st);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(st, &graph);
             if (le != hipSuccess) {
@@ -357,9 +452,9 @@ static pf_status step_impl(pf_solver* s, T* phi, const T* U, const T* V, const T
             if (e != hipSuccess) return hip_fail(e, "phasefield_step: graph launch");
         }
     }
-    for (; done < nsteps; ++done) {
-        const double t = t0 + (double)done * p.dt;
-        hipError_t e = enqueue_step<T>(p, s->variant, phi, U, V, W, ya, yb, acc, t, st);
+    if (done < nsteps) {
+        hipError_t e = enqueue_steps<T>(p, s->variant, phi, U, V, W, ya, yb, acc,
+                                        t0 + (double)done * p.dt, nsteps - done, st);
         if (e != hipSuccess) return hip_fail(e, "phasefield_step: launch");
     }
     return PF_OK;
@@ -437,18 +532,19 @@ static pf_status autotune_impl(pf_solver* s, int reps, int32_t* best, double* ti
     }
     double best_t = INFINITY;
     int best_v = s->variant;
-    const int nv = stage_variant_count();
+    const int nv = stage_variant_count(p.dtype);
     for (int v = 0; v < nv && e == hipSuccess; ++v) {
-        e = enqueue_step<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, (T*)s->acc, 0.0, st);
+        e = enqueue_steps<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, (T*)s->acc, 0.0, 2, st);
         if (e != hipSuccess) break;
         e = hipEventRecord(ev0, st);
-        for (int r = 0; r < reps && e == hipSuccess; ++r)
-            e = enqueue_step<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, (T*)s->acc, 0.0, st);
+        if (e == hipSuccess)
+            e = enqueue_steps<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, (T*)s->acc, 0.0,
+                                 2 * reps, st);
         if (e == hipSuccess) e = hipEventRecord(ev1, st);
         if (e == hipSuccess) e = hipEventSynchronize(ev1);
         float ms = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-        const double per = ms / std::max(reps, 1);
+        const double per = ms / (2.0 * std::max(reps, 1));
         if (times_ms) times_ms[v] = per;
         if (e == hipSuccess && per < best_t) {
             best_t = per;

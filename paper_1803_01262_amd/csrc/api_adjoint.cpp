@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "pf_api_internal.h"
 
@@ -41,16 +42,6 @@ static AdjArgs<T> make_adj(const pf_params& p, double svel, const T* y, const T*
     return a;
 }
 
-template <typename T>
-static hipError_t run_stage(int variant, const StageArgs<T>& a, hipStream_t st)
-{
-    const StageVariant& v = stage_variant(variant);
-    if constexpr (sizeof(T) == 4)
-        return v.launch_f32(a, st);
-    else
-        return v.launch_f64(a, st);
-}
-
 // Reverse sweep of one classic RK4 step  phi' = phi + dt/6 (k1 + 2k2 + 2k3 + k4),
 // y1 = phi, y2 = phi + dt/2 k1, y3 = phi + dt/2 k2, y4 = phi + dt k3, k_s = f(y_s, t_s):
 //   kap4 = dt/6 lam'                       lam_n = lam' + sum_s ybar_s,
@@ -73,10 +64,15 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     T* Kb = (T*)s->adj[1];
     T* L = (T*)s->adj[2];
     const double dt = p.dt;
+    // the plain forward variant pairs with the plain adjoint kernel (both one thread per cell)
+    const bool plain = std::strcmp(stage_variant(p.dtype, s->variant).name, "global") == 0;
+    auto adj = [&](const AdjArgs<T>& a, hipStream_t hs) {
+        return plain ? launch_adjoint_stage_global<T>(a, hs) : launch_adjoint_stage<T>(a, hs);
+    };
     hipError_t e;
     if (p.scheme == PF_EULER) {
         // phi' = phi + dt f(phi):  lam_n = lam' + (df/dphi)^T (dt lam')
-        e = launch_adjoint_stage<T>(make_adj<T>(p, time_factor(p, t), phi, lam, dt, lam, L, nullptr,
+        e = adj(make_adj<T>(p, time_factor(p, t), phi, lam, dt, lam, L, nullptr,
                                                 nullptr, 0.0, 0.0, gU, gV, gW, U, V, W), st);
         if (e == hipSuccess) e = launch_copy<T>(lam, L, s->N, st);
         return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
@@ -95,16 +91,16 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         e = run_stage<T>(v, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W), st);
     // reverse stages
     if (e == hipSuccess)
-        e = launch_adjoint_stage<T>(make_adj<T>(p, s4, y4, lam, dt / 6.0, lam, L, lam, Ka, dt / 3.0,
+        e = adj(make_adj<T>(p, s4, y4, lam, dt / 6.0, lam, L, lam, Ka, dt / 3.0,
                                                 dt, gU, gV, gW, U, V, W), st);
     if (e == hipSuccess)
-        e = launch_adjoint_stage<T>(make_adj<T>(p, s2, y3, Ka, 1.0, L, L, lam, Kb, dt / 3.0,
+        e = adj(make_adj<T>(p, s2, y3, Ka, 1.0, L, L, lam, Kb, dt / 3.0,
                                                 0.5 * dt, gU, gV, gW, U, V, W), st);
     if (e == hipSuccess)
-        e = launch_adjoint_stage<T>(make_adj<T>(p, s2, y2, Kb, 1.0, L, L, lam, Ka, dt / 6.0,
+        e = adj(make_adj<T>(p, s2, y2, Kb, 1.0, L, L, lam, Ka, dt / 6.0,
                                                 0.5 * dt, gU, gV, gW, U, V, W), st);
     if (e == hipSuccess)
-        e = launch_adjoint_stage<T>(make_adj<T>(p, s1, phi, Ka, 1.0, L, lam, nullptr, nullptr, 0.0,
+        e = adj(make_adj<T>(p, s1, phi, Ka, 1.0, L, lam, nullptr, nullptr, 0.0,
                                                 0.0, gU, gV, gW, U, V, W), st);
     // the forward graph (if any) captured the stage buffers' old contents only; nothing to redo
     return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");

@@ -40,6 +40,15 @@ template <typename T>
 hipError_t enqueue_step(const pf_params& p, int variant, T* phi, const T* U, const T* V,
                         const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st);
 
+template <typename T>
+hipError_t enqueue_steps(const pf_params& p, int variant, T* phi, const T* U, const T* V,
+                         const T* W, T* ya, T* yb, T* acc, double t0, int nsteps,
+                         hipStream_t st);
+
+// One stage launch with the per-stage kernel of a variant (fused variants use variant 0).
+template <typename T>
+hipError_t run_stage(int variant, const StageArgs<T>& a, hipStream_t st);
+
 }  // namespace pf
 
 struct pf_solver {

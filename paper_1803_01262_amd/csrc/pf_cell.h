@@ -51,6 +51,59 @@ __device__ __forceinline__ T flux_divergence(T fx0, T fx1, T fy0, T fy1, T fz0, 
     return (((fx1 - fx0) + (fy1 - fy0)) + (fz1 - fz0)) * inv_dx;
 }
 
+// ---------------------------------------------------------------- adjoint (transpose) helpers
+// Cotangent of the flux on the face between cells lo and hi: the flux enters f[lo] with +1/dx
+// and f[hi] with -1/dx, so Fbar = (kap[lo] - kap[hi]) / dx.
+template <typename T>
+__device__ __forceinline__ T adj_face(T kap_lo, T kap_hi, T inv_dx)
+{
+    return (kap_lo - kap_hi) * inv_dx;
+}
+
+// Per-cell part of the transpose: given the stage input p and central gradient g at a cell and
+// the cotangents qb of its sharpening product (qb_a = -gamma/2 (Fbar_a[low] + Fbar_a[high])),
+// return gbar = (dq/dg)^T qb through n = g r, r = (|g|^2 + delta^2)^(-1/2), and the local term
+// (1 - 2p)(n . qb) of d(p(1-p))/dp.
+template <typename T>
+__device__ __forceinline__ T adj_cell(T p, const T g[3], const T qb[3], T delta2, T gb[3])
+{
+    const T r = inv_mag(g[0], g[1], g[2], delta2);
+    const T w = p * (T(1) - p);
+    T nq = T(0), gn = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        nq = fma(g[b] * r, qb[b], nq);
+        gn = fma(g[b], w * qb[b], gn);
+    }
+    const T r3gn = r * r * r * gn;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gb[b] = r * (w * qb[b]) - g[b] * r3gn;
+    return (T(1) - T(2) * p) * nq;
+}
+
+// Global-memory access through a uniform base pointer plus a 32-bit byte offset, so the load or
+// store uses the scalar-base / vector-offset addressing form with no 64-bit address arithmetic
+// in vector registers. Offsets stay below 4 GiB (they never cross a plane).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, unsigned byte_off, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// Periodic wrap of a plane index for the z-march: the marches reach at most 8 planes outside
+// [0, n); for n >= 8 two compares suffice, smaller grids take the general modulo.
+__device__ __forceinline__ int wrapz(int k, int n)
+{
+    if (n >= 8) return k < 0 ? k + n : (k >= n ? k - n : k);
+    k %= n;
+    return k < 0 ? k + n : k;
+}
+
 // Periodic wrap of an index that is at most one period out of range.
 __device__ __forceinline__ int wrap1(int i, int n)
 {

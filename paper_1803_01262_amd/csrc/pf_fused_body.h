@@ -1,0 +1,355 @@
+// Two RK4 stages in one z-march (the fused variants).
+//
+// A classic RK4 step is run as two sweeps instead of four:
+//   sweep A (stages 1+2):  k1 = f(phi);  ya = phi + dt/2 k1;  acc1 = phi + dt/6 k1;
+//                          k2 = f(ya);   writes yb = phi + dt/2 k2,  acc = acc1 + dt/3 k2
+//   sweep B (stages 3+4):  k3 = f(yb);   ya = phi + dt k3;   acc3 = acc + dt/3 k3;
+//                          k4 = f(ya);   writes phi' = acc3 + dt/6 k4
+// with every operation in the same order and precision as the four separate stage launches, so
+// the result is bit-identical to them. The intermediate stage value ya never leaves LDS: the
+// first evaluation (E1) produces it on the tile plus a two-cell halo (the reach of the second
+// evaluation E2), plane by plane, two planes ahead of E2. HBM traffic per cell-update drops from
+// 28 to 13 words (A: phi, u, v, w in, yb, acc out; B: yb, phi, acc, u, v, w in, phi' out).
+//
+// Sweep B cannot write phi in place (other tiles still read phi on their halo), so it writes
+// phi' over acc (read only at the cell itself) and the host alternates the roles of the two
+// buffers from step to step.
+//
+// Regions, for a TX x TY tile at (i0, j0), as (x range) x (y range):
+//   IN   stage input, ring of 3 planes       [i0-4, i0+TX+4) x [j0-4, j0+TY+4)
+//   MID  E1 cells / ya ring of 3 planes      [i0-2, i0+TX+2) x [j0-2, j0+TY+2)
+//   Q1X  x-sharpening of E1, 2 planes        [i0-3, i0+TX+3) x [j0-2, j0+TY+2)
+//   Q1Y  y-sharpening of E1, 2 planes        [i0-2, i0+TX+2) x [j0-3, j0+TY+3)
+//   Q2X  x-sharpening of E2, 2 planes        [i0-1, i0+TX+1) x [j0, j0+TY)
+//   Q2Y  y-sharpening of E2, 2 planes        [i0, i0+TX) x [j0-1, j0+TY+1)
+//   PB   phi on MID (sweep B only), 1 plane
+// Pipeline: iteration t loads input plane t+4, E1 computes q1 at plane t+3 and ya at plane
+// t+2, E2 computes q2 at plane t+1 and the outputs of plane t. Six warm-up iterations precede
+// the first output plane of a z-chunk. Two barriers per iteration.
+#pragma once
+
+#include "pf_cell.h"
+#include "pf_internal.h"
+
+namespace pf {
+
+template <typename T, int TX, int TY, int KZ, bool SWEEP_B>
+__device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int tk)
+{
+    constexpr int NT = TX * TY;
+    constexpr int INW = TX + 8, INH = TY + 8, INS = INW * INH;
+    constexpr int MW = TX + 4, MH = TY + 4, MS = MW * MH;
+    constexpr int Q1XW = TX + 6, Q1XS = Q1XW * MH;
+    constexpr int Q1YS = MW * (TY + 6);
+    constexpr int Q2XW = TX + 2, Q2XS = Q2XW * TY;
+    constexpr int Q2YS = TX * (TY + 2);
+    constexpr int NRING = 4 * MW + 4 * TY;  // MID cells outside the tile
+    constexpr int NOUT = 2 * MH + 2 * MW;   // q1-only cells (x- and y-outer ring)
+    constexpr int NH2 = 2 * TX + 2 * TY;    // q2 halo cells
+    constexpr int NLI = (INS + NT - 1) / NT;
+    constexpr int NLB = SWEEP_B ? (MS + NT - 1) / NT : 0;
+    static_assert(NRING + NOUT <= NT, "tile too small for the E1 halo assignment");
+    static_assert(NH2 <= NT, "tile too small for the E2 halo assignment");
+
+    __shared__ T s_in[3 * INS];
+    __shared__ T s_mid[3 * MS];
+    __shared__ T s_q1x[2 * Q1XS];
+    __shared__ T s_q1y[2 * Q1YS];
+    __shared__ T s_q2x[2 * Q2XS];
+    __shared__ T s_q2y[2 * Q2YS];
+    __shared__ T s_pb[SWEEP_B ? MS : 1];
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const size_t plane = (size_t)nx * ny;
+    const int i0 = ti * TX, j0 = tj * TY, k0 = tk * KZ;
+    const int k1 = min(k0 + KZ, nz);
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const bool active = (i0 + tx < nx) && (j0 + ty < ny);
+    const T inv_2dx = a.inv_2dx, d2 = a.delta2;
+
+    // ---- E1 cell slots: slot 0 = own cell, slot 1 = a MID ring cell (tid < NRING)
+    int e_lx[2], e_ly[2];
+    e_lx[0] = tx + 2;
+    e_ly[0] = ty + 2;
+    const bool has_ring = tid < NRING;
+    {
+        int r = has_ring ? tid : 0, lx, ly;
+        if (r < 2 * MW) {
+            ly = r / MW;
+            lx = r - ly * MW;
+        } else if (r < 4 * MW) {
+            const int r2 = r - 2 * MW;
+            ly = TY + 2 + r2 / MW;
+            lx = r2 % MW;
+        } else {
+            const int r3 = r - 4 * MW;
+            ly = 2 + r3 / 4;
+            const int c = r3 % 4;
+            lx = c < 2 ? c : TX + c;
+        }
+        e_lx[1] = lx;
+        e_ly[1] = ly;
+    }
+    // byte offsets within a plane of the slots' (wrapped) columns and their +1 neighbours
+    constexpr unsigned ES = sizeof(T);
+    unsigned e_col[2], e_colx[2], e_coly[2];
+    for (int s = 0; s < 2; ++s) {
+        const int gx = wrapn(i0 - 2 + e_lx[s], nx), gy = wrapn(j0 - 2 + e_ly[s], ny);
+        e_col[s] = (unsigned)(gy * nx + gx) * ES;
+        e_colx[s] = (unsigned)(gy * nx + wrapn(gx + 1, nx)) * ES;
+        e_coly[s] = (unsigned)(wrapn(gy + 1, ny) * nx + gx) * ES;
+    }
+    // ---- q1-only cell (x-outer: Q1X columns 0 and TX+5; y-outer: Q1Y rows 0 and TY+5)
+    const int ro = tid - NRING;
+    const bool has_out = ro >= 0 && ro < NOUT;
+    int o_in = 0, o_dst = 0, o_axis = 0;
+    if (has_out) {
+        if (ro < 2 * MH) {
+            const int side = ro / MH, ry = ro - side * MH;
+            o_in = (side ? TX + 6 : 1) + (ry + 2) * INW;
+            o_dst = (side ? TX + 5 : 0) + ry * Q1XW;
+            o_axis = 0;
+        } else {
+            const int r2 = ro - 2 * MH;
+            const int side = r2 / MW, cx = r2 - side * MW;
+            o_in = (cx + 2) + (side ? TY + 6 : 1) * INW;
+            o_dst = cx + (side ? TY + 5 : 0) * MW;
+            o_axis = 1;
+        }
+    }
+    // ---- q2 halo cell (threads at the top of the block, which have no ring work)
+    const int rh = tid - (NT - NH2);
+    const bool has_h2 = rh >= 0;
+    int h_om = 0, h_dst = 0, h_axis = 0;
+    if (has_h2) {
+        if (rh < 2 * TY) {
+            const int side = rh / TY, r = rh - side * TY;
+            h_om = (side ? TX + 2 : 1) + (r + 2) * MW;
+            h_dst = (side ? TX + 1 : 0) + r * Q2XW;
+            h_axis = 0;
+        } else {
+            const int r2 = rh - 2 * TY;
+            const int side = r2 / TX, c = r2 - side * TX;
+            h_om = (c + 2) + (side ? TY + 2 : 1) * MW;
+            h_dst = c + (side ? TY + 1 : 0) * TX;
+            h_axis = 1;
+        }
+    }
+
+    // ---- plane loads: IN (stage input with halo 4) and, for sweep B, phi on MID
+    unsigned li_off[NLI];
+    int li_pos[NLI];
+#pragma unroll
+    for (int s = 0; s < NLI; ++s) {
+        const int e = tid + s * NT;
+        li_pos[s] = e < INS ? e : -1;
+        const int r = e / INW, c = e - r * INW;
+        li_off[s] = e < INS ? (unsigned)(wrapn(j0 - 4 + r, ny) * nx + wrapn(i0 - 4 + c, nx)) * ES : 0u;
+    }
+    unsigned lb_off[NLB > 0 ? NLB : 1];
+    int lb_pos[NLB > 0 ? NLB : 1];
+#pragma unroll
+    for (int s = 0; s < NLB; ++s) {
+        const int e = tid + s * NT;
+        lb_pos[s] = e < MS ? e : -1;
+        const int r = e / MW, c = e - r * MW;
+        lb_off[s] = e < MS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
+    }
+    T pre_in[NLI];
+    T pre_b[NLB > 0 ? NLB : 1];
+    auto fetch_in = [&](int kk) {
+        const T* src = a.y + (size_t)wrapz(kk, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < NLI; ++s)
+            if (li_pos[s] >= 0) pre_in[s] = ldg(src, li_off[s]);
+    };
+    auto commit_in = [&](int slot) {
+#pragma unroll
+        for (int s = 0; s < NLI; ++s)
+            if (li_pos[s] >= 0) s_in[slot * INS + li_pos[s]] = pre_in[s];
+    };
+    auto fetch_b = [&](int kk) {
+        const T* src = a.phi + (size_t)wrapz(kk, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < NLB; ++s)
+            if (lb_pos[s] >= 0) pre_b[s] = ldg(src, lb_off[s]);
+    };
+    auto commit_b = [&]() {
+#pragma unroll
+        for (int s = 0; s < NLB; ++s)
+            if (lb_pos[s] >= 0) s_pb[lb_pos[s]] = pre_b[s];
+    };
+
+    // per-slot z state of E1 (q1_z and the z-face flux) and of E2
+    T e_qz[2] = {T(0), T(0)}, e_fz[2] = {T(0), T(0)};
+    T q2z = T(0), fz2 = T(0);
+    // own-cell queues from E1 (plane p) to E2 (plane p, two iterations later): after E1 of
+    // iteration t they hold planes t, t+1, t+2 in entries 0, 1, 2
+    T qa_phi[3] = {T(0), T(0), T(0)}, qa_acc[3] = {T(0), T(0), T(0)};
+    T qa_u0[3] = {T(0), T(0), T(0)}, qa_u1[3] = {T(0), T(0), T(0)};
+    T qa_v0[3] = {T(0), T(0), T(0)}, qa_v1[3] = {T(0), T(0), T(0)};
+    T qa_w1[3] = {T(0), T(0), T(0)};
+
+    const int tbeg = k0 - 6;
+    fetch_in(tbeg + 2);
+    commit_in(0);
+    fetch_in(tbeg + 3);
+    commit_in(1);
+    fetch_in(tbeg + 4);
+    if (SWEEP_B) fetch_b(tbeg + 2);
+
+    int it = 0;
+    for (int t = tbeg; t < k1; ++t, ++it) {
+        const int sa = it % 3, sb = (it + 1) % 3, sc = (it + 2) % 3;  // planes t+2, t+3, t+4
+        commit_in(sc);
+        if (SWEEP_B) commit_b();
+        if (t + 1 < k1) {
+            fetch_in(t + 5);
+            if (SWEEP_B) fetch_b(t + 3);
+        }
+        // E1 operands from global memory (plane p = t+2), issued before the barrier
+        const int p = t + 2;
+        const size_t pp = (size_t)wrapz(p, nz) * plane;
+        const size_t pp1 = (size_t)wrapz(p + 1, nz) * plane;
+        const T* Up = a.U + pp;
+        const T* Vp = a.V + pp;
+        const T* Wp = a.W + pp1;
+        T eu0[2], eu1[2], ev0[2], ev1[2], ew1[2], eacc = T(0);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            eu0[s] = ldg(Up, e_col[s]);
+            eu1[s] = ldg(Up, e_colx[s]);
+            ev0[s] = ldg(Vp, e_col[s]);
+            ev1[s] = ldg(Vp, e_coly[s]);
+            ew1[s] = ldg(Wp, e_col[s]);
+        }
+        if (SWEEP_B) eacc = ldg(a.acc_in + pp, e_col[0]);
+        __syncthreads();  // input plane t+4 (and phi plane t+2) visible
+
+        const T* IA = s_in + sa * INS;  // plane t+2
+        const T* IB = s_in + sb * INS;  // plane t+3
+        const T* IC = s_in + sc * INS;  // plane t+4
+        const int q1new = (it + 1) & 1, q1old = it & 1;
+        T* Q1Xn = s_q1x + q1new * Q1XS;
+        T* Q1Yn = s_q1y + q1new * Q1YS;
+        const T* Q1Xo = s_q1x + q1old * Q1XS;
+        const T* Q1Yo = s_q1y + q1old * Q1YS;
+        T* YM = s_mid + sa * MS;  // ya at plane t+2
+
+        // q1 at plane t+3 on the E1 slots and the outer ring
+        T qzn[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (s == 1 && !has_ring) {
+                qzn[s] = T(0);
+                continue;
+            }
+            const int oi = (e_lx[s] + 2) + (e_ly[s] + 2) * INW;
+            const T gx = grad1(IB[oi + 1], IB[oi - 1], inv_2dx);
+            const T gy = grad1(IB[oi + INW], IB[oi - INW], inv_2dx);
+            const T gz = grad1(IC[oi], IA[oi], inv_2dx);
+            const T fac = sharpen_factor(IB[oi], gx, gy, gz, d2);
+            Q1Xn[(e_lx[s] + 1) + e_ly[s] * Q1XW] = fac * gx;
+            Q1Yn[e_lx[s] + (e_ly[s] + 1) * MW] = fac * gy;
+            qzn[s] = fac * gz;
+        }
+        if (has_out) {
+            const T gx = grad1(IB[o_in + 1], IB[o_in - 1], inv_2dx);
+            const T gy = grad1(IB[o_in + INW], IB[o_in - INW], inv_2dx);
+            const T gz = grad1(IC[o_in], IA[o_in], inv_2dx);
+            const T fac = sharpen_factor(IB[o_in], gx, gy, gz, d2);
+            if (o_axis == 0)
+                Q1Xn[o_dst] = fac * gx;
+            else
+                Q1Yn[o_dst] = fac * gy;
+        }
+        // E1: f1 at plane t+2 on the slots -> ya (and own-cell queues)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (s == 1 && !has_ring) continue;
+            const int lx = e_lx[s], ly = e_ly[s];
+            const int oi = (lx + 2) + (ly + 2) * INW;
+            const T pc = IA[oi];
+            const T fz1 = face_flux(pc, IB[oi], e_qz[s], qzn[s], ew1[s], a.hs1, a.ge, a.hg);
+            const T* qx = Q1Xo + lx + ly * Q1XW;  // q1_x at lx-1, lx, lx+1
+            const T* qy = Q1Yo + lx + ly * MW;     // q1_y at ly-1, ly, ly+1 (stride MW)
+            const T fx0 = face_flux(IA[oi - 1], pc, qx[0], qx[1], eu0[s], a.hs1, a.ge, a.hg);
+            const T fx1 = face_flux(pc, IA[oi + 1], qx[1], qx[2], eu1[s], a.hs1, a.ge, a.hg);
+            const T fy0 = face_flux(IA[oi - INW], pc, qy[0], qy[MW], ev0[s], a.hs1, a.ge, a.hg);
+            const T fy1 = face_flux(pc, IA[oi + INW], qy[MW], qy[2 * MW], ev1[s], a.hs1, a.ge, a.hg);
+            const T f1 = flux_divergence(fx0, fx1, fy0, fy1, e_fz[s], fz1, a.inv_dx);
+            const T base = SWEEP_B ? s_pb[lx + ly * MW] : pc;
+            YM[lx + ly * MW] = fma(a.c_mid, f1, base);
+            if (s == 0) {
+                // own cell: hand plane p's values to E2 (used two iterations later)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    qa_phi[q] = qa_phi[q + 1];
+                    qa_acc[q] = qa_acc[q + 1];
+                    qa_u0[q] = qa_u0[q + 1];
+                    qa_u1[q] = qa_u1[q + 1];
+                    qa_v0[q] = qa_v0[q + 1];
+                    qa_v1[q] = qa_v1[q + 1];
+                    qa_w1[q] = qa_w1[q + 1];
+                }
+                qa_phi[2] = pc;
+                qa_acc[2] = SWEEP_B ? fma(a.c_acc1, f1, eacc) : fma(a.c_acc1, f1, pc);
+                qa_u0[2] = eu0[0];
+                qa_u1[2] = eu1[0];
+                qa_v0[2] = ev0[0];
+                qa_v1[2] = ev1[0];
+                qa_w1[2] = ew1[0];
+            }
+            e_fz[s] = fz1;
+            e_qz[s] = qzn[s];
+        }
+        __syncthreads();  // ya at plane t+2 visible
+
+        if (t >= k0 - 2) {
+            // E2: q2 at plane t+1, outputs of plane t
+            const T* M0 = s_mid + ((it + 1) % 3) * MS;  // plane t   (written at iteration it-2)
+            const T* M1 = s_mid + ((it + 2) % 3) * MS;  // plane t+1 (written at iteration it-1)
+            const T* M2 = YM;                            // plane t+2
+            const int q2new = (it + 1) & 1, q2old = it & 1;
+            const int om = (tx + 2) + (ty + 2) * MW;
+            const T pc1 = M1[om];
+            const T gx = grad1(M1[om + 1], M1[om - 1], inv_2dx);
+            const T gy = grad1(M1[om + MW], M1[om - MW], inv_2dx);
+            const T gz = grad1(M2[om], M0[om], inv_2dx);
+            const T fac = sharpen_factor(pc1, gx, gy, gz, d2);
+            s_q2x[q2new * Q2XS + (tx + 1) + ty * Q2XW] = fac * gx;
+            s_q2y[q2new * Q2YS + tx + (ty + 1) * TX] = fac * gy;
+            const T q2zn = fac * gz;
+            if (has_h2) {
+                const T hgx = grad1(M1[h_om + 1], M1[h_om - 1], inv_2dx);
+                const T hgy = grad1(M1[h_om + MW], M1[h_om - MW], inv_2dx);
+                const T hgz = grad1(M2[h_om], M0[h_om], inv_2dx);
+                const T hf = sharpen_factor(M1[h_om], hgx, hgy, hgz, d2);
+                if (h_axis == 0)
+                    s_q2x[q2new * Q2XS + h_dst] = hf * hgx;
+                else
+                    s_q2y[q2new * Q2YS + h_dst] = hf * hgy;
+            }
+            const T pc = M0[om];
+            const T fz1 = face_flux(pc, pc1, q2z, q2zn, qa_w1[0], a.hs2, a.ge, a.hg);
+            if (t >= k0 && active) {
+                const T* qx = s_q2x + q2old * Q2XS + tx + ty * Q2XW;
+                const T* qy = s_q2y + q2old * Q2YS + tx + ty * TX;
+                const T fx0 = face_flux(M0[om - 1], pc, qx[0], qx[1], qa_u0[0], a.hs2, a.ge, a.hg);
+                const T fx1 = face_flux(pc, M0[om + 1], qx[1], qx[2], qa_u1[0], a.hs2, a.ge, a.hg);
+                const T fy0 = face_flux(M0[om - MW], pc, qy[0], qy[TX], qa_v0[0], a.hs2, a.ge, a.hg);
+                const T fy1 = face_flux(pc, M0[om + MW], qy[TX], qy[2 * TX], qa_v1[0], a.hs2, a.ge, a.hg);
+                const T f2 = flux_divergence(fx0, fx1, fy0, fy1, fz2, fz1, a.inv_dx);
+                const size_t pt = (size_t)t * plane;
+                const unsigned c = e_col[0];  // own cell: (i0+tx, j0+ty), no wrap when active
+                if (!SWEEP_B) stg(a.out_y + pt, c, fma(a.c_y2, f2, qa_phi[0]));
+                stg(a.out_acc + pt, c, fma(a.c_acc2, f2, qa_acc[0]));
+            }
+            fz2 = fz1;
+            q2z = q2zn;
+        }
+    }
+}
+
+}  // namespace pf

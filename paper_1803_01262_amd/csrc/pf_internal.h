@@ -58,15 +58,40 @@ struct AdjArgs {
     T inv_dx, inv_2dx, ge, hg, hs, delta2;
 };
 
-// ------------------------------------------------------------------ launchers (stage.hip)
+// Two RK4 stages in one sweep (pf_fused_body.h): E1 evaluates f on the stage input y over the
+// tile plus a two-cell halo and keeps y_mid = base + c_mid f1 in LDS; E2 evaluates f on y_mid.
+//   sweep A: y = phi;  writes out_y = phi + c_y2 f2 and out_acc = (phi + c_acc1 f1) + c_acc2 f2
+//   sweep B: y = yb, base of y_mid = phi;  writes out_acc = (acc_in + c_acc1 f1) + c_acc2 f2
+template <typename T>
+struct FusedArgs {
+    const T* y;       // E1 stencil input: phi (sweep A) or yb (sweep B)
+    const T* phi;     // phi: base of y_mid and (sweep A) of the outputs
+    const T* acc_in;  // sweep B: accumulator after stage 2 (read at the cell only)
+    T* out_y;         // sweep A: yb
+    T* out_acc;       // sweep A: accumulator;  sweep B: phi' (may alias acc_in)
+    const T* U;
+    const T* V;
+    const T* W;
+    int nx, ny, nz;
+    T inv_dx, inv_2dx, ge, hg, delta2;
+    T hs1, hs2;  // s/2 at the stage time of E1 and of E2
+    T c_mid, c_acc1, c_y2, c_acc2;
+};
+
+// ------------------------------------------------------------------ stage-kernel variants
+// Either a per-stage kernel (four launches per RK4 step) or a fused pair of sweeps (two
+// launches per RK4 step). Every variant produces bit-identical results.
 struct StageVariant {
     const char* name;
-    hipError_t (*launch_f32)(const StageArgs<float>&, hipStream_t);
+    hipError_t (*launch_f32)(const StageArgs<float>&, hipStream_t);    // per-stage
     hipError_t (*launch_f64)(const StageArgs<double>&, hipStream_t);
-    bool (*fits)(int nx, int ny, int nz, int dtype);  // shape/dtype supported by this variant
+    hipError_t (*fused_f32)(const FusedArgs<float>&, bool sweep_b, hipStream_t);  // fused
+    hipError_t (*fused_f64)(const FusedArgs<double>&, bool sweep_b, hipStream_t);
 };
-int stage_variant_count();
-const StageVariant& stage_variant(int v);
+// Variants available for a storage dtype, indexed 0..count-1 (per dtype).
+int stage_variant_count(int dtype);
+const StageVariant& stage_variant(int dtype, int v);
+bool variant_is_fused(int dtype, int v);
 int default_stage_variant(int nx, int ny, int nz, int dtype);
 
 // ------------------------------------------------------------------ batched stages (batch.hip)
@@ -84,7 +109,9 @@ void batch_tile_counts(int nx, int ny, int nz, int* tx, int* ty, int* cz);
 
 // ------------------------------------------------------------------ adjoint (adjoint.hip)
 template <typename T>
-hipError_t launch_adjoint_stage(const AdjArgs<T>& a, hipStream_t st);
+hipError_t launch_adjoint_stage(const AdjArgs<T>& a, hipStream_t st);         // tiled z-march
+template <typename T>
+hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st);  // one thread per cell
 
 // ------------------------------------------------------------------ reduction (reduce.hip)
 constexpr int kReduceBlocks = 1024;

@@ -43,19 +43,20 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
     const bool active = (i < nx) && (j < ny);
     // wrapped coordinates of this thread's column and of its +1 neighbours (face velocities)
     const int iw = wrapn(i, nx), jw = wrapn(j, ny);
-    const size_t col = (size_t)jw * nx + iw;
-    const size_t col_xp = (size_t)jw * nx + wrapn(i + 1, nx);
-    const size_t col_yp = (size_t)wrapn(j + 1, ny) * nx + iw;
+    constexpr unsigned ES = sizeof(T);  // byte offsets within a plane
+    const unsigned col = (unsigned)(jw * nx + iw) * ES;
+    const unsigned col_xp = (unsigned)(jw * nx + wrapn(i + 1, nx)) * ES;
+    const unsigned col_yp = (unsigned)(wrapn(j + 1, ny) * nx + iw) * ES;
 
     // fixed (x, y) sources of this thread's share of every plane load
-    int loff[NL];
+    unsigned loff[NL];
     int lpos[NL];
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
         const int e = tid + s * NT;
         if (e < PS) {
             const int r = e / PW, c = e - r * PW;
-            loff[s] = wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx);
+            loff[s] = (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES;
             lpos[s] = e;
         } else {
             loff[s] = 0;
@@ -64,10 +65,10 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
     }
     T pre[NL];
     auto fetch = [&](int kk) {
-        const T* src = a.y + (size_t)wrapn(kk, nz) * plane;
+        const T* src = a.y + (size_t)wrapz(kk, nz) * plane;
 #pragma unroll
         for (int s = 0; s < NL; ++s)
-            if (lpos[s] >= 0) pre[s] = src[loff[s]];
+            if (lpos[s] >= 0) pre[s] = ldg(src, loff[s]);
     };
     auto commit = [&](int slot) {
 #pragma unroll
@@ -109,18 +110,18 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         if (k + 1 < k1) fetch(k + 3);
 
         // operands from global memory for this plane's outputs (issued early)
-        const size_t pk = (size_t)k * plane;
-        const size_t pk1 = (size_t)wrapn(k + 1, nz) * plane;
+        const size_t pk = (size_t)(k < 0 ? 0 : k) * plane;
+        const size_t pk1 = (size_t)wrapz(k + 1, nz) * plane;
         T u0 = T(0), u1 = T(0), v0 = T(0), v1 = T(0), w1 = T(0), b1 = T(0), b2 = T(0);
         if (active) {
-            w1 = a.W[pk1 + col];
+            w1 = ldg(a.W + pk1, col);
             if (k >= k0) {
-                u0 = a.U[pk + col];
-                u1 = a.U[pk + col_xp];
-                v0 = a.V[pk + col];
-                v1 = a.V[pk + col_yp];
-                if (a.out1) b1 = a.base1[pk + col];
-                if (a.out2) b2 = a.base2[pk + col];
+                u0 = ldg(a.U + pk, col);
+                u1 = ldg(a.U + pk, col_xp);
+                v0 = ldg(a.V + pk, col);
+                v1 = ldg(a.V + pk, col_yp);
+                if (a.out1) b1 = ldg(a.base1 + pk, col);
+                if (a.out2) b2 = ldg(a.base2 + pk, col);
             }
         }
         __syncthreads();
@@ -162,8 +163,8 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
             const T fy0 = face_flux(P0[o - PW], pc, QY[0], QY[TX], v0, a.hs, a.ge, a.hg);
             const T fy1 = face_flux(pc, P0[o + PW], QY[TX], QY[2 * TX], v1, a.hs, a.ge, a.hg);
             const T f = flux_divergence(fx0, fx1, fy0, fy1, fz_prev, fz1, a.inv_dx);
-            if (a.out1) a.out1[pk + col] = fma(a.c1, f, b1);
-            if (a.out2) a.out2[pk + col] = fma(a.c2, f, b2);
+            if (a.out1) stg(a.out1 + pk, col, fma(a.c1, f, b1));
+            if (a.out2) stg(a.out2 + pk, col, fma(a.c2, f, b2));
         }
         fz_prev = fz1;
         qz_cur = qz_next;

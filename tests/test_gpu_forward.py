@@ -64,13 +64,32 @@ def test_rk4_fp64_all_variants_match_oracle_and_each_other(lib, shape):
     pf = lib
     rng = np.random.default_rng(sum(shape))
     phi, U, V, W, dx = random_case(rng, shape)
-    kw = dict(dx=dx, eps=dx, gamma=1.3, dt=0.15 * dx, nsteps=6, delta=0.0)
+    kw = dict(dx=dx, eps=dx, gamma=1.3, dt=0.15 * dx, nsteps=7, delta=0.0)
     ref = oracle.step(phi, U, V, W, **kw)
     outs = []
     for v in range(pf.phasefield_variant_count(pf.PF_F64)):
         print("case", shape, "variant", pf.phasefield_variant_name(pf.PF_F64, v), flush=True)
         outs.append(gpu_run(pf, phi, U, V, W, variant=v, **kw))
         assert rel_linf(outs[-1], ref) <= TOL64, (v, rel_linf(outs[-1], ref))
+    for v, o in enumerate(outs[1:], 1):
+        assert np.array_equal(o, outs[0]), f"variant {v} differs from variant 0"
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 70), (1, 33, 130), (9, 5, 7)])
+def test_fp32_all_variants_match_oracle_and_each_other(lib, shape):
+    """Every FP32 variant (per-stage and fused two-stage sweeps) against the oracle's FP32
+    storage mode, and bit-identical to each other; odd step count."""
+    pf = lib
+    rng = np.random.default_rng(11 + sum(shape))
+    phi, U, V, W, dx = random_case(rng, shape)
+    phi, U, V, W = (a.astype(np.float32).astype(np.float64) for a in (phi, U, V, W))
+    kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.15 * dx, nsteps=5)
+    ref = oracle.step(phi, U, V, W, fp32=True, **kw)
+    outs = []
+    for v in range(pf.phasefield_variant_count(pf.PF_F32)):
+        print("case", shape, "variant", pf.phasefield_variant_name(pf.PF_F32, v), flush=True)
+        outs.append(gpu_run(pf, phi, U, V, W, variant=v, dtype="f32", **kw))
+        assert rel_linf(outs[-1], ref) <= TOL32, (v, rel_linf(outs[-1], ref))
     for v, o in enumerate(outs[1:], 1):
         assert np.array_equal(o, outs[0]), f"variant {v} differs from variant 0"
 
@@ -185,23 +204,28 @@ def test_shift_equivariance_bitwise(lib):
     assert np.array_equal(b, r(a))
 
 
-def test_graph_replay_matches_eager(lib):
+@pytest.mark.parametrize("kind", ["tiled", "fused"])
+def test_graph_replay_matches_eager(lib, kind):
     """Graph replays (8 steps per graph) agree bitwise with plain launches, replay after replay
-    with eager work and synchronisations in between."""
+    with eager work and synchronisations in between; 19 steps = two replays + an odd remainder
+    (which, for a fused variant, ends on the alternate buffer and is copied back)."""
     pf = lib
     rng = np.random.default_rng(11)
     shape = (20, 24, 28)
     phi, U, V, W, dx = random_case(rng, shape)
     st = torch.cuda.Stream()
-    kw = dict(dx=dx, eps=dx, gamma=1.0, dt=0.1 * dx)
+    names = [pf.phasefield_variant_name(pf.PF_F64, v)
+             for v in range(pf.phasefield_variant_count(pf.PF_F64))]
+    variant = [i for i, n in enumerate(names) if n.startswith(kind)][0]
+    kw = dict(dx=dx, eps=dx, gamma=1.0, dt=0.1 * dx, variant=variant)
     sg = pf.Solver((28, 24, 20), use_graph=True, **kw)
     se = pf.Solver((28, 24, 20), use_graph=False, **kw)
     a = [dev(x) for x in (phi, U, V, W)]
     b = [dev(x) for x in (phi, U, V, W)]
     for rep in range(4):
         with torch.cuda.stream(st):
-            sg.step(*a, nsteps=16, stream=st)
-            se.step(*b, nsteps=16, stream=st)
+            sg.step(*a, nsteps=19, stream=st)
+            se.step(*b, nsteps=19, stream=st)
             junk = torch.ones(1000, device="cuda").sum()  # unrelated eager work between replays
         st.synchronize()
         assert float(junk) == 1000.0

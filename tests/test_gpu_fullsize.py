@@ -51,7 +51,7 @@ def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol):
     st = torch.cuda.Stream()
     s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype)
     s.autotune(reps=1, stream=st)
-    print("variant", pf.phasefield_variant_name(0, s.variant), flush=True)
+    print("variant", s.variant_name, flush=True)
     g = [torch.tensor(a, dtype=tdt, device="cuda") for a in inputs]
     m0 = s.reduce(g[0], stream=st)
     with torch.cuda.stream(st):
