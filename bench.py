@@ -25,9 +25,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gcell-updates/s & % HBM peak (fwd, adjoint, batched vs looped) at FP32/FP64 tol"
 HBM_PEAK_GBS = 8000.0
-WORDS_PER_CELL_STEP = 28  # algorithmic words per RK4 cell-update (see stage schedule)
+# algorithmic words per RK4 cell-update: four per-stage sweeps (6 + 8 + 8 + 6) or two fused
+# two-stage sweeps (6 + 7)
+WORDS_PER_CELL_STEP = {"tiled": 28, "global": 28, "fused": 13}
+LAUNCHES_PER_STEP = {"tiled": 4, "global": 4, "fused": 2}
+
+
+def kind(variant_name: str) -> str:
+    return variant_name.split("_")[0]
 KERNEL_SOURCES = ("paper_1803_01262_amd/csrc/pf_tiled_body.h", "paper_1803_01262_amd/csrc/pf_cell.h",
-                  "paper_1803_01262_amd/csrc/stage_tiled.hip")
+                  "paper_1803_01262_amd/csrc/stage_tiled.hip", "paper_1803_01262_amd/csrc/pf_fused_body.h",
+                  "paper_1803_01262_amd/csrc/stage_fused.hip")
 
 
 def kernel_hash() -> str:
@@ -197,14 +205,16 @@ def cpu_baseline(fx, n=128, budget_s=12.0):
                       f"gamma=1.1max|u|), FP32-storage RK4, {steps} steps in {el:.1f} s"}
 
 
-def stored_traffic(khash: str):
+def stored_traffic(khash: str, vname: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken on this exact
+    kernel source and variant (else None)."""
     f = os.path.join(ROOT, "profiles", "stage_traffic_roofline512_f32.json")
     if not os.path.exists(f):
         return None
     d = json.load(open(f))
-    if d.get("kernel_hash") != khash:
+    if d.get("kernel_hash") != khash or d.get("kernel") != vname:
         return None
-    return d
+    return d["bytes_per_launch"]
 
 
 def main():
@@ -251,15 +261,17 @@ def main():
                                             variant=args.variant)
     cells = c.cells
     value = cells / ms / 1e6  # Gcell-updates/s
-    achieved = WORDS_PER_CELL_STEP * esz * cells / ms / 1e6  # GB/s, = per-launch bytes / launch time
+    words, launches = WORDS_PER_CELL_STEP[kind(vname)], LAUNCHES_PER_STEP[kind(vname)]
+    # every step is exactly `launches` launches of the dominant kernel, so algorithmic bytes per
+    # launch over the average launch time equals bytes per step over time per step
+    achieved = words * esz * cells / ms / 1e6  # GB/s
     khash = kernel_hash()
-    tr = stored_traffic(khash)
-    launch_bytes = WORDS_PER_CELL_STEP * esz * cells / 4
+    tr = stored_traffic(khash, vname)
+    launch_bytes = words * esz * cells / launches
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if tr is None else tr["bytes_per_launch"],
-            "algorithmic_bytes_per_launch": int(launch_bytes), "kernel": vname,
-            "kernel_hash": khash}
+            "traffic": tr, "algorithmic_bytes_per_launch": int(launch_bytes),
+            "launches_per_step": launches, "kernel": vname, "kernel_hash": khash}
     del phi, u, v, w
     torch.cuda.empty_cache()
     extras = {"tile_autotune_ms_per_step": tuned,
@@ -272,9 +284,11 @@ def main():
         ms2, vname2, _, _, _ = time_forward(pf, c2, phi2, u2, v2, w2, other, min(args.steps, 200),
                                             5, st, autotune=not args.no_autotune)
         e2 = 8 if other == "f64" else 4
+        w2 = WORDS_PER_CELL_STEP[kind(vname2)]
         extras[f"{other}_{n}"] = {"ms_per_step": round(ms2, 4),
                                   "gcell_s": round(cells / ms2 / 1e6, 2),
-                                  "achieved_gbs": round(WORDS_PER_CELL_STEP * e2 * cells / ms2 / 1e6, 1),
+                                  "achieved_gbs": round(w2 * e2 * cells / ms2 / 1e6, 1),
+                                  "frac_of_8tbs": round(w2 * e2 * cells / ms2 / 1e6 / HBM_PEAK_GBS, 4),
                                   "kernel": vname2}
         del phi2, u2, v2, w2
         torch.cuda.empty_cache()

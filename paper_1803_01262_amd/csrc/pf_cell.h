@@ -95,6 +95,43 @@ __device__ __forceinline__ void stg(T* base, unsigned byte_off, T v)
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// Raw buffer access: a scalar resource descriptor for one plane (base, size in bytes; range
+// checked by the hardware) and a 32-bit byte offset in a vector register. No per-access
+// address arithmetic in vector registers.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t plane_rsrc(const void* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+__device__ __forceinline__ float bload(rsrc_t r, unsigned off, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double bload(rsrc_t r, unsigned off, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, unsigned off)
+{
+    return bload(r, off, T(0));
+}
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned off, double v)
+{
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc_t(), 0, 0, 0)) u64v;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, (int)off, 0, 0);
+}
+
+template <int N>
+struct IntC {
+    static constexpr int value = N;
+};
+
 // Periodic wrap of a plane index for the z-march: the marches reach at most 8 planes outside
 // [0, n); for n >= 8 two compares suffice, smaller grids take the general modulo.
 __device__ __forceinline__ int wrapz(int k, int n)

@@ -158,11 +158,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     }
     T pre_in[NLI];
     T pre_b[NLB > 0 ? NLB : 1];
+    const unsigned pbytes = (unsigned)(plane * sizeof(T));
+    auto prs = [&](const T* base, int kk) { return plane_rsrc(base + (size_t)wrapz(kk, nz) * plane, pbytes); };
     auto fetch_in = [&](int kk) {
-        const T* src = a.y + (size_t)wrapz(kk, nz) * plane;
+        const rsrc_t r = prs(a.y, kk);
 #pragma unroll
         for (int s = 0; s < NLI; ++s)
-            if (li_pos[s] >= 0) pre_in[s] = ldg(src, li_off[s]);
+            if (li_pos[s] >= 0) pre_in[s] = bload<T>(r, li_off[s]);
     };
     auto commit_in = [&](int slot) {
 #pragma unroll
@@ -170,10 +172,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             if (li_pos[s] >= 0) s_in[slot * INS + li_pos[s]] = pre_in[s];
     };
     auto fetch_b = [&](int kk) {
-        const T* src = a.phi + (size_t)wrapz(kk, nz) * plane;
+        const rsrc_t r = prs(a.phi, kk);
 #pragma unroll
         for (int s = 0; s < NLB; ++s)
-            if (lb_pos[s] >= 0) pre_b[s] = ldg(src, lb_off[s]);
+            if (lb_pos[s] >= 0) pre_b[s] = bload<T>(r, lb_off[s]);
     };
     auto commit_b = [&]() {
 #pragma unroll
@@ -199,9 +201,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     fetch_in(tbeg + 4);
     if (SWEEP_B) fetch_b(tbeg + 2);
 
-    int it = 0;
-    for (int t = tbeg; t < k1; ++t, ++it) {
-        const int sa = it % 3, sb = (it + 1) % 3, sc = (it + 2) % 3;  // planes t+2, t+3, t+4
+    // One iteration of the march; R = (t - tbeg) mod 6 fixes every ring slot at compile time.
+    auto iteration = [&](auto RC, int t) {
+        constexpr int R = decltype(RC)::value;
+        constexpr int sa = R % 3, sb = (R + 1) % 3, sc = (R + 2) % 3;  // planes t+2, t+3, t+4
+        constexpr int q1new = (R + 1) & 1, q1old = R & 1;
         commit_in(sc);
         if (SWEEP_B) commit_b();
         if (t + 1 < k1) {
@@ -210,27 +214,22 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         }
         // E1 operands from global memory (plane p = t+2), issued before the barrier
         const int p = t + 2;
-        const size_t pp = (size_t)wrapz(p, nz) * plane;
-        const size_t pp1 = (size_t)wrapz(p + 1, nz) * plane;
-        const T* Up = a.U + pp;
-        const T* Vp = a.V + pp;
-        const T* Wp = a.W + pp1;
+        const rsrc_t rU = prs(a.U, p), rV = prs(a.V, p), rW = prs(a.W, p + 1);
         T eu0[2], eu1[2], ev0[2], ev1[2], ew1[2], eacc = T(0);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            eu0[s] = ldg(Up, e_col[s]);
-            eu1[s] = ldg(Up, e_colx[s]);
-            ev0[s] = ldg(Vp, e_col[s]);
-            ev1[s] = ldg(Vp, e_coly[s]);
-            ew1[s] = ldg(Wp, e_col[s]);
+            eu0[s] = bload<T>(rU, e_col[s]);
+            eu1[s] = bload<T>(rU, e_colx[s]);
+            ev0[s] = bload<T>(rV, e_col[s]);
+            ev1[s] = bload<T>(rV, e_coly[s]);
+            ew1[s] = bload<T>(rW, e_col[s]);
         }
-        if (SWEEP_B) eacc = ldg(a.acc_in + pp, e_col[0]);
+        if (SWEEP_B) eacc = bload<T>(prs(a.acc_in, p), e_col[0]);
         __syncthreads();  // input plane t+4 (and phi plane t+2) visible
 
         const T* IA = s_in + sa * INS;  // plane t+2
         const T* IB = s_in + sb * INS;  // plane t+3
         const T* IC = s_in + sc * INS;  // plane t+4
-        const int q1new = (it + 1) & 1, q1old = it & 1;
         T* Q1Xn = s_q1x + q1new * Q1XS;
         T* Q1Yn = s_q1y + q1new * Q1YS;
         const T* Q1Xo = s_q1x + q1old * Q1XS;
@@ -308,10 +307,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
 
         if (t >= k0 - 2) {
             // E2: q2 at plane t+1, outputs of plane t
-            const T* M0 = s_mid + ((it + 1) % 3) * MS;  // plane t   (written at iteration it-2)
-            const T* M1 = s_mid + ((it + 2) % 3) * MS;  // plane t+1 (written at iteration it-1)
-            const T* M2 = YM;                            // plane t+2
-            const int q2new = (it + 1) & 1, q2old = it & 1;
+            constexpr int m0 = (R + 1) % 3, m1 = (R + 2) % 3;  // planes t, t+1
+            const T* M0 = s_mid + m0 * MS;
+            const T* M1 = s_mid + m1 * MS;
+            const T* M2 = YM;  // plane t+2
+            constexpr int q2new = (R + 1) & 1, q2old = R & 1;
             const int om = (tx + 2) + (ty + 2) * MW;
             const T pc1 = M1[om];
             const T gx = grad1(M1[om + 1], M1[om - 1], inv_2dx);
@@ -341,14 +341,24 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 const T fy0 = face_flux(M0[om - MW], pc, qy[0], qy[TX], qa_v0[0], a.hs2, a.ge, a.hg);
                 const T fy1 = face_flux(pc, M0[om + MW], qy[TX], qy[2 * TX], qa_v1[0], a.hs2, a.ge, a.hg);
                 const T f2 = flux_divergence(fx0, fx1, fy0, fy1, fz2, fz1, a.inv_dx);
-                const size_t pt = (size_t)t * plane;
-                const unsigned c = e_col[0];  // own cell: (i0+tx, j0+ty), no wrap when active
-                if (!SWEEP_B) stg(a.out_y + pt, c, fma(a.c_y2, f2, qa_phi[0]));
-                stg(a.out_acc + pt, c, fma(a.c_acc2, f2, qa_acc[0]));
+                const unsigned c = e_col[0];  // own cell (i0+tx, j0+ty): no wrap when active
+                if (!SWEEP_B) bstore(plane_rsrc(a.out_y + (size_t)t * plane, pbytes), c,
+                                     fma(a.c_y2, f2, qa_phi[0]));
+                bstore(plane_rsrc(a.out_acc + (size_t)t * plane, pbytes), c,
+                       fma(a.c_acc2, f2, qa_acc[0]));
             }
             fz2 = fz1;
             q2z = q2zn;
         }
+    };
+
+    for (int t = tbeg; t < k1; t += 6) {
+        iteration(IntC<0>(), t);
+        if (t + 1 < k1) iteration(IntC<1>(), t + 1);
+        if (t + 2 < k1) iteration(IntC<2>(), t + 2);
+        if (t + 3 < k1) iteration(IntC<3>(), t + 3);
+        if (t + 4 < k1) iteration(IntC<4>(), t + 4);
+        if (t + 5 < k1) iteration(IntC<5>(), t + 5);
     }
 }
 

@@ -64,11 +64,13 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         }
     }
     T pre[NL];
+    const unsigned pbytes = (unsigned)(plane * sizeof(T));
+    auto prs = [&](const T* base, int kk) { return plane_rsrc(base + (size_t)wrapz(kk, nz) * plane, pbytes); };
     auto fetch = [&](int kk) {
-        const T* src = a.y + (size_t)wrapz(kk, nz) * plane;
+        const rsrc_t r = prs(a.y, kk);
 #pragma unroll
         for (int s = 0; s < NL; ++s)
-            if (lpos[s] >= 0) pre[s] = ldg(src, loff[s]);
+            if (lpos[s] >= 0) pre[s] = bload<T>(r, loff[s]);
     };
     auto commit = [&](int slot) {
 #pragma unroll
@@ -102,26 +104,27 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
     fetch(k0);
 
     T qz_cur = T(0), fz_prev = T(0);
-    int it = 0;
-    for (int k = k0 - 2; k < k1; ++k, ++it) {
+    // One iteration of the march; R = (k - k0 + 2) mod 6 fixes every ring slot at compile time.
+    auto iteration = [&](auto RC, int k) {
+        constexpr int R = decltype(RC)::value;
+        constexpr int s0 = R % 3, s1 = (R + 1) % 3, s2 = (R + 2) % 3;  // planes k, k+1, k+2
+        constexpr int q0 = R & 1, q1 = (R + 1) & 1;
         __syncthreads();  // every read of the slots reused below has completed
-        const int s0 = it % 3, s1 = (it + 1) % 3, s2 = (it + 2) % 3;
-        commit(s2);  // plane k+2
+        commit(s2);       // plane k+2
         if (k + 1 < k1) fetch(k + 3);
 
         // operands from global memory for this plane's outputs (issued early)
-        const size_t pk = (size_t)(k < 0 ? 0 : k) * plane;
-        const size_t pk1 = (size_t)wrapz(k + 1, nz) * plane;
         T u0 = T(0), u1 = T(0), v0 = T(0), v1 = T(0), w1 = T(0), b1 = T(0), b2 = T(0);
         if (active) {
-            w1 = ldg(a.W + pk1, col);
+            w1 = bload<T>(prs(a.W, k + 1), col);
             if (k >= k0) {
-                u0 = ldg(a.U + pk, col);
-                u1 = ldg(a.U + pk, col_xp);
-                v0 = ldg(a.V + pk, col);
-                v1 = ldg(a.V + pk, col_yp);
-                if (a.out1) b1 = ldg(a.base1 + pk, col);
-                if (a.out2) b2 = ldg(a.base2 + pk, col);
+                const rsrc_t rU = prs(a.U, k), rV = prs(a.V, k);
+                u0 = bload<T>(rU, col);
+                u1 = bload<T>(rU, col_xp);
+                v0 = bload<T>(rV, col);
+                v1 = bload<T>(rV, col_yp);
+                if (a.out1) b1 = bload<T>(prs(a.base1, k), col);
+                if (a.out2) b2 = bload<T>(prs(a.base2, k), col);
             }
         }
         __syncthreads();
@@ -129,14 +132,13 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         const T* P0 = sp + s0 * PS;  // plane k
         const T* P1 = sp + s1 * PS;  // plane k+1
         const T* P2 = sp + s2 * PS;  // plane k+2
-        const int q0 = it & 1, q1 = (it + 1) & 1;
 
         // sharpening product at plane k+1 for this thread's cell
         const T pc1 = P1[o];
-        T gx = grad1(P1[o + 1], P1[o - 1], inv_2dx);
-        T gy = grad1(P1[o + PW], P1[o - PW], inv_2dx);
-        T gz = grad1(P2[o], P0[o], inv_2dx);
-        T fac = sharpen_factor(pc1, gx, gy, gz, d2);
+        const T gx = grad1(P1[o + 1], P1[o - 1], inv_2dx);
+        const T gy = grad1(P1[o + PW], P1[o - PW], inv_2dx);
+        const T gz = grad1(P2[o], P0[o], inv_2dx);
+        const T fac = sharpen_factor(pc1, gx, gy, gz, d2);
         sqx[q1 * QXS + ty * QXW + tx + 1] = fac * gx;
         sqy[q1 * QYS + (ty + 1) * TX + tx] = fac * gy;
         const T qz_next = fac * gz;
@@ -163,11 +165,20 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
             const T fy0 = face_flux(P0[o - PW], pc, QY[0], QY[TX], v0, a.hs, a.ge, a.hg);
             const T fy1 = face_flux(pc, P0[o + PW], QY[TX], QY[2 * TX], v1, a.hs, a.ge, a.hg);
             const T f = flux_divergence(fx0, fx1, fy0, fy1, fz_prev, fz1, a.inv_dx);
-            if (a.out1) stg(a.out1 + pk, col, fma(a.c1, f, b1));
-            if (a.out2) stg(a.out2 + pk, col, fma(a.c2, f, b2));
+            if (a.out1) bstore(prs(a.out1, k), col, fma(a.c1, f, b1));
+            if (a.out2) bstore(prs(a.out2, k), col, fma(a.c2, f, b2));
         }
         fz_prev = fz1;
         qz_cur = qz_next;
+    };
+
+    for (int k = k0 - 2; k < k1; k += 6) {
+        iteration(IntC<0>(), k);
+        if (k + 1 < k1) iteration(IntC<1>(), k + 1);
+        if (k + 2 < k1) iteration(IntC<2>(), k + 2);
+        if (k + 3 < k1) iteration(IntC<3>(), k + 3);
+        if (k + 4 < k1) iteration(IntC<4>(), k + 4);
+        if (k + 5 < k1) iteration(IntC<5>(), k + 5);
     }
 }
 

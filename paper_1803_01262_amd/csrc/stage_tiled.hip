@@ -62,6 +62,8 @@ hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st);
 
 static const StageVariant kVariants[] = {
     PF_TILED(64, 8, 16),
+    PF_TILED(64, 4, 16),
+    PF_TILED(32, 4, 16),
     PF_TILED(64, 8, 32),
     PF_TILED(64, 8, 64),
     PF_TILED(64, 4, 32),
@@ -118,16 +120,34 @@ bool variant_is_fused(int dtype, int v)
     return dtype == PF_F32 ? s.fused_f32 != nullptr : s.fused_f64 != nullptr;
 }
 
+// Default tile choice before (or without) autotuning: the first variant of a per-dtype
+// preference list (fastest first, as measured on MI355X at 256^3-512^3) whose launch has at
+// least 512 workgroups, i.e. two per compute unit; small grids fall through to small tiles.
 int default_stage_variant(int nx, int ny, int nz, int dtype)
 {
-    // measured on MI355X at 256^3 and 512^3: the fused sweeps win in FP32, the per-stage
-    // kernel in FP64 (there the fused sweeps are limited by issue rate, not by HBM)
-    (void)nx;
-    (void)ny;
-    (void)nz;
-    const char* want = dtype == PF_F32 ? "fused_64x8x64" : "tiled_64x8x32";
+    struct Cand {
+        const char* name;
+        int tx, ty, kz;
+    };
+    static const Cand f32[] = {{"fused_64x8x64", 64, 8, 64}, {"fused_64x8x32", 64, 8, 32},
+                               {"tiled_64x8x16", 64, 8, 16}, {"tiled_64x4x16", 64, 4, 16},
+                               {"tiled_32x4x16", 32, 4, 16}};
+    static const Cand f64[] = {{"tiled_64x8x32", 64, 8, 32}, {"tiled_64x8x16", 64, 8, 16},
+                               {"tiled_64x4x16", 64, 4, 16}, {"tiled_32x4x16", 32, 4, 16}};
+    const Cand* list = dtype == PF_F32 ? f32 : f64;
+    const int n = dtype == PF_F32 ? 5 : 4;
+    int pick = n - 1;
+    for (int c = 0; c < n; ++c) {
+        const long long blocks = (long long)((nx + list[c].tx - 1) / list[c].tx) *
+                                 ((ny + list[c].ty - 1) / list[c].ty) *
+                                 ((nz + list[c].kz - 1) / list[c].kz);
+        if (blocks >= 512) {
+            pick = c;
+            break;
+        }
+    }
     for (int v = 0; v < stage_variant_count(dtype); ++v)
-        if (std::strcmp(stage_variant(dtype, v).name, want) == 0) return v;
+        if (std::strcmp(stage_variant(dtype, v).name, list[pick].name) == 0) return v;
     return 0;
 }
 
