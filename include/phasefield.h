@@ -102,8 +102,9 @@ typedef struct pf_solver pf_solver;
 
 /* Validate p and allocate the handle with its device scratch (three field-sized stage
  * buffers). Errors: PF_ERR_INVALID (n < 1, dx <= 0, eps < 0, gamma < 0, dt <= 0, delta < 0,
- * bad enum, vel_T <= 0 in cos mode, variant out of range), PF_ERR_UNSUPPORTED (wall BC),
- * PF_ERR_OOM, PF_ERR_DEVICE. *out is NULL on failure. */
+ * bad enum, vel_T <= 0 in cos mode, variant out of range, n[1] or n[2] > 65535, an xy plane of
+ * 2^28 cells or more), PF_ERR_UNSUPPORTED (wall BC), PF_ERR_OOM, PF_ERR_DEVICE. *out is NULL on
+ * failure. */
 pf_status phasefield_create(const pf_params *p, pf_solver **out);
 
 /* Release the handle and all its device memory (NULL is accepted). Synchronises the device
@@ -113,6 +114,8 @@ pf_status phasefield_destroy(pf_solver *s);
 /* Advance phi IN PLACE by nsteps steps of the handle's scheme (Sec. 2.3), starting at time
  * t0; step m runs from t0 + m dt. u, v, w: face velocity u0 (the time factor s(t) is applied
  * by the library at the RK4 stage times t, t+dt/2, t+dt/2, t+dt). nsteps = 0 is a no-op.
+ * The handle's stage buffers are overwritten (and, with a fused variant, one of them holds phi
+ * between steps); phi holds the result when the enqueued work completes.
  * Errors: PF_ERR_INVALID (null/misaligned pointer, nsteps < 0), PF_ERR_DEVICE. */
 pf_status phasefield_step(pf_solver *s, void *phi, const void *u, const void *v, const void *w,
                           double t0, int32_t nsteps, void *hip_stream);
@@ -121,7 +124,7 @@ pf_status phasefield_step(pf_solver *s, void *phi, const void *u, const void *v,
  * nsteps = 1, taken at phi_n and time t_n). On entry lam = dL/dphi_{n+1}; on exit
  * lam = dL/dphi_n (in place). gu, gv, gw (may each be NULL to skip) ACCUMULATE
  * dL/du0 etc. (+=). The stage inputs of the forward step are recomputed from phi_n.
- * Allocates five more field-sized scratch buffers on first use.
+ * Allocates three more field-sized scratch buffers on first use.
  * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
@@ -161,10 +164,14 @@ int32_t phasefield_variant_count(int32_t dtype);
 /* Short name of a variant (static string), or NULL if out of range. */
 const char *phasefield_variant_name(int32_t dtype, int32_t variant);
 
-/* Time every variant on the handle's grid (using the handle's scratch only; caller data is
- * untouched), store the fastest as the handle's variant and return it in *best; times_ms
- * (HOST, may be NULL) receives phasefield_variant_count(dtype) per-step times. Synchronises.
- * The choice is cached per (dtype, grid shape) for the life of the process. */
+/* Time every variant on the handle's grid (using the handle's scratch and temporary buffers
+ * only; caller data is untouched), store the fastest as the handle's variant and return it in
+ * *best; times_ms (HOST, may be NULL) receives phasefield_variant_count(dtype) per-step times.
+ * Synchronises. The choice is cached per (dtype, grid shape) for the life of the process and
+ * used by later phasefield_create calls with variant -1; if the environment variable
+ * PF_TUNE_CACHE names a file, the cache is also read from and written to it (one line per
+ * entry: dtype nx ny nz variant-name). Without a cached choice, create picks a default tile
+ * from the grid size. */
 pf_status phasefield_autotune(pf_solver *s, int32_t reps, int32_t *best, double *times_ms,
                               void *hip_stream);
 
@@ -173,15 +180,17 @@ int32_t phasefield_solver_variant(const pf_solver *s);
 
 /* ----------------------------------------------------------------------------------------
  * Batched driver: many independent simulations (each its own pf_params, uneven grid sizes,
- * same dtype and scheme) advanced together. Each RK stage is ONE launch over a global tile
- * list that covers every instance; the step sequence is replayed from a captured HIP graph.
+ * same dtype, RK4, steady velocity) advanced together. Each sweep is ONE persistent launch over
+ * a global tile list that covers every instance (FP32: two fused two-stage sweeps per step;
+ * FP64: four single-stage sweeps); the step sequence is replayed from a captured HIP graph.
  * Results are bit-identical to running each instance alone with phasefield_step.
  * ------------------------------------------------------------------------------------- */
 typedef struct pf_batch pf_batch;
 
-/* per_instance: HOST array of count parameter sets (all with the same dtype and scheme).
- * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtype/scheme), PF_ERR_OOM,
- * PF_ERR_DEVICE. */
+/* per_instance: HOST array of count parameter sets (all with the same dtype).
+ * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtypes), PF_ERR_UNSUPPORTED (a set
+ * with the Euler scheme, a time-varying velocity, or a field of 4 GiB or more: such grids take
+ * a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_batch_create(const pf_params *per_instance, int32_t count, pf_batch **out);
 
 /* Advance every instance b by nsteps steps: phi[b], u[b], v[b], w[b] are HOST arrays of count

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -120,12 +121,57 @@ extern "C" pf_status phasefield_check_params(const pf_params* p, double max_face
 }
 
 // ------------------------------------------------------------------------------ tuning cache
+// Tuned variants per (dtype, grid), kept for the process and, when the environment variable
+// PF_TUNE_CACHE names a file, persisted there as lines "dtype nx ny nz variant_name" (names,
+// not indices, so a cache survives a rebuild that reorders the table; unknown names are
+// ignored).
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int>, int> g_tuned;
+static std::string g_tune_path;  // cache file the in-process table was last read from
+
+static int variant_by_name(int dtype, const char* name)
+{
+    for (int v = 0; v < stage_variant_count(dtype); ++v)
+        if (std::strcmp(stage_variant(dtype, v).name, name) == 0) return v;
+    return -1;
+}
+
+static void load_tune_cache_locked()
+{
+    const char* path = std::getenv("PF_TUNE_CACHE");
+    if (!path || !*path || g_tune_path == path) return;
+    g_tune_path = path;  // (re)read whenever the variable names a different file
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    int d, nx, ny, nz;
+    char name[128];
+    while (std::fscanf(f, "%d %d %d %d %127s", &d, &nx, &ny, &nz, name) == 5) {
+        if (d != PF_F32 && d != PF_F64) continue;
+        const int v = variant_by_name(d, name);
+        if (v >= 0) g_tuned[std::make_tuple(d, nx, ny, nz)] = v;
+    }
+    std::fclose(f);
+}
+
+static void save_tune_cache_locked()
+{
+    const char* path = std::getenv("PF_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto& kv : g_tuned)
+        std::fprintf(f, "%d %d %d %d %s\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                     std::get<2>(kv.first), std::get<3>(kv.first),
+                     stage_variant(std::get<0>(kv.first), kv.second).name);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
 
 int pf::tuned_variant(int dtype, const int32_t n[3])
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
     auto it = g_tuned.find(std::make_tuple(dtype, n[0], n[1], n[2]));
     if (it != g_tuned.end()) return it->second;
     return default_stage_variant(n[0], n[1], n[2], dtype);
@@ -134,7 +180,9 @@ int pf::tuned_variant(int dtype, const int32_t n[3])
 static void store_tuned(int dtype, const int32_t n[3], int v)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache_locked();
     g_tuned[std::make_tuple(dtype, n[0], n[1], n[2])] = v;
+    save_tune_cache_locked();
 }
 
 extern "C" int32_t phasefield_variant_count(int32_t dtype)
@@ -239,11 +287,10 @@ StageArgs<T> pf::make_stage(const pf_params& p, double svel, const T* y, const T
     a.nx = p.n[0];
     a.ny = p.n[1];
     a.nz = p.n[2];
-    a.inv_dx = (T)(1.0 / p.dx);
     a.inv_2dx = (T)(1.0 / (2.0 * p.dx));
-    a.ge = (T)(p.gamma * p.eps / p.dx);
-    a.hg = (T)(0.5 * p.gamma);
-    a.hs = (T)(0.5 * svel);
+    a.ge = (T)(p.gamma * p.eps / (p.dx * p.dx));
+    a.hg = (T)(0.5 * p.gamma / p.dx);
+    a.nhs = (T)(-0.5 * svel / p.dx);
     a.delta2 = (T)(p.delta * p.delta);
     a.c1 = (T)c1;
     a.c2 = (T)c2;
@@ -313,12 +360,12 @@ template hipError_t pf::enqueue_step<double>(const pf_params&, int, double*, con
                                              const double*, const double*, double*, double*,
                                              double*, double, hipStream_t);
 
-// One RK4 step as two fused sweeps (pf_fused_body.h). phi_cur holds phi; the new phi is
-// written to phi_next (the accumulator of sweep A, overwritten in place by sweep B).
+// Arguments of one fused sweep of the RK4 step at time t (pf_fused_body.h): sweep A runs stages
+// 1-2 from phi_cur (writing yb and the accumulator into phi_next), sweep B runs stages 3-4 from
+// yb (writing the new phi over the accumulator in phi_next).
 template <typename T>
-static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* phi_cur,
-                                     T* phi_next, const T* U, const T* V, const T* W, T* yb,
-                                     double t, hipStream_t st)
+FusedArgs<T> pf::make_fused(const pf_params& p, bool sweep_b, double t, const T* phi_cur,
+                            T* phi_next, const T* U, const T* V, const T* W, T* yb)
 {
     const double dt = p.dt;
     FusedArgs<T> a;
@@ -328,47 +375,60 @@ static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* p
     a.nx = p.n[0];
     a.ny = p.n[1];
     a.nz = p.n[2];
-    a.inv_dx = (T)(1.0 / p.dx);
     a.inv_2dx = (T)(1.0 / (2.0 * p.dx));
-    a.ge = (T)(p.gamma * p.eps / p.dx);
-    a.hg = (T)(0.5 * p.gamma);
+    a.ge = (T)(p.gamma * p.eps / (p.dx * p.dx));
+    a.hg = (T)(0.5 * p.gamma / p.dx);
     a.delta2 = (T)(p.delta * p.delta);
-    // sweep A: stages 1 and 2
-    a.y = phi_cur;
     a.phi = phi_cur;
-    a.acc_in = nullptr;
-    a.out_y = yb;
     a.out_acc = phi_next;
-    a.hs1 = (T)(0.5 * time_factor(p, t));
-    a.hs2 = (T)(0.5 * time_factor(p, t + 0.5 * dt));
-    a.c_mid = (T)(0.5 * dt);
-    a.c_acc1 = (T)(dt / 6.0);
-    a.c_y2 = (T)(0.5 * dt);
-    a.c_acc2 = (T)(dt / 3.0);
+    if (!sweep_b) {
+        a.y = phi_cur;
+        a.acc_in = nullptr;
+        a.out_y = yb;
+        a.nhs1 = (T)(-0.5 * time_factor(p, t) / p.dx);
+        a.nhs2 = (T)(-0.5 * time_factor(p, t + 0.5 * dt) / p.dx);
+        a.c_mid = (T)(0.5 * dt);
+        a.c_acc1 = (T)(dt / 6.0);
+        a.c_y2 = (T)(0.5 * dt);
+        a.c_acc2 = (T)(dt / 3.0);
+    } else {
+        a.y = yb;
+        a.acc_in = phi_next;
+        a.out_y = nullptr;
+        a.nhs1 = (T)(-0.5 * time_factor(p, t + 0.5 * dt) / p.dx);
+        a.nhs2 = (T)(-0.5 * time_factor(p, t + dt) / p.dx);
+        a.c_mid = (T)dt;
+        a.c_acc1 = (T)(dt / 3.0);
+        a.c_y2 = (T)0;
+        a.c_acc2 = (T)(dt / 6.0);
+    }
+    return a;
+}
+template FusedArgs<float> pf::make_fused<float>(const pf_params&, bool, double, const float*,
+                                                float*, const float*, const float*, const float*,
+                                                float*);
+template FusedArgs<double> pf::make_fused<double>(const pf_params&, bool, double, const double*,
+                                                  double*, const double*, const double*,
+                                                  const double*, double*);
+
+// One RK4 step as two fused sweeps; the new phi lands in phi_next.
+template <typename T>
+static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* phi_cur,
+                                     T* phi_next, const T* U, const T* V, const T* W, T* yb,
+                                     double t, hipStream_t st)
+{
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
     const StageVariant& sv = stage_variant(dtype, variant);
-    hipError_t e;
-    if constexpr (sizeof(T) == 4)
-        e = sv.fused_f32(a, false, st);
-    else
-        e = sv.fused_f64(a, false, st);
-    if (e != hipSuccess) return e;
-    // sweep B: stages 3 and 4
-    a.y = yb;
-    a.phi = phi_cur;
-    a.acc_in = phi_next;
-    a.out_y = nullptr;
-    a.out_acc = phi_next;
-    a.hs1 = (T)(0.5 * time_factor(p, t + 0.5 * dt));
-    a.hs2 = (T)(0.5 * time_factor(p, t + dt));
-    a.c_mid = (T)dt;
-    a.c_acc1 = (T)(dt / 3.0);
-    a.c_y2 = (T)0;
-    a.c_acc2 = (T)(dt / 6.0);
-    if constexpr (sizeof(T) == 4)
-        return sv.fused_f32(a, true, st);
-    else
-        return sv.fused_f64(a, true, st);
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        const FusedArgs<T> a = make_fused<T>(p, sweep == 1, t, phi_cur, phi_next, U, V, W, yb);
+        hipError_t e;
+        if constexpr (sizeof(T) == 4)
+            e = sv.fused_f32(a, sweep == 1, st);
+        else
+            e = sv.fused_f64(a, sweep == 1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // nsteps steps from t0 (step m at t0 + m dt), phi updated in place. A fused variant alternates

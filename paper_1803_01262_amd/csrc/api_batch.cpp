@@ -1,5 +1,13 @@
-// C ABI: batched driver. Each RK4 stage of every instance runs in ONE persistent launch over a
-// global tile list; the step sequence is captured once into a HIP graph and replayed.
+// C ABI: batched driver. Every instance of the batch advances together: each sweep is ONE
+// persistent launch over a global tile list that covers all instances, and the step sequence
+// is captured once into a HIP graph and replayed.
+//
+// Two modes, chosen by storage dtype as for single solves:
+//   FP32: fused two-stage sweeps (two launches per step). phi alternates with the accumulator
+//         buffer from step to step; tables for even and odd steps are kept, and after an odd
+//         step count one batched copy returns phi to the caller's buffers.
+//   FP64: per-stage sweeps (four launches per step), fixed buffers.
+// Either way every instance is bit-identical to its own single solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,15 +21,18 @@ using namespace pf;
 struct pf_batch {
     int count = 0;
     int dtype = PF_F64;
+    bool fused = false;
     std::vector<pf_params> p;
     std::vector<size_t> N;
-    void* pool = nullptr;                // stage buffers of every instance
-    std::vector<size_t> pool_off;        // element offset of instance b's ya (yb, acc follow)
+    void* pool = nullptr;          // stage buffers of every instance (ya, yb, acc each)
+    std::vector<size_t> pool_off;  // element offset of instance b's first buffer
     int total_tiles = 0;
     int grid_blocks = 0;
-    int* owner = nullptr;                // device: instance of each global tile
-    void* tables[4] = {nullptr, nullptr, nullptr, nullptr};  // device BatchEntry<T>[count] per stage
-    std::vector<const void*> key;        // pointer set the tables and graph were built for
+    int* owner = nullptr;  // device: instance of each global tile
+    // device tables: per-stage mode S1..S4; fused mode A_even, B_even, A_odd, B_odd
+    void* tables[4] = {nullptr, nullptr, nullptr, nullptr};
+    void* copies = nullptr;        // device BatchCopy<T>[count]: acc -> phi after an odd count
+    std::vector<const void*> key;  // pointer set the tables and graph were built for
     hipStream_t key_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -42,11 +53,14 @@ extern "C" pf_status phasefield_batch_destroy(pf_batch* b)
     batch_release_graph(b);
     if (b->pool) (void)hipFree(b->pool);
     if (b->owner) (void)hipFree(b->owner);
+    if (b->copies) (void)hipFree(b->copies);
     for (void* t : b->tables)
         if (t) (void)hipFree(t);
     delete b;
     return PF_OK;
 }
+
+static size_t padded(size_t n) { return (n + 63) / 64 * 64; }  // keeps buffers 256-byte aligned
 
 extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int32_t count,
                                              pf_batch** out)
@@ -63,10 +77,15 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
             return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver runs RK4 only", b);
         if (per_instance[b].vel_mode != PF_VEL_STEADY)
             return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver needs a steady velocity", b);
+        const pf_params& q = per_instance[b];
+        if (field_needs_big(q.n[0], q.n[1], q.n[2], q.dtype == PF_F32 ? 4 : 8))
+            return fail(PF_ERR_UNSUPPORTED,
+                        "instance %d: a field of 4 GiB or more; use a single-grid solver", b);
     }
     auto* B = new pf_batch();
     B->count = count;
     B->dtype = per_instance[0].dtype;
+    B->fused = B->dtype == PF_F32;
     B->p.assign(per_instance, per_instance + count);
     const size_t esz = B->dtype == PF_F32 ? sizeof(float) : sizeof(double);
     size_t total = 0;
@@ -75,9 +94,9 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
         const size_t n = (size_t)B->p[b].n[0] * B->p[b].n[1] * B->p[b].n[2];
         B->N.push_back(n);
         B->pool_off.push_back(total);
-        total += 3 * ((n + 63) / 64 * 64);  // keep every buffer 256-byte aligned
+        total += 3 * padded(n);
         int tx, ty, cz;
-        batch_tile_counts(B->p[b].n[0], B->p[b].n[1], B->p[b].n[2], &tx, &ty, &cz);
+        batch_tile_counts(B->fused, B->p[b].n[0], B->p[b].n[1], B->p[b].n[2], &tx, &ty, &cz);
         for (int t = 0; t < tx * ty * cz; ++t) owner.push_back(b);
     }
     B->total_tiles = (int)owner.size();
@@ -90,8 +109,14 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
     if (e == hipSuccess) e = hipMalloc((void**)&B->owner, owner.size() * sizeof(int));
     if (e == hipSuccess)
         e = hipMemcpy(B->owner, owner.data(), owner.size() * sizeof(int), hipMemcpyHostToDevice);
-    const size_t tsz = B->dtype == PF_F32 ? sizeof(BatchEntry<float>) : sizeof(BatchEntry<double>);
+    size_t tsz;
+    if (B->fused)
+        tsz = B->dtype == PF_F32 ? sizeof(FusedBatchEntry<float>) : sizeof(FusedBatchEntry<double>);
+    else
+        tsz = B->dtype == PF_F32 ? sizeof(BatchEntry<float>) : sizeof(BatchEntry<double>);
     for (int s = 0; s < 4 && e == hipSuccess; ++s) e = hipMalloc(&B->tables[s], tsz * count);
+    if (e == hipSuccess)
+        e = hipMalloc(&B->copies, (B->dtype == PF_F32 ? sizeof(BatchCopy<float>) : sizeof(BatchCopy<double>)) * count);
     if (e != hipSuccess) {
         phasefield_batch_destroy(B);
         return hip_fail(e, "phasefield_batch_create: allocation");
@@ -100,52 +125,70 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
     return PF_OK;
 }
 
-// Build the four RK4 stage tables for one pointer set (same schedule as the single solve:
-// S1 ya = phi + dt/2 k1, acc = phi + dt/6 k1; S2 yb = phi + dt/2 k2, acc += dt/3 k2;
-// S3 ya = phi + dt k3, acc += dt/3 k3; S4 phi = acc + dt/6 k4).
+// Build the device tables for one pointer set.
+//   per-stage: S1 ya = phi + dt/2 k1, acc = phi + dt/6 k1;  S2 yb = phi + dt/2 k2, acc += dt/3 k2;
+//              S3 ya = phi + dt k3, acc += dt/3 k3;        S4 phi = acc + dt/6 k4.
+//   fused:     even steps run from phi into acc, odd steps from acc back into phi.
 template <typename T>
 static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const* u,
                                const void* const* v, const void* const* w)
 {
-    std::vector<BatchEntry<T>> tab[4];
+    std::vector<BatchEntry<T>> st_tab[4];
+    std::vector<FusedBatchEntry<T>> fu_tab[4];
+    std::vector<BatchCopy<T>> copies;
     int tile = 0;
     for (int b = 0; b < B->count; ++b) {
         const pf_params& p = B->p[b];
         T* ph = (T*)phi[b];
         const T *U = (const T*)u[b], *V = (const T*)v[b], *W = (const T*)w[b];
         T* base = (T*)B->pool + B->pool_off[b];
-        const size_t stride = (B->N[b] + 63) / 64 * 64;
+        const size_t stride = padded(B->N[b]);
         T *ya = base, *yb = base + stride, *acc = base + 2 * stride;
-        const double dt = p.dt;
-        StageArgs<T> st[4] = {
-            make_stage<T>(p, 1.0, ph, ph, ph, ya, acc, 0.5 * dt, dt / 6.0, U, V, W),
-            make_stage<T>(p, 1.0, ya, ph, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W),
-            make_stage<T>(p, 1.0, yb, ph, acc, ya, acc, dt, dt / 3.0, U, V, W),
-            make_stage<T>(p, 1.0, ya, nullptr, acc, nullptr, ph, 0.0, dt / 6.0, U, V, W)};
         int tx, ty, cz;
-        batch_tile_counts(p.n[0], p.n[1], p.n[2], &tx, &ty, &cz);
-        for (int s = 0; s < 4; ++s) {
-            BatchEntry<T> e;
-            e.a = st[s];
-            e.tile_begin = tile;
-            e.tiles_x = tx;
-            e.tiles_y = ty;
-            e.chunks_z = cz;
-            tab[s].push_back(e);
+        batch_tile_counts(B->fused, p.n[0], p.n[1], p.n[2], &tx, &ty, &cz);
+        if (B->fused) {
+            const FusedArgs<T> f[4] = {make_fused<T>(p, false, 0.0, ph, acc, U, V, W, yb),
+                                       make_fused<T>(p, true, 0.0, ph, acc, U, V, W, yb),
+                                       make_fused<T>(p, false, 0.0, acc, ph, U, V, W, yb),
+                                       make_fused<T>(p, true, 0.0, acc, ph, U, V, W, yb)};
+            for (int s = 0; s < 4; ++s) fu_tab[s].push_back({f[s], tile, tx, ty, cz});
+        } else {
+            const double dt = p.dt;
+            const StageArgs<T> sa[4] = {
+                make_stage<T>(p, 1.0, ph, ph, ph, ya, acc, 0.5 * dt, dt / 6.0, U, V, W),
+                make_stage<T>(p, 1.0, ya, ph, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W),
+                make_stage<T>(p, 1.0, yb, ph, acc, ya, acc, dt, dt / 3.0, U, V, W),
+                make_stage<T>(p, 1.0, ya, nullptr, acc, nullptr, ph, 0.0, dt / 6.0, U, V, W)};
+            for (int s = 0; s < 4; ++s) st_tab[s].push_back({sa[s], tile, tx, ty, cz});
         }
+        copies.push_back({acc, ph, B->N[b]});
         tile += tx * ty * cz;
     }
     for (int s = 0; s < 4; ++s) {
-        hipError_t e = hipMemcpy(B->tables[s], tab[s].data(), sizeof(BatchEntry<T>) * B->count,
-                                 hipMemcpyHostToDevice);
+        hipError_t e = B->fused ? hipMemcpy(B->tables[s], fu_tab[s].data(),
+                                            sizeof(FusedBatchEntry<T>) * B->count, hipMemcpyHostToDevice)
+                                : hipMemcpy(B->tables[s], st_tab[s].data(),
+                                            sizeof(BatchEntry<T>) * B->count, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: table upload");
     }
+    hipError_t e = hipMemcpy(B->copies, copies.data(), sizeof(BatchCopy<T>) * B->count,
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: table upload");
     return PF_OK;
 }
 
+// One step; `odd` selects the fused tables of an odd step within a call.
 template <typename T>
-static hipError_t enqueue_batch_step(pf_batch* B, hipStream_t st)
+static hipError_t enqueue_batch_step(pf_batch* B, bool odd, hipStream_t st)
 {
+    if (B->fused) {
+        for (int s = 0; s < 2; ++s) {
+            hipError_t e = launch_batch_fused<T>((const FusedBatchEntry<T>*)B->tables[(odd ? 2 : 0) + s],
+                                                 s == 1, B->owner, B->total_tiles, B->grid_blocks, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     for (int s = 0; s < 4; ++s) {
         hipError_t e = launch_batch_stage<T>((const BatchEntry<T>*)B->tables[s], B->owner,
                                              B->total_tiles, B->grid_blocks, st);
@@ -176,13 +219,15 @@ static pf_status batch_step_impl(pf_batch* B, void* const* phi, const void* cons
         B->key = key;
     }
     int32_t done = 0;
+    // the captured sequence has an even number of steps, so phi is back in place after each replay
     if (st != nullptr && nsteps >= kGraphSteps) {
         if (!B->exec || B->key_stream != st) {
             batch_release_graph(B);
             hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: begin capture");
             hipError_t le = hipSuccess;
-            for (int m = 0; m < kGraphSteps && le == hipSuccess; ++m) le = enqueue_batch_step<T>(B, st);
+            for (int m = 0; m < kGraphSteps && le == hipSuccess; ++m)
+                le = enqueue_batch_step<T>(B, (m & 1) != 0, st);
             e = hipStreamEndCapture(st, &B->graph);
             if (le != hipSuccess) return hip_fail(le, "phasefield_batch_step: launch during capture");
             if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: end capture");
@@ -195,9 +240,14 @@ static pf_status batch_step_impl(pf_batch* B, void* const* phi, const void* cons
         }
     }
     B->key_stream = st;
-    for (; done < nsteps; ++done) {
-        hipError_t e = enqueue_batch_step<T>(B, st);
+    const int32_t rest = nsteps - done;
+    for (int32_t m = 0; m < rest; ++m) {
+        hipError_t e = enqueue_batch_step<T>(B, (m & 1) != 0, st);
         if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: launch");
+    }
+    if (B->fused && (rest & 1)) {
+        hipError_t e = launch_batch_copy<T>((const BatchCopy<T>*)B->copies, B->count, st);
+        if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: copy back");
     }
     return PF_OK;
 }

@@ -45,6 +45,10 @@ hipError_t enqueue_steps(const pf_params& p, int variant, T* phi, const T* U, co
                          const T* W, T* ya, T* yb, T* acc, double t0, int nsteps,
                          hipStream_t st);
 
+template <typename T>
+FusedArgs<T> make_fused(const pf_params& p, bool sweep_b, double t, const T* phi_cur, T* phi_next,
+                        const T* U, const T* V, const T* W, T* yb);
+
 // One stage launch with the per-stage kernel of a variant (fused variants use variant 0).
 template <typename T>
 hipError_t run_stage(int variant, const StageArgs<T>& a, hipStream_t st);

@@ -7,7 +7,6 @@
 
 namespace pf {
 
-__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 
 // Central gradient component from the two neighbours along one axis (step 1).
@@ -19,36 +18,60 @@ __device__ __forceinline__ T grad1(T p_plus, T p_minus, T inv_2dx)
 
 // 1 / sqrt(|g|^2 + delta^2), and 0 where that vanishes: the unit normal is then 0, the
 // reading of sgn(0) = 0 for a flat field (steps 1-2).
-template <typename T>
-__device__ __forceinline__ T inv_mag(T gx, T gy, T gz, T delta2)
+// FP32 uses the hardware reciprocal square root (1 ulp) on an argument clamped at the smallest
+// normal number. The clamp keeps the result finite, so a flat cell (g = 0) still gets n = g r = 0
+// without a compare; |g|^2 + delta^2 is subnormal only where phi itself is below ~1e-19, and
+// there the sharpening product phi (1 - phi) n is below ~1e-19 whatever the normal.
+__device__ __forceinline__ float inv_mag(float gx, float gy, float gz, float delta2)
 {
-    const T m2 = fma(gx, gx, fma(gy, gy, fma(gz, gz, delta2)));
-    return m2 > T(0) ? rsq(m2) : T(0);
+    const float m2 = fmaf(gx, gx, fmaf(gy, gy, fmaf(gz, gz, delta2)));
+    return __builtin_amdgcn_rsqf(fmaxf(m2, 1.17549435e-38f));
+}
+__device__ __forceinline__ double inv_mag(double gx, double gy, double gz, double delta2)
+{
+    const double m2 = fma(gx, gx, fma(gy, gy, fma(gz, gz, delta2)));
+    return m2 > 0.0 ? rsq(m2) : 0.0;
 }
 
-// Sharpening product q = phi (1 - phi) n at a cell centre (step 2), returned as the common
-// factor phi (1 - phi) / |g|; q_a = factor * g_a.
+// Sharpening product at a cell centre (step 2), pre-scaled for the flux: returns
+// hg * phi (1 - phi) / |g| with hg = gamma / (2 dx), so that q'_a = factor * g_a is the cell's
+// share gamma q_a / (2 dx) of the face-averaged sharpening flux.
 template <typename T>
-__device__ __forceinline__ T sharpen_factor(T p, T gx, T gy, T gz, T delta2)
+__device__ __forceinline__ T sharpen_factor(T p, T gx, T gy, T gz, T delta2, T hg)
 {
-    return (p * (T(1) - p)) * inv_mag(gx, gy, gz, delta2);
+    return ((p * (T(1) - p)) * inv_mag(gx, gy, gz, delta2)) * hg;
 }
 
-// Total flux on the face between cells m (low side) and c (high side) (steps 3-4):
-//   F = -s u (phi_m + phi_c)/2 + gamma eps (phi_c - phi_m)/dx - gamma (q_m + q_c)/2
-// hs = s/2, ge = gamma eps/dx, hg = gamma/2.
+// Per face, between cells lo and hi: the sum (for the face mean of phi) and the difference (for
+// the diffusive flux) of the two stage-input values.
 template <typename T>
-__device__ __forceinline__ T face_flux(T pm, T pc, T qm, T qc, T u, T hs, T ge, T hg)
-{
-    const T adv = (-hs * u) * (pm + pc);
-    return fma(-hg, qm + qc, fma(ge, pc - pm, adv));
-}
+__device__ __forceinline__ T face_sum(T p_lo, T p_hi) { return p_lo + p_hi; }
+template <typename T>
+__device__ __forceinline__ T face_diff(T p_lo, T p_hi) { return p_hi - p_lo; }
 
-// Divergence of the six face fluxes of a cell (step 5).
+// f = d(phi)/dt at a cell (steps 3-5): the divergence of its six face fluxes
+//   F_a = -s u_a (phi_lo + phi_hi)/2 + gamma eps (phi_hi - phi_lo)/dx - gamma (q_lo + q_hi)/2,
+// with the fluxes of each axis' high (+) and low (-) face summed per term:
+//   f = nhs * sum_a [u_a+ S_a+ - u_a- S_a-] + ge * sum_a [D_a+ - D_a-] - sum_a [q'_a+ - q'_a-]
+// where S, D are the face sums and differences above, nhs = -s/(2 dx), ge = gamma eps / dx^2,
+// and q'_a+ / q'_a- the pre-scaled sharpening products of the two neighbours along axis a (the
+// cell's own q cancels between its two faces). Exactly the flux difference of the recipe,
+// regrouped; every variant evaluates it through this one function, in this order.
 template <typename T>
-__device__ __forceinline__ T flux_divergence(T fx0, T fx1, T fy0, T fy1, T fz0, T fz1, T inv_dx)
+__device__ __forceinline__ T cell_rhs(T sxm, T sxp, T sym, T syp, T szm, T szp,
+                                      T dxm, T dxp, T dym, T dyp, T dzm, T dzp,
+                                      T qxm, T qxp, T qym, T qyp, T qzm, T qzp,
+                                      T u0, T u1, T v0, T v1, T w0, T w1, T nhs, T ge)
 {
-    return (((fx1 - fx0) + (fy1 - fy0)) + (fz1 - fz0)) * inv_dx;
+    T adv = u1 * sxp;
+    adv = fma(-u0, sxm, adv);
+    adv = fma(v1, syp, adv);
+    adv = fma(-v0, sym, adv);
+    adv = fma(w1, szp, adv);
+    adv = fma(-w0, szm, adv);
+    const T dif = ((dxp - dxm) + (dyp - dym)) + (dzp - dzm);
+    const T shp = ((qxp - qxm) + (qyp - qym)) + (qzp - qzm);
+    return fma(nhs, adv, fma(ge, dif, -shp));
 }
 
 // ---------------------------------------------------------------- adjoint (transpose) helpers
@@ -132,11 +155,61 @@ struct IntC {
     static constexpr int value = N;
 };
 
-// Periodic wrap of a plane index for the z-march: the marches reach at most 8 planes outside
-// [0, n); for n >= 8 two compares suffice, smaller grids take the general modulo.
+__device__ __forceinline__ float bload_so(rsrc_t r, unsigned off, unsigned soff, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+}
+__device__ __forceinline__ double bload_so(rsrc_t r, unsigned off, unsigned soff, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore_so(rsrc_t r, unsigned off, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore_so(rsrc_t r, unsigned off, unsigned soff, double v)
+{
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc_t(), 0, 0, 0)) u64v;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, (int)off, (int)soff, 0);
+}
+
+// One field (an array of nz planes) for the z-marches. Element (plane kw, byte offset off in
+// the plane) is addressed with one descriptor for the whole array, the plane offset kw * pbytes
+// in the scalar soffset operand and off in a vector register. Arrays of 4 GiB or more (BIG)
+// take a descriptor per plane instead, since buffer offsets are 32-bit.
+template <typename T, bool BIG>
+struct FieldRef {
+    const T* base;
+    rsrc_t whole;
+    unsigned pbytes;
+    size_t pelems;
+    __device__ __forceinline__ FieldRef(const T* b, size_t plane_elems, int nplanes)
+        : base(b), pbytes((unsigned)(plane_elems * sizeof(T))), pelems(plane_elems)
+    {
+        whole = plane_rsrc(b, BIG ? 0u : (unsigned)(plane_elems * sizeof(T) * (size_t)nplanes));
+    }
+    __device__ __forceinline__ T load(int kw, unsigned off) const
+    {
+        if constexpr (BIG)
+            return bload<T>(plane_rsrc(base + (size_t)kw * pelems, pbytes), off);
+        else
+            return bload_so(whole, off, (unsigned)kw * pbytes, T(0));
+    }
+    __device__ __forceinline__ void store(int kw, unsigned off, T v) const
+    {
+        if constexpr (BIG)
+            bstore(plane_rsrc(base + (size_t)kw * pelems, pbytes), off, v);
+        else
+            bstore_so(whole, off, (unsigned)kw * pbytes, v);
+    }
+};
+
+// Periodic wrap of a plane index for the z-march: the marches (with the iterations that pad a
+// chunk to whole groups of six) reach at most 10 planes outside [0, n); for n >= 16 two compares
+// suffice, smaller grids take the general modulo.
 __device__ __forceinline__ int wrapz(int k, int n)
 {
-    if (n >= 8) return k < 0 ? k + n : (k >= n ? k - n : k);
+    if (n >= 16) return k < 0 ? k + n : (k >= n ? k - n : k);
     k %= n;
     return k < 0 ? k + n : k;
 }

@@ -25,7 +25,11 @@
 //   PB   phi on MID (sweep B only), 1 plane
 // Pipeline: iteration t loads input plane t+4, E1 computes q1 at plane t+3 and ya at plane
 // t+2, E2 computes q2 at plane t+1 and the outputs of plane t. Six warm-up iterations precede
-// the first output plane of a z-chunk. Two barriers per iteration.
+// the first output plane of a z-chunk: four with E1 alone (a straight-line prologue), then the
+// main loop, which runs E1 and E2 in whole groups of six unconditional iterations so that the
+// values handed from plane to plane stay in place; iterations past the chunk end compute on
+// wrapped planes and store nothing. Two barriers per iteration.
+// Global memory goes through FieldRef buffer descriptors (BIG: arrays of 4 GiB or more).
 #pragma once
 
 #include "pf_cell.h"
@@ -33,7 +37,7 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, int KZ, bool SWEEP_B>
+template <typename T, int TX, int TY, int KZ, bool SWEEP_B, bool BIG>
 __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int tk)
 {
     constexpr int NT = TX * TY;
@@ -66,7 +70,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const bool active = (i0 + tx < nx) && (j0 + ty < ny);
-    const T inv_2dx = a.inv_2dx, d2 = a.delta2;
+    const T inv_2dx = a.inv_2dx, d2 = a.delta2, hg = a.hg, ge = a.ge;
 
     // ---- E1 cell slots: slot 0 = own cell, slot 1 = a MID ring cell (tid < NRING)
     int e_lx[2], e_ly[2];
@@ -158,13 +162,14 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     }
     T pre_in[NLI];
     T pre_b[NLB > 0 ? NLB : 1];
-    const unsigned pbytes = (unsigned)(plane * sizeof(T));
-    auto prs = [&](const T* base, int kk) { return plane_rsrc(base + (size_t)wrapz(kk, nz) * plane, pbytes); };
+    const FieldRef<T, BIG> fy(a.y, plane, nz), fphi(a.phi, plane, nz), facc(a.acc_in, plane, nz),
+        foy(a.out_y, plane, nz), foacc(a.out_acc, plane, nz), fU(a.U, plane, nz),
+        fV(a.V, plane, nz), fW(a.W, plane, nz);
     auto fetch_in = [&](int kk) {
-        const rsrc_t r = prs(a.y, kk);
+        const int kw = wrapz(kk, nz);
 #pragma unroll
         for (int s = 0; s < NLI; ++s)
-            if (li_pos[s] >= 0) pre_in[s] = bload<T>(r, li_off[s]);
+            if (li_pos[s] >= 0) pre_in[s] = fy.load(kw, li_off[s]);
     };
     auto commit_in = [&](int slot) {
 #pragma unroll
@@ -172,10 +177,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             if (li_pos[s] >= 0) s_in[slot * INS + li_pos[s]] = pre_in[s];
     };
     auto fetch_b = [&](int kk) {
-        const rsrc_t r = prs(a.phi, kk);
+        const int kw = wrapz(kk, nz);
 #pragma unroll
         for (int s = 0; s < NLB; ++s)
-            if (lb_pos[s] >= 0) pre_b[s] = bload<T>(r, lb_off[s]);
+            if (lb_pos[s] >= 0) pre_b[s] = fphi.load(kw, lb_off[s]);
     };
     auto commit_b = [&]() {
 #pragma unroll
@@ -184,8 +189,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     };
 
     // per-slot z state of E1 (q1_z and the z-face flux) and of E2
-    T e_qz[2] = {T(0), T(0)}, e_fz[2] = {T(0), T(0)};
-    T q2z = T(0), fz2 = T(0);
+    // per-slot z state of E1 at plane p: q1_z at p-1 and p, sum and difference of phi on the
+    // face (p-1, p), W at p; the same for E2 at plane t
+    T e_qzm[2] = {T(0), T(0)}, e_qz[2] = {T(0), T(0)}, e_sz[2] = {T(0), T(0)};
+    T e_dz[2] = {T(0), T(0)}, e_w0[2] = {T(0), T(0)};
+    T q2zm = T(0), q2z = T(0), sz2 = T(0), dz2 = T(0), w2 = T(0);
     // own-cell queues from E1 (plane p) to E2 (plane p, two iterations later): after E1 of
     // iteration t they hold planes t, t+1, t+2 in entries 0, 1, 2
     T qa_phi[3] = {T(0), T(0), T(0)}, qa_acc[3] = {T(0), T(0), T(0)};
@@ -201,30 +209,29 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     fetch_in(tbeg + 4);
     if (SWEEP_B) fetch_b(tbeg + 2);
 
-    // One iteration of the march; R = (t - tbeg) mod 6 fixes every ring slot at compile time.
-    auto iteration = [&](auto RC, int t) {
+    // One iteration of the march; R = (t - tbeg) mod 6 fixes every ring slot at compile time,
+    // WITH_E2 whether the second evaluation runs.
+    auto iteration = [&](auto RC, auto E2C, int t) {
         constexpr int R = decltype(RC)::value;
+        constexpr bool WITH_E2 = decltype(E2C)::value != 0;
         constexpr int sa = R % 3, sb = (R + 1) % 3, sc = (R + 2) % 3;  // planes t+2, t+3, t+4
         constexpr int q1new = (R + 1) & 1, q1old = R & 1;
         commit_in(sc);
         if (SWEEP_B) commit_b();
-        if (t + 1 < k1) {
-            fetch_in(t + 5);
-            if (SWEEP_B) fetch_b(t + 3);
-        }
+        fetch_in(t + 5);
+        if (SWEEP_B) fetch_b(t + 3);
         // E1 operands from global memory (plane p = t+2), issued before the barrier
-        const int p = t + 2;
-        const rsrc_t rU = prs(a.U, p), rV = prs(a.V, p), rW = prs(a.W, p + 1);
+        const int pw = wrapz(t + 2, nz), pw1 = wrapz(t + 3, nz);
         T eu0[2], eu1[2], ev0[2], ev1[2], ew1[2], eacc = T(0);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            eu0[s] = bload<T>(rU, e_col[s]);
-            eu1[s] = bload<T>(rU, e_colx[s]);
-            ev0[s] = bload<T>(rV, e_col[s]);
-            ev1[s] = bload<T>(rV, e_coly[s]);
-            ew1[s] = bload<T>(rW, e_col[s]);
+            eu0[s] = fU.load(pw, e_col[s]);
+            eu1[s] = fU.load(pw, e_colx[s]);
+            ev0[s] = fV.load(pw, e_col[s]);
+            ev1[s] = fV.load(pw, e_coly[s]);
+            ew1[s] = fW.load(pw1, e_col[s]);
         }
-        if (SWEEP_B) eacc = bload<T>(prs(a.acc_in, p), e_col[0]);
+        if (SWEEP_B) eacc = facc.load(pw, e_col[0]);
         __syncthreads();  // input plane t+4 (and phi plane t+2) visible
 
         const T* IA = s_in + sa * INS;  // plane t+2
@@ -248,7 +255,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             const T gx = grad1(IB[oi + 1], IB[oi - 1], inv_2dx);
             const T gy = grad1(IB[oi + INW], IB[oi - INW], inv_2dx);
             const T gz = grad1(IC[oi], IA[oi], inv_2dx);
-            const T fac = sharpen_factor(IB[oi], gx, gy, gz, d2);
+            const T fac = sharpen_factor(IB[oi], gx, gy, gz, d2, hg);
             Q1Xn[(e_lx[s] + 1) + e_ly[s] * Q1XW] = fac * gx;
             Q1Yn[e_lx[s] + (e_ly[s] + 1) * MW] = fac * gy;
             qzn[s] = fac * gz;
@@ -257,7 +264,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             const T gx = grad1(IB[o_in + 1], IB[o_in - 1], inv_2dx);
             const T gy = grad1(IB[o_in + INW], IB[o_in - INW], inv_2dx);
             const T gz = grad1(IC[o_in], IA[o_in], inv_2dx);
-            const T fac = sharpen_factor(IB[o_in], gx, gy, gz, d2);
+            const T fac = sharpen_factor(IB[o_in], gx, gy, gz, d2, hg);
             if (o_axis == 0)
                 Q1Xn[o_dst] = fac * gx;
             else
@@ -270,14 +277,16 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             const int lx = e_lx[s], ly = e_ly[s];
             const int oi = (lx + 2) + (ly + 2) * INW;
             const T pc = IA[oi];
-            const T fz1 = face_flux(pc, IB[oi], e_qz[s], qzn[s], ew1[s], a.hs1, a.ge, a.hg);
+            const T pz = IB[oi];
+            const T szp = face_sum(pc, pz), dzp = face_diff(pc, pz);
             const T* qx = Q1Xo + lx + ly * Q1XW;  // q1_x at lx-1, lx, lx+1
             const T* qy = Q1Yo + lx + ly * MW;     // q1_y at ly-1, ly, ly+1 (stride MW)
-            const T fx0 = face_flux(IA[oi - 1], pc, qx[0], qx[1], eu0[s], a.hs1, a.ge, a.hg);
-            const T fx1 = face_flux(pc, IA[oi + 1], qx[1], qx[2], eu1[s], a.hs1, a.ge, a.hg);
-            const T fy0 = face_flux(IA[oi - INW], pc, qy[0], qy[MW], ev0[s], a.hs1, a.ge, a.hg);
-            const T fy1 = face_flux(pc, IA[oi + INW], qy[MW], qy[2 * MW], ev1[s], a.hs1, a.ge, a.hg);
-            const T f1 = flux_divergence(fx0, fx1, fy0, fy1, e_fz[s], fz1, a.inv_dx);
+            const T pxm = IA[oi - 1], pxp = IA[oi + 1], pym = IA[oi - INW], pyp = IA[oi + INW];
+            const T f1 = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc),
+                                  face_sum(pc, pyp), e_sz[s], szp, face_diff(pxm, pc),
+                                  face_diff(pc, pxp), face_diff(pym, pc), face_diff(pc, pyp), e_dz[s],
+                                  dzp, qx[0], qx[2], qy[0], qy[2 * MW], e_qzm[s], qzn[s], eu0[s],
+                                  eu1[s], ev0[s], ev1[s], e_w0[s], ew1[s], a.nhs1, ge);
             const T base = SWEEP_B ? s_pb[lx + ly * MW] : pc;
             YM[lx + ly * MW] = fma(a.c_mid, f1, base);
             if (s == 0) {
@@ -300,12 +309,15 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 qa_v1[2] = ev1[0];
                 qa_w1[2] = ew1[0];
             }
-            e_fz[s] = fz1;
+            e_sz[s] = szp;
+            e_dz[s] = dzp;
+            e_qzm[s] = e_qz[s];
             e_qz[s] = qzn[s];
+            e_w0[s] = ew1[s];
         }
         __syncthreads();  // ya at plane t+2 visible
 
-        if (t >= k0 - 2) {
+        if constexpr (WITH_E2) {
             // E2: q2 at plane t+1, outputs of plane t
             constexpr int m0 = (R + 1) % 3, m1 = (R + 2) % 3;  // planes t, t+1
             const T* M0 = s_mid + m0 * MS;
@@ -317,7 +329,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             const T gx = grad1(M1[om + 1], M1[om - 1], inv_2dx);
             const T gy = grad1(M1[om + MW], M1[om - MW], inv_2dx);
             const T gz = grad1(M2[om], M0[om], inv_2dx);
-            const T fac = sharpen_factor(pc1, gx, gy, gz, d2);
+            const T fac = sharpen_factor(pc1, gx, gy, gz, d2, hg);
             s_q2x[q2new * Q2XS + (tx + 1) + ty * Q2XW] = fac * gx;
             s_q2y[q2new * Q2YS + tx + (ty + 1) * TX] = fac * gy;
             const T q2zn = fac * gz;
@@ -325,40 +337,48 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 const T hgx = grad1(M1[h_om + 1], M1[h_om - 1], inv_2dx);
                 const T hgy = grad1(M1[h_om + MW], M1[h_om - MW], inv_2dx);
                 const T hgz = grad1(M2[h_om], M0[h_om], inv_2dx);
-                const T hf = sharpen_factor(M1[h_om], hgx, hgy, hgz, d2);
+                const T hf = sharpen_factor(M1[h_om], hgx, hgy, hgz, d2, hg);
                 if (h_axis == 0)
                     s_q2x[q2new * Q2XS + h_dst] = hf * hgx;
                 else
                     s_q2y[q2new * Q2YS + h_dst] = hf * hgy;
             }
             const T pc = M0[om];
-            const T fz1 = face_flux(pc, pc1, q2z, q2zn, qa_w1[0], a.hs2, a.ge, a.hg);
-            if (t >= k0 && active) {
+            const T szp = face_sum(pc, pc1), dzp = face_diff(pc, pc1);
+            if (t >= k0 && t < k1 && active) {
                 const T* qx = s_q2x + q2old * Q2XS + tx + ty * Q2XW;
                 const T* qy = s_q2y + q2old * Q2YS + tx + ty * TX;
-                const T fx0 = face_flux(M0[om - 1], pc, qx[0], qx[1], qa_u0[0], a.hs2, a.ge, a.hg);
-                const T fx1 = face_flux(pc, M0[om + 1], qx[1], qx[2], qa_u1[0], a.hs2, a.ge, a.hg);
-                const T fy0 = face_flux(M0[om - MW], pc, qy[0], qy[TX], qa_v0[0], a.hs2, a.ge, a.hg);
-                const T fy1 = face_flux(pc, M0[om + MW], qy[TX], qy[2 * TX], qa_v1[0], a.hs2, a.ge, a.hg);
-                const T f2 = flux_divergence(fx0, fx1, fy0, fy1, fz2, fz1, a.inv_dx);
+                const T pxm = M0[om - 1], pxp = M0[om + 1], pym = M0[om - MW], pyp = M0[om + MW];
+                const T f2 = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc),
+                                      face_sum(pc, pyp), sz2, szp, face_diff(pxm, pc),
+                                      face_diff(pc, pxp), face_diff(pym, pc), face_diff(pc, pyp),
+                                      dz2, dzp, qx[0], qx[2], qy[0], qy[2 * TX], q2zm, q2zn,
+                                      qa_u0[0], qa_u1[0], qa_v0[0], qa_v1[0], w2, qa_w1[0], a.nhs2,
+                                      ge);
                 const unsigned c = e_col[0];  // own cell (i0+tx, j0+ty): no wrap when active
-                if (!SWEEP_B) bstore(plane_rsrc(a.out_y + (size_t)t * plane, pbytes), c,
-                                     fma(a.c_y2, f2, qa_phi[0]));
-                bstore(plane_rsrc(a.out_acc + (size_t)t * plane, pbytes), c,
-                       fma(a.c_acc2, f2, qa_acc[0]));
+                if (!SWEEP_B) foy.store(t, c, fma(a.c_y2, f2, qa_phi[0]));
+                foacc.store(t, c, fma(a.c_acc2, f2, qa_acc[0]));
             }
-            fz2 = fz1;
+            sz2 = szp;
+            dz2 = dzp;
+            q2zm = q2z;
             q2z = q2zn;
+            w2 = qa_w1[0];
         }
     };
 
-    for (int t = tbeg; t < k1; t += 6) {
-        iteration(IntC<0>(), t);
-        if (t + 1 < k1) iteration(IntC<1>(), t + 1);
-        if (t + 2 < k1) iteration(IntC<2>(), t + 2);
-        if (t + 3 < k1) iteration(IntC<3>(), t + 3);
-        if (t + 4 < k1) iteration(IntC<4>(), t + 4);
-        if (t + 5 < k1) iteration(IntC<5>(), t + 5);
+    iteration(IntC<0>(), IntC<0>(), tbeg);
+    iteration(IntC<1>(), IntC<0>(), tbeg + 1);
+    iteration(IntC<2>(), IntC<0>(), tbeg + 2);
+    iteration(IntC<3>(), IntC<0>(), tbeg + 3);
+    const int tend = k0 - 2 + 6 * ((k1 - k0 + 7) / 6);  // k0-2 .. k1-1, in groups of six
+    for (int t = k0 - 2; t < tend; t += 6) {
+        iteration(IntC<4>(), IntC<1>(), t);
+        iteration(IntC<5>(), IntC<1>(), t + 1);
+        iteration(IntC<0>(), IntC<1>(), t + 2);
+        iteration(IntC<1>(), IntC<1>(), t + 3);
+        iteration(IntC<2>(), IntC<1>(), t + 4);
+        iteration(IntC<3>(), IntC<1>(), t + 5);
     }
 }
 

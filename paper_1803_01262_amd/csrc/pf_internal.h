@@ -25,11 +25,11 @@ struct StageArgs {
     const T* V;
     const T* W;
     int nx, ny, nz;
-    T inv_dx;   // 1 / dx
+    // Flux coefficients carry the 1/dx of the divergence, so face fluxes are summed directly.
     T inv_2dx;  // 1 / (2 dx), central gradient
-    T ge;       // gamma * eps / dx, diffusive flux coefficient
-    T hg;       // gamma / 2, sharpening flux (face mean of q)
-    T hs;       // s(t) / 2, advective flux (face mean of phi)
+    T ge;       // gamma eps / dx^2, diffusive flux
+    T hg;       // gamma / (2 dx), sharpening flux (face mean of q), folded into q
+    T nhs;      // -s(t) / (2 dx), advective flux (face mean of phi)
     T delta2;   // delta^2, |grad phi| regulariser
     T c1, c2;
 };
@@ -73,10 +73,17 @@ struct FusedArgs {
     const T* V;
     const T* W;
     int nx, ny, nz;
-    T inv_dx, inv_2dx, ge, hg, delta2;
-    T hs1, hs2;  // s/2 at the stage time of E1 and of E2
+    T inv_2dx, ge, hg, delta2;  // as in StageArgs
+    T nhs1, nhs2;               // -s / (2 dx) at the stage time of E1 and of E2
     T c_mid, c_acc1, c_y2, c_acc2;
 };
+
+// An array of nx*ny*nz elements of `es` bytes needs the per-plane buffer descriptors of the
+// z-marches (buffer offsets are 32-bit) when it spans 4 GiB or more.
+inline bool field_needs_big(int nx, int ny, int nz, size_t es)
+{
+    return (size_t)nx * (size_t)ny * (size_t)nz * es > 0xffffffffull;
+}
 
 // ------------------------------------------------------------------ stage-kernel variants
 // Either a per-stage kernel (four launches per RK4 step) or a fused pair of sweeps (two
@@ -105,7 +112,25 @@ struct BatchEntry {
 template <typename T>
 hipError_t launch_batch_stage(const BatchEntry<T>* table_dev, const int* owner_dev, int total_tiles,
                               int grid_blocks, hipStream_t st);
-void batch_tile_counts(int nx, int ny, int nz, int* tx, int* ty, int* cz);
+// Fused mode (two-stage sweeps): per-instance sweep arguments plus tile bookkeeping.
+template <typename T>
+struct FusedBatchEntry {
+    FusedArgs<T> a;
+    int tile_begin;
+    int tiles_x, tiles_y, chunks_z;
+};
+template <typename T>
+struct BatchCopy {
+    const T* src;
+    T* dst;
+    size_t n;
+};
+template <typename T>
+hipError_t launch_batch_fused(const FusedBatchEntry<T>* table_dev, bool sweep_b, const int* owner_dev,
+                              int total_tiles, int grid_blocks, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream_t st);
+void batch_tile_counts(bool fused, int nx, int ny, int nz, int* tx, int* ty, int* cz);
 
 // ------------------------------------------------------------------ adjoint (adjoint.hip)
 template <typename T>

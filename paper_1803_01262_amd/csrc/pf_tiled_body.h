@@ -6,11 +6,15 @@
 // with a two-cell halo (the reach of the sharpening term: the normal at a face neighbour needs
 // its own neighbours), and the x- and y-components of the sharpening product q = phi(1-phi)n of
 // the current and next plane (with a one-cell halo in their own direction only); the
-// z-component of q and the z-face flux stay in registers and are handed from one plane to the
-// next. Every q is computed once per cell plus the halo ring, every face flux once per face
-// except the x/y faces on the tile edge. The next plane is prefetched into registers while the
-// current one is computed. Grids smaller than a tile, and ragged tiles, work through periodic
+// z-components of q of the planes below and above, the z-face sum and difference of phi and
+// the z-face velocity stay in registers and are handed from one plane to the next. Every q is
+// computed once per cell plus the halo ring. The next plane is prefetched into registers while
+// the current one is computed. Grids smaller than a tile, and ragged tiles, work through periodic
 // wrapping of every load; only the writes are masked.
+//
+// Global memory is read and written through buffer descriptors (FieldRef): one per array, the
+// plane offset in a scalar register, so no address arithmetic runs in vector registers. BIG
+// selects the per-plane descriptor form needed for arrays of 4 GiB or more.
 #pragma once
 
 #include "pf_cell.h"
@@ -18,7 +22,7 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, int KZ>
+template <typename T, int TX, int TY, int KZ, bool BIG>
 __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, int tj, int tk)
 {
     constexpr int NT = TX * TY;
@@ -64,13 +68,14 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         }
     }
     T pre[NL];
-    const unsigned pbytes = (unsigned)(plane * sizeof(T));
-    auto prs = [&](const T* base, int kk) { return plane_rsrc(base + (size_t)wrapz(kk, nz) * plane, pbytes); };
+    const FieldRef<T, BIG> fy(a.y, plane, nz), fU(a.U, plane, nz), fV(a.V, plane, nz),
+        fW(a.W, plane, nz), fb1(a.base1, plane, nz), fb2(a.base2, plane, nz),
+        fo1(a.out1, plane, nz), fo2(a.out2, plane, nz);
     auto fetch = [&](int kk) {
-        const rsrc_t r = prs(a.y, kk);
+        const int kw = wrapz(kk, nz);
 #pragma unroll
         for (int s = 0; s < NL; ++s)
-            if (lpos[s] >= 0) pre[s] = bload<T>(r, loff[s]);
+            if (lpos[s] >= 0) pre[s] = fy.load(kw, loff[s]);
     };
     auto commit = [&](int slot) {
 #pragma unroll
@@ -94,7 +99,7 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         h_axis = 1;
     }
 
-    const T inv_2dx = a.inv_2dx, d2 = a.delta2;
+    const T inv_2dx = a.inv_2dx, d2 = a.delta2, hg = a.hg, nhs = a.nhs, ge = a.ge;
     const int o = (ty + 2) * PW + (tx + 2);  // this thread's cell in a plane of sp
 
     fetch(k0 - 2);
@@ -103,29 +108,32 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
     commit(1);
     fetch(k0);
 
-    T qz_cur = T(0), fz_prev = T(0);
+    // z state handed from plane to plane: q_z at k-1 and k, the face (k-1, k) and W at k
+    T qz_m1 = T(0), qz_cur = T(0), szm = T(0), dzm = T(0), w0 = T(0);
     // One iteration of the march; R = (k - k0 + 2) mod 6 fixes every ring slot at compile time.
+    // The march runs in whole groups of six unconditional iterations (so the values handed from
+    // plane to plane stay in place); iterations past the chunk end only compute, on wrapped
+    // planes, and store nothing.
     auto iteration = [&](auto RC, int k) {
         constexpr int R = decltype(RC)::value;
         constexpr int s0 = R % 3, s1 = (R + 1) % 3, s2 = (R + 2) % 3;  // planes k, k+1, k+2
         constexpr int q0 = R & 1, q1 = (R + 1) & 1;
         __syncthreads();  // every read of the slots reused below has completed
         commit(s2);       // plane k+2
-        if (k + 1 < k1) fetch(k + 3);
+        fetch(k + 3);
+        const bool out_plane = k >= k0 && k < k1;
 
-        // operands from global memory for this plane's outputs (issued early)
-        T u0 = T(0), u1 = T(0), v0 = T(0), v1 = T(0), w1 = T(0), b1 = T(0), b2 = T(0);
-        if (active) {
-            w1 = bload<T>(prs(a.W, k + 1), col);
-            if (k >= k0) {
-                const rsrc_t rU = prs(a.U, k), rV = prs(a.V, k);
-                u0 = bload<T>(rU, col);
-                u1 = bload<T>(rU, col_xp);
-                v0 = bload<T>(rV, col);
-                v1 = bload<T>(rV, col_yp);
-                if (a.out1) b1 = bload<T>(prs(a.base1, k), col);
-                if (a.out2) b2 = bload<T>(prs(a.base2, k), col);
-            }
+        // operands from global memory for this plane's outputs (issued early); lanes outside the
+        // grid read their wrapped column, in bounds, and store nothing
+        const T w1 = fW.load(wrapz(k + 1, nz), col);
+        T u0, u1, v0, v1, b1, b2;
+        if (out_plane) {
+            u0 = fU.load(k, col);
+            u1 = fU.load(k, col_xp);
+            v0 = fV.load(k, col);
+            v1 = fV.load(k, col_yp);
+            if (a.out1) b1 = fb1.load(k, col);
+            if (a.out2) b2 = fb2.load(k, col);
         }
         __syncthreads();
 
@@ -138,7 +146,7 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         const T gx = grad1(P1[o + 1], P1[o - 1], inv_2dx);
         const T gy = grad1(P1[o + PW], P1[o - PW], inv_2dx);
         const T gz = grad1(P2[o], P0[o], inv_2dx);
-        const T fac = sharpen_factor(pc1, gx, gy, gz, d2);
+        const T fac = sharpen_factor(pc1, gx, gy, gz, d2, hg);
         sqx[q1 * QXS + ty * QXW + tx + 1] = fac * gx;
         sqy[q1 * QYS + (ty + 1) * TX + tx] = fac * gy;
         const T qz_next = fac * gz;
@@ -147,7 +155,7 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
             const T hgx = grad1(P1[h_o + 1], P1[h_o - 1], inv_2dx);
             const T hgy = grad1(P1[h_o + PW], P1[h_o - PW], inv_2dx);
             const T hgz = grad1(P2[h_o], P0[h_o], inv_2dx);
-            const T hf = sharpen_factor(P1[h_o], hgx, hgy, hgz, d2);
+            const T hf = sharpen_factor(P1[h_o], hgx, hgy, hgz, d2, hg);
             if (h_axis == 0)
                 sqx[q1 * QXS + h_dst] = hf * hgx;
             else
@@ -155,30 +163,34 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         }
 
         const T pc = P0[o];
-        // flux through the z-face between planes k and k+1
-        const T fz1 = face_flux(pc, pc1, qz_cur, qz_next, w1, a.hs, a.ge, a.hg);
-        if (k >= k0 && active) {
+        // z-face between planes k and k+1
+        const T szp = face_sum(pc, pc1), dzp = face_diff(pc, pc1);
+        if (out_plane && active) {
             const T* QX = sqx + q0 * QXS + ty * QXW + tx;  // q_x at i-1, i, i+1
             const T* QY = sqy + q0 * QYS + ty * TX + tx;   // q_y at j-1, j, j+1 (stride TX)
-            const T fx0 = face_flux(P0[o - 1], pc, QX[0], QX[1], u0, a.hs, a.ge, a.hg);
-            const T fx1 = face_flux(pc, P0[o + 1], QX[1], QX[2], u1, a.hs, a.ge, a.hg);
-            const T fy0 = face_flux(P0[o - PW], pc, QY[0], QY[TX], v0, a.hs, a.ge, a.hg);
-            const T fy1 = face_flux(pc, P0[o + PW], QY[TX], QY[2 * TX], v1, a.hs, a.ge, a.hg);
-            const T f = flux_divergence(fx0, fx1, fy0, fy1, fz_prev, fz1, a.inv_dx);
-            if (a.out1) bstore(prs(a.out1, k), col, fma(a.c1, f, b1));
-            if (a.out2) bstore(prs(a.out2, k), col, fma(a.c2, f, b2));
+            const T pxm = P0[o - 1], pxp = P0[o + 1], pym = P0[o - PW], pyp = P0[o + PW];
+            const T f = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc),
+                                 face_sum(pc, pyp), szm, szp, face_diff(pxm, pc), face_diff(pc, pxp),
+                                 face_diff(pym, pc), face_diff(pc, pyp), dzm, dzp, QX[0], QX[2],
+                                 QY[0], QY[2 * TX], qz_m1, qz_next, u0, u1, v0, v1, w0, w1, nhs, ge);
+            if (a.out1) fo1.store(k, col, fma(a.c1, f, b1));
+            if (a.out2) fo2.store(k, col, fma(a.c2, f, b2));
         }
-        fz_prev = fz1;
+        szm = szp;
+        dzm = dzp;
+        qz_m1 = qz_cur;
         qz_cur = qz_next;
+        w0 = w1;
     };
 
-    for (int k = k0 - 2; k < k1; k += 6) {
+    const int kend = k0 - 2 + 6 * ((k1 - k0 + 7) / 6);  // k0-2 .. k1-1, in groups of six
+    for (int k = k0 - 2; k < kend; k += 6) {
         iteration(IntC<0>(), k);
-        if (k + 1 < k1) iteration(IntC<1>(), k + 1);
-        if (k + 2 < k1) iteration(IntC<2>(), k + 2);
-        if (k + 3 < k1) iteration(IntC<3>(), k + 3);
-        if (k + 4 < k1) iteration(IntC<4>(), k + 4);
-        if (k + 5 < k1) iteration(IntC<5>(), k + 5);
+        iteration(IntC<1>(), k + 1);
+        iteration(IntC<2>(), k + 2);
+        iteration(IntC<3>(), k + 3);
+        iteration(IntC<4>(), k + 4);
+        iteration(IntC<5>(), k + 5);
     }
 }
 

@@ -24,24 +24,19 @@ __global__ void __launch_bounds__(256) stage_global_kernel(StageArgs<T> a)
         const T gx = grad1(at(di + 1, dj, dk), at(di - 1, dj, dk), a.inv_2dx);
         const T gy = grad1(at(di, dj + 1, dk), at(di, dj - 1, dk), a.inv_2dx);
         const T gz = grad1(at(di, dj, dk + 1), at(di, dj, dk - 1), a.inv_2dx);
-        const T fac = sharpen_factor(at(di, dj, dk), gx, gy, gz, a.delta2);
+        const T fac = sharpen_factor(at(di, dj, dk), gx, gy, gz, a.delta2, a.hg);
         return fac * (ax == 0 ? gx : (ax == 1 ? gy : gz));
     };
     const size_t c = idx(0, 0, 0);
     const T pc = y[c];
-    const T gx = grad1(at(1, 0, 0), at(-1, 0, 0), a.inv_2dx);
-    const T gy = grad1(at(0, 1, 0), at(0, -1, 0), a.inv_2dx);
-    const T gz = grad1(at(0, 0, 1), at(0, 0, -1), a.inv_2dx);
-    const T fac = sharpen_factor(pc, gx, gy, gz, a.delta2);
-    const T qx = fac * gx, qy = fac * gy, qz = fac * gz;
-
-    const T fx0 = face_flux(at(-1, 0, 0), pc, qcomp(-1, 0, 0, 0), qx, a.U[c], a.hs, a.ge, a.hg);
-    const T fx1 = face_flux(pc, at(1, 0, 0), qx, qcomp(1, 0, 0, 0), a.U[idx(1, 0, 0)], a.hs, a.ge, a.hg);
-    const T fy0 = face_flux(at(0, -1, 0), pc, qcomp(0, -1, 0, 1), qy, a.V[c], a.hs, a.ge, a.hg);
-    const T fy1 = face_flux(pc, at(0, 1, 0), qy, qcomp(0, 1, 0, 1), a.V[idx(0, 1, 0)], a.hs, a.ge, a.hg);
-    const T fz0 = face_flux(at(0, 0, -1), pc, qcomp(0, 0, -1, 2), qz, a.W[c], a.hs, a.ge, a.hg);
-    const T fz1 = face_flux(pc, at(0, 0, 1), qz, qcomp(0, 0, 1, 2), a.W[idx(0, 0, 1)], a.hs, a.ge, a.hg);
-    const T f = flux_divergence(fx0, fx1, fy0, fy1, fz0, fz1, a.inv_dx);
+    const T pxm = at(-1, 0, 0), pxp = at(1, 0, 0), pym = at(0, -1, 0), pyp = at(0, 1, 0);
+    const T pzm = at(0, 0, -1), pzp = at(0, 0, 1);
+    const T f = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc), face_sum(pc, pyp),
+                         face_sum(pzm, pc), face_sum(pc, pzp), face_diff(pxm, pc), face_diff(pc, pxp),
+                         face_diff(pym, pc), face_diff(pc, pyp), face_diff(pzm, pc), face_diff(pc, pzp),
+                         qcomp(-1, 0, 0, 0), qcomp(1, 0, 0, 0), qcomp(0, -1, 0, 1), qcomp(0, 1, 0, 1),
+                         qcomp(0, 0, -1, 2), qcomp(0, 0, 1, 2), a.U[c], a.U[idx(1, 0, 0)], a.V[c],
+                         a.V[idx(0, 1, 0)], a.W[c], a.W[idx(0, 0, 1)], a.nhs, a.ge);
     if (a.out1) a.out1[c] = fma(a.c1, f, a.base1[c]);
     if (a.out2) a.out2[c] = fma(a.c2, f, a.base2[c]);
 }

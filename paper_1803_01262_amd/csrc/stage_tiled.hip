@@ -16,7 +16,7 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, int KZ>
+template <typename T, int TX, int TY, int KZ, bool BIG>
 __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int tiles_x,
                                                              int tiles_y)
 {
@@ -29,10 +29,12 @@ __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int tk = b / tiles_y;
-    tiled_stage_body<T, TX, TY, KZ>(a, ti, tj, tk);
+    tiled_stage_body<T, TX, TY, KZ, BIG>(a, ti, tj, tk);
 }
 
-template <typename T, int TX, int TY, int KZ>
+// FORCE_BIG selects the per-plane descriptor form even for small arrays (it is what arrays of
+// 4 GiB or more take), so that form can be checked against the default one at any size.
+template <typename T, int TX, int TY, int KZ, bool FORCE_BIG>
 hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
 {
     const int tiles_x = (a.nx + TX - 1) / TX;
@@ -40,25 +42,29 @@ hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
     const int chunks = (a.nz + KZ - 1) / KZ;
     const long long blocks = (long long)tiles_x * tiles_y * chunks;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, KZ>), dim3((unsigned)blocks), dim3(TX * TY),
-                       0, st, a, tiles_x, tiles_y);
+    if (FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T)))
+        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, KZ, true>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+    else
+        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, KZ, false>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_stage_global(const StageArgs<T>& a, hipStream_t st);
-template <typename T, int TX, int TY, int KZ>
+template <typename T, int TX, int TY, int KZ, bool FORCE_BIG>
 hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st);
 
 #define PF_TILED(TX, TY, KZ)                                                            \
-    {"tiled_" #TX "x" #TY "x" #KZ, launch_stage_tiled<float, TX, TY, KZ>,               \
-     launch_stage_tiled<double, TX, TY, KZ>, nullptr, nullptr}
+    {"tiled_" #TX "x" #TY "x" #KZ, launch_stage_tiled<float, TX, TY, KZ, false>,        \
+     launch_stage_tiled<double, TX, TY, KZ, false>, nullptr, nullptr}
 #define PF_FUSED(TX, TY, KZ)                                                            \
-    {"fused_" #TX "x" #TY "x" #KZ, nullptr, nullptr, launch_fused<float, TX, TY, KZ>,   \
-     launch_fused<double, TX, TY, KZ>}
+    {"fused_" #TX "x" #TY "x" #KZ, nullptr, nullptr,                                    \
+     launch_fused<float, TX, TY, KZ, false>, launch_fused<double, TX, TY, KZ, false>}
 #define PF_FUSED32(TX, TY, KZ)                                                          \
-    {"fused_" #TX "x" #TY "x" #KZ, nullptr, nullptr, launch_fused<float, TX, TY, KZ>,   \
-     nullptr}
+    {"fused_" #TX "x" #TY "x" #KZ, nullptr, nullptr,                                    \
+     launch_fused<float, TX, TY, KZ, false>, nullptr}
 
 static const StageVariant kVariants[] = {
     PF_TILED(64, 8, 16),
@@ -73,9 +79,16 @@ static const StageVariant kVariants[] = {
     {"global", launch_stage_global<float>, launch_stage_global<double>, nullptr, nullptr},
     PF_FUSED(64, 8, 32),
     PF_FUSED(64, 8, 64),
+    PF_FUSED(32, 16, 32),
+    PF_FUSED(32, 16, 64),
     PF_FUSED32(64, 16, 32),
     PF_FUSED32(64, 16, 64),
     PF_FUSED32(128, 8, 32),
+    // the large-array addressing form, forced (selected automatically at 4 GiB per array)
+    {"tiled_64x8x16_big", launch_stage_tiled<float, 64, 8, 16, true>,
+     launch_stage_tiled<double, 64, 8, 16, true>, nullptr, nullptr},
+    {"fused_64x8x32_big", nullptr, nullptr, launch_fused<float, 64, 8, 32, true>,
+     launch_fused<double, 64, 8, 32, true>},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 

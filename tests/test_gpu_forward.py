@@ -255,3 +255,28 @@ def test_argument_errors(lib):
                                                t.data_ptr(), 0.0, 1, 0))
     assert ei.value.status == pf.PF_ERR_INVALID
     s.close()
+
+
+def test_autotune_and_persistent_cache(lib, tmp_path, monkeypatch):
+    """phasefield_autotune times every variant, the winner is used by later handles of the same
+    shape, and PF_TUNE_CACHE persists choices by variant name."""
+    pf = lib
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PF_TUNE_CACHE", str(cache))
+    s = pf.Solver((48, 40, 36), 1 / 48, 1 / 48, 1.0, 0.1 / 48, dtype="f32")
+    best, times = s.autotune(reps=1)
+    assert len(times) == pf.phasefield_variant_count(pf.PF_F32) and all(t > 0 for t in times.values())
+    name = pf.phasefield_variant_name(pf.PF_F32, best)
+    assert s.variant == best and times[name] == min(times.values())
+    s.close()
+    assert cache.read_text().split() == ["0", "48", "40", "36", name]
+    s2 = pf.Solver((48, 40, 36), 1 / 48, 1 / 48, 1.0, 0.1 / 48, dtype="f32")
+    assert s2.variant == best
+    s2.close()
+    # a cache written by hand (by name) is honoured once the variable points at it
+    other = tmp_path / "other.txt"
+    other.write_text("1 40 40 40 tiled_32x4x16\n1 40 40 40 no_such_variant\n")
+    monkeypatch.setenv("PF_TUNE_CACHE", str(other))
+    s3 = pf.Solver((40, 40, 40), 1 / 40, 1 / 40, 1.0, 0.1 / 40, dtype="f64")
+    assert s3.variant_name == "tiled_32x4x16"
+    s3.close()
