@@ -35,7 +35,9 @@ def kind(variant_name: str) -> str:
     return variant_name.split("_")[0]
 KERNEL_SOURCES = ("paper_1803_01262_amd/csrc/pf_tiled_body.h", "paper_1803_01262_amd/csrc/pf_cell.h",
                   "paper_1803_01262_amd/csrc/stage_tiled.hip", "paper_1803_01262_amd/csrc/pf_fused_body.h",
-                  "paper_1803_01262_amd/csrc/stage_fused.hip")
+                  "paper_1803_01262_amd/csrc/pf_fused_launch.h",
+                  "paper_1803_01262_amd/csrc/stage_fused_f32.hip",
+                  "paper_1803_01262_amd/csrc/stage_fused_f64.hip")
 
 
 def kernel_hash() -> str:
@@ -124,8 +126,8 @@ def adjoint_ratio(pf, fx, dtype, st, n=128, reps=10):
 
 
 def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
-    """The batched driver against a loop of single solves (each its own handle, one stream,
-    no graphs), on the same uneven FP32 instances."""
+    """The batched driver (default mode, and both modes forced) against a loop of single
+    solves (each its own handle, one stream, no graphs), on the same uneven FP32 instances."""
     import torch
     cases = fx.batch_cases(count=count, nsteps=nsteps)
     params, fields = [], []
@@ -139,13 +141,21 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
         params.append(pf.make_params((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype="f32"))
         fields.append([torch.tensor(c.phi0, dtype=torch.float32, device="cuda"), u, v, w])
     cells = sum(int(c.cells) for c in cases)
-    # batched
-    bs = pf.BatchSolver(params)
-    bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
-    with torch.cuda.stream(st):
-        bs.step(*zip(*bf), nsteps=8, stream=st)
-        t_batch = cuda_timer(st, lambda: bs.step(*zip(*bf), nsteps=nsteps, stream=st))
-    bs.close()
+    # batched: default mode, then each mode forced through instance 0's variant
+    names = [pf.phasefield_variant_name(pf.PF_F32, v)
+             for v in range(pf.phasefield_variant_count(pf.PF_F32))]
+    modes = {}
+    for mode, pick in (("default", -1), ("fused", names.index("fused_32x16x32")),
+                       ("per_stage", names.index("tiled_64x8x16"))):
+        params[0].variant = pick
+        bs = pf.BatchSolver(params)
+        bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+        with torch.cuda.stream(st):
+            bs.step(*zip(*bf), nsteps=8, stream=st)
+            modes[mode] = cuda_timer(st, lambda: bs.step(*zip(*bf), nsteps=nsteps, stream=st))
+        bs.close()
+    params[0].variant = -1
+    t_batch = modes["default"]
     # looped single solves, uncaptured
     solvers = [pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype="f32", use_graph=False)
                for p in params]
@@ -176,6 +186,7 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
             "batched_ms": round(t_batch, 2), "looped_ms": round(t_loop, 2),
             "looped_graph_ms": round(t_gloop, 2),
             "batched_gcell_s": round(cells * nsteps / t_batch / 1e6, 2),
+            "batched_mode_ms": {k: round(v, 2) for k, v in modes.items()},
             "looped_gcell_s": round(cells * nsteps / t_loop / 1e6, 2),
             "speedup_vs_looped": round(t_loop / t_batch, 2),
             "speedup_vs_looped_graph": round(t_gloop / t_batch, 2)}

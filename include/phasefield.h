@@ -180,10 +180,12 @@ int32_t phasefield_solver_variant(const pf_solver *s);
 
 /* ----------------------------------------------------------------------------------------
  * Batched driver: many independent simulations (each its own pf_params, uneven grid sizes,
- * same dtype, RK4, steady velocity) advanced together. Each sweep is ONE persistent launch over
- * a global tile list that covers every instance (FP32: two fused two-stage sweeps per step;
- * FP64: four single-stage sweeps); the step sequence is replayed from a captured HIP graph.
- * Results are bit-identical to running each instance alone with phasefield_step.
+ * same dtype, RK4, steady velocity) advanced together. Each sweep is ONE launch over a global
+ * tile list that covers every instance (one workgroup per tile): two fused two-stage sweeps per
+ * step, or four single-stage sweeps. per_instance[0].variant selects the mode by its kind (a "fused_*" variant
+ * or a per-stage one); with variant -1, FP32 runs fused and FP64 per-stage. The step sequence
+ * is replayed from a captured HIP graph. Results are bit-identical to running each instance
+ * alone with phasefield_step.
  * ------------------------------------------------------------------------------------- */
 typedef struct pf_batch pf_batch;
 

@@ -92,7 +92,7 @@ class Solver:
 
 class BatchSolver:
     """Many independent RK4 simulations (uneven grids, one storage dtype, steady velocity)
-    advanced together: one persistent launch per stage, graph-replayed steps."""
+    advanced together: one launch per sweep over a global tile list, graph-replayed steps."""
 
     def __init__(self, params_list):
         self.params = list(params_list)

@@ -75,10 +75,12 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
 // Tiled form of the same stage adjoint: a TX x TY workgroup marches KZ planes along z, with
 // three-plane LDS rings (two-cell halo) of the stage input and of the cotangent, the x- and
 // y-components of gbar of the current and next plane in LDS (one-cell halo in their own
-// direction), and the z-component of gbar, the local term and the z-face cotangent carried in
+// direction), and the z-component of gbar, the local term, the z-face cotangent and W carried in
 // registers. Iteration k computes gbar at plane k+1 and finishes plane k. Same per-cell
-// arithmetic, in the same order, as the plain kernel above, so the two agree bitwise.
-template <typename T, int TX, int TY, int KZ>
+// arithmetic, in the same order, as the plain kernel above, so the two agree bitwise. Memory
+// access, ring slots and the march in whole groups of six iterations follow the forward tiled
+// kernel (buffer descriptors; BIG for arrays of 4 GiB or more).
+template <typename T, int TX, int TY, int KZ, bool BIG>
 __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int tiles_x, int tiles_y)
 {
     constexpr int NT = TX * TY;
@@ -122,14 +124,21 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         const int r = e / PW, c = e - r * PW;
         loff[s] = e < PS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
     }
+    // buffer descriptors for the stencil and velocity arrays; the cotangent and gradient arrays,
+    // touched once per cell, go through a scalar plane pointer and a vector byte offset (which
+    // keeps the scalar registers for the descriptors). The stores name T explicitly: inside the
+    // generic lambda below, deduction from an fma() argument would see its host overload.
+    const FieldRef<T, BIG> fy(a.y, plane, nz), fk(a.kap_in, plane, nz), fU(a.U, plane, nz),
+        fV(a.V, plane, nz), fW(a.W, plane, nz);
+
     T pre_y[NL], pre_k[NL];
     auto fetch = [&](int kk) {
-        const size_t base = (size_t)wrapz(kk, nz) * plane;
+        const int kw = wrapz(kk, nz);
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (lpos[s] >= 0) {
-                pre_y[s] = ldg(a.y + base, loff[s]);
-                pre_k[s] = a.kap_scale * ldg(a.kap_in + base, loff[s]);
+                pre_y[s] = fy.load(kw, loff[s]);
+                pre_k[s] = a.kap_scale * fk.load(kw, loff[s]);
             }
     };
     auto commit = [&](int slot) {
@@ -174,37 +183,40 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     fetch(k0 - 1);
     commit(1);
     fetch(k0);
-    T gz_prev = T(0), gz_cur = T(0), loc_cur = T(0), fbz_cur = T(0);
-    int it = 0;
-    for (int k = k0 - 2; k < k1; ++k, ++it) {
+    // handed from plane to plane: gbar_z at k-1 and k, the local term and z-face cotangent of
+    // plane k, W at k
+    T gz_prev = T(0), gz_cur = T(0), loc_cur = T(0), fbz_cur = T(0), w0 = T(0);
+    // R = (k - k0 + 2) mod 6 fixes the ring slots at compile time; iterations past the chunk end
+    // compute on wrapped planes and store nothing
+    auto iteration = [&](auto RC, int k) {
+        constexpr int R = decltype(RC)::value;
+        constexpr int s0 = R % 3, s1 = (R + 1) % 3, s2 = (R + 2) % 3;  // planes k, k+1, k+2
+        constexpr int q0 = R & 1, q1 = (R + 1) & 1;
         __syncthreads();
-        const int s0 = it % 3, s1 = (it + 1) % 3, s2 = (it + 2) % 3;
         commit(s2);
-        if (k + 1 < k1) fetch(k + 3);
-        const size_t pk = (size_t)(k < 0 ? 0 : k) * plane;
-        const size_t pk1 = (size_t)wrapz(k + 1, nz) * plane;
-        const bool out = k >= k0 && active;
-        const bool zface = active && k + 1 >= k0 && k + 1 < k1;  // low z-face of plane k+1
-        T u0 = T(0), u1 = T(0), v0 = T(0), v1 = T(0), w0 = T(0), w1 = T(0);
-        T gu = T(0), gv = T(0), gw = T(0), lb = T(0), lp = T(0);
-        if (out) {
-            u0 = ldg(a.U + pk, col);
-            u1 = ldg(a.U + pk, col_xp);
-            v0 = ldg(a.V + pk, col);
-            v1 = ldg(a.V + pk, col_yp);
-            w0 = ldg(a.W + pk, col);
-            w1 = ldg(a.W + pk1, col);
-            if (a.gU) gu = ldg(a.gU + pk, col);
-            if (a.gV) gv = ldg(a.gV + pk, col);
-            if (a.lam_out) lb = ldg(a.lam_base + pk, col);
-            if (a.kap_out) lp = ldg(a.lamp + pk, col);
+        fetch(k + 3);
+        const bool out_plane = k >= k0 && k < k1;
+        const bool zplane = k + 1 >= k0 && k + 1 < k1;  // plane k+1, whose low z-face is done here
+        const int kw1 = wrapz(k + 1, nz);
+        const T w1 = fW.load(kw1, col);
+        // element offsets of planes k and k+1, used only where those planes are in the chunk
+        const size_t ok = (size_t)(k < 0 ? 0 : k) * plane, ok1 = ok + (k < 0 ? 0 : plane);
+        T u0, u1, v0, v1, gu, gv, gw, lb, lp;
+        if (out_plane) {
+            u0 = fU.load(k, col);
+            u1 = fU.load(k, col_xp);
+            v0 = fV.load(k, col);
+            v1 = fV.load(k, col_yp);
+            if (a.gU) gu = ldg(a.gU + ok, col);
+            if (a.gV) gv = ldg(a.gV + ok, col);
+            if (a.lam_out) lb = ldg(a.lam_base + ok, col);
+            if (a.kap_out) lp = ldg(a.lamp + ok, col);
         }
-        if (zface && a.gW) gw = ldg(a.gW + pk1, col);
+        if (zplane && a.gW) gw = ldg(a.gW + ok1, col);
         __syncthreads();
 
         const T *Y0 = sy + s0 * PS, *Y1 = sy + s1 * PS, *Y2 = sy + s2 * PS;
         const T *K0 = sk + s0 * PS, *K1 = sk + s1 * PS, *K2 = sk + s2 * PS;
-        const int q0 = it & 1, q1 = (it + 1) & 1;
         T gb[3];
         const T loc_next = cell(Y0, Y1, Y2, K0, K1, K2, o, gb);
         sgx[q1 * GXS + ty * GXW + tx + 1] = gb[0];
@@ -219,14 +231,14 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
                 sgy[q1 * GYS + h_dst] = hb[1];
         }
         const T fbz_next = adj_face(K0[o], K1[o], inv_dx);  // z-face between planes k and k+1
-        if (zface && a.gW) stg(a.gW + pk1, col, fma(-hs * (Y0[o] + Y1[o]), fbz_next, gw));
-        if (out) {
+        if (zplane && active && a.gW) stg<T>(a.gW + ok1, col, fma(-hs * (Y0[o] + Y1[o]), fbz_next, gw));
+        if (out_plane && active) {
             T ybar = loc_cur;
             // x faces
             T lo = adj_face(K0[o - 1], K0[o], inv_dx), hi = adj_face(K0[o], K0[o + 1], inv_dx);
             ybar = fma(lo, fma(-hs, u0, ge), ybar);
             ybar = fma(hi, fma(-hs, u1, -ge), ybar);
-            if (a.gU) stg(a.gU + pk, col, fma(-hs * (Y0[o - 1] + Y0[o]), lo, gu));
+            if (a.gU) stg<T>(a.gU + ok, col, fma(-hs * (Y0[o - 1] + Y0[o]), lo, gu));
             const T* GX = sgx + q0 * GXS + ty * GXW + tx;
             ybar = fma(GX[0] - GX[2], inv_2dx, ybar);
             // y faces
@@ -234,20 +246,30 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
             hi = adj_face(K0[o], K0[o + PW], inv_dx);
             ybar = fma(lo, fma(-hs, v0, ge), ybar);
             ybar = fma(hi, fma(-hs, v1, -ge), ybar);
-            if (a.gV) stg(a.gV + pk, col, fma(-hs * (Y0[o - PW] + Y0[o]), lo, gv));
+            if (a.gV) stg<T>(a.gV + ok, col, fma(-hs * (Y0[o - PW] + Y0[o]), lo, gv));
             const T* GY = sgy + q0 * GYS + ty * TX + tx;
             ybar = fma(GY[0] - GY[2 * TX], inv_2dx, ybar);
             // z faces
             ybar = fma(fbz_cur, fma(-hs, w0, ge), ybar);
             ybar = fma(fbz_next, fma(-hs, w1, -ge), ybar);
             ybar = fma(gz_prev - gz_next, inv_2dx, ybar);
-            if (a.lam_out) stg(a.lam_out + pk, col, lb + ybar);
-            if (a.kap_out) stg(a.kap_out + pk, col, fma(a.ka, ybar, a.kb * lp));
+            if (a.lam_out) stg<T>(a.lam_out + ok, col, lb + ybar);
+            if (a.kap_out) stg<T>(a.kap_out + ok, col, fma(a.ka, ybar, a.kb * lp));
         }
         gz_prev = gz_cur;
         gz_cur = gz_next;
         loc_cur = loc_next;
         fbz_cur = fbz_next;
+        w0 = w1;
+    };
+    const int kend = k0 - 2 + 6 * ((k1 - k0 + 7) / 6);  // k0-2 .. k1-1, in groups of six
+    for (int k = k0 - 2; k < kend; k += 6) {
+        iteration(IntC<0>(), k);
+        iteration(IntC<1>(), k + 1);
+        iteration(IntC<2>(), k + 2);
+        iteration(IntC<3>(), k + 3);
+        iteration(IntC<4>(), k + 4);
+        iteration(IntC<5>(), k + 5);
     }
 }
 
@@ -259,22 +281,59 @@ hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_adjoint_stage(const AdjArgs<T>& a, hipStream_t st)
+template <typename T, int TX, int TY, int KZ>
+static hipError_t launch_adjoint_tiled(const AdjArgs<T>& a, bool big, hipStream_t st)
 {
-    constexpr int TX = 64, TY = 8, KZ = 32;
     const int tiles_x = (a.nx + TX - 1) / TX;
     const int tiles_y = (a.ny + TY - 1) / TY;
     const int chunks = (a.nz + KZ - 1) / KZ;
     const long long blocks = (long long)tiles_x * tiles_y * chunks;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, KZ>), dim3((unsigned)blocks), dim3(TX * TY),
-                       0, st, a, tiles_x, tiles_y);
+    if (big || field_needs_big(a.nx, a.ny, a.nz, sizeof(T)))
+        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, KZ, true>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+    else
+        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, KZ, false>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
     return hipGetLastError();
 }
 
-template hipError_t launch_adjoint_stage<float>(const AdjArgs<float>&, hipStream_t);
-template hipError_t launch_adjoint_stage<double>(const AdjArgs<double>&, hipStream_t);
+// Tile shapes of the tiled adjoint, largest first.
+static const int kAdjTiles[][3] = {{64, 8, 64}, {64, 8, 16}, {64, 4, 16}, {32, 4, 16}};
+constexpr int kNumAdjTiles = (int)(sizeof(kAdjTiles) / sizeof(kAdjTiles[0]));
+
+int adjoint_tile_index(int tx, int ty, int kz)
+{
+    for (int t = 0; t < kNumAdjTiles; ++t)
+        if (kAdjTiles[t][0] == tx && kAdjTiles[t][1] == ty && kAdjTiles[t][2] == kz) return t;
+    return -1;
+}
+
+int adjoint_default_tile(int nx, int ny, int nz)
+{
+    for (int t = 0; t < kNumAdjTiles; ++t) {
+        const long long blocks = (long long)((nx + kAdjTiles[t][0] - 1) / kAdjTiles[t][0]) *
+                                 ((ny + kAdjTiles[t][1] - 1) / kAdjTiles[t][1]) *
+                                 ((nz + kAdjTiles[t][2] - 1) / kAdjTiles[t][2]);
+        if (blocks >= 512) return t;
+    }
+    return kNumAdjTiles - 1;
+}
+
+template <typename T>
+hipError_t launch_adjoint_stage(const AdjArgs<T>& a, int tile, bool big, hipStream_t st)
+{
+    switch (tile) {
+    case 0: return launch_adjoint_tiled<T, 64, 8, 64>(a, big, st);
+    case 1: return launch_adjoint_tiled<T, 64, 8, 16>(a, big, st);
+    case 2: return launch_adjoint_tiled<T, 64, 4, 16>(a, big, st);
+    case 3: return launch_adjoint_tiled<T, 32, 4, 16>(a, big, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_adjoint_stage<float>(const AdjArgs<float>&, int, bool, hipStream_t);
+template hipError_t launch_adjoint_stage<double>(const AdjArgs<double>&, int, bool, hipStream_t);
 template hipError_t launch_adjoint_stage_global<float>(const AdjArgs<float>&, hipStream_t);
 template hipError_t launch_adjoint_stage_global<double>(const AdjArgs<double>&, hipStream_t);
 

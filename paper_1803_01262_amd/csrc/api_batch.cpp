@@ -1,12 +1,13 @@
 // C ABI: batched driver. Every instance of the batch advances together: each sweep is ONE
-// persistent launch over a global tile list that covers all instances, and the step sequence
-// is captured once into a HIP graph and replayed.
+// launch over a global tile list that covers all instances (one workgroup per tile), and the
+// step sequence is captured once into a HIP graph and replayed.
 //
-// Two modes, chosen by storage dtype as for single solves:
-//   FP32: fused two-stage sweeps (two launches per step). phi alternates with the accumulator
-//         buffer from step to step; tables for even and odd steps are kept, and after an odd
-//         step count one batched copy returns phi to the caller's buffers.
-//   FP64: per-stage sweeps (four launches per step), fixed buffers.
+// Two modes. The kind of the variant that instance 0 names (variant >= 0) selects one; with
+// variant -1 FP32 runs fused and FP64 per-stage:
+//   fused:     two-stage sweeps (two launches per step). phi alternates with the accumulator
+//              buffer from step to step; tables for even and odd steps are kept, and after an
+//              odd step count one batched copy returns phi to the caller's buffers.
+//   per-stage: four launches per step, fixed buffers.
 // Either way every instance is bit-identical to its own single solve.
 #include <hip/hip_runtime.h>
 
@@ -26,10 +27,10 @@ struct pf_batch {
     std::vector<size_t> N;
     void* pool = nullptr;          // stage buffers of every instance (ya, yb, acc each)
     std::vector<size_t> pool_off;  // element offset of instance b's first buffer
-    int total_tiles = 0;
-    int grid_blocks = 0;
-    int* owner = nullptr;  // device: instance of each global tile
-    // device tables: per-stage mode S1..S4; fused mode A_even, B_even, A_odd, B_odd
+    int num_tiles = 0;
+    BatchTile* tiles = nullptr;  // device: the global tile list (8 equal per-XCD ranges)
+    // device per-instance argument arrays: per-stage mode S1..S4 (StageArgs);
+    // fused mode A_even, B_even, A_odd, B_odd (FusedArgs)
     void* tables[4] = {nullptr, nullptr, nullptr, nullptr};
     void* copies = nullptr;        // device BatchCopy<T>[count]: acc -> phi after an odd count
     std::vector<const void*> key;  // pointer set the tables and graph were built for
@@ -52,7 +53,7 @@ extern "C" pf_status phasefield_batch_destroy(pf_batch* b)
     (void)hipDeviceSynchronize();
     batch_release_graph(b);
     if (b->pool) (void)hipFree(b->pool);
-    if (b->owner) (void)hipFree(b->owner);
+    if (b->tiles) (void)hipFree(b->tiles);
     if (b->copies) (void)hipFree(b->copies);
     for (void* t : b->tables)
         if (t) (void)hipFree(t);
@@ -61,6 +62,57 @@ extern "C" pf_status phasefield_batch_destroy(pf_batch* b)
 }
 
 static size_t padded(size_t n) { return (n + 63) / 64 * 64; }  // keeps buffers 256-byte aligned
+
+// Mode: the kind (fused or per-stage) of the variant named by instance 0, else by dtype.
+static bool B_mode_fused(const pf_params* per_instance)
+{
+    const int dtype = per_instance[0].dtype, v0 = per_instance[0].variant;
+    if (v0 >= 0 && v0 < stage_variant_count(dtype)) return variant_is_fused(dtype, v0);
+    return dtype == PF_F32;
+}
+
+// The global tile list. Instances are packed onto the 8 XCDs by longest processing time (largest
+// first, each onto the least-loaded XCD), so the tiles of one instance share one L2; within an
+// XCD's range the tiles run longest z-chunk first, so short tiles fill the end; the ranges are
+// padded to one length with empty entries (the launch maps workgroup ids onto the ranges).
+static bool build_tile_list(const pf_params* p, int count, bool fused, std::vector<BatchTile>& out)
+{
+    int TX, TY, KZ;
+    batch_tile_shape(fused, &TX, &TY, &KZ);
+    const int warm = fused ? 6 : 2;  // warm-up planes per z-chunk
+    std::vector<double> work(count);
+    std::vector<int> order(count);
+    for (int b = 0; b < count; ++b) {
+        const double tx = (p[b].n[0] + TX - 1) / TX, ty = (p[b].n[1] + TY - 1) / TY;
+        const double cz = (p[b].n[2] + KZ - 1) / KZ;
+        work[b] = tx * ty * ((double)p[b].n[2] + cz * warm);
+        order[b] = b;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    constexpr int kXcd = 8;
+    std::vector<BatchTile> bins[kXcd];
+    double load[kXcd] = {0};
+    for (int b : order) {
+        const int x = (int)(std::min_element(load, load + kXcd) - load);
+        load[x] += work[b];
+        const int tx = (p[b].n[0] + TX - 1) / TX, ty = (p[b].n[1] + TY - 1) / TY;
+        const int cz = (p[b].n[2] + KZ - 1) / KZ;
+        for (int k = 0; k < cz; ++k)
+            for (int j = 0; j < ty; ++j)
+                for (int i = 0; i < tx; ++i) bins[x].push_back({b, i, j, k});
+    }
+    size_t len = 0;
+    for (auto& bin : bins) {
+        std::stable_sort(bin.begin(), bin.end(), [&](const BatchTile& u, const BatchTile& v) {
+            return std::min(KZ, p[u.b].n[2] - u.tk * KZ) > std::min(KZ, p[v.b].n[2] - v.tk * KZ);
+        });
+        len = std::max(len, bin.size());
+    }
+    if (len * kXcd > 0x7fffffffull) return false;
+    out.assign(len * kXcd, BatchTile{-1, 0, 0, 0});
+    for (int x = 0; x < kXcd; ++x) std::copy(bins[x].begin(), bins[x].end(), out.begin() + x * len);
+    return true;
+}
 
 extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int32_t count,
                                              pf_batch** out)
@@ -82,38 +134,32 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
             return fail(PF_ERR_UNSUPPORTED,
                         "instance %d: a field of 4 GiB or more; use a single-grid solver", b);
     }
+    std::vector<BatchTile> list;
+    if (!build_tile_list(per_instance, count, B_mode_fused(per_instance), list))
+        return fail(PF_ERR_INVALID, "the batch has too many tiles for one launch");
     auto* B = new pf_batch();
     B->count = count;
     B->dtype = per_instance[0].dtype;
-    B->fused = B->dtype == PF_F32;
+    B->fused = B_mode_fused(per_instance);
     B->p.assign(per_instance, per_instance + count);
     const size_t esz = B->dtype == PF_F32 ? sizeof(float) : sizeof(double);
     size_t total = 0;
-    std::vector<int> owner;
     for (int b = 0; b < count; ++b) {
         const size_t n = (size_t)B->p[b].n[0] * B->p[b].n[1] * B->p[b].n[2];
         B->N.push_back(n);
         B->pool_off.push_back(total);
         total += 3 * padded(n);
-        int tx, ty, cz;
-        batch_tile_counts(B->fused, B->p[b].n[0], B->p[b].n[1], B->p[b].n[2], &tx, &ty, &cz);
-        for (int t = 0; t < tx * ty * cz; ++t) owner.push_back(b);
     }
-    B->total_tiles = (int)owner.size();
-    int cus = 256;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    B->grid_blocks = std::min(B->total_tiles, cus * 8);
+    B->num_tiles = (int)list.size();
     hipError_t e = hipMalloc(&B->pool, total * esz);
-    if (e == hipSuccess) e = hipMalloc((void**)&B->owner, owner.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&B->tiles, list.size() * sizeof(BatchTile));
     if (e == hipSuccess)
-        e = hipMemcpy(B->owner, owner.data(), owner.size() * sizeof(int), hipMemcpyHostToDevice);
+        e = hipMemcpy(B->tiles, list.data(), list.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
     size_t tsz;
     if (B->fused)
-        tsz = B->dtype == PF_F32 ? sizeof(FusedBatchEntry<float>) : sizeof(FusedBatchEntry<double>);
+        tsz = B->dtype == PF_F32 ? sizeof(FusedArgs<float>) : sizeof(FusedArgs<double>);
     else
-        tsz = B->dtype == PF_F32 ? sizeof(BatchEntry<float>) : sizeof(BatchEntry<double>);
+        tsz = B->dtype == PF_F32 ? sizeof(StageArgs<float>) : sizeof(StageArgs<double>);
     for (int s = 0; s < 4 && e == hipSuccess; ++s) e = hipMalloc(&B->tables[s], tsz * count);
     if (e == hipSuccess)
         e = hipMalloc(&B->copies, (B->dtype == PF_F32 ? sizeof(BatchCopy<float>) : sizeof(BatchCopy<double>)) * count);
@@ -133,10 +179,9 @@ template <typename T>
 static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const* u,
                                const void* const* v, const void* const* w)
 {
-    std::vector<BatchEntry<T>> st_tab[4];
-    std::vector<FusedBatchEntry<T>> fu_tab[4];
+    std::vector<StageArgs<T>> st_tab[4];
+    std::vector<FusedArgs<T>> fu_tab[4];
     std::vector<BatchCopy<T>> copies;
-    int tile = 0;
     for (int b = 0; b < B->count; ++b) {
         const pf_params& p = B->p[b];
         T* ph = (T*)phi[b];
@@ -144,14 +189,12 @@ static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const*
         T* base = (T*)B->pool + B->pool_off[b];
         const size_t stride = padded(B->N[b]);
         T *ya = base, *yb = base + stride, *acc = base + 2 * stride;
-        int tx, ty, cz;
-        batch_tile_counts(B->fused, p.n[0], p.n[1], p.n[2], &tx, &ty, &cz);
         if (B->fused) {
             const FusedArgs<T> f[4] = {make_fused<T>(p, false, 0.0, ph, acc, U, V, W, yb),
                                        make_fused<T>(p, true, 0.0, ph, acc, U, V, W, yb),
                                        make_fused<T>(p, false, 0.0, acc, ph, U, V, W, yb),
                                        make_fused<T>(p, true, 0.0, acc, ph, U, V, W, yb)};
-            for (int s = 0; s < 4; ++s) fu_tab[s].push_back({f[s], tile, tx, ty, cz});
+            for (int s = 0; s < 4; ++s) fu_tab[s].push_back(f[s]);
         } else {
             const double dt = p.dt;
             const StageArgs<T> sa[4] = {
@@ -159,16 +202,15 @@ static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const*
                 make_stage<T>(p, 1.0, ya, ph, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W),
                 make_stage<T>(p, 1.0, yb, ph, acc, ya, acc, dt, dt / 3.0, U, V, W),
                 make_stage<T>(p, 1.0, ya, nullptr, acc, nullptr, ph, 0.0, dt / 6.0, U, V, W)};
-            for (int s = 0; s < 4; ++s) st_tab[s].push_back({sa[s], tile, tx, ty, cz});
+            for (int s = 0; s < 4; ++s) st_tab[s].push_back(sa[s]);
         }
         copies.push_back({acc, ph, B->N[b]});
-        tile += tx * ty * cz;
     }
     for (int s = 0; s < 4; ++s) {
         hipError_t e = B->fused ? hipMemcpy(B->tables[s], fu_tab[s].data(),
-                                            sizeof(FusedBatchEntry<T>) * B->count, hipMemcpyHostToDevice)
+                                            sizeof(FusedArgs<T>) * B->count, hipMemcpyHostToDevice)
                                 : hipMemcpy(B->tables[s], st_tab[s].data(),
-                                            sizeof(BatchEntry<T>) * B->count, hipMemcpyHostToDevice);
+                                            sizeof(StageArgs<T>) * B->count, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: table upload");
     }
     hipError_t e = hipMemcpy(B->copies, copies.data(), sizeof(BatchCopy<T>) * B->count,
@@ -183,15 +225,15 @@ static hipError_t enqueue_batch_step(pf_batch* B, bool odd, hipStream_t st)
 {
     if (B->fused) {
         for (int s = 0; s < 2; ++s) {
-            hipError_t e = launch_batch_fused<T>((const FusedBatchEntry<T>*)B->tables[(odd ? 2 : 0) + s],
-                                                 s == 1, B->owner, B->total_tiles, B->grid_blocks, st);
+            hipError_t e = launch_batch_fused<T>((const FusedArgs<T>*)B->tables[(odd ? 2 : 0) + s],
+                                                 s == 1, B->tiles, B->num_tiles, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
     for (int s = 0; s < 4; ++s) {
-        hipError_t e = launch_batch_stage<T>((const BatchEntry<T>*)B->tables[s], B->owner,
-                                             B->total_tiles, B->grid_blocks, st);
+        hipError_t e = launch_batch_stage<T>((const StageArgs<T>*)B->tables[s], B->tiles,
+                                             B->num_tiles, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

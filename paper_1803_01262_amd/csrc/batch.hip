@@ -1,52 +1,43 @@
-// Batched stage kernel: one persistent launch advances one RK stage of many independent
-// simulations. The tiles of all instances form one global list; each workgroup strides over it
-// and runs the same per-tile body as the single-grid tiled kernel, so every instance's result
-// is bit-identical to its own single solve.
+// Batched sweeps: one launch advances one RK stage (per-stage mode) or one two-stage sweep
+// (fused mode) of many independent simulations. The tiles of all instances form one global list,
+// one workgroup per entry, and each runs the same per-tile body as the single-grid kernels, so
+// every instance's result is bit-identical to its own single solve.
 #include "pf_fused_body.h"
 #include "pf_tiled_body.h"
 
 namespace pf {
 
-constexpr int kBTX = 32, kBTY = 8, kBKZ = 32;   // per-stage mode tile shape
-constexpr int kFTX = 32, kFTY = 16, kFKZ = 32;  // fused mode tile shape
+// Tile shapes: 32 wide (instances down to 32 cells), 64-plane z-chunks (a whole number of the
+// six-iteration groups of the marches, and little warm-up per chunk).
+constexpr int kBTX = 32, kBTY = 8, kBKZ = 64;   // per-stage mode tile shape
+constexpr int kFTX = 32, kFTY = 16, kFKZ = 64;  // fused mode tile shape
 
-template <typename T>
-__global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const BatchEntry<T>* __restrict__ table,
-                                                                  const int* __restrict__ owner,
-                                                                  int total_tiles)
+// Workgroup -> tile-list entry. Consecutive workgroups go round-robin over the 8 XCDs; the list
+// holds 8 equal ranges, one per XCD, so each XCD walks its own range in order.
+__device__ __forceinline__ int batch_slot()
 {
-    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-        const int b = owner[t];
-        const StageArgs<T> a = table[b].a;
-        int local = t - table[b].tile_begin;
-        const int tiles_x = table[b].tiles_x, tiles_y = table[b].tiles_y;
-        const int ti = local % tiles_x;
-        local /= tiles_x;
-        const int tj = local % tiles_y;
-        const int tk = local / tiles_y;
-        __syncthreads();  // the previous tile's LDS reads are complete
-        tiled_stage_body<T, kBTX, kBTY, kBKZ, false>(a, ti, tj, tk);
-    }
+    const int nb = gridDim.x, b = blockIdx.x;
+    return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
-// Fused mode: the same persistent walk over the tile list, one launch per two-stage sweep.
-template <typename T, bool SWEEP_B>
-__global__ void __launch_bounds__(kFTX* kFTY) batch_fused_kernel(const FusedBatchEntry<T>* __restrict__ table,
-                                                                  const int* __restrict__ owner,
-                                                                  int total_tiles)
+template <typename T>
+__global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs<T>* __restrict__ args,
+                                                                  const BatchTile* __restrict__ tiles)
 {
-    for (int t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-        const int b = owner[t];
-        const FusedArgs<T> a = table[b].a;
-        int local = t - table[b].tile_begin;
-        const int tiles_x = table[b].tiles_x, tiles_y = table[b].tiles_y;
-        const int ti = local % tiles_x;
-        local /= tiles_x;
-        const int tj = local % tiles_y;
-        const int tk = local / tiles_y;
-        __syncthreads();  // the previous tile's LDS reads are complete
-        fused_body<T, kFTX, kFTY, kFKZ, SWEEP_B, false>(a, ti, tj, tk);
-    }
+    const BatchTile tl = tiles[batch_slot()];
+    if (tl.b < 0) return;
+    tiled_stage_body<T, kBTX, kBTY, kBKZ, false>(args[tl.b], tl.ti, tl.tj, tl.tk);
+}
+
+// Fused mode: one launch per two-stage sweep, with the register budget of the single-grid fused
+// kernel (FP32: four waves per SIMD).
+template <typename T, bool SWEEP_B>
+__global__ void __launch_bounds__(kFTX* kFTY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __restrict__ tiles)
+{
+    const BatchTile tl = tiles[batch_slot()];
+    if (tl.b < 0) return;
+    fused_body<T, kFTX, kFTY, kFKZ, SWEEP_B, false>(args[tl.b], tl.ti, tl.tj, tl.tk);
 }
 
 // dst[b] = src[b] for every instance b (blockIdx.y), grid-stride within the instance.
@@ -58,24 +49,24 @@ __global__ void batch_copy_kernel(const BatchCopy<T>* __restrict__ e)
         c.dst[i] = c.src[i];
 }
 
-void batch_tile_counts(bool fused, int nx, int ny, int nz, int* tx, int* ty, int* cz)
+void batch_tile_shape(bool fused, int* tx, int* ty, int* kz)
 {
-    const int TX = fused ? kFTX : kBTX, TY = fused ? kFTY : kBTY, KZ = fused ? kFKZ : kBKZ;
-    *tx = (nx + TX - 1) / TX;
-    *ty = (ny + TY - 1) / TY;
-    *cz = (nz + KZ - 1) / KZ;
+    *tx = fused ? kFTX : kBTX;
+    *ty = fused ? kFTY : kBTY;
+    *kz = fused ? kFKZ : kBKZ;
 }
 
 template <typename T>
-hipError_t launch_batch_fused(const FusedBatchEntry<T>* table_dev, bool sweep_b, const int* owner_dev,
-                              int total_tiles, int grid_blocks, hipStream_t st)
+hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, const BatchTile* tiles_dev,
+                              int num_tiles, hipStream_t st)
 {
+    if (num_tiles <= 0) return hipErrorInvalidValue;
     if (sweep_b)
-        hipLaunchKernelGGL((batch_fused_kernel<T, true>), dim3(grid_blocks), dim3(kFTX * kFTY), 0,
-                           st, table_dev, owner_dev, total_tiles);
+        hipLaunchKernelGGL((batch_fused_kernel<T, true>), dim3(num_tiles), dim3(kFTX * kFTY), 0,
+                           st, args_dev, tiles_dev);
     else
-        hipLaunchKernelGGL((batch_fused_kernel<T, false>), dim3(grid_blocks), dim3(kFTX * kFTY), 0,
-                           st, table_dev, owner_dev, total_tiles);
+        hipLaunchKernelGGL((batch_fused_kernel<T, false>), dim3(num_tiles), dim3(kFTX * kFTY), 0,
+                           st, args_dev, tiles_dev);
     return hipGetLastError();
 }
 
@@ -86,21 +77,22 @@ hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_fused<float>(const FusedBatchEntry<float>*, bool, const int*, int, int, hipStream_t);
-template hipError_t launch_batch_fused<double>(const FusedBatchEntry<double>*, bool, const int*, int, int, hipStream_t);
+template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, const BatchTile*, int, hipStream_t);
+template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, const BatchTile*, int, hipStream_t);
 template hipError_t launch_batch_copy<float>(const BatchCopy<float>*, int, hipStream_t);
 template hipError_t launch_batch_copy<double>(const BatchCopy<double>*, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_batch_stage(const BatchEntry<T>* table_dev, const int* owner_dev, int total_tiles,
-                              int grid_blocks, hipStream_t st)
+hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* tiles_dev, int num_tiles,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(batch_stage_kernel<T>, dim3(grid_blocks), dim3(kBTX * kBTY), 0, st,
-                       table_dev, owner_dev, total_tiles);
+    if (num_tiles <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_stage_kernel<T>, dim3(num_tiles), dim3(kBTX * kBTY), 0, st, args_dev,
+                       tiles_dev);
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_stage<float>(const BatchEntry<float>*, const int*, int, int, hipStream_t);
-template hipError_t launch_batch_stage<double>(const BatchEntry<double>*, const int*, int, int, hipStream_t);
+template hipError_t launch_batch_stage<float>(const StageArgs<float>*, const BatchTile*, int, hipStream_t);
+template hipError_t launch_batch_stage<double>(const StageArgs<double>*, const BatchTile*, int, hipStream_t);
 
 }  // namespace pf

@@ -102,22 +102,11 @@ bool variant_is_fused(int dtype, int v);
 int default_stage_variant(int nx, int ny, int nz, int dtype);
 
 // ------------------------------------------------------------------ batched stages (batch.hip)
-// One entry per instance: the stage arguments plus where its tiles start in the global list.
-template <typename T>
-struct BatchEntry {
-    StageArgs<T> a;
-    int tile_begin;   // first global tile index of this instance
-    int tiles_x, tiles_y, chunks_z;
-};
-template <typename T>
-hipError_t launch_batch_stage(const BatchEntry<T>* table_dev, const int* owner_dev, int total_tiles,
-                              int grid_blocks, hipStream_t st);
-// Fused mode (two-stage sweeps): per-instance sweep arguments plus tile bookkeeping.
-template <typename T>
-struct FusedBatchEntry {
-    FusedArgs<T> a;
-    int tile_begin;
-    int tiles_x, tiles_y, chunks_z;
+// Per-instance arguments of one sweep (per-stage mode: StageArgs, fused mode: FusedArgs), and the
+// global tile list: one entry {instance, ti, tj, tk} per workgroup, instance < 0 for the padding
+// entries that even out the per-XCD ranges (they do nothing).
+struct BatchTile {
+    int b, ti, tj, tk;
 };
 template <typename T>
 struct BatchCopy {
@@ -126,15 +115,23 @@ struct BatchCopy {
     size_t n;
 };
 template <typename T>
-hipError_t launch_batch_fused(const FusedBatchEntry<T>* table_dev, bool sweep_b, const int* owner_dev,
-                              int total_tiles, int grid_blocks, hipStream_t st);
+hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* tiles_dev,
+                              int num_tiles, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, const BatchTile* tiles_dev,
+                              int num_tiles, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream_t st);
-void batch_tile_counts(bool fused, int nx, int ny, int nz, int* tx, int* ty, int* cz);
+// Tile shape of a batch mode: x, y extent and z-chunk.
+void batch_tile_shape(bool fused, int* tx, int* ty, int* kz);
 
 // ------------------------------------------------------------------ adjoint (adjoint.hip)
+// Tiled z-march with tile shape `tile` (an index from adjoint_tile_index or
+// adjoint_default_tile); big forces the large-array addressing form.
 template <typename T>
-hipError_t launch_adjoint_stage(const AdjArgs<T>& a, hipStream_t st);         // tiled z-march
+hipError_t launch_adjoint_stage(const AdjArgs<T>& a, int tile, bool big, hipStream_t st);
+int adjoint_tile_index(int tx, int ty, int kz);       // -1 if that shape has no adjoint kernel
+int adjoint_default_tile(int nx, int ny, int nz);     // first shape with >= 512 workgroups
 template <typename T>
 hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st);  // one thread per cell
 

@@ -66,8 +66,10 @@ def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
 @pytest.mark.parametrize("dtype,shape", [("f64", (20, 16, 70)), ("f32", (33, 9, 65)),
                                          ("f64", (1, 12, 5))])
 def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape):
-    """The tiled adjoint stage kernel (default) and the one-thread-per-cell kernel (paired with
-    the 'global' forward variant) give bit-identical lam and velocity gradients."""
+    """The tiled adjoint stage kernel and the one-thread-per-cell kernel (paired with the
+    'global' forward variant) give bit-identical lam and velocity gradients, for every adjoint
+    tile shape (lent by the per-stage forward variant of that shape), the large-array
+    addressing form (a '_big' variant) and a fused forward variant (tile chosen by size)."""
     pf = lib
     rng, phi, U, V, W, lam, dx = adj_case(4, shape)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -75,8 +77,10 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape):
     names = [pf.phasefield_variant_name(kd, v) for v in range(pf.phasefield_variant_count(kd))]
     kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, dtype=dtype)
     nz, ny, nx = shape
+    picks = ["global", "tiled_64x8x64", "tiled_64x8x16", "tiled_64x4x16", "tiled_32x4x16",
+             "tiled_64x8x16_big", "fused_32x16x32"]
     res = []
-    for v in (0, names.index("global")):
+    for v in (names.index(nm) for nm in picks):
         s = pf.Solver((nx, ny, nz), variant=v, **kw)
         g = [dev(a, tdt) for a in (phi, U, V, W)]
         L = dev(lam, tdt)
@@ -85,8 +89,9 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape):
         torch.cuda.synchronize()
         res.append([L] + grads)
         s.close()
-    for a, b in zip(*res):
-        assert torch.equal(a, b)
+    for nm, other in zip(picks[1:], res[1:]):
+        for a, b in zip(res[0], other):
+            assert torch.equal(a, b), nm
 
 
 def test_adjoint_step_fp32_close_to_fp64_oracle(lib):
@@ -215,14 +220,23 @@ def _batch_instances(sizes, seed=4):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_batch_bitwise_equals_single_solves(lib, dtype):
+@pytest.mark.parametrize("mode", ["default", "fused", "per-stage"])
+def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
+    """Both batched modes (chosen through instance 0's variant) give every instance exactly
+    its own single solve, over uneven, ragged and degenerate grids."""
     pf = lib
-    sizes = [(32, 32, 32), (48, 40, 24), (17, 9, 33), (64, 64, 8), (5, 70, 3), (96, 1, 1)]
+    sizes = [(32, 32, 32), (48, 40, 24), (17, 9, 33), (64, 64, 8), (5, 70, 3), (96, 1, 1),
+             (40, 24, 130)]
     cases = _batch_instances(sizes)
     tdt = torch.float64 if dtype == "f64" else torch.float32
+    kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
+    names = [pf.phasefield_variant_name(kd, v) for v in range(pf.phasefield_variant_count(kd))]
+    pick = {"default": -1, "fused": names.index("fused_32x16x32"),
+            "per-stage": names.index("tiled_64x8x16")}[mode]
     params, singles = [], []
     for (n, dx, phi, U, V, W) in cases:
         params.append(pf.make_params(n, dx, dx, 1.0, fx.rk4_dt_3d(dx, 1.0, dx), dtype=dtype))
+    params[0].variant = pick
     st = torch.cuda.Stream()
     bs = pf.BatchSolver(params)
     bt = [[dev(a, tdt) for a in cs[2:]] for cs in cases]
@@ -231,7 +245,7 @@ def test_batch_bitwise_equals_single_solves(lib, dtype):
                 nsteps=19, stream=st)
     st.synchronize()
     for p, cs, b in zip(params, cases, bt):
-        s = pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype=dtype)
+        s = pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype=dtype)  # default variant
         g = [dev(a, tdt) for a in cs[2:]]
         s.step(*g, nsteps=19)
         torch.cuda.synchronize()
