@@ -99,6 +99,19 @@ def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, v
     return ms, name, tuned, m0, m1
 
 
+def copy_ceiling(st, nbytes=2 ** 31, reps=10):
+    """Read + write bandwidth of a plain device copy of nbytes (4-byte elements), GB/s."""
+    import torch
+    with torch.cuda.stream(st):
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        ms = cuda_timer(st, lambda: b.copy_(a), reps)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / ms / 1e6
+
+
 def adjoint_ratio(pf, fx, dtype, st, n=128, reps=10):
     """Cost of one adjoint step (stage recompute + four reverse stages + velocity gradient) over
     one forward step, on the adjoint workload (128^3, 8-mode field, delta = 1e-6/dx)."""
@@ -239,6 +252,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the FP64/adjoint/batch extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", metavar="PARTS",
+                    help="comma-separated subset of {adjoint, batch}: run only those "
+                         "measurements and print their JSON (for profiling them)")
+    ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also run one plain device copy of BYTES bytes (hardware-counter "
                          "calibration: its FETCH_SIZE/WRITE_SIZE should read BYTES each)")
@@ -255,6 +272,20 @@ def main():
     import pf_fixtures as fx
 
     st = torch.cuda.Stream()
+    if args.only:
+        parts = {x.strip() for x in args.only.split(",") if x.strip()}
+        unknown = parts - {"adjoint", "batch"}
+        if unknown:
+            print(f"--only: unknown parts {sorted(unknown)}", file=sys.stderr)
+            sys.exit(2)
+        res = {}
+        if "adjoint" in parts:
+            res["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st, reps=20)
+            res["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st, reps=20)
+        if "batch" in parts:
+            res["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
+        print(json.dumps(res), flush=True)
+        return
     if args.copy_probe:
         src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -285,6 +316,9 @@ def main():
             "launches_per_step": launches, "kernel": vname, "kernel_hash": khash}
     del phi, u, v, w
     torch.cuda.empty_cache()
+    cc = copy_ceiling(st)
+    roof["copy_ceiling_gbs"] = round(cc, 1)
+    roof["frac_of_copy_ceiling"] = round(achieved / cc, 4)
     extras = {"tile_autotune_ms_per_step": tuned,
               "mass_drift_timed_region": (m1[0] - m0[0]) / m0[0], "min": m1[1], "max": m1[2],
               "eq17_margin": c.eps / c.dx - (c.gamma + c.extra["umax"]) / (2 * c.gamma)}
@@ -307,7 +341,7 @@ def main():
         extras["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st)
         extras["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st)
         log("timing batch vs loop")
-        extras["batch96_f32"] = batch_vs_loop(pf, fx, st)
+        extras["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing CPU oracle")
