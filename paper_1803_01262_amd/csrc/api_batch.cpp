@@ -28,6 +28,7 @@ struct pf_batch {
     void* pool = nullptr;          // stage buffers of every instance (ya, yb, acc each)
     std::vector<size_t> pool_off;  // element offset of instance b's first buffer
     int num_tiles = 0;
+    bool wide = false;  // every instance's nx allows 16-byte plane loads
     BatchTile* tiles = nullptr;  // device: the global tile list (8 equal per-XCD ranges)
     // device per-instance argument arrays: per-stage mode S1..S4 (StageArgs);
     // fused mode A_even, B_even, A_odd, B_odd (FusedArgs)
@@ -151,6 +152,9 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
         total += 3 * padded(n);
     }
     B->num_tiles = (int)list.size();
+    B->wide = true;
+    for (int b = 0; b < count; ++b)
+        B->wide = B->wide && B->p[b].n[0] % (int)(16 / esz) == 0;
     hipError_t e = hipMalloc(&B->pool, total * esz);
     if (e == hipSuccess) e = hipMalloc((void**)&B->tiles, list.size() * sizeof(BatchTile));
     if (e == hipSuccess)
@@ -226,7 +230,7 @@ static hipError_t enqueue_batch_step(pf_batch* B, bool odd, hipStream_t st)
     if (B->fused) {
         for (int s = 0; s < 2; ++s) {
             hipError_t e = launch_batch_fused<T>((const FusedArgs<T>*)B->tables[(odd ? 2 : 0) + s],
-                                                 s == 1, B->tiles, B->num_tiles, st);
+                                                 s == 1, B->wide, B->tiles, B->num_tiles, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

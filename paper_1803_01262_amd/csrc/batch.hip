@@ -31,13 +31,14 @@ __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs
 
 // Fused mode: one launch per two-stage sweep, with the register budget of the single-grid fused
 // kernel (FP32: four waves per SIMD).
-template <typename T, bool SWEEP_B>
+// WIDE: every instance's rows are a whole number of 16-byte pieces (16-byte plane loads).
+template <typename T, bool SWEEP_B, bool WIDE>
 __global__ void __launch_bounds__(kFTX* kFTY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __restrict__ tiles)
 {
     const BatchTile tl = tiles[batch_slot()];
     if (tl.b < 0) return;
-    fused_body<T, kFTX, kFTY, kFKZ, SWEEP_B, false>(args[tl.b], tl.ti, tl.tj, tl.tk);
+    fused_body<T, kFTX, kFTY, kFKZ, SWEEP_B, false, WIDE>(args[tl.b], tl.ti, tl.tj, tl.tk);
 }
 
 // dst[b] = src[b] for every instance b (blockIdx.y), grid-stride within the instance.
@@ -56,17 +57,27 @@ void batch_tile_shape(bool fused, int* tx, int* ty, int* kz)
     *kz = fused ? kFKZ : kBKZ;
 }
 
+template <typename T, bool WIDE>
+static void launch_batch_fused_form(const FusedArgs<T>* args_dev, bool sweep_b,
+                                    const BatchTile* tiles_dev, int num_tiles, hipStream_t st)
+{
+    if (sweep_b)
+        hipLaunchKernelGGL((batch_fused_kernel<T, true, WIDE>), dim3(num_tiles), dim3(kFTX * kFTY),
+                           0, st, args_dev, tiles_dev);
+    else
+        hipLaunchKernelGGL((batch_fused_kernel<T, false, WIDE>), dim3(num_tiles), dim3(kFTX * kFTY),
+                           0, st, args_dev, tiles_dev);
+}
+
 template <typename T>
-hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, const BatchTile* tiles_dev,
-                              int num_tiles, hipStream_t st)
+hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
+                              const BatchTile* tiles_dev, int num_tiles, hipStream_t st)
 {
     if (num_tiles <= 0) return hipErrorInvalidValue;
-    if (sweep_b)
-        hipLaunchKernelGGL((batch_fused_kernel<T, true>), dim3(num_tiles), dim3(kFTX * kFTY), 0,
-                           st, args_dev, tiles_dev);
+    if (wide)
+        launch_batch_fused_form<T, true>(args_dev, sweep_b, tiles_dev, num_tiles, st);
     else
-        hipLaunchKernelGGL((batch_fused_kernel<T, false>), dim3(num_tiles), dim3(kFTX * kFTY), 0,
-                           st, args_dev, tiles_dev);
+        launch_batch_fused_form<T, false>(args_dev, sweep_b, tiles_dev, num_tiles, st);
     return hipGetLastError();
 }
 
@@ -77,8 +88,8 @@ hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, const BatchTile*, int, hipStream_t);
-template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, const BatchTile*, int, hipStream_t);
+template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, bool, const BatchTile*, int, hipStream_t);
+template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, bool, const BatchTile*, int, hipStream_t);
 template hipError_t launch_batch_copy<float>(const BatchCopy<float>*, int, hipStream_t);
 template hipError_t launch_batch_copy<double>(const BatchCopy<double>*, int, hipStream_t);
 

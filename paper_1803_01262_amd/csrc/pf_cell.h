@@ -173,6 +173,9 @@ __device__ __forceinline__ void bstore_so(rsrc_t r, unsigned off, unsigned soff,
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u64v, v), r, (int)off, (int)soff, 0);
 }
 
+// 16 bytes of a field (four floats or two doubles), moved as one unit.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
 // One field (an array of nz planes) for the z-marches. Element (plane kw, byte offset off in
 // the plane) is addressed with one descriptor for the whole array, the plane offset kw * pbytes
 // in the scalar soffset operand and off in a vector register. Arrays of 4 GiB or more (BIG)
@@ -194,6 +197,15 @@ struct FieldRef {
             return bload<T>(plane_rsrc(base + (size_t)kw * pelems, pbytes), off);
         else
             return bload_so(whole, off, (unsigned)kw * pbytes, T(0));
+    }
+    // 16 bytes at (plane kw, byte offset off); off must be a multiple of 16
+    __device__ __forceinline__ v4i_t load16(int kw, unsigned off) const
+    {
+        if constexpr (BIG)
+            return __builtin_amdgcn_raw_buffer_load_b128(plane_rsrc(base + (size_t)kw * pelems, pbytes),
+                                                         (int)off, 0, 0);
+        else
+            return __builtin_amdgcn_raw_buffer_load_b128(whole, (int)off, (int)((unsigned)kw * pbytes), 0);
     }
     __device__ __forceinline__ void store(int kw, unsigned off, T v) const
     {

@@ -29,18 +29,25 @@
 // main loop, which runs E1 and E2 in whole groups of six unconditional iterations so that the
 // values handed from plane to plane stay in place; iterations past the chunk end compute on
 // wrapped planes and store nothing. Two barriers per iteration.
-// Global memory goes through FieldRef buffer descriptors (BIG: arrays of 4 GiB or more).
+// Global memory goes through FieldRef buffer descriptors (BIG: arrays of 4 GiB or more). With
+// WIDE (nx a multiple of 16 bytes' worth of elements), the planes of the stage input and of phi
+// are read in 16-byte pieces: groups of consecutive x-columns that start at a multiple of the
+// group size never straddle the periodic wrap, so each group is one aligned load.
 #pragma once
+
+#include <type_traits>
 
 #include "pf_cell.h"
 #include "pf_internal.h"
 
 namespace pf {
 
-template <typename T, int TX, int TY, int KZ, bool SWEEP_B, bool BIG>
+template <typename T, int TX, int TY, int KZ, bool SWEEP_B, bool BIG, bool WIDE>
 __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int tk)
 {
     constexpr int NT = TX * TY;
+    constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte piece
+    static_assert(TX % VEC == 0, "the tile width must be a whole number of 16-byte pieces");
     constexpr int INW = TX + 8, INH = TY + 8, INS = INW * INH;
     constexpr int MW = TX + 4, MH = TY + 4, MS = MW * MH;
     constexpr int Q1XW = TX + 6, Q1XS = Q1XW * MH;
@@ -50,18 +57,26 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     constexpr int NRING = 4 * MW + 4 * TY;  // MID cells outside the tile
     constexpr int NOUT = 2 * MH + 2 * MW;   // q1-only cells (x- and y-outer ring)
     constexpr int NH2 = 2 * TX + 2 * TY;    // q2 halo cells
-    constexpr int NLI = (INS + NT - 1) / NT;
-    constexpr int NLB = SWEEP_B ? (MS + NT - 1) / NT : 0;
-    static_assert(NRING + NOUT <= NT, "tile too small for the E1 halo assignment");
+    // the q1-only cells start at the first whole wave after the ring cells, so no wave carries
+    // both kinds of E1 halo work (the waves meet at a barrier after E1)
+    constexpr int OUT0 = (NRING + 63) / 64 * 64;
+    // plane loads: WIDE moves pieces of VEC elements (IN: whole rows; PB: the MID rows at the IN
+    // width, so that pieces stay aligned), else single elements
+    constexpr int INGW = INW / VEC;                 // pieces per IN row
+    constexpr int PBW = WIDE ? INW : MW, PBS = PBW * MH;  // PB row width and plane size
+    constexpr int NLI = WIDE ? (INGW * INH + NT - 1) / NT : (INS + NT - 1) / NT;
+    constexpr int NLB = SWEEP_B ? (WIDE ? (INGW * MH + NT - 1) / NT : (MS + NT - 1) / NT) : 0;
+    static_assert(OUT0 + NOUT <= NT, "tile too small for the E1 halo assignment");
     static_assert(NH2 <= NT, "tile too small for the E2 halo assignment");
 
-    __shared__ T s_in[3 * INS];
+    // separate arrays, so that the compiler knows the regions do not overlap
+    __shared__ __align__(16) T s_in[3 * INS];
     __shared__ T s_mid[3 * MS];
     __shared__ T s_q1x[2 * Q1XS];
     __shared__ T s_q1y[2 * Q1YS];
     __shared__ T s_q2x[2 * Q2XS];
     __shared__ T s_q2y[2 * Q2YS];
-    __shared__ T s_pb[SWEEP_B ? MS : 1];
+    __shared__ __align__(16) T s_pb[SWEEP_B ? PBS : 1];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * ny;
@@ -105,7 +120,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         e_coly[s] = (unsigned)(wrapn(gy + 1, ny) * nx + gx) * ES;
     }
     // ---- q1-only cell (x-outer: Q1X columns 0 and TX+5; y-outer: Q1Y rows 0 and TY+5)
-    const int ro = tid - NRING;
+    const int ro = tid - OUT0;
     const bool has_out = ro >= 0 && ro < NOUT;
     int o_in = 0, o_dst = 0, o_axis = 0;
     if (has_out) {
@@ -147,45 +162,74 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
 #pragma unroll
     for (int s = 0; s < NLI; ++s) {
         const int e = tid + s * NT;
-        li_pos[s] = e < INS ? e : -1;
-        const int r = e / INW, c = e - r * INW;
-        li_off[s] = e < INS ? (unsigned)(wrapn(j0 - 4 + r, ny) * nx + wrapn(i0 - 4 + c, nx)) * ES : 0u;
+        if (WIDE) {
+            const int r = e / INGW, g = e - r * INGW;
+            li_pos[s] = e < INGW * INH ? r * INW + g * VEC : -1;
+            li_off[s] = e < INGW * INH
+                            ? (unsigned)(wrapn(j0 - 4 + r, ny) * nx + wrapn(i0 - 4 + g * VEC, nx)) * ES
+                            : 0u;
+        } else {
+            const int r = e / INW, c = e - r * INW;
+            li_pos[s] = e < INS ? e : -1;
+            li_off[s] = e < INS ? (unsigned)(wrapn(j0 - 4 + r, ny) * nx + wrapn(i0 - 4 + c, nx)) * ES : 0u;
+        }
     }
     unsigned lb_off[NLB > 0 ? NLB : 1];
     int lb_pos[NLB > 0 ? NLB : 1];
 #pragma unroll
     for (int s = 0; s < NLB; ++s) {
         const int e = tid + s * NT;
-        lb_pos[s] = e < MS ? e : -1;
-        const int r = e / MW, c = e - r * MW;
-        lb_off[s] = e < MS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
+        if (WIDE) {
+            const int r = e / INGW, g = e - r * INGW;
+            lb_pos[s] = e < INGW * MH ? r * PBW + g * VEC : -1;
+            lb_off[s] = e < INGW * MH
+                            ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 4 + g * VEC, nx)) * ES
+                            : 0u;
+        } else {
+            const int r = e / MW, c = e - r * MW;
+            lb_pos[s] = e < MS ? e : -1;
+            lb_off[s] = e < MS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
+        }
     }
-    T pre_in[NLI];
-    T pre_b[NLB > 0 ? NLB : 1];
+    typedef typename std::conditional<WIDE, v4i_t, T>::type piece_t;
+    piece_t pre_in[NLI];
+    piece_t pre_b[NLB > 0 ? NLB : 1];
     const FieldRef<T, BIG> fy(a.y, plane, nz), fphi(a.phi, plane, nz), facc(a.acc_in, plane, nz),
         foy(a.out_y, plane, nz), foacc(a.out_acc, plane, nz), fU(a.U, plane, nz),
         fV(a.V, plane, nz), fW(a.W, plane, nz);
+    auto load_piece = [&](const FieldRef<T, BIG>& f, int kw, unsigned off) -> piece_t {
+        if constexpr (WIDE)
+            return f.load16(kw, off);
+        else
+            return f.load(kw, off);
+    };
+    auto put_piece = [&](T* dst, const piece_t& v) {
+        if constexpr (WIDE)
+            *reinterpret_cast<v4i_t*>(dst) = v;
+        else
+            *dst = v;
+    };
     auto fetch_in = [&](int kk) {
         const int kw = wrapz(kk, nz);
 #pragma unroll
         for (int s = 0; s < NLI; ++s)
-            if (li_pos[s] >= 0) pre_in[s] = fy.load(kw, li_off[s]);
+            if (li_pos[s] >= 0) pre_in[s] = load_piece(fy, kw, li_off[s]);
     };
     auto commit_in = [&](int slot) {
 #pragma unroll
         for (int s = 0; s < NLI; ++s)
-            if (li_pos[s] >= 0) s_in[slot * INS + li_pos[s]] = pre_in[s];
+            if (li_pos[s] >= 0) put_piece(s_in + slot * INS + li_pos[s], pre_in[s]);
     };
     auto fetch_b = [&](int kk) {
         const int kw = wrapz(kk, nz);
 #pragma unroll
         for (int s = 0; s < NLB; ++s)
-            if (lb_pos[s] >= 0) pre_b[s] = fphi.load(kw, lb_off[s]);
+            if (lb_pos[s] >= 0) pre_b[s] = load_piece(fphi, kw, lb_off[s]);
     };
     auto commit_b = [&]() {
 #pragma unroll
         for (int s = 0; s < NLB; ++s)
-            if (lb_pos[s] >= 0) s_pb[lb_pos[s]] = pre_b[s];
+            if (lb_pos[s] >= 0) put_piece(s_pb + lb_pos[s], pre_b[s]);
     };
 
     // per-slot z state of E1 (q1_z and the z-face flux) and of E2
@@ -287,7 +331,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                                   face_diff(pc, pxp), face_diff(pym, pc), face_diff(pc, pyp), e_dz[s],
                                   dzp, qx[0], qx[2], qy[0], qy[2 * MW], e_qzm[s], qzn[s], eu0[s],
                                   eu1[s], ev0[s], ev1[s], e_w0[s], ew1[s], a.nhs1, ge);
-            const T base = SWEEP_B ? s_pb[lx + ly * MW] : pc;
+            const T base = SWEEP_B ? s_pb[(WIDE ? lx + 2 : lx) + ly * PBW] : pc;
             YM[lx + ly * MW] = fma(a.c_mid, f1, base);
             if (s == 0) {
                 // own cell: hand plane p's values to E2 (used two iterations later)

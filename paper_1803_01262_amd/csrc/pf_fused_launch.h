@@ -9,7 +9,7 @@ namespace pf {
 
 // FP32: at least four waves per SIMD (at most 128 VGPRs), two workgroups of eight waves per CU.
 // FP64 needs more registers than that and runs at two waves per SIMD.
-template <typename T, int TX, int TY, int KZ, bool SWEEP_B, bool BIG>
+template <typename T, int TX, int TY, int KZ, bool SWEEP_B, bool BIG, bool WIDE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y)
 {
@@ -20,19 +20,19 @@ fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y)
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int tk = b / tiles_y;
-    fused_body<T, TX, TY, KZ, SWEEP_B, BIG>(a, ti, tj, tk);
+    fused_body<T, TX, TY, KZ, SWEEP_B, BIG, WIDE>(a, ti, tj, tk);
 }
 
-template <typename T, int TX, int TY, int KZ, bool BIG>
+template <typename T, int TX, int TY, int KZ, bool BIG, bool WIDE>
 static hipError_t launch_fused_sweep(const FusedArgs<T>& a, bool sweep_b, unsigned blocks,
                                      int tiles_x, int tiles_y, hipStream_t st)
 {
     if (sweep_b)
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, KZ, true, BIG>), dim3(blocks), dim3(TX * TY),
-                           0, st, a, tiles_x, tiles_y);
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, KZ, true, BIG, WIDE>), dim3(blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
     else
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, KZ, false, BIG>), dim3(blocks), dim3(TX * TY),
-                           0, st, a, tiles_x, tiles_y);
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, KZ, false, BIG, WIDE>), dim3(blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
     return hipGetLastError();
 }
 
@@ -45,11 +45,14 @@ hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st)
     const int chunks = (a.nz + KZ - 1) / KZ;
     const long long blocks = (long long)tiles_x * tiles_y * chunks;
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    // 16-byte plane loads need rows that are a whole number of 16-byte pieces
+    const bool wide = a.nx % (16 / (int)sizeof(T)) == 0;
+    const unsigned nb = (unsigned)blocks;
     if (FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T)))
-        return launch_fused_sweep<T, TX, TY, KZ, true>(a, sweep_b, (unsigned)blocks, tiles_x,
-                                                       tiles_y, st);
-    return launch_fused_sweep<T, TX, TY, KZ, false>(a, sweep_b, (unsigned)blocks, tiles_x,
-                                                    tiles_y, st);
+        return wide ? launch_fused_sweep<T, TX, TY, KZ, true, true>(a, sweep_b, nb, tiles_x, tiles_y, st)
+                    : launch_fused_sweep<T, TX, TY, KZ, true, false>(a, sweep_b, nb, tiles_x, tiles_y, st);
+    return wide ? launch_fused_sweep<T, TX, TY, KZ, false, true>(a, sweep_b, nb, tiles_x, tiles_y, st)
+                : launch_fused_sweep<T, TX, TY, KZ, false, false>(a, sweep_b, nb, tiles_x, tiles_y, st);
 }
 
 }  // namespace pf

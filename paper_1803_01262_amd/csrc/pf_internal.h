@@ -117,9 +117,10 @@ struct BatchCopy {
 template <typename T>
 hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* tiles_dev,
                               int num_tiles, hipStream_t st);
+// wide: every instance's nx is a multiple of 16 bytes' worth of elements (16-byte plane loads)
 template <typename T>
-hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, const BatchTile* tiles_dev,
-                              int num_tiles, hipStream_t st);
+hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
+                              const BatchTile* tiles_dev, int num_tiles, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream_t st);
 // Tile shape of a batch mode: x, y extent and z-chunk.
