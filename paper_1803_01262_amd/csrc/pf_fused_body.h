@@ -23,6 +23,9 @@
 //   Q2X  x-sharpening of E2, 2 planes        [i0-1, i0+TX+1) x [j0, j0+TY)
 //   Q2Y  y-sharpening of E2, 2 planes        [i0, i0+TX) x [j0-1, j0+TY+1)
 //   PB   phi on MID (sweep B only), 1 plane
+//   VEL  FP64 only: U, V of plane t+2 and W of plane t+3 on the MID rows (V with one more
+//        row), loaded one plane ahead in 16-byte pieces where rows allow (FP32 reads the
+//        velocities at the E1 cells directly: its register budget has no room for the staging)
 // Pipeline: iteration t loads input plane t+4, E1 computes q1 at plane t+3 and ya at plane
 // t+2, E2 computes q2 at plane t+1 and the outputs of plane t. Six warm-up iterations precede
 // the first output plane of a z-chunk: four with E1 alone (a straight-line prologue), then the
@@ -77,6 +80,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     __shared__ T s_q2x[2 * Q2XS];
     __shared__ T s_q2y[2 * Q2YS];
     __shared__ __align__(16) T s_pb[SWEEP_B ? PBS : 1];
+    // velocity staging (x from i0-4 at the IN width, rows from j0-2): U on MH rows, V on MH+1
+    // rows (its +y neighbour), W on MH rows
+    constexpr int VSU = 0, VSV = MH * INW, VSW = (2 * MH + 1) * INW, VSS = (3 * MH + 1) * INW;
+    constexpr bool STAGE = sizeof(T) == 8;  // velocity staging (FP64)
+    __shared__ __align__(16) T s_vel[STAGE ? VSS : 1];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * ny;
@@ -191,6 +199,34 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             lb_off[s] = e < MS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
         }
     }
+    // velocity staging loads: a flattened list of the U, V and W pieces, NLV per thread
+    constexpr int PPR = WIDE ? INGW : INW, PV = WIDE ? VEC : 1;  // pieces per row, their width
+    constexpr int NGU = PPR * MH, NGV = PPR * (MH + 1), NGVEL = 2 * NGU + NGV;
+    constexpr int NLV = STAGE ? (NGVEL + NT - 1) / NT : 0;
+    unsigned lv_off[NLV > 0 ? NLV : 1];
+    int lv_pos[NLV > 0 ? NLV : 1], lv_reg[NLV > 0 ? NLV : 1];  // region: 0 U, 1 V, 2 W, -1 none
+#pragma unroll
+    for (int s = 0; s < NLV; ++s) {
+        const int e = tid + s * NT;
+        int reg = -1, q = 0, base = 0;
+        if (e < NGU) {
+            reg = 0;
+            q = e;
+            base = VSU;
+        } else if (e < NGU + NGV) {
+            reg = 1;
+            q = e - NGU;
+            base = VSV;
+        } else if (e < NGVEL) {
+            reg = 2;
+            q = e - NGU - NGV;
+            base = VSW;
+        }
+        const int r = q / PPR, g = q - r * PPR;
+        lv_reg[s] = reg;
+        lv_pos[s] = base + r * INW + g * PV;
+        lv_off[s] = (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 4 + g * PV, nx)) * ES;
+    }
     typedef typename std::conditional<WIDE, v4i_t, T>::type piece_t;
     piece_t pre_in[NLI];
     piece_t pre_b[NLB > 0 ? NLB : 1];
@@ -226,6 +262,24 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         for (int s = 0; s < NLB; ++s)
             if (lb_pos[s] >= 0) pre_b[s] = load_piece(fphi, kw, lb_off[s]);
     };
+    piece_t pre_v[NLV > 0 ? NLV : 1];
+    auto fetch_vel = [&](int p) {  // U, V at plane p, W at plane p+1
+        const int kw = wrapz(p, nz), kw1 = wrapz(p + 1, nz);
+#pragma unroll
+        for (int s = 0; s < NLV; ++s) {
+            if (lv_reg[s] == 0)
+                pre_v[s] = load_piece(fU, kw, lv_off[s]);
+            else if (lv_reg[s] == 1)
+                pre_v[s] = load_piece(fV, kw, lv_off[s]);
+            else if (lv_reg[s] == 2)
+                pre_v[s] = load_piece(fW, kw1, lv_off[s]);
+        }
+    };
+    auto commit_vel = [&]() {
+#pragma unroll
+        for (int s = 0; s < NLV; ++s)
+            if (lv_reg[s] >= 0) put_piece(s_vel + lv_pos[s], pre_v[s]);
+    };
     auto commit_b = [&]() {
 #pragma unroll
         for (int s = 0; s < NLB; ++s)
@@ -251,6 +305,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     fetch_in(tbeg + 3);
     commit_in(1);
     fetch_in(tbeg + 4);
+    if (STAGE) fetch_vel(tbeg + 2);
     if (SWEEP_B) fetch_b(tbeg + 2);
 
     // One iteration of the march; R = (t - tbeg) mod 6 fixes every ring slot at compile time,
@@ -261,22 +316,37 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         constexpr int sa = R % 3, sb = (R + 1) % 3, sc = (R + 2) % 3;  // planes t+2, t+3, t+4
         constexpr int q1new = (R + 1) & 1, q1old = R & 1;
         commit_in(sc);
+        if (STAGE) commit_vel();  // velocities of plane t+2 (W: t+3)
         if (SWEEP_B) commit_b();
         fetch_in(t + 5);
+        if (STAGE) fetch_vel(t + 3);
         if (SWEEP_B) fetch_b(t + 3);
         // E1 operands from global memory (plane p = t+2), issued before the barrier
         const int pw = wrapz(t + 2, nz), pw1 = wrapz(t + 3, nz);
         T eu0[2], eu1[2], ev0[2], ev1[2], ew1[2], eacc = T(0);
+        if (!STAGE) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            eu0[s] = fU.load(pw, e_col[s]);
-            eu1[s] = fU.load(pw, e_colx[s]);
-            ev0[s] = fV.load(pw, e_col[s]);
-            ev1[s] = fV.load(pw, e_coly[s]);
-            ew1[s] = fW.load(pw1, e_col[s]);
+            for (int s = 0; s < 2; ++s) {
+                eu0[s] = fU.load(pw, e_col[s]);
+                eu1[s] = fU.load(pw, e_colx[s]);
+                ev0[s] = fV.load(pw, e_col[s]);
+                ev1[s] = fV.load(pw, e_coly[s]);
+                ew1[s] = fW.load(pw1, e_col[s]);
+            }
         }
         if (SWEEP_B) eacc = facc.load(pw, e_col[0]);
-        __syncthreads();  // input plane t+4 (and phi plane t+2) visible
+        __syncthreads();  // input plane t+4, phi (and staged velocities) of plane t+2 visible
+        if (STAGE) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int vo = e_ly[s] * INW + e_lx[s] + 2;
+                eu0[s] = s_vel[VSU + vo];
+                eu1[s] = s_vel[VSU + vo + 1];
+                ev0[s] = s_vel[VSV + vo];
+                ev1[s] = s_vel[VSV + vo + INW];
+                ew1[s] = s_vel[VSW + vo];
+            }
+        }
 
         const T* IA = s_in + sa * INS;  // plane t+2
         const T* IB = s_in + sb * INS;  // plane t+3

@@ -142,13 +142,14 @@ int default_stage_variant(int nx, int ny, int nz, int dtype)
         const char* name;
         int tx, ty, kz;
     };
-    static const Cand f32[] = {{"fused_64x8x64", 64, 8, 64}, {"fused_64x8x32", 64, 8, 32},
-                               {"tiled_64x8x16", 64, 8, 16}, {"tiled_64x4x16", 64, 4, 16},
-                               {"tiled_32x4x16", 32, 4, 16}};
-    static const Cand f64[] = {{"tiled_64x8x32", 64, 8, 32}, {"tiled_64x8x16", 64, 8, 16},
-                               {"tiled_64x4x16", 64, 4, 16}, {"tiled_32x4x16", 32, 4, 16}};
+    static const Cand f32[] = {{"fused_64x8x64", 64, 8, 64},  {"fused_32x16x64", 32, 16, 64},
+                               {"fused_64x8x32", 64, 8, 32},  {"fused_32x16x32", 32, 16, 32},
+                               {"tiled_64x4x16", 64, 4, 16},  {"tiled_32x4x16", 32, 4, 16}};
+    static const Cand f64[] = {{"fused_32x16x64", 32, 16, 64}, {"fused_64x8x64", 64, 8, 64},
+                               {"fused_32x16x32", 32, 16, 32}, {"fused_64x8x32", 64, 8, 32},
+                               {"tiled_64x4x16", 64, 4, 16},   {"tiled_32x4x16", 32, 4, 16}};
     const Cand* list = dtype == PF_F32 ? f32 : f64;
-    const int n = dtype == PF_F32 ? 5 : 4;
+    const int n = 6;
     int pick = n - 1;
     for (int c = 0; c < n; ++c) {
         const long long blocks = (long long)((nx + list[c].tx - 1) / list[c].tx) *
