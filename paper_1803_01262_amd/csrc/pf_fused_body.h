@@ -327,6 +327,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         if (!STAGE) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
+                if (s == 1 && !has_ring) continue;  // whole waves without ring cells skip these
                 eu0[s] = fU.load(pw, e_col[s]);
                 eu1[s] = fU.load(pw, e_colx[s]);
                 ev0[s] = fV.load(pw, e_col[s]);

@@ -55,8 +55,10 @@ def gpu_run(pf, phi, U, V, W, *, dx, eps, gamma, dt, nsteps, dtype="f64", scheme
     return out
 
 
+# (nz, ny, nx): ragged tiles, degenerate axes, and nx both a multiple of the 16-byte piece (two
+# doubles / four floats: the fused sweeps' 16-byte plane loads) and not
 SHAPES = [(16, 20, 24), (5, 9, 70), (1, 33, 17), (1, 1, 37), (3, 2, 1), (7, 6, 65), (2, 1, 3),
-          (33, 17, 9)]
+          (33, 17, 9), (6, 5, 4)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -75,7 +77,7 @@ def test_rk4_fp64_all_variants_match_oracle_and_each_other(lib, shape):
         assert np.array_equal(o, outs[0]), f"variant {v} differs from variant 0"
 
 
-@pytest.mark.parametrize("shape", [(40, 36, 70), (1, 33, 130), (9, 5, 7)])
+@pytest.mark.parametrize("shape", [(40, 36, 70), (1, 33, 130), (9, 5, 7), (40, 36, 68), (3, 7, 8)])
 def test_fp32_all_variants_match_oracle_and_each_other(lib, shape):
     """Every FP32 variant (per-stage and fused two-stage sweeps) against the oracle's FP32
     storage mode, and bit-identical to each other; odd step count."""
