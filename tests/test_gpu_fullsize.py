@@ -72,3 +72,67 @@ def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol):
         worst = max(worst, abs(out[k, j, i] - ref[R, R, R]))
     print(dtype, "worst sampled |gpu - oracle| =", worst, "mass drift", drift, flush=True)
     assert worst <= tol * np.abs(out).max()
+
+
+def _drops_f32(n, dx, centres, radii, eps):
+    """The fixture's drop union, built window by window straight into float32 (the union of
+    tanh profiles is the profile of the union, and rounding to float32 commutes with max)."""
+    phi = np.zeros((n, n, n), dtype=np.float32)
+    for c, r in zip(centres, radii):
+        reach = r + 60.0 * eps
+        ix, ox = fx._axis_offsets(n, dx, c[0], n * dx, reach)
+        iy, oy = fx._axis_offsets(n, dx, c[1], n * dx, reach)
+        iz, oz = fx._axis_offsets(n, dx, c[2], n * dx, reach)
+        dist = np.sqrt(oz[:, None, None] ** 2 + oy[None, :, None] ** 2 + ox[None, None, :] ** 2)
+        prof = fx.tanh_profile(r - dist, eps).astype(np.float32)
+        sel = np.ix_(iz, iy, ix)
+        phi[sel] = np.maximum(phi[sel], prof)
+    return phi
+
+
+def test_4gib_fields_switch_to_per_plane_addressing(lib):
+    """At 1024^3 FP32 every field is 4 GiB, past the 32-bit offsets of one buffer descriptor,
+    and the z-marches switch to per-plane descriptors by themselves. Two RK4 steps of the
+    default (fused) variant, checked against the oracle on sampled patches as above. Velocity:
+    U(y, z), V(z, x), W(x, y), products of sines; each component is constant along its own axis,
+    so the discrete divergence vanishes exactly."""
+    pf = lib
+    n = 1024
+    dx = 1.0 / n
+    eps, gamma, nsteps = dx, 1.1, 2
+    dt = fx.rk4_dt_3d(dx, gamma, eps)
+    rng = np.random.default_rng(29)
+    centres, radii = rng.uniform(0.2, 0.8, size=(3, 3)), np.array([0.12, 0.08, 0.1])
+    print("building 1024^3 inputs", flush=True)
+    phi = _drops_f32(n, dx, centres, radii, eps)
+    x = ((np.arange(n) + 0.5) * dx).astype(np.float64)
+    s1, c2 = np.sin(2 * np.pi * x + 0.3), np.cos(4 * np.pi * x + 1.1)
+    full = (n, n, n)
+    U = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(c2, s1).astype(np.float32)[:, :, None], full))
+    V = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(s1, c2).astype(np.float32)[:, None, :], full))
+    W = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(c2, s1).astype(np.float32)[None, :, :], full))
+    inputs = (phi, U, V, W)
+    st = torch.cuda.Stream()
+    s = pf.Solver((n, n, n), dx, eps, gamma, dt, dtype="f32")
+    print("variant", s.variant_name, flush=True)
+    g = [torch.from_numpy(a).cuda() for a in inputs]
+    m0 = s.reduce(g[0], stream=st)
+    with torch.cuda.stream(st):
+        s.step(*g, nsteps=nsteps, stream=st)
+    m1 = s.reduce(g[0], stream=st)
+    out = g[0].cpu().numpy()
+    del g
+    s.close()
+    torch.cuda.empty_cache()
+    drift = abs(m1[0] - m0[0]) / m0[0]
+    print("mass drift", drift, flush=True)
+    assert drift <= 1e-6
+    R = 8 * nsteps + 2
+    worst = 0.0
+    samples = sample_cells(phi, np.random.default_rng(31), 16)
+    for (k, j, i) in samples:
+        pp = [patch(a, k, j, i, R).astype(np.float64) for a in inputs]
+        ref = oracle.step(*pp, dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=nsteps, fp32=True)
+        worst = max(worst, abs(float(out[k, j, i]) - ref[R, R, R]))
+    print("worst sampled |gpu - oracle| =", worst, flush=True)
+    assert worst <= 1e-5
