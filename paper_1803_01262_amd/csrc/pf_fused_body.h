@@ -24,8 +24,9 @@
 //   Q2Y  y-sharpening of E2, 2 planes        [i0, i0+TX) x [j0-1, j0+TY+1)
 //   PB   phi on MID (sweep B only), 1 plane
 //   VEL  FP64 only: U, V of plane t+2 and W of plane t+3 on the MID rows (V with one more
-//        row), loaded one plane ahead in 16-byte pieces where rows allow (FP32 reads the
-//        velocities at the E1 cells directly: its register budget has no room for the staging)
+//        row), loaded one plane ahead in 16-byte pieces where rows allow. FP32 reads the
+//        velocities at the E1 cells directly: within its 128-register budget the staging
+//        registers spill, and staging ran slower (also with U and V alone).
 // Pipeline: iteration t loads input plane t+4, E1 computes q1 at plane t+3 and ya at plane
 // t+2, E2 computes q2 at plane t+1 and the outputs of plane t. Six warm-up iterations precede
 // the first output plane of a z-chunk: four with E1 alone (a straight-line prologue), then the
@@ -82,8 +83,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     __shared__ __align__(16) T s_pb[SWEEP_B ? PBS : 1];
     // velocity staging (x from i0-4 at the IN width, rows from j0-2): U on MH rows, V on MH+1
     // rows (its +y neighbour), W on MH rows
-    constexpr int VSU = 0, VSV = MH * INW, VSW = (2 * MH + 1) * INW, VSS = (3 * MH + 1) * INW;
     constexpr bool STAGE = sizeof(T) == 8;  // velocity staging (FP64)
+    constexpr int VSU = 0, VSV = MH * INW, VSW = (2 * MH + 1) * INW, VSS = (3 * MH + 1) * INW;
     __shared__ __align__(16) T s_vel[STAGE ? VSS : 1];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -203,30 +204,18 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     constexpr int PPR = WIDE ? INGW : INW, PV = WIDE ? VEC : 1;  // pieces per row, their width
     constexpr int NGU = PPR * MH, NGV = PPR * (MH + 1), NGVEL = 2 * NGU + NGV;
     constexpr int NLV = STAGE ? (NGVEL + NT - 1) / NT : 0;
+    // piece e of the list lands at LDS element e * PV (the regions are stacked row by row at
+    // the IN width); only its source offset is kept per thread
     unsigned lv_off[NLV > 0 ? NLV : 1];
-    int lv_pos[NLV > 0 ? NLV : 1], lv_reg[NLV > 0 ? NLV : 1];  // region: 0 U, 1 V, 2 W, -1 none
 #pragma unroll
     for (int s = 0; s < NLV; ++s) {
         const int e = tid + s * NT;
-        int reg = -1, q = 0, base = 0;
-        if (e < NGU) {
-            reg = 0;
-            q = e;
-            base = VSU;
-        } else if (e < NGU + NGV) {
-            reg = 1;
-            q = e - NGU;
-            base = VSV;
-        } else if (e < NGVEL) {
-            reg = 2;
-            q = e - NGU - NGV;
-            base = VSW;
-        }
+        const int q = e < NGU ? e : (e < NGU + NGV ? e - NGU : e - NGU - NGV);
         const int r = q / PPR, g = q - r * PPR;
-        lv_reg[s] = reg;
-        lv_pos[s] = base + r * INW + g * PV;
-        lv_off[s] = (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 4 + g * PV, nx)) * ES;
+        lv_off[s] = e < NGVEL ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 4 + g * PV, nx)) * ES
+                              : 0u;
     }
+    static_assert(VSV == NGU * PV && VSW == (NGU + NGV) * PV, "staging regions must be stacked");
     typedef typename std::conditional<WIDE, v4i_t, T>::type piece_t;
     piece_t pre_in[NLI];
     piece_t pre_b[NLB > 0 ? NLB : 1];
@@ -267,18 +256,21 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         const int kw = wrapz(p, nz), kw1 = wrapz(p + 1, nz);
 #pragma unroll
         for (int s = 0; s < NLV; ++s) {
-            if (lv_reg[s] == 0)
+            const int e = tid + s * NT;
+            if (e < NGU)
                 pre_v[s] = load_piece(fU, kw, lv_off[s]);
-            else if (lv_reg[s] == 1)
+            else if (e < NGU + NGV)
                 pre_v[s] = load_piece(fV, kw, lv_off[s]);
-            else if (lv_reg[s] == 2)
+            else if (e < NGVEL)
                 pre_v[s] = load_piece(fW, kw1, lv_off[s]);
         }
     };
     auto commit_vel = [&]() {
 #pragma unroll
-        for (int s = 0; s < NLV; ++s)
-            if (lv_reg[s] >= 0) put_piece(s_vel + lv_pos[s], pre_v[s]);
+        for (int s = 0; s < NLV; ++s) {
+            const int e = tid + s * NT;
+            if (e < NGVEL) put_piece(s_vel + e * PV, pre_v[s]);
+        }
     };
     auto commit_b = [&]() {
 #pragma unroll
@@ -340,7 +332,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         if (STAGE) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const int vo = e_ly[s] * INW + e_lx[s] + 2;
+                // the slot's IN offset (e_lx + 2) + (e_ly + 2) INW, two rows up: same pitch
+                const int vo = (e_lx[s] + 2) + (e_ly[s] + 2) * INW - 2 * INW;
                 eu0[s] = s_vel[VSU + vo];
                 eu1[s] = s_vel[VSU + vo + 1];
                 ev0[s] = s_vel[VSV + vo];

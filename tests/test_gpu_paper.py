@@ -1,0 +1,80 @@
+"""The paper's 2D uniform-translation experiment (Sec. 3.2.1, Tables 1-2) on the HIP stepper.
+
+A D = 1 drop in a 2 x 2 periodic box (dx = D/25) is carried by (u, v) = (sqrt2/2, sqrt2/2) for
+T = 2 sqrt2 with classic RK4 at dt = min(Eq. 31, Eq. 32), for the seven (eps/dx, gamma/|u|)
+points of Table 2. Checked against the paper: points 1-5 stay inside [0, 1] at every step, 6-7
+leave it. Checked against the oracle: the final field and E_delta = mean |phi(T) - phi(0)|.
+The printed E_delta, E_eps, E_tot of Table 1 depend on a relaxed top-hat initial condition the
+paper does not specify, so they are printed beside ours, not asserted.
+
+Tolerance. Several of these runs are ill-conditioned: where the tails of the drop's periodic
+images meet, grad phi vanishes and the unit normal g/|g| (delta = 0, as in the paper) flips under
+rounding-level changes, and points 6-7 (outside the bounded regime) amplify them further. The
+test measures this on the oracle itself, rerunning it from phi0 perturbed by 1e-16 relative,
+and accepts a GPU-oracle difference up to 100 times that response (and at least 1e-12 relative):
+the GPU may differ from the oracle by no more than its different rounding can explain.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import params
+import pf_fixtures as fx
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = float(np.finfo(np.float64).eps)
+
+
+def test_table2_classification_and_table1_errors_on_the_gpu(lib):
+    pf = lib
+    pts = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
+    n, L = 50, 2.0
+    dx = L / n
+    u = math.sqrt(2) / 2
+    U = np.full((1, n, n), u)
+    Z = np.zeros_like(U)
+    T = 2 * math.sqrt(2)
+    x = (np.arange(n) + 0.5) * dx
+    top_hat = (np.sqrt((x[None, :] - 1) ** 2 + (x[:, None] - 1) ** 2) < 0.5).astype(float)
+    st = torch.cuda.Stream()
+    for p in pts["points"]:
+        eps, gamma = p["eps_over_dx"] * dx, p["gamma_over_u"]
+        phi0 = fx.drops_ic((1, n, n), dx, [(1.0, 1.0, 0.0)], [0.5], eps, window=False)
+        dt = min(params.dt_rk4_2d_eq31(dx, gamma, eps), params.dt_rk4_2d_eq32(dx, u, u, gamma))
+        ns = math.ceil(T / dt)
+        dt = T / ns
+        s = pf.Solver((n, n, 1), dx, eps, gamma, dt, dtype="f64", use_graph=False)
+        g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi0, U, U, Z)]
+        lo, hi = 1.0, 0.0
+        with torch.cuda.stream(st):
+            for k in range(ns):
+                s.step(*g, t0=k * dt, nsteps=1, stream=st)
+                _, mn, mx, bad = s.reduce(g[0], stream=st)
+                assert bad == 0
+                lo, hi = min(lo, mn), max(hi, mx)
+        got = g[0].cpu().numpy()
+        s.close()
+        kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns)
+        ref = oracle.step(phi0, U, U, Z, **kw)
+        wobble = np.random.default_rng(p["point"]).standard_normal(phi0.shape)
+        ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, U, Z, **kw)
+        tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
+        diff = np.abs(got - ref).max()
+        print(f"point {p['point']}: |gpu - oracle| = {diff:.2e}, tolerance {tol:.2e}", flush=True)
+        assert diff <= tol, p["point"]
+        bounded = lo >= -EPS64 and hi <= 1 + EPS64
+        assert bounded == p["bounded"], (p["point"], lo, hi)
+        e_delta = np.abs(got - phi0).mean()
+        e_delta_ref = np.abs(ref - phi0).mean()
+        assert abs(e_delta - e_delta_ref) <= tol
+        e_eps = np.abs(phi0[0] - top_hat).mean()
+        e_tot = np.abs(got[0] - top_hat).mean()
+        print(f"point {p['point']}: {ns} steps, min {lo:.3e}, max-1 {hi - 1:.3e}, "
+              f"E_delta {e_delta:.5f} (paper {p['E_delta']}), E_eps {e_eps:.5f} "
+              f"(paper {p['E_eps']}), E_tot {e_tot:.5f} (paper {p['E_tot']})", flush=True)
