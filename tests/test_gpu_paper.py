@@ -78,3 +78,60 @@ def test_table2_classification_and_table1_errors_on_the_gpu(lib):
         print(f"point {p['point']}: {ns} steps, min {lo:.3e}, max-1 {hi - 1:.3e}, "
               f"E_delta {e_delta:.5f} (paper {p['E_delta']}), E_eps {e_eps:.5f} "
               f"(paper {p['E_eps']}), E_tot {e_tot:.5f} (paper {p['E_tot']})", flush=True)
+
+
+def _gpu_run_1d(pf, phi0, U, dx, eps, gamma, dt, ns):
+    n = phi0.shape[2]
+    s = pf.Solver((n, 1, 1), dx, eps, gamma, dt, dtype="f64")
+    z = np.zeros_like(U)
+    g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi0, U, z, z)]
+    s.step(*g, nsteps=ns)
+    out = g[0].cpu().numpy()
+    s.close()
+    return out
+
+
+def test_1d_drop_refinement_on_the_gpu(lib):
+    """Sec. 3.1 on the HIP stepper: a D = 1 drop advected by u = 1 over one period T = 2 of the
+    periodic domain [-1, 1], RK4 at 0.9 x Eq. 28, with eps/dx fixed while dx is refined. The
+    paper reports first-order convergence of E_eps, E_delta and E_tot (Figure 8) and smaller
+    total errors on the crossover line than above it at the same gamma/u (Figure 9): here
+    eps/dx = 1 (on the line for gamma/u = 1) against eps/dx = 2, N = 100 .. 800 cells.
+    (At exactly the Eq. 28 limit the longest runs let round-off grow; 0.9 x keeps every run
+    inside the stable range.) Each GPU run is also compared with the oracle, with the
+    tolerance measured on the oracle as in the 2D test (grad phi vanishes at the drop's centre).
+    """
+    pf = lib
+    T = 2.0
+    errs = {}
+    for eps_dx in (1.0, 2.0):
+        for n in (100, 200, 400, 800):
+            dx = 2.0 / n
+            eps, gamma = eps_dx * dx, 1.0
+            phi0 = fx.drops_ic((1, 1, n), dx, [(1.0, 0.5 * dx, 0.0)], [0.5], eps, window=False)
+            U = np.ones((1, 1, n))
+            Z = np.zeros_like(U)
+            dt = 0.9 * params.dt_max("rk4", 1, dx, gamma, eps)
+            ns = math.ceil(T / dt)
+            dt = T / ns
+            got = _gpu_run_1d(pf, phi0, U, dx, eps, gamma, dt, ns)
+            kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns)
+            ref = oracle.step(phi0, U, Z, Z, **kw)
+            wobble = np.random.default_rng(n).standard_normal(phi0.shape)
+            ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, Z, Z, **kw)
+            tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
+            assert np.abs(got - ref).max() <= tol, (eps_dx, n)
+            x = (np.arange(n) + 0.5) * dx
+            top_hat = (np.abs(x - 1.0) < 0.5).astype(float)
+            e = (np.abs(phi0[0, 0] - top_hat).mean(), np.abs(got[0, 0] - phi0[0, 0]).mean(),
+                 np.abs(got[0, 0] - top_hat).mean())
+            errs[(eps_dx, n)] = e
+            print(f"eps/dx {eps_dx} N {n}: {ns} steps, E_eps {e[0]:.4e} E_delta {e[1]:.4e} "
+                  f"E_tot {e[2]:.4e}", flush=True)
+    for eps_dx in (1.0, 2.0):
+        for n in (100, 200, 400):
+            a, b = errs[(eps_dx, n)], errs[(eps_dx, 2 * n)]
+            orders = [math.log2(u / v) for u, v in zip(a, b)]
+            assert all(0.8 <= o <= 1.2 for o in orders), (eps_dx, n, orders)
+    for n in (100, 200, 400, 800):
+        assert errs[(1.0, n)][2] < errs[(2.0, n)][2], n
