@@ -158,7 +158,11 @@ pf_status phasefield_velocity_coeffs_grad(const pf_params *p, int32_t modes,
                                           const double *phases, const void *gu, const void *gv,
                                           const void *gw, double *coeff_grad, void *hip_stream);
 
-/* Number of compiled stage-kernel variants (tile shapes) for a storage dtype. */
+/* Number of compiled stage-kernel variants for a storage dtype. A name gives the kind
+ * ("tiled": one launch per RK stage; "fused": two stages per launch; "global": one thread per
+ * cell), the column tile (x by y) and, when it ends in a third number, the planes per z-chunk;
+ * without one, each launch chooses the chunk length for the grid and the device's resident
+ * workgroups. "_big" forces the addressing form of arrays of 4 GiB or more. */
 int32_t phasefield_variant_count(int32_t dtype);
 
 /* Short name of a variant (static string), or NULL if out of range. */
@@ -170,8 +174,9 @@ const char *phasefield_variant_name(int32_t dtype, int32_t variant);
  * Synchronises. The choice is cached per (dtype, grid shape) for the life of the process and
  * used by later phasefield_create calls with variant -1; if the environment variable
  * PF_TUNE_CACHE names a file, the cache is also read from and written to it (one line per
- * entry: dtype nx ny nz variant-name). Without a cached choice, create picks a default tile
- * from the grid size. */
+ * entry: dtype nx ny nz variant-name). Without a cached choice, create picks a default from
+ * the grid size and dtype (fused sweeps from about 80^3 cells in FP32 and 128^3 in FP64,
+ * per-stage kernels below; both with per-launch chunk lengths). */
 pf_status phasefield_autotune(pf_solver *s, int32_t reps, int32_t *best, double *times_ms,
                               void *hip_stream);
 

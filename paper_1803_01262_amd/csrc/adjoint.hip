@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
     if (a.kap_out) a.kap_out[c] = fma(a.ka, ybar, a.kb * a.lamp[c]);
 }
 
-// Tiled form of the same stage adjoint: a TX x TY workgroup marches KZ planes along z, with
+// Tiled form of the same stage adjoint: a TX x TY workgroup marches kz planes along z, with
 // three-plane LDS rings (two-cell halo) of the stage input and of the cotangent, the x- and
 // y-components of gbar of the current and next plane in LDS (one-cell halo in their own
 // direction), and the z-component of gbar, the local term, the z-face cotangent and W carried in
@@ -80,8 +80,9 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
 // arithmetic, in the same order, as the plain kernel above, so the two agree bitwise. Memory
 // access, ring slots and the march in whole groups of six iterations follow the forward tiled
 // kernel (buffer descriptors; BIG for arrays of 4 GiB or more).
-template <typename T, int TX, int TY, int KZ, bool BIG>
-__global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int tiles_x, int tiles_y)
+template <typename T, int TX, int TY, bool BIG>
+__global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int tiles_x, int tiles_y,
+                                                               int kz)
 {
     constexpr int NT = TX * TY;
     constexpr int PW = TX + 4, PH = TY + 4, PS = PW * PH;
@@ -94,17 +95,14 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     __shared__ T sgx[2 * GXS];
     __shared__ T sgy[2 * GYS];
 
-    int b = blockIdx.x;
-    const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    int b = xcd_tile_order(blockIdx.x, gridDim.x);
     const int ti = b % tiles_x;
     b /= tiles_x;
     const int tj = b % tiles_y;
-    const int tk = b / tiles_y;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * ny;
-    const int i0 = ti * TX, j0 = tj * TY, k0 = tk * KZ;
-    const int k1 = min(k0 + KZ, nz);
+    const int i0 = ti * TX, j0 = tj * TY, k0 = (b / tiles_y) * kz;
+    const int k1 = min(k0 + kz, nz);
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int i = i0 + tx, j = j0 + ty;
@@ -281,59 +279,64 @@ hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T, int TX, int TY, int KZ>
-static hipError_t launch_adjoint_tiled(const AdjArgs<T>& a, bool big, hipStream_t st)
+template <typename T, int TX, int TY>
+static hipError_t launch_adjoint_tiled(const AdjArgs<T>& a, int kz, bool big, hipStream_t st)
 {
     const int tiles_x = (a.nx + TX - 1) / TX;
     const int tiles_y = (a.ny + TY - 1) / TY;
-    const int chunks = (a.nz + KZ - 1) / KZ;
-    const long long blocks = (long long)tiles_x * tiles_y * chunks;
+    if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0 || kz < 0) return hipErrorInvalidValue;
+    big = big || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
+    if (kz == 0) {
+        const void* k = big ? (const void*)adjoint_tiled_kernel<T, TX, TY, true>
+                            : (const void*)adjoint_tiled_kernel<T, TX, TY, false>;
+        kz = launch_chunk_planes(k, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
+        if (kz <= 0) return hipErrorInvalidDevice;
+    }
+    const long long blocks = (long long)tiles_x * tiles_y * ((a.nz + kz - 1) / kz);
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (big || field_needs_big(a.nx, a.ny, a.nz, sizeof(T)))
-        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, KZ, true>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+    if (big)
+        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, true>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     else
-        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, KZ, false>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, false>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     return hipGetLastError();
 }
 
-// Tile shapes of the tiled adjoint, largest first.
-static const int kAdjTiles[][3] = {{64, 8, 64}, {64, 8, 16}, {64, 4, 16}, {32, 4, 16}};
+// Tile shapes (x, y) of the tiled adjoint, widest first.
+static const int kAdjTiles[][2] = {{64, 8}, {64, 4}, {32, 4}};
 constexpr int kNumAdjTiles = (int)(sizeof(kAdjTiles) / sizeof(kAdjTiles[0]));
 
-int adjoint_tile_index(int tx, int ty, int kz)
+int adjoint_tile_index(int tx, int ty)
 {
     for (int t = 0; t < kNumAdjTiles; ++t)
-        if (kAdjTiles[t][0] == tx && kAdjTiles[t][1] == ty && kAdjTiles[t][2] == kz) return t;
+        if (kAdjTiles[t][0] == tx && kAdjTiles[t][1] == ty) return t;
     return -1;
 }
 
+// 64 wide unless that pads more columns than 32 wide; 4 rows (one wave per row, four per
+// workgroup, so that small grids still spread over many workgroups).
 int adjoint_default_tile(int nx, int ny, int nz)
 {
-    for (int t = 0; t < kNumAdjTiles; ++t) {
-        const long long blocks = (long long)((nx + kAdjTiles[t][0] - 1) / kAdjTiles[t][0]) *
-                                 ((ny + kAdjTiles[t][1] - 1) / kAdjTiles[t][1]) *
-                                 ((nz + kAdjTiles[t][2] - 1) / kAdjTiles[t][2]);
-        if (blocks >= 512) return t;
-    }
-    return kNumAdjTiles - 1;
+    (void)ny;
+    (void)nz;
+    const int p64 = (nx + 63) / 64 * 64, p32 = (nx + 31) / 32 * 32;
+    return p64 <= p32 ? 1 : 2;
 }
 
 template <typename T>
-hipError_t launch_adjoint_stage(const AdjArgs<T>& a, int tile, bool big, hipStream_t st)
+hipError_t launch_adjoint_stage(const AdjArgs<T>& a, int tile, int kz, bool big, hipStream_t st)
 {
     switch (tile) {
-    case 0: return launch_adjoint_tiled<T, 64, 8, 64>(a, big, st);
-    case 1: return launch_adjoint_tiled<T, 64, 8, 16>(a, big, st);
-    case 2: return launch_adjoint_tiled<T, 64, 4, 16>(a, big, st);
-    case 3: return launch_adjoint_tiled<T, 32, 4, 16>(a, big, st);
+    case 0: return launch_adjoint_tiled<T, 64, 8>(a, kz, big, st);
+    case 1: return launch_adjoint_tiled<T, 64, 4>(a, kz, big, st);
+    case 2: return launch_adjoint_tiled<T, 32, 4>(a, kz, big, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_adjoint_stage<float>(const AdjArgs<float>&, int, bool, hipStream_t);
-template hipError_t launch_adjoint_stage<double>(const AdjArgs<double>&, int, bool, hipStream_t);
+template hipError_t launch_adjoint_stage<float>(const AdjArgs<float>&, int, int, bool, hipStream_t);
+template hipError_t launch_adjoint_stage<double>(const AdjArgs<double>&, int, int, bool, hipStream_t);
 template hipError_t launch_adjoint_stage_global<float>(const AdjArgs<float>&, hipStream_t);
 template hipError_t launch_adjoint_stage_global<double>(const AdjArgs<double>&, hipStream_t);
 

@@ -309,7 +309,7 @@ template <typename T>
 hipError_t pf::run_stage(int variant, const StageArgs<T>& a, hipStream_t st)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
-    const int v = variant_is_fused(dtype, variant) ? 0 : variant;  // variant 0 is per-stage
+    const int v = variant_is_fused(dtype, variant) ? per_stage_variant(a.nx, a.ny, a.nz, dtype) : variant;
     const StageVariant& sv = stage_variant(dtype, v);
     if constexpr (sizeof(T) == 4)
         return sv.launch_f32(a, st);

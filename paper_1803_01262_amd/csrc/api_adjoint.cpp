@@ -66,18 +66,21 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     T* L = (T*)s->adj[2];
     const double dt = p.dt;
     // The plain forward variant pairs with the plain adjoint kernel (both one thread per cell).
-    // A per-stage tiled variant lends its tile shape (and large-array form) to the tiled adjoint
-    // when that shape has an adjoint kernel; otherwise the tile is chosen from the grid size.
+    // A per-stage tiled variant lends its tile shape, chunk length (none: chosen per launch) and
+    // large-array form to the tiled adjoint when that shape has an adjoint kernel; otherwise the
+    // tile is chosen from the grid size and the chunk per launch.
     const char* vname = stage_variant(p.dtype, s->variant).name;
     const bool plain = std::strcmp(vname, "global") == 0;
     int tile = -1, tx = 0, ty = 0, kz = 0;
-    if (std::sscanf(vname, "tiled_%dx%dx%d", &tx, &ty, &kz) == 3) tile = adjoint_tile_index(tx, ty, kz);
+    const int got = std::sscanf(vname, "tiled_%dx%dx%d", &tx, &ty, &kz);
+    if (got >= 2) tile = adjoint_tile_index(tx, ty);
+    if (got < 3 || tile < 0) kz = 0;
     if (tile < 0) tile = adjoint_default_tile(p.n[0], p.n[1], p.n[2]);
     const size_t vlen = std::strlen(vname);
     const bool big = vlen > 4 && std::strcmp(vname + vlen - 4, "_big") == 0;
     auto adj = [&](const AdjArgs<T>& a, hipStream_t hs) {
         return plain ? launch_adjoint_stage_global<T>(a, hs)
-                     : launch_adjoint_stage<T>(a, tile, big, hs);
+                     : launch_adjoint_stage<T>(a, tile, kz, big, hs);
     };
     hipError_t e;
     if (p.scheme == PF_EULER) {

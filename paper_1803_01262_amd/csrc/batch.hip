@@ -12,12 +12,11 @@ namespace pf {
 constexpr int kBTX = 32, kBTY = 8, kBKZ = 64;   // per-stage mode tile shape
 constexpr int kFTX = 32, kFTY = 16, kFKZ = 64;  // fused mode tile shape
 
-// Workgroup -> tile-list entry. Consecutive workgroups go round-robin over the 8 XCDs; the list
-// holds 8 equal ranges, one per XCD, so each XCD walks its own range in order.
+// Workgroup -> tile-list entry: the list holds 8 equal ranges, one per XCD, and xcd_tile_order
+// lets each XCD walk its own range in order.
 __device__ __forceinline__ int batch_slot()
 {
-    const int nb = gridDim.x, b = blockIdx.x;
-    return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+    return xcd_tile_order(blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -26,7 +25,8 @@ __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs
 {
     const BatchTile tl = tiles[batch_slot()];
     if (tl.b < 0) return;
-    tiled_stage_body<T, kBTX, kBTY, kBKZ, false>(args[tl.b], tl.ti, tl.tj, tl.tk);
+    const int k0 = tl.tk * kBKZ;
+    tiled_stage_body<T, kBTX, kBTY, false>(args[tl.b], tl.ti, tl.tj, k0, min(k0 + kBKZ, args[tl.b].nz));
 }
 
 // Fused mode: one launch per two-stage sweep, with the register budget of the single-grid fused
@@ -38,7 +38,9 @@ batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __res
 {
     const BatchTile tl = tiles[batch_slot()];
     if (tl.b < 0) return;
-    fused_body<T, kFTX, kFTY, kFKZ, SWEEP_B, false, WIDE>(args[tl.b], tl.ti, tl.tj, tl.tk);
+    const int k0 = tl.tk * kFKZ;
+    fused_body<T, kFTX, kFTY, SWEEP_B, false, WIDE>(args[tl.b], tl.ti, tl.tj, k0,
+                                                    min(k0 + kFKZ, args[tl.b].nz));
 }
 
 // dst[b] = src[b] for every instance b (blockIdx.y), grid-stride within the instance.

@@ -226,6 +226,16 @@ __device__ __forceinline__ int wrapz(int k, int n)
     return k < 0 ? k + n : k;
 }
 
+// XCD-aware tile order. Consecutive workgroup ids are dispatched round-robin over the 8 XCDs, so
+// workgroup b runs on XCD b mod 8; this maps the ids onto [0, nb) such that each XCD takes one
+// contiguous range of tile indices (nb/8 of them, one more for the first nb mod 8 XCDs), and the
+// halo rows that neighbouring tiles share stay in that XCD's L2.
+__device__ __forceinline__ int xcd_tile_order(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 // Periodic wrap of an index that is at most one period out of range.
 __device__ __forceinline__ int wrap1(int i, int n)
 {

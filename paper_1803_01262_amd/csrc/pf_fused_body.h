@@ -46,8 +46,9 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, int KZ, bool SWEEP_B, bool BIG, bool WIDE>
-__device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int tk)
+// The workgroup owns the TX x TY column tile (ti, tj) and the output planes [k0, k1).
+template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE>
+__device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int k0, int k1)
 {
     constexpr int NT = TX * TY;
     constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte piece
@@ -89,8 +90,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * ny;
-    const int i0 = ti * TX, j0 = tj * TY, k0 = tk * KZ;
-    const int k1 = min(k0 + KZ, nz);
+    const int i0 = ti * TX, j0 = tj * TY;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const bool active = (i0 + tx < nx) && (j0 + ty < ny);

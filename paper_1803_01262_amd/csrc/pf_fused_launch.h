@@ -7,52 +7,64 @@
 
 namespace pf {
 
+// One workgroup per (tile, z-chunk of kz planes); the chunk length is a launch argument.
 // FP32: at least four waves per SIMD (at most 128 VGPRs), two workgroups of eight waves per CU.
 // FP64 needs more registers than that and runs at two waves per SIMD.
-template <typename T, int TX, int TY, int KZ, bool SWEEP_B, bool BIG, bool WIDE>
+template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
-fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y)
+fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y, int kz)
 {
-    int b = blockIdx.x;
-    const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    int b = xcd_tile_order(blockIdx.x, gridDim.x);
     const int ti = b % tiles_x;
     b /= tiles_x;
     const int tj = b % tiles_y;
-    const int tk = b / tiles_y;
-    fused_body<T, TX, TY, KZ, SWEEP_B, BIG, WIDE>(a, ti, tj, tk);
+    const int k0 = (b / tiles_y) * kz;
+    fused_body<T, TX, TY, SWEEP_B, BIG, WIDE>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
-template <typename T, int TX, int TY, int KZ, bool BIG, bool WIDE>
-static hipError_t launch_fused_sweep(const FusedArgs<T>& a, bool sweep_b, unsigned blocks,
-                                     int tiles_x, int tiles_y, hipStream_t st)
+template <typename T, int TX, int TY, bool BIG, bool WIDE>
+hipError_t launch_fused_sweep(const FusedArgs<T>& a, bool sweep_b, unsigned blocks, int tiles_x,
+                              int tiles_y, int kz, hipStream_t st)
 {
     if (sweep_b)
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, KZ, true, BIG, WIDE>), dim3(blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, true, BIG, WIDE>), dim3(blocks), dim3(TX * TY),
+                           0, st, a, tiles_x, tiles_y, kz);
     else
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, KZ, false, BIG, WIDE>), dim3(blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE>), dim3(blocks), dim3(TX * TY),
+                           0, st, a, tiles_x, tiles_y, kz);
     return hipGetLastError();
 }
 
+// KZ: planes per z-chunk, a host-side choice (every KZ shares the kernels of its tile shape);
+// KZ = 0 chooses it per launch (launch_chunk_planes) for the grid and the current device.
 // FORCE_BIG selects the per-plane descriptor form even for small arrays (see the tiled launcher).
 template <typename T, int TX, int TY, int KZ, bool FORCE_BIG>
 hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st)
 {
     const int tiles_x = (a.nx + TX - 1) / TX;
     const int tiles_y = (a.ny + TY - 1) / TY;
-    const int chunks = (a.nz + KZ - 1) / KZ;
-    const long long blocks = (long long)tiles_x * tiles_y * chunks;
-    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0) return hipErrorInvalidValue;
     // 16-byte plane loads need rows that are a whole number of 16-byte pieces
     const bool wide = a.nx % (16 / (int)sizeof(T)) == 0;
+    const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
+    int kz = KZ;
+    if (KZ == 0) {
+        // sweeps A and B share the register budget, hence the residency, of their form
+        const void* k = big ? (wide ? (const void*)fused_kernel<T, TX, TY, false, true, true>
+                                    : (const void*)fused_kernel<T, TX, TY, false, true, false>)
+                            : (wide ? (const void*)fused_kernel<T, TX, TY, false, false, true>
+                                    : (const void*)fused_kernel<T, TX, TY, false, false, false>);
+        kz = launch_chunk_planes(k, TX * TY, (long long)tiles_x * tiles_y, a.nz, 5);
+        if (kz <= 0) return hipErrorInvalidDevice;
+    }
+    const long long blocks = (long long)tiles_x * tiles_y * ((a.nz + kz - 1) / kz);
+    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)blocks;
-    if (FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T)))
-        return wide ? launch_fused_sweep<T, TX, TY, KZ, true, true>(a, sweep_b, nb, tiles_x, tiles_y, st)
-                    : launch_fused_sweep<T, TX, TY, KZ, true, false>(a, sweep_b, nb, tiles_x, tiles_y, st);
-    return wide ? launch_fused_sweep<T, TX, TY, KZ, false, true>(a, sweep_b, nb, tiles_x, tiles_y, st)
-                : launch_fused_sweep<T, TX, TY, KZ, false, false>(a, sweep_b, nb, tiles_x, tiles_y, st);
+    if (big)
+        return wide ? launch_fused_sweep<T, TX, TY, true, true>(a, sweep_b, nb, tiles_x, tiles_y, kz, st)
+                    : launch_fused_sweep<T, TX, TY, true, false>(a, sweep_b, nb, tiles_x, tiles_y, kz, st);
+    return wide ? launch_fused_sweep<T, TX, TY, false, true>(a, sweep_b, nb, tiles_x, tiles_y, kz, st)
+                : launch_fused_sweep<T, TX, TY, false, false>(a, sweep_b, nb, tiles_x, tiles_y, kz, st);
 }
 
 }  // namespace pf

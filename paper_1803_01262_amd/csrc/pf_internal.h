@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 
@@ -85,6 +86,42 @@ inline bool field_needs_big(int nx, int ny, int nz, size_t es)
     return (size_t)nx * (size_t)ny * (size_t)nz * es > 0xffffffffull;
 }
 
+// ------------------------------------------------------------------ z-chunks of the marches
+// Every tiled kernel (per-stage, fused, adjoint) gives each workgroup a column tile and a chunk of
+// consecutive planes, marched in whole groups of six iterations after a warm-up. The chunk
+// length is a launch-time choice: the number of chunks c minimises
+//   rounds x (6 ceil((kz + 2) / 6) + extra),   kz = ceil(nz / c),
+// where a round is one workgroup per resident slot and the second factor is the iterations one
+// workgroup runs (extra: warm-up beyond the two planes every march needs, plus start-up; about 5
+// for the fused sweeps, 1 for the per-stage and adjoint kernels, as measured on MI355X). Longer
+// chunks repeat less warm-up and re-read fewer halo planes; more chunks fill the device. Ties go
+// to the longer chunk.
+inline int march_chunk_planes(long long tiles, int nz, long long slots, int extra)
+{
+    int best_kz = nz;
+    long long best = -1;
+    // far past the chunks that fill the slots, more chunks only add warm-up
+    const long long cmax = std::min<long long>(nz, std::max<long long>(64, 4 * ((slots + tiles - 1) / tiles)));
+    for (int c = 1; c <= cmax; ++c) {
+        const int kz = (nz + c - 1) / c;
+        if (c > 1 && kz == (nz + c - 2) / (c - 1)) continue;  // same chunks as c - 1
+        const long long rounds = (tiles * ((nz + kz - 1) / kz) + slots - 1) / slots;
+        const long long cost = rounds * (6 * ((kz + 7) / 6) + extra);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_kz = kz;
+        }
+    }
+    return best_kz;
+}
+
+// Workgroups of `kernel` (launched with `threads` threads, no dynamic LDS) resident on one compute
+// unit, from the HIP occupancy calculator; cached per kernel. 0 on error.
+int resident_groups_per_cu(const void* kernel, int threads);
+// Chunk length for a launch of `kernel` over `tiles` column tiles of an nz-plane grid on the
+// current device (march_chunk_planes with the device's resident slots); 0 on error.
+int launch_chunk_planes(const void* kernel, int threads, long long tiles, int nz, int extra);
+
 // ------------------------------------------------------------------ stage-kernel variants
 // Either a per-stage kernel (four launches per RK4 step) or a fused pair of sweeps (two
 // launches per RK4 step). Every variant produces bit-identical results.
@@ -100,6 +137,8 @@ int stage_variant_count(int dtype);
 const StageVariant& stage_variant(int dtype, int v);
 bool variant_is_fused(int dtype, int v);
 int default_stage_variant(int nx, int ny, int nz, int dtype);
+// The per-stage variant that single stages of a fused solver run on (adjoint recompute, Euler).
+int per_stage_variant(int nx, int ny, int nz, int dtype);
 
 // ------------------------------------------------------------------ batched stages (batch.hip)
 // Per-instance arguments of one sweep (per-stage mode: StageArgs, fused mode: FusedArgs), and the
@@ -128,11 +167,12 @@ void batch_tile_shape(bool fused, int* tx, int* ty, int* kz);
 
 // ------------------------------------------------------------------ adjoint (adjoint.hip)
 // Tiled z-march with tile shape `tile` (an index from adjoint_tile_index or
-// adjoint_default_tile); big forces the large-array addressing form.
+// adjoint_default_tile) and z-chunks of kz planes (0: chosen per launch); big forces the
+// large-array addressing form.
 template <typename T>
-hipError_t launch_adjoint_stage(const AdjArgs<T>& a, int tile, bool big, hipStream_t st);
-int adjoint_tile_index(int tx, int ty, int kz);       // -1 if that shape has no adjoint kernel
-int adjoint_default_tile(int nx, int ny, int nz);     // first shape with >= 512 workgroups
+hipError_t launch_adjoint_stage(const AdjArgs<T>& a, int tile, int kz, bool big, hipStream_t st);
+int adjoint_tile_index(int tx, int ty);               // -1 if that shape has no adjoint kernel
+int adjoint_default_tile(int nx, int ny, int nz);
 template <typename T>
 hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st);  // one thread per cell
 
@@ -155,6 +195,7 @@ hipError_t launch_velocity_grad(int nx, int ny, int nz, double dx, int M, const 
                                 double* scratch, hipStream_t st);
 
 // ------------------------------------------------------------------ small utilities
+int device_compute_units();  // of the current device; 0 on error (cached per device)
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t st);
 template <typename T>

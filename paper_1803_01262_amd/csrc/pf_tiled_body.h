@@ -2,7 +2,7 @@
 // and the batched persistent launch (batch.hip) so that both give bit-identical results.
 //
 // A workgroup of TX x TY threads owns the column tile [i0, i0+TX) x [j0, j0+TY) and marches the
-// planes [k0, k0+KZ) along z. Per plane it keeps, in LDS, a three-plane ring of the stage input
+// planes [k0, k1) along z. Per plane it keeps, in LDS, a three-plane ring of the stage input
 // with a two-cell halo (the reach of the sharpening term: the normal at a face neighbour needs
 // its own neighbours), and the x- and y-components of the sharpening product q = phi(1-phi)n of
 // the current and next plane (with a one-cell halo in their own direction only); the
@@ -22,8 +22,8 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, int KZ, bool BIG>
-__device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, int tj, int tk)
+template <typename T, int TX, int TY, bool BIG>
+__device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, int tj, int k0, int k1)
 {
     constexpr int NT = TX * TY;
     constexpr int PW = TX + 4, PH = TY + 4, PS = PW * PH;  // stage-input plane with halo 2
@@ -38,8 +38,7 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * ny;
 
-    const int i0 = ti * TX, j0 = tj * TY, k0 = tk * KZ;
-    const int k1 = min(k0 + KZ, nz);
+    const int i0 = ti * TX, j0 = tj * TY;
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;

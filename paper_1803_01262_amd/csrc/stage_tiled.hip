@@ -1,5 +1,5 @@
 // Stage kernel, tiled variants: each workgroup owns a TX x TY column tile and marches a chunk of
-// KZ planes along z.
+// kz planes along z (kz fixed by the variant, or chosen per launch).
 //
 // Per plane it keeps, in LDS, a three-plane ring of the stage input with a two-cell halo (the
 // reach of the sharpening term: the normal at a face neighbour needs its own neighbours), the
@@ -16,22 +16,21 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, int KZ, bool BIG>
+template <typename T, int TX, int TY, bool BIG>
 __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int tiles_x,
-                                                             int tiles_y)
+                                                             int tiles_y, int kz)
 {
     // XCD-aware tile order: consecutive workgroup ids go round-robin over the 8 XCDs; give each
     // XCD a contiguous range of tiles (x fastest, then y, then z-chunk).
-    int b = blockIdx.x;
-    const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    int b = xcd_tile_order(blockIdx.x, gridDim.x);
     const int ti = b % tiles_x;
     b /= tiles_x;
     const int tj = b % tiles_y;
-    const int tk = b / tiles_y;
-    tiled_stage_body<T, TX, TY, KZ, BIG>(a, ti, tj, tk);
+    const int k0 = (b / tiles_y) * kz;
+    tiled_stage_body<T, TX, TY, BIG>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
+// KZ: planes per z-chunk; KZ = 0 chooses it per launch (launch_chunk_planes).
 // FORCE_BIG selects the per-plane descriptor form even for small arrays (it is what arrays of
 // 4 GiB or more take), so that form can be checked against the default one at any size.
 template <typename T, int TX, int TY, int KZ, bool FORCE_BIG>
@@ -39,15 +38,23 @@ hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
 {
     const int tiles_x = (a.nx + TX - 1) / TX;
     const int tiles_y = (a.ny + TY - 1) / TY;
-    const int chunks = (a.nz + KZ - 1) / KZ;
-    const long long blocks = (long long)tiles_x * tiles_y * chunks;
+    if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0) return hipErrorInvalidValue;
+    const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
+    int kz = KZ;
+    if (KZ == 0) {
+        const void* k = big ? (const void*)stage_tiled_kernel<T, TX, TY, true>
+                            : (const void*)stage_tiled_kernel<T, TX, TY, false>;
+        kz = launch_chunk_planes(k, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
+        if (kz <= 0) return hipErrorInvalidDevice;
+    }
+    const long long blocks = (long long)tiles_x * tiles_y * ((a.nz + kz - 1) / kz);
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T)))
-        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, KZ, true>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+    if (big)
+        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, true>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     else
-        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, KZ, false>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y);
+        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, false>), dim3((unsigned)blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     return hipGetLastError();
 }
 
@@ -62,6 +69,13 @@ hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st);
 #define PF_FUSED(TX, TY, KZ)                                                            \
     {"fused_" #TX "x" #TY "x" #KZ, nullptr, nullptr,                                    \
      launch_fused<float, TX, TY, KZ, false>, launch_fused<double, TX, TY, KZ, false>}
+// chunk length chosen per launch (launch_chunk_planes)
+#define PF_TILED_AUTO(TX, TY)                                                           \
+    {"tiled_" #TX "x" #TY, launch_stage_tiled<float, TX, TY, 0, false>,                  \
+     launch_stage_tiled<double, TX, TY, 0, false>, nullptr, nullptr}
+#define PF_FUSED_AUTO(TX, TY)                                                           \
+    {"fused_" #TX "x" #TY, nullptr, nullptr, launch_fused<float, TX, TY, 0, false>,     \
+     launch_fused<double, TX, TY, 0, false>}
 #define PF_FUSED32(TX, TY, KZ)                                                          \
     {"fused_" #TX "x" #TY "x" #KZ, nullptr, nullptr,                                    \
      launch_fused<float, TX, TY, KZ, false>, nullptr}
@@ -76,11 +90,16 @@ static const StageVariant kVariants[] = {
     PF_TILED(64, 4, 64),
     PF_TILED(32, 8, 32),
     PF_TILED(128, 4, 32),
+    PF_TILED_AUTO(64, 8),
+    PF_TILED_AUTO(64, 4),
+    PF_TILED_AUTO(32, 4),
     {"global", launch_stage_global<float>, launch_stage_global<double>, nullptr, nullptr},
     PF_FUSED(64, 8, 32),
     PF_FUSED(64, 8, 64),
     PF_FUSED(32, 16, 32),
     PF_FUSED(32, 16, 64),
+    PF_FUSED_AUTO(64, 8),
+    PF_FUSED_AUTO(32, 16),
     PF_FUSED32(64, 16, 32),
     PF_FUSED32(64, 16, 64),
     PF_FUSED32(128, 8, 32),
@@ -133,36 +152,45 @@ bool variant_is_fused(int dtype, int v)
     return dtype == PF_F32 ? s.fused_f32 != nullptr : s.fused_f64 != nullptr;
 }
 
-// Default tile choice before (or without) autotuning: the first variant of a per-dtype
-// preference list (fastest first, as measured on MI355X at 256^3-512^3) whose launch has at
-// least 512 workgroups, i.e. two per compute unit; small grids fall through to small tiles.
+static int variant_by_name(int dtype, const char* name)
+{
+    for (int v = 0; v < stage_variant_count(dtype); ++v)
+        if (std::strcmp(stage_variant(dtype, v).name, name) == 0) return v;
+    return 0;
+}
+
+// 64-wide tiles unless they pad more columns than 32-wide ones.
+static bool prefer_x64(int nx)
+{
+    return (nx + 63) / 64 * 64 <= (nx + 31) / 32 * 32;
+}
+
+// Grids from this many cells up take the fused sweeps by default, smaller ones the per-stage
+// kernels (MI355X, 32^3-256^3: FP32 per-stage leads to 64^3, fused from 96^3; FP64 per-stage leads
+// to 96^3 and ties at 128^3).
+constexpr long long kFusedMinCellsF32 = 80LL * 80 * 80;
+constexpr long long kFusedMinCellsF64 = 128LL * 128 * 128;
+
+// Default variant before (or without) autotuning, from MI355X measurements at 32^3-640^3, all with
+// the chunk length chosen per launch: the fused sweeps (FP32 on 64x8 tiles unless those pad more
+// columns than 32x16, FP64 on 32x16) and, below the size thresholds, the per-stage kernel.
 int default_stage_variant(int nx, int ny, int nz, int dtype)
 {
-    struct Cand {
-        const char* name;
-        int tx, ty, kz;
-    };
-    static const Cand f32[] = {{"fused_64x8x64", 64, 8, 64},  {"fused_32x16x64", 32, 16, 64},
-                               {"fused_64x8x32", 64, 8, 32},  {"fused_32x16x32", 32, 16, 32},
-                               {"tiled_64x4x16", 64, 4, 16},  {"tiled_32x4x16", 32, 4, 16}};
-    static const Cand f64[] = {{"fused_32x16x64", 32, 16, 64}, {"fused_64x8x64", 64, 8, 64},
-                               {"fused_32x16x32", 32, 16, 32}, {"fused_64x8x32", 64, 8, 32},
-                               {"tiled_64x4x16", 64, 4, 16},   {"tiled_32x4x16", 32, 4, 16}};
-    const Cand* list = dtype == PF_F32 ? f32 : f64;
-    const int n = 6;
-    int pick = n - 1;
-    for (int c = 0; c < n; ++c) {
-        const long long blocks = (long long)((nx + list[c].tx - 1) / list[c].tx) *
-                                 ((ny + list[c].ty - 1) / list[c].ty) *
-                                 ((nz + list[c].kz - 1) / list[c].kz);
-        if (blocks >= 512) {
-            pick = c;
-            break;
-        }
-    }
-    for (int v = 0; v < stage_variant_count(dtype); ++v)
-        if (std::strcmp(stage_variant(dtype, v).name, list[pick].name) == 0) return v;
-    return 0;
+    const long long cells = (long long)nx * ny * nz;
+    if (dtype == PF_F32)
+        return cells >= kFusedMinCellsF32 ? variant_by_name(dtype, prefer_x64(nx) ? "fused_64x8" : "fused_32x16")
+                                          : per_stage_variant(nx, ny, nz, dtype);
+    return cells >= kFusedMinCellsF64 ? variant_by_name(dtype, "fused_32x16")
+                                      : per_stage_variant(nx, ny, nz, dtype);
+}
+
+// FP32 on 64x4 tiles unless those pad more columns than 32x4; FP64 on 32x4 (as fast or faster at
+// every measured size).
+int per_stage_variant(int nx, int ny, int nz, int dtype)
+{
+    (void)ny;
+    (void)nz;
+    return variant_by_name(dtype, dtype == PF_F32 && prefer_x64(nx) ? "tiled_64x4" : "tiled_32x4");
 }
 
 }  // namespace pf

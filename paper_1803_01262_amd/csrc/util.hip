@@ -1,5 +1,10 @@
 // Small element-wise kernels (copy, fill) used by the step schedules. They are plain kernels
 // rather than hipMemcpyAsync / hipMemsetAsync so that captured graphs hold kernel nodes only.
+#include <atomic>
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "pf_internal.h"
 
 namespace pf {
@@ -16,6 +21,48 @@ __global__ void fill_kernel(T* __restrict__ dst, T value, size_t n)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) dst[c] = value;
+}
+
+// Compute units of the current device, read once per device.
+int device_compute_units()
+{
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+    if (dev < 64) {
+        const int c = cached[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (dev < 64) cached[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
+
+int resident_groups_per_cu(const void* kernel, int threads)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, int>> cache;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const auto& e : cache)
+            if (e.first == kernel) return e.second;
+    }
+    int groups = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&groups, kernel, threads, 0) != hipSuccess ||
+        groups <= 0)
+        return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    cache.emplace_back(kernel, groups);
+    return groups;
+}
+
+int launch_chunk_planes(const void* kernel, int threads, long long tiles, int nz, int extra)
+{
+    const int cus = device_compute_units();
+    const int groups = resident_groups_per_cu(kernel, threads);
+    if (cus <= 0 || groups <= 0 || tiles <= 0 || nz <= 0) return 0;
+    return march_chunk_planes(tiles, nz, (long long)cus * groups, extra);
 }
 
 static unsigned grid_for(size_t n)

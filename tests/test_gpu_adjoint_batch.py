@@ -68,8 +68,9 @@ def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
 def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape):
     """The tiled adjoint stage kernel and the one-thread-per-cell kernel (paired with the
     'global' forward variant) give bit-identical lam and velocity gradients, for every adjoint
-    tile shape (lent by the per-stage forward variant of that shape), the large-array
-    addressing form (a '_big' variant) and a fused forward variant (tile chosen by size)."""
+    tile shape and chunk length (lent by the per-stage forward variant of that shape; none in
+    its name: chosen per launch), the large-array addressing form (a '_big' variant) and fused
+    forward variants (tile chosen by size, chunk per launch)."""
     pf = lib
     rng, phi, U, V, W, lam, dx = adj_case(4, shape)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -78,7 +79,7 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape):
     kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, dtype=dtype)
     nz, ny, nx = shape
     picks = ["global", "tiled_64x8x64", "tiled_64x8x16", "tiled_64x4x16", "tiled_32x4x16",
-             "tiled_64x8x16_big", "fused_32x16x32"]
+             "tiled_64x8x16_big", "fused_32x16x32", "tiled_64x4", "tiled_32x4", "fused_64x8"]
     res = []
     for v in (names.index(nm) for nm in picks):
         s = pf.Solver((nx, ny, nz), variant=v, **kw)
