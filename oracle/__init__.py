@@ -90,13 +90,20 @@ def rhs(phi, U, V, W, *, dx, eps, gamma, delta=0.0, s=1.0) -> np.ndarray:
     return f
 
 
+def _check_scheme(scheme):
+    if scheme not in (1, 2, 4):
+        raise ValueError(f"scheme must be 1 (Euler), 2 (RK2) or 4 (RK4), not {scheme!r}")
+
+
 def step(phi, U, V, W, *, dx, eps, gamma, dt, nsteps=1, delta=0.0, t0=0.0, scheme=4,
          fp32=False, vel_mode=0, vel_T=1.0) -> np.ndarray:
-    """nsteps explicit steps (scheme 1: Euler, Eq. 25; scheme 4: classic RK4, Eq. 28).
+    """nsteps explicit steps (scheme 1: Euler, Eq. 25; scheme 2: explicit midpoint RK2, Eq. 26;
+    scheme 4: classic RK4, Eq. 28).
 
     vel_mode 0: steady velocity; 1: u(x, t) = u0(x) cos(pi t / vel_T). fp32=True rounds every
     stage input and each new phi to float32 (storage precision) while computing in FP64.
     """
+    _check_scheme(scheme)
     out = _f64(phi).copy()
     U, V, W = map(_f64, (U, V, W))
     g = _grid(out.shape, dx, eps, gamma, delta)
@@ -144,6 +151,7 @@ def rhs_vjp(phi, U, V, W, lam, *, dx, eps, gamma, delta=0.0, s=1.0):
 def adjoint_step(phi, U, V, W, lam, *, dx, eps, gamma, dt, delta=0.0, t=0.0, scheme=4,
                  vel_mode=0, vel_T=1.0):
     """Adjoint of one step at phi_n: returns (lam_n, dU, dV, dW) given lam = dL/dphi_{n+1}."""
+    _check_scheme(scheme)
     phi, U, V, W = map(_f64, (phi, U, V, W))
     lam = _f64(lam).copy()
     ub, vb, wb = (np.zeros_like(phi) for _ in range(3))

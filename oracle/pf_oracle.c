@@ -25,7 +25,7 @@
  *    With delta > 0 the regularised n = g/sqrt(|g|^2 + delta^2) is used everywhere.
  *  - The i-1 sharpening term of Eq. 11/12 carries (phi^2 - phi), as Eq. 13 and Eq. 21 require.
  *  - Velocity with a time factor: u(x,t) = u0(x) s(t), s = 1 (steady) or cos(pi t / T);
- *    classic RK4 evaluates s at t, t+dt/2, t+dt/2, t+dt.
+ *    classic RK4 evaluates s at t, t+dt/2, t+dt/2, t+dt; the explicit midpoint RK2 at t, t+dt/2.
  *  - FP32-storage mode: every RK stage input and the new phi are rounded to float32 at the
  *    points where a value must be materialised; arithmetic stays FP64.
  */
@@ -141,8 +141,9 @@ static double time_factor(int vel_mode, double vel_T, double t)
 }
 
 /* nsteps explicit steps of Eq. 1 in place on phi (Sec. 2.3).
- * scheme 1: forward Euler (Eq. 25 regime); scheme 4: classic RK4 (Eq. 28, used for every
- * experiment of Sec. 3). Step n starts at t0 + n*dt. */
+ * scheme 1: forward Euler (Eq. 25 regime); scheme 2: the explicit midpoint rule (RK2, Eq. 26
+ * regime); scheme 4: classic RK4 (Eq. 28, used for every experiment of Sec. 3). Step n starts
+ * at t0 + n*dt. */
 void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int vel_mode,
               double vel_T, int64_t nsteps, double *phi, const double *U, const double *V,
               const double *W)
@@ -156,6 +157,14 @@ void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int
         if (scheme == 1) {
             orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
             for (int64_t c = 0; c < N; ++c) phi[c] = round_storage(phi[c] + dt * k1[c], fp32);
+            continue;
+        }
+        if (scheme == 2) {
+            /* half an Euler step to the midpoint, then the whole step with the midpoint slope */
+            orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
+            for (int64_t c = 0; c < N; ++c) y[c] = round_storage(phi[c] + 0.5 * dt * k1[c], fp32);
+            orc_rhs(g, time_factor(vel_mode, vel_T, t + 0.5 * dt), y, U, V, W, k2);
+            for (int64_t c = 0; c < N; ++c) phi[c] = round_storage(phi[c] + dt * k2[c], fp32);
             continue;
         }
         orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
@@ -351,24 +360,34 @@ void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int ve
         free(out);
         return;
     }
-    /* recompute the stage inputs y1..y4 of the forward RK4 step */
+    /* Both Runge-Kutta schemes have stage inputs y_1 = phi, y_{s+1} = phi + ca[s] k_s and
+     * phi' = phi + sum_s bw[s] k_s, with k_s = f(y_s, st[s]):
+     *   RK2 (explicit midpoint): ca = {dt/2}, bw = {0, dt}, st = {t, t+dt/2};
+     *   RK4 (classic): ca = {dt/2, dt/2, dt}, bw = {dt/6, dt/3, dt/3, dt/6},
+     *                  st = {t, t+dt/2, t+dt/2, t+dt}. */
+    const int ns = scheme == 2 ? 2 : 4;
+    double st[4] = {t, t + 0.5 * dt, t + 0.5 * dt, t + dt};
+    double ca[3] = {0.5 * dt, 0.5 * dt, dt};
+    double bw[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    if (scheme == 2) {
+        bw[0] = 0.0;
+        bw[1] = dt;
+    }
+    /* recompute the stage inputs of the forward step */
     double *y[4], *kk[3];
-    for (int s = 0; s < 4; ++s) y[s] = malloc(sizeof(double) * N);
-    for (int s = 0; s < 3; ++s) kk[s] = malloc(sizeof(double) * N);
-    const double st[4] = {t, t + 0.5 * dt, t + 0.5 * dt, t + dt};
-    const double ca[3] = {0.5 * dt, 0.5 * dt, dt};  /* y_{s+1} = phi + ca[s] k_s */
+    for (int s = 0; s < ns; ++s) y[s] = malloc(sizeof(double) * N);
+    for (int s = 0; s < ns - 1; ++s) kk[s] = malloc(sizeof(double) * N);
     memcpy(y[0], phi, sizeof(double) * N);
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < ns - 1; ++s) {
         orc_rhs(g, time_factor(vel_mode, vel_T, st[s]), y[s], U, V, W, kk[s]);
         for (int64_t c = 0; c < N; ++c) y[s + 1][c] = phi[c] + ca[s] * kk[s][c];
     }
-    /* reverse sweep: phi' = phi + dt/6 (k1 + 2 k2 + 2 k3 + k4) */
-    const double bw[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    /* reverse sweep over the stages, newest first */
     for (int64_t c = 0; c < N; ++c) out[c] = lam[c];
     double *ybar_next = NULL; /* ybar of the stage after the current one */
     double *ybar[4];
-    for (int s = 0; s < 4; ++s) ybar[s] = calloc(N, sizeof(double));
-    for (int s = 3; s >= 0; --s) {
+    for (int s = 0; s < ns; ++s) ybar[s] = calloc(N, sizeof(double));
+    for (int s = ns - 1; s >= 0; --s) {
         for (int64_t c = 0; c < N; ++c)
             kb[c] = bw[s] * lam[c] + (ybar_next ? ca[s] * ybar_next[c] : 0.0);
         orc_rhs_vjp(g, time_factor(vel_mode, vel_T, st[s]), y[s], U, V, W, kb, ybar[s], Ubar,
@@ -376,12 +395,16 @@ void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int ve
         ybar_next = ybar[s];
     }
     /* every stage input is phi + (something), so phibar collects all the ybar */
-    for (int64_t c = 0; c < N; ++c) lam[c] = out[c] + ybar[0][c] + ybar[1][c] + ybar[2][c] + ybar[3][c];
-    for (int s = 0; s < 4; ++s) {
+    for (int64_t c = 0; c < N; ++c) {
+        double sum = out[c];
+        for (int s = 0; s < ns; ++s) sum += ybar[s][c];
+        lam[c] = sum;
+    }
+    for (int s = 0; s < ns; ++s) {
         free(y[s]);
         free(ybar[s]);
     }
-    for (int s = 0; s < 3; ++s) free(kk[s]);
+    for (int s = 0; s < ns - 1; ++s) free(kk[s]);
     free(kb);
     free(yb);
     free(out);

@@ -2,9 +2,10 @@
 
 Each test ties the oracle to something other than itself: the printed coefficient forms
 (Eqs. 13, 18-22), telescoping conservation, the complement symmetry of Eq. 16, the Euler
-boundedness theorem of Sec. 2.2, the analytic tanh equilibrium (Sec. 1), the textbook RK4
-amplification factor for pure advection (Eq. 3 with gamma = 0), shift equivariance and the
-printed parameter criteria.
+boundedness theorem of Sec. 2.2, the analytic tanh equilibrium (Sec. 1), the textbook RK2 and RK4
+amplification factors for pure advection (Eq. 3 with gamma = 0), the boundedness of RK2 at its
+Eq. 26 step above the crossover line (Sec. 2.3, Fig. 6), shift equivariance and the printed
+parameter criteria.
 """
 import math
 
@@ -85,8 +86,9 @@ def test_eq19_divergence_term():
 # --------------------------------------------------------------------- conservation
 
 
+@pytest.mark.parametrize("scheme", [2, 4])
 @pytest.mark.parametrize("solenoidal_field", [True, False])
-def test_mass_conserved_to_roundoff(solenoidal_field):
+def test_mass_conserved_to_roundoff(solenoidal_field, scheme):
     """Sum of f telescopes to zero for any face velocity (Sec. 2.2 flux form)."""
     rng = np.random.default_rng(3)
     shape, dx = (12, 10, 14), 1.0 / 14
@@ -96,7 +98,9 @@ def test_mass_conserved_to_roundoff(solenoidal_field):
     else:
         U, V, W = (rng.uniform(-1, 1, size=shape) for _ in range(3))
     m0 = oracle.reduce(phi, dx=dx)[0]
-    out = oracle.step(phi, U, V, W, dx=dx, eps=dx, gamma=1.0, dt=0.2 * dx, nsteps=50)
+    # within both schemes' 3D limits (Eq. 26: dx/6 here; Eq. 28: 0.23 dx)
+    out = oracle.step(phi, U, V, W, dx=dx, eps=dx, gamma=1.0, dt=0.15 * dx, nsteps=50,
+                      scheme=scheme)
     m1 = oracle.reduce(out, dx=dx)[0]
     assert abs(m1 - m0) / m0 < 1e-12
     f = oracle.rhs(phi, U, V, W, dx=dx, eps=dx, gamma=1.0)
@@ -106,7 +110,7 @@ def test_mass_conserved_to_roundoff(solenoidal_field):
 # --------------------------------------------------------------------- complement symmetry
 
 
-@pytest.mark.parametrize("scheme", [1, 4])
+@pytest.mark.parametrize("scheme", [1, 2, 4])
 def test_complement_symmetry(scheme):
     """step(1 - phi) == 1 - step(phi) for a discretely solenoidal field (Eq. 16, Sec. 2.2.2)."""
     rng = np.random.default_rng(4)
@@ -191,10 +195,12 @@ def test_tanh_profile_is_discrete_equilibrium():
 # --------------------------------------------------------------------- pure advection
 
 
+@pytest.mark.parametrize("scheme", [2, 4])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_gamma0_rk4_amplification(axis):
-    """gamma = 0, uniform u: a sampled Fourier mode is multiplied per step by the RK4 polynomial
-    R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24, z = -i u dt sin(k dx)/dx (Eq. 3 with gamma = 0)."""
+def test_gamma0_rk_amplification(axis, scheme):
+    """gamma = 0, uniform u: a sampled Fourier mode is multiplied per step by the scheme's
+    stability polynomial, z = -i u dt sin(k dx)/dx (Eq. 3 with gamma = 0): RK4
+    R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24; the explicit midpoint rule R(z) = 1 + z + z^2/2."""
     n, m, u, dx = 24, 3, 0.8, 1.0 / 24
     dt = 0.4 * dx / u
     k = 2 * np.pi * m
@@ -205,9 +211,9 @@ def test_gamma0_rk4_amplification(axis):
     vel = [np.zeros(shape) for _ in range(3)]
     vel[axis][:] = u
     nsteps = 7
-    out = oracle.step(phi, *vel, dx=dx, eps=dx, gamma=0.0, dt=dt, nsteps=nsteps)
+    out = oracle.step(phi, *vel, dx=dx, eps=dx, gamma=0.0, dt=dt, nsteps=nsteps, scheme=scheme)
     z = -1j * u * dt * np.sin(k * dx) / dx
-    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    R = 1 + z + z ** 2 / 2 + (z ** 3 / 6 + z ** 4 / 24 if scheme == 4 else 0)
     exact = np.real(R ** nsteps * np.exp(1j * k * x)).reshape(shape)
     np.testing.assert_allclose(out, exact, rtol=0, atol=1e-14)
 
@@ -230,6 +236,25 @@ def test_time_factor_cos_reversal():
     k3 = s[2] * D(phi + dt / 2 * k2)
     k4 = s[3] * D(phi + dt * k3)
     np.testing.assert_allclose(got, phi + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4), atol=1e-15)
+
+
+def test_time_factor_cos_reversal_rk2():
+    """The same for the explicit midpoint rule: s at t for the half step and at t + dt/2 for
+    the whole step (a stage time of t or t + dt would differ at O(dt^2))."""
+    n, dx, T = 16, 1.0 / 16, 0.7
+    rng = np.random.default_rng(18)
+    phi = rand_phi(rng, (1, 1, n))
+    U = np.full((1, 1, n), 0.9)
+    Z = np.zeros_like(U)
+    t0, dt = 0.13, 0.01
+    got = oracle.step(phi, U, Z, Z, dx=dx, eps=dx, gamma=0.0, dt=dt, t0=t0, vel_mode=1,
+                      vel_T=T, scheme=2)
+    D = lambda p: oracle.rhs(p, U, Z, Z, dx=dx, eps=dx, gamma=0.0)  # noqa: E731
+    s0, s1 = math.cos(math.pi * t0 / T), math.cos(math.pi * (t0 + dt / 2) / T)
+    want = phi + dt * s1 * D(phi + dt / 2 * s0 * D(phi))
+    np.testing.assert_allclose(got, want, atol=1e-15)
+    wrong = phi + dt * math.cos(math.pi * (t0 + dt) / T) * D(phi + dt / 2 * s0 * D(phi))
+    assert np.abs(wrong - got).max() > 1e-7
 
 
 # --------------------------------------------------------------------- equivariance, dims
@@ -363,3 +388,44 @@ def test_table2_classification_reproduced_by_the_stepper():
             lo, hi = min(lo, phi.min()), max(hi, phi.max())
         bounded = lo >= -EPS64 and hi <= 1 + EPS64
         assert bounded == p["bounded"], (p["point"], lo, hi)
+
+
+# --------------------------------------------------------------------- RK2 boundedness
+
+
+def _drop_1d_extremes(eps_over_dx, gamma_over_u, scheme_name, scheme):
+    """1D drop of diameter 1 advected by u = 1 for one period in [0, 2) (Sec. 2.1, Fig. 1),
+    n = 50, tanh interfaces, dt = the scheme's diffusion limit (Eqs. 25-28) rounded down to a
+    whole number of steps; returns the extremes of phi over the run."""
+    n, L, u = 50, 2.0, 1.0
+    dx = L / n
+    eps, gamma = eps_over_dx * dx, gamma_over_u * u
+    x = (np.arange(n) + 0.5) * dx
+    phi = fx.tanh_profile(0.5 - np.abs(x - L / 2), eps).reshape(1, 1, n)
+    U = np.full_like(phi, u)
+    Z = np.zeros_like(phi)
+    nsteps = math.ceil(L / u / params.dt_max(scheme_name, 1, dx, gamma, eps))
+    lo, hi = 1.0, 0.0
+    for _ in range(nsteps):
+        phi = oracle.step(phi, U, Z, Z, dx=dx, eps=eps, gamma=gamma, dt=L / u / nsteps,
+                          scheme=scheme)
+        lo, hi = min(lo, phi.min()), max(hi, phi.max())
+    return lo, hi
+
+
+@pytest.mark.parametrize("eps_over_dx,gamma_over_u", [(1.0, 1.0), (0.75, 2.0), (1.5, 1.0),
+                                                       (2.0, 0.5)])
+def test_rk2_at_eq26_bounded_on_and_above_the_crossover_line(eps_over_dx, gamma_over_u):
+    """Sec. 2.3 and Fig. 6(a): with the explicit midpoint rule at its diffusive limit (Eq. 26),
+    points on or above the crossover line (Eq. 9) keep phi in [0, 1] for a whole period."""
+    assert eps_over_dx >= params.crossover_eps_over_dx(gamma_over_u) - 1e-12
+    lo, hi = _drop_1d_extremes(eps_over_dx, gamma_over_u, "rk2", 2)
+    assert lo >= -EPS64 and hi <= 1 + EPS64, (lo, hi)
+
+
+@pytest.mark.parametrize("eps_over_dx,gamma_over_u", [(0.55, 1.0), (0.8, 0.5)])
+def test_rk2_below_the_crossover_line_leaves_bounds(eps_over_dx, gamma_over_u):
+    """Negative control: below the line the same runs leave [0, 1] (Fig. 6(a))."""
+    assert eps_over_dx < params.crossover_eps_over_dx(gamma_over_u)
+    lo, hi = _drop_1d_extremes(eps_over_dx, gamma_over_u, "rk2", 2)
+    assert lo < -1e-3 and hi > 1 + 1e-3, (lo, hi)
