@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # two-stage sweeps (6 + 7)
 WORDS_PER_CELL_STEP = {"tiled": 28, "global": 28, "fused": 13}
 LAUNCHES_PER_STEP = {"tiled": 4, "global": 4, "fused": 2}
+# the explicit midpoint rule: per-stage S1 reads phi, U, V, W and writes ya; S2 reads ya, phi, U,
+# V, W and writes phi. Fused: one sweep reads phi, U, V, W and writes the new phi.
+RK2_WORDS_PER_CELL_STEP = {"tiled": 11, "global": 11, "fused": 5}
 
 
 def kind(variant_name: str) -> str:
@@ -80,10 +83,12 @@ def setup_roofline(pf, fx, n, dtype, st, seed=3):
     return c, phi, u, v, w
 
 
-def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, variant=-1):
+def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, variant=-1,
+                 scheme="rk4", dt=None):
     import torch
     n = c.shape[0]
-    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, variant=variant)
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt if dt is None else dt, dtype=dtype,
+                  variant=variant, scheme=scheme)
     tuned = None
     if autotune and variant < 0:
         best, times = s.autotune(reps=3, stream=st)
@@ -336,6 +341,22 @@ def main():
                                   "frac_of_8tbs": round(w2 * e2 * cells / ms2 / 1e6 / HBM_PEAK_GBS, 4),
                                   "kernel": vname2}
         del phi2, u2, v2, w2
+        torch.cuda.empty_cache()
+        log("timing RK2")
+        c3, phi3, u3, v3, w3 = setup_roofline(pf, fx, n, args.dtype, st)
+        # the explicit midpoint rule at 0.9 x its diffusive limit (Eq. 26, three axes)
+        dt_rk2 = min(c3.dt, 0.9 * c3.dx * c3.dx / (6.0 * c3.gamma * c3.eps))
+        ms3, vname3, _, _, _ = time_forward(pf, c3, phi3, u3, v3, w3, args.dtype,
+                                            min(args.steps, 200), 5, st, autotune=False,
+                                            scheme="rk2", dt=dt_rk2)
+        e3 = 8 if args.dtype == "f64" else 4
+        w3 = RK2_WORDS_PER_CELL_STEP[kind(vname3)]
+        extras[f"rk2_{n}_{args.dtype}"] = {"ms_per_step": round(ms3, 4),
+                                           "gcell_s": round(cells / ms3 / 1e6, 2),
+                                           "achieved_gbs": round(w3 * e3 * cells / ms3 / 1e6, 1),
+                                           "frac_of_8tbs": round(w3 * e3 * cells / ms3 / 1e6 / HBM_PEAK_GBS, 4),
+                                           "words_per_cell_step": w3, "kernel": vname3}
+        del phi3, u3, v3, w3
         torch.cuda.empty_cache()
         log("timing adjoint")
         extras["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st)

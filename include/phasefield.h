@@ -8,8 +8,8 @@
  * faces (a staggered MAC grid), unit normal and the sharpening product phi(1-phi)n at cell
  * centres averaged onto faces, diffusive and advective face fluxes from second-order central
  * differences, and the cell update as the divergence of the face fluxes. Time integration is
- * forward Euler (Sec. 2.3, Eq. 25) or classic fourth-order Runge-Kutta (Eq. 28; the scheme of
- * every experiment in Sec. 3).
+ * forward Euler (Sec. 2.3, Eq. 25), the explicit midpoint rule (RK2, Eq. 26) or classic
+ * fourth-order Runge-Kutta (Eq. 28; the scheme of every experiment in Sec. 3).
  *
  * Data layout (every array): C-contiguous [nz][ny][nx], x fastest, periodic in every axis.
  *   phi[k][j][i]  cell-centre phase field.
@@ -55,7 +55,7 @@ typedef enum {
 
 typedef enum { PF_F32 = 0, PF_F64 = 1 } pf_dtype;             /* storage precision      */
 typedef enum { PF_BC_PERIODIC = 0, PF_BC_WALL = 1 } pf_bc;      /* WALL: unsupported      */
-typedef enum { PF_EULER = 1, PF_RK4 = 4 } pf_scheme;
+typedef enum { PF_EULER = 1, PF_RK2 = 2, PF_RK4 = 4 } pf_scheme;
 typedef enum { PF_VEL_STEADY = 0, PF_VEL_COS_REVERSAL = 1 } pf_velmode;
 
 /* Problem statement of one simulation (Sec. 2.2: uniform isotropic mesh dx; eps and gamma
@@ -88,7 +88,8 @@ void phasefield_default_params(pf_params *p);
  *                          >= 0 is the bounded regime proven in Sec. 2.2.
  *   crossover_margin_eq24: the same with the relaxed line of Eqs. 23-24 (identical here,
  *                          because the face speed is already the largest component).
- *   dt_max_scheme:         Eq. 25 (Euler) or Eq. 28 (RK4) with D_f = axes longer than 1 cell.
+ *   dt_max_scheme:         Eq. 25 (Euler), Eq. 26 (RK2) or Eq. 28 (RK4) with D_f = axes
+ *                          longer than 1 cell.
  *   dt_over_dtmax:         dt / dt_max_scheme. */
 typedef struct {
     double crossover_margin_eq17;
@@ -113,7 +114,8 @@ pf_status phasefield_destroy(pf_solver *s);
 
 /* Advance phi IN PLACE by nsteps steps of the handle's scheme (Sec. 2.3), starting at time
  * t0; step m runs from t0 + m dt. u, v, w: face velocity u0 (the time factor s(t) is applied
- * by the library at the RK4 stage times t, t+dt/2, t+dt/2, t+dt). nsteps = 0 is a no-op.
+ * by the library at the stage times: RK4 t, t+dt/2, t+dt/2, t+dt; RK2 t, t+dt/2; Euler t).
+ * nsteps = 0 is a no-op.
  * The handle's stage buffers are overwritten (and, with a fused variant, one of them holds phi
  * between steps); phi holds the result when the enqueued work completes.
  * Errors: PF_ERR_INVALID (null/misaligned pointer, nsteps < 0), PF_ERR_DEVICE. */
@@ -196,8 +198,8 @@ typedef struct pf_batch pf_batch;
 
 /* per_instance: HOST array of count parameter sets (all with the same dtype).
  * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtypes), PF_ERR_UNSUPPORTED (a set
- * with the Euler scheme, a time-varying velocity, or a field of 4 GiB or more: such grids take
- * a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * with a scheme other than RK4, a time-varying velocity, or a field of 4 GiB or more: such
+ * grids take a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_batch_create(const pf_params *per_instance, int32_t count, pf_batch **out);
 
 /* Advance every instance b by nsteps steps: phi[b], u[b], v[b], w[b] are HOST arrays of count

@@ -80,7 +80,7 @@ pf_status pf::validate_params(const pf_params* p)
     if (!(p->delta >= 0.0) || !std::isfinite(p->delta))
         return fail(PF_ERR_INVALID, "delta must be >= 0");
     if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_ERR_INVALID, "dtype = %d", p->dtype);
-    if (p->scheme != PF_EULER && p->scheme != PF_RK4)
+    if (p->scheme != PF_EULER && p->scheme != PF_RK2 && p->scheme != PF_RK4)
         return fail(PF_ERR_INVALID, "scheme = %d", p->scheme);
     if (p->vel_mode != PF_VEL_STEADY && p->vel_mode != PF_VEL_COS_REVERSAL)
         return fail(PF_ERR_INVALID, "vel_mode = %d", p->vel_mode);
@@ -115,7 +115,8 @@ extern "C" pf_status phasefield_check_params(const pf_params* p, double max_face
     const int D = active_dims(p->n);
     const double ge = p->gamma * p->eps;
     const double base = ge > 0.0 ? p->dx * p->dx / ge : INFINITY;
-    out->dt_max_scheme = p->scheme == PF_EULER ? base / (2.0 * D) : 2.79 * base / (4.0 * D);
+    // Eq. 25 (Euler) and Eq. 26 (RK2) coincide; Eq. 28 (RK4)
+    out->dt_max_scheme = p->scheme == PF_RK4 ? 2.79 * base / (4.0 * D) : base / (2.0 * D);
     out->dt_over_dtmax = p->dt / out->dt_max_scheme;
     return PF_OK;
 }
@@ -326,8 +327,10 @@ template hipError_t pf::run_stage<double>(int, const StageArgs<double>&, hipStre
 //     S3: ya = phi + dt k3,    acc += dt/3 k3               (k3 = f(yb, t + dt/2))
 //     S4: phi = acc + dt/6 k4                               (k4 = f(ya, t + dt))
 //   Euler (Eq. 25): acc = phi + dt f(phi, t); phi = acc.
+//   RK2, the explicit midpoint rule (Eq. 26):
+//     S1: ya = phi + dt/2 k1;  S2: phi = phi + dt k2   (k2 = f(ya, t + dt/2))
 // S4 writes phi in place: it reads phi nowhere (its stencil input is ya, acc is read only at
-// the cell being written).
+// the cell being written). RK2's S2 likewise reads phi only at the cell it writes.
 template <typename T>
 hipError_t pf::enqueue_step(const pf_params& p, int variant, T* phi, const T* U, const T* V,
                             const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st)
@@ -341,6 +344,13 @@ hipError_t pf::enqueue_step(const pf_params& p, int variant, T* phi, const T* U,
         return launch_copy<T>(phi, acc, (size_t)p.n[0] * p.n[1] * p.n[2], st);
     }
     const double sh = time_factor(p, t + 0.5 * dt);
+    if (p.scheme == PF_RK2) {
+        e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, nullptr, ya,
+                                                nullptr, 0.5 * dt, 0.0, U, V, W), st);
+        if (e != hipSuccess) return e;
+        return run_stage<T>(variant, make_stage<T>(p, sh, ya, nullptr, phi, nullptr, phi, 0.0, dt,
+                                                   U, V, W), st);
+    }
     e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, phi, ya, acc,
                                             0.5 * dt, dt / 6.0, U, V, W), st);
     if (e != hipSuccess) return e;
@@ -362,7 +372,8 @@ template hipError_t pf::enqueue_step<double>(const pf_params&, int, double*, con
 
 // Arguments of one fused sweep of the RK4 step at time t (pf_fused_body.h): sweep A runs stages
 // 1-2 from phi_cur (writing yb and the accumulator into phi_next), sweep B runs stages 3-4 from
-// yb (writing the new phi over the accumulator in phi_next).
+// yb (writing the new phi over the accumulator in phi_next). RK2 is sweep A alone: the midpoint
+// value in LDS, the new phi into phi_next, no accumulator.
 template <typename T>
 FusedArgs<T> pf::make_fused(const pf_params& p, bool sweep_b, double t, const T* phi_cur,
                             T* phi_next, const T* U, const T* V, const T* W, T* yb)
@@ -381,7 +392,18 @@ FusedArgs<T> pf::make_fused(const pf_params& p, bool sweep_b, double t, const T*
     a.delta2 = (T)(p.delta * p.delta);
     a.phi = phi_cur;
     a.out_acc = phi_next;
-    if (!sweep_b) {
+    if (p.scheme == PF_RK2) {
+        a.y = phi_cur;
+        a.acc_in = nullptr;
+        a.out_y = phi_next;
+        a.out_acc = nullptr;
+        a.nhs1 = (T)(-0.5 * time_factor(p, t) / p.dx);
+        a.nhs2 = (T)(-0.5 * time_factor(p, t + 0.5 * dt) / p.dx);
+        a.c_mid = (T)(0.5 * dt);
+        a.c_acc1 = (T)0;
+        a.c_y2 = (T)dt;
+        a.c_acc2 = (T)0;
+    } else if (!sweep_b) {
         a.y = phi_cur;
         a.acc_in = nullptr;
         a.out_y = yb;
@@ -411,7 +433,7 @@ template FusedArgs<double> pf::make_fused<double>(const pf_params&, bool, double
                                                   double*, const double*, const double*,
                                                   const double*, double*);
 
-// One RK4 step as two fused sweeps; the new phi lands in phi_next.
+// One RK4 step as two fused sweeps (RK2: sweep A alone); the new phi lands in phi_next.
 template <typename T>
 static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* phi_cur,
                                      T* phi_next, const T* U, const T* V, const T* W, T* yb,
@@ -419,7 +441,8 @@ static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* p
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
     const StageVariant& sv = stage_variant(dtype, variant);
-    for (int sweep = 0; sweep < 2; ++sweep) {
+    const int sweeps = p.scheme == PF_RK2 ? 1 : 2;
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
         const FusedArgs<T> a = make_fused<T>(p, sweep == 1, t, phi_cur, phi_next, U, V, W, yb);
         hipError_t e;
         if constexpr (sizeof(T) == 4)
@@ -439,7 +462,7 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
                              hipStream_t st)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
-    const bool fused = p.scheme == PF_RK4 && variant_is_fused(dtype, variant);
+    const bool fused = p.scheme != PF_EULER && variant_is_fused(dtype, variant);
     T* cur = phi;
     for (int m = 0; m < nsteps; ++m) {
         const double t = t0 + (double)m * p.dt;

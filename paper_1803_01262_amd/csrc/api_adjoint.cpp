@@ -90,6 +90,22 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         if (e == hipSuccess) e = launch_copy<T>(lam, L, s->N, st);
         return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
     }
+    if (p.scheme == PF_RK2) {
+        // phi' = phi + dt k2,  k2 = f(y2, t + dt/2),  y2 = phi + dt/2 k1:
+        //   kap2 = dt lam';  ybar2 = (df/dy at y2)^T kap2;  kap1 = dt/2 ybar2;
+        //   lam_n = lam' + ybar2 + (df/dy at phi)^T kap1
+        T* y2 = (T*)s->ya;
+        const double s1 = time_factor(p, t), s2 = time_factor(p, t + 0.5 * dt);
+        e = run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt,
+                                                   0.0, U, V, W), st);
+        if (e == hipSuccess)
+            e = adj(make_adj<T>(p, s2, y2, lam, dt, lam, L, lam, Ka, 0.0, 0.5 * dt, gU, gV, gW, U,
+                                V, W), st);
+        if (e == hipSuccess)
+            e = adj(make_adj<T>(p, s1, phi, Ka, 1.0, L, lam, nullptr, nullptr, 0.0, 0.0, gU, gV,
+                                gW, U, V, W), st);
+        return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
+    }
     T* y2 = (T*)s->ya;
     T* y3 = (T*)s->yb;
     T* y4 = (T*)s->acc;

@@ -15,6 +15,9 @@
 // phi' over acc (read only at the cell itself) and the host alternates the roles of the two
 // buffers from step to step.
 //
+// The explicit midpoint rule (RK2) is sweep A alone: with c_mid = dt/2 and c_y2 = dt its out_y
+// is the new phi (into the other buffer of the pair), and a null out_acc skips the accumulator.
+//
 // Regions, for a TX x TY tile at (i0, j0), as (x range) x (y range):
 //   IN   stage input, ring of 3 planes       [i0-4, i0+TX+4) x [j0-4, j0+TY+4)
 //   MID  E1 cells / ya ring of 3 planes      [i0-2, i0+TX+2) x [j0-2, j0+TY+2)
@@ -465,7 +468,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                                       ge);
                 const unsigned c = e_col[0];  // own cell (i0+tx, j0+ty): no wrap when active
                 if (!SWEEP_B) foy.store(t, c, fma(a.c_y2, f2, qa_phi[0]));
-                foacc.store(t, c, fma(a.c_acc2, f2, qa_acc[0]));
+                if (SWEEP_B || a.out_acc) foacc.store(t, c, fma(a.c_acc2, f2, qa_acc[0]));
             }
             sz2 = szp;
             dz2 = dzp;

@@ -62,6 +62,7 @@ struct AdjArgs {
 // Two RK4 stages in one sweep (pf_fused_body.h): E1 evaluates f on the stage input y over the
 // tile plus a two-cell halo and keeps y_mid = base + c_mid f1 in LDS; E2 evaluates f on y_mid.
 //   sweep A: y = phi;  writes out_y = phi + c_y2 f2 and out_acc = (phi + c_acc1 f1) + c_acc2 f2
+//            (out_acc may be null: RK2 is sweep A alone, its out_y the new phi)
 //   sweep B: y = yb, base of y_mid = phi;  writes out_acc = (acc_in + c_acc1 f1) + c_acc2 f2
 template <typename T>
 struct FusedArgs {
@@ -69,7 +70,7 @@ struct FusedArgs {
     const T* phi;     // phi: base of y_mid and (sweep A) of the outputs
     const T* acc_in;  // sweep B: accumulator after stage 2 (read at the cell only)
     T* out_y;         // sweep A: yb
-    T* out_acc;       // sweep A: accumulator;  sweep B: phi' (may alias acc_in)
+    T* out_acc;       // sweep A: accumulator (nullable);  sweep B: phi' (may alias acc_in)
     const T* U;
     const T* V;
     const T* W;

@@ -39,12 +39,14 @@ def adj_case(seed, shape):
 
 
 @pytest.mark.parametrize("scheme,shape", [("rk4", (12, 10, 14)), ("rk4", (1, 20, 18)),
-                                          ("euler", (9, 11, 7)), ("rk4", (20, 16, 70))])
+                                          ("euler", (9, 11, 7)), ("rk4", (20, 16, 70)),
+                                          ("rk2", (12, 10, 14)), ("rk2", (1, 20, 18))])
 def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
     pf = lib
     rng, phi, U, V, W, lam, dx = adj_case(1, shape)
     kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, vel_mode=1, vel_T=0.8)
-    ref = oracle.adjoint_step(phi, U, V, W, lam, t=0.1, scheme={"rk4": 4, "euler": 1}[scheme], **kw)
+    ref = oracle.adjoint_step(phi, U, V, W, lam, t=0.1,
+                              scheme={"rk4": 4, "rk2": 2, "euler": 1}[scheme], **kw)
     nz, ny, nx = shape
     s = pf.Solver((nx, ny, nz), scheme=scheme, **kw)
     g = [dev(a) for a in (phi, U, V, W)]
@@ -63,9 +65,9 @@ def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
     s.close()
 
 
-@pytest.mark.parametrize("dtype,shape", [("f64", (20, 16, 70)), ("f32", (33, 9, 65)),
-                                         ("f64", (1, 12, 5))])
-def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape):
+@pytest.mark.parametrize("dtype,shape,scheme", [("f64", (20, 16, 70), "rk4"), ("f32", (33, 9, 65), "rk4"),
+                                                ("f64", (1, 12, 5), "rk4"), ("f64", (20, 16, 70), "rk2")])
+def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape, scheme):
     """The tiled adjoint stage kernel and the one-thread-per-cell kernel (paired with the
     'global' forward variant) give bit-identical lam and velocity gradients, for every adjoint
     tile shape and chunk length (lent by the per-stage forward variant of that shape; none in
@@ -76,7 +78,7 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
     names = [pf.phasefield_variant_name(kd, v) for v in range(pf.phasefield_variant_count(kd))]
-    kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, dtype=dtype)
+    kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, dtype=dtype, scheme=scheme)
     nz, ny, nx = shape
     picks = ["global", "tiled_64x8x64", "tiled_64x8x16", "tiled_64x4x16", "tiled_32x4x16",
              "tiled_64x8x16_big", "fused_32x16x32", "tiled_64x4", "tiled_32x4", "fused_64x8"]

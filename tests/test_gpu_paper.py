@@ -1,4 +1,7 @@
-"""The paper's 2D uniform-translation experiment (Sec. 3.2.1, Tables 1-2) on the HIP stepper.
+"""The paper's 2D uniform-translation experiment (Sec. 3.2.1, Tables 1-2), its 1D refinement
+study (Sec. 3.1) and the RK2 boundedness map (Sec. 2.3, Fig. 6(a)) on the HIP stepper.
+
+2D translation:
 
 A D = 1 drop in a 2 x 2 periodic box (dx = D/25) is carried by (u, v) = (sqrt2/2, sqrt2/2) for
 T = 2 sqrt2 with classic RK4 at dt = min(Eq. 31, Eq. 32), for the seven (eps/dx, gamma/|u|)
@@ -80,9 +83,9 @@ def test_table2_classification_and_table1_errors_on_the_gpu(lib):
               f"(paper {p['E_eps']}), E_tot {e_tot:.5f} (paper {p['E_tot']})", flush=True)
 
 
-def _gpu_run_1d(pf, phi0, U, dx, eps, gamma, dt, ns):
+def _gpu_run_1d(pf, phi0, U, dx, eps, gamma, dt, ns, scheme="rk4"):
     n = phi0.shape[2]
-    s = pf.Solver((n, 1, 1), dx, eps, gamma, dt, dtype="f64")
+    s = pf.Solver((n, 1, 1), dx, eps, gamma, dt, dtype="f64", scheme=scheme)
     z = np.zeros_like(U)
     g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi0, U, z, z)]
     s.step(*g, nsteps=ns)
@@ -135,3 +138,49 @@ def test_1d_drop_refinement_on_the_gpu(lib):
             assert all(0.8 <= o <= 1.2 for o in orders), (eps_dx, n, orders)
     for n in (100, 200, 400, 800):
         assert errs[(1.0, n)][2] < errs[(2.0, n)][2], n
+
+
+@pytest.mark.parametrize("eps_over_dx,gamma_over_u,bounded", [
+    (1.0, 1.0, True), (0.75, 2.0, True), (1.5, 1.0, True), (2.0, 0.5, True),
+    (0.55, 1.0, False), (0.8, 0.5, False)])
+def test_rk2_boundedness_map_on_the_gpu(lib, eps_over_dx, gamma_over_u, bounded):
+    """Sec. 2.3, Fig. 6(a): the explicit midpoint rule at its diffusive limit (Eq. 26) keeps the
+    1D drop (diameter 1, u = 1, one period of [0, 2), n = 50) inside [0, 1] at every step for
+    points on or above the crossover line (Eq. 9), and leaves it below the line. The extremes
+    come from the library's reduction after every step; the final field matches the oracle."""
+    pf = lib
+    n, L, u = 50, 2.0, 1.0
+    dx = L / n
+    eps, gamma = eps_over_dx * dx, gamma_over_u * u
+    assert (eps_over_dx >= params.crossover_eps_over_dx(gamma_over_u) - 1e-12) == bounded
+    x = (np.arange(n) + 0.5) * dx
+    phi0 = fx.tanh_profile(0.5 - np.abs(x - L / 2), eps).reshape(1, 1, n)
+    U = np.full_like(phi0, u)
+    Z = np.zeros_like(phi0)
+    ns = math.ceil(L / u / params.dt_max("rk2", 1, dx, gamma, eps))
+    dt = L / u / ns
+    s = pf.Solver((n, 1, 1), dx, eps, gamma, dt, dtype="f64", scheme="rk2", use_graph=False)
+    g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi0, U, Z, Z)]
+    st = torch.cuda.Stream()
+    lo, hi = 1.0, 0.0
+    with torch.cuda.stream(st):
+        for k in range(ns):
+            s.step(*g, t0=k * dt, nsteps=1, stream=st)
+            _, mn, mx, bad = s.reduce(g[0], stream=st)
+            assert bad == 0
+            lo, hi = min(lo, mn), max(hi, mx)
+    got = g[0].cpu().numpy()
+    s.close()
+    kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns, scheme=2)
+    ref = oracle.step(phi0, U, Z, Z, **kw)
+    wobble = np.random.default_rng(ns).standard_normal(phi0.shape)
+    ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, Z, Z, **kw)
+    tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
+    diff = np.abs(got - ref).max()
+    print(f"eps/dx {eps_over_dx} gamma/u {gamma_over_u}: {ns} steps, min {lo:.3e}, "
+          f"max-1 {hi - 1:.3e}, |gpu - oracle| {diff:.2e} (tolerance {tol:.2e})", flush=True)
+    assert diff <= tol
+    if bounded:
+        assert lo >= -EPS64 and hi <= 1 + EPS64, (lo, hi)
+    else:
+        assert lo < -1e-3 and hi > 1 + 1e-3, (lo, hi)
