@@ -184,3 +184,61 @@ def test_rk2_boundedness_map_on_the_gpu(lib, eps_over_dx, gamma_over_u, bounded)
         assert lo >= -EPS64 and hi <= 1 + EPS64, (lo, hi)
     else:
         assert lo < -1e-3 and hi > 1 + 1e-3, (lo, hi)
+
+
+@pytest.mark.parametrize("scheme,sch,limit", [("euler", 1, "euler"), ("rk2", 2, "rk2"),
+                                              ("rk4", 4, "rk4")])
+def test_boundedness_map_on_the_gpu(lib, scheme, sch, limit):
+    """Secs. 2.2-2.3, Figs. 5(a) and 6: the 1D drop (diameter 1, u = 1, one period of [0, 2),
+    n = 50) over a grid of (eps/dx, gamma/u) points, each scheme at its diffusive limit
+    (Eqs. 25, 26, 28). Every point on or above the crossover line (Eq. 9) keeps phi inside
+    [0, 1] at every step (proven for Euler, observed by the paper for the Runge-Kutta schemes),
+    and its final field matches the oracle (tolerance measured on the oracle, as above). The
+    criterion is sufficient, not necessary, so below the line only the existence of unbounded
+    points is checked."""
+    pf = lib
+    n, L, u = 50, 2.0, 1.0
+    dx = L / n
+    x = (np.arange(n) + 0.5) * dx
+    st = torch.cuda.Stream()
+    above = below_unbounded = below = 0
+    for eod in (0.3, 0.5, 0.7, 0.9, 1.2, 1.6, 2.0):
+        for gou in (0.25, 0.5, 1.0, 2.0, 4.0):
+            eps, gamma = eod * dx, gou * u
+            on_or_above = eod >= params.crossover_eps_over_dx(gou) - 1e-12
+            phi0 = fx.tanh_profile(0.5 - np.abs(x - L / 2), eps).reshape(1, 1, n)
+            U = np.full_like(phi0, u)
+            Z = np.zeros_like(phi0)
+            ns = math.ceil(L / u / params.dt_max(limit, 1, dx, gamma, eps))
+            dt = L / u / ns
+            s = pf.Solver((n, 1, 1), dx, eps, gamma, dt, dtype="f64", scheme=scheme,
+                          use_graph=False)
+            g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi0, U, Z, Z)]
+            lo, hi, bad = 1.0, 0.0, 0
+            with torch.cuda.stream(st):
+                for k in range(ns):
+                    s.step(*g, t0=k * dt, nsteps=1, stream=st)
+                    try:
+                        _, mn, mx, nb = s.reduce(g[0], stream=st)
+                    except pf.PhaseFieldError:  # a run below the line may overflow
+                        bad = 1
+                        break
+                    lo, hi = min(lo, mn), max(hi, mx)
+            got = g[0].cpu().numpy()
+            s.close()
+            bounded = not bad and lo >= -EPS64 and hi <= 1 + EPS64
+            if on_or_above:
+                above += 1
+                assert bounded, (scheme, eod, gou, lo, hi)
+                kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns, scheme=sch)
+                ref = oracle.step(phi0, U, Z, Z, **kw)
+                wobble = np.random.default_rng(ns).standard_normal(phi0.shape)
+                ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, Z, Z, **kw)
+                tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
+                assert np.abs(got - ref).max() <= tol, (scheme, eod, gou)
+            else:
+                below += 1
+                below_unbounded += not bounded
+    print(f"{scheme}: {above} points on or above the line, all bounded; "
+          f"{below_unbounded} of {below} below it unbounded", flush=True)
+    assert above >= 10 and below_unbounded >= 5
