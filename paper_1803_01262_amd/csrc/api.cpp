@@ -392,6 +392,8 @@ FusedArgs<T> pf::make_fused(const pf_params& p, bool sweep_b, double t, const T*
     a.delta2 = (T)(p.delta * p.delta);
     a.phi = phi_cur;
     a.out_acc = phi_next;
+    a.out_mid = nullptr;
+    a.out_phi = nullptr;
     if (p.scheme == PF_RK2) {
         a.y = phi_cur;
         a.acc_in = nullptr;
@@ -433,29 +435,41 @@ template FusedArgs<double> pf::make_fused<double>(const pf_params&, bool, double
                                                   double*, const double*, const double*,
                                                   const double*, double*);
 
-// One RK4 step as two fused sweeps (RK2: sweep A alone); the new phi lands in phi_next.
 template <typename T>
-static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* phi_cur,
-                                     T* phi_next, const T* U, const T* V, const T* W, T* yb,
-                                     double t, hipStream_t st)
+hipError_t pf::run_fused_sweep(int variant, const FusedArgs<T>& a, bool sweep_b, hipStream_t st)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
     const StageVariant& sv = stage_variant(dtype, variant);
-    const int sweeps = p.scheme == PF_RK2 ? 1 : 2;
-    for (int sweep = 0; sweep < sweeps; ++sweep) {
-        const FusedArgs<T> a = make_fused<T>(p, sweep == 1, t, phi_cur, phi_next, U, V, W, yb);
-        hipError_t e;
-        if constexpr (sizeof(T) == 4)
-            e = sv.fused_f32(a, sweep == 1, st);
-        else
-            e = sv.fused_f64(a, sweep == 1, st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if constexpr (sizeof(T) == 4)
+        return sv.fused_f32 ? sv.fused_f32(a, sweep_b, st) : hipErrorInvalidValue;
+    else
+        return sv.fused_f64 ? sv.fused_f64(a, sweep_b, st) : hipErrorInvalidValue;
+}
+template hipError_t pf::run_fused_sweep<float>(int, const FusedArgs<float>&, bool, hipStream_t);
+template hipError_t pf::run_fused_sweep<double>(int, const FusedArgs<double>&, bool, hipStream_t);
+
+// One RK4 step as two fused sweeps (RK2: sweep A alone); the new phi lands in phi_next. Sweep A
+// writes the accumulator into acc_buf (for the plain form, phi_next itself). With phi_copy (RK4
+// only), sweep A also copies phi_cur there and sweep B takes its phi from that copy, so nothing
+// reads phi_cur during sweep B and phi_next may be phi_cur: the step runs in place.
+template <typename T>
+static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* phi_cur,
+                                     T* phi_next, T* acc_buf, T* phi_copy, const T* U,
+                                     const T* V, const T* W, T* yb, double t, hipStream_t st)
+{
+    FusedArgs<T> a = make_fused<T>(p, false, t, phi_cur, p.scheme == PF_RK2 ? phi_next : acc_buf,
+                                   U, V, W, yb);
+    if (phi_copy) a.out_phi = phi_copy;
+    hipError_t e = run_fused_sweep<T>(variant, a, false, st);
+    if (e != hipSuccess || p.scheme == PF_RK2) return e;
+    FusedArgs<T> b = make_fused<T>(p, true, t, phi_copy ? phi_copy : phi_cur, acc_buf, U, V, W, yb);
+    b.out_acc = phi_next;
+    return run_fused_sweep<T>(variant, b, true, st);
 }
 
 // nsteps steps from t0 (step m at t0 + m dt), phi updated in place. A fused variant alternates
-// phi between the caller's buffer and acc and copies back after an odd count.
+// phi between the caller's buffer and acc; after an odd count RK4 runs its last step in place
+// (through a copy of phi in ya), RK2 copies back.
 template <typename T>
 hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U, const T* V,
                              const T* W, T* ya, T* yb, T* acc, double t0, int nsteps,
@@ -468,9 +482,13 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
         const double t = t0 + (double)m * p.dt;
         hipError_t e;
         if (fused) {
-            T* next = cur == phi ? acc : phi;
-            e = enqueue_step_fused<T>(p, variant, cur, next, U, V, W, yb, t, st);
-            cur = next;
+            if (m == nsteps - 1 && cur == phi && p.scheme == PF_RK4) {
+                e = enqueue_step_fused<T>(p, variant, phi, phi, acc, ya, U, V, W, yb, t, st);
+            } else {
+                T* next = cur == phi ? acc : phi;
+                e = enqueue_step_fused<T>(p, variant, cur, next, next, nullptr, U, V, W, yb, t, st);
+                cur = next;
+            }
         } else {
             e = enqueue_step<T>(p, variant, phi, U, V, W, ya, yb, acc, t, st);
         }

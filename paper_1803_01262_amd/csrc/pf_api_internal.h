@@ -49,9 +49,14 @@ template <typename T>
 FusedArgs<T> make_fused(const pf_params& p, bool sweep_b, double t, const T* phi_cur, T* phi_next,
                         const T* U, const T* V, const T* W, T* yb);
 
-// One stage launch with the per-stage kernel of a variant (fused variants use variant 0).
+// One stage launch with the per-stage kernel of a variant (fused variants use the per-stage
+// default for the grid).
 template <typename T>
 hipError_t run_stage(int variant, const StageArgs<T>& a, hipStream_t st);
+
+// One sweep of a fused variant.
+template <typename T>
+hipError_t run_fused_sweep(int variant, const FusedArgs<T>& a, bool sweep_b, hipStream_t st);
 
 }  // namespace pf
 

@@ -17,6 +17,10 @@
 //
 // The explicit midpoint rule (RK2) is sweep A alone: with c_mid = dt/2 and c_y2 = dt its out_y
 // is the new phi (into the other buffer of the pair), and a null out_acc skips the accumulator.
+// Two more optional outputs of sweep A (XOUT, a separate instantiation so that the descriptors
+// cost the plain sweeps no registers): out_mid receives y_mid on the tile (so the adjoint can
+// recompute two stage inputs in one sweep), and out_phi a copy of phi (then sweep B may read that
+// copy and write the new phi into phi's own buffer, which ends an odd step count in place).
 //
 // Regions, for a TX x TY tile at (i0, j0), as (x range) x (y range):
 //   IN   stage input, ring of 3 planes       [i0-4, i0+TX+4) x [j0-4, j0+TY+4)
@@ -50,9 +54,10 @@
 namespace pf {
 
 // The workgroup owns the TX x TY column tile (ti, tj) and the output planes [k0, k1).
-template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE>
+template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT = false>
 __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int k0, int k1)
 {
+    static_assert(!(XOUT && SWEEP_B), "the optional outputs belong to sweep A");
     constexpr int NT = TX * TY;
     constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte piece
     static_assert(TX % VEC == 0, "the tile width must be a whole number of 16-byte pieces");
@@ -223,7 +228,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     piece_t pre_in[NLI];
     piece_t pre_b[NLB > 0 ? NLB : 1];
     const FieldRef<T, BIG> fy(a.y, plane, nz), fphi(a.phi, plane, nz), facc(a.acc_in, plane, nz),
-        foy(a.out_y, plane, nz), foacc(a.out_acc, plane, nz), fU(a.U, plane, nz),
+        foy(a.out_y, plane, nz), foacc(a.out_acc, plane, nz), fomid(a.out_mid, plane, nz),
+        fophi(a.out_phi, plane, nz), fU(a.U, plane, nz),
         fV(a.V, plane, nz), fW(a.W, plane, nz);
     auto load_piece = [&](const FieldRef<T, BIG>& f, int kw, unsigned off) -> piece_t {
         if constexpr (WIDE)
@@ -399,8 +405,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                                   dzp, qx[0], qx[2], qy[0], qy[2 * MW], e_qzm[s], qzn[s], eu0[s],
                                   eu1[s], ev0[s], ev1[s], e_w0[s], ew1[s], a.nhs1, ge);
             const T base = SWEEP_B ? s_pb[(WIDE ? lx + 2 : lx) + ly * PBW] : pc;
-            YM[lx + ly * MW] = fma(a.c_mid, f1, base);
+            const T ym = fma(a.c_mid, f1, base);
+            YM[lx + ly * MW] = ym;
             if (s == 0) {
+                if constexpr (XOUT) {
+                    const int p = t + 2;
+                    if (a.out_mid && p >= k0 && p < k1 && active) fomid.store(p, e_col[0], ym);
+                }
                 // own cell: hand plane p's values to E2 (used two iterations later)
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
@@ -468,6 +479,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                                       ge);
                 const unsigned c = e_col[0];  // own cell (i0+tx, j0+ty): no wrap when active
                 if (!SWEEP_B) foy.store(t, c, fma(a.c_y2, f2, qa_phi[0]));
+                if constexpr (XOUT)
+                    if (a.out_phi) fophi.store(t, c, qa_phi[0]);
                 if (SWEEP_B || a.out_acc) foacc.store(t, c, fma(a.c_acc2, f2, qa_acc[0]));
             }
             sz2 = szp;

@@ -10,7 +10,8 @@ namespace pf {
 // One workgroup per (tile, z-chunk of kz planes); the chunk length is a launch argument.
 // FP32: at least four waves per SIMD (at most 128 VGPRs), two workgroups of eight waves per CU.
 // FP64 needs more registers than that and runs at two waves per SIMD.
-template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE>
+// XOUT: sweep A with its optional outputs (out_mid, out_phi).
+template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y, int kz)
 {
@@ -19,7 +20,7 @@ fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y, int kz)
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int k0 = (b / tiles_y) * kz;
-    fused_body<T, TX, TY, SWEEP_B, BIG, WIDE>(a, ti, tj, k0, min(k0 + kz, a.nz));
+    fused_body<T, TX, TY, SWEEP_B, BIG, WIDE, XOUT>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
 template <typename T, int TX, int TY, bool BIG, bool WIDE>
@@ -27,11 +28,14 @@ hipError_t launch_fused_sweep(const FusedArgs<T>& a, bool sweep_b, unsigned bloc
                               int tiles_y, int kz, hipStream_t st)
 {
     if (sweep_b)
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, true, BIG, WIDE>), dim3(blocks), dim3(TX * TY),
-                           0, st, a, tiles_x, tiles_y, kz);
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, true, BIG, WIDE, false>), dim3(blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
+    else if (a.out_mid || a.out_phi)
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE, true>), dim3(blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     else
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE>), dim3(blocks), dim3(TX * TY),
-                           0, st, a, tiles_x, tiles_y, kz);
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE, false>), dim3(blocks),
+                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     return hipGetLastError();
 }
 
@@ -50,10 +54,10 @@ hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st)
     int kz = KZ;
     if (KZ == 0) {
         // sweeps A and B share the register budget, hence the residency, of their form
-        const void* k = big ? (wide ? (const void*)fused_kernel<T, TX, TY, false, true, true>
-                                    : (const void*)fused_kernel<T, TX, TY, false, true, false>)
-                            : (wide ? (const void*)fused_kernel<T, TX, TY, false, false, true>
-                                    : (const void*)fused_kernel<T, TX, TY, false, false, false>);
+        const void* k = big ? (wide ? (const void*)fused_kernel<T, TX, TY, false, true, true, false>
+                                    : (const void*)fused_kernel<T, TX, TY, false, true, false, false>)
+                            : (wide ? (const void*)fused_kernel<T, TX, TY, false, false, true, false>
+                                    : (const void*)fused_kernel<T, TX, TY, false, false, false, false>);
         kz = launch_chunk_planes(k, TX * TY, (long long)tiles_x * tiles_y, a.nz, 5);
         if (kz <= 0) return hipErrorInvalidDevice;
     }

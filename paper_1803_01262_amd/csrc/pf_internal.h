@@ -71,6 +71,8 @@ struct FusedArgs {
     const T* acc_in;  // sweep B: accumulator after stage 2 (read at the cell only)
     T* out_y;         // sweep A: yb
     T* out_acc;       // sweep A: accumulator (nullable);  sweep B: phi' (may alias acc_in)
+    T* out_mid;       // sweep A, nullable: y_mid = phi + c_mid f1 at the tile (the adjoint's y2)
+    T* out_phi;       // sweep A, nullable: a copy of phi (so that sweep B can write phi in place)
     const T* U;
     const T* V;
     const T* W;
