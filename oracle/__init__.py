@@ -40,7 +40,8 @@ def build(force: bool = False) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
                 ("dx", ctypes.c_double), ("eps", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("delta", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("delta", ctypes.c_double),
+                ("wall", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -76,16 +77,17 @@ def _ptr(a: np.ndarray | None):
     return None if a is None else a.ctypes.data
 
 
-def _grid(shape, dx, eps=0.0, gamma=0.0, delta=0.0) -> _Grid:
+def _grid(shape, dx, eps=0.0, gamma=0.0, delta=0.0, walls=(False, False, False)) -> _Grid:
     nz, ny, nx = shape
-    return _Grid(nx, ny, nz, dx, eps, gamma, delta)
+    return _Grid(nx, ny, nz, dx, eps, gamma, delta, (ctypes.c_int32 * 3)(*(int(bool(w)) for w in walls)))
 
 
-def rhs(phi, U, V, W, *, dx, eps, gamma, delta=0.0, s=1.0) -> np.ndarray:
-    """f = d(phi)/dt of the semi-discrete Eq. 1 (Sec. 2.2 recipe, steps 1-5)."""
+def rhs(phi, U, V, W, *, dx, eps, gamma, delta=0.0, s=1.0, walls=(False, False, False)) -> np.ndarray:
+    """f = d(phi)/dt of the semi-discrete Eq. 1 (Sec. 2.2 recipe, steps 1-5). walls: per axis
+    (x, y, z), solid walls at both ends instead of periodicity (see pf_oracle.c)."""
     phi, U, V, W = map(_f64, (phi, U, V, W))
     f = np.empty_like(phi)
-    g = _grid(phi.shape, dx, eps, gamma, delta)
+    g = _grid(phi.shape, dx, eps, gamma, delta, walls)
     _l().orc_rhs(ctypes.byref(g), s, _ptr(phi), _ptr(U), _ptr(V), _ptr(W), _ptr(f))
     return f
 
@@ -96,17 +98,18 @@ def _check_scheme(scheme):
 
 
 def step(phi, U, V, W, *, dx, eps, gamma, dt, nsteps=1, delta=0.0, t0=0.0, scheme=4,
-         fp32=False, vel_mode=0, vel_T=1.0) -> np.ndarray:
+         fp32=False, vel_mode=0, vel_T=1.0, walls=(False, False, False)) -> np.ndarray:
     """nsteps explicit steps (scheme 1: Euler, Eq. 25; scheme 2: explicit midpoint RK2, Eq. 26;
     scheme 4: classic RK4, Eq. 28).
 
     vel_mode 0: steady velocity; 1: u(x, t) = u0(x) cos(pi t / vel_T). fp32=True rounds every
     stage input and each new phi to float32 (storage precision) while computing in FP64.
+    walls: per axis (x, y, z), solid walls at both ends instead of periodicity.
     """
     _check_scheme(scheme)
     out = _f64(phi).copy()
     U, V, W = map(_f64, (U, V, W))
-    g = _grid(out.shape, dx, eps, gamma, delta)
+    g = _grid(out.shape, dx, eps, gamma, delta, walls)
     _l().orc_step(ctypes.byref(g), int(scheme), int(bool(fp32)), dt, t0, int(vel_mode),
                   float(vel_T), int(nsteps), _ptr(out), _ptr(U), _ptr(V), _ptr(W))
     return out

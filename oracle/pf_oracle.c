@@ -28,6 +28,12 @@
  *    classic RK4 evaluates s at t, t+dt/2, t+dt/2, t+dt; the explicit midpoint RK2 at t, t+dt/2.
  *  - FP32-storage mode: every RK stage input and the new phi are rounded to float32 at the
  *    points where a value must be materialised; arithmetic stays FP64.
+ *  - Walls (the paper names slip walls for its 2D random-field test but gives no discrete
+ *    form): an axis flagged as walled has solid walls at x_a = 0 and x_a = n dx. The total flux
+ *    through a wall face is zero (no normal velocity, no diffusive or sharpening flux), and the
+ *    central gradient of a cell next to a wall takes the wall-side value from a mirror ghost
+ *    (ghost of cell 0 = cell 0, of cell n-1 = cell n-1). The velocity stored on a wall face is
+ *    ignored. Forward step only (the adjoint is for periodic grids).
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -38,6 +44,7 @@
 typedef struct {
     int64_t nx, ny, nz;
     double dx, eps, gamma, delta;
+    int32_t wall[3]; /* per axis (x, y, z): 0 periodic, 1 walls at both ends */
 } orc_grid;
 
 static inline int64_t wrap(int64_t i, int64_t n)
@@ -62,6 +69,22 @@ static inline int64_t nb(const orc_grid *g, int64_t i, int64_t j, int64_t k, int
 
 static inline double round_storage(double v, int fp32) { return fp32 ? (double)(float)v : v; }
 
+/* offset of neighbour c + d*e_a (|d| = 1) for the central gradient: across a wall, the mirror
+ * ghost, i.e. the cell itself */
+static inline int64_t nb_grad(const orc_grid *g, int64_t i, int64_t j, int64_t k, int a, int d)
+{
+    const int64_t n = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+    const int64_t idx = (a == 0 ? i : (a == 1 ? j : k)) + d;
+    if (g->wall[a] && (idx < 0 || idx >= n)) return at(g, i, j, k);
+    return nb(g, i, j, k, a, d);
+}
+
+/* whether the low a-face of cell (i,j,k) is a wall face */
+static inline int low_face_is_wall(const orc_grid *g, int64_t i, int64_t j, int64_t k, int a)
+{
+    return g->wall[a] && (a == 0 ? i : (a == 1 ? j : k)) == 0;
+}
+
 /* Steps 1-3 of the recipe: central gradient, unit normal and sharpening product at centres.
  * Fills gr[3N] (gradient), nrm[3N] (normal), q[3N] = phi(1-phi) n. */
 static void centre_fields(const orc_grid *g, const double *phi, double *gr, double *nrm,
@@ -76,7 +99,8 @@ static void centre_fields(const orc_grid *g, const double *phi, double *gr, doub
                 const int64_t c = at(g, i, j, k);
                 double gv[3], mag2 = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    gv[a] = (phi[nb(g, i, j, k, a, +1)] - phi[nb(g, i, j, k, a, -1)]) / (2.0 * g->dx);
+                    gv[a] = (phi[nb_grad(g, i, j, k, a, +1)] - phi[nb_grad(g, i, j, k, a, -1)]) /
+                            (2.0 * g->dx);
                     mag2 += gv[a] * gv[a];
                 }
                 const double mag = sqrt(mag2 + g->delta * g->delta);
@@ -110,6 +134,10 @@ void orc_rhs(const orc_grid *g, double s, const double *phi, const double *U, co
             for (int64_t i = 0; i < g->nx; ++i) {
                 const int64_t c = at(g, i, j, k);
                 for (int a = 0; a < 3; ++a) {
+                    if (low_face_is_wall(g, i, j, k, a)) {
+                        F[3 * c + a] = 0.0; /* no flux through a wall */
+                        continue;
+                    }
                     const int64_t m = nb(g, i, j, k, a, -1);
                     const double adv = -s * vel[a][c] * 0.5 * (phi[m] + phi[c]);
                     const double dif = g->gamma * g->eps * (phi[c] - phi[m]) / g->dx;
@@ -118,7 +146,8 @@ void orc_rhs(const orc_grid *g, double s, const double *phi, const double *U, co
                 }
             }
 
-    /* step 5: divergence of the face fluxes */
+    /* step 5: divergence of the face fluxes (with walls, the high face of the last cell is the
+     * wall face stored at index 0, whose flux is zero) */
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < g->nz; ++k)
         for (int64_t j = 0; j < g->ny; ++j)
