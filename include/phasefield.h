@@ -47,14 +47,15 @@ extern "C" {
 typedef enum {
     PF_OK = 0,
     PF_ERR_INVALID = 1,     /* bad argument: size, spacing, parameter, null/misaligned pointer */
-    PF_ERR_UNSUPPORTED = 2, /* valid request this build does not provide (e.g. a wall BC)     */
+    PF_ERR_UNSUPPORTED = 2, /* valid request this build does not provide (e.g. walls in an    */
+                            /* adjoint or batched run)                                        */
     PF_ERR_DEVICE = 3,      /* a HIP call failed                                              */
     PF_ERR_OOM = 4,         /* device allocation failed                                       */
     PF_ERR_NONFINITE = 5    /* phasefield_reduce found NaN or Inf                             */
 } pf_status;
 
 typedef enum { PF_F32 = 0, PF_F64 = 1 } pf_dtype;             /* storage precision      */
-typedef enum { PF_BC_PERIODIC = 0, PF_BC_WALL = 1 } pf_bc;      /* WALL: unsupported      */
+typedef enum { PF_BC_PERIODIC = 0, PF_BC_WALL = 1 } pf_bc;      /* per axis               */
 typedef enum { PF_EULER = 1, PF_RK2 = 2, PF_RK4 = 4 } pf_scheme;
 typedef enum { PF_VEL_STEADY = 0, PF_VEL_COS_REVERSAL = 1 } pf_velmode;
 
@@ -68,7 +69,11 @@ typedef struct {
     double dt;          /* time step (> 0)                                                     */
     double delta;       /* |grad phi| regulariser: n = g / sqrt(|g|^2 + delta^2); 0 gives the  */
                         /* plain unit normal with n = 0 where g = 0                            */
-    int32_t bc[3];      /* pf_bc per axis; only PF_BC_PERIODIC is provided                     */
+    int32_t bc[3];      /* pf_bc per axis. PF_BC_WALL: solid walls at x_a = 0 and n dx, with   */
+                        /* zero total flux through the wall faces and mirror ghosts for the   */
+                        /* central gradient; the face velocity stored at index 0 of a walled  */
+                        /* axis (the wall face) is ignored. Walls run on the per-stage        */
+                        /* kernels (a fused variant falls back to them); forward step only.   */
     int32_t dtype;      /* pf_dtype                                                            */
     int32_t scheme;     /* pf_scheme                                                           */
     int32_t vel_mode;   /* pf_velmode: velocity u0(x) * s(t), s = 1 or cos(pi t / vel_T)       */
@@ -104,8 +109,7 @@ typedef struct pf_solver pf_solver;
 /* Validate p and allocate the handle with its device scratch (three field-sized stage
  * buffers). Errors: PF_ERR_INVALID (n < 1, dx <= 0, eps < 0, gamma < 0, dt <= 0, delta < 0,
  * bad enum, vel_T <= 0 in cos mode, variant out of range, n[1] or n[2] > 65535, an xy plane of
- * 2^28 cells or more), PF_ERR_UNSUPPORTED (wall BC), PF_ERR_OOM, PF_ERR_DEVICE. *out is NULL on
- * failure. */
+ * 2^28 cells or more), PF_ERR_OOM, PF_ERR_DEVICE. *out is NULL on failure. */
 pf_status phasefield_create(const pf_params *p, pf_solver **out);
 
 /* Release the handle and all its device memory (NULL is accepted). Synchronises the device
@@ -127,7 +131,8 @@ pf_status phasefield_step(pf_solver *s, void *phi, const void *u, const void *v,
  * lam = dL/dphi_n (in place). gu, gv, gw (may each be NULL to skip) ACCUMULATE
  * dL/du0 etc. (+=). The stage inputs of the forward step are recomputed from phi_n.
  * Allocates three more field-sized scratch buffers on first use.
- * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_UNSUPPORTED (a handle with
+ * walls), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);
@@ -198,8 +203,8 @@ typedef struct pf_batch pf_batch;
 
 /* per_instance: HOST array of count parameter sets (all with the same dtype).
  * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtypes), PF_ERR_UNSUPPORTED (a set
- * with a scheme other than RK4, a time-varying velocity, or a field of 4 GiB or more: such
- * grids take a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * with a scheme other than RK4, a time-varying velocity, walls, or a field of 4 GiB or more:
+ * such grids take a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_batch_create(const pf_params *per_instance, int32_t count, pf_batch **out);
 
 /* Advance every instance b by nsteps steps: phi[b], u[b], v[b], w[b] are HOST arrays of count

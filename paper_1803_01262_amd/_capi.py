@@ -122,8 +122,8 @@ def _ptr(t, dtype: int | None = None, numel: int | None = None, name: str = "ten
 
 
 def make_params(n, dx, eps, gamma, dt, *, dtype="f64", scheme="rk4", delta=0.0, vel_mode=0,
-                vel_T=1.0, variant=-1, use_graph=True) -> Params:
-    """pf_params from keyword arguments; n = (nx, ny, nz)."""
+                vel_T=1.0, variant=-1, use_graph=True, walls=(False, False, False)) -> Params:
+    """pf_params from keyword arguments; n = (nx, ny, nz); walls: per axis (x, y, z)."""
     p = Params()
     lib.phasefield_default_params(ctypes.byref(p))
     p.n[0], p.n[1], p.n[2] = (int(v) for v in n)
@@ -135,6 +135,8 @@ def make_params(n, dx, eps, gamma, dt, *, dtype="f64", scheme="rk4", delta=0.0, 
     p.vel_T = float(vel_T)
     p.variant = int(variant)
     p.use_graph = int(bool(use_graph))
+    for a, w in enumerate(walls):
+        p.bc[a] = PF_BC_WALL if w else PF_BC_PERIODIC
     return p
 
 

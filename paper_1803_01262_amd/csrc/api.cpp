@@ -56,15 +56,20 @@ extern "C" void phasefield_default_params(pf_params* p)
     p->use_graph = 1;
 }
 
+int pf::wall_mask(const pf_params& p)
+{
+    return (p.bc[0] == PF_BC_WALL ? 1 : 0) | (p.bc[1] == PF_BC_WALL ? 2 : 0) |
+           (p.bc[2] == PF_BC_WALL ? 4 : 0);
+}
+
 pf_status pf::validate_params(const pf_params* p)
 {
     if (!p) return fail(PF_ERR_INVALID, "params is NULL");
     for (int a = 0; a < 3; ++a) {
         if (p->n[a] < 1 || p->n[a] > (1 << 20))
             return fail(PF_ERR_INVALID, "n[%d] = %d out of range [1, 2^20]", a, p->n[a]);
-        if (p->bc[a] == PF_BC_WALL)
-            return fail(PF_ERR_UNSUPPORTED, "wall boundary (axis %d) is not provided", a);
-        if (p->bc[a] != PF_BC_PERIODIC) return fail(PF_ERR_INVALID, "bc[%d] = %d", a, p->bc[a]);
+        if (p->bc[a] != PF_BC_PERIODIC && p->bc[a] != PF_BC_WALL)
+            return fail(PF_ERR_INVALID, "bc[%d] = %d", a, p->bc[a]);
     }
     const double cells = (double)p->n[0] * p->n[1] * p->n[2];
     if (cells > 4.0e9) return fail(PF_ERR_INVALID, "grid of %.3g cells is too large", cells);
@@ -295,6 +300,7 @@ StageArgs<T> pf::make_stage(const pf_params& p, double svel, const T* y, const T
     a.delta2 = (T)(p.delta * p.delta);
     a.c1 = (T)c1;
     a.c2 = (T)c2;
+    a.walls = wall_mask(p);
     return a;
 }
 template StageArgs<float> pf::make_stage<float>(const pf_params&, double, const float*,
@@ -476,7 +482,8 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
                              hipStream_t st)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
-    const bool fused = p.scheme != PF_EULER && variant_is_fused(dtype, variant);
+    // the fused sweeps have periodic axes only; with walls their variants run the per-stage kernel
+    const bool fused = p.scheme != PF_EULER && variant_is_fused(dtype, variant) && wall_mask(p) == 0;
     T* cur = phi;
     for (int m = 0; m < nsteps; ++m) {
         const double t = t0 + (double)m * p.dt;

@@ -130,6 +130,8 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
             return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver runs RK4 only", b);
         if (per_instance[b].vel_mode != PF_VEL_STEADY)
             return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver needs a steady velocity", b);
+        if (wall_mask(per_instance[b]) != 0)
+            return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver needs periodic axes", b);
         const pf_params& q = per_instance[b];
         if (field_needs_big(q.n[0], q.n[1], q.n[2], q.dtype == PF_F32 ? 4 : 8))
             return fail(PF_ERR_UNSUPPORTED,

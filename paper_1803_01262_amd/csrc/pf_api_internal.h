@@ -26,6 +26,7 @@ struct StepGraph {
 pf_status fail(pf_status st, const char* fmt, ...);
 pf_status hip_fail(hipError_t e, const char* what);
 pf_status validate_params(const pf_params* p);
+int wall_mask(const pf_params& p);  // bit a set: walls on axis a
 pf_status check_field_ptr(const void* ptr, const char* name);
 int tuned_variant(int dtype, const int32_t n[3]);
 void release_graph(StepGraph& g);

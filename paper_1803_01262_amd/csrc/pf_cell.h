@@ -250,4 +250,23 @@ __device__ __forceinline__ int wrapn(int i, int n)
     return i < 0 ? i + n : i;
 }
 
+// Mirror index across walls at 0 and n (any index, n >= 1): the ghost of cell -1 is cell 0, of
+// -2 cell 1, of n cell n-1; equivalently, the index on a periodic axis of 2n cells holding the
+// data and its mirror image.
+__device__ __forceinline__ int reflectn(int i, int n)
+{
+    const int m2 = 2 * n;
+    int m = i % m2;
+    m = m < 0 ? m + m2 : m;
+    return m < n ? m : m2 - 1 - m;
+}
+
+// The same for a z-march plane index, which lies at most 10 planes outside [0, n) (see wrapz):
+// for n >= 16 two compares suffice.
+__device__ __forceinline__ int reflectz(int k, int n)
+{
+    if (n >= 16) return k < 0 ? -k - 1 : (k >= n ? 2 * n - 1 - k : k);
+    return reflectn(k, n);
+}
+
 }  // namespace pf

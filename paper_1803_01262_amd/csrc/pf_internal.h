@@ -33,6 +33,10 @@ struct StageArgs {
     T nhs;      // -s(t) / (2 dx), advective flux (face mean of phi)
     T delta2;   // delta^2, |grad phi| regulariser
     T c1, c2;
+    // Walls (bit 0: x, 1: y, 2: z): on a walled axis the stage input is read through mirror
+    // indices (reflectn) and the face velocity stored at index 0 (the wall faces, low and, by
+    // periodic storage, high) counts as zero, which makes every flux through a wall face zero.
+    int walls;
 };
 
 // Adjoint of one stage: given the cotangent kap of the stage's f (a field), accumulate

@@ -14,7 +14,10 @@
 //
 // Global memory is read and written through buffer descriptors (FieldRef): one per array, the
 // plane offset in a scalar register, so no address arithmetic runs in vector registers. BIG
-// selects the per-plane descriptor form needed for arrays of 4 GiB or more.
+// selects the per-plane descriptor form needed for arrays of 4 GiB or more. WALLS selects the
+// form with solid walls on the axes flagged in a.walls: the stage input is read through mirror
+// indices there (so the diffusive and sharpening fluxes through a wall face vanish) and the face
+// velocity at index 0 of a walled axis counts as zero.
 #pragma once
 
 #include "pf_cell.h"
@@ -22,7 +25,7 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, bool BIG>
+template <typename T, int TX, int TY, bool BIG, bool WALLS = false>
 __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, int tj, int k0, int k1)
 {
     constexpr int NT = TX * TY;
@@ -39,6 +42,11 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
     const size_t plane = (size_t)nx * ny;
 
     const int i0 = ti * TX, j0 = tj * TY;
+    const bool wx = WALLS && (a.walls & 1), wy = WALLS && (a.walls & 2), wz = WALLS && (a.walls & 4);
+    // stage-input index maps: periodic wrap, or the mirror across walls
+    auto mapx = [&](int v) { return WALLS && wx ? reflectn(v, nx) : wrapn(v, nx); };
+    auto mapy = [&](int v) { return WALLS && wy ? reflectn(v, ny) : wrapn(v, ny); };
+    auto mapz = [&](int v) { return WALLS && wz ? reflectz(v, nz) : wrapz(v, nz); };
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -59,7 +67,7 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         const int e = tid + s * NT;
         if (e < PS) {
             const int r = e / PW, c = e - r * PW;
-            loff[s] = (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES;
+            loff[s] = (unsigned)(mapy(j0 - 2 + r) * nx + mapx(i0 - 2 + c)) * ES;
             lpos[s] = e;
         } else {
             loff[s] = 0;
@@ -71,7 +79,7 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         fW(a.W, plane, nz), fb1(a.base1, plane, nz), fb2(a.base2, plane, nz),
         fo1(a.out1, plane, nz), fo2(a.out2, plane, nz);
     auto fetch = [&](int kk) {
-        const int kw = wrapz(kk, nz);
+        const int kw = mapz(kk);
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (lpos[s] >= 0) pre[s] = fy.load(kw, loff[s]);
@@ -124,13 +132,21 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
 
         // operands from global memory for this plane's outputs (issued early); lanes outside the
         // grid read their wrapped column, in bounds, and store nothing
-        const T w1 = fW.load(wrapz(k + 1, nz), col);
+        const int kw1 = wrapz(k + 1, nz);
+        T w1 = fW.load(kw1, col);
+        if (WALLS && wz && kw1 == 0) w1 = T(0);  // a wall face
         T u0, u1, v0, v1, b1, b2;
         if (out_plane) {
             u0 = fU.load(k, col);
             u1 = fU.load(k, col_xp);
             v0 = fV.load(k, col);
             v1 = fV.load(k, col_yp);
+            if constexpr (WALLS) {  // velocities on wall faces (index 0 of a walled axis)
+                if (wx && iw == 0) u0 = T(0);
+                if (wx && iw == nx - 1) u1 = T(0);
+                if (wy && jw == 0) v0 = T(0);
+                if (wy && jw == ny - 1) v1 = T(0);
+            }
             if (a.out1) b1 = fb1.load(k, col);
             if (a.out2) b2 = fb2.load(k, col);
         }

@@ -15,10 +15,23 @@ __global__ void __launch_bounds__(256) stage_global_kernel(StageArgs<T> a)
     if (i >= a.nx || j >= a.ny) return;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const T* __restrict__ y = a.y;
+    const bool wx = a.walls & 1, wy = a.walls & 2, wz = a.walls & 4;
+    // velocity faces: periodic storage (the high wall face of a walled axis is index 0)
     auto idx = [&](int di, int dj, int dk) -> size_t {
         return ((size_t)wrapn(k + dk, nz) * ny + wrapn(j + dj, ny)) * nx + wrapn(i + di, nx);
     };
-    auto at = [&](int di, int dj, int dk) -> T { return y[idx(di, dj, dk)]; };
+    // stage input: periodic, or mirrored across walls
+    auto at = [&](int di, int dj, int dk) -> T {
+        const int ii = wx ? reflectn(i + di, nx) : wrapn(i + di, nx);
+        const int jj = wy ? reflectn(j + dj, ny) : wrapn(j + dj, ny);
+        const int kk = wz ? reflectn(k + dk, nz) : wrapn(k + dk, nz);
+        return y[((size_t)kk * ny + jj) * nx + ii];
+    };
+    // a face velocity, zero on the wall faces (index 0 of a walled axis)
+    auto vel = [&](const T* f, int di, int dj, int dk, bool wall, int ax) -> T {
+        const int w = ax == 0 ? wrapn(i + di, nx) : (ax == 1 ? wrapn(j + dj, ny) : wrapn(k + dk, nz));
+        return wall && w == 0 ? T(0) : f[idx(di, dj, dk)];
+    };
     // one component of the sharpening product at a neighbouring centre
     auto qcomp = [&](int di, int dj, int dk, int ax) -> T {
         const T gx = grad1(at(di + 1, dj, dk), at(di - 1, dj, dk), a.inv_2dx);
@@ -28,15 +41,16 @@ __global__ void __launch_bounds__(256) stage_global_kernel(StageArgs<T> a)
         return fac * (ax == 0 ? gx : (ax == 1 ? gy : gz));
     };
     const size_t c = idx(0, 0, 0);
-    const T pc = y[c];
+    const T pc = at(0, 0, 0);
     const T pxm = at(-1, 0, 0), pxp = at(1, 0, 0), pym = at(0, -1, 0), pyp = at(0, 1, 0);
     const T pzm = at(0, 0, -1), pzp = at(0, 0, 1);
     const T f = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc), face_sum(pc, pyp),
                          face_sum(pzm, pc), face_sum(pc, pzp), face_diff(pxm, pc), face_diff(pc, pxp),
                          face_diff(pym, pc), face_diff(pc, pyp), face_diff(pzm, pc), face_diff(pc, pzp),
                          qcomp(-1, 0, 0, 0), qcomp(1, 0, 0, 0), qcomp(0, -1, 0, 1), qcomp(0, 1, 0, 1),
-                         qcomp(0, 0, -1, 2), qcomp(0, 0, 1, 2), a.U[c], a.U[idx(1, 0, 0)], a.V[c],
-                         a.V[idx(0, 1, 0)], a.W[c], a.W[idx(0, 0, 1)], a.nhs, a.ge);
+                         qcomp(0, 0, -1, 2), qcomp(0, 0, 1, 2), vel(a.U, 0, 0, 0, wx, 0),
+                         vel(a.U, 1, 0, 0, wx, 0), vel(a.V, 0, 0, 0, wy, 1), vel(a.V, 0, 1, 0, wy, 1),
+                         vel(a.W, 0, 0, 0, wz, 2), vel(a.W, 0, 0, 1, wz, 2), a.nhs, a.ge);
     if (a.out1) a.out1[c] = fma(a.c1, f, a.base1[c]);
     if (a.out2) a.out2[c] = fma(a.c2, f, a.base2[c]);
 }

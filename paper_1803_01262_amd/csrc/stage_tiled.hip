@@ -16,7 +16,7 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, bool BIG>
+template <typename T, int TX, int TY, bool BIG, bool WALLS>
 __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int tiles_x,
                                                              int tiles_y, int kz)
 {
@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int k0 = (b / tiles_y) * kz;
-    tiled_stage_body<T, TX, TY, BIG>(a, ti, tj, k0, min(k0 + kz, a.nz));
+    tiled_stage_body<T, TX, TY, BIG, WALLS>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
 // KZ: planes per z-chunk; KZ = 0 chooses it per launch (launch_chunk_planes).
@@ -40,21 +40,20 @@ hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
     const int tiles_y = (a.ny + TY - 1) / TY;
     if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0) return hipErrorInvalidValue;
     const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
+    const bool walls = a.walls != 0;
+    using Kernel = void (*)(StageArgs<T>, int, int, int);
+    const Kernel kern = big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true>
+                                     : stage_tiled_kernel<T, TX, TY, true, false>)
+                            : (walls ? stage_tiled_kernel<T, TX, TY, false, true>
+                                     : stage_tiled_kernel<T, TX, TY, false, false>);
     int kz = KZ;
     if (KZ == 0) {
-        const void* k = big ? (const void*)stage_tiled_kernel<T, TX, TY, true>
-                            : (const void*)stage_tiled_kernel<T, TX, TY, false>;
-        kz = launch_chunk_planes(k, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
+        kz = launch_chunk_planes((const void*)kern, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
         if (kz <= 0) return hipErrorInvalidDevice;
     }
     const long long blocks = (long long)tiles_x * tiles_y * ((a.nz + kz - 1) / kz);
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (big)
-        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, true>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
-    else
-        hipLaunchKernelGGL((stage_tiled_kernel<T, TX, TY, false>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     return hipGetLastError();
 }
 

@@ -271,10 +271,10 @@ def test_argument_errors(lib):
         pf.Solver((8, 8, 8), -1.0, 0.1, 1.0, 0.01)
     assert ei.value.status == pf.PF_ERR_INVALID
     p = pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01)
-    p.bc[0] = pf.PF_BC_WALL
+    p.bc[0] = 7  # not a pf_bc value
     with pytest.raises(pf.PhaseFieldError) as ei:
         pf.phasefield_create(p)
-    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+    assert ei.value.status == pf.PF_ERR_INVALID
     s = pf.Solver((8, 8, 8), 0.1, 0.1, 1.0, 0.01)
     t = torch.zeros(8 * 8 * 8 + 1, dtype=torch.float64, device="cuda")
     with pytest.raises(pf.PhaseFieldError) as ei:  # misaligned pointer reaches the C ABI
