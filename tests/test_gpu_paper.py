@@ -242,3 +242,40 @@ def test_boundedness_map_on_the_gpu(lib, scheme, sch, limit):
     print(f"{scheme}: {above} points on or above the line, all bounded; "
           f"{below_unbounded} of {below} below it unbounded", flush=True)
     assert above >= 10 and below_unbounded >= 5
+
+
+def test_reinitialisation_relaxes_a_top_hat_to_the_tanh_profile(lib):
+    """Reinitialisation mode (u = 0; Eq. 1 with only its diffusive and sharpening terms, the
+    gamma/|u| -> infinity limit discussed in Sec. 2.3): a 1D top hat of width 1 in [0, 2) relaxes
+    to a steady state that keeps the mass, stays in [0, 1], matches the oracle, and approaches
+    the tanh profile of the same interfaces as dx is refined at fixed eps (the central scheme's
+    O(dx^2) equilibrium error: about 4 x per halving)."""
+    pf = lib
+    L, eps, gamma = 2.0, 0.02, 1.0
+    errs = []
+    for n in (100, 200, 400):
+        dx = L / n
+        x = (np.arange(n) + 0.5) * dx
+        top_hat = (np.abs(x - 1.0) < 0.5).astype(float).reshape(1, 1, n)
+        Z = np.zeros_like(top_hat)
+        dt = 0.9 * params.dt_max("rk4", 1, dx, gamma, eps)
+        s = pf.Solver((n, 1, 1), dx, eps, gamma, dt, dtype="f64")
+        g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (top_hat, Z, Z, Z)]
+        steps, change = 0, 1.0
+        while change > 1e-12 and steps < 40000:
+            prev = g[0].clone()
+            s.step(*g, nsteps=400)
+            steps += 400
+            change = float((g[0] - prev).abs().max())
+        mass, mn, mx, _ = s.reduce(g[0])
+        got = g[0].cpu().numpy()
+        s.close()
+        ref = oracle.step(top_hat, Z, Z, Z, dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=steps)
+        assert np.abs(got - ref).max() <= 1e-12, n
+        assert change <= 1e-12 and abs(mass - 1.0) < 1e-12 and mn >= 0.0 and mx <= 1.0
+        tanh = fx.tanh_profile(0.5 - np.abs(x - 1.0), eps).reshape(1, 1, n)
+        errs.append(np.abs(got - tanh).max())
+        print(f"n {n} (eps/dx {eps / dx:.0f}): steady after {steps} steps, max|phi - tanh| "
+              f"{errs[-1]:.3e}", flush=True)
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(3.0 < r < 5.0 for r in ratios), ratios
