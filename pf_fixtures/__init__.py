@@ -82,6 +82,33 @@ def edge_curl(Ax, Ay, Az, dx):
     return U, V, W
 
 
+def zalesak_ic(n: int, eps: float, L: float = 100.0, centre=(50.0, 75.0), R: float = 15.0,
+               w: float = 5.0, l: float = 25.0) -> np.ndarray:
+    """Notched disk (Sec. 3.3.2) on an n x n x 1 grid of an L x L box: the tanh profile of an
+    approximate signed distance, positive inside the disk and outside the notch. The notch is a
+    w-wide slot rising l from the bottom of the disk, centred on its vertical axis. (The printed
+    radius "0.15" is read as 15 box units, the scale of the printed w, l and box.)"""
+    dx = L / n
+    x = (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(x, x)  # [j, i]: X = x_i, Y = y_j
+    s_disk = R - np.hypot(X - centre[0], Y - centre[1])
+    x0, x1 = centre[0] - w / 2, centre[0] + w / 2
+    y0, y1 = centre[1] - R, centre[1] - R + l
+    s_slot = np.minimum.reduce([X - x0, x1 - X, Y - y0, y1 - Y])  # > 0 inside the slot
+    return tanh_profile(np.minimum(s_disk, -s_slot), eps).reshape(1, n, n)
+
+
+def zalesak_faces(n: int, L: float = 100.0):
+    """Solid-body rotation u = (pi (50 - y) / 314, pi (x - 50) / 314) (Sec. 3.3.2), one turn in
+    t = 628, sampled on the faces: U on the x-faces depends on y only and V on the y-faces on x
+    only, so the discrete divergence is exactly zero (also across the periodic seams)."""
+    dx = L / n
+    c = (np.arange(n) + 0.5) * dx
+    U = np.broadcast_to((np.pi * (50.0 - c) / 314.0)[:, None], (n, n)).reshape(1, n, n).copy()
+    V = np.broadcast_to((np.pi * (c - 50.0) / 314.0)[None, :], (n, n)).reshape(1, n, n).copy()
+    return U, V, np.zeros((1, n, n))
+
+
 def vortex2d_faces(n: int):
     """Single-vortex field on the unit square, n x n x 1 (Sec. 3.3.1, Eq. 33).
 

@@ -279,3 +279,59 @@ def test_reinitialisation_relaxes_a_top_hat_to_the_tanh_profile(lib):
               f"{errs[-1]:.3e}", flush=True)
     ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
     assert all(3.0 < r < 5.0 for r in ratios), ratios
+
+
+def test_zalesak_disk_one_revolution(lib):
+    """Sec. 3.3.2 on the HIP stepper: the notched disk (R = 15, notch 5 x 25, in a 100 x 100 box;
+    the printed "R = 0.15" is read as 15 box units) turned once by u = (pi (50 - y) / 314,
+    pi (x - 50) / 314) in t = 628, RK4 at dt = dx/4, eps/dx = 0.7 and gamma / max|u| = 2.5
+    (on the crossover line). At N = 100, 200, 400: phi stays in [0, 1] (checked every 8 steps),
+    mass is conserved, and the shape error mean|phi(T) - phi(0)| falls with refinement (the
+    paper's Fig. 12 shows the same trend). At N = 100 the first quarter turn matches the oracle
+    (tolerance measured on the oracle, as above)."""
+    pf = lib
+    L = 100.0
+    errs = []
+    for n in (100, 200, 400):
+        dx = L / n
+        eps = 0.7 * dx
+        U, V, W = fx.zalesak_faces(n)
+        gamma = 2.5 * fx.max_face_speed(U, V, W)
+        phi0 = fx.zalesak_ic(n, eps)
+        dt = dx / 4
+        ns = int(round(628.0 / dt))
+        s = pf.Solver((n, n, 1), dx, eps, gamma, dt, dtype="f64")
+        g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi0, U, V, W)]
+        st = torch.cuda.Stream()
+        lo, hi = 1.0, 0.0
+        with torch.cuda.stream(st):
+            m0 = s.reduce(g[0], stream=st)[0]
+            if n == 100:
+                s.step(*g, nsteps=ns // 4, stream=st)
+                quarter = g[0].cpu().numpy()
+                done = ns // 4
+            else:
+                done = 0
+            while done < ns:
+                m = min(8, ns - done)
+                s.step(*g, nsteps=m, stream=st)
+                done += m
+                _, mn, mx, bad = s.reduce(g[0], stream=st)
+                assert bad == 0
+                lo, hi = min(lo, mn), max(hi, mx)
+            m1 = s.reduce(g[0], stream=st)[0]
+        got = g[0].cpu().numpy()
+        s.close()
+        assert lo >= -EPS64 and hi <= 1 + EPS64, (n, lo, hi)
+        assert abs(m1 - m0) / m0 < 1e-12, (n, m0, m1)
+        errs.append(np.abs(got - phi0).mean())
+        print(f"N {n}: {ns} steps, min {lo:.2e}, max-1 {hi - 1:.2e}, shape error {errs[-1]:.4e}",
+              flush=True)
+        if n == 100:
+            kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns // 4)
+            ref = oracle.step(phi0, U, V, W, **kw)
+            wobble = np.random.default_rng(n).standard_normal(phi0.shape)
+            ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, V, W, **kw)
+            tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
+            assert np.abs(quarter - ref).max() <= tol
+    assert errs[1] < errs[0] and errs[2] < errs[1], errs
