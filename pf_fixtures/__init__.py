@@ -109,6 +109,20 @@ def zalesak_faces(n: int, L: float = 100.0):
     return U, V, np.zeros((1, n, n))
 
 
+def random_wall_stream_faces(rng: np.random.Generator, n: int, dx: float):
+    """A cell-to-cell random, discretely solenoidal 2D face velocity for an n x n box with walls
+    on x and y (Sec. 3.2.2 stand-in): i.i.d. standard normal stream-function values at the
+    interior cell corners, zero on the walls, and its discrete curl (u = -dPsi/dy, v = dPsi/dx).
+    The normal velocity on the wall faces is then exactly zero. Scaled so that the largest face
+    component is 1. (The paper projects random point vectors with a Poisson solve instead.)"""
+    psi = np.zeros((n + 1, n + 1))  # [j, i] at corner (i dx, j dx)
+    psi[1:n, 1:n] = rng.standard_normal((n - 1, n - 1))
+    U = -(psi[1:, :n] - psi[:n, :n]) / dx  # x-face (i dx, (j + 1/2) dx)
+    V = (psi[:n, 1:] - psi[:n, :n]) / dx   # y-face ((i + 1/2) dx, j dx)
+    s = 1.0 / max(np.abs(U).max(), np.abs(V).max())
+    return (U * s).reshape(1, n, n), (V * s).reshape(1, n, n), np.zeros((1, n, n))
+
+
 def vortex2d_faces(n: int):
     """Single-vortex field on the unit square, n x n x 1 (Sec. 3.3.1, Eq. 33).
 
