@@ -25,7 +25,12 @@
  *    With delta > 0 the regularised n = g/sqrt(|g|^2 + delta^2) is used everywhere.
  *  - The i-1 sharpening term of Eq. 11/12 carries (phi^2 - phi), as Eq. 13 and Eq. 21 require.
  *  - Velocity with a time factor: u(x,t) = u0(x) s(t), s = 1 (steady) or cos(pi t / T);
- *    classic RK4 evaluates s at t, t+dt/2, t+dt/2, t+dt; the explicit midpoint RK2 at t, t+dt/2.
+ *    classic RK4 evaluates s at t, t+dt/2, t+dt/2, t+dt; the explicit midpoint RK2 at t, t+dt/2;
+ *    the RK3 at t, t+8dt/15, t+2dt/3.
+ *  - RK3 (the paper names Wray's low-storage third-order scheme and its limit, Eq. 27, but not its
+ *    coefficients): u1 = u0 + dt g1 k1, u2 = u1 + dt (g2 k2 + z2 k1), u3 = u2 + dt (g3 k3 + z3 k2)
+ *    with g = (8/15, 5/12, 3/4), z2 = -17/60, z3 = -5/12, k_s = f(u_{s-1}). Third order; its
+ *    stability polynomial 1 + z + z^2/2 + z^3/6 reaches -2.51 on the real axis, Eq. 27's factor.
  *  - FP32-storage mode: every RK stage input and the new phi are rounded to float32 at the
  *    points where a value must be materialised; arithmetic stays FP64.
  *  - Walls (the paper names slip walls for its 2D random-field test but gives no discrete
@@ -171,8 +176,8 @@ static double time_factor(int vel_mode, double vel_T, double t)
 
 /* nsteps explicit steps of Eq. 1 in place on phi (Sec. 2.3).
  * scheme 1: forward Euler (Eq. 25 regime); scheme 2: the explicit midpoint rule (RK2, Eq. 26
- * regime); scheme 4: classic RK4 (Eq. 28, used for every experiment of Sec. 3). Step n starts
- * at t0 + n*dt. */
+ * regime); scheme 3: the low-storage RK3 above (Eq. 27 regime); scheme 4: classic RK4 (Eq. 28,
+ * used for every experiment of Sec. 3). Step n starts at t0 + n*dt. */
 void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int vel_mode,
               double vel_T, int64_t nsteps, double *phi, const double *U, const double *V,
               const double *W)
@@ -186,6 +191,20 @@ void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int
         if (scheme == 1) {
             orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
             for (int64_t c = 0; c < N; ++c) phi[c] = round_storage(phi[c] + dt * k1[c], fp32);
+            continue;
+        }
+        if (scheme == 3) {
+            const double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0,
+                         z3 = -5.0 / 12.0;
+            double *u2 = k4;
+            orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
+            for (int64_t c = 0; c < N; ++c) y[c] = round_storage(phi[c] + dt * g1 * k1[c], fp32);
+            orc_rhs(g, time_factor(vel_mode, vel_T, t + g1 * dt), y, U, V, W, k2);
+            for (int64_t c = 0; c < N; ++c)
+                u2[c] = round_storage(y[c] + dt * (g2 * k2[c] + z2 * k1[c]), fp32);
+            orc_rhs(g, time_factor(vel_mode, vel_T, t + (g1 + g2 + z2) * dt), u2, U, V, W, k3);
+            for (int64_t c = 0; c < N; ++c)
+                phi[c] = round_storage(u2[c] + dt * (g3 * k3[c] + z3 * k2[c]), fp32);
             continue;
         }
         if (scheme == 2) {

@@ -86,7 +86,7 @@ def test_eq19_divergence_term():
 # --------------------------------------------------------------------- conservation
 
 
-@pytest.mark.parametrize("scheme", [2, 4])
+@pytest.mark.parametrize("scheme", [2, 3, 4])
 @pytest.mark.parametrize("solenoidal_field", [True, False])
 def test_mass_conserved_to_roundoff(solenoidal_field, scheme):
     """Sum of f telescopes to zero for any face velocity (Sec. 2.2 flux form)."""
@@ -110,7 +110,7 @@ def test_mass_conserved_to_roundoff(solenoidal_field, scheme):
 # --------------------------------------------------------------------- complement symmetry
 
 
-@pytest.mark.parametrize("scheme", [1, 2, 4])
+@pytest.mark.parametrize("scheme", [1, 2, 3, 4])
 def test_complement_symmetry(scheme):
     """step(1 - phi) == 1 - step(phi) for a discretely solenoidal field (Eq. 16, Sec. 2.2.2)."""
     rng = np.random.default_rng(4)
@@ -195,12 +195,13 @@ def test_tanh_profile_is_discrete_equilibrium():
 # --------------------------------------------------------------------- pure advection
 
 
-@pytest.mark.parametrize("scheme", [2, 4])
+@pytest.mark.parametrize("scheme", [2, 3, 4])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_gamma0_rk_amplification(axis, scheme):
     """gamma = 0, uniform u: a sampled Fourier mode is multiplied per step by the scheme's
     stability polynomial, z = -i u dt sin(k dx)/dx (Eq. 3 with gamma = 0): RK4
-    R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24; the explicit midpoint rule R(z) = 1 + z + z^2/2."""
+    R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24; any three-stage third-order scheme (the RK3)
+    1 + z + z^2/2 + z^3/6; the explicit midpoint rule R(z) = 1 + z + z^2/2."""
     n, m, u, dx = 24, 3, 0.8, 1.0 / 24
     dt = 0.4 * dx / u
     k = 2 * np.pi * m
@@ -213,7 +214,7 @@ def test_gamma0_rk_amplification(axis, scheme):
     nsteps = 7
     out = oracle.step(phi, *vel, dx=dx, eps=dx, gamma=0.0, dt=dt, nsteps=nsteps, scheme=scheme)
     z = -1j * u * dt * np.sin(k * dx) / dx
-    R = 1 + z + z ** 2 / 2 + (z ** 3 / 6 + z ** 4 / 24 if scheme == 4 else 0)
+    R = sum(z ** m / math.factorial(m) for m in range(scheme + 1))
     exact = np.real(R ** nsteps * np.exp(1j * k * x)).reshape(shape)
     np.testing.assert_allclose(out, exact, rtol=0, atol=1e-14)
 
@@ -429,3 +430,43 @@ def test_rk2_below_the_crossover_line_leaves_bounds(eps_over_dx, gamma_over_u):
     assert eps_over_dx < params.crossover_eps_over_dx(gamma_over_u)
     lo, hi = _drop_1d_extremes(eps_over_dx, gamma_over_u, "rk2", 2)
     assert lo < -1e-3 and hi > 1 + 1e-3, (lo, hi)
+
+
+def test_rk3_stage_times_and_eq27_factor():
+    """The RK3's stage times (the velocity factor at t, t + 8dt/15, t + 2dt/3, with a wrong-time
+    negative control), and Eq. 27's 2.51: the real-axis stability limit of its polynomial
+    1 + z + z^2/2 + z^3/6 (the largest diffusive eigenvalue is -4 D_f gamma eps / dx^2)."""
+    n, dx, T = 16, 1.0 / 16, 0.7
+    rng = np.random.default_rng(28)
+    phi = rand_phi(rng, (1, 1, n))
+    U = np.full((1, 1, n), 0.9)
+    Z = np.zeros_like(U)
+    t0, dt = 0.13, 0.01
+    got = oracle.step(phi, U, Z, Z, dx=dx, eps=dx, gamma=0.0, dt=dt, t0=t0, vel_mode=1,
+                      vel_T=T, scheme=3)
+    D = lambda p: oracle.rhs(p, U, Z, Z, dx=dx, eps=dx, gamma=0.0)  # noqa: E731
+    s = [math.cos(math.pi * (t0 + c * dt) / T) for c in (0.0, 8 / 15, 2 / 3)]
+    k1 = s[0] * D(phi)
+    u1 = phi + dt * 8 / 15 * k1
+    k2 = s[1] * D(u1)
+    u2 = u1 + dt * (5 / 12 * k2 - 17 / 60 * k1)
+    k3 = s[2] * D(u2)
+    np.testing.assert_allclose(got, u2 + dt * (3 / 4 * k3 - 5 / 12 * k2), atol=1e-15)
+    k3w = math.cos(math.pi * (t0 + dt / 2) / T) * D(u2)
+    assert np.abs(u2 + dt * (3 / 4 * k3w - 5 / 12 * k2) - got).max() > 1e-9
+    # stability limit on the negative real axis
+    z = np.linspace(-3.0, 0.0, 3000001)
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6
+    limit = -z[np.abs(R) <= 1.0].min()
+    assert limit == pytest.approx(2.51, abs=0.005)
+    assert params.dt_max("rk3", 2, 0.1, 1.3, 0.07) == pytest.approx(
+        2.51 * 0.1 ** 2 / (4 * 2 * 1.3 * 0.07), rel=1e-15)
+
+
+@pytest.mark.parametrize("eps_over_dx,gamma_over_u", [(1.0, 1.0), (0.75, 2.0), (1.5, 1.0),
+                                                       (2.0, 0.5)])
+def test_rk3_at_eq27_bounded_on_and_above_the_crossover_line(eps_over_dx, gamma_over_u):
+    """Fig. 6(c): the RK3 at its diffusive limit (Eq. 27) keeps the 1D drop in [0, 1] for a
+    whole period on and above the crossover line."""
+    lo, hi = _drop_1d_extremes(eps_over_dx, gamma_over_u, "rk3", 3)
+    assert lo >= -EPS64 and hi <= 1 + EPS64, (lo, hi)
