@@ -8,8 +8,9 @@
  * faces (a staggered MAC grid), unit normal and the sharpening product phi(1-phi)n at cell
  * centres averaged onto faces, diffusive and advective face fluxes from second-order central
  * differences, and the cell update as the divergence of the face fluxes. Time integration is
- * forward Euler (Sec. 2.3, Eq. 25), the explicit midpoint rule (RK2, Eq. 26) or classic
- * fourth-order Runge-Kutta (Eq. 28; the scheme of every experiment in Sec. 3).
+ * forward Euler (Sec. 2.3, Eq. 25), the explicit midpoint rule (RK2, Eq. 26), the low-storage
+ * third-order Runge-Kutta the paper names (RK3, Eq. 27) or classic fourth-order Runge-Kutta
+ * (Eq. 28; the scheme of every experiment in Sec. 3).
  *
  * Data layout (every array): C-contiguous [nz][ny][nx], x fastest, periodic in every axis.
  *   phi[k][j][i]  cell-centre phase field.
@@ -56,7 +57,7 @@ typedef enum {
 
 typedef enum { PF_F32 = 0, PF_F64 = 1 } pf_dtype;             /* storage precision      */
 typedef enum { PF_BC_PERIODIC = 0, PF_BC_WALL = 1 } pf_bc;      /* per axis               */
-typedef enum { PF_EULER = 1, PF_RK2 = 2, PF_RK4 = 4 } pf_scheme;
+typedef enum { PF_EULER = 1, PF_RK2 = 2, PF_RK3 = 3, PF_RK4 = 4 } pf_scheme;
 typedef enum { PF_VEL_STEADY = 0, PF_VEL_COS_REVERSAL = 1 } pf_velmode;
 
 /* Problem statement of one simulation (Sec. 2.2: uniform isotropic mesh dx; eps and gamma
@@ -93,7 +94,7 @@ void phasefield_default_params(pf_params *p);
  *                          >= 0 is the bounded regime proven in Sec. 2.2.
  *   crossover_margin_eq24: the same with the relaxed line of Eqs. 23-24 (identical here,
  *                          because the face speed is already the largest component).
- *   dt_max_scheme:         Eq. 25 (Euler), Eq. 26 (RK2) or Eq. 28 (RK4) with D_f = axes
+ *   dt_max_scheme:         Eq. 25 (Euler), 26 (RK2), 27 (RK3) or 28 (RK4) with D_f = axes
  *                          longer than 1 cell.
  *   dt_over_dtmax:         dt / dt_max_scheme. */
 typedef struct {
@@ -118,7 +119,8 @@ pf_status phasefield_destroy(pf_solver *s);
 
 /* Advance phi IN PLACE by nsteps steps of the handle's scheme (Sec. 2.3), starting at time
  * t0; step m runs from t0 + m dt. u, v, w: face velocity u0 (the time factor s(t) is applied
- * by the library at the stage times: RK4 t, t+dt/2, t+dt/2, t+dt; RK2 t, t+dt/2; Euler t).
+ * by the library at the stage times: RK4 t, t+dt/2, t+dt/2, t+dt; RK3 t, t+8dt/15, t+2dt/3;
+ * RK2 t, t+dt/2; Euler t). RK3 runs on the per-stage kernels (a fused variant falls back).
  * nsteps = 0 is a no-op.
  * The handle's stage buffers are overwritten (and, with a fused variant, one of them holds phi
  * between steps); phi holds the result when the enqueued work completes.
@@ -132,7 +134,7 @@ pf_status phasefield_step(pf_solver *s, void *phi, const void *u, const void *v,
  * dL/du0 etc. (+=). The stage inputs of the forward step are recomputed from phi_n.
  * Allocates three more field-sized scratch buffers on first use.
  * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_UNSUPPORTED (a handle with
- * walls), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * walls or the RK3 scheme), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);

@@ -14,7 +14,7 @@ import math
 import torch
 
 from ._capi import (EXPORTED, PF_BC_PERIODIC, PF_BC_WALL, PF_ERR_DEVICE, PF_ERR_INVALID,  # noqa: F401
-                    PF_ERR_NONFINITE, PF_ERR_OOM, PF_ERR_UNSUPPORTED, PF_EULER, PF_F32, PF_F64, PF_RK2,
+                    PF_ERR_NONFINITE, PF_ERR_OOM, PF_ERR_UNSUPPORTED, PF_EULER, PF_F32, PF_F64, PF_RK2, PF_RK3,
                     PF_OK, PF_RK4, PF_VEL_COS_REVERSAL, PF_VEL_STEADY, LIB_PATH, Params,
                     PhaseFieldError, Report, cells, lib, make_params, phasefield_adjoint_step,
                     phasefield_autotune, phasefield_batch_create, phasefield_batch_destroy,

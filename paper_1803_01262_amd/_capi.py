@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libphasefield.so")
 PF_OK, PF_ERR_INVALID, PF_ERR_UNSUPPORTED, PF_ERR_DEVICE, PF_ERR_OOM, PF_ERR_NONFINITE = range(6)
 PF_F32, PF_F64 = 0, 1
 PF_BC_PERIODIC, PF_BC_WALL = 0, 1
-PF_EULER, PF_RK2, PF_RK4 = 1, 2, 4
+PF_EULER, PF_RK2, PF_RK3, PF_RK4 = 1, 2, 3, 4
 PF_VEL_STEADY, PF_VEL_COS_REVERSAL = 0, 1
 
 _STATUS = {0: "PF_OK", 1: "PF_ERR_INVALID", 2: "PF_ERR_UNSUPPORTED", 3: "PF_ERR_DEVICE",
@@ -129,8 +129,8 @@ def make_params(n, dx, eps, gamma, dt, *, dtype="f64", scheme="rk4", delta=0.0, 
     p.n[0], p.n[1], p.n[2] = (int(v) for v in n)
     p.dx, p.eps, p.gamma, p.dt, p.delta = float(dx), float(eps), float(gamma), float(dt), float(delta)
     p.dtype = {"f32": PF_F32, "f64": PF_F64, PF_F32: PF_F32, PF_F64: PF_F64}[dtype]
-    p.scheme = {"rk4": PF_RK4, "rk2": PF_RK2, "euler": PF_EULER, PF_RK4: PF_RK4, PF_RK2: PF_RK2,
-                PF_EULER: PF_EULER}[scheme]
+    p.scheme = {"rk4": PF_RK4, "rk3": PF_RK3, "rk2": PF_RK2, "euler": PF_EULER, PF_RK4: PF_RK4,
+                PF_RK3: PF_RK3, PF_RK2: PF_RK2, PF_EULER: PF_EULER}[scheme]
     p.vel_mode = int(vel_mode)
     p.vel_T = float(vel_T)
     p.variant = int(variant)

@@ -85,7 +85,7 @@ pf_status pf::validate_params(const pf_params* p)
     if (!(p->delta >= 0.0) || !std::isfinite(p->delta))
         return fail(PF_ERR_INVALID, "delta must be >= 0");
     if (p->dtype != PF_F32 && p->dtype != PF_F64) return fail(PF_ERR_INVALID, "dtype = %d", p->dtype);
-    if (p->scheme != PF_EULER && p->scheme != PF_RK2 && p->scheme != PF_RK4)
+    if (p->scheme != PF_EULER && p->scheme != PF_RK2 && p->scheme != PF_RK3 && p->scheme != PF_RK4)
         return fail(PF_ERR_INVALID, "scheme = %d", p->scheme);
     if (p->vel_mode != PF_VEL_STEADY && p->vel_mode != PF_VEL_COS_REVERSAL)
         return fail(PF_ERR_INVALID, "vel_mode = %d", p->vel_mode);
@@ -120,8 +120,10 @@ extern "C" pf_status phasefield_check_params(const pf_params* p, double max_face
     const int D = active_dims(p->n);
     const double ge = p->gamma * p->eps;
     const double base = ge > 0.0 ? p->dx * p->dx / ge : INFINITY;
-    // Eq. 25 (Euler) and Eq. 26 (RK2) coincide; Eq. 28 (RK4)
-    out->dt_max_scheme = p->scheme == PF_RK4 ? 2.79 * base / (4.0 * D) : base / (2.0 * D);
+    // Eq. 25 (Euler) and Eq. 26 (RK2) coincide; Eq. 27 (RK3), Eq. 28 (RK4)
+    out->dt_max_scheme = p->scheme == PF_RK4   ? 2.79 * base / (4.0 * D)
+                         : p->scheme == PF_RK3 ? 2.51 * base / (4.0 * D)
+                                               : base / (2.0 * D);
     out->dt_over_dtmax = p->dt / out->dt_max_scheme;
     return PF_OK;
 }
@@ -335,6 +337,11 @@ template hipError_t pf::run_stage<double>(int, const StageArgs<double>&, hipStre
 //   Euler (Eq. 25): acc = phi + dt f(phi, t); phi = acc.
 //   RK2, the explicit midpoint rule (Eq. 26):
 //     S1: ya = phi + dt/2 k1;  S2: phi = phi + dt k2   (k2 = f(ya, t + dt/2))
+//   RK3, low storage (Eq. 27), u1 = u0 + dt g1 k1, u2 = u1 + dt (g2 k2 + z2 k1),
+//   u3 = u2 + dt (g3 k3 + z3 k2), with acc carrying the part of the next stage known so far:
+//     S1: ya = phi + dt g1 k1,  acc = phi + dt (g1 + z2) k1             (k1 = f(phi, t))
+//     S2: yb = acc + dt g2 k2  (acc += dt (g2 + z3) k2 is a no-op: g2 + z3 = 0)
+//     S3: phi = acc + dt g3 k3                            (k2, k3 at t + g1 dt, t + (g1 + g2 + z2) dt)
 // S4 writes phi in place: it reads phi nowhere (its stencil input is ya, acc is read only at
 // the cell being written). RK2's S2 likewise reads phi only at the cell it writes.
 template <typename T>
@@ -350,6 +357,20 @@ hipError_t pf::enqueue_step(const pf_params& p, int variant, T* phi, const T* U,
         return launch_copy<T>(phi, acc, (size_t)p.n[0] * p.n[1] * p.n[2], st);
     }
     const double sh = time_factor(p, t + 0.5 * dt);
+    if (p.scheme == PF_RK3) {
+        constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0,
+                         z3 = -5.0 / 12.0;
+        e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, phi, ya, acc,
+                                                dt * g1, dt * (g1 + z2), U, V, W), st);
+        if (e != hipSuccess) return e;
+        static_assert(g2 + z3 == 0.0, "acc already holds u2 + dt z3 k2 after S2");
+        e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t + g1 * dt), ya, acc, nullptr,
+                                                yb, nullptr, dt * g2, 0.0, U, V, W), st);
+        if (e != hipSuccess) return e;
+        return run_stage<T>(variant, make_stage<T>(p, time_factor(p, t + (g1 + g2 + z2) * dt), yb,
+                                                   nullptr, acc, nullptr, phi, 0.0, dt * g3, U, V, W),
+                            st);
+    }
     if (p.scheme == PF_RK2) {
         e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, nullptr, ya,
                                                 nullptr, 0.5 * dt, 0.0, U, V, W), st);
@@ -482,8 +503,10 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
                              hipStream_t st)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
-    // the fused sweeps have periodic axes only; with walls their variants run the per-stage kernel
-    const bool fused = p.scheme != PF_EULER && variant_is_fused(dtype, variant) && wall_mask(p) == 0;
+    // the fused sweeps run RK4 and RK2 on periodic axes; otherwise their variants run the
+    // per-stage kernel
+    const bool fused = (p.scheme == PF_RK4 || p.scheme == PF_RK2) && variant_is_fused(dtype, variant) &&
+                       wall_mask(p) == 0;
     T* cur = phi;
     for (int m = 0; m < nsteps; ++m) {
         const double t = t0 + (double)m * p.dt;

@@ -40,7 +40,7 @@ def test_default_params(pf):
 
 @pytest.mark.parametrize("field,value", [("dx", 0.0), ("dx", -1.0), ("eps", -0.1),
                                          ("gamma", -1.0), ("dt", 0.0), ("delta", -1.0),
-                                         ("dtype", 7), ("scheme", 3), ("vel_mode", 3),
+                                         ("dtype", 7), ("scheme", 5), ("vel_mode", 3),
                                          ("variant", 999)])
 def test_invalid_params_rejected_before_device_work(pf, field, value):
     p = pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01)
@@ -72,7 +72,7 @@ def test_invalid_sizes_and_bcs(pf):
     with pytest.raises(pf.PhaseFieldError) as ei:
         pf.phasefield_batch_create([pw])
     assert ei.value.status == pf.PF_ERR_UNSUPPORTED
-    for scheme in ("euler", "rk2"):
+    for scheme in ("euler", "rk2", "rk3"):
         with pytest.raises(pf.PhaseFieldError) as ei:
             pf.phasefield_batch_create([pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01,
                                                        scheme=scheme)])
@@ -81,7 +81,8 @@ def test_invalid_sizes_and_bcs(pf):
 
 @pytest.mark.parametrize("n,scheme", [((64, 64, 1), "rk4"), ((32, 32, 32), "rk4"),
                                       ((50, 1, 1), "euler"), ((20, 30, 1), "euler"),
-                                      ((40, 1, 1), "rk2"), ((16, 16, 16), "rk2")])
+                                      ((40, 1, 1), "rk2"), ((16, 16, 16), "rk2"),
+                                      ((30, 20, 1), "rk3"), ((12, 12, 12), "rk3")])
 def test_check_params_states_eq17_and_dt_limits(pf, n, scheme):
     dx, eps, gamma, umax = 0.02, 0.017, 1.3, 0.9
     p = pf.make_params(n, dx, eps, gamma, 1e-4, scheme=scheme)

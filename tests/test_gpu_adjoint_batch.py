@@ -97,6 +97,17 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape, scheme):
             assert torch.equal(a, b), nm
 
 
+def test_adjoint_declines_rk3(lib):
+    pf = lib
+    rng, phi, U, V, W, lam, dx = adj_case(3, (6, 7, 8))
+    s = pf.Solver((8, 7, 6), dx, dx, 1.0, 0.05 * dx, scheme="rk3")
+    g = [dev(a) for a in (phi, U, V, W)]
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        s.adjoint_step(*g, 0.0, dev(lam))
+    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+    s.close()
+
+
 def test_adjoint_step_fp32_close_to_fp64_oracle(lib):
     pf = lib
     rng, phi, U, V, W, lam, dx = adj_case(2, (16, 16, 16))

@@ -96,15 +96,17 @@ def test_fp32_all_variants_match_oracle_and_each_other(lib, shape):
         assert np.array_equal(o, outs[0]), f"variant {v} differs from variant 0"
 
 
+@pytest.mark.parametrize("scheme", ["rk2", "rk3"])
 @pytest.mark.parametrize("dtype,shape", [("f64", (16, 20, 24)), ("f64", (5, 9, 70)),
                                          ("f64", (1, 33, 17)), ("f64", (3, 2, 1)),
                                          ("f64", (7, 6, 65)), ("f32", (40, 36, 68)),
                                          ("f32", (9, 5, 7)), ("f32", (1, 33, 130))])
-def test_rk2_all_variants_match_oracle_and_each_other(lib, dtype, shape):
-    """The explicit midpoint rule (Sec. 2.3, Eq. 26) on every variant: the per-stage form (two
-    launches) and the fused form (one sweep, the midpoint value kept in LDS) agree bitwise and
-    match the oracle, over an odd and an even step count (the fused form alternates phi with a
-    second buffer)."""
+def test_rk2_rk3_all_variants_match_oracle_and_each_other(lib, dtype, shape, scheme):
+    """The explicit midpoint rule (Eq. 26) and the low-storage RK3 (Eq. 27) of Sec. 2.3 on every
+    variant: RK2's per-stage form (two launches) and fused form (one sweep, the midpoint value
+    kept in LDS), RK3's per-stage form (three launches; fused variants fall back to it), all
+    bitwise equal and matching the oracle, over an odd and an even step count (the fused form
+    alternates phi with a second buffer)."""
     pf = lib
     kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
     rng = np.random.default_rng(21 + sum(shape))
@@ -113,12 +115,12 @@ def test_rk2_all_variants_match_oracle_and_each_other(lib, dtype, shape):
         phi, U, V, W = (a.astype(np.float32).astype(np.float64) for a in (phi, U, V, W))
     for nsteps in (7, 4):
         kw = dict(dx=dx, eps=dx, gamma=1.3, dt=0.1 * dx, nsteps=nsteps)
-        ref = oracle.step(phi, U, V, W, scheme=2, fp32=dtype == "f32", **kw)
+        ref = oracle.step(phi, U, V, W, scheme={"rk2": 2, "rk3": 3}[scheme], fp32=dtype == "f32", **kw)
         outs = []
         for v in range(pf.phasefield_variant_count(kd)):
             print("case", dtype, shape, nsteps, "variant", pf.phasefield_variant_name(kd, v),
                   flush=True)
-            outs.append(gpu_run(pf, phi, U, V, W, variant=v, dtype=dtype, scheme="rk2", **kw))
+            outs.append(gpu_run(pf, phi, U, V, W, variant=v, dtype=dtype, scheme=scheme, **kw))
             err = rel_linf(outs[-1], ref)
             assert err <= (TOL64 if dtype == "f64" else TOL32), (v, err)
         for v, o in enumerate(outs[1:], 1):
@@ -129,7 +131,7 @@ def test_rk2_all_variants_match_oracle_and_each_other(lib, dtype, shape):
 def test_euler_and_cos_reversal_fp64(lib, shape):
     rng = np.random.default_rng(3)
     phi, U, V, W, dx = random_case(rng, shape)
-    for scheme, sch in (("euler", 1), ("rk2", 2), ("rk4", 4)):
+    for scheme, sch in (("euler", 1), ("rk2", 2), ("rk3", 3), ("rk4", 4)):
         kw = dict(dx=dx, eps=dx, gamma=1.0, dt=0.1 * dx, nsteps=9, delta=0.01 / dx, vel_mode=1,
                   vel_T=0.37, t0=0.05)
         ref = oracle.step(phi, U, V, W, scheme=sch, **kw)

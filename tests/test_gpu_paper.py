@@ -187,11 +187,11 @@ def test_rk2_boundedness_map_on_the_gpu(lib, eps_over_dx, gamma_over_u, bounded)
 
 
 @pytest.mark.parametrize("scheme,sch,limit", [("euler", 1, "euler"), ("rk2", 2, "rk2"),
-                                              ("rk4", 4, "rk4")])
+                                              ("rk3", 3, "rk3"), ("rk4", 4, "rk4")])
 def test_boundedness_map_on_the_gpu(lib, scheme, sch, limit):
     """Secs. 2.2-2.3, Figs. 5(a) and 6: the 1D drop (diameter 1, u = 1, one period of [0, 2),
     n = 50) over a grid of (eps/dx, gamma/u) points, each scheme at its diffusive limit
-    (Eqs. 25, 26, 28). Every point on or above the crossover line (Eq. 9) keeps phi inside
+    (Eqs. 25-28). Every point on or above the crossover line (Eq. 9) keeps phi inside
     [0, 1] at every step (proven for Euler, observed by the paper for the Runge-Kutta schemes),
     and its final field matches the oracle (tolerance measured on the oracle, as above). The
     criterion is sufficient, not necessary, so below the line only the existence of unbounded
