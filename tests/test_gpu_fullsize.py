@@ -4,8 +4,8 @@ Inputs are built on the host (seeded drops; the Fourier face field contracted wi
 no oracle input comes from the GPU path. The GPU advances the whole grid in the benchmark's
 configuration (tuned tile variant, FP32 storage). The oracle cannot step 134M cells in a test,
 but a cell's value after m RK4 steps depends only on the input within 8m cells of it (four
-stages, each reaching two cells along an axis), so the oracle runs on a periodic patch of radius
-8m + 2 around each sampled cell and its centre value is exact.
+stages, each reaching two cells along an axis; 4m for RK2's two stages), so the oracle runs on a
+periodic patch of that radius plus 2 around each sampled cell and its centre value is exact.
 """
 import numpy as np
 import pytest
@@ -40,8 +40,9 @@ def sample_cells(phi, rng, count):
     return np.concatenate([pick, rand])
 
 
-@pytest.mark.parametrize("dtype,nsteps,tol", [("f32", 2, 1e-5), ("f64", 1, 1e-12)])
-def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol):
+@pytest.mark.parametrize("dtype,nsteps,tol,scheme", [("f32", 2, 1e-5, "rk4"), ("f64", 1, 1e-12, "rk4"),
+                                                    ("f32", 3, 1e-5, "rk2")])
+def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol, scheme):
     pf = lib
     c, U, V, W = case512
     np_dt = np.float32 if dtype == "f32" else np.float64
@@ -49,7 +50,9 @@ def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol):
     inputs = [a.astype(np_dt).astype(np.float64) for a in (c.phi0, U, V, W)]
     n = c.shape[0]
     st = torch.cuda.Stream()
-    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype)
+    # RK2 at 0.9 x its diffusive limit (Eq. 26, three axes), below RK4's step
+    dt = c.dt if scheme == "rk4" else min(c.dt, 0.9 * c.dx * c.dx / (6.0 * c.gamma * c.eps))
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, dt, dtype=dtype, scheme=scheme)
     s.autotune(reps=1, stream=st)
     print("variant", s.variant_name, flush=True)
     g = [torch.tensor(a, dtype=tdt, device="cuda") for a in inputs]
@@ -62,15 +65,15 @@ def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol):
     s.close()
     drift = abs(m1[0] - m0[0]) / m0[0]
     assert drift <= (1e-6 if dtype == "f32" else 1e-13), drift
-    R = 8 * nsteps + 2
+    R = (8 if scheme == "rk4" else 4) * nsteps + 2
     rng = np.random.default_rng(17)
     worst = 0.0
     for (k, j, i) in sample_cells(inputs[0], rng, 24):
         pp = [patch(a, k, j, i, R) for a in inputs]
-        ref = oracle.step(*pp, dx=c.dx, eps=c.eps, gamma=c.gamma, dt=c.dt, nsteps=nsteps,
-                          fp32=(dtype == "f32"))
+        ref = oracle.step(*pp, dx=c.dx, eps=c.eps, gamma=c.gamma, dt=dt, nsteps=nsteps,
+                          fp32=(dtype == "f32"), scheme=4 if scheme == "rk4" else 2)
         worst = max(worst, abs(out[k, j, i] - ref[R, R, R]))
-    print(dtype, "worst sampled |gpu - oracle| =", worst, "mass drift", drift, flush=True)
+    print(dtype, scheme, "worst sampled |gpu - oracle| =", worst, "mass drift", drift, flush=True)
     assert worst <= tol * np.abs(out).max()
 
 
