@@ -92,11 +92,9 @@ def rhs(phi, U, V, W, *, dx, eps, gamma, delta=0.0, s=1.0, walls=(False, False, 
     return f
 
 
-def _check_scheme(scheme, adjoint=False):
-    ok = (1, 2, 4) if adjoint else (1, 2, 3, 4)
-    if scheme not in ok:
-        raise ValueError(f"scheme must be one of {ok} (1 Euler, 2 RK2, 3 RK3, 4 RK4)"
-                         f"{' for the adjoint' if adjoint else ''}, not {scheme!r}")
+def _check_scheme(scheme):
+    if scheme not in (1, 2, 3, 4):
+        raise ValueError(f"scheme must be 1 (Euler), 2 (RK2), 3 (RK3) or 4 (RK4), not {scheme!r}")
 
 
 def step(phi, U, V, W, *, dx, eps, gamma, dt, nsteps=1, delta=0.0, t0=0.0, scheme=4,
@@ -155,9 +153,8 @@ def rhs_vjp(phi, U, V, W, lam, *, dx, eps, gamma, delta=0.0, s=1.0):
 
 def adjoint_step(phi, U, V, W, lam, *, dx, eps, gamma, dt, delta=0.0, t=0.0, scheme=4,
                  vel_mode=0, vel_T=1.0):
-    """Adjoint of one step at phi_n: returns (lam_n, dU, dV, dW) given lam = dL/dphi_{n+1}
-    (Euler, RK2, RK4)."""
-    _check_scheme(scheme, adjoint=True)
+    """Adjoint of one step at phi_n: returns (lam_n, dU, dV, dW) given lam = dL/dphi_{n+1}."""
+    _check_scheme(scheme)
     phi, U, V, W = map(_f64, (phi, U, V, W))
     lam = _f64(lam).copy()
     ub, vb, wb = (np.zeros_like(phi) for _ in range(3))

@@ -408,39 +408,66 @@ void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int ve
         free(out);
         return;
     }
-    /* Both Runge-Kutta schemes have stage inputs y_1 = phi, y_{s+1} = phi + ca[s] k_s and
-     * phi' = phi + sum_s bw[s] k_s, with k_s = f(y_s, st[s]):
-     *   RK2 (explicit midpoint): ca = {dt/2}, bw = {0, dt}, st = {t, t+dt/2};
-     *   RK4 (classic): ca = {dt/2, dt/2, dt}, bw = {dt/6, dt/3, dt/3, dt/6},
-     *                  st = {t, t+dt/2, t+dt/2, t+dt}. */
-    const int ns = scheme == 2 ? 2 : 4;
-    double st[4] = {t, t + 0.5 * dt, t + 0.5 * dt, t + dt};
-    double ca[3] = {0.5 * dt, 0.5 * dt, dt};
-    double bw[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    /* Explicit Runge-Kutta in Butcher form: y_s = phi + dt sum_{j<s} a[s][j] k_j,
+     * phi' = phi + dt sum_s b[s] k_s, k_s = f(y_s, t + c[s] dt). Reverse: with
+     * kbar_s = dt (b[s] lam' + sum_{i>s} a[i][s] ybar_i) and ybar_s = (df/dy at y_s)^T kbar_s,
+     * phibar = lam' + sum_s ybar_s.
+     *   RK2 (explicit midpoint): a21 = 1/2; b = (0, 1); c = (0, 1/2).
+     *   RK3 (low storage, see the header): a21 = 8/15, a31 = 1/4, a32 = 5/12; b = (1/4, 0, 3/4);
+     *                                      c = (0, 8/15, 2/3).
+     *   RK4 (classic): a21 = a32 = 1/2, a43 = 1; b = (1/6, 1/3, 1/3, 1/6); c = (0, 1/2, 1/2, 1). */
+    double a[4][4] = {{0}}, b[4] = {0}, cs[4] = {0};
+    int ns;
     if (scheme == 2) {
-        bw[0] = 0.0;
-        bw[1] = dt;
+        ns = 2;
+        a[1][0] = 0.5;
+        b[1] = 1.0;
+        cs[1] = 0.5;
+    } else if (scheme == 3) {
+        ns = 3;
+        a[1][0] = 8.0 / 15.0;
+        a[2][0] = 0.25;
+        a[2][1] = 5.0 / 12.0;
+        b[0] = 0.25;
+        b[2] = 0.75;
+        cs[1] = 8.0 / 15.0;
+        cs[2] = 2.0 / 3.0;
+    } else {
+        ns = 4;
+        a[1][0] = a[2][1] = 0.5;
+        a[3][2] = 1.0;
+        b[0] = b[3] = 1.0 / 6.0;
+        b[1] = b[2] = 1.0 / 3.0;
+        cs[1] = cs[2] = 0.5;
+        cs[3] = 1.0;
     }
-    /* recompute the stage inputs of the forward step */
-    double *y[4], *kk[3];
-    for (int s = 0; s < ns; ++s) y[s] = malloc(sizeof(double) * N);
-    for (int s = 0; s < ns - 1; ++s) kk[s] = malloc(sizeof(double) * N);
-    memcpy(y[0], phi, sizeof(double) * N);
-    for (int s = 0; s < ns - 1; ++s) {
-        orc_rhs(g, time_factor(vel_mode, vel_T, st[s]), y[s], U, V, W, kk[s]);
-        for (int64_t c = 0; c < N; ++c) y[s + 1][c] = phi[c] + ca[s] * kk[s][c];
+    /* recompute the stage inputs and slopes of the forward step */
+    double *y[4], *kk[4];
+    for (int s = 0; s < ns; ++s) {
+        y[s] = malloc(sizeof(double) * N);
+        kk[s] = malloc(sizeof(double) * N);
+    }
+    for (int s = 0; s < ns; ++s) {
+        for (int64_t c = 0; c < N; ++c) {
+            double v = phi[c];
+            for (int j = 0; j < s; ++j) v += dt * a[s][j] * kk[j][c];
+            y[s][c] = v;
+        }
+        if (s < ns - 1) /* the last slope enters no stage input */
+            orc_rhs(g, time_factor(vel_mode, vel_T, t + cs[s] * dt), y[s], U, V, W, kk[s]);
     }
     /* reverse sweep over the stages, newest first */
     for (int64_t c = 0; c < N; ++c) out[c] = lam[c];
-    double *ybar_next = NULL; /* ybar of the stage after the current one */
     double *ybar[4];
     for (int s = 0; s < ns; ++s) ybar[s] = calloc(N, sizeof(double));
     for (int s = ns - 1; s >= 0; --s) {
-        for (int64_t c = 0; c < N; ++c)
-            kb[c] = bw[s] * lam[c] + (ybar_next ? ca[s] * ybar_next[c] : 0.0);
-        orc_rhs_vjp(g, time_factor(vel_mode, vel_T, st[s]), y[s], U, V, W, kb, ybar[s], Ubar,
-                    Vbar, Wbar);
-        ybar_next = ybar[s];
+        for (int64_t c = 0; c < N; ++c) {
+            double v = b[s] * lam[c];
+            for (int i = s + 1; i < ns; ++i) v += a[i][s] * ybar[i][c];
+            kb[c] = dt * v;
+        }
+        orc_rhs_vjp(g, time_factor(vel_mode, vel_T, t + cs[s] * dt), y[s], U, V, W, kb, ybar[s],
+                    Ubar, Vbar, Wbar);
     }
     /* every stage input is phi + (something), so phibar collects all the ybar */
     for (int64_t c = 0; c < N; ++c) {
@@ -451,8 +478,8 @@ void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int ve
     for (int s = 0; s < ns; ++s) {
         free(y[s]);
         free(ybar[s]);
+        free(kk[s]);
     }
-    for (int s = 0; s < ns - 1; ++s) free(kk[s]);
     free(kb);
     free(yb);
     free(out);

@@ -68,7 +68,7 @@ def _fd_check(fun, x, v, lam, h):
     return np.sum(lam * (fun(x + h * v) - fun(x - h * v))) / (2 * h)
 
 
-@pytest.mark.parametrize("scheme", [1, 2, 4])
+@pytest.mark.parametrize("scheme", [1, 2, 3, 4])
 def test_adjoint_step_matches_finite_differences(scheme):
     """<lam, (step(phi + h v) - step(phi - h v)) / 2h> == <adjoint(lam), v>, and likewise for
     each face-velocity array, over 16 random directions (FP64)."""
