@@ -134,7 +134,7 @@ pf_status phasefield_step(pf_solver *s, void *phi, const void *u, const void *v,
  * dL/du0 etc. (+=). The stage inputs of the forward step are recomputed from phi_n.
  * Allocates three more field-sized scratch buffers on first use.
  * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_UNSUPPORTED (a handle with
- * walls or the RK3 scheme), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * walls), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);

@@ -68,8 +68,10 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
         cell(ex, ey, ez, gbp, dummy);
         ybar = fma(gbm[ax] - gbp[ax], a.inv_2dx, ybar);
     }
-    if (a.lam_out) a.lam_out[c] = a.lam_base[c] + ybar;
-    if (a.kap_out) a.kap_out[c] = fma(a.ka, ybar, a.kb * a.lamp[c]);
+    // both per-cell operands are read before either store: lam_out may alias lamp
+    const T lb = a.lam_out ? a.lam_base[c] : T(0), lp = a.kap_out ? a.lamp[c] : T(0);
+    if (a.lam_out) a.lam_out[c] = lb + ybar;
+    if (a.kap_out) a.kap_out[c] = fma(a.ka, ybar, a.kb * lp);
 }
 
 // Tiled form of the same stage adjoint: a TX x TY workgroup marches kz planes along z, with

@@ -90,6 +90,35 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         if (e == hipSuccess) e = launch_copy<T>(lam, L, s->N, st);
         return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
     }
+    if (p.scheme == PF_RK3) {
+        // Butcher form of the low-storage RK3: a21 = 8/15, a31 = 1/4, a32 = 5/12, b = (1/4, 0, 3/4),
+        // stage times t, t + 8/15 dt, t + 2/3 dt. Reverse:
+        //   kap3 = dt 3/4 lam';  L = lam' + ybar3;  kap2 = dt a32 ybar3 (b2 = 0);
+        //   kap1 = dt (b1 lam' + a21 ybar2 + a31 ybar3) = dt/4 L + dt 8/15 ybar2   (a31 = b1);
+        //   L += ybar2;  lam_n = L + ybar1
+        constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, z2 = -17.0 / 60.0;
+        static_assert(g1 + z2 == 0.25, "a31 must equal b1 for the folded kap1");
+        T* y2 = (T*)s->ya;
+        T* y3 = (T*)s->yb;
+        T* A = (T*)s->acc;  // u1 + dt z2 k1, the base of y3
+        const double s1 = time_factor(p, t), s2 = time_factor(p, t + g1 * dt),
+                     s3 = time_factor(p, t + (g1 + g2 + z2) * dt);
+        e = run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, phi, y2, A, dt * g1,
+                                                   dt * (g1 + z2), U, V, W), st);
+        if (e == hipSuccess)
+            e = run_stage<T>(s->variant, make_stage<T>(p, s2, y2, A, nullptr, y3, nullptr, dt * g2,
+                                                       0.0, U, V, W), st);
+        if (e == hipSuccess)
+            e = adj(make_adj<T>(p, s3, y3, lam, 0.75 * dt, lam, L, lam, Ka, 0.0, g2 * dt, gU, gV,
+                                gW, U, V, W), st);
+        if (e == hipSuccess)
+            e = adj(make_adj<T>(p, s2, y2, Ka, 1.0, L, L, L, Kb, 0.25 * dt, g1 * dt, gU, gV, gW, U,
+                                V, W), st);
+        if (e == hipSuccess)
+            e = adj(make_adj<T>(p, s1, phi, Kb, 1.0, L, lam, nullptr, nullptr, 0.0, 0.0, gU, gV,
+                                gW, U, V, W), st);
+        return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
+    }
     if (p.scheme == PF_RK2) {
         // phi' = phi + dt k2,  k2 = f(y2, t + dt/2),  y2 = phi + dt/2 k1:
         //   kap2 = dt lam';  ybar2 = (df/dy at y2)^T kap2;  kap1 = dt/2 ybar2;
@@ -159,8 +188,6 @@ extern "C" pf_status phasefield_adjoint_step(pf_solver* s, const void* phi_n, co
     if (!std::isfinite(t_n)) return fail(PF_ERR_INVALID, "t_n is not finite");
     if (wall_mask(s->p) != 0)
         return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint is provided for periodic axes only");
-    if (s->p.scheme == PF_RK3)
-        return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint covers Euler, RK2 and RK4");
     hipStream_t hs = (hipStream_t)hip_stream;
     if (s->p.dtype == PF_F32)
         return adjoint_impl<float>(s, (const float*)phi_n, (const float*)u, (const float*)v,

@@ -50,7 +50,7 @@ struct AdjArgs {
     T kap_scale;       // kap = kap_scale * kap_in
     const T* lam_base; // lam_out = lam_base + ybar
     T* lam_out;
-    const T* lamp;     // lambda' (cotangent of the step output), centre only
+    const T* lamp;     // lambda' (cotangent of the step output), centre only; may alias lam_out
     T* kap_out;        // = kb * lamp + ka * ybar (nullable)
     T kb, ka;
     T* gU;

@@ -40,13 +40,14 @@ def adj_case(seed, shape):
 
 @pytest.mark.parametrize("scheme,shape", [("rk4", (12, 10, 14)), ("rk4", (1, 20, 18)),
                                           ("euler", (9, 11, 7)), ("rk4", (20, 16, 70)),
-                                          ("rk2", (12, 10, 14)), ("rk2", (1, 20, 18))])
+                                          ("rk2", (12, 10, 14)), ("rk2", (1, 20, 18)),
+                                          ("rk3", (12, 10, 14)), ("rk3", (1, 20, 18))])
 def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
     pf = lib
     rng, phi, U, V, W, lam, dx = adj_case(1, shape)
     kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, vel_mode=1, vel_T=0.8)
     ref = oracle.adjoint_step(phi, U, V, W, lam, t=0.1,
-                              scheme={"rk4": 4, "rk2": 2, "euler": 1}[scheme], **kw)
+                              scheme={"rk4": 4, "rk3": 3, "rk2": 2, "euler": 1}[scheme], **kw)
     nz, ny, nx = shape
     s = pf.Solver((nx, ny, nz), scheme=scheme, **kw)
     g = [dev(a) for a in (phi, U, V, W)]
@@ -66,7 +67,8 @@ def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
 
 
 @pytest.mark.parametrize("dtype,shape,scheme", [("f64", (20, 16, 70), "rk4"), ("f32", (33, 9, 65), "rk4"),
-                                                ("f64", (1, 12, 5), "rk4"), ("f64", (20, 16, 70), "rk2")])
+                                                ("f64", (1, 12, 5), "rk4"), ("f64", (20, 16, 70), "rk2"),
+                                                ("f64", (20, 16, 70), "rk3")])
 def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape, scheme):
     """The tiled adjoint stage kernel and the one-thread-per-cell kernel (paired with the
     'global' forward variant) give bit-identical lam and velocity gradients, for every adjoint
@@ -95,17 +97,6 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape, scheme):
     for nm, other in zip(picks[1:], res[1:]):
         for a, b in zip(res[0], other):
             assert torch.equal(a, b), nm
-
-
-def test_adjoint_declines_rk3(lib):
-    pf = lib
-    rng, phi, U, V, W, lam, dx = adj_case(3, (6, 7, 8))
-    s = pf.Solver((8, 7, 6), dx, dx, 1.0, 0.05 * dx, scheme="rk3")
-    g = [dev(a) for a in (phi, U, V, W)]
-    with pytest.raises(pf.PhaseFieldError) as ei:
-        s.adjoint_step(*g, 0.0, dev(lam))
-    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
-    s.close()
 
 
 def test_adjoint_step_fp32_close_to_fp64_oracle(lib):
