@@ -63,6 +63,16 @@ def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
     s.adjoint_step(*g, 0.1, L2)
     torch.cuda.synchronize()
     assert torch.equal(L2, L)
+    # the gradients accumulate onto what the arrays hold; a NULL one is skipped on its own
+    g0 = [rng.standard_normal(shape) * np.abs(b).max() for b in ref[1:]]
+    acc = [dev(x) for x in g0]
+    L3 = dev(lam)
+    s.adjoint_step(*g, 0.1, L3, acc[0], None, acc[2])
+    torch.cuda.synchronize()
+    assert torch.equal(L3, L)
+    assert torch.equal(acc[1], dev(g0[1]))
+    for ax in (0, 2):
+        assert rel_linf(host(acc[ax]) - g0[ax], ref[1 + ax]) <= 1e-12
     s.close()
 
 
