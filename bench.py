@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gcell-updates/s & % HBM peak (fwd, adjoint, batched vs looped) at FP32/FP64 tol"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # dense FP64, MI355X
 # algorithmic words per RK4 cell-update: four per-stage sweeps (6 + 8 + 8 + 6) or two fused
 # two-stage sweeps (6 + 7)
 WORDS_PER_CELL_STEP = {"tiled": 28, "global": 28, "fused": 13}
@@ -115,6 +116,31 @@ def copy_ceiling(st, nbytes=2 ** 31, reps=10):
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / ms / 1e6
+
+
+def velocity_timing(pf, fx, st, n=512, dtype="f32", reps=3):
+    """Velocity synthesis from the roofline workload's 16-mode potential, and its transpose (the
+    coefficient gradient of a face field), one whole library call each (scratch allocation and
+    the closing synchronisation included). Floors: the faces written once (3 words per cell at
+    8 TB/s) and the last contraction's 3M fused multiply-adds per cell at the FP64 peak."""
+    import torch
+    c = fx.roofline512(n, seed=3)
+    phases, coeffs = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in c.modes)
+    M = int(phases.shape[1])
+    p0 = pf.make_params((n, n, n), c.dx, c.eps, 1.0, 1.0, dtype=dtype)
+    with torch.cuda.stream(st):
+        u, v, w = pf.velocity_from_coeffs(p0, phases, coeffs, stream=st)
+        synth = cuda_timer(st, lambda: pf.velocity_from_coeffs(p0, phases, coeffs, stream=st), reps)
+        pf.velocity_coeffs_grad(p0, phases, u, v, w, stream=st)
+        grad = cuda_timer(st, lambda: pf.velocity_coeffs_grad(p0, phases, u, v, w, stream=st), reps)
+    cells = n ** 3
+    e = 8 if dtype == "f64" else 4
+    del u, v, w
+    torch.cuda.empty_cache()
+    return {"grid": n, "modes": M, "dtype": dtype, "synthesis_ms": round(synth, 3),
+            "transpose_ms": round(grad, 3),
+            "hbm_floor_ms": round(3 * e * cells / HBM_PEAK_GBS / 1e6, 3),
+            "fp64_floor_ms": round(2 * 3 * M * cells / FP64_PEAK_TFLOPS / 1e9, 3)}
 
 
 def adjoint_ratio(pf, fx, dtype, st, n=128, reps=10):
@@ -258,7 +284,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the FP64/adjoint/batch extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", metavar="PARTS",
-                    help="comma-separated subset of {adjoint, batch}: run only those "
+                    help="comma-separated subset of {adjoint, batch, velocity}: run only those "
                          "measurements and print their JSON (for profiling them)")
     ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -279,7 +305,7 @@ def main():
     st = torch.cuda.Stream()
     if args.only:
         parts = {x.strip() for x in args.only.split(",") if x.strip()}
-        unknown = parts - {"adjoint", "batch"}
+        unknown = parts - {"adjoint", "batch", "velocity"}
         if unknown:
             print(f"--only: unknown parts {sorted(unknown)}", file=sys.stderr)
             sys.exit(2)
@@ -289,6 +315,9 @@ def main():
             res["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st, reps=20)
         if "batch" in parts:
             res["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
+        if "velocity" in parts:
+            res[f"velocity_{args.n}_{args.dtype}"] = velocity_timing(pf, fx, st, n=args.n,
+                                                                   dtype=args.dtype)
         print(json.dumps(res), flush=True)
         return
     if args.copy_probe:
@@ -358,6 +387,8 @@ def main():
                                            "words_per_cell_step": w3, "kernel": vname3}
         del phi3, u3, v3, w3
         torch.cuda.empty_cache()
+        log("timing velocity synthesis")
+        extras[f"velocity_{n}_{args.dtype}"] = velocity_timing(pf, fx, st, n=n, dtype=args.dtype)
         log("timing adjoint")
         extras["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st)
         extras["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st)

@@ -4,9 +4,9 @@
 // Z_c(m3, z) is evaluated by sum factorisation (contract x, then y, then z) instead of the
 // M^3-term direct sum, and the last contraction is fused with the discrete curl so the edge
 // potential is never stored. All arithmetic is double; the faces are written in the storage
-// type. The transpose runs the same steps backwards: curl^T gathered per edge, then projection
-// onto the 1-D sine tables along x, y and z, each as a plain serial sum per output (fixed
-// order, deterministic).
+// type. The transpose runs the same steps backwards: curl^T gathered per edge and projected
+// onto the x sine tables in one pass, then projected along y and z, each output a plain serial
+// sum (fixed order, deterministic).
 #include <cmath>
 
 #include "pf_cell.h"
@@ -21,23 +21,40 @@ struct VelGeom {
     double dx;
 };
 
-// tab[((axis * 2 + pos) * M + m) * nmax + i] = sin(2 pi (m+1) (i + pos/2) / n_axis + phase)
+// sin(2 pi (m+1) (i + pos/2) / n_axis + phase[axis][m]): mode m along an axis at the nodes
+// (pos 0) or mid-points (pos 1)
+__device__ __forceinline__ double sine_value(const VelGeom& g, const double* phases, int axis,
+                                             int pos, int m, int i)
+{
+    const double off = pos ? 0.5 : 0.0;
+    return sin(2.0 * M_PI * (double)(m + 1) * ((double)i + off) / (double)g.n[axis] +
+               phases[axis * g.M + m]);
+}
+
+// tab[((axis * 2 + pos) * M + m) * nmax + i] = sine_value(axis, pos, m, i), 0 past the axis end
 __global__ void sine_table_kernel(VelGeom g, const double* __restrict__ phases, double* __restrict__ tab)
 {
-    const int total = 6 * g.M * g.nmax;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        const int i = e % g.nmax;
-        const int m = (e / g.nmax) % g.M;
-        const int pos = (e / (g.nmax * g.M)) % 2;
-        const int axis = e / (g.nmax * g.M * 2);
-        const int n = g.n[axis];
-        if (i >= n) {
-            tab[e] = 0.0;
-            continue;
-        }
-        const double off = pos ? 0.5 : 0.0;
-        tab[e] = sin(2.0 * M_PI * (double)(m + 1) * ((double)i + off) / (double)n +
-                     phases[axis * g.M + m]);
+    const size_t total = (size_t)6 * g.M * g.nmax, nm = (size_t)g.nmax * g.M;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.nmax);
+        const int m = (int)((e / g.nmax) % g.M);
+        const int pos = (int)((e / nm) % 2);
+        const int axis = (int)(e / (nm * 2));
+        tab[e] = i < g.n[axis] ? sine_value(g, phases, axis, pos, m, i) : 0.0;
+    }
+}
+
+// The x tables mode-fastest for the projection: xT[(pos * nx + i) * M + m] = sine_value(0, pos, m, i)
+__global__ void sine_table_xT_kernel(VelGeom g, const double* __restrict__ phases, double* __restrict__ xT)
+{
+    const size_t total = (size_t)2 * g.n[0] * g.M, nm = (size_t)g.n[0] * g.M;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int m = (int)(e % g.M);
+        const int i = (int)((e / g.M) % g.n[0]);
+        const int pos = (int)(e / nm);
+        xT[e] = sine_value(g, phases, 0, pos, m, i);
     }
 }
 
@@ -85,90 +102,122 @@ __global__ void contract_y_kernel(VelGeom g, const double* __restrict__ T1,
     }
 }
 
-// A_c at edge (i, j, k) = sum_m3 T2[c][m3][j][i] Z_c(m3, k);  Z_c on the mid-points for c = 2
-__device__ __forceinline__ double edge_pot(const VelGeom& g, const double* T2, const double* tab,
-                                           int c, int i, int j, int k)
+// A_c at edge (i, j, k) = sum_m3 T2[c][m3][j][i] Z_c(m3, k) (Z_c on the mid-points for c = 2),
+// fused with the discrete curl. A thread owns one (i, j) column and KB consecutive planes (the
+// workgroup's plane block): it
+// loads the seven T2 columns its curl needs (A_x, A_y, A_z at (i, j); A_x, A_z at (i, j+1); A_y,
+// A_z at (i+1, j)) once per mode and reuses them for all KB planes, and keeps A_x and A_y one
+// plane further for the k+1 edges. Each edge potential is the same m3-ordered fma chain as a
+// direct per-edge sum.
+template <typename T, int KB>
+__global__ void __launch_bounds__(256) curl_kernel(VelGeom g, const double* __restrict__ T2,
+                                                   const double* __restrict__ tab,
+                                                   T* __restrict__ U, T* __restrict__ V,
+                                                   T* __restrict__ W)
 {
-    const int M = g.M, nx = g.n[0], ny = g.n[1];
-    const double* t2 = T2 + (size_t)c * M * ny * nx + (size_t)j * nx + i;
-    const double* z = table(g, tab, 2, c == 2, 0) + k;
-    double s = 0.0;
-    for (int m3 = 0; m3 < M; ++m3) s = fma(t2[(size_t)m3 * ny * nx], z[(size_t)m3 * g.nmax], s);
-    return s;
-}
-
-template <typename T>
-__global__ void curl_kernel(VelGeom g, const double* __restrict__ T2, const double* __restrict__ tab,
-                            T* __restrict__ U, T* __restrict__ V, T* __restrict__ W)
-{
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const size_t total = (size_t)nx * ny * nz;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2], M = g.M;
+    const size_t ms = (size_t)ny * nx, cs = (size_t)M * ms;
+    const double* zn = table(g, tab, 2, 0, 0);  // Z_x and Z_y: nodes
+    const double* zm = table(g, tab, 2, 1, 0);  // Z_z: mid-points
+    // blockIdx.y picks the plane block, so the table reads below are uniform across the workgroup
+    const int k0 = (int)blockIdx.y * KB;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < ms) {
         const int i = (int)(e % nx);
-        const int j = (int)((e / nx) % ny);
-        const int k = (int)(e / ((size_t)nx * ny));
-        const int ip = wrap1(i + 1, nx), jp = wrap1(j + 1, ny), kp = wrap1(k + 1, nz);
-        const double ax = edge_pot(g, T2, tab, 0, i, j, k);
-        const double ay = edge_pot(g, T2, tab, 1, i, j, k);
-        const double az = edge_pot(g, T2, tab, 2, i, j, k);
-        const double az_jp = edge_pot(g, T2, tab, 2, i, jp, k);
-        const double ay_kp = edge_pot(g, T2, tab, 1, i, j, kp);
-        const double ax_kp = edge_pot(g, T2, tab, 0, i, j, kp);
-        const double az_ip = edge_pot(g, T2, tab, 2, ip, j, k);
-        const double ay_ip = edge_pot(g, T2, tab, 1, ip, j, k);
-        const double ax_jp = edge_pot(g, T2, tab, 0, i, jp, k);
-        U[e] = (T)((((az_jp - az) - ay_kp) + ay) / g.dx);
-        V[e] = (T)((((ax_kp - ax) - az_ip) + az) / g.dx);
-        W[e] = (T)((((ay_ip - ay) - ax_jp) + ax) / g.dx);
+        const int j = (int)(e / nx);
+        const int ip = wrap1(i + 1, nx), jp = wrap1(j + 1, ny);
+        const size_t o = (size_t)j * nx + i, o_jp = (size_t)jp * nx + i, o_ip = (size_t)j * nx + ip;
+        int kq[KB + 1];  // plane of slot q; slots past the grid wrap and are not stored
+#pragma unroll
+        for (int q = 0; q <= KB; ++q) kq[q] = (k0 + q) % nz;
+        double ax[KB + 1], ay[KB + 1], az[KB], ax_jp[KB], az_jp[KB], ay_ip[KB], az_ip[KB];
+#pragma unroll
+        for (int q = 0; q <= KB; ++q) ax[q] = ay[q] = 0.0;
+#pragma unroll
+        for (int q = 0; q < KB; ++q) az[q] = ax_jp[q] = az_jp[q] = ay_ip[q] = az_ip[q] = 0.0;
+        for (int m3 = 0; m3 < M; ++m3) {
+            const double* t = T2 + (size_t)m3 * ms;
+            const double a0 = t[o], a0_jp = t[o_jp];
+            const double a1 = t[cs + o], a1_ip = t[cs + o_ip];
+            const double a2 = t[2 * cs + o], a2_jp = t[2 * cs + o_jp], a2_ip = t[2 * cs + o_ip];
+            const double* zn_m = zn + (size_t)m3 * g.nmax;
+            const double* zm_m = zm + (size_t)m3 * g.nmax;
+#pragma unroll
+            for (int q = 0; q <= KB; ++q) {
+                const double z = zn_m[kq[q]];
+                ax[q] = fma(a0, z, ax[q]);
+                ay[q] = fma(a1, z, ay[q]);
+                if (q < KB) {
+                    ax_jp[q] = fma(a0_jp, z, ax_jp[q]);
+                    ay_ip[q] = fma(a1_ip, z, ay_ip[q]);
+                    const double zz = zm_m[kq[q]];
+                    az[q] = fma(a2, zz, az[q]);
+                    az_jp[q] = fma(a2_jp, zz, az_jp[q]);
+                    az_ip[q] = fma(a2_ip, zz, az_ip[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q)
+            if (k0 + q < nz) {
+                const size_t c = (size_t)(k0 + q) * ms + o;
+                U[c] = (T)((((az_jp[q] - az[q]) - ay[q + 1]) + ay[q]) / g.dx);
+                V[c] = (T)((((ax[q + 1] - ax[q]) - az_ip[q]) + az[q]) / g.dx);
+                W[c] = (T)((((ay_ip[q] - ay[q]) - ax_jp[q]) + ax[q]) / g.dx);
+            }
     }
 }
 
 // ------------------------------------------------------------------ transpose
-// Edge cotangent Abar = curl^T (Ubar, Vbar, Wbar), gathered per edge (c, i, j, k).
-template <typename T>
-__global__ void curl_T_kernel(VelGeom g, const T* __restrict__ gU, const T* __restrict__ gV,
-                              const T* __restrict__ gW, double* __restrict__ Ab)
+// Edge cotangent Abar = curl^T (Ubar, Vbar, Wbar) gathered on the fly and projected onto the x
+// sine tables: P1[c][k][j][m1] = sum_i X_c(m1, i) Abar_c[k][j][i], a serial sum over i per
+// output. A group of MC lanes takes one (k, j) row, one lane per mode of the current chunk of MC
+// modes, so a wave covers 64 / MC rows; the lanes of a group read the same gradient entries and
+// consecutive table entries (mode-fastest table xT).
+template <typename T, int MC>
+__global__ void __launch_bounds__(256) curl_T_project_x_kernel(VelGeom g, const T* __restrict__ gU,
+                                                              const T* __restrict__ gV,
+                                                              const T* __restrict__ gW,
+                                                              const double* __restrict__ xT,
+                                                              double* __restrict__ P1)
 {
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const size_t N = (size_t)nx * ny * nz;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % nx);
-        const int j = (int)((e / nx) % ny);
-        const int k = (int)(e / ((size_t)nx * ny));
-        auto at = [&](int ii, int jj, int kk) -> size_t {
-            return ((size_t)wrap1(kk, nz) * ny + wrap1(jj, ny)) * nx + wrap1(ii, nx);
-        };
-        const double inv = 1.0 / g.dx;
-        // Ax(k) enters V(k-1) with +1 and V(k) with -1; W(j-1) with -1 and W(j) with +1
-        Ab[e] = (((double)gV[at(i, j, k - 1)] - (double)gV[e]) - (double)gW[at(i, j - 1, k)] +
-                 (double)gW[e]) * inv;
-        // Ay(k) enters U(k-1) with -1 and U(k) with +1; W(i-1) with +1 and W(i) with -1
-        Ab[N + e] = ((-(double)gU[at(i, j, k - 1)] + (double)gU[e]) + (double)gW[at(i - 1, j, k)] -
-                     (double)gW[e]) * inv;
-        // Az(j) enters U(j-1) with +1 and U(j) with -1; V(i-1) with -1 and V(i) with +1
-        Ab[2 * N + e] = (((double)gU[at(i, j - 1, k)] - (double)gU[e]) - (double)gV[at(i - 1, j, k)] +
-                         (double)gV[e]) * inv;
-    }
-}
-
-// P1[c][k][j][m1] = sum_i X_c(m1, i) Abar_c[k][j][i]
-__global__ void project_x_kernel(VelGeom g, const double* __restrict__ Ab,
-                                 const double* __restrict__ tab, double* __restrict__ P1)
-{
-    const int M = g.M, nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const size_t total = (size_t)3 * nz * ny * M;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int m1 = (int)(e % M);
-        const size_t row = e / M;  // (c, k, j)
-        const int c = (int)(row / ((size_t)nz * ny));
-        const double* x = table(g, tab, 0, c == 0, m1);
-        const double* ab = Ab + row * nx;
-        double s = 0.0;
-        for (int i = 0; i < nx; ++i) s = fma(x[i], ab[i], s);
-        P1[e] = s;
+    constexpr int RPW = 64 / MC;  // rows per wave
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2], M = g.M;
+    const int lane = threadIdx.x & 63, mm = lane % MC;
+    const long long row = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + lane / MC;
+    if (row >= (long long)nz * ny) return;
+    const int j = (int)(row % ny), k = (int)(row / ny);
+    const int jm = wrap1(j - 1, ny), km = wrap1(k - 1, nz);
+    const size_t o = ((size_t)k * ny + j) * nx;
+    const size_t o_km = ((size_t)km * ny + j) * nx;
+    const size_t o_jm = ((size_t)k * ny + jm) * nx;
+    const double inv = 1.0 / g.dx;
+    const double* xmid = xT + (size_t)nx * M;  // X_x: mid-points; X_y, X_z: nodes (xT itself)
+    for (int m0 = 0; m0 < M; m0 += MC) {
+        const int m = m0 + mm < M ? m0 + mm : M - 1;  // lanes past the last mode idle along
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < nx; ++i) {
+            const int im = i == 0 ? nx - 1 : i - 1;
+            // Ax(k) enters V(k-1) with +1 and V(k) with -1; W(j-1) with -1 and W(j) with +1
+            const double ab0 = ((((double)gV[o_km + i] - (double)gV[o + i]) - (double)gW[o_jm + i]) +
+                                (double)gW[o + i]) * inv;
+            // Ay(k) enters U(k-1) with -1 and U(k) with +1; W(i-1) with +1 and W(i) with -1
+            const double ab1 = ((-(double)gU[o_km + i] + (double)gU[o + i]) + (double)gW[o + im] -
+                                (double)gW[o + i]) * inv;
+            // Az(j) enters U(j-1) with +1 and U(j) with -1; V(i-1) with -1 and V(i) with +1
+            const double ab2 = ((((double)gU[o_jm + i] - (double)gU[o + i]) - (double)gV[o + im]) +
+                                (double)gV[o + i]) * inv;
+            const double xn = xT[(size_t)i * M + m];
+            s0 = fma(xmid[(size_t)i * M + m], ab0, s0);
+            s1 = fma(xn, ab1, s1);
+            s2 = fma(xn, ab2, s2);
+        }
+        if (m0 + mm < M) {
+            P1[(((size_t)0 * nz + k) * ny + j) * M + m] = s0;
+            P1[(((size_t)1 * nz + k) * ny + j) * M + m] = s1;
+            P1[(((size_t)2 * nz + k) * ny + j) * M + m] = s2;
+        }
     }
 }
 
@@ -229,8 +278,7 @@ size_t velocity_scratch_doubles(int nx, int ny, int nz, int M)
 {
     const VelGeom g = geom(nx, ny, nz, 1.0, M);
     const size_t synth = (size_t)3 * M * M * nx + (size_t)3 * M * ny * nx;
-    const size_t N = (size_t)nx * ny * nz;
-    const size_t grad = 3 * N + (size_t)3 * nz * ny * M + (size_t)3 * nz * M * M;
+    const size_t grad = (size_t)2 * nx * M + (size_t)3 * nz * ny * M + (size_t)3 * nz * M * M;
     return table_doubles(g) + (synth > grad ? synth : grad);
 }
 
@@ -255,8 +303,11 @@ hipError_t launch_velocity(int nx, int ny, int nz, double dx, int M, const doubl
                        st, g, coeffs, tab, T1);
     hipLaunchKernelGGL(contract_y_kernel, dim3(blocks_for((size_t)3 * M * ny * nx)), dim3(256), 0,
                        st, g, T1, tab, T2);
-    hipLaunchKernelGGL(curl_kernel<T>, dim3(blocks_for((size_t)nx * ny * nz)), dim3(256), 0, st, g,
-                       T2, tab, U, V, W);
+    constexpr int KB = 8;
+    const size_t cols = (size_t)nx * ny;
+    if ((cols + 255) / 256 > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((curl_kernel<T, KB>), dim3((unsigned)((cols + 255) / 256), (nz + KB - 1) / KB),
+                       dim3(256), 0, st, g, T2, tab, U, V, W);
     return hipGetLastError();
 }
 
@@ -266,16 +317,26 @@ hipError_t launch_velocity_grad(int nx, int ny, int nz, double dx, int M, const 
                                 double* scratch, hipStream_t st)
 {
     const VelGeom g = geom(nx, ny, nz, dx, M);
-    const size_t N = (size_t)nx * ny * nz;
     double* tab = scratch;
-    double* Ab = tab + table_doubles(g);
-    double* P1 = Ab + 3 * N;
+    double* xT = tab + table_doubles(g);
+    double* P1 = xT + (size_t)2 * nx * M;
     double* P2 = P1 + (size_t)3 * nz * ny * M;
     hipLaunchKernelGGL(sine_table_kernel, dim3(blocks_for(table_doubles(g))), dim3(256), 0, st, g,
                        phases, tab);
-    hipLaunchKernelGGL(curl_T_kernel<T>, dim3(blocks_for(N)), dim3(256), 0, st, g, gU, gV, gW, Ab);
-    hipLaunchKernelGGL(project_x_kernel, dim3(blocks_for((size_t)3 * nz * ny * M)), dim3(256), 0,
-                       st, g, Ab, tab, P1);
+    hipLaunchKernelGGL(sine_table_xT_kernel, dim3(blocks_for((size_t)2 * nx * M)), dim3(256), 0, st,
+                       g, phases, xT);
+    const long long rows = (long long)nz * ny;
+    if (M <= 8) {  // 8 rows per wave, 32 per workgroup
+        const long long blocks = (rows + 31) / 32;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((curl_T_project_x_kernel<T, 8>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           g, gU, gV, gW, xT, P1);
+    } else {  // 4 rows per wave, 16 per workgroup
+        const long long blocks = (rows + 15) / 16;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((curl_T_project_x_kernel<T, 16>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           g, gU, gV, gW, xT, P1);
+    }
     hipLaunchKernelGGL(project_y_kernel, dim3(blocks_for((size_t)3 * nz * M * M)), dim3(256), 0,
                        st, g, P1, tab, P2);
     hipLaunchKernelGGL(project_z_kernel, dim3(blocks_for((size_t)3 * M * M * M)), dim3(256), 0, st,
