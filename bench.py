@@ -143,6 +143,35 @@ def velocity_timing(pf, fx, st, n=512, dtype="f32", reps=3):
             "fp64_floor_ms": round(2 * 3 * M * cells / FP64_PEAK_TFLOPS / 1e9, 3)}
 
 
+def vortex_timing(pf, fx, st):
+    """The 2D reversing-vortex workload (64 x 64, FP64, RK4, 2560 steps to t = T): a
+    launch-bound grid of 4096 cells. Times the full run as specified (time-dependent velocity,
+    launched step by step) and, for the launch overhead, the same grid with the velocity held
+    steady, eager and replayed from captured graphs."""
+    import torch
+    c = fx.vortex2d(64)
+    n = c.shape[2]
+    phi0 = torch.tensor(c.phi0, dtype=torch.float64, device="cuda")
+    u, v, w = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (c.U, c.V, c.W))
+    out = {"grid": [n, n, 1], "steps": c.nsteps, "dtype": "f64"}
+    runs = (("cos_us_per_step", dict(vel_mode=1, vel_T=c.vel_T, use_graph=True)),
+            ("steady_eager_us_per_step", dict(use_graph=False)),
+            ("steady_graph_us_per_step", dict(use_graph=True)))
+    for key, kw in runs:
+        s = pf.Solver((n, n, 1), c.dx, c.eps, c.gamma, c.dt, dtype="f64", **kw)
+        with torch.cuda.stream(st):
+            phi = phi0.clone()
+            s.step(phi, u, v, w, nsteps=64, stream=st)
+            phi.copy_(phi0)
+            ms = cuda_timer(st, lambda: s.step(phi, u, v, w, nsteps=c.nsteps, stream=st))
+        if key == "cos_us_per_step":
+            out["e_shape"] = float((phi - phi0).abs().sum()) * c.dx * c.dx
+        out[key] = round(1e3 * ms / c.nsteps, 2)
+        out["variant"] = s.variant_name
+        s.close()
+    return out
+
+
 def adjoint_ratio(pf, fx, dtype, st, n=128, reps=10):
     """Cost of one adjoint step (stage recompute + four reverse stages + velocity gradient) over
     one forward step, on the adjoint workload (128^3, 8-mode field, delta = 1e-6/dx)."""
@@ -284,7 +313,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the FP64/adjoint/batch extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", metavar="PARTS",
-                    help="comma-separated subset of {adjoint, batch, velocity}: run only those "
+                    help="comma-separated subset of {adjoint, batch, velocity, vortex}: run only those "
                          "measurements and print their JSON (for profiling them)")
     ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -305,7 +334,7 @@ def main():
     st = torch.cuda.Stream()
     if args.only:
         parts = {x.strip() for x in args.only.split(",") if x.strip()}
-        unknown = parts - {"adjoint", "batch", "velocity"}
+        unknown = parts - {"adjoint", "batch", "velocity", "vortex"}
         if unknown:
             print(f"--only: unknown parts {sorted(unknown)}", file=sys.stderr)
             sys.exit(2)
@@ -315,6 +344,8 @@ def main():
             res["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st, reps=20)
         if "batch" in parts:
             res["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
+        if "vortex" in parts:
+            res["vortex64_f64"] = vortex_timing(pf, fx, st)
         if "velocity" in parts:
             res[f"velocity_{args.n}_{args.dtype}"] = velocity_timing(pf, fx, st, n=args.n,
                                                                    dtype=args.dtype)
@@ -387,6 +418,8 @@ def main():
                                            "words_per_cell_step": w3, "kernel": vname3}
         del phi3, u3, v3, w3
         torch.cuda.empty_cache()
+        log("timing the 2D vortex")
+        extras["vortex64_f64"] = vortex_timing(pf, fx, st)
         log("timing velocity synthesis")
         extras[f"velocity_{n}_{args.dtype}"] = velocity_timing(pf, fx, st, n=n, dtype=args.dtype)
         log("timing adjoint")

@@ -30,6 +30,102 @@ __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int
     tiled_stage_body<T, TX, TY, BIG, WALLS>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
+// The same stage on a grid of one plane (nz = 1): the z-neighbours of every cell are the cell
+// itself (periodic wrap, or the mirror of a z-wall), so the march's warm-up planes and its
+// plane-to-plane hand-over carry copies of the one plane. This kernel loads the tile with its
+// two-cell halo once and feeds the cell function exactly the values the march would (z-face sum
+// 2 phi, z-face difference and z-gradient zero, both z-faces of q and of W the cell's own), so
+// the two agree bitwise, with one load round and two barriers instead of six march iterations.
+template <typename T, int TX, int TY, bool WALLS>
+__global__ void __launch_bounds__(TX* TY) stage_plane_kernel(StageArgs<T> a, int tiles_x)
+{
+    constexpr int NT = TX * TY;
+    constexpr int PW = TX + 4, PH = TY + 4, PS = PW * PH;
+    constexpr int QXW = TX + 2, QXS = QXW * TY;
+    constexpr int QYS = TX * (TY + 2);
+    constexpr int NL = (PS + NT - 1) / NT;
+    static_assert(NT >= 2 * TX + 2 * TY, "halo ring needs one thread per halo cell");
+    __shared__ T sp[PS];
+    __shared__ T sqx[QXS];
+    __shared__ T sqy[QYS];
+
+    const int b = xcd_tile_order(blockIdx.x, gridDim.x);
+    const int i0 = (b % tiles_x) * TX, j0 = (b / tiles_x) * TY;
+    const int nx = a.nx, ny = a.ny;
+    const bool wx = WALLS && (a.walls & 1), wy = WALLS && (a.walls & 2), wz = WALLS && (a.walls & 4);
+    auto mapx = [&](int v) { return WALLS && wx ? reflectn(v, nx) : wrapn(v, nx); };
+    auto mapy = [&](int v) { return WALLS && wy ? reflectn(v, ny) : wrapn(v, ny); };
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = (i < nx) && (j < ny);
+    const int iw = wrapn(i, nx), jw = wrapn(j, ny);
+    const size_t col = (size_t)jw * nx + iw;
+    const size_t col_xp = (size_t)jw * nx + wrapn(i + 1, nx);
+    const size_t col_yp = (size_t)wrapn(j + 1, ny) * nx + iw;
+
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+        const int e = tid + s * NT;
+        if (e < PS) {
+            const int r = e / PW, c = e - r * PW;
+            sp[e] = a.y[(size_t)mapy(j0 - 2 + r) * nx + mapx(i0 - 2 + c)];
+        }
+    }
+    T u0 = a.U[col], u1 = a.U[col_xp], v0 = a.V[col], v1 = a.V[col_yp], w = a.W[col];
+    if constexpr (WALLS) {  // velocities on wall faces (index 0 of a walled axis)
+        if (wx && iw == 0) u0 = T(0);
+        if (wx && iw == nx - 1) u1 = T(0);
+        if (wy && jw == 0) v0 = T(0);
+        if (wy && jw == ny - 1) v1 = T(0);
+        if (wz) w = T(0);
+    }
+    T b1 = T(0), b2 = T(0);
+    if (a.out1) b1 = a.base1[col];
+    if (a.out2) b2 = a.base2[col];
+    __syncthreads();
+
+    const T inv_2dx = a.inv_2dx, d2 = a.delta2, hg = a.hg;
+    const int o = (ty + 2) * PW + (tx + 2);
+    const T pc = sp[o];
+    const T gx = grad1(sp[o + 1], sp[o - 1], inv_2dx);
+    const T gy = grad1(sp[o + PW], sp[o - PW], inv_2dx);
+    const T gz = grad1(pc, pc, inv_2dx);
+    const T fac = sharpen_factor(pc, gx, gy, gz, d2, hg);
+    sqx[ty * QXW + tx + 1] = fac * gx;
+    sqy[(ty + 1) * TX + tx] = fac * gy;
+    const T qz = fac * gz;
+    // halo ring, assigned as in the march
+    if (tid < 2 * TY) {
+        const int side = tid / TY, r = tid - side * TY;
+        const int h = (r + 2) * PW + (side ? TX + 2 : 1);
+        const T hgx = grad1(sp[h + 1], sp[h - 1], inv_2dx);
+        const T hgy = grad1(sp[h + PW], sp[h - PW], inv_2dx);
+        const T hgz = grad1(sp[h], sp[h], inv_2dx);
+        sqx[r * QXW + (side ? TX + 1 : 0)] = sharpen_factor(sp[h], hgx, hgy, hgz, d2, hg) * hgx;
+    } else if (tid < 2 * TY + 2 * TX) {
+        const int t2 = tid - 2 * TY;
+        const int side = t2 / TX, c = t2 - side * TX;
+        const int h = (side ? TY + 2 : 1) * PW + c + 2;
+        const T hgx = grad1(sp[h + 1], sp[h - 1], inv_2dx);
+        const T hgy = grad1(sp[h + PW], sp[h - PW], inv_2dx);
+        const T hgz = grad1(sp[h], sp[h], inv_2dx);
+        sqy[(side ? TY + 1 : 0) * TX + c] = sharpen_factor(sp[h], hgx, hgy, hgz, d2, hg) * hgy;
+    }
+    __syncthreads();
+    if (!active) return;
+    const T sz = face_sum(pc, pc), dz = face_diff(pc, pc);
+    const T* QX = sqx + ty * QXW + tx;
+    const T* QY = sqy + ty * TX + tx;
+    const T pxm = sp[o - 1], pxp = sp[o + 1], pym = sp[o - PW], pyp = sp[o + PW];
+    const T f = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc), face_sum(pc, pyp),
+                         sz, sz, face_diff(pxm, pc), face_diff(pc, pxp), face_diff(pym, pc),
+                         face_diff(pc, pyp), dz, dz, QX[0], QX[2], QY[0], QY[2 * TX], qz, qz, u0,
+                         u1, v0, v1, w, w, a.nhs, a.ge);
+    if (a.out1) a.out1[col] = fma(a.c1, f, b1);
+    if (a.out2) a.out2[col] = fma(a.c2, f, b2);
+}
+
 // KZ: planes per z-chunk; KZ = 0 chooses it per launch (launch_chunk_planes).
 // FORCE_BIG selects the per-plane descriptor form even for small arrays (it is what arrays of
 // 4 GiB or more take), so that form can be checked against the default one at any size.
@@ -39,8 +135,15 @@ hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
     const int tiles_x = (a.nx + TX - 1) / TX;
     const int tiles_y = (a.ny + TY - 1) / TY;
     if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0) return hipErrorInvalidValue;
-    const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
     const bool walls = a.walls != 0;
+    if (a.nz == 1) {  // one plane: no march (a plane is below 2^28 cells, plain addressing)
+        const long long blocks = (long long)tiles_x * tiles_y;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((walls ? stage_plane_kernel<T, TX, TY, true> : stage_plane_kernel<T, TX, TY, false>),
+                           dim3((unsigned)blocks), dim3(TX * TY), 0, st, a, tiles_x);
+        return hipGetLastError();
+    }
+    const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
     using Kernel = void (*)(StageArgs<T>, int, int, int);
     const Kernel kern = big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true>
                                      : stage_tiled_kernel<T, TX, TY, true, false>)
