@@ -198,6 +198,46 @@ def adjoint_ratio(pf, fx, dtype, st, n=128, reps=10):
             "grid": n, "dtype": dtype}
 
 
+def rollout_timing(pf, fx, dtype, n=128):
+    """The full differentiable rollout of the adjoint workload: 400 steps with a checkpoint
+    every 20, loss 0.5 ||phi_T - target||^2, gradients for phi_0 and the 8^3 x 3 velocity
+    coefficients. Times the forward (velocity synthesis, steps, checkpoint copies) and the
+    backward (segment re-forward, 400 adjoint steps, projection onto the coefficients), on the
+    current stream."""
+    import torch
+    c = fx.adjoint_case(n)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    phases, coeffs = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in c.modes)
+    p0 = pf.make_params((n, n, n), c.dx, c.eps, 1.0, 1.0, dtype=dtype)
+    u, v, w = pf.velocity_from_coeffs(p0, phases, coeffs)
+    torch.cuda.synchronize()
+    fx.set_speed(c, max(float(t.abs().max()) for t in (u, v, w)))
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, delta=c.delta)
+    phi0 = torch.tensor(c.phi0, dtype=tdt, device="cuda").requires_grad_(True)
+    cf = coeffs.clone().requires_grad_(True)
+    target = torch.tensor(c.extra["target"], dtype=tdt, device="cuda")
+    # warm-up: one short rollout (first launches of every kernel, graph capture)
+    w0 = pf.Rollout.apply(phi0, cf, s, phases, 20, 20, 0.0)
+    (0.5 * ((w0 - target) ** 2).sum()).backward()
+    phi0.grad = None
+    cf.grad = None
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    phiT = pf.Rollout.apply(phi0, cf, s, phases, c.nsteps, 20, 0.0)
+    loss = 0.5 * ((phiT - target) ** 2).sum()
+    ev[1].record()
+    loss.backward()
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd, bwd = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    s.close()
+    return {"grid": n, "dtype": dtype, "steps": c.nsteps, "checkpoint_every": 20,
+            "forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
+            "backward_over_forward": round(bwd / fwd, 3),
+            "grad_finite": bool(torch.isfinite(phi0.grad).all() and torch.isfinite(cf.grad).all())}
+
+
 def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
     """The batched driver (default mode, and both modes forced) against a loop of single
     solves (each its own handle, one stream, no graphs), on the same uneven FP32 instances."""
@@ -313,8 +353,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the FP64/adjoint/batch extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", metavar="PARTS",
-                    help="comma-separated subset of {adjoint, batch, velocity, vortex}: run only those "
-                         "measurements and print their JSON (for profiling them)")
+                    help="comma-separated subset of {adjoint, batch, velocity, vortex, rollout}: "
+                         "run only those measurements and print their JSON (for profiling "
+                         "them)")
     ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also run one plain device copy of BYTES bytes (hardware-counter "
@@ -334,7 +375,7 @@ def main():
     st = torch.cuda.Stream()
     if args.only:
         parts = {x.strip() for x in args.only.split(",") if x.strip()}
-        unknown = parts - {"adjoint", "batch", "velocity", "vortex"}
+        unknown = parts - {"adjoint", "batch", "velocity", "vortex", "rollout"}
         if unknown:
             print(f"--only: unknown parts {sorted(unknown)}", file=sys.stderr)
             sys.exit(2)
@@ -344,6 +385,9 @@ def main():
             res["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st, reps=20)
         if "batch" in parts:
             res["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
+        if "rollout" in parts:
+            res["rollout_128_f64"] = rollout_timing(pf, fx, "f64")
+            res["rollout_128_f32"] = rollout_timing(pf, fx, "f32")
         if "vortex" in parts:
             res["vortex64_f64"] = vortex_timing(pf, fx, st)
         if "velocity" in parts:
@@ -425,6 +469,9 @@ def main():
         log("timing adjoint")
         extras["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st)
         extras["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st)
+        log("timing the checkpointed rollout")
+        extras["rollout_128_f64"] = rollout_timing(pf, fx, "f64")
+        extras["rollout_128_f32"] = rollout_timing(pf, fx, "f32")
         log("timing batch vs loop")
         extras["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
     cpu = None
