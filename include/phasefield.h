@@ -48,7 +48,7 @@ extern "C" {
 typedef enum {
     PF_OK = 0,
     PF_ERR_INVALID = 1,     /* bad argument: size, spacing, parameter, null/misaligned pointer */
-    PF_ERR_UNSUPPORTED = 2, /* valid request this build does not provide (e.g. walls in an    */
+    PF_ERR_UNSUPPORTED = 2, /* valid request the library does not provide (e.g. walls in an  */
                             /* adjoint or batched run)                                        */
     PF_ERR_DEVICE = 3,      /* a HIP call failed                                              */
     PF_ERR_OOM = 4,         /* device allocation failed                                       */
