@@ -275,9 +275,18 @@ constexpr long long kFusedMinCellsF64 = 128LL * 128 * 128;
 
 // Default variant before (or without) autotuning, from MI355X measurements at 32^3-640^3, all with
 // the chunk length chosen per launch: the fused sweeps (FP32 on 64x8 tiles unless those pad more
-// columns than 32x16, FP64 on 32x16) and, below the size thresholds, the per-stage kernel.
+// columns than 32x16, FP64 on 32x16) and, below the size thresholds or on one-plane grids, the
+// per-stage kernel.
 int default_stage_variant(int nx, int ny, int nz, int dtype)
 {
+    // one plane: the per-stage launch takes the march-free plane kernel (a fused sweep would march
+    // its warm-up over copies of the same plane: 3-8 x slower at 512^2-4096^2); from 256^2 cells
+    // on 64x8 tiles (fastest at 512^2-4096^2 in both precisions) unless those pad more columns
+    // than 32x4, below that on the per-stage rule's smaller tiles (more workgroups: 64^2 FP64
+    // 14.2 against 15.8 us per step)
+    if (nz == 1)
+        return (long long)nx * ny >= 256LL * 256 && prefer_x64(nx) ? variant_by_name(dtype, "tiled_64x8")
+                                                                   : per_stage_variant(nx, ny, nz, dtype);
     const long long cells = (long long)nx * ny * nz;
     if (dtype == PF_F32)
         return cells >= kFusedMinCellsF32 ? variant_by_name(dtype, prefer_x64(nx) ? "fused_64x8" : "fused_32x16")

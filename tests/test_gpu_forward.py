@@ -313,3 +313,16 @@ def test_autotune_and_persistent_cache(lib, tmp_path, monkeypatch):
     s3 = pf.Solver((40, 40, 40), 1 / 40, 1 / 40, 1.0, 0.1 / 40, dtype="f64")
     assert s3.variant_name == "tiled_32x4x16"
     s3.close()
+
+
+def test_default_variant_on_one_plane_grids(lib):
+    """Grids of one plane take the per-stage (march-free plane) kernel at every size, never a
+    fused sweep; 64x8 tiles from 256^2 cells, the per-stage rule's tiles below."""
+    pf = lib
+    cases = [((1024, 1024, 1), "f32", "tiled_64x8"), ((512, 512, 1), "f64", "tiled_64x8"),
+             ((64, 64, 1), "f64", "tiled_32x4"), ((96, 4000, 1), "f32", "tiled_32x4"),
+             ((1024, 1024, 2), "f32", "fused_64x8")]
+    for n, dtype, want in cases:
+        s = pf.Solver(n, 1.0 / n[0], 1.0 / n[0], 1.0, 0.1 / n[0], dtype=dtype)
+        assert s.variant_name == want, (n, dtype, s.variant_name)
+        s.close()
