@@ -137,6 +137,12 @@ def test_euler_and_cos_reversal_fp64(lib, shape):
         ref = oracle.step(phi, U, V, W, scheme=sch, **kw)
         got = gpu_run(lib, phi, U, V, W, scheme=scheme, **kw)
         assert rel_linf(got, ref) <= TOL64
+        # one plane: the one-launch step equals the per-stage launches of the 'global' variant
+        if shape[0] == 1:
+            names = [lib.phasefield_variant_name(lib.PF_F64, v)
+                     for v in range(lib.phasefield_variant_count(lib.PF_F64))]
+            per_stage = gpu_run(lib, phi, U, V, W, scheme=scheme, variant=names.index("global"), **kw)
+            assert np.array_equal(got, per_stage), scheme
 
 
 @pytest.mark.parametrize("shape", [(16, 20, 24), (1, 40, 33), (9, 70, 5)])
