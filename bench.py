@@ -143,6 +143,31 @@ def velocity_timing(pf, fx, st, n=512, dtype="f32", reps=3):
             "fp64_floor_ms": round(2 * 3 * M * cells / FP64_PEAK_TFLOPS / 1e9, 3)}
 
 
+def deformation_timing(pf, fx, st, dtype, n=256, steps=100):
+    """The 3D deformation workload (256^3, sphere in the reversing deformation field, cos(pi t/T)
+    time factor, eps = dx, gamma = max|u|): throughput of the default variant over `steps` steps
+    from t = 0 (the time-dependent velocity is launched step by step)."""
+    import torch
+    c = fx.deformation3d(n)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    phi = torch.tensor(c.phi0, dtype=tdt, device="cuda")
+    u, v, w = (torch.tensor(a, dtype=tdt, device="cuda") for a in (c.U, c.V, c.W))
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, vel_mode=c.vel_mode,
+                  vel_T=c.vel_T)
+    with torch.cuda.stream(st):
+        s.step(phi, u, v, w, nsteps=4, stream=st)
+        ms = cuda_timer(st, lambda: s.step(phi, u, v, w, t0=0.0, nsteps=steps, stream=st)) / steps
+    name = s.variant_name
+    s.close()
+    cells = n ** 3
+    e = 8 if dtype == "f64" else 4
+    words = WORDS_PER_CELL_STEP[kind(name)]
+    return {"grid": n, "dtype": dtype, "steps": steps, "ms_per_step": round(ms, 4),
+            "gcell_s": round(cells / ms / 1e6, 2),
+            "achieved_gbs": round(words * e * cells / ms / 1e6, 1),
+            "frac_of_8tbs": round(words * e * cells / ms / 1e6 / HBM_PEAK_GBS, 4), "kernel": name}
+
+
 def vortex_timing(pf, fx, st):
     """The 2D reversing-vortex workload (64 x 64, FP64, RK4, 2560 steps to t = T): a
     launch-bound grid of 4096 cells. Times the full run as specified (time-dependent velocity,
@@ -353,7 +378,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the FP64/adjoint/batch extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", metavar="PARTS",
-                    help="comma-separated subset of {adjoint, batch, velocity, vortex, rollout}: "
+                    help="comma-separated subset of {adjoint, batch, velocity, vortex, rollout, "
+                         "deformation}: "
                          "run only those measurements and print their JSON (for profiling "
                          "them)")
     ap.add_argument("--batch-steps", type=int, default=300)
@@ -375,7 +401,7 @@ def main():
     st = torch.cuda.Stream()
     if args.only:
         parts = {x.strip() for x in args.only.split(",") if x.strip()}
-        unknown = parts - {"adjoint", "batch", "velocity", "vortex", "rollout"}
+        unknown = parts - {"adjoint", "batch", "velocity", "vortex", "rollout", "deformation"}
         if unknown:
             print(f"--only: unknown parts {sorted(unknown)}", file=sys.stderr)
             sys.exit(2)
@@ -385,6 +411,9 @@ def main():
             res["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st, reps=20)
         if "batch" in parts:
             res["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
+        if "deformation" in parts:
+            res["deformation256_f64"] = deformation_timing(pf, fx, st, "f64")
+            res["deformation256_f32"] = deformation_timing(pf, fx, st, "f32")
         if "rollout" in parts:
             res["rollout_128_f64"] = rollout_timing(pf, fx, "f64")
             res["rollout_128_f32"] = rollout_timing(pf, fx, "f32")
@@ -462,6 +491,9 @@ def main():
                                            "words_per_cell_step": w3, "kernel": vname3}
         del phi3, u3, v3, w3
         torch.cuda.empty_cache()
+        log("timing the 3D deformation workload")
+        extras["deformation256_f64"] = deformation_timing(pf, fx, st, "f64")
+        extras["deformation256_f32"] = deformation_timing(pf, fx, st, "f32")
         log("timing the 2D vortex")
         extras["vortex64_f64"] = vortex_timing(pf, fx, st)
         log("timing velocity synthesis")
