@@ -271,3 +271,36 @@ def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
         assert torch.equal(g[0], b[0]), p.n[:]
         s.close()
     bs.close()
+
+
+def test_batch_workload_full_size_bitwise(lib):
+    """The batched workload at its full size (96 FP32 instances of 32^3-128^3, seeded drops and
+    8-mode fields, 62.7M cells), in the configuration the benchmark times (default mode, steps
+    replayed from a captured graph): after 10 steps every instance equals its own single solve
+    bit for bit (single solves are checked against the oracle elsewhere)."""
+    pf = lib
+    cases = fx.batch_cases(count=96)
+    st = torch.cuda.Stream()
+    params, fields = [], []
+    for c in cases:
+        n = c.shape[0]
+        phases, coeffs = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in c.modes)
+        p0 = pf.make_params((n, n, n), c.dx, c.eps, 1.0, 1.0, dtype="f32")
+        u, v, w = pf.velocity_from_coeffs(p0, phases, coeffs)
+        torch.cuda.synchronize()
+        fx.set_speed(c, max(float(t.abs().max()) for t in (u, v, w)))
+        params.append(pf.make_params((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype="f32"))
+        fields.append([torch.tensor(c.phi0, dtype=torch.float32, device="cuda"), u, v, w])
+    bs = pf.BatchSolver(params)
+    bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+    with torch.cuda.stream(st):
+        bs.step(*zip(*bf), nsteps=10, stream=st)
+    st.synchronize()
+    bs.close()
+    for p, f, b in zip(params, fields, bf):
+        s = pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype="f32")
+        phi = f[0].clone()
+        s.step(phi, f[1], f[2], f[3], nsteps=10)
+        torch.cuda.synchronize()
+        s.close()
+        assert torch.equal(phi, b[0]), tuple(p.n)
