@@ -184,7 +184,7 @@ template <typename T>
 hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st);  // one thread per cell
 
 // ------------------------------------------------------------------ reduction (reduce.hip)
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 2048;
 template <typename T>
 hipError_t launch_reduce(const T* phi, size_t n, double* partial /*4*kReduceBlocks*/,
                          double* out4 /*device, 4*/, hipStream_t st);
