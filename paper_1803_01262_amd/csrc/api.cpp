@@ -334,7 +334,8 @@ template hipError_t pf::run_stage<double>(int, const StageArgs<double>&, hipStre
 //     S2: yb = phi + dt/2 k2,  acc += dt/3 k2               (k2 = f(ya, t + dt/2))
 //     S3: ya = phi + dt k3,    acc += dt/3 k3               (k3 = f(yb, t + dt/2))
 //     S4: phi = acc + dt/6 k4                               (k4 = f(ya, t + dt))
-//   Euler (Eq. 25): acc = phi + dt f(phi, t); phi = acc.
+//   Euler (Eq. 25): acc = phi + dt f(phi, t); phi = acc (a run of steps alternates phi and acc
+//   instead, enqueue_steps).
 //   RK2, the explicit midpoint rule (Eq. 26):
 //     S1: ya = phi + dt/2 k1;  S2: phi = phi + dt k2   (k2 = f(ya, t + dt/2))
 //   RK3, low storage (Eq. 27), u1 = u0 + dt g1 k1, u2 = u1 + dt (g2 k2 + z2 k1),
@@ -511,7 +512,14 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
     for (int m = 0; m < nsteps; ++m) {
         const double t = t0 + (double)m * p.dt;
         hipError_t e;
-        if (fused) {
+        if (p.scheme == PF_EULER) {
+            // the Euler stage reads cur with its stencil and writes the other buffer of the pair
+            // (phi, acc); no copy per step
+            T* next = cur == phi ? acc : phi;
+            e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), cur, nullptr, cur, nullptr,
+                                                    next, 0.0, p.dt, U, V, W), st);
+            cur = next;
+        } else if (fused) {
             if (m == nsteps - 1 && cur == phi && p.scheme == PF_RK4) {
                 e = enqueue_step_fused<T>(p, variant, phi, phi, acc, ya, U, V, W, yb, t, st);
             } else {
