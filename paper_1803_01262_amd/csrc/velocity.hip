@@ -172,8 +172,10 @@ __global__ void __launch_bounds__(256) curl_kernel(VelGeom g, const double* __re
 // Edge cotangent Abar = curl^T (Ubar, Vbar, Wbar) gathered on the fly and projected onto the x
 // sine tables: P1[c][k][j][m1] = sum_i X_c(m1, i) Abar_c[k][j][i], a serial sum over i per
 // output. A group of MC lanes takes one (k, j) row, one lane per mode of the current chunk of MC
-// modes, so a wave covers 64 / MC rows; the lanes of a group read the same gradient entries and
-// consecutive table entries (mode-fastest table xT).
+// modes, so a wave covers 64 / MC rows. For each run of 64 x-positions the wave first gathers
+// Abar of its rows with one coalesced load per array and row (lane = x-position) into LDS, then
+// every lane adds the run to its three sums; the table is mode-fastest (xT), so a group's table
+// reads are consecutive.
 template <typename T, int MC>
 __global__ void __launch_bounds__(256) curl_T_project_x_kernel(VelGeom g, const T* __restrict__ gU,
                                                               const T* __restrict__ gV,
@@ -182,38 +184,61 @@ __global__ void __launch_bounds__(256) curl_T_project_x_kernel(VelGeom g, const 
                                                               double* __restrict__ P1)
 {
     constexpr int RPW = 64 / MC;  // rows per wave
+    constexpr int RS = 3 * 64 + 1;  // LDS doubles per row (padded: the groups hit distinct banks)
+    __shared__ double sab[4][RPW][RS];
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2], M = g.M;
-    const int lane = threadIdx.x & 63, mm = lane % MC;
-    const long long row = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + lane / MC;
-    if (row >= (long long)nz * ny) return;
-    const int j = (int)(row % ny), k = (int)(row / ny);
-    const int jm = wrap1(j - 1, ny), km = wrap1(k - 1, nz);
-    const size_t o = ((size_t)k * ny + j) * nx;
-    const size_t o_km = ((size_t)km * ny + j) * nx;
-    const size_t o_jm = ((size_t)k * ny + jm) * nx;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / MC, mm = lane % MC;
+    const long long rows = (long long)nz * ny;
+    const long long row0 = ((long long)blockIdx.x * 4 + wave) * RPW;  // first row of this wave
+    const long long row = row0 + grp;                                   // this lane's row
     const double inv = 1.0 / g.dx;
     const double* xmid = xT + (size_t)nx * M;  // X_x: mid-points; X_y, X_z: nodes (xT itself)
+    double* my = sab[wave][0];
     for (int m0 = 0; m0 < M; m0 += MC) {
         const int m = m0 + mm < M ? m0 + mm : M - 1;  // lanes past the last mode idle along
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll 4
-        for (int i = 0; i < nx; ++i) {
-            const int im = i == 0 ? nx - 1 : i - 1;
-            // Ax(k) enters V(k-1) with +1 and V(k) with -1; W(j-1) with -1 and W(j) with +1
-            const double ab0 = ((((double)gV[o_km + i] - (double)gV[o + i]) - (double)gW[o_jm + i]) +
-                                (double)gW[o + i]) * inv;
-            // Ay(k) enters U(k-1) with -1 and U(k) with +1; W(i-1) with +1 and W(i) with -1
-            const double ab1 = ((-(double)gU[o_km + i] + (double)gU[o + i]) + (double)gW[o + im] -
-                                (double)gW[o + i]) * inv;
-            // Az(j) enters U(j-1) with +1 and U(j) with -1; V(i-1) with -1 and V(i) with +1
-            const double ab2 = ((((double)gU[o_jm + i] - (double)gU[o + i]) - (double)gV[o + im]) +
-                                (double)gV[o + i]) * inv;
-            const double xn = xT[(size_t)i * M + m];
-            s0 = fma(xmid[(size_t)i * M + m], ab0, s0);
-            s1 = fma(xn, ab1, s1);
-            s2 = fma(xn, ab2, s2);
+        for (int i0 = 0; i0 < nx; i0 += 64) {
+            const int i = i0 + lane;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                double ab0 = 0.0, ab1 = 0.0, ab2 = 0.0;
+                const long long rr = row0 + r;
+                if (rr < rows && i < nx) {
+                    const int j = (int)(rr % ny), k = (int)(rr / ny);
+                    const int jm = wrap1(j - 1, ny), km = wrap1(k - 1, nz), im = i == 0 ? nx - 1 : i - 1;
+                    const size_t o = ((size_t)k * ny + j) * nx;
+                    const size_t o_km = ((size_t)km * ny + j) * nx;
+                    const size_t o_jm = ((size_t)k * ny + jm) * nx;
+                    // Ax(k) enters V(k-1) with +1 and V(k) with -1; W(j-1) with -1 and W(j) with +1
+                    ab0 = ((((double)gV[o_km + i] - (double)gV[o + i]) - (double)gW[o_jm + i]) +
+                           (double)gW[o + i]) * inv;
+                    // Ay(k) enters U(k-1) with -1 and U(k) with +1; W(i-1) with +1 and W(i) with -1
+                    ab1 = ((-(double)gU[o_km + i] + (double)gU[o + i]) + (double)gW[o + im] -
+                           (double)gW[o + i]) * inv;
+                    // Az(j) enters U(j-1) with +1 and U(j) with -1; V(i-1) with -1 and V(i) with +1
+                    ab2 = ((((double)gU[o_jm + i] - (double)gU[o + i]) - (double)gV[o + im]) +
+                           (double)gV[o + i]) * inv;
+                }
+                my[r * RS + lane] = ab0;
+                my[r * RS + 64 + lane] = ab1;
+                my[r * RS + 128 + lane] = ab2;
+            }
+            __syncthreads();
+            const int cnt = nx - i0 < 64 ? nx - i0 : 64;
+            if (row < rows) {
+                const double* A = my + grp * RS;
+                for (int ii = 0; ii < cnt; ++ii) {
+                    const size_t t = (size_t)(i0 + ii) * M + m;
+                    const double xn = xT[t];
+                    s0 = fma(xmid[t], A[ii], s0);
+                    s1 = fma(xn, A[64 + ii], s1);
+                    s2 = fma(xn, A[128 + ii], s2);
+                }
+            }
+            __syncthreads();
         }
-        if (m0 + mm < M) {
+        if (row < rows && m0 + mm < M) {
+            const int j = (int)(row % ny), k = (int)(row / ny);
             P1[(((size_t)0 * nz + k) * ny + j) * M + m] = s0;
             P1[(((size_t)1 * nz + k) * ny + j) * M + m] = s1;
             P1[(((size_t)2 * nz + k) * ny + j) * M + m] = s2;
