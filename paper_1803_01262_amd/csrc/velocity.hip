@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(256) curl_T_project_x_kernel(VelGeom g, const 
     constexpr int RPW = 64 / MC;  // rows per wave
     constexpr int RS = 3 * 64 + 1;  // LDS doubles per row (padded: the groups hit distinct banks)
     __shared__ double sab[4][RPW][RS];
+    __shared__ double sxt[2][64 * MC];  // the run's x tables for the mode chunk, mid-points / nodes
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2], M = g.M;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / MC, mm = lane % MC;
     const long long rows = (long long)nz * ny;
@@ -223,14 +224,21 @@ __global__ void __launch_bounds__(256) curl_T_project_x_kernel(VelGeom g, const 
                 my[r * RS + 64 + lane] = ab1;
                 my[r * RS + 128 + lane] = ab2;
             }
-            __syncthreads();
             const int cnt = nx - i0 < 64 ? nx - i0 : 64;
+            // the workgroup stages the x tables of this run and mode chunk (padded modes repeat
+            // the last one, as the lanes past it do)
+            for (int e = threadIdx.x; e < 64 * MC; e += 256) {
+                const int ii = e / MC, mc = m0 + e % MC < M ? m0 + e % MC : M - 1;
+                const size_t t = (size_t)(i0 + (ii < cnt ? ii : 0)) * M + mc;
+                sxt[0][e] = xmid[t];
+                sxt[1][e] = xT[t];
+            }
+            __syncthreads();
             if (row < rows) {
                 const double* A = my + grp * RS;
                 for (int ii = 0; ii < cnt; ++ii) {
-                    const size_t t = (size_t)(i0 + ii) * M + m;
-                    const double xn = xT[t];
-                    s0 = fma(xmid[t], A[ii], s0);
+                    const double xn = sxt[1][ii * MC + mm];
+                    s0 = fma(sxt[0][ii * MC + mm], A[ii], s0);
                     s1 = fma(xn, A[64 + ii], s1);
                     s2 = fma(xn, A[128 + ii], s2);
                 }
