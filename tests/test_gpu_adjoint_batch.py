@@ -127,11 +127,12 @@ def test_adjoint_step_fp32_close_to_fp64_oracle(lib):
 
 
 @pytest.mark.parametrize("shape,M", [((12, 10, 14), 3), ((32, 32, 32), 8), ((1, 16, 20), 4),
-                                     ((9, 5, 150), 12), ((6, 7, 70), 20), ((3, 2, 64), 16)])
+                                     ((9, 5, 150), 12), ((6, 7, 70), 20), ((3, 2, 64), 16),
+                                     ((9, 6, 70), 64)])
 def test_velocity_synthesis_matches_oracle(lib, shape, M):
-    """Synthesis (plane blocks of the curl, ragged and shorter than a block) and transpose (one
-    wave per grid row over rows wider and narrower than a wave, mode chunks of 8 and 16, padded
-    and whole) against the oracle."""
+    """Synthesis (plane blocks of the curl, ragged and shorter than a block) and transpose (runs
+    of 64 x-positions, rows wider and narrower than a run, mode chunks of 8 and 16, padded and
+    whole, up to the largest mode count the library takes, 64) against the oracle."""
     pf = lib
     rng = np.random.default_rng(3)
     nz, ny, nx = shape
