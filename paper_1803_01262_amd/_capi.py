@@ -44,10 +44,28 @@ class Report(ctypes.Structure):
                 ("dt_max_scheme", ctypes.c_double), ("dt_over_dtmax", ctypes.c_double)]
 
 
+def _build_once():
+    """Compile the library when nothing is built yet (a fresh tree); a failed build raises."""
+    import importlib.util
+    import sys
+    print(f"{LIB_PATH} is not built; building it now", file=sys.stderr, flush=True)
+    spec = importlib.util.spec_from_file_location(
+        "pf_hip_build", os.path.join(os.path.dirname(os.path.abspath(__file__)), "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.build(verbose=False)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
-                          "python paper_1803_01262_amd/build.py")
+        try:
+            _build_once()
+        except Exception as e:  # no compiler, or the build failed: no fallback
+            raise ImportError(f"{LIB_PATH} is not built and building it failed ({e}); run "
+                              "__graft_entry__.build() or python paper_1803_01262_amd/build.py") from e
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                              "python paper_1803_01262_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, d, i32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32
