@@ -142,11 +142,11 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
                  s4 = time_factor(p, t + dt);
     const int v = s->variant;
     // recompute the stage inputs exactly as the forward step stores them; a fused variant
-    // produces y2 and y3 in one sweep (sweep A with its y_mid output; its accumulator output goes
-    // to y4's buffer, overwritten next)
+    // produces y2 and y3 in one sweep (sweep A with its y_mid output and no accumulator output)
     if (variant_is_fused(p.dtype, v)) {
         FusedArgs<T> a = make_fused<T>(p, false, t, phi, y4, U, V, W, y3);
         a.out_mid = y2;
+        a.out_acc = nullptr;
         e = run_fused_sweep<T>(v, a, false, st);
     } else {
         e = run_stage<T>(v, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt, 0.0, U, V, W), st);
