@@ -186,6 +186,29 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     // handed from plane to plane: gbar_z at k-1 and k, the local term and z-face cotangent of
     // plane k, W at k
     T gz_prev = T(0), gz_cur = T(0), loc_cur = T(0), fbz_cur = T(0), w0 = T(0);
+    // the per-cell operands of iteration k (velocities, gradient and cotangent values of plane k,
+    // the z-face gradient of plane k+1, W at k+1), loaded one iteration ahead so that their
+    // latency spans a whole iteration; each is read only where the iteration uses it, and every
+    // cell's values are written by this thread alone, at the iteration that reads them
+    T nu0, nu1, nv0, nv1, ngu, ngv, ngw, nlb, nlp, nw1;
+    auto load_ops = [&](int k) {
+        const bool out_plane = k >= k0 && k < k1;
+        const bool zplane = k + 1 >= k0 && k + 1 < k1;
+        nw1 = fW.load(wrapz(k + 1, nz), col);
+        const size_t ok = (size_t)(k < 0 ? 0 : k) * plane, ok1 = ok + (k < 0 ? 0 : plane);
+        if (out_plane) {
+            nu0 = fU.load(k, col);
+            nu1 = fU.load(k, col_xp);
+            nv0 = fV.load(k, col);
+            nv1 = fV.load(k, col_yp);
+            if (a.gU) ngu = ldg(a.gU + ok, col);
+            if (a.gV) ngv = ldg(a.gV + ok, col);
+            if (a.lam_out) nlb = ldg(a.lam_base + ok, col);
+            if (a.kap_out) nlp = ldg(a.lamp + ok, col);
+        }
+        if (zplane && a.gW) ngw = ldg(a.gW + ok1, col);
+    };
+    load_ops(k0 - 2);
     // R = (k - k0 + 2) mod 6 fixes the ring slots at compile time; iterations past the chunk end
     // compute on wrapped planes and store nothing
     auto iteration = [&](auto RC, int k) {
@@ -197,22 +220,11 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         fetch(k + 3);
         const bool out_plane = k >= k0 && k < k1;
         const bool zplane = k + 1 >= k0 && k + 1 < k1;  // plane k+1, whose low z-face is done here
-        const int kw1 = wrapz(k + 1, nz);
-        const T w1 = fW.load(kw1, col);
         // element offsets of planes k and k+1, used only where those planes are in the chunk
         const size_t ok = (size_t)(k < 0 ? 0 : k) * plane, ok1 = ok + (k < 0 ? 0 : plane);
-        T u0, u1, v0, v1, gu, gv, gw, lb, lp;
-        if (out_plane) {
-            u0 = fU.load(k, col);
-            u1 = fU.load(k, col_xp);
-            v0 = fV.load(k, col);
-            v1 = fV.load(k, col_yp);
-            if (a.gU) gu = ldg(a.gU + ok, col);
-            if (a.gV) gv = ldg(a.gV + ok, col);
-            if (a.lam_out) lb = ldg(a.lam_base + ok, col);
-            if (a.kap_out) lp = ldg(a.lamp + ok, col);
-        }
-        if (zplane && a.gW) gw = ldg(a.gW + ok1, col);
+        const T w1 = nw1, u0 = nu0, u1 = nu1, v0 = nv0, v1 = nv1, gu = ngu, gv = ngv, gw = ngw,
+                lb = nlb, lp = nlp;
+        load_ops(k + 1);
         __syncthreads();
 
         const T *Y0 = sy + s0 * PS, *Y1 = sy + s1 * PS, *Y2 = sy + s2 * PS;
