@@ -16,7 +16,7 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, bool BIG, bool WALLS>
+template <typename T, int TX, int TY, bool BIG, bool WALLS, bool PREFETCH>
 __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int tiles_x,
                                                              int tiles_y, int kz)
 {
@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int k0 = (b / tiles_y) * kz;
-    tiled_stage_body<T, TX, TY, BIG, WALLS>(a, ti, tj, k0, min(k0 + kz, a.nz));
+    tiled_stage_body<T, TX, TY, BIG, WALLS, PREFETCH>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
 // The same stage on a grid of one plane (nz = 1): the z-neighbours of every cell are the cell
@@ -145,15 +145,32 @@ hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
     }
     const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
     using Kernel = void (*)(StageArgs<T>, int, int, int);
-    const Kernel kern = big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true>
-                                     : stage_tiled_kernel<T, TX, TY, true, false>)
-                            : (walls ? stage_tiled_kernel<T, TX, TY, false, true>
-                                     : stage_tiled_kernel<T, TX, TY, false, false>);
+    // chunks of kPrefetchPlanes planes or more take the form that loads the per-cell operands one
+    // iteration ahead
+    constexpr int kPrefetchPlanes = 48;
+    auto pick = [&](bool prefetch) -> Kernel {
+        if (prefetch)
+            return big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true, true>
+                                : stage_tiled_kernel<T, TX, TY, true, false, true>)
+                       : (walls ? stage_tiled_kernel<T, TX, TY, false, true, true>
+                                : stage_tiled_kernel<T, TX, TY, false, false, true>);
+        return big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true, false>
+                            : stage_tiled_kernel<T, TX, TY, true, false, false>)
+                   : (walls ? stage_tiled_kernel<T, TX, TY, false, true, false>
+                            : stage_tiled_kernel<T, TX, TY, false, false, false>);
+    };
     int kz = KZ;
-    if (KZ == 0) {
-        kz = launch_chunk_planes((const void*)kern, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
+    bool prefetch = KZ >= kPrefetchPlanes;
+    if (KZ == 0) {  // the chunk the prefetching form would take (its own occupancy), if long
+        kz = launch_chunk_planes((const void*)pick(true), TX * TY, (long long)tiles_x * tiles_y,
+                                 a.nz, 1);
+        prefetch = kz >= kPrefetchPlanes;
+        if (!prefetch)
+            kz = launch_chunk_planes((const void*)pick(false), TX * TY,
+                                     (long long)tiles_x * tiles_y, a.nz, 1);
         if (kz <= 0) return hipErrorInvalidDevice;
     }
+    const Kernel kern = pick(prefetch);
     const long long blocks = (long long)tiles_x * tiles_y * ((a.nz + kz - 1) / kz);
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
