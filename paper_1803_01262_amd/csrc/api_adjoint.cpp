@@ -141,20 +141,24 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     const double s1 = time_factor(p, t), s2 = time_factor(p, t + 0.5 * dt),
                  s4 = time_factor(p, t + dt);
     const int v = s->variant;
-    // recompute the stage inputs exactly as the forward step stores them; a fused variant
-    // produces y2 and y3 in one sweep (sweep A with its y_mid output and no accumulator output)
-    if (variant_is_fused(p.dtype, v)) {
+    // recompute the stage inputs exactly as the forward step stores them (every variant rounds
+    // alike). A fused FP32 variant produces y2 and y3 in one sweep (sweep A with its y_mid output
+    // and no accumulator output); in FP64 three per-stage launches on 64x8 tiles are faster at
+    // 128^3-320^3 (at 128^3 0.244 against 0.261 ms per adjoint step).
+    const bool fused_rc = variant_is_fused(p.dtype, v) && p.dtype == PF_F32;
+    const int vs = variant_is_fused(p.dtype, v) && !fused_rc ? stage_variant_index(p.dtype, "tiled_64x8") : v;
+    if (fused_rc) {
         FusedArgs<T> a = make_fused<T>(p, false, t, phi, y4, U, V, W, y3);
         a.out_mid = y2;
         a.out_acc = nullptr;
         e = run_fused_sweep<T>(v, a, false, st);
     } else {
-        e = run_stage<T>(v, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt, 0.0, U, V, W), st);
+        e = run_stage<T>(vs, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt, 0.0, U, V, W), st);
         if (e == hipSuccess)
-            e = run_stage<T>(v, make_stage<T>(p, s2, y2, phi, nullptr, y3, nullptr, 0.5 * dt, 0.0, U, V, W), st);
+            e = run_stage<T>(vs, make_stage<T>(p, s2, y2, phi, nullptr, y3, nullptr, 0.5 * dt, 0.0, U, V, W), st);
     }
     if (e == hipSuccess)
-        e = run_stage<T>(v, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W), st);
+        e = run_stage<T>(vs, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W), st);
     // reverse stages
     if (e == hipSuccess)
         e = adj(make_adj<T>(p, s4, y4, lam, dt / 6.0, lam, L, lam, Ka, dt / 3.0,

@@ -146,6 +146,8 @@ bool variant_is_fused(int dtype, int v);
 int default_stage_variant(int nx, int ny, int nz, int dtype);
 // The per-stage variant that single stages of a fused solver run on (adjoint recompute, Euler).
 int per_stage_variant(int nx, int ny, int nz, int dtype);
+// Index of the variant of that name (0 if there is none).
+int stage_variant_index(int dtype, const char* name);
 
 // ------------------------------------------------------------------ batched stages (batch.hip)
 // Per-instance arguments of one sweep (per-stage mode: StageArgs, fused mode: FusedArgs), and the

@@ -278,6 +278,8 @@ static int variant_by_name(int dtype, const char* name)
     return 0;
 }
 
+int stage_variant_index(int dtype, const char* name) { return variant_by_name(dtype, name); }
+
 // 64-wide tiles unless they pad more columns than 32-wide ones.
 static bool prefer_x64(int nx)
 {
