@@ -291,6 +291,7 @@ static bool prefer_x64(int nx)
 // to 96^3 and ties at 128^3).
 constexpr long long kFusedMinCellsF32 = 80LL * 80 * 80;
 constexpr long long kFusedMinCellsF64 = 128LL * 128 * 128;
+constexpr long long kX64MinCellsF32 = 256LL * 256 * 256;
 
 // Default variant before (or without) autotuning, from MI355X measurements at 32^3-640^3, all with
 // the chunk length chosen per launch: the fused sweeps (FP32 on 64x8 tiles unless those pad more
@@ -307,9 +308,13 @@ int default_stage_variant(int nx, int ny, int nz, int dtype)
         return (long long)nx * ny >= 256LL * 256 && prefer_x64(nx) ? variant_by_name(dtype, "tiled_64x8")
                                                                    : per_stage_variant(nx, ny, nz, dtype);
     const long long cells = (long long)nx * ny * nz;
+    // FP32 fused tiles: 64x8 from 256^3 cells (512^3: 1.87 against 2.09 ms) unless they pad more
+    // columns than 32x16; 32x16 below (128^3 and 192^3: 2-3 % faster, medians of four runs)
     if (dtype == PF_F32)
-        return cells >= kFusedMinCellsF32 ? variant_by_name(dtype, prefer_x64(nx) ? "fused_64x8" : "fused_32x16")
-                                          : per_stage_variant(nx, ny, nz, dtype);
+        return cells >= kFusedMinCellsF32
+                   ? variant_by_name(dtype, cells >= kX64MinCellsF32 && prefer_x64(nx) ? "fused_64x8"
+                                                                                     : "fused_32x16")
+                   : per_stage_variant(nx, ny, nz, dtype);
     return cells >= kFusedMinCellsF64 ? variant_by_name(dtype, "fused_32x16")
                                       : per_stage_variant(nx, ny, nz, dtype);
 }

@@ -323,11 +323,12 @@ def test_autotune_and_persistent_cache(lib, tmp_path, monkeypatch):
 
 def test_default_variant_on_one_plane_grids(lib):
     """Grids of one plane take the per-stage (march-free plane) kernel at every size, never a
-    fused sweep; 64x8 tiles from 256^2 cells, the per-stage rule's tiles below."""
+    fused sweep; 64x8 tiles from 256^2 cells, the per-stage rule's tiles below. Thicker FP32 grids
+    take the fused sweeps, on 32x16 tiles below 256^3 cells and 64x8 from there."""
     pf = lib
     cases = [((1024, 1024, 1), "f32", "tiled_64x8"), ((512, 512, 1), "f64", "tiled_64x8"),
              ((64, 64, 1), "f64", "tiled_32x4"), ((96, 4000, 1), "f32", "tiled_32x4"),
-             ((1024, 1024, 2), "f32", "fused_64x8")]
+             ((1024, 1024, 2), "f32", "fused_32x16"), ((256, 256, 256), "f32", "fused_64x8")]
     for n, dtype, want in cases:
         s = pf.Solver(n, 1.0 / n[0], 1.0 / n[0], 1.0, 0.1 / n[0], dtype=dtype)
         assert s.variant_name == want, (n, dtype, s.variant_name)
