@@ -66,7 +66,18 @@ def _l():
                                           p, p, p, p]
         _lib.orc_velocity_from_coeffs.argtypes = [gp, ctypes.c_int, p, p, p, p, p]
         _lib.orc_velocity_from_coeffs_T.argtypes = [gp, ctypes.c_int, p, p, p, p, p]
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib.orc_max_threads.restype = ctypes.c_int
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads the oracle's loops use from now on."""
+    _l().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_l().orc_max_threads())
 
 
 def _f64(a) -> np.ndarray:

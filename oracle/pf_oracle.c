@@ -42,6 +42,7 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -89,6 +90,10 @@ static inline int low_face_is_wall(const orc_grid *g, int64_t i, int64_t j, int6
 {
     return g->wall[a] && (a == 0 ? i : (a == 1 ? j : k)) == 0;
 }
+
+/* Threads of the OpenMP loops (for timing the oracle on a stated number of cores). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* Steps 1-3 of the recipe: central gradient, unit normal and sharpening product at centres.
  * Fills gr[3N] (gradient), nrm[3N] (normal), q[3N] = phi(1-phi) n. */
