@@ -39,6 +39,7 @@
 #ifndef PHASEFIELD_H
 #define PHASEFIELD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -218,6 +219,13 @@ pf_status phasefield_batch_step(pf_batch *b, void *const *phi, const void *const
                                 int32_t nsteps, void *hip_stream);
 
 pf_status phasefield_batch_destroy(pf_batch *b);
+
+/* Copy `bytes` bytes (a multiple of 4) from src to dst, both device pointers, asynchronously
+ * on hip_stream: the library's streaming copy (16-byte pieces, four in flight per thread, when
+ * both pointers are 16-byte aligned), which also ends odd step counts of the alternating
+ * schedules. It serves as the measured bandwidth reference of a plain read-plus-write stream.
+ * The ranges must not overlap. Errors: PF_ERR_INVALID (null pointer, size), PF_ERR_DEVICE. */
+pf_status phasefield_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 /* Description of the last error on the calling thread (empty string if none); valid until
  * the next library call on that thread. */

@@ -87,6 +87,7 @@ def _load():
         "phasefield_batch_step": (i32, [vp, P(vp), P(vp), P(vp), P(vp), P(d), i32, vp]),
         "phasefield_batch_destroy": (i32, [vp]),
         "phasefield_last_error": (ctypes.c_char_p, []),
+        "phasefield_device_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -103,7 +104,7 @@ EXPORTED = ("phasefield_default_params", "phasefield_check_params", "phasefield_
             "phasefield_velocity_coeffs_grad", "phasefield_variant_count",
             "phasefield_variant_name", "phasefield_autotune", "phasefield_solver_variant",
             "phasefield_batch_create", "phasefield_batch_step", "phasefield_batch_destroy",
-            "phasefield_last_error")
+            "phasefield_last_error", "phasefield_device_copy")
 
 
 def _check(status: int) -> None:
@@ -274,6 +275,15 @@ def phasefield_batch_step(h, params_list, phis, us, vs, ws, t0s=None, nsteps=1, 
 
 def phasefield_batch_destroy(h) -> None:
     _check(lib.phasefield_batch_destroy(h))
+
+
+def phasefield_device_copy(dst, src, stream=None) -> None:
+    """dst <- src (same dtype and size, contiguous GPU tensors) with the library's copy."""
+    if dst.dtype != src.dtype or dst.numel() != src.numel():
+        raise ValueError("dst and src must have the same dtype and size")
+    nbytes = src.numel() * src.element_size()
+    _check(lib.phasefield_device_copy(_ptr(dst, name="dst"), _ptr(src, name="src"), nbytes,
+                                      _stream(stream)))
 
 
 def phasefield_last_error() -> str:

@@ -83,24 +83,42 @@ __device__ __forceinline__ T adj_face(T kap_lo, T kap_hi, T inv_dx)
     return (kap_lo - kap_hi) * inv_dx;
 }
 
+// 1 / sqrt(|g|^2 + delta^2) for the transpose: as inv_mag, but 0 wherever the argument is below
+// the smallest normal number. The forward's clamp gives such a cell a finite but huge r (up to
+// 2^63), harmless there because the sharpening product multiplies it by phi (1 - phi) ~ |g| dx;
+// the transpose would multiply it by the cotangent, so r = 0 instead: the normal and its
+// derivative vanish, as for a flat cell (g = 0) in FP64.
+__device__ __forceinline__ float inv_mag_adj(float gx, float gy, float gz, float delta2)
+{
+    const float m2 = fmaf(gx, gx, fmaf(gy, gy, fmaf(gz, gz, delta2)));
+    return m2 >= 1.17549435e-38f ? __builtin_amdgcn_rsqf(m2) : 0.0f;
+}
+__device__ __forceinline__ double inv_mag_adj(double gx, double gy, double gz, double delta2)
+{
+    return inv_mag(gx, gy, gz, delta2);
+}
+
 // Per-cell part of the transpose: given the stage input p and central gradient g at a cell and
 // the cotangents qb of its sharpening product (qb_a = -gamma/2 (Fbar_a[low] + Fbar_a[high])),
 // return gbar = (dq/dg)^T qb through n = g r, r = (|g|^2 + delta^2)^(-1/2), and the local term
-// (1 - 2p)(n . qb) of d(p(1-p))/dp.
+// (1 - 2p)(n . qb) of d(p(1-p))/dp. With nbar = p (1 - p) qb,
+//   gbar_b = sum_a (r delta_ab - g_a g_b r^3) nbar_a = r (nbar_b - n_b (n . nbar)),
+// written with n = g r so that r^3 is never formed (it overflows FP32 where |g| is tiny).
 template <typename T>
 __device__ __forceinline__ T adj_cell(T p, const T g[3], const T qb[3], T delta2, T gb[3])
 {
-    const T r = inv_mag(g[0], g[1], g[2], delta2);
+    const T r = inv_mag_adj(g[0], g[1], g[2], delta2);
     const T w = p * (T(1) - p);
-    T nq = T(0), gn = T(0);
+    T n[3];
+    T nq = T(0);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        nq = fma(g[b] * r, qb[b], nq);
-        gn = fma(g[b], w * qb[b], gn);
+        n[b] = g[b] * r;
+        nq = fma(n[b], qb[b], nq);
     }
-    const T r3gn = r * r * r * gn;
+    const T wnq = w * nq;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) gb[b] = r * (w * qb[b]) - g[b] * r3gn;
+    for (int b = 0; b < 3; ++b) gb[b] = r * fma(-n[b], wnq, w * qb[b]);
     return (T(1) - T(2) * p) * nq;
 }
 
