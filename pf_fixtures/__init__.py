@@ -332,11 +332,12 @@ def batch_cases(count: int = 96, seed: int = 4, nsteps: int = 300, sizes=BATCH_S
 def adjoint_case(n: int = 128, seed: int = 5, nsteps: int = 400) -> Case:
     """Adjoint workload: drop of R = 0.2 at (0.4, 0.45, 0.5) carried by a seeded 8-mode field
     for nsteps; target = drop of R = 0.2 at the centre; eps = dx, gamma = max|u|;
-    |grad phi| regulariser delta = 1e-6 / dx."""
+    |grad phi| regulariser delta = 1e-3 / dx (small against the largest interface gradient
+    1 / (4 eps), and large enough that the FP32 adjoint is well conditioned where phi is flat)."""
     rng = np.random.default_rng(seed)
     dx = 1.0 / n
     phases, coeffs = random_modes(rng, 8, n)
     phi0 = drops_ic((n, n, n), dx, [(0.4, 0.45, 0.5)], [0.2], dx)
     target = drops_ic((n, n, n), dx, [(0.5, 0.5, 0.5)], [0.2], dx)
     return Case("adjoint", (n, n, n), dx, dx, 0.0, 0.0, nsteps, phi0, modes=(phases, coeffs),
-                delta=1e-6 / dx, extra={"gamma_over_u": 1.0, "target": target})
+                delta=1e-3 / dx, extra={"gamma_over_u": 1.0, "target": target})

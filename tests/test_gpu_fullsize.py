@@ -143,15 +143,13 @@ def test_4gib_fields_switch_to_per_plane_addressing(lib):
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-3)])
 def test_adjoint_workload_full_grid(lib, dtype, tol):
-    """The adjoint workload at its full size (128^3, 8-mode field, delta = 1e-6/dx): one adjoint
+    """The adjoint workload at its full size (128^3, 8-mode field, delta = 1e-3/dx): one adjoint
     step in the configuration the benchmark times (default variant: fused sweeps recompute the
     stage inputs, tiled reverse stages) against the oracle's FP64 adjoint on every cell, for
-    lambda and the three face-velocity gradients. FP32 storage against the FP64 oracle at 1e-3,
-    as in the small FP32 case. Far from the drop phi is flat to within the regulariser, where the
-    transpose of the normal divides by |grad phi|_delta ~ delta, so the bar is measured on the
-    oracle itself, as for the other ill-conditioned runs: max(the fixed bar, 10 x the change of
-    the oracle's output when phi is scaled by 1 + u (seeded noise), u the storage precision's
-    unit roundoff: 1e-16 in FP64, 2^-24 in FP32)."""
+    lambda and the three face-velocity gradients, at the fixed bars: 1e-12 in FP64, and 1e-3 for
+    FP32 storage against the FP64 oracle. With this delta the problem is well conditioned: the
+    oracle's own output moves by about 2e-14 (FP64) and 9e-6 (FP32) when phi is scaled by
+    1 + u (seeded noise, u the storage's unit roundoff); the test prints that response."""
     pf = lib
     c = fx.adjoint_case(128)
     U, V, W = oracle.velocity_from_coeffs(c.shape, dx=c.dx, phases=c.modes[0], coeffs=c.modes[1])
@@ -180,9 +178,9 @@ def test_adjoint_workload_full_grid(lib, dtype, tol):
                                 gamma=c.gamma, dt=c.dt, delta=c.delta)
     for k, (got, want) in enumerate(zip([L] + grads, ref)):
         got = got.cpu().numpy().astype(np.float64)
+        assert np.isfinite(got).all(), k
         scale = np.abs(want).max()
         err = float(np.abs(got - want).max() / scale)
         resp = float(np.abs(ref_p[k] - want).max() / scale)
-        bar = max(tol, 10 * resp)
-        print("output", k, "error", err, "oracle response", resp, "bar", bar, flush=True)
-        assert err <= bar, (k, err, bar)
+        print("output", k, "error", err, "oracle response to unit roundoff", resp, flush=True)
+        assert err <= tol, (k, err, tol)
