@@ -26,10 +26,14 @@ sys.path.insert(0, ROOT)
 METRIC = "Gcell-updates/s & % HBM peak (fwd, adjoint, batched vs looped) at FP32/FP64 tol"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6  # dense FP64, MI355X
-# algorithmic words per RK4 cell-update: four per-stage sweeps (6 + 8 + 8 + 6) or two fused
-# two-stage sweeps (6 + 7)
+# Algorithmic words per RK4 cell-update (the roofline's unit): the fixed-buffer stage schedule
+# moves 6 + 8 + 8 + 6 = 28 words (stage input, face velocities, bases and accumulator in; stage
+# value and accumulator out). The fused two-stage sweeps keep the middle stage value on chip and
+# move 6 + 7 = 13 words, which is reported beside it as the fused minimum.
+ALG_WORDS = 28
 WORDS_PER_CELL_STEP = {"tiled": 28, "global": 28, "fused": 13}
 LAUNCHES_PER_STEP = {"tiled": 4, "global": 4, "fused": 2}
+GRAPH_STEPS = 8  # steps per captured graph in the library (steady velocity)
 # the explicit midpoint rule: per-stage S1 reads phi, U, V, W and writes ya; S2 reads ya, phi, U,
 # V, W and writes phi. Fused: one sweep reads phi, U, V, W and writes the new phi.
 RK2_WORDS_PER_CELL_STEP = {"tiled": 11, "global": 11, "fused": 5}
@@ -95,6 +99,12 @@ def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, v
         best, times = s.autotune(reps=3, stream=st)
         tuned = {k: round(t, 4) for k, t in times.items()}
     with torch.cuda.stream(st):
+        # capture and instantiate the step graph before any timed step: one graph-length run,
+        # then phi restored in place (the graph is keyed on the buffer addresses)
+        keep = phi.clone()
+        s.step(phi, u, v, w, nsteps=GRAPH_STEPS, stream=st)
+        phi.copy_(keep)
+        del keep
         if warmup:
             s.step(phi, u, v, w, nsteps=warmup, stream=st)
         m0 = s.reduce(phi, stream=st)
@@ -105,17 +115,21 @@ def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, v
     return ms, name, tuned, m0, m1
 
 
-def copy_ceiling(st, nbytes=2 ** 31, reps=10):
-    """Read + write bandwidth of a plain device copy of nbytes (4-byte elements), GB/s."""
+def copy_ceiling(pf, st, nbytes=2 ** 31, reps=10):
+    """Read + write bandwidth (GB/s) of a plain device copy of nbytes: torch's copy of float32
+    elements and the library's 16-byte streaming copy (phasefield_device_copy)."""
     import torch
     with torch.cuda.stream(st):
-        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
-        ms = cuda_timer(st, lambda: b.copy_(a), reps)
+        ms_t = cuda_timer(st, lambda: b.copy_(a), reps)
+        pf.phasefield_device_copy(b, a, stream=st)
+        ms_l = cuda_timer(st, lambda: pf.phasefield_device_copy(b, a, stream=st), reps)
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / ms / 1e6
+    return {"torch_copy_gbs": round(2 * nbytes / ms_t / 1e6, 1),
+            "library_copy_gbs": round(2 * nbytes / ms_l / 1e6, 1)}
 
 
 def velocity_timing(pf, fx, st, n=512, dtype="f32", reps=3):
@@ -146,7 +160,7 @@ def velocity_timing(pf, fx, st, n=512, dtype="f32", reps=3):
 def deformation_timing(pf, fx, st, dtype, n=256, steps=100):
     """The 3D deformation workload (256^3, sphere in the reversing deformation field, cos(pi t/T)
     time factor, eps = dx, gamma = max|u|): throughput of the default variant over `steps` steps
-    from t = 0 (the time-dependent velocity is launched step by step)."""
+    from t = 0 (the loop replayed from one captured graph)."""
     import torch
     c = fx.deformation3d(n)
     tdt = torch.float32 if dtype == "f32" else torch.float64
@@ -155,7 +169,11 @@ def deformation_timing(pf, fx, st, dtype, n=256, steps=100):
     s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, vel_mode=c.vel_mode,
                   vel_T=c.vel_T)
     with torch.cuda.stream(st):
-        s.step(phi, u, v, w, nsteps=4, stream=st)
+        # the same loop once untimed (its whole-loop graph is captured there), phi restored
+        keep = phi.clone()
+        s.step(phi, u, v, w, t0=0.0, nsteps=steps, stream=st)
+        phi.copy_(keep)
+        del keep
         ms = cuda_timer(st, lambda: s.step(phi, u, v, w, t0=0.0, nsteps=steps, stream=st)) / steps
     name = s.variant_name
     s.close()
@@ -164,15 +182,18 @@ def deformation_timing(pf, fx, st, dtype, n=256, steps=100):
     words = WORDS_PER_CELL_STEP[kind(name)]
     return {"grid": n, "dtype": dtype, "steps": steps, "ms_per_step": round(ms, 4),
             "gcell_s": round(cells / ms / 1e6, 2),
-            "achieved_gbs": round(words * e * cells / ms / 1e6, 1),
-            "frac_of_8tbs": round(words * e * cells / ms / 1e6 / HBM_PEAK_GBS, 4), "kernel": name}
+            "achieved_gbs": round(ALG_WORDS * e * cells / ms / 1e6, 1),
+            "frac_of_8tbs": round(ALG_WORDS * e * cells / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "moved_words_per_cell_update": words,
+            "moved_frac_of_8tbs": round(words * e * cells / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "kernel": name}
 
 
 def vortex_timing(pf, fx, st):
-    """The 2D reversing-vortex workload (64 x 64, FP64, RK4, 2560 steps to t = T): a
+    """The 2D reversing-vortex workload (64 x 64, FP64, RK4, 2556 steps to t = T): a
     launch-bound grid of 4096 cells. Times the full run as specified (time-dependent velocity,
-    launched step by step) and, for the launch overhead, the same grid with the velocity held
-    steady, eager and replayed from captured graphs."""
+    the whole loop replayed from one captured graph) and, for the launch overhead, the same grid
+    with the velocity held steady, eager and replayed from 8-step graphs."""
     import torch
     c = fx.vortex2d(64)
     n = c.shape[2]
@@ -185,8 +206,9 @@ def vortex_timing(pf, fx, st):
     for key, kw in runs:
         s = pf.Solver((n, n, 1), c.dx, c.eps, c.gamma, c.dt, dtype="f64", **kw)
         with torch.cuda.stream(st):
+            # the same loop once untimed (graphs are captured there), phi restored in place
             phi = phi0.clone()
-            s.step(phi, u, v, w, nsteps=64, stream=st)
+            s.step(phi, u, v, w, nsteps=c.nsteps, stream=st)
             phi.copy_(phi0)
             ms = cuda_timer(st, lambda: s.step(phi, u, v, w, nsteps=c.nsteps, stream=st))
         if key == "cos_us_per_step":
@@ -199,7 +221,7 @@ def vortex_timing(pf, fx, st):
 
 def adjoint_ratio(pf, fx, dtype, st, n=128, reps=10):
     """Cost of one adjoint step (stage recompute + four reverse stages + velocity gradient) over
-    one forward step, on the adjoint workload (128^3, 8-mode field, delta = 1e-6/dx)."""
+    one forward step, on the adjoint workload (128^3, 8-mode field, delta = 1e-3/dx)."""
     import torch
     c = fx.adjoint_case(n)
     tdt = torch.float32 if dtype == "f32" else torch.float64
@@ -330,28 +352,53 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
             "speedup_vs_looped_graph": round(t_gloop / t_batch, 2)}
 
 
-def cpu_baseline(fx, n=128, budget_s=12.0):
-    """The FP64 oracle (FP32-storage mode) on a 128^3 instance of the same recipe, timed on
-    the host cores: RK4 steps until about budget_s seconds have passed."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(fx, n=128, budget_s=12.0, n1=64, budget1_s=8.0):
+    """The FP64 oracle (FP32-storage mode, RK4) timed on the host: on every core on a 128^3
+    instance of the same recipe, RK4 steps until about budget_s seconds have passed, and on one
+    thread on a 64^3 instance for about budget1_s seconds."""
     import numpy as np
 
     import oracle
-    c = fx.roofline512(n, seed=3)
-    U, V, W = fx.fourier_faces(c.shape, c.dx, *c.modes)
-    fx.set_speed(c, fx.max_face_speed(U, V, W))
-    U, V, W, phi = (a.astype(np.float32).astype(np.float64) for a in (U, V, W, c.phi0))
-    kw = dict(dx=c.dx, eps=c.eps, gamma=c.gamma, dt=c.dt, fp32=True)
-    phi = oracle.step(phi, U, V, W, nsteps=1, **kw)  # warm-up
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        phi = oracle.step(phi, U, V, W, nsteps=1, **kw)
-        steps += 1
-    el = time.perf_counter() - t0
+
+    def rate(m, threads, budget):
+        c = fx.roofline512(m, seed=3)
+        U, V, W = fx.fourier_faces(c.shape, c.dx, *c.modes)
+        fx.set_speed(c, fx.max_face_speed(U, V, W))
+        U, V, W, phi = (a.astype(np.float32).astype(np.float64) for a in (U, V, W, c.phi0))
+        kw = dict(dx=c.dx, eps=c.eps, gamma=c.gamma, dt=c.dt, fp32=True)
+        oracle.set_threads(threads)
+        used = oracle.max_threads()
+        phi = oracle.step(phi, U, V, W, nsteps=1, **kw)  # warm-up
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            phi = oracle.step(phi, U, V, W, nsteps=1, **kw)
+            steps += 1
+        el = time.perf_counter() - t0
+        return c.cells * steps / el / 1e9, steps, el, used
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(c.cells * steps / el / 1e9, 5), "unit": "Gcell-updates/s",
-            "cores": cores, "kind": "oracle",
+    v_all, steps, el, used = rate(n, cores, budget_s)
+    v_one, steps1, el1, _ = rate(n1, 1, budget1_s)
+    oracle.set_threads(cores)
+    return {"value": round(v_all, 5), "unit": "Gcell-updates/s", "cores": used, "kind": "oracle",
             "sample": f"{n}^3 instance of the same recipe (64 drops, 16 modes, eps=0.75dx, "
-                      f"gamma=1.1max|u|), FP32-storage RK4, {steps} steps in {el:.1f} s"}
+                      f"gamma=1.1max|u|), FP32-storage RK4, {steps} steps in {el:.1f} s on "
+                      f"{used} threads",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": round(v_one, 6), "unit": "Gcell-updates/s",
+                              "sample": f"{n1}^3 instance, {steps1} steps in {el1:.1f} s, "
+                                        "1 thread"}}
 
 
 def stored_traffic(khash: str, vname: str):
@@ -442,21 +489,32 @@ def main():
     cells = c.cells
     value = cells / ms / 1e6  # Gcell-updates/s
     words, launches = WORDS_PER_CELL_STEP[kind(vname)], LAUNCHES_PER_STEP[kind(vname)]
-    # every step is exactly `launches` launches of the dominant kernel, so algorithmic bytes per
-    # launch over the average launch time equals bytes per step over time per step
-    achieved = words * esz * cells / ms / 1e6  # GB/s
+    # every step is exactly `launches` launches of the dominant kernel (graph replays and eager
+    # steps alike), so the average launch takes ms / launches; algorithmic bytes per launch are
+    # the 28-word cell-update split evenly over them
+    launch_ms = ms / launches
+    launch_bytes = ALG_WORDS * esz * cells / launches
+    achieved = launch_bytes / launch_ms / 1e6  # GB/s
     khash = kernel_hash()
     tr = stored_traffic(khash, vname)
-    launch_bytes = words * esz * cells / launches
+    fused_bytes = words * esz * cells / launches
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": tr, "algorithmic_bytes_per_launch": int(launch_bytes),
-            "launches_per_step": launches, "kernel": vname, "kernel_hash": khash}
+            "traffic": tr, "algorithmic_words_per_cell_update": ALG_WORDS,
+            "algorithmic_bytes_per_launch": int(launch_bytes), "launches_per_step": launches,
+            "avg_launch_ms": round(launch_ms, 4), "kernel": vname, "kernel_hash": khash,
+            "moved_words_per_cell_update": words,
+            "moved_gbs": round(fused_bytes / launch_ms / 1e6, 1),
+            "moved_frac": round(fused_bytes / launch_ms / 1e6 / HBM_PEAK_GBS, 4)}
+    if tr:
+        roof["counter_gbs"] = round(tr / launch_ms / 1e6, 1)
+        roof["counter_frac"] = round(tr / launch_ms / 1e6 / HBM_PEAK_GBS, 4)
+        roof["counter_over_moved"] = round(tr / fused_bytes, 3)
     del phi, u, v, w
     torch.cuda.empty_cache()
-    cc = copy_ceiling(st)
-    roof["copy_ceiling_gbs"] = round(cc, 1)
-    roof["frac_of_copy_ceiling"] = round(achieved / cc, 4)
+    cc = copy_ceiling(pf, st)
+    roof["copy_ceiling"] = cc
+    roof["moved_frac_of_library_copy"] = round(roof["moved_gbs"] / cc["library_copy_gbs"], 4)
     extras = {"tile_autotune_ms_per_step": tuned,
               "mass_drift_timed_region": (m1[0] - m0[0]) / m0[0], "min": m1[1], "max": m1[2],
               "eq17_margin": c.eps / c.dx - (c.gamma + c.extra["umax"]) / (2 * c.gamma)}
@@ -470,8 +528,10 @@ def main():
         w2 = WORDS_PER_CELL_STEP[kind(vname2)]
         extras[f"{other}_{n}"] = {"ms_per_step": round(ms2, 4),
                                   "gcell_s": round(cells / ms2 / 1e6, 2),
-                                  "achieved_gbs": round(w2 * e2 * cells / ms2 / 1e6, 1),
-                                  "frac_of_8tbs": round(w2 * e2 * cells / ms2 / 1e6 / HBM_PEAK_GBS, 4),
+                                  "achieved_gbs": round(ALG_WORDS * e2 * cells / ms2 / 1e6, 1),
+                                  "frac_of_8tbs": round(ALG_WORDS * e2 * cells / ms2 / 1e6 / HBM_PEAK_GBS, 4),
+                                  "moved_words_per_cell_update": w2,
+                                  "moved_frac_of_8tbs": round(w2 * e2 * cells / ms2 / 1e6 / HBM_PEAK_GBS, 4),
                                   "kernel": vname2}
         del phi2, u2, v2, w2
         torch.cuda.empty_cache()

@@ -542,49 +542,73 @@ template hipError_t pf::enqueue_steps<double>(const pf_params&, int, double*, co
                                               const double*, const double*, double*, double*,
                                               double*, double, int, hipStream_t);
 
+// Capture `nsteps` steps from t0 on stream st into the handle's graph (replacing what it held)
+// and instantiate it.
+template <typename T>
+static pf_status capture_steps(pf_solver* s, T* phi, const T* U, const T* V, const T* W,
+                               double t0, int32_t nsteps, hipStream_t st)
+{
+    StepGraph& g = s->graph;
+    release_graph(g);
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "phasefield_step: begin capture");
+    const hipError_t le = enqueue_steps<T>(s->p, s->variant, phi, U, V, W, (T*)s->ya, (T*)s->yb,
+                                           (T*)s->acc, t0, nsteps, st);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "phasefield_step: launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "phasefield_step: end capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "phasefield_step: instantiate");
+    }
+    g.graph = graph;
+    g.exec = exec;
+    g.phi = phi;
+    g.U = U;
+    g.V = V;
+    g.W = W;
+    g.stream = st;
+    g.variant = s->variant;
+    g.t0 = t0;
+    g.nsteps = nsteps;
+    return PF_OK;
+}
+
 template <typename T>
 static pf_status step_impl(pf_solver* s, T* phi, const T* U, const T* V, const T* W, double t0,
                            int32_t nsteps, hipStream_t st)
 {
     const pf_params& p = s->p;
-    T* ya = (T*)s->ya;
-    T* yb = (T*)s->yb;
-    T* acc = (T*)s->acc;
+    StepGraph& g = s->graph;
+    // (capture is not possible on the legacy NULL stream)
+    const bool graphs = p.use_graph && st != nullptr;
+    auto same_operands = [&]() {
+        return g.exec && g.phi == phi && g.U == U && g.V == V && g.W == W && g.stream == st &&
+               g.variant == s->variant;
+    };
+    if (graphs && p.vel_mode != PF_VEL_STEADY && nsteps >= kLoopGraphMin &&
+        nsteps <= kLoopGraphMax) {
+        // time-varying velocity: the whole loop is one graph
+        if (!(same_operands() && g.t0 == t0 && g.nsteps == nsteps)) {
+            const pf_status cs = capture_steps<T>(s, phi, U, V, W, t0, nsteps, st);
+            if (cs != PF_OK) return cs;
+        }
+        const hipError_t e = hipGraphLaunch(g.exec, st);
+        return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_step: graph launch");
+    }
     // Steady velocity: every step is the same launch sequence, replayed from a captured graph
-    // of kGraphSteps steps (capture is not possible on the legacy NULL stream).
-    const bool graphable = p.use_graph && p.vel_mode == PF_VEL_STEADY && st != nullptr;
+    // of kGraphSteps steps.
     int32_t done = 0;
-    if (graphable && nsteps >= kGraphSteps) {
-        StepGraph& g = s->graph;
-        const bool hit = g.exec && g.phi == phi && g.U == U && g.V == V && g.W == W &&
-                         g.stream == st && g.variant == s->variant;
-        if (!hit) {
-            release_graph(g);
-            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return hip_fail(e, "phasefield_step: begin capture");
-            hipError_t le = hipSuccess;
-            le = enqueue_steps<T>(p, s->variant, phi, U, V, W, ya, yb, acc, t0, kGraphSteps, st);
-            hipGraph_t graph = nullptr;
-            e = hipStreamEndCapture(st, &graph);
-            if (le != hipSuccess) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return hip_fail(le, "phasefield_step: launch during capture");
-            }
-            if (e != hipSuccess) return hip_fail(e, "phasefield_step: end capture");
-            hipGraphExec_t exec = nullptr;
-            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return hip_fail(e, "phasefield_step: instantiate");
-            }
-            g.graph = graph;
-            g.exec = exec;
-            g.phi = phi;
-            g.U = U;
-            g.V = V;
-            g.W = W;
-            g.stream = st;
-            g.variant = s->variant;
+    if (graphs && p.vel_mode == PF_VEL_STEADY && nsteps >= kGraphSteps) {
+        if (!(same_operands() && g.nsteps == kGraphSteps)) {
+            const pf_status cs = capture_steps<T>(s, phi, U, V, W, 0.0, kGraphSteps, st);
+            if (cs != PF_OK) return cs;
         }
         for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
             hipError_t e = hipGraphLaunch(g.exec, st);
@@ -592,8 +616,8 @@ static pf_status step_impl(pf_solver* s, T* phi, const T* U, const T* V, const T
         }
     }
     if (done < nsteps) {
-        hipError_t e = enqueue_steps<T>(p, s->variant, phi, U, V, W, ya, yb, acc,
-                                        t0 + (double)done * p.dt, nsteps - done, st);
+        hipError_t e = enqueue_steps<T>(p, s->variant, phi, U, V, W, (T*)s->ya, (T*)s->yb,
+                                        (T*)s->acc, t0 + (double)done * p.dt, nsteps - done, st);
         if (e != hipSuccess) return hip_fail(e, "phasefield_step: launch");
     }
     return PF_OK;
@@ -644,6 +668,17 @@ extern "C" pf_status phasefield_reduce(pf_solver* s, const void* phi, double out
     out4[3] = s->red_host[3];
     if (out4[3] > 0.0) return fail(PF_ERR_NONFINITE, "%.0f non-finite cells", out4[3]);
     return PF_OK;
+}
+
+extern "C" pf_status phasefield_device_copy(void* dst, const void* src, size_t bytes,
+                                           void* hip_stream)
+{
+    if (!dst || !src) return fail(PF_ERR_INVALID, "dst or src is NULL");
+    if (bytes % 4) return fail(PF_ERR_INVALID, "bytes must be a multiple of 4");
+    if (bytes == 0) return PF_OK;
+    hipError_t e = launch_copy<float>((float*)dst, (const float*)src, bytes / 4,
+                                      (hipStream_t)hip_stream);
+    return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_device_copy");
 }
 
 // ------------------------------------------------------------------------------ autotune

@@ -11,6 +11,12 @@
 namespace pf {
 
 constexpr int kGraphSteps = 8;  // steps per captured graph (steady velocity)
+// A time-varying velocity gives every step its own launch arguments (the time factor at the
+// stage times), so such a run is captured whole: one graph of the nsteps-step loop from t0,
+// replayed when the same loop is asked for again. Shorter loops launch eagerly; longer ones too
+// (a graph of more than kLoopGraphMax steps would hold tens of thousands of nodes).
+constexpr int kLoopGraphMin = 16;
+constexpr int kLoopGraphMax = 4096;
 
 struct StepGraph {
     hipGraph_t graph = nullptr;
@@ -21,6 +27,9 @@ struct StepGraph {
     const void* W = nullptr;
     hipStream_t stream = nullptr;
     int variant = -1;
+    // whole-loop graphs (time-varying velocity): the loop they hold
+    double t0 = 0.0;
+    int nsteps = 0;
 };
 
 pf_status fail(pf_status st, const char* fmt, ...);

@@ -273,6 +273,35 @@ def test_graph_replay_matches_eager(lib, kind):
     se.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_time_varying_loop_graph_matches_eager(lib, dtype):
+    """With the cos(pi t / T) velocity a loop of 16 or more steps is captured whole into one
+    graph (each step has its own time factors) and replayed when the same loop (t0, nsteps,
+    buffers) comes again: bitwise equal to plain launches, replay after replay with eager work
+    and synchronisations in between, and after a different loop has replaced the graph."""
+    pf = lib
+    rng = np.random.default_rng(12)
+    shape = (20, 24, 28)
+    phi, U, V, W, dx = random_case(rng, shape)
+    st = torch.cuda.Stream()
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    kw = dict(dx=dx, eps=dx, gamma=1.0, dt=0.1 * dx, dtype=dtype, vel_mode=1, vel_T=0.07)
+    sg = pf.Solver((28, 24, 20), use_graph=True, **kw)
+    se = pf.Solver((28, 24, 20), use_graph=False, **kw)
+    a = [dev(x, tdt) for x in (phi, U, V, W)]
+    b = [dev(x, tdt) for x in (phi, U, V, W)]
+    for rep, (t0, n) in enumerate([(0.0, 21), (0.0, 21), (0.013, 21), (0.0, 40), (0.0, 21)]):
+        with torch.cuda.stream(st):
+            sg.step(*a, t0=t0, nsteps=n, stream=st)
+            se.step(*b, t0=t0, nsteps=n, stream=st)
+            junk = torch.ones(1000, device="cuda").sum()  # unrelated eager work between replays
+        st.synchronize()
+        assert float(junk) == 1000.0
+        assert torch.equal(a[0], b[0]), rep
+    sg.close()
+    se.close()
+
+
 def test_argument_errors(lib):
     pf = lib
     with pytest.raises(pf.PhaseFieldError) as ei:
