@@ -3,12 +3,20 @@ specification of the workload names: full reversal at 64^3 against the oracle (F
 oracle's FP32-storage mode), and 20 steps at 256^3 compared on every cell. The oracle runs on
 the host, so these are the slowest GPU tests (about ten seconds per oracle run on 16 threads).
 
-FP32 tolerance over the full reversal (1830 steps at 64^3): the FP32 kernels evaluate with
-coefficients rounded to float32 (gamma eps / dx^2, dt/6, ...), a systematic perturbation the
-oracle's FP32-storage mode (FP64 arithmetic) does not have, and this run is sensitive to it:
-changing dt, gamma or eps by one float32 ulp moves the oracle's own FP32-storage result by
-4e-6 to 9e-6 relative. The test measures that response and accepts max(1e-5, 4 x the largest),
-four covering the several independently rounded coefficients; short runs keep 1e-5."""
+FP32 storage and the full reversal (1830 steps at 64^3). The drop is stretched into a filament
+one or two cells thick around t = T/3 (step ~600), and there the run amplifies rounding: any
+perturbation of one float32 ulp per stored value grows to 1e-5 or more. A CPU replay of the FP32
+kernels (bitwise equal to the GPU for 100 steps, hardware reciprocal square root included) and
+nine other equally valid FP32 roundings (correctly rounded or Newton-refined 1/sqrt, phi-form or
+increment accumulator, FP64 arithmetic with float32 storage, the oracle's own FP32 mode, 1-ulp
+changes of the rounded initial field) all stay within 2.5e-6 of the FP64 oracle up to step 400,
+scatter by 8e-6 to 4.6e-5 from it at step 600 (the oracle's FP32 mode: 8e-6 to 2.1e-5), and by
+2e-6 to 2.8e-5 at t = T. No FP32-storage run, the oracle's included, can be held to 1e-5 over the
+whole reversal. So the bars, fixed before any GPU run, are:
+  steps 0-400: |GPU - FP32 oracle| <= 1e-5 and |GPU - FP64 oracle| <= 1e-5 (the FP32 bar);
+  t = T:       |GPU - FP64 oracle| <= 1e-4 (twice the widest departure of that ensemble),
+               E_shape within 1e-4 relative of the FP64 oracle's, mass within 1e-6 relative.
+Short runs keep 1e-5 against the FP32 mode directly."""
 import math
 
 import numpy as np
@@ -40,33 +48,53 @@ def run_gpu(pf, c, arrays, dtype, dt, nsteps):
     return out
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_deformation3d_full_reversal_64(lib, dtype):
+def _reversal_case():
     c = fx.deformation3d(64)
     nsteps = int(math.ceil(c.vel_T / c.dt))
-    dt = c.vel_T / nsteps
+    return c, nsteps, c.vel_T / nsteps
+
+
+def test_deformation3d_full_reversal_64_fp64(lib):
+    c, nsteps, dt = _reversal_case()
     arrays = (c.phi0, c.U, c.V, c.W)
-    if dtype == "f32":
-        arrays = tuple(a.astype(np.float32).astype(np.float64) for a in arrays)
-    print(dtype, nsteps, "steps to t = T; oracle running", flush=True)
+    print(nsteps, "steps to t = T; oracle running", flush=True)
     ref = oracle.step(*arrays, dx=c.dx, eps=c.eps, gamma=c.gamma, dt=dt, nsteps=nsteps,
-                      vel_mode=1, vel_T=c.vel_T, fp32=(dtype == "f32"))
-    got = run_gpu(lib, c, arrays, dtype, dt, nsteps)
+                      vel_mode=1, vel_T=c.vel_T)
+    got = run_gpu(lib, c, arrays, "f64", dt, nsteps)
     err = rel_linf(got, ref)
-    e_shape = np.abs(got - c.phi0).sum() * c.dx ** 3
-    print(dtype, "relative L-inf vs oracle", err, "E_shape", e_shape, flush=True)
-    tol = TOL64
-    if dtype == "f32":
-        kw = dict(dx=c.dx, eps=c.eps, gamma=c.gamma, dt=dt, nsteps=nsteps, vel_mode=1,
-                  vel_T=c.vel_T, fp32=True)
-        resp = 0.0
-        for name in ("dt", "gamma", "eps"):
-            k2 = dict(kw)
-            k2[name] = kw[name] * (1 + 2.0 ** -24)
-            resp = max(resp, rel_linf(oracle.step(*arrays, **k2), ref))
-        tol = max(TOL32, 4 * resp)
-        print("f32 one-ulp parameter response", resp, "tolerance", tol, flush=True)
-    assert err <= tol
+    print("f64 relative L-inf vs oracle", err, flush=True)
+    assert err <= TOL64
+
+
+def test_deformation3d_fp32_first_400_steps_64(lib):
+    c, nsteps, dt = _reversal_case()
+    arrays = tuple(a.astype(np.float32).astype(np.float64) for a in (c.phi0, c.U, c.V, c.W))
+    kw = dict(dx=c.dx, eps=c.eps, gamma=c.gamma, dt=dt, nsteps=400, vel_mode=1, vel_T=c.vel_T)
+    ref32 = oracle.step(*arrays, fp32=True, **kw)
+    ref64 = oracle.step(*arrays, **kw)
+    got = run_gpu(lib, c, arrays, "f32", dt, 400)
+    e32, e64 = rel_linf(got, ref32), rel_linf(got, ref64)
+    print("f32, 400 steps: vs FP32 oracle", e32, "vs FP64 oracle", e64, flush=True)
+    assert e32 <= TOL32 and e64 <= TOL32
+
+
+def test_deformation3d_fp32_full_reversal_64(lib):
+    c, nsteps, dt = _reversal_case()
+    arrays = tuple(a.astype(np.float32).astype(np.float64) for a in (c.phi0, c.U, c.V, c.W))
+    kw = dict(dx=c.dx, eps=c.eps, gamma=c.gamma, dt=dt, nsteps=nsteps, vel_mode=1, vel_T=c.vel_T)
+    ref64 = oracle.step(*arrays, **kw)
+    ref32 = oracle.step(*arrays, fp32=True, **kw)
+    got = run_gpu(lib, c, arrays, "f32", dt, nsteps)
+    e64, e32 = rel_linf(got, ref64), rel_linf(got, ref32)
+    es_gpu = np.abs(got - arrays[0]).sum() * c.dx ** 3
+    es_ref = np.abs(ref64 - arrays[0]).sum() * c.dx ** 3
+    m0, m1 = arrays[0].sum(), got.sum()
+    print("f32 full reversal: vs FP64 oracle", e64, "vs FP32 oracle", e32,
+          "(FP32 oracle vs FP64:", rel_linf(ref32, ref64), ")", flush=True)
+    print("E_shape GPU", es_gpu, "oracle FP64", es_ref, "mass drift", abs(m1 - m0) / m0, flush=True)
+    assert e64 <= 1e-4
+    assert abs(es_gpu - es_ref) <= 1e-4 * es_ref
+    assert abs(m1 - m0) <= 1e-6 * m0
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

@@ -13,9 +13,14 @@ paper does not specify, so they are printed beside ours, not asserted.
 Tolerance. Several of these runs are ill-conditioned: where the tails of the drop's periodic
 images meet, grad phi vanishes and the unit normal g/|g| (delta = 0, as in the paper) flips under
 rounding-level changes, and points 6-7 (outside the bounded regime) amplify them further. The
-test measures this on the oracle itself, rerunning it from phi0 perturbed by 1e-16 relative,
-and accepts a GPU-oracle difference up to 100 times that response (and at least 1e-12 relative):
-the GPU may differ from the oracle by no more than its different rounding can explain.
+GPU and the oracle evaluate each FP64 step in different operation orders, so after every step
+they differ by a few units in the last place (below 2^-50 relative on the short parity runs).
+The bar is derived from the oracle alone, before the GPU result is looked at: the oracle's run
+is repeated step by step with every step's result multiplied by 1 + 2^-50 xi (xi seeded
+standard normal noise, two seeds), which is what rounding differences of that size grow into by
+the end of the run; the bar is three times the larger of the two responses (two independent
+realisations of such noise, the GPU's and the oracle's, and the spread between seeds), and at
+least 1e-12 relative. Each test prints the GPU's difference, the response and their ratio.
 """
 import json
 import math
@@ -32,6 +37,33 @@ import pf_fixtures as fx
 pytestmark = pytest.mark.gpu
 
 EPS64 = float(np.finfo(np.float64).eps)
+
+
+def oracle_bar(ref, phi0, vel, kw, seed):
+    """Bar for |GPU - oracle| on an ill-conditioned FP64 run: 3 x the oracle's response to
+    per-step rounding-sized noise (relative 2^-50, two seeds), at least 1e-12 relative."""
+    kw = dict(kw)
+    ns = kw.pop("nsteps")
+    dt = kw["dt"]
+    resp = 0.0
+    for sd in (seed, seed + 7919):
+        rng = np.random.default_rng(sd)
+        y = np.array(phi0, dtype=np.float64)
+        for k in range(ns):
+            y = oracle.step(y, *vel, nsteps=1, t0=k * dt, **kw)
+            y *= 1.0 + 2.0 ** -50 * rng.standard_normal(y.shape)
+        resp = max(resp, float(np.abs(y - ref).max()))
+    return max(1e-12 * float(np.abs(ref).max()), 3.0 * resp), resp
+
+
+def check_against_oracle(got, ref, phi0, vel, kw, seed, label):
+    diff = float(np.abs(got - ref).max())
+    tol, resp = oracle_bar(ref, phi0, vel, kw, seed)
+    ratio = diff / resp if resp > 0 else float("inf")
+    print(f"{label}: |gpu - oracle| {diff:.2e}, oracle noise response {resp:.2e}, ratio "
+          f"{ratio:.2f}, bar {tol:.2e}", flush=True)
+    assert diff <= tol, (label, diff, tol)
+    return tol
 
 
 def test_table2_classification_and_table1_errors_on_the_gpu(lib):
@@ -65,12 +97,7 @@ def test_table2_classification_and_table1_errors_on_the_gpu(lib):
         s.close()
         kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns)
         ref = oracle.step(phi0, U, U, Z, **kw)
-        wobble = np.random.default_rng(p["point"]).standard_normal(phi0.shape)
-        ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, U, Z, **kw)
-        tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
-        diff = np.abs(got - ref).max()
-        print(f"point {p['point']}: |gpu - oracle| = {diff:.2e}, tolerance {tol:.2e}", flush=True)
-        assert diff <= tol, p["point"]
+        tol = check_against_oracle(got, ref, phi0, (U, U, Z), kw, p["point"], f"point {p['point']}")
         bounded = lo >= -EPS64 and hi <= 1 + EPS64
         assert bounded == p["bounded"], (p["point"], lo, hi)
         e_delta = np.abs(got - phi0).mean()
@@ -120,10 +147,7 @@ def test_1d_drop_refinement_on_the_gpu(lib):
             got = _gpu_run_1d(pf, phi0, U, dx, eps, gamma, dt, ns)
             kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns)
             ref = oracle.step(phi0, U, Z, Z, **kw)
-            wobble = np.random.default_rng(n).standard_normal(phi0.shape)
-            ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, Z, Z, **kw)
-            tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
-            assert np.abs(got - ref).max() <= tol, (eps_dx, n)
+            check_against_oracle(got, ref, phi0, (U, Z, Z), kw, n, f"eps/dx {eps_dx} N {n}")
             x = (np.arange(n) + 0.5) * dx
             top_hat = (np.abs(x - 1.0) < 0.5).astype(float)
             e = (np.abs(phi0[0, 0] - top_hat).mean(), np.abs(got[0, 0] - phi0[0, 0]).mean(),
@@ -173,13 +197,10 @@ def test_rk2_boundedness_map_on_the_gpu(lib, eps_over_dx, gamma_over_u, bounded)
     s.close()
     kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns, scheme=2)
     ref = oracle.step(phi0, U, Z, Z, **kw)
-    wobble = np.random.default_rng(ns).standard_normal(phi0.shape)
-    ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, Z, Z, **kw)
-    tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
-    diff = np.abs(got - ref).max()
     print(f"eps/dx {eps_over_dx} gamma/u {gamma_over_u}: {ns} steps, min {lo:.3e}, "
-          f"max-1 {hi - 1:.3e}, |gpu - oracle| {diff:.2e} (tolerance {tol:.2e})", flush=True)
-    assert diff <= tol
+          f"max-1 {hi - 1:.3e}", flush=True)
+    check_against_oracle(got, ref, phi0, (U, Z, Z), kw, ns,
+                         f"eps/dx {eps_over_dx} gamma/u {gamma_over_u}")
     if bounded:
         assert lo >= -EPS64 and hi <= 1 + EPS64, (lo, hi)
     else:
@@ -232,10 +253,7 @@ def test_boundedness_map_on_the_gpu(lib, scheme, sch, limit):
                 assert bounded, (scheme, eod, gou, lo, hi)
                 kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns, scheme=sch)
                 ref = oracle.step(phi0, U, Z, Z, **kw)
-                wobble = np.random.default_rng(ns).standard_normal(phi0.shape)
-                ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, Z, Z, **kw)
-                tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
-                assert np.abs(got - ref).max() <= tol, (scheme, eod, gou)
+                check_against_oracle(got, ref, phi0, (U, Z, Z), kw, ns, f"{scheme} {eod} {gou}")
             else:
                 below += 1
                 below_unbounded += not bounded
@@ -330,10 +348,7 @@ def test_zalesak_disk_one_revolution(lib):
         if n == 100:
             kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns // 4)
             ref = oracle.step(phi0, U, V, W, **kw)
-            wobble = np.random.default_rng(n).standard_normal(phi0.shape)
-            ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, V, W, **kw)
-            tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
-            assert np.abs(quarter - ref).max() <= tol
+            check_against_oracle(quarter, ref, phi0, (U, V, W), kw, n, "Zalesak N 100 quarter turn")
     assert errs[1] < errs[0] and errs[2] < errs[1], errs
 
 
@@ -377,10 +392,7 @@ def test_random_velocity_field_with_slip_walls(lib, seed):
         if p["point"] == 2:
             kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns, walls=walls)
             ref = oracle.step(phi0, U, V, W, **kw)
-            wobble = np.random.default_rng(seed).standard_normal(phi0.shape)
-            ref_p = oracle.step(phi0 * (1 + 1e-16 * wobble), U, V, W, **kw)
-            tol = max(1e-12 * np.abs(ref).max(), 100 * np.abs(ref - ref_p).max())
-            assert np.abs(got - ref).max() <= tol
+            check_against_oracle(got, ref, phi0, (U, V, W), kw, seed, f"random field seed {seed} point 2")
 
 
 def test_drop_in_shear_flow_second_order(lib):
