@@ -129,6 +129,26 @@ pf_status phasefield_destroy(pf_solver *s);
 pf_status phasefield_step(pf_solver *s, void *phi, const void *u, const void *v, const void *w,
                           double t0, int32_t nsteps, void *hip_stream);
 
+/* phasefield_step for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same steps, kernels and
+ * results as phasefield_step on a handle created from *p, but with no handle and no allocating
+ * call. The three stage buffers live in one fixed device array of the library
+ * (phasefield_noalloc_scratch_bytes() bytes, 64 MiB, held by each GPU the library runs on until
+ * the process ends), so 3 * round_up_256(cells * element size) must fit in it: up to about
+ * 5.59M cells in FP32 (e.g. 176^3) and 2.79M in FP64 (e.g. 140^3); larger grids are rejected
+ * with PF_ERR_INVALID before any device work. Steps are launched one by one (no captured graph,
+ * p->use_graph is ignored). Every call on a GPU shares that GPU's array, and the array keeps
+ * the last call's contents (the stage buffers need no clearing: every value is written before it
+ * is read): calls that overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller. The first call on a device looks up that device's address of the
+ * array (hipGetSymbolAddress). Errors: as phasefield_create's parameter checks and
+ * phasefield_step's, PF_ERR_INVALID for a grid beyond the array, PF_ERR_DEVICE. */
+pf_status phasefield_step_noalloc(const pf_params *p, void *phi, const void *u, const void *v,
+                                  const void *w, double t0, int32_t nsteps, void *hip_stream);
+
+/* Size in bytes of the fixed device array behind phasefield_step_noalloc. */
+size_t phasefield_noalloc_scratch_bytes(void);
+
 /* Discrete adjoint of ONE step (the transpose of the derivative of phasefield_step with
  * nsteps = 1, taken at phi_n and time t_n). On entry lam = dL/dphi_{n+1}; on exit
  * lam = dL/dphi_n (in place). gu, gv, gw (may each be NULL to skip) ACCUMULATE

@@ -21,7 +21,7 @@ from ._capi import (EXPORTED, PF_BC_PERIODIC, PF_BC_WALL, PF_ERR_DEVICE, PF_ERR_
                     phasefield_batch_step, phasefield_check_params, phasefield_create,
                     phasefield_default_params, phasefield_destroy, phasefield_last_error,
                     phasefield_reduce, phasefield_solver_variant, phasefield_step,
-                    phasefield_device_copy,
+                    phasefield_step_noalloc, phasefield_noalloc_scratch_bytes, phasefield_device_copy,
                     phasefield_variant_count, phasefield_variant_name,
                     phasefield_velocity_coeffs_grad, phasefield_velocity_from_coeffs)
 

@@ -87,6 +87,8 @@ def _load():
         "phasefield_batch_step": (i32, [vp, P(vp), P(vp), P(vp), P(vp), P(d), i32, vp]),
         "phasefield_batch_destroy": (i32, [vp]),
         "phasefield_last_error": (ctypes.c_char_p, []),
+        "phasefield_step_noalloc": (i32, [P(Params), vp, vp, vp, vp, d, i32, vp]),
+        "phasefield_noalloc_scratch_bytes": (ctypes.c_size_t, []),
         "phasefield_device_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
@@ -104,7 +106,8 @@ EXPORTED = ("phasefield_default_params", "phasefield_check_params", "phasefield_
             "phasefield_velocity_coeffs_grad", "phasefield_variant_count",
             "phasefield_variant_name", "phasefield_autotune", "phasefield_solver_variant",
             "phasefield_batch_create", "phasefield_batch_step", "phasefield_batch_destroy",
-            "phasefield_last_error", "phasefield_device_copy")
+            "phasefield_last_error", "phasefield_step_noalloc",
+            "phasefield_noalloc_scratch_bytes", "phasefield_device_copy")
 
 
 def _check(status: int) -> None:
@@ -192,6 +195,18 @@ def phasefield_step(h, p: Params, phi, u, v, w, t0=0.0, nsteps=1, stream=None) -
     _check(lib.phasefield_step(h, _ptr(phi, p.dtype, n, "phi"), _ptr(u, p.dtype, n, "u"),
                                _ptr(v, p.dtype, n, "v"), _ptr(w, p.dtype, n, "w"),
                                float(t0), int(nsteps), _stream(stream)))
+
+
+def phasefield_step_noalloc(p: Params, phi, u, v, w, t0=0.0, nsteps=1, stream=None) -> None:
+    n = cells(p)
+    _check(lib.phasefield_step_noalloc(ctypes.byref(p), _ptr(phi, p.dtype, n, "phi"),
+                                       _ptr(u, p.dtype, n, "u"), _ptr(v, p.dtype, n, "v"),
+                                       _ptr(w, p.dtype, n, "w"), float(t0), int(nsteps),
+                                       _stream(stream)))
+
+
+def phasefield_noalloc_scratch_bytes() -> int:
+    return int(lib.phasefield_noalloc_scratch_bytes())
 
 
 def phasefield_adjoint_step(h, p: Params, phi_n, u, v, w, t_n, lam, gu=None, gv=None, gw=None,

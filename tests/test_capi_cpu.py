@@ -99,3 +99,19 @@ def test_variant_table(pf):
     names = [pf.phasefield_variant_name(pf.PF_F64, v) for v in range(nv)]
     assert all(names) and len(set(names)) == nv
     assert pf.phasefield_variant_name(pf.PF_F64, nv) is None
+
+
+def test_noalloc_step_refuses_oversized_grid_on_the_host(pf):
+    """phasefield_step_noalloc checks the grid against its fixed scratch array before any device
+    work (the pointers here are never dereferenced)."""
+    import ctypes
+    assert pf.phasefield_noalloc_scratch_bytes() == 64 << 20
+    for n, dtype in ((150, "f64"), (190, "f32")):
+        p = pf.make_params((n, n, n), 1.0 / n, 1.0 / n, 1.0, 1e-4, dtype=dtype)
+        fake = ctypes.c_void_p(256)
+        st = pf.lib.phasefield_step_noalloc(ctypes.byref(p), fake, fake, fake, fake, 0.0, 1, None)
+        assert st == pf.PF_ERR_INVALID
+        assert "scratch" in pf.phasefield_last_error()
+    p = pf.make_params((8, 8, 8), 0.0, 0.1, 1.0, 0.01)  # dx = 0: parameter check first
+    st = pf.lib.phasefield_step_noalloc(ctypes.byref(p), fake, fake, fake, fake, 0.0, 1, None)
+    assert st == pf.PF_ERR_INVALID
