@@ -305,10 +305,14 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
     names = [pf.phasefield_variant_name(pf.PF_F32, v)
              for v in range(pf.phasefield_variant_count(pf.PF_F32))]
     modes = {}
-    for mode, pick in (("default", -1), ("fused", names.index("fused_32x16x32")),
-                       ("per_stage", names.index("tiled_64x8x16"))):
+    for mode, pick, persistent in (("default", -1, False),
+                                   ("fused", names.index("fused_32x16x32"), False),
+                                   ("per_stage", names.index("tiled_64x8x16"), False),
+                                   ("fused_persistent", names.index("fused_32x16x32"), True),
+                                   ("per_stage_persistent", names.index("tiled_64x8x16"), True)):
         params[0].variant = pick
         bs = pf.BatchSolver(params)
+        bs.set_persistent(persistent)
         bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
         with torch.cuda.stream(st):
             bs.step(*zip(*bf), nsteps=8, stream=st)
@@ -401,16 +405,87 @@ def cpu_baseline(fx, n=128, budget_s=12.0, n1=64, budget1_s=8.0):
                                         "1 thread"}}
 
 
-def stored_traffic(khash: str, vname: str):
+def stored_traffic(khash: str, vname: str, n: int = 512, dtype: str = "f32"):
     """HBM bytes per launch from the committed counter summary, if it was taken on this exact
     kernel source and variant (else None)."""
-    f = os.path.join(ROOT, "profiles", "stage_traffic_roofline512_f32.json")
+    f = os.path.join(ROOT, "profiles", f"stage_traffic_roofline{n}_{dtype}.json")
     if not os.path.exists(f):
         return None
     d = json.load(open(f))
     if d.get("kernel_hash") != khash or d.get("kernel") != vname:
         return None
     return d["bytes_per_launch"]
+
+
+def _counter_values(d: str, counter: str) -> dict:
+    """Per kernel name, the values of one counter for each dispatch in dispatch order, from the
+    counter_collection CSV files of a rocprofv3 --pmc run under directory d (the rows of one
+    dispatch are summed)."""
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (f, int(row["Dispatch_Id"]))
+                per.setdefault(key, [row["Kernel_Name"], 0.0])
+                per[key][1] += float(row["Counter_Value"])
+    out = {}
+    for key in sorted(per):
+        name, v = per[key]
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def write_traffic(args):
+    """HBM bytes per launch of the stage kernel of this benchmark's workload, from FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for the
+    library copy of --traffic-copy-bytes bytes (the probe: the first copy16 dispatch of the run;
+    later ones are the copy-ceiling measurement)."""
+    fetch = _counter_values(args.traffic_from[0], "FETCH_SIZE")
+    write = _counter_values(args.traffic_from[1], "WRITE_SIZE")
+    copy_name = next(k for k in fetch if "copy16_kernel" in k)
+    ffac = args.traffic_copy_bytes / (fetch[copy_name][0] * 1024.0)
+    wfac = args.traffic_copy_bytes / (write[copy_name][0] * 1024.0)
+    esz = 4 if args.dtype == "f32" else 8
+    n = args.n
+    cells = n ** 3
+    # the timed steps' kernels: the plain sweeps (the fused form with the optional outputs,
+    # XOUT, only ends odd step counts) or the per-stage kernel
+    stage = sorted(k for k in fetch if ("fused_kernel" in k and not k.split(">")[0].endswith("true"))
+                   or "stage_kernel" in k)
+    sweeps = {}
+    for k in stage:
+        fk = sum(fetch[k]) / len(fetch[k])
+        wk = sum(write.get(k, [0.0])) / len(write.get(k, [0.0]))
+        sweeps[k] = {"fetch_kib_raw": fk, "write_kib_raw": wk,
+                     "bytes": int(fk * 1024 * ffac + wk * 1024 * wfac)}
+    per_launch = sum(v["bytes"] for v in sweeps.values()) / len(sweeps)
+    fused = any("fused_kernel" in k for k in stage)
+    moved = (6.5 if fused else 7.0) * esz * cells
+    out = {"kernel": args.traffic_variant, "kernel_name": stage, "dtype": args.dtype,
+           "grid": [n, n, n], "kernel_hash": kernel_hash(), "sweeps": sweeps,
+           "fetch_calibration": {"factor": round(ffac, 4), "kernel": copy_name,
+                                 "bytes": args.traffic_copy_bytes, "fetch_kib": fetch[copy_name][0]},
+           "write_calibration": {"factor": round(wfac, 4), "kernel": copy_name,
+                                 "bytes": args.traffic_copy_bytes, "write_kib": write[copy_name][0]},
+           "bytes_per_launch": int(per_launch), "moved_bytes_per_launch": int(moved),
+           "counter_over_moved": round(per_launch / moved, 4),
+           "commands": [f"rocprofv3 --pmc {c} -d gpurun_out/pmc_{c}_{args.dtype} -o bench "
+                        f"--output-format csv -- python3 bench.py --steps 3 --warmup 1 --quick "
+                        f"--no-cpu-baseline --no-autotune --dtype {args.dtype} "
+                        f"--copy-probe {args.traffic_copy_bytes}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+                       + [f"python3 bench.py --traffic-from gpurun_out/pmc_FETCH_SIZE_{args.dtype} "
+                          f"gpurun_out/pmc_WRITE_SIZE_{args.dtype} --dtype {args.dtype} "
+                          f"--traffic-variant {args.traffic_variant}"],
+           "note": "means over the dispatches of each sweep; factors scale the raw KiB counters "
+                   "to bytes by the library copy of known size"}
+    path = os.path.join(ROOT, "profiles", f"stage_traffic_roofline{n}_{args.dtype}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def main():
@@ -430,10 +505,22 @@ def main():
                          "run only those measurements and print their JSON (for profiling "
                          "them)")
     ap.add_argument("--batch-steps", type=int, default=300)
+    ap.add_argument("--adjoint-n", type=int, default=128,
+                    help="grid of the adjoint measurement in --only adjoint")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="also run one plain device copy of BYTES bytes (hardware-counter "
+                    help="also run one library copy of BYTES bytes (hardware-counter "
                          "calibration: its FETCH_SIZE/WRITE_SIZE should read BYTES each)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: read two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "this benchmark with --copy-probe, and write the HBM traffic per launch "
+                         "of the dominant kernel to profiles/stage_traffic_<workload>.json")
+    ap.add_argument("--traffic-copy-bytes", type=int, default=2 ** 30)
+    ap.add_argument("--traffic-variant", default="fused_64x8",
+                    help="name of the variant the --pmc runs timed (recorded in the json)")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the method runs on one device here; multi-GPU slab "
@@ -454,8 +541,10 @@ def main():
             sys.exit(2)
         res = {}
         if "adjoint" in parts:
-            res["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st, reps=20)
-            res["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st, reps=20)
+            na = args.adjoint_n
+            for dt_ in ("f64", "f32") if args.dtype == "f32" else ("f64",):
+                res[f"adjoint_{na}_{dt_}"] = adjoint_ratio(pf, fx, dt_, st, n=na,
+                                                         reps=20 if na <= 256 else 5)
         if "batch" in parts:
             res["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
         if "deformation" in parts:
@@ -472,10 +561,11 @@ def main():
         print(json.dumps(res), flush=True)
         return
     if args.copy_probe:
+        # one library copy of known size (pf::copy16_kernel): BYTES read and BYTES written
         src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        pf.phasefield_device_copy(dst, src)
         torch.cuda.synchronize()
         del src, dst
     n = args.n
@@ -496,7 +586,7 @@ def main():
     launch_bytes = ALG_WORDS * esz * cells / launches
     achieved = launch_bytes / launch_ms / 1e6  # GB/s
     khash = kernel_hash()
-    tr = stored_traffic(khash, vname)
+    tr = stored_traffic(khash, vname, n, args.dtype)
     fused_bytes = words * esz * cells / launches
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -566,6 +656,10 @@ def main():
         extras["rollout_128_f32"] = rollout_timing(pf, fx, "f32")
         log("timing batch vs loop")
         extras["batch96_f32"] = batch_vs_loop(pf, fx, st, nsteps=args.batch_steps)
+        if args.dtype == "f32":
+            extras["batch96_f32"]["best_single_grid_gcell_s"] = round(value, 2)
+            extras["batch96_f32"]["batched_over_best_single_grid"] = round(
+                extras["batch96_f32"]["batched_gcell_s"] / value, 3)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing CPU oracle")

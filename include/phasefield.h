@@ -238,6 +238,14 @@ pf_status phasefield_batch_step(pf_batch *b, void *const *phi, const void *const
                                 const void *const *v, const void *const *w, const double *t0,
                                 int32_t nsteps, void *hip_stream);
 
+/* Launch form of the batched sweeps: 0 (the default) launches one workgroup per tile-list entry
+ * and lets the hardware dispatcher hand out the entries; 1 launches a persistent grid (the
+ * sweep kernel's resident workgroups, a multiple of 8) whose workgroups each walk their XCD's
+ * share of the list. Results are identical either way. Synchronises work queued on the batch's
+ * last stream when the form changes; the next step re-captures its graph. Errors: PF_ERR_INVALID
+ * (NULL), PF_ERR_DEVICE. */
+pf_status phasefield_batch_set_persistent(pf_batch *b, int32_t persistent);
+
 pf_status phasefield_batch_destroy(pf_batch *b);
 
 /* Copy `bytes` bytes (a multiple of 4) from src to dst, both device pointers, asynchronously

@@ -18,7 +18,8 @@ from ._capi import (EXPORTED, PF_BC_PERIODIC, PF_BC_WALL, PF_ERR_DEVICE, PF_ERR_
                     PF_OK, PF_RK4, PF_VEL_COS_REVERSAL, PF_VEL_STEADY, LIB_PATH, Params,
                     PhaseFieldError, Report, cells, lib, make_params, phasefield_adjoint_step,
                     phasefield_autotune, phasefield_batch_create, phasefield_batch_destroy,
-                    phasefield_batch_step, phasefield_check_params, phasefield_create,
+                    phasefield_batch_step, phasefield_batch_set_persistent,
+                    phasefield_check_params, phasefield_create,
                     phasefield_default_params, phasefield_destroy, phasefield_last_error,
                     phasefield_reduce, phasefield_solver_variant, phasefield_step,
                     phasefield_step_noalloc, phasefield_noalloc_scratch_bytes, phasefield_device_copy,
@@ -101,6 +102,10 @@ class BatchSolver:
 
     def step(self, phis, us, vs, ws, nsteps=1, t0s=None, stream=None):
         phasefield_batch_step(self.handle, self.params, phis, us, vs, ws, t0s, nsteps, stream)
+
+    def set_persistent(self, persistent: bool = True):
+        """Launch form of the sweeps: a persistent resident grid, or one workgroup per tile."""
+        phasefield_batch_set_persistent(self.handle, persistent)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -86,6 +86,7 @@ def _load():
         "phasefield_batch_create": (i32, [P(Params), i32, P(vp)]),
         "phasefield_batch_step": (i32, [vp, P(vp), P(vp), P(vp), P(vp), P(d), i32, vp]),
         "phasefield_batch_destroy": (i32, [vp]),
+        "phasefield_batch_set_persistent": (i32, [vp, i32]),
         "phasefield_last_error": (ctypes.c_char_p, []),
         "phasefield_step_noalloc": (i32, [P(Params), vp, vp, vp, vp, d, i32, vp]),
         "phasefield_noalloc_scratch_bytes": (ctypes.c_size_t, []),
@@ -106,6 +107,7 @@ EXPORTED = ("phasefield_default_params", "phasefield_check_params", "phasefield_
             "phasefield_velocity_coeffs_grad", "phasefield_variant_count",
             "phasefield_variant_name", "phasefield_autotune", "phasefield_solver_variant",
             "phasefield_batch_create", "phasefield_batch_step", "phasefield_batch_destroy",
+            "phasefield_batch_set_persistent",
             "phasefield_last_error", "phasefield_step_noalloc",
             "phasefield_noalloc_scratch_bytes", "phasefield_device_copy")
 
@@ -286,6 +288,10 @@ def phasefield_batch_step(h, params_list, phis, us, vs, ws, t0s=None, nsteps=1, 
     t0 = None if t0s is None else (ctypes.c_double * B)(*[float(x) for x in t0s])
     _check(lib.phasefield_batch_step(h, arr(phis, "phi"), arr(us, "u"), arr(vs, "v"),
                                      arr(ws, "w"), t0, int(nsteps), _stream(stream)))
+
+
+def phasefield_batch_set_persistent(h, persistent: bool) -> None:
+    _check(lib.phasefield_batch_set_persistent(h, int(bool(persistent))))
 
 
 def phasefield_batch_destroy(h) -> None:

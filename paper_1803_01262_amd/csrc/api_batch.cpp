@@ -28,6 +28,7 @@ struct pf_batch {
     void* pool = nullptr;          // stage buffers of every instance (ya, yb, acc each)
     std::vector<size_t> pool_off;  // element offset of instance b's first buffer
     int num_tiles = 0;
+    bool persistent = false;  // launch form: resident-slot grid looping over the list
     bool wide = false;  // every instance's nx allows 16-byte plane loads
     BatchTile* tiles = nullptr;  // device: the global tile list (8 equal per-XCD ranges)
     // device per-instance argument arrays: per-stage mode S1..S4 (StageArgs);
@@ -232,14 +233,15 @@ static hipError_t enqueue_batch_step(pf_batch* B, bool odd, hipStream_t st)
     if (B->fused) {
         for (int s = 0; s < 2; ++s) {
             hipError_t e = launch_batch_fused<T>((const FusedArgs<T>*)B->tables[(odd ? 2 : 0) + s],
-                                                 s == 1, B->wide, B->tiles, B->num_tiles, st);
+                                                 s == 1, B->wide, B->tiles, B->num_tiles,
+                                                 B->persistent, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
     for (int s = 0; s < 4; ++s) {
         hipError_t e = launch_batch_stage<T>((const StageArgs<T>*)B->tables[s], B->tiles,
-                                             B->num_tiles, st);
+                                             B->num_tiles, B->persistent, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -296,6 +298,19 @@ static pf_status batch_step_impl(pf_batch* B, void* const* phi, const void* cons
     if (B->fused && (rest & 1)) {
         hipError_t e = launch_batch_copy<T>((const BatchCopy<T>*)B->copies, B->count, st);
         if (e != hipSuccess) return hip_fail(e, "phasefield_batch_step: copy back");
+    }
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_batch_set_persistent(pf_batch* b, int32_t persistent)
+{
+    if (!b) return fail(PF_ERR_INVALID, "batch is NULL");
+    if (b->persistent != (persistent != 0)) {
+        // queued replays of the old graph may still run; the new form is captured on next use
+        hipError_t e = b->key_stream ? hipStreamSynchronize(b->key_stream) : hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "phasefield_batch_set_persistent: synchronize");
+        batch_release_graph(b);
+        b->persistent = persistent != 0;
     }
     return PF_OK;
 }

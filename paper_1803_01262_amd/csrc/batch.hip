@@ -12,37 +12,55 @@ namespace pf {
 constexpr int kBTX = 32, kBTY = 8, kBKZ = 64;   // per-stage mode tile shape
 constexpr int kFTX = 32, kFTY = 16, kFKZ = 64;  // fused mode tile shape
 
-// Workgroup -> tile-list entry: the list holds 8 equal ranges, one per XCD, and xcd_tile_order
-// lets each XCD walk its own range in order.
-__device__ __forceinline__ int batch_slot()
+// Workgroup -> tile-list entry: the list holds 8 equal ranges of `len` entries, one per XCD.
+// One workgroup per entry: xcd_tile_order lets each XCD walk its own range in order.
+// Persistent form (PERSIST, a grid of G workgroups, G a multiple of 8 and at most the resident
+// slots): workgroup w stays on XCD w mod 8 and takes entries r, r + G/8, r + 2G/8, ... of that
+// XCD's range (r = w / 8), in the range's longest-first order; every workgroup leaves the loop
+// when it runs past the range end.
+template <bool PERSIST, typename Body>
+__device__ __forceinline__ void for_batch_tiles(const BatchTile* __restrict__ tiles, int len,
+                                                Body body)
 {
-    return xcd_tile_order(blockIdx.x, gridDim.x);
+    if constexpr (!PERSIST) {
+        const BatchTile tl = tiles[xcd_tile_order(blockIdx.x, gridDim.x)];
+        if (tl.b >= 0) body(tl);
+    } else {
+        const int x = blockIdx.x & 7, r = blockIdx.x >> 3, step = gridDim.x >> 3;
+        for (int e = r; e < len; e += step) {
+            __syncthreads();  // the previous tile's LDS reads have completed
+            const BatchTile tl = tiles[x * len + e];
+            if (tl.b >= 0) body(tl);
+        }
+    }
 }
 
-template <typename T>
+template <typename T, bool PERSIST>
 __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs<T>* __restrict__ args,
-                                                                  const BatchTile* __restrict__ tiles)
+                                                                  const BatchTile* __restrict__ tiles,
+                                                                  int len)
 {
-    const BatchTile tl = tiles[batch_slot()];
-    if (tl.b < 0) return;
-    const int k0 = tl.tk * kBKZ;
-    // 64-plane chunks: the form that loads per-cell operands one iteration ahead (1.6-1.8 % faster)
-    tiled_stage_body<T, kBTX, kBTY, false, false, true>(args[tl.b], tl.ti, tl.tj, k0,
-                                                        min(k0 + kBKZ, args[tl.b].nz));
+    for_batch_tiles<PERSIST>(tiles, len, [&](const BatchTile& tl) {
+        const int k0 = tl.tk * kBKZ;
+        // 64-plane chunks: the form that loads per-cell operands one iteration ahead (1.6-1.8 %
+        // faster)
+        tiled_stage_body<T, kBTX, kBTY, false, false, true>(args[tl.b], tl.ti, tl.tj, k0,
+                                                            min(k0 + kBKZ, args[tl.b].nz));
+    });
 }
 
 // Fused mode: one launch per two-stage sweep, with the register budget of the single-grid fused
 // kernel (FP32: four waves per SIMD).
 // WIDE: every instance's rows are a whole number of 16-byte pieces (16-byte plane loads).
-template <typename T, bool SWEEP_B, bool WIDE>
+template <typename T, bool SWEEP_B, bool WIDE, bool PERSIST>
 __global__ void __launch_bounds__(kFTX* kFTY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
-batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __restrict__ tiles)
+batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __restrict__ tiles, int len)
 {
-    const BatchTile tl = tiles[batch_slot()];
-    if (tl.b < 0) return;
-    const int k0 = tl.tk * kFKZ;
-    fused_body<T, kFTX, kFTY, SWEEP_B, false, WIDE>(args[tl.b], tl.ti, tl.tj, k0,
-                                                    min(k0 + kFKZ, args[tl.b].nz));
+    for_batch_tiles<PERSIST>(tiles, len, [&](const BatchTile& tl) {
+        const int k0 = tl.tk * kFKZ;
+        fused_body<T, kFTX, kFTY, SWEEP_B, false, WIDE>(args[tl.b], tl.ti, tl.tj, k0,
+                                                        min(k0 + kFKZ, args[tl.b].nz));
+    });
 }
 
 // dst[b] = src[b] for every instance b (blockIdx.y), grid-stride within the instance.
@@ -61,28 +79,46 @@ void batch_tile_shape(bool fused, int* tx, int* ty, int* kz)
     *kz = fused ? kFKZ : kBKZ;
 }
 
-template <typename T, bool WIDE>
-static void launch_batch_fused_form(const FusedArgs<T>* args_dev, bool sweep_b,
-                                    const BatchTile* tiles_dev, int num_tiles, hipStream_t st)
+// Grid of the persistent form: the resident slots of the kernel (compute units x workgroups per
+// compute unit), rounded down to a multiple of 8 and capped at the list length; 0 on error.
+static int persistent_grid(const void* kernel, int threads, int num_tiles)
 {
-    if (sweep_b)
-        hipLaunchKernelGGL((batch_fused_kernel<T, true, WIDE>), dim3(num_tiles), dim3(kFTX * kFTY),
-                           0, st, args_dev, tiles_dev);
-    else
-        hipLaunchKernelGGL((batch_fused_kernel<T, false, WIDE>), dim3(num_tiles), dim3(kFTX * kFTY),
-                           0, st, args_dev, tiles_dev);
+    const int cus = device_compute_units();
+    const int groups = resident_groups_per_cu(kernel, threads);
+    if (cus <= 0 || groups <= 0) return 0;
+    int g = (cus * groups) / 8 * 8;
+    return g > num_tiles ? num_tiles : g;
+}
+
+template <typename T, bool SWEEP_B, bool WIDE>
+static hipError_t launch_batch_fused_form(const FusedArgs<T>* args_dev, const BatchTile* tiles_dev,
+                                          int num_tiles, bool persistent, hipStream_t st)
+{
+    const int len = num_tiles / 8;
+    if (persistent) {
+        const void* k = (const void*)batch_fused_kernel<T, SWEEP_B, WIDE, true>;
+        const int g = persistent_grid(k, kFTX * kFTY, num_tiles);
+        if (g < 8) return hipErrorInvalidDevice;
+        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, true>), dim3(g), dim3(kFTX * kFTY),
+                           0, st, args_dev, tiles_dev, len);
+    } else {
+        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, false>), dim3(num_tiles),
+                           dim3(kFTX * kFTY), 0, st, args_dev, tiles_dev, len);
+    }
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
-                              const BatchTile* tiles_dev, int num_tiles, hipStream_t st)
+                              const BatchTile* tiles_dev, int num_tiles, bool persistent,
+                              hipStream_t st)
 {
-    if (num_tiles <= 0) return hipErrorInvalidValue;
+    if (num_tiles <= 0 || num_tiles % 8) return hipErrorInvalidValue;
     if (wide)
-        launch_batch_fused_form<T, true>(args_dev, sweep_b, tiles_dev, num_tiles, st);
-    else
-        launch_batch_fused_form<T, false>(args_dev, sweep_b, tiles_dev, num_tiles, st);
-    return hipGetLastError();
+        return sweep_b ? launch_batch_fused_form<T, true, true>(args_dev, tiles_dev, num_tiles, persistent, st)
+                       : launch_batch_fused_form<T, false, true>(args_dev, tiles_dev, num_tiles, persistent, st);
+    return sweep_b ? launch_batch_fused_form<T, true, false>(args_dev, tiles_dev, num_tiles, persistent, st)
+                   : launch_batch_fused_form<T, false, false>(args_dev, tiles_dev, num_tiles, persistent, st);
 }
 
 template <typename T>
@@ -92,22 +128,30 @@ hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, bool, const BatchTile*, int, hipStream_t);
-template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, bool, const BatchTile*, int, hipStream_t);
+template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, bool, const BatchTile*, int, bool, hipStream_t);
+template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, bool, const BatchTile*, int, bool, hipStream_t);
 template hipError_t launch_batch_copy<float>(const BatchCopy<float>*, int, hipStream_t);
 template hipError_t launch_batch_copy<double>(const BatchCopy<double>*, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* tiles_dev, int num_tiles,
-                              hipStream_t st)
+                              bool persistent, hipStream_t st)
 {
-    if (num_tiles <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(batch_stage_kernel<T>, dim3(num_tiles), dim3(kBTX * kBTY), 0, st, args_dev,
-                       tiles_dev);
+    if (num_tiles <= 0 || num_tiles % 8) return hipErrorInvalidValue;
+    const int len = num_tiles / 8;
+    if (persistent) {
+        const int g = persistent_grid((const void*)batch_stage_kernel<T, true>, kBTX * kBTY, num_tiles);
+        if (g < 8) return hipErrorInvalidDevice;
+        hipLaunchKernelGGL((batch_stage_kernel<T, true>), dim3(g), dim3(kBTX * kBTY), 0, st, args_dev,
+                           tiles_dev, len);
+    } else {
+        hipLaunchKernelGGL((batch_stage_kernel<T, false>), dim3(num_tiles), dim3(kBTX * kBTY), 0, st,
+                           args_dev, tiles_dev, len);
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_stage<float>(const StageArgs<float>*, const BatchTile*, int, hipStream_t);
-template hipError_t launch_batch_stage<double>(const StageArgs<double>*, const BatchTile*, int, hipStream_t);
+template hipError_t launch_batch_stage<float>(const StageArgs<float>*, const BatchTile*, int, bool, hipStream_t);
+template hipError_t launch_batch_stage<double>(const StageArgs<double>*, const BatchTile*, int, bool, hipStream_t);
 
 }  // namespace pf

@@ -294,10 +294,12 @@ def _batch_instances(sizes, seed=4):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("mode", ["default", "fused", "per-stage"])
+@pytest.mark.parametrize("mode", ["default", "fused", "per-stage", "fused-persistent",
+                                  "per-stage-persistent"])
 def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
-    """Both batched modes (chosen through instance 0's variant) give every instance exactly
-    its own single solve, over uneven, ragged and degenerate grids."""
+    """Both batched modes (chosen through instance 0's variant), each in both launch forms (one
+    workgroup per tile entry, or a persistent resident grid), give every instance exactly its
+    own single solve, over uneven, ragged and degenerate grids."""
     pf = lib
     sizes = [(32, 32, 32), (48, 40, 24), (17, 9, 33), (64, 64, 8), (5, 70, 3), (96, 1, 1),
              (40, 24, 130)]
@@ -306,13 +308,15 @@ def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
     kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
     names = [pf.phasefield_variant_name(kd, v) for v in range(pf.phasefield_variant_count(kd))]
     pick = {"default": -1, "fused": names.index("fused_32x16x32"),
-            "per-stage": names.index("tiled_64x8x16")}[mode]
+            "per-stage": names.index("tiled_64x8x16")}[mode.replace("-persistent", "")]
     params, singles = [], []
     for (n, dx, phi, U, V, W) in cases:
         params.append(pf.make_params(n, dx, dx, 1.0, fx.rk4_dt_3d(dx, 1.0, dx), dtype=dtype))
     params[0].variant = pick
     st = torch.cuda.Stream()
     bs = pf.BatchSolver(params)
+    if mode.endswith("persistent"):
+        bs.set_persistent(True)
     bt = [[dev(a, tdt) for a in cs[2:]] for cs in cases]
     with torch.cuda.stream(st):
         bs.step([b[0] for b in bt], [b[1] for b in bt], [b[2] for b in bt], [b[3] for b in bt],
