@@ -9,7 +9,6 @@ been built — there is no fallback path.
 from __future__ import annotations
 
 import ctypes
-import math
 
 import torch
 
@@ -203,7 +202,3 @@ def _advance(solver, phi, u, v, w, t0, n0, m, single):
     else:
         solver.step(phi, u, v, w, t0 + n0 * dt, m)
 
-
-def rk4_dt_limit(dims: int, dx: float, gamma: float, eps: float) -> float:
-    """Eq. 28: 2.79 dx^2 / (4 D_f gamma eps)."""
-    return 2.79 * dx * dx / (4.0 * dims * gamma * eps) if gamma * eps > 0 else math.inf
