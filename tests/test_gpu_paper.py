@@ -7,8 +7,10 @@ A D = 1 drop in a 2 x 2 periodic box (dx = D/25) is carried by (u, v) = (sqrt2/2
 T = 2 sqrt2 with classic RK4 at dt = min(Eq. 31, Eq. 32), for the seven (eps/dx, gamma/|u|)
 points of Table 2. Checked against the paper: points 1-5 stay inside [0, 1] at every step, 6-7
 leave it. Checked against the oracle: the final field and E_delta = mean |phi(T) - phi(0)|.
-The printed E_delta, E_eps, E_tot of Table 1 depend on a relaxed top-hat initial condition the
-paper does not specify, so they are printed beside ours, not asserted.
+E_tot of Table 1 is asserted within 3 % for every point (it is dominated by E_eps, the initial
+profile's own departure from the top hat, which the tanh profile reproduces within 2.4 %); the
+printed E_delta column follows no reading of the unstated details that was tried (see the design
+notes), so E_delta is compared with the oracle's and printed beside the paper's.
 
 Tolerance. Several of these runs are ill-conditioned: where the tails of the drop's periodic
 images meet, grad phi vanishes and the unit normal g/|g| (delta = 0, as in the paper) flips under
@@ -105,6 +107,7 @@ def test_table2_classification_and_table1_errors_on_the_gpu(lib):
         assert abs(e_delta - e_delta_ref) <= tol
         e_eps = np.abs(phi0[0] - top_hat).mean()
         e_tot = np.abs(got[0] - top_hat).mean()
+        assert abs(e_tot - p["E_tot"]) <= 0.03 * p["E_tot"], (p["point"], e_tot, p["E_tot"])
         print(f"point {p['point']}: {ns} steps, min {lo:.3e}, max-1 {hi - 1:.3e}, "
               f"E_delta {e_delta:.5f} (paper {p['E_delta']}), E_eps {e_eps:.5f} "
               f"(paper {p['E_eps']}), E_tot {e_tot:.5f} (paper {p['E_tot']})", flush=True)
