@@ -74,8 +74,10 @@ typedef struct {
     int32_t bc[3];      /* pf_bc per axis. PF_BC_WALL: solid walls at x_a = 0 and n dx, with   */
                         /* zero total flux through the wall faces and mirror ghosts for the   */
                         /* central gradient; the face velocity stored at index 0 of a walled  */
-                        /* axis (the wall face) is ignored. Walls run on the per-stage        */
-                        /* kernels (a fused variant falls back to them); forward step only.   */
+                        /* axis (the wall face) is ignored. Walls on x and y run on every      */
+                        /* kernel (the fused sweeps included); with a walled z axis a fused   */
+                        /* variant runs the per-stage kernel. Forward step only (the adjoint  */
+                        /* and the batched driver take periodic axes).                        */
     int32_t dtype;      /* pf_dtype                                                            */
     int32_t scheme;     /* pf_scheme                                                           */
     int32_t vel_mode;   /* pf_velmode: velocity u0(x) * s(t), s = 1 or cos(pi t / vel_T)       */

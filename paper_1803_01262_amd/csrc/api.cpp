@@ -418,6 +418,7 @@ FusedArgs<T> pf::make_fused(const pf_params& p, bool sweep_b, double t, const T*
     a.ge = (T)(p.gamma * p.eps / (p.dx * p.dx));
     a.hg = (T)(0.5 * p.gamma / p.dx);
     a.delta2 = (T)(p.delta * p.delta);
+    a.walls = wall_mask(p) & 3;  // a walled z axis never reaches the fused sweeps
     a.phi = phi_cur;
     a.out_acc = phi_next;
     a.out_mid = nullptr;
@@ -504,10 +505,12 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
                              hipStream_t st)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
-    // the fused sweeps run RK4 and RK2 on periodic axes; otherwise their variants run the
-    // per-stage kernel
+    // the fused sweeps run RK4 and RK2 with periodic or walled x and y axes (arrays below 4 GiB
+    // when walled); otherwise their variants run the per-stage kernel
+    const int wm = wall_mask(p);
     const bool fused = (p.scheme == PF_RK4 || p.scheme == PF_RK2) && variant_is_fused(dtype, variant) &&
-                       wall_mask(p) == 0;
+                       (wm & 4) == 0 &&
+                       !(wm != 0 && field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T)));
     T* cur = phi;
     for (int m = 0; m < nsteps; ++m) {
         const double t = t0 + (double)m * p.dt;

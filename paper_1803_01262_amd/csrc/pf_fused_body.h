@@ -44,6 +44,14 @@
 // WIDE (nx a multiple of 16 bytes' worth of elements), the planes of the stage input and of phi
 // are read in 16-byte pieces: groups of consecutive x-columns that start at a multiple of the
 // group size never straddle the periodic wrap, so each group is one aligned load.
+// WALLS (x and/or y walled, a.walls bits 0 and 1; a walled z axis runs on the per-stage kernel):
+// the stage input and phi are read through mirror indices, so the sharpening products of the
+// ghost cells are the exact mirror images of their partners' (the normal component flips sign)
+// and the diffusive and sharpening fluxes through a wall face vanish; the face velocity on a
+// wall face counts as zero. E1 evaluates only cells inside the domain; after it, each ghost cell
+// of the middle-stage ring takes the value of its mirror partner (one more barrier), which is
+// exactly what the per-stage kernel reads there, so the walled sweeps stay bit-identical to the
+// per-stage launches.
 #pragma once
 
 #include <type_traits>
@@ -54,10 +62,12 @@
 namespace pf {
 
 // The workgroup owns the TX x TY column tile (ti, tj) and the output planes [k0, k1).
-template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT = false>
+template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT = false,
+          bool WALLS = false>
 __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int k0, int k1)
 {
     static_assert(!(XOUT && SWEEP_B), "the optional outputs belong to sweep A");
+    static_assert(!(WALLS && WIDE), "mirror reads are element-wise");
     constexpr int NT = TX * TY;
     constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte piece
     static_assert(TX % VEC == 0, "the tile width must be a whole number of 16-byte pieces");
@@ -103,6 +113,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     const int tx = tid % TX, ty = tid / TX;
     const bool active = (i0 + tx < nx) && (j0 + ty < ny);
     const T inv_2dx = a.inv_2dx, d2 = a.delta2, hg = a.hg, ge = a.ge;
+    // index maps of the stage input and phi: periodic wrap, or the mirror across walls
+    const bool wx = WALLS && (a.walls & 1), wy = WALLS && (a.walls & 2);
+    auto mapx = [&](int v) { return WALLS && wx ? reflectn(v, nx) : wrapn(v, nx); };
+    auto mapy = [&](int v) { return WALLS && wy ? reflectn(v, ny) : wrapn(v, ny); };
 
     // ---- E1 cell slots: slot 0 = own cell, slot 1 = a MID ring cell (tid < NRING)
     int e_lx[2], e_ly[2];
@@ -130,11 +144,20 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     // byte offsets within a plane of the slots' (wrapped) columns and their +1 neighbours
     constexpr unsigned ES = sizeof(T);
     unsigned e_col[2], e_colx[2], e_coly[2];
+    // WALLS: per slot, bit 0/1: its low/high x-face is a wall face, bit 2/3 likewise in y; bit 4:
+    // the cell is a ghost (outside the domain along a walled axis)
+    int e_wall[2] = {0, 0};
     for (int s = 0; s < 2; ++s) {
         const int gx = wrapn(i0 - 2 + e_lx[s], nx), gy = wrapn(j0 - 2 + e_ly[s], ny);
         e_col[s] = (unsigned)(gy * nx + gx) * ES;
         e_colx[s] = (unsigned)(gy * nx + wrapn(gx + 1, nx)) * ES;
         e_coly[s] = (unsigned)(wrapn(gy + 1, ny) * nx + gx) * ES;
+        if constexpr (WALLS) {
+            const int ux = i0 - 2 + e_lx[s], uy = j0 - 2 + e_ly[s];  // unwrapped
+            e_wall[s] = (wx && ux == 0 ? 1 : 0) | (wx && ux == nx - 1 ? 2 : 0) |
+                        (wy && uy == 0 ? 4 : 0) | (wy && uy == ny - 1 ? 8 : 0) |
+                        ((wx && (ux < 0 || ux >= nx)) || (wy && (uy < 0 || uy >= ny)) ? 16 : 0);
+        }
     }
     // ---- q1-only cell (x-outer: Q1X columns 0 and TX+5; y-outer: Q1Y rows 0 and TY+5)
     const int ro = tid - OUT0;
@@ -188,7 +211,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         } else {
             const int r = e / INW, c = e - r * INW;
             li_pos[s] = e < INS ? e : -1;
-            li_off[s] = e < INS ? (unsigned)(wrapn(j0 - 4 + r, ny) * nx + wrapn(i0 - 4 + c, nx)) * ES : 0u;
+            li_off[s] = e < INS ? (unsigned)(mapy(j0 - 4 + r) * nx + mapx(i0 - 4 + c)) * ES : 0u;
         }
     }
     unsigned lb_off[NLB > 0 ? NLB : 1];
@@ -205,7 +228,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
         } else {
             const int r = e / MW, c = e - r * MW;
             lb_pos[s] = e < MS ? e : -1;
-            lb_off[s] = e < MS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
+            lb_off[s] = e < MS ? (unsigned)(mapy(j0 - 2 + r) * nx + mapx(i0 - 2 + c)) * ES : 0u;
         }
     }
     // velocity staging loads: a flattened list of the U, V and W pieces, NLV per thread
@@ -351,6 +374,17 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             }
         }
 
+        if constexpr (WALLS) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (s == 1 && !has_ring) continue;
+                if (e_wall[s] & 1) eu0[s] = T(0);
+                if (e_wall[s] & 2) eu1[s] = T(0);
+                if (e_wall[s] & 4) ev0[s] = T(0);
+                if (e_wall[s] & 8) ev1[s] = T(0);
+            }
+        }
+
         const T* IA = s_in + sa * INS;  // plane t+2
         const T* IB = s_in + sb * INS;  // plane t+3
         const T* IC = s_in + sc * INS;  // plane t+4
@@ -436,6 +470,18 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             e_qzm[s] = e_qz[s];
             e_qz[s] = qzn[s];
             e_w0[s] = ew1[s];
+        }
+        if constexpr (WALLS) {
+            __syncthreads();  // every E1 value of plane t+2 is in YM
+            // ghost cells of the ring take their mirror partner's value
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (s == 1 && !has_ring) continue;
+                if (!(e_wall[s] & 16)) continue;
+                const int ux = i0 - 2 + e_lx[s], uy = j0 - 2 + e_ly[s];
+                const int mx = wx ? reflectn(ux, nx) : ux, my = wy ? reflectn(uy, ny) : uy;
+                YM[e_lx[s] + e_ly[s] * MW] = YM[(mx - (i0 - 2)) + (my - (j0 - 2)) * MW];
+            }
         }
         __syncthreads();  // ya at plane t+2 visible
 

@@ -10,8 +10,9 @@ namespace pf {
 // One workgroup per (tile, z-chunk of kz planes); the chunk length is a launch argument.
 // FP32: at least four waves per SIMD (at most 128 VGPRs), two workgroups of eight waves per CU.
 // FP64 needs more registers than that and runs at two waves per SIMD.
-// XOUT: sweep A with its optional outputs (out_mid, out_phi).
-template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT>
+// XOUT: sweep A with its optional outputs (out_mid, out_phi). WALLS: x and/or y walled
+// (a.walls), element-wise plane loads, single-descriptor addressing.
+template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT, bool WALLS = false>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y, int kz)
 {
@@ -20,21 +21,21 @@ fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y, int kz)
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int k0 = (b / tiles_y) * kz;
-    fused_body<T, TX, TY, SWEEP_B, BIG, WIDE, XOUT>(a, ti, tj, k0, min(k0 + kz, a.nz));
+    fused_body<T, TX, TY, SWEEP_B, BIG, WIDE, XOUT, WALLS>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
-template <typename T, int TX, int TY, bool BIG, bool WIDE>
+template <typename T, int TX, int TY, bool BIG, bool WIDE, bool WALLS = false>
 hipError_t launch_fused_sweep(const FusedArgs<T>& a, bool sweep_b, unsigned blocks, int tiles_x,
                               int tiles_y, int kz, hipStream_t st)
 {
     if (sweep_b)
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, true, BIG, WIDE, false>), dim3(blocks),
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, true, BIG, WIDE, false, WALLS>), dim3(blocks),
                            dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     else if (a.out_mid || a.out_phi)
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE, true>), dim3(blocks),
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE, true, WALLS>), dim3(blocks),
                            dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     else
-        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE, false>), dim3(blocks),
+        hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE, false, WALLS>), dim3(blocks),
                            dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     return hipGetLastError();
 }
@@ -51,6 +52,21 @@ hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st)
     // 16-byte plane loads need rows that are a whole number of 16-byte pieces
     const bool wide = a.nx % (16 / (int)sizeof(T)) == 0;
     const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
+    if (a.walls) {
+        // walled x/y: one form (mirror reads element by element, single-descriptor addressing:
+        // arrays below 4 GiB, also for the variants that force the large-array form)
+        if (field_needs_big(a.nx, a.ny, a.nz, sizeof(T))) return hipErrorInvalidValue;
+        int kzw = KZ;
+        if (KZ == 0) {
+            const void* k = (const void*)fused_kernel<T, TX, TY, false, false, false, false, true>;
+            kzw = launch_chunk_planes(k, TX * TY, (long long)tiles_x * tiles_y, a.nz, 5);
+            if (kzw <= 0) return hipErrorInvalidDevice;
+        }
+        const long long wb = (long long)tiles_x * tiles_y * ((a.nz + kzw - 1) / kzw);
+        if (wb <= 0 || wb > 0x7fffffffLL) return hipErrorInvalidValue;
+        return launch_fused_sweep<T, TX, TY, false, false, true>(a, sweep_b, (unsigned)wb, tiles_x,
+                                                                 tiles_y, kzw, st);
+    }
     int kz = KZ;
     if (KZ == 0) {
         // sweeps A and B share the register budget, hence the residency, of their form

@@ -1,7 +1,9 @@
 """GPU parity of the solid-wall boundaries (through the C ABI).
 
-Walls run on the per-stage kernels (tiled and one-thread-per-cell; fused variants fall back to
-the per-stage default). Bars as for the periodic grids: FP64 <= 1e-12 relative L-inf against the
+Walls on x and y run on every kernel: per-stage (tiled, one-plane, one-thread-per-cell) and the
+fused two-stage sweeps (mirror reads, ghost cells of the middle stage copied from their mirror
+partners); a walled z axis runs on the per-stage kernels (fused variants fall back to the
+per-stage default). Bars as for the periodic grids: FP64 <= 1e-12 relative L-inf against the
 oracle with the same walls, FP32 <= 1e-5 against its FP32-storage mode, every variant bitwise
 equal to every other. The face velocity on the wall faces is random (it must be ignored).
 """
@@ -49,7 +51,9 @@ def run(pf, phi, U, V, W, *, variant, dtype, walls, **kw):
 CASES = [("f64", (12, 10, 70), (True, False, False)), ("f64", (9, 33, 17), (False, True, False)),
          ("f64", (20, 6, 9), (False, False, True)), ("f64", (7, 13, 66), (True, True, True)),
          ("f64", (1, 30, 40), (True, True, False)), ("f64", (3, 2, 1), (False, True, True)),
-         ("f32", (18, 12, 68), (True, False, True)), ("f32", (1, 37, 33), (True, True, False))]
+         ("f32", (18, 12, 68), (True, False, True)), ("f32", (1, 37, 33), (True, True, False)),
+         ("f32", (20, 45, 70), (True, True, False)), ("f64", (16, 40, 36), (True, True, False)),
+         ("f32", (24, 70, 130), (True, False, False)), ("f64", (21, 35, 67), (False, True, False))]
 
 
 @pytest.mark.parametrize("dtype,shape,walls", CASES)
@@ -71,14 +75,18 @@ def test_walls_every_variant_matches_oracle_and_each_other(lib, dtype, shape, wa
         assert np.array_equal(o, outs[0]), f"variant {v} differs from variant 0"
 
 
-@pytest.mark.parametrize("scheme,sch", [("euler", 1), ("rk2", 2)])
-def test_walls_other_schemes(lib, scheme, sch):
+@pytest.mark.parametrize("scheme,sch,walls", [("euler", 1, (True, False, True)),
+                                              ("rk2", 2, (True, False, True)),
+                                              ("rk2", 2, (True, True, False))])
+def test_walls_other_schemes(lib, scheme, sch, walls):
     phi, U, V, W, dx = wall_case(5, (10, 12, 14))
-    walls = (True, False, True)
     kw = dict(dx=dx, eps=dx, gamma=1.0, dt=0.08 * dx, nsteps=7, scheme=scheme)
     ref = oracle.step(phi, U, V, W, walls=walls, **{**kw, "scheme": sch})
     got = run(lib, phi, U, V, W, variant=-1, dtype="f64", walls=walls, **kw)
     assert rel_linf(got, ref) <= TOL64
+    names = [lib.phasefield_variant_name(lib.PF_F64, v) for v in range(lib.phasefield_variant_count(lib.PF_F64))]
+    fused = run(lib, phi, U, V, W, variant=names.index("fused_32x16x32"), dtype="f64", walls=walls, **kw)
+    assert np.array_equal(fused, got)
 
 
 def test_walls_conserve_mass_and_reject_the_adjoint(lib):
