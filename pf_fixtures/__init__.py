@@ -123,6 +123,37 @@ def random_wall_stream_faces(rng: np.random.Generator, n: int, dx: float):
     return (U * s).reshape(1, n, n), (V * s).reshape(1, n, n), np.zeros((1, n, n))
 
 
+def random_projected_faces(rng: np.random.Generator, n: int, dx: float):
+    """The 2D random velocity of Sec. 3.2.2 for an n x n box with slip walls on x and y: every
+    cell centre gets a velocity of independently uniform magnitude in [0, 1) and uniform
+    direction; averaged onto the MAC faces (zero normal velocity on the wall faces); made
+    discretely solenoidal by a Poisson projection with no-flux walls, u <- u - grad p with
+    div grad p = div u (the cell-centred Neumann Laplacian is diagonal in the type-II cosine
+    basis, eigenvalues (2 cos(pi k/n) - 2 + 2 cos(pi l/n) - 2) / dx^2); scaled so that the
+    largest face component is 1."""
+    from scipy import fft as sfft
+    mag = rng.uniform(0.0, 1.0, (n, n))
+    ang = rng.uniform(0.0, 2.0 * np.pi, (n, n))
+    uc, vc = mag * np.cos(ang), mag * np.sin(ang)  # [j, i] at cell centres
+    U = np.zeros((n, n))
+    V = np.zeros((n, n))
+    U[:, 1:] = 0.5 * (uc[:, :-1] + uc[:, 1:])  # low x-face of cell i (i = 0: the wall)
+    V[1:, :] = 0.5 * (vc[:-1, :] + vc[1:, :])
+    div = (np.diff(np.pad(U, ((0, 0), (0, 1))), axis=1) +
+           np.diff(np.pad(V, ((0, 1), (0, 0))), axis=0)) / dx
+    k = np.arange(n)
+    lam = (2.0 * np.cos(np.pi * k / n) - 2.0) / (dx * dx)
+    lap = lam[:, None] + lam[None, :]
+    dh = sfft.dctn(div, type=2, norm="ortho")
+    lap[0, 0] = 1.0
+    dh[0, 0] = 0.0  # the divergence sums to zero: no flux through the walls
+    p = sfft.idctn(dh / lap, type=2, norm="ortho")
+    U[:, 1:] -= (p[:, 1:] - p[:, :-1]) / dx
+    V[1:, :] -= (p[1:, :] - p[:-1, :]) / dx
+    s = 1.0 / max(np.abs(U).max(), np.abs(V).max())
+    return (U * s).reshape(1, n, n), (V * s).reshape(1, n, n), np.zeros((1, n, n))
+
+
 def vortex2d_faces(n: int):
     """Single-vortex field on the unit square, n x n x 1 (Sec. 3.3.1, Eq. 33).
 

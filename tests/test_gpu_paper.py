@@ -355,20 +355,23 @@ def test_zalesak_disk_one_revolution(lib):
     assert errs[1] < errs[0] and errs[2] < errs[1], errs
 
 
+@pytest.mark.parametrize("field", ["projected", "stream"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_random_velocity_field_with_slip_walls(lib, seed):
+def test_random_velocity_field_with_slip_walls(lib, seed, field):
     """Sec. 3.2.2 on the HIP stepper: a D = 1 drop at the centre of a 2 x 2 box with slip walls
     (walls on x and y), a steady velocity that changes randomly from cell to cell, solenoidal,
-    with largest face component 1 (a random stream function vanishing on the walls, in place of
-    the paper's Poisson projection of random vectors), T = 10, dx = D/25, RK4 at
-    min(Eq. 31, Eq. 32), for the seven (eps/dx, gamma/u) points of Table 2. The paper finds
-    every point bounded at all times except point 7; so does this run, for each seed checked.
-    Point 2 is compared with the oracle (tolerance measured on the oracle, as above)."""
+    with largest face component 1, T = 10, dx = D/25, RK4 at min(Eq. 31, Eq. 32), for the seven
+    (eps/dx, gamma/u) points of Table 2. Two constructions of the field: the paper's (random
+    point vectors of uniform magnitude and direction, made solenoidal by a Poisson projection with
+    no-flux walls) and a random stream function vanishing on the walls. The paper finds every
+    point bounded at all times except point 7; so does this run, for each field and seed checked.
+    Point 2 is compared with the oracle (bar derived on the oracle, as above)."""
     pf = lib
     pts = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
     n, L, T = 50, 2.0, 10.0
     dx = L / n
-    U, V, W = fx.random_wall_stream_faces(np.random.default_rng(100 + seed), n, dx)
+    make = fx.random_projected_faces if field == "projected" else fx.random_wall_stream_faces
+    U, V, W = make(np.random.default_rng(100 + seed), n, dx)
     walls = (True, True, False)
     st = torch.cuda.Stream()
     for p in pts["points"]:
@@ -389,24 +392,28 @@ def test_random_velocity_field_with_slip_walls(lib, seed):
         got = g[0].cpu().numpy()
         s.close()
         bounded = lo >= -EPS64 and hi <= 1 + EPS64
-        print(f"seed {seed} point {p['point']}: {ns} steps, min {lo:.2e}, max-1 {hi - 1:.2e}",
-              flush=True)
+        print(f"{field} seed {seed} point {p['point']}: {ns} steps, min {lo:.2e}, "
+              f"max-1 {hi - 1:.2e}", flush=True)
         assert bounded == (p["point"] != 7), (p["point"], lo, hi)
         if p["point"] == 2:
             kw = dict(dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=ns, walls=walls)
             ref = oracle.step(phi0, U, V, W, **kw)
-            check_against_oracle(got, ref, phi0, (U, V, W), kw, seed, f"random field seed {seed} point 2")
+            check_against_oracle(got, ref, phi0, (U, V, W), kw, seed,
+                                 f"{field} random field seed {seed} point 2")
 
 
 def test_drop_in_shear_flow_second_order(lib):
     """Sec. 3.3.1 on the HIP stepper: the R = 0.15 drop at (0.5, 0.75) in the reversing single
     vortex (Eq. 33, T = 4), RK4 at dt = dx/8, eps/dx = 0.7 and gamma / max|u| = 2.5 (on the
     crossover line), at N = 64, 128, 256, 512. The paper reports E_shape of Eq. 34 (the L1
-    distance between phi(T) and phi(0)) falling at about second order (Fig. 11): here it falls at
-    every doubling and its mean order from N = 64 to 512 lies in [1.5, 2.5] (the single-doubling
-    orders are irregular: about 2.7, 2.0, 1.1, and 1.6 to N = 1024 in a separate measurement;
-    dt = dx/16 changes E_shape at N = 512 by 1e-5 relative, so the spread is spatial). phi stays
-    in [0, 1] (checked at t = T/2 and T) and the mass is conserved."""
+    distance between phi(T) and phi(0)) falling at about second order (Fig. 11). A sweep over
+    N = 64 ... 1024 (ratios 1.5 and 4/3) shows second order up to N = 256 (least squares 2.4 over
+    64-256) and a slower rate above it (1.5 over 128-1024): with eps/dx fixed, the first-order
+    floor that Sec. 3.1 explains (the sign switch of n, E_delta ~ dx; and E_eps ~ eps ~ dx) takes
+    over at fine meshes; dt = dx/16 changes E_shape at N = 512 by 1e-5 relative, so the rate is
+    spatial. Asserted: each of the two doublings up to N = 256 at order >= 1.5, the finest
+    doubling at order > 0.5, and the mean order over 64-512 in [1.5, 2.5]; phi stays in [0, 1]
+    (checked at t = T/2 and T) and the mass is conserved."""
     pf = lib
     T = 4.0
     errs = []
@@ -435,7 +442,7 @@ def test_drop_in_shear_flow_second_order(lib):
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     mean_order = math.log2(errs[0] / errs[-1]) / (len(errs) - 1)
     print("observed orders", orders, "mean", mean_order, flush=True)
-    assert all(o > 0.5 for o in orders), orders
+    assert orders[0] >= 1.5 and orders[1] >= 1.5 and orders[2] > 0.5, orders
     assert 1.5 <= mean_order <= 2.5, mean_order
 
 
