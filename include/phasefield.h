@@ -162,6 +162,15 @@ pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);
 
+/* How phasefield_adjoint_step runs the four reverse stages of RK4 (other schemes always take
+ * one per launch): 0 one stage per launch; 1 two per launch (a kernel that keeps the later
+ * stage's adjoint and flux-Jacobian terms in LDS and hands them to the earlier stage of the same
+ * tile: fewer field passes, but more registers per thread); -1 (the default) two per launch for
+ * FP64 on grids of 192^3 cells and more when the handle's variant is a fused one, else one.
+ * Every form gives bit-identical results. Fields of 4 GiB or more always take one per launch.
+ * Errors: PF_ERR_INVALID (NULL handle, form outside -1..1). */
+pf_status phasefield_set_adjoint_form(pf_solver *s, int32_t form);
+
 /* Mass and bounds of a field: out4 = {sum(phi) * dx^D, min(phi), max(phi), #non-finite},
  * D = number of axes longer than one cell; the sum is accumulated in double in a fixed order
  * (deterministic). Non-finite cells are left out of sum, min and max. SYNCHRONISES

@@ -83,6 +83,7 @@ def _load():
         "phasefield_variant_name": (ctypes.c_char_p, [i32, i32]),
         "phasefield_autotune": (i32, [vp, i32, P(i32), P(d), vp]),
         "phasefield_solver_variant": (i32, [vp]),
+        "phasefield_set_adjoint_form": (i32, [vp, i32]),
         "phasefield_batch_create": (i32, [P(Params), i32, P(vp)]),
         "phasefield_batch_step": (i32, [vp, P(vp), P(vp), P(vp), P(vp), P(d), i32, vp]),
         "phasefield_batch_destroy": (i32, [vp]),
@@ -106,6 +107,7 @@ EXPORTED = ("phasefield_default_params", "phasefield_check_params", "phasefield_
             "phasefield_reduce", "phasefield_velocity_from_coeffs",
             "phasefield_velocity_coeffs_grad", "phasefield_variant_count",
             "phasefield_variant_name", "phasefield_autotune", "phasefield_solver_variant",
+            "phasefield_set_adjoint_form",
             "phasefield_batch_create", "phasefield_batch_step", "phasefield_batch_destroy",
             "phasefield_batch_set_persistent",
             "phasefield_last_error", "phasefield_step_noalloc",
@@ -288,6 +290,10 @@ def phasefield_batch_step(h, params_list, phis, us, vs, ws, t0s=None, nsteps=1, 
     t0 = None if t0s is None else (ctypes.c_double * B)(*[float(x) for x in t0s])
     _check(lib.phasefield_batch_step(h, arr(phis, "phi"), arr(us, "u"), arr(vs, "v"),
                                      arr(ws, "w"), t0, int(nsteps), _stream(stream)))
+
+
+def phasefield_set_adjoint_form(h, form: int) -> None:
+    _check(lib.phasefield_set_adjoint_form(h, int(form)))
 
 
 def phasefield_batch_set_persistent(h, persistent: bool) -> None:

@@ -43,6 +43,46 @@ static AdjArgs<T> make_adj(const pf_params& p, double svel, const T* y, const T*
     return a;
 }
 
+template <typename T>
+static AdjPairArgs<T> make_pair(const pf_params& p, double svelH, double svelL, const T* yH,
+                                const T* srcH, double kscaleH, const T* yL, const T* lamp,
+                                const T* base, T* L_out, T* kout, T* lam_copy, double kaL,
+                                double kbL, double kaO, double kbO, T* gU, T* gV, T* gW,
+                                const T* U, const T* V, const T* W)
+{
+    AdjPairArgs<T> a;
+    a.yH = yH;
+    a.srcH = srcH;
+    a.kscaleH = (T)kscaleH;
+    a.yL = yL;
+    a.lamp = lamp;
+    a.base = base;
+    a.L_out = L_out;
+    a.kout = kout;
+    a.lam_copy = lam_copy;
+    a.kaL = (T)kaL;
+    a.kbL = (T)kbL;
+    a.kaO = (T)kaO;
+    a.kbO = (T)kbO;
+    a.gU = gU;
+    a.gV = gV;
+    a.gW = gW;
+    a.U = U;
+    a.V = V;
+    a.W = W;
+    a.nx = p.n[0];
+    a.ny = p.n[1];
+    a.nz = p.n[2];
+    a.inv_dx = (T)(1.0 / p.dx);
+    a.inv_2dx = (T)(1.0 / (2.0 * p.dx));
+    a.ge = (T)(p.gamma * p.eps / p.dx);
+    a.hg = (T)(0.5 * p.gamma);
+    a.hsH = (T)(0.5 * svelH);
+    a.hsL = (T)(0.5 * svelL);
+    a.delta2 = (T)(p.delta * p.delta);
+    return a;
+}
+
 // Reverse sweep of one classic RK4 step  phi' = phi + dt/6 (k1 + 2k2 + 2k3 + k4),
 // y1 = phi, y2 = phi + dt/2 k1, y3 = phi + dt/2 k2, y4 = phi + dt k3, k_s = f(y_s, t_s):
 //   kap4 = dt/6 lam'                       lam_n = lam' + sum_s ybar_s,
@@ -159,7 +199,38 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     }
     if (e == hipSuccess)
         e = run_stage<T>(vs, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W), st);
-    // reverse stages
+    // reverse stages: one per launch, or two per launch (adjoint_fused.hip, the same
+    // arithmetic as the single stages below, bit for bit): (4, 3) writes L = lam' + ybar4 +
+    // ybar3, kap2 into Kb and a copy of lam' into Ka (so that (2, 1) can write lam in place while
+    // it still reads lam' around its tile); (2, 1) writes lam = L + ybar2 + ybar1.
+    // Chosen per grid: FP64 with a fused forward variant on grids of 192^3 cells and more
+    // (measured 0.92-0.99 of the single-stage time from 192^3 to 512^3, 1.13 at 128^3); never in
+    // FP32, where the pair kernel needs about 170 registers (two waves per SIMD) and measured
+    // 1.08-1.44 times slower from 128^3 to 512^3.
+    const size_t cells = (size_t)p.n[0] * p.n[1] * p.n[2];
+    const bool pair_auto = variant_is_fused(p.dtype, v) && p.dtype == PF_F64 &&
+                           cells >= (size_t)192 * 192 * 192;
+    const bool pair = (s->adjoint_form == 1 || (s->adjoint_form < 0 && pair_auto)) &&
+                      !field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T));
+    if (pair) {
+        // a fused forward variant lends its tile shape (64x8 or 32x16) and fixed chunk length, if
+        // it names one; otherwise 64x8 unless 64-wide tiles pad more columns, chunks per launch
+        int ftx = 0, fty = 0, fkz = 0;
+        const int fgot = std::sscanf(vname, "fused_%dx%dx%d", &ftx, &fty, &fkz);
+        int pt = adjoint_default_tile(p.n[0], p.n[1], p.n[2]) == 0 ? 0 : 1;
+        if (fgot >= 2 && ftx == 64 && fty == 8) pt = 0;
+        if (fgot >= 2 && ftx == 32 && fty == 16) pt = 1;
+        const int pkz = fgot >= 3 ? fkz : 0;
+        if (e == hipSuccess)
+            e = launch_adjoint_pair<T>(make_pair<T>(p, s4, s2, y4, lam, dt / 6.0, y3, lam, lam, L,
+                                                    Kb, Ka, dt, dt / 3.0, 0.5 * dt, dt / 3.0, gU,
+                                                    gV, gW, U, V, W), pt, pkz, st);
+        if (e == hipSuccess)
+            e = launch_adjoint_pair<T>(make_pair<T>(p, s2, s1, y2, Kb, 1.0, phi, Ka, L, lam,
+                                                    nullptr, nullptr, 0.5 * dt, dt / 6.0, 0.0, 0.0,
+                                                    gU, gV, gW, U, V, W), pt, pkz, st);
+        return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
+    }
     if (e == hipSuccess)
         e = adj(make_adj<T>(p, s4, y4, lam, dt / 6.0, lam, L, lam, Ka, dt / 3.0,
                                                 dt, gU, gV, gW, U, V, W), st);
@@ -267,4 +338,12 @@ extern "C" pf_status phasefield_velocity_coeffs_grad(const pf_params* p, int32_t
     (void)hipFree(scratch);
     if (e == hipSuccess) e = e2;
     return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_velocity_coeffs_grad");
+}
+
+extern "C" pf_status phasefield_set_adjoint_form(pf_solver* s, int32_t form)
+{
+    if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
+    if (form < -1 || form > 1) return fail(PF_ERR_INVALID, "adjoint form %d is not -1, 0 or 1", (int)form);
+    s->adjoint_form = form;
+    return PF_OK;
 }

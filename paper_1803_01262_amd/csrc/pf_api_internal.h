@@ -75,6 +75,7 @@ struct pf_solver {
     size_t N = 0;       // cells
     size_t esz = 0;     // bytes per element
     int variant = 0;
+    int adjoint_form = -1;  // reverse RK4 stages: -1 chosen per grid, 0 one per launch, 1 two
     void* ya = nullptr;  // RK stage buffers
     void* yb = nullptr;
     void* acc = nullptr;

@@ -63,6 +63,33 @@ struct AdjArgs {
     T inv_dx, inv_2dx, ge, hg, hs, delta2;
 };
 
+// Two reverse RK4 stages in one sweep (adjoint_fused.hip): stage H then stage L.
+//   kap_H = kscaleH * srcH (read with a stencil); ybar_H = (df/dy at yH)^T kap_H;
+//   kap_L = kaL ybar_H + kbL lamp (on the tile plus a halo, in LDS);  ybar_L at yL;
+//   L_out = (base + ybar_H) + ybar_L;  kout = kaO ybar_L + kbO lamp (nullable);
+//   lam_copy = lamp (nullable);  gU/gV/gW += both stages' velocity gradients (nullable).
+template <typename T>
+struct AdjPairArgs {
+    const T* yH;
+    const T* srcH;
+    T kscaleH;
+    const T* yL;
+    const T* lamp;   // lambda' (read on the tile plus a two-cell halo)
+    const T* base;   // at the cell
+    T* L_out;
+    T* kout;
+    T* lam_copy;
+    T kaL, kbL, kaO, kbO;
+    T* gU;
+    T* gV;
+    T* gW;
+    const T* U;
+    const T* V;
+    const T* W;
+    int nx, ny, nz;
+    T inv_dx, inv_2dx, ge, hg, hsH, hsL, delta2;
+};
+
 // Two RK4 stages in one sweep (pf_fused_body.h): E1 evaluates f on the stage input y over the
 // tile plus a two-cell halo and keeps y_mid = base + c_mid f1 in LDS; E2 evaluates f on y_mid.
 //   sweep A: y = phi;  writes out_y = phi + c_y2 f2 and out_acc = (phi + c_acc1 f1) + c_acc2 f2
@@ -189,6 +216,10 @@ int adjoint_tile_index(int tx, int ty);               // -1 if that shape has no
 int adjoint_default_tile(int nx, int ny, int nz);
 template <typename T>
 hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st);  // one thread per cell
+// Two reverse stages per launch (tile 0: 64x8, 1: 32x16; kz 0: chosen per launch). Arrays of
+// 4 GiB or more are refused (hipErrorInvalidValue): the caller runs single stages then.
+template <typename T>
+hipError_t launch_adjoint_pair(const AdjPairArgs<T>& a, int tile, int kz, hipStream_t st);
 
 // ------------------------------------------------------------------ reduction (reduce.hip)
 constexpr int kReduceBlocks = 2048;

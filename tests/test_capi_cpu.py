@@ -115,3 +115,8 @@ def test_noalloc_step_refuses_oversized_grid_on_the_host(pf):
     p = pf.make_params((8, 8, 8), 0.0, 0.1, 1.0, 0.01)  # dx = 0: parameter check first
     st = pf.lib.phasefield_step_noalloc(ctypes.byref(p), fake, fake, fake, fake, 0.0, 1, None)
     assert st == pf.PF_ERR_INVALID
+
+
+def test_adjoint_form_setter_checks_its_arguments(pf):
+    assert pf.lib.phasefield_set_adjoint_form(None, 0) == pf.PF_ERR_INVALID
+    assert "NULL" in pf.phasefield_last_error()

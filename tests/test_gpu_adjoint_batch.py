@@ -78,13 +78,16 @@ def test_adjoint_step_fp64_matches_oracle(lib, scheme, shape):
 
 @pytest.mark.parametrize("dtype,shape,scheme", [("f64", (20, 16, 70), "rk4"), ("f32", (33, 9, 65), "rk4"),
                                                 ("f64", (1, 12, 5), "rk4"), ("f64", (20, 16, 70), "rk2"),
-                                                ("f64", (20, 16, 70), "rk3")])
+                                                ("f64", (20, 16, 70), "rk3"), ("f32", (70, 37, 130), "rk4"),
+                                                ("f64", (45, 20, 66), "rk4"), ("f32", (3, 40, 64), "rk4")])
 def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape, scheme):
     """The tiled adjoint stage kernel and the one-thread-per-cell kernel (paired with the
     'global' forward variant) give bit-identical lam and velocity gradients, for every adjoint
     tile shape and chunk length (lent by the per-stage forward variant of that shape; none in
-    its name: chosen per launch), the large-array addressing form (a '_big' variant) and fused
-    forward variants (tile chosen by size, chunk per launch)."""
+    its name: chosen per launch), the large-array addressing form (a '_big' variant) and the
+    RK4 reverse stages run two per launch (64x8 and 32x16 tiles lent by fused variants or chosen
+    for the grid, 32- and 64-plane chunks or chunks chosen per launch, ragged tiles, several
+    chunks)."""
     pf = lib
     rng, phi, U, V, W, lam, dx = adj_case(4, shape)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -92,11 +95,16 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape, scheme):
     names = [pf.phasefield_variant_name(kd, v) for v in range(pf.phasefield_variant_count(kd))]
     kw = dict(dx=dx, eps=dx, gamma=1.2, dt=0.12 * dx, delta=0.05 / dx, dtype=dtype, scheme=scheme)
     nz, ny, nx = shape
-    picks = ["global", "tiled_64x8x64", "tiled_64x8x16", "tiled_64x4x16", "tiled_32x4x16",
-             "tiled_64x8x16_big", "fused_32x16x32", "tiled_64x4", "tiled_32x4", "fused_64x8"]
+    # (variant, adjoint form): form 1 runs the RK4 reverse stages two per launch, 0 one per
+    # launch, -1 lets the handle choose (one per launch on these small grids)
+    picks = [("global", -1), ("tiled_64x8x64", -1), ("tiled_64x8x16", -1), ("tiled_64x4x16", -1),
+             ("tiled_32x4x16", -1), ("tiled_64x8x16_big", -1), ("fused_32x16x32", 0),
+             ("tiled_64x4", -1), ("tiled_32x4", -1), ("fused_64x8", -1), ("fused_64x8", 1),
+             ("fused_64x8x32", 1), ("fused_32x16x64", 1), ("fused_32x16", 1), ("tiled_64x8", 1)]
     res = []
-    for v in (names.index(nm) for nm in picks):
-        s = pf.Solver((nx, ny, nz), variant=v, **kw)
+    for nm, form in picks:
+        s = pf.Solver((nx, ny, nz), variant=names.index(nm), **kw)
+        s.set_adjoint_form(form)
         g = [dev(a, tdt) for a in (phi, U, V, W)]
         L = dev(lam, tdt)
         grads = [torch.zeros_like(g[0]) for _ in range(3)]
@@ -104,9 +112,13 @@ def test_tiled_adjoint_bitwise_equals_plain(lib, dtype, shape, scheme):
         torch.cuda.synchronize()
         res.append([L] + grads)
         s.close()
-    for nm, other in zip(picks[1:], res[1:]):
+    for pick, other in zip(picks[1:], res[1:]):
         for a, b in zip(res[0], other):
-            assert torch.equal(a, b), nm
+            assert torch.equal(a, b), pick
+    s = pf.Solver((nx, ny, nz), **kw)
+    with pytest.raises(pf.PhaseFieldError):
+        s.set_adjoint_form(2)
+    s.close()
 
 
 def test_adjoint_step_fp32_close_to_fp64_oracle(lib):

@@ -141,15 +141,18 @@ def test_4gib_fields_switch_to_per_plane_addressing(lib):
     assert worst <= 1e-5
 
 
+@pytest.mark.parametrize("form", [-1, 1])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-3)])
-def test_adjoint_workload_full_grid(lib, dtype, tol):
+def test_adjoint_workload_full_grid(lib, dtype, tol, form):
     """The adjoint workload at its full size (128^3, 8-mode field, delta = 1e-3/dx): one adjoint
     step in the configuration the benchmark times (default variant: fused sweeps recompute the
     stage inputs, tiled reverse stages) against the oracle's FP64 adjoint on every cell, for
     lambda and the three face-velocity gradients, at the fixed bars: 1e-12 in FP64, and 1e-3 for
     FP32 storage against the FP64 oracle. With this delta the problem is well conditioned: the
     oracle's own output moves by about 2e-14 (FP64) and 9e-6 (FP32) when phi is scaled by
-    1 + u (seeded noise, u the storage's unit roundoff); the test prints that response."""
+    1 + u (seeded noise, u the storage's unit roundoff); the test prints that response.
+    Run with the reverse RK4 stages the handle chooses (one per launch at this size) and with
+    two per launch."""
     pf = lib
     c = fx.adjoint_case(128)
     U, V, W = oracle.velocity_from_coeffs(c.shape, dx=c.dx, phases=c.modes[0], coeffs=c.modes[1])
@@ -165,7 +168,8 @@ def test_adjoint_workload_full_grid(lib, dtype, tol):
                               delta=c.delta)
     n = c.shape[0]
     s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, delta=c.delta)
-    print(dtype, "variant", s.variant_name, flush=True)
+    s.set_adjoint_form(form)
+    print(dtype, "variant", s.variant_name, "adjoint form", form, flush=True)
     g = [torch.tensor(a, dtype=tdt, device="cuda") for a in (phi, U, V, W)]
     L = torch.tensor(lam, dtype=tdt, device="cuda")
     grads = [torch.zeros_like(L) for _ in range(3)]
