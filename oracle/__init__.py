@@ -66,6 +66,10 @@ def _l():
                                           p, p, p, p]
         _lib.orc_velocity_from_coeffs.argtypes = [gp, ctypes.c_int, p, p, p, p, p]
         _lib.orc_velocity_from_coeffs_T.argtypes = [gp, ctypes.c_int, p, p, p, p, p]
+        _lib.orc_rhs_nu.argtypes = [gp, p, p, p, ctypes.c_int, d, p, p, p, p, p]
+        _lib.orc_step_nu.argtypes = [gp, p, p, p, ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d,
+                                     ctypes.c_int, d, i64, p, p, p, p]
+        _lib.orc_reduce_nu.argtypes = [gp, p, p, p, p, p]
         _lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib.orc_max_threads.restype = ctypes.c_int
     return _lib
@@ -201,3 +205,54 @@ def velocity_from_coeffs_T(shape, *, dx, phases, Ubar, Vbar, Wbar) -> np.ndarray
     _l().orc_velocity_from_coeffs_T(ctypes.byref(g), M, _ptr(phases), _ptr(Ubar), _ptr(Vbar),
                                     _ptr(Wbar), _ptr(cb))
     return cb
+
+
+def _widths(shape, hx, hy, hz):
+    nz, ny, nx = shape
+    out = []
+    for h, n, name in ((hx, nx, "hx"), (hy, ny, "hy"), (hz, nz, "hz")):
+        h = _f64(h).ravel()
+        if h.size != n or not np.all(np.isfinite(h)) or not np.all(h > 0):
+            raise ValueError(f"{name} must hold {n} positive finite widths")
+        out.append(h)
+    return out
+
+
+def rhs_nu(phi, U, V, W, *, hx, hy, hz, dx, eps, gamma, delta=0.0, s=1.0, eps_mode=0,
+           walls=(False, False, False)) -> np.ndarray:
+    """rhs() on a non-uniform rectilinear mesh with cell widths hx (nx), hy (ny), hz (nz).
+
+    eps_mode 0: eps everywhere; 1: eps * max(h_x, h_y, h_z) / dx per cell (dx the reference
+    spacing of eps), averaged onto faces. See pf_oracle.c for the discrete form."""
+    phi, U, V, W = map(_f64, (phi, U, V, W))
+    h = _widths(phi.shape, hx, hy, hz)
+    f = np.empty_like(phi)
+    g = _grid(phi.shape, dx, eps, gamma, delta, walls)
+    _l().orc_rhs_nu(ctypes.byref(g), *(_ptr(a) for a in h), int(eps_mode), s, _ptr(phi), _ptr(U),
+                    _ptr(V), _ptr(W), _ptr(f))
+    return f
+
+
+def step_nu(phi, U, V, W, *, hx, hy, hz, dx, eps, gamma, dt, nsteps=1, delta=0.0, t0=0.0,
+            scheme=4, fp32=False, vel_mode=0, vel_T=1.0, eps_mode=0,
+            walls=(False, False, False)) -> np.ndarray:
+    """step() on a non-uniform rectilinear mesh (widths and eps_mode as rhs_nu)."""
+    _check_scheme(scheme)
+    out = _f64(phi).copy()
+    U, V, W = map(_f64, (U, V, W))
+    h = _widths(out.shape, hx, hy, hz)
+    g = _grid(out.shape, dx, eps, gamma, delta, walls)
+    _l().orc_step_nu(ctypes.byref(g), *(_ptr(a) for a in h), int(eps_mode), int(scheme),
+                     int(bool(fp32)), dt, t0, int(vel_mode), float(vel_T), int(nsteps), _ptr(out),
+                     _ptr(U), _ptr(V), _ptr(W))
+    return out
+
+
+def reduce_nu(phi, *, hx, hy, hz) -> tuple[float, float, float, float]:
+    """(sum(phi * cell volume), min, max, number of non-finite cells) on a non-uniform mesh."""
+    phi = _f64(phi)
+    h = _widths(phi.shape, hx, hy, hz)
+    out = np.zeros(4)
+    g = _grid(phi.shape, 1.0)
+    _l().orc_reduce_nu(ctypes.byref(g), *(_ptr(a) for a in h), _ptr(phi), _ptr(out))
+    return tuple(float(v) for v in out)

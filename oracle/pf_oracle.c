@@ -39,6 +39,17 @@
  *    central gradient of a cell next to a wall takes the wall-side value from a mirror ghost
  *    (ghost of cell 0 = cell 0, of cell n-1 = cell n-1). The velocity stored on a wall face is
  *    ignored. Forward step only (the adjoint is for periodic grids).
+ *  - Non-uniform rectilinear meshes (the closing remarks say the method extends to non-uniform
+ *    anisotropic Cartesian grids, with eps either fixed by the worst case or tuned to the local
+ *    mesh, and give no discrete form; orc_rhs_nu and the functions after it): cell widths
+ *    h_a[idx] per axis; the width index wraps on a periodic axis and mirrors across walls. The
+ *    centre distance across the low a-face of cell idx is d_a(idx) = (h_a(idx-1) + h_a(idx))/2;
+ *    the central gradient divides the difference of the two neighbours by the distance between
+ *    their centres, d_a(idx) + d_a(idx+1); the diffusive flux uses the centre distance of its
+ *    face; the face value of phi and of the sharpening product stays the mean of the two cells;
+ *    the divergence divides by the cell's own width. eps is either the given value everywhere
+ *    (mode 0) or, per cell, eps * max(h_x, h_y, h_z) / dx (mode 1, dx the reference spacing the
+ *    given eps belongs to), averaged onto each face. Mass is sum(phi * cell volume).
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -183,9 +194,13 @@ static double time_factor(int vel_mode, double vel_T, double t)
  * scheme 1: forward Euler (Eq. 25 regime); scheme 2: the explicit midpoint rule (RK2, Eq. 26
  * regime); scheme 3: the low-storage RK3 above (Eq. 27 regime); scheme 4: classic RK4 (Eq. 28,
  * used for every experiment of Sec. 3). Step n starts at t0 + n*dt. */
-void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int vel_mode,
-              double vel_T, int64_t nsteps, double *phi, const double *U, const double *V,
-              const double *W)
+typedef struct orc_mesh orc_mesh;
+static void rhs_any(const orc_grid *g, const orc_mesh *m, double s, const double *phi,
+                    const double *U, const double *V, const double *W, double *f);
+
+static void step_impl(const orc_grid *g, const orc_mesh *mesh, int scheme, int fp32, double dt,
+                      double t0, int vel_mode, double vel_T, int64_t nsteps, double *phi,
+                      const double *U, const double *V, const double *W)
 {
     const int64_t N = ncell(g);
     double *k1 = malloc(sizeof(double) * N), *k2 = malloc(sizeof(double) * N);
@@ -194,7 +209,7 @@ void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int
     for (int64_t n = 0; n < nsteps; ++n) {
         const double t = t0 + (double)n * dt;
         if (scheme == 1) {
-            orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
+            rhs_any(g, mesh, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
             for (int64_t c = 0; c < N; ++c) phi[c] = round_storage(phi[c] + dt * k1[c], fp32);
             continue;
         }
@@ -202,31 +217,31 @@ void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int
             const double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0,
                          z3 = -5.0 / 12.0;
             double *u2 = k4;
-            orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
+            rhs_any(g, mesh, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
             for (int64_t c = 0; c < N; ++c) y[c] = round_storage(phi[c] + dt * g1 * k1[c], fp32);
-            orc_rhs(g, time_factor(vel_mode, vel_T, t + g1 * dt), y, U, V, W, k2);
+            rhs_any(g, mesh, time_factor(vel_mode, vel_T, t + g1 * dt), y, U, V, W, k2);
             for (int64_t c = 0; c < N; ++c)
                 u2[c] = round_storage(y[c] + dt * (g2 * k2[c] + z2 * k1[c]), fp32);
-            orc_rhs(g, time_factor(vel_mode, vel_T, t + (g1 + g2 + z2) * dt), u2, U, V, W, k3);
+            rhs_any(g, mesh, time_factor(vel_mode, vel_T, t + (g1 + g2 + z2) * dt), u2, U, V, W, k3);
             for (int64_t c = 0; c < N; ++c)
                 phi[c] = round_storage(u2[c] + dt * (g3 * k3[c] + z3 * k2[c]), fp32);
             continue;
         }
         if (scheme == 2) {
             /* half an Euler step to the midpoint, then the whole step with the midpoint slope */
-            orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
+            rhs_any(g, mesh, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
             for (int64_t c = 0; c < N; ++c) y[c] = round_storage(phi[c] + 0.5 * dt * k1[c], fp32);
-            orc_rhs(g, time_factor(vel_mode, vel_T, t + 0.5 * dt), y, U, V, W, k2);
+            rhs_any(g, mesh, time_factor(vel_mode, vel_T, t + 0.5 * dt), y, U, V, W, k2);
             for (int64_t c = 0; c < N; ++c) phi[c] = round_storage(phi[c] + dt * k2[c], fp32);
             continue;
         }
-        orc_rhs(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
+        rhs_any(g, mesh, time_factor(vel_mode, vel_T, t), phi, U, V, W, k1);
         for (int64_t c = 0; c < N; ++c) y[c] = round_storage(phi[c] + 0.5 * dt * k1[c], fp32);
-        orc_rhs(g, time_factor(vel_mode, vel_T, t + 0.5 * dt), y, U, V, W, k2);
+        rhs_any(g, mesh, time_factor(vel_mode, vel_T, t + 0.5 * dt), y, U, V, W, k2);
         for (int64_t c = 0; c < N; ++c) y[c] = round_storage(phi[c] + 0.5 * dt * k2[c], fp32);
-        orc_rhs(g, time_factor(vel_mode, vel_T, t + 0.5 * dt), y, U, V, W, k3);
+        rhs_any(g, mesh, time_factor(vel_mode, vel_T, t + 0.5 * dt), y, U, V, W, k3);
         for (int64_t c = 0; c < N; ++c) y[c] = round_storage(phi[c] + dt * k3[c], fp32);
-        orc_rhs(g, time_factor(vel_mode, vel_T, t + dt), y, U, V, W, k4);
+        rhs_any(g, mesh, time_factor(vel_mode, vel_T, t + dt), y, U, V, W, k4);
         for (int64_t c = 0; c < N; ++c)
             phi[c] = round_storage(
                 phi[c] + dt / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]), fp32);
@@ -236,6 +251,13 @@ void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int
     free(k3);
     free(k4);
     free(y);
+}
+
+void orc_step(const orc_grid *g, int scheme, int fp32, double dt, double t0, int vel_mode,
+              double vel_T, int64_t nsteps, double *phi, const double *U, const double *V,
+              const double *W)
+{
+    step_impl(g, NULL, scheme, fp32, dt, t0, vel_mode, vel_T, nsteps, phi, U, V, W);
 }
 
 /* One forward-Euler step written in the printed 1D coefficient form (Sec. 2.2.1, Eq. 13):
@@ -322,6 +344,168 @@ void orc_reduce(const orc_grid *g, const double *phi, double *out4)
         if (v > mx) mx = v;
     }
     out4[0] = sum * dV;
+    out4[1] = mn;
+    out4[2] = mx;
+    out4[3] = bad;
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Non-uniform rectilinear meshes (the reading in the header): the recipe's five steps with
+ * per-axis cell widths.
+ * ------------------------------------------------------------------------------------- */
+struct orc_mesh {
+    const double *h[3]; /* cell widths along x, y, z: h[0][nx], h[1][ny], h[2][nz] */
+    int32_t eps_mode;   /* 0: eps everywhere; 1: eps * max(h_x, h_y, h_z) / dx per cell */
+};
+
+/* width of cell idx along axis a (index wrapped on a periodic axis, mirrored across walls) */
+static double width(const orc_grid *g, const orc_mesh *m, int a, int64_t idx)
+{
+    const int64_t n = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+    if (g->wall[a]) {
+        const int64_t p = 2 * n;
+        int64_t r = idx % p;
+        if (r < 0) r += p;
+        idx = r < n ? r : p - 1 - r;
+    } else {
+        idx = wrap(idx, n);
+    }
+    return m->h[a][idx];
+}
+
+/* distance between the centres of cells idx-1 and idx along axis a */
+static double centre_dist(const orc_grid *g, const orc_mesh *m, int a, int64_t idx)
+{
+    return 0.5 * (width(g, m, a, idx - 1) + width(g, m, a, idx));
+}
+
+/* interface thickness at cell (i, j, k) */
+static double eps_cell(const orc_grid *g, const orc_mesh *m, int64_t i, int64_t j, int64_t k)
+{
+    if (m->eps_mode == 0) return g->eps;
+    double hmax = width(g, m, 0, i);
+    const double hy = width(g, m, 1, j), hz = width(g, m, 2, k);
+    if (hy > hmax) hmax = hy;
+    if (hz > hmax) hmax = hz;
+    return g->eps * hmax / g->dx;
+}
+
+static void rhs_nu(const orc_grid *g, const orc_mesh *m, double s, const double *phi,
+                   const double *U, const double *V, const double *W, double *f)
+{
+    const int64_t N = ncell(g);
+    double *q = malloc(sizeof(double) * 3 * N);
+    double *F = malloc(sizeof(double) * 3 * N);
+    const double *vel[3] = {U, V, W};
+    /* steps 1-3: gradient over the distance between the two neighbours' centres, normal,
+     * sharpening product */
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                const int64_t c = at(g, i, j, k);
+                const int64_t idx[3] = {i, j, k};
+                double gv[3], mag2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double span = centre_dist(g, m, a, idx[a]) + centre_dist(g, m, a, idx[a] + 1);
+                    gv[a] = (phi[nb_grad(g, i, j, k, a, +1)] - phi[nb_grad(g, i, j, k, a, -1)]) / span;
+                    mag2 += gv[a] * gv[a];
+                }
+                const double mag = sqrt(mag2 + g->delta * g->delta);
+                const double p = phi[c];
+                for (int a = 0; a < 3; ++a) q[3 * c + a] = p * (1.0 - p) * (mag > 0.0 ? gv[a] / mag : 0.0);
+            }
+    /* step 4: low-face fluxes */
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                const int64_t c = at(g, i, j, k);
+                const int64_t idx[3] = {i, j, k};
+                for (int a = 0; a < 3; ++a) {
+                    if (low_face_is_wall(g, i, j, k, a)) {
+                        F[3 * c + a] = 0.0;
+                        continue;
+                    }
+                    const int64_t mc = nb(g, i, j, k, a, -1);
+                    const double eps_f =
+                        0.5 * (eps_cell(g, m, i - (a == 0), j - (a == 1), k - (a == 2)) +
+                               eps_cell(g, m, i, j, k));
+                    const double adv = -s * vel[a][c] * 0.5 * (phi[mc] + phi[c]);
+                    const double dif = g->gamma * eps_f * (phi[c] - phi[mc]) / centre_dist(g, m, a, idx[a]);
+                    const double shp = -g->gamma * 0.5 * (q[3 * mc + a] + q[3 * c + a]);
+                    F[3 * c + a] = adv + dif + shp;
+                }
+            }
+    /* step 5: divergence over the cell's widths */
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                const int64_t c = at(g, i, j, k);
+                const int64_t idx[3] = {i, j, k};
+                double acc = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    acc += (F[3 * nb(g, i, j, k, a, +1) + a] - F[3 * c + a]) / width(g, m, a, idx[a]);
+                f[c] = acc;
+            }
+    free(q);
+    free(F);
+}
+
+static void rhs_any(const orc_grid *g, const orc_mesh *m, double s, const double *phi,
+                    const double *U, const double *V, const double *W, double *f)
+{
+    if (m)
+        rhs_nu(g, m, s, phi, U, V, W, f);
+    else
+        orc_rhs(g, s, phi, U, V, W, f);
+}
+
+/* f = d(phi)/dt on a non-uniform mesh: hx[nx], hy[ny], hz[nz] cell widths. */
+void orc_rhs_nu(const orc_grid *g, const double *hx, const double *hy, const double *hz,
+                int eps_mode, double s, const double *phi, const double *U, const double *V,
+                const double *W, double *f)
+{
+    const orc_mesh m = {{hx, hy, hz}, eps_mode};
+    rhs_nu(g, &m, s, phi, U, V, W, f);
+}
+
+/* orc_step on a non-uniform mesh */
+void orc_step_nu(const orc_grid *g, const double *hx, const double *hy, const double *hz,
+                 int eps_mode, int scheme, int fp32, double dt, double t0, int vel_mode,
+                 double vel_T, int64_t nsteps, double *phi, const double *U, const double *V,
+                 const double *W)
+{
+    const orc_mesh m = {{hx, hy, hz}, eps_mode};
+    step_impl(g, &m, scheme, fp32, dt, t0, vel_mode, vel_T, nsteps, phi, U, V, W);
+}
+
+/* Mass on a non-uniform mesh: sum of phi times the cell volume (the product of the widths of
+ * the axes longer than one cell); extrema and non-finite count as orc_reduce. */
+void orc_reduce_nu(const orc_grid *g, const double *hx, const double *hy, const double *hz,
+                   const double *phi, double *out4)
+{
+    const double *h[3] = {hx, hy, hz};
+    const int64_t n[3] = {g->nx, g->ny, g->nz};
+    double sum = 0.0, mn = INFINITY, mx = -INFINITY, bad = 0.0;
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                const double v = phi[at(g, i, j, k)];
+                if (!isfinite(v)) {
+                    bad += 1.0;
+                    continue;
+                }
+                const int64_t idx[3] = {i, j, k};
+                double vol = 1.0;
+                for (int a = 0; a < 3; ++a)
+                    if (n[a] > 1) vol *= h[a][idx[a]];
+                sum += v * vol;
+                if (v < mn) mn = v;
+                if (v > mx) mx = v;
+            }
+    out4[0] = sum;
     out4[1] = mn;
     out4[2] = mx;
     out4[3] = bad;

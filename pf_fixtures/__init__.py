@@ -82,6 +82,39 @@ def edge_curl(Ax, Ay, Az, dx):
     return U, V, W
 
 
+def edge_curl_nu(Ax, Ay, Az, hx, hy, hz):
+    """edge_curl on a rectilinear mesh with cell widths hx (nx), hy (ny), hz (nz): each
+    difference of the potential is divided by the width of the cell it spans, so that
+    sum_a (u_a[+] - u_a[-]) / h_a = 0 in every cell."""
+    r = np.roll
+    hx, hy, hz = (np.asarray(h, dtype=np.float64) for h in (hx, hy, hz))
+    HX, HY, HZ = hx[None, None, :], hy[None, :, None], hz[:, None, None]
+    U = (r(Az, -1, 1) - Az) / HY - (r(Ay, -1, 0) - Ay) / HZ
+    V = (r(Ax, -1, 0) - Ax) / HZ - (r(Az, -1, 2) - Az) / HX
+    W = (r(Ay, -1, 2) - Ay) / HX - (r(Ax, -1, 1) - Ax) / HY
+    return U, V, W
+
+
+def smooth_widths(n: int, L: float = 1.0, ratio: float = 2.0, phase: float = 0.0) -> np.ndarray:
+    """n cell widths summing to L that vary smoothly and periodically between w and ratio * w
+    (h_i proportional to 1 + a cos(2 pi (i + 1/2) / n + phase), a = (ratio - 1)/(ratio + 1))."""
+    a = (ratio - 1.0) / (ratio + 1.0)
+    h = 1.0 + a * np.cos(2.0 * np.pi * (np.arange(n) + 0.5) / n + phase)
+    return h * (L / h.sum())
+
+
+def random_widths(rng: np.random.Generator, n: int, L: float = 1.0, ratio: float = 2.0) -> np.ndarray:
+    """n cell widths summing to L, independent U[1, ratio] draws (jumps from cell to cell)."""
+    h = rng.uniform(1.0, ratio, size=n)
+    return h * (L / h.sum())
+
+
+def cell_centres(h) -> np.ndarray:
+    """Centre coordinates of cells of widths h laid end to end from 0."""
+    h = np.asarray(h, dtype=np.float64)
+    return np.cumsum(h) - 0.5 * h
+
+
 def zalesak_ic(n: int, eps: float, L: float = 100.0, centre=(50.0, 75.0), R: float = 15.0,
                w: float = 5.0, l: float = 25.0) -> np.ndarray:
     """Notched disk (Sec. 3.3.2) on an n x n x 1 grid of an L x L box: the tanh profile of an
