@@ -49,7 +49,8 @@
  *    face; the face value of phi and of the sharpening product stays the mean of the two cells;
  *    the divergence divides by the cell's own width. eps is either the given value everywhere
  *    (mode 0) or, per cell, eps * max(h_x, h_y, h_z) / dx (mode 1, dx the reference spacing the
- *    given eps belongs to), averaged onto each face. Mass is sum(phi * cell volume).
+ *    given eps belongs to; the maximum over the axes longer than one cell), averaged onto each
+ *    face. Mass is sum(phi * cell volume), the volume over the axes longer than one cell.
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -383,10 +384,13 @@ static double centre_dist(const orc_grid *g, const orc_mesh *m, int a, int64_t i
 static double eps_cell(const orc_grid *g, const orc_mesh *m, int64_t i, int64_t j, int64_t k)
 {
     if (m->eps_mode == 0) return g->eps;
-    double hmax = width(g, m, 0, i);
-    const double hy = width(g, m, 1, j), hz = width(g, m, 2, k);
-    if (hy > hmax) hmax = hy;
-    if (hz > hmax) hmax = hz;
+    /* the largest width over the axes longer than one cell (a one-cell axis is not resolved) */
+    const int64_t n[3] = {g->nx, g->ny, g->nz}, idx[3] = {i, j, k};
+    double hmax = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double h = n[a] > 1 ? width(g, m, a, idx[a]) : 0.0;
+        if (h > hmax) hmax = h;
+    }
     return g->eps * hmax / g->dx;
 }
 

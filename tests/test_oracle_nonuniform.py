@@ -137,6 +137,21 @@ def test_mirrored_mesh_gives_the_mirrored_update():
     assert nx % 2 == 1
 
 
+def test_one_cell_axis_does_not_enter_the_local_eps():
+    """On a grid of one plane the z width is not resolved: with eps tuned to the local mesh the
+    update does not depend on it (the largest width is taken over the axes longer than one
+    cell, as the volume is)."""
+    rng = np.random.default_rng(8)
+    shape = (1, 10, 12)
+    phi, U, V, W, h = random_case(rng, shape)
+    W = np.zeros(shape)
+    kw = dict(dx=0.08, eps=0.06, gamma=1.1, delta=0.1, eps_mode=1)
+    a = oracle.rhs_nu(phi, U, V, W, hx=h[0], hy=h[1], hz=[1e-3], **kw)
+    b = oracle.rhs_nu(phi, U, V, W, hx=h[0], hy=h[1], hz=[10.0], **kw)
+    assert np.array_equal(a, b)
+    assert oracle.reduce_nu(phi, hx=h[0], hy=h[1], hz=[1e-3]) == oracle.reduce_nu(phi, hx=h[0], hy=h[1], hz=[10.0])
+
+
 @pytest.mark.parametrize("eps_mode", [0, 1])
 def test_walled_axis_equals_its_even_reflection(eps_mode):
     """Walls on x with mirror ghosts are the even reflection: the walled update of n cells
