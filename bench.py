@@ -115,6 +115,40 @@ def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, v
     return ms, name, tuned, m0, m1
 
 
+def nonuniform_timing(pf, fx, st, dtype, n=512, steps=20):
+    """RK4 on a smoothly stretched n^3 mesh (widths varying 2x along every axis, eps tuned to the
+    local mesh): the per-stage kernel's non-uniform form against its uniform form (tiled_64x4)
+    on the same grid. Fields and velocity of the roofline workload (timing does not depend on
+    the velocity's divergence on the stretched mesh)."""
+    import torch
+    c, phi, u, v, w = setup_roofline(pf, fx, n, dtype, st)
+    h = [fx.smooth_widths(n, 1.0, 2.0, 0.9 * a) for a in range(3)]
+    dt = min(c.dt, 0.1 * min(map(min, h)) ** 2 / (c.gamma * c.eps * max(map(max, h)) / c.dx))
+    res = {}
+    names = [pf.phasefield_variant_name(pf.PF_F32 if dtype == "f32" else pf.PF_F64, k)
+             for k in range(pf.phasefield_variant_count(pf.PF_F32 if dtype == "f32" else pf.PF_F64))]
+    for label, widths in (("nonuniform", h), ("uniform_tiled_64x4", None)):
+        s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, dt, dtype=dtype,
+                      variant=names.index("tiled_64x4"))
+        if widths is not None:
+            s.set_spacing(*widths, eps_mode=1)
+        with torch.cuda.stream(st):
+            keep = phi.clone()
+            s.step(phi, u, v, w, nsteps=GRAPH_STEPS, stream=st)
+            ms = cuda_timer(st, lambda: s.step(phi, u, v, w, nsteps=steps, stream=st)) / steps
+            phi.copy_(keep)
+            del keep
+        s.close()
+        esz = 4 if dtype == "f32" else 8
+        res[label] = {"ms_per_step": round(ms, 4), "gcell_s": round(c.cells / ms / 1e6, 2),
+                      "frac_of_8tbs_28_words": round(ALG_WORDS * esz * c.cells / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    res["nonuniform_over_uniform"] = round(res["nonuniform"]["ms_per_step"] /
+                                           res["uniform_tiled_64x4"]["ms_per_step"], 3)
+    del phi, u, v, w
+    torch.cuda.empty_cache()
+    return res
+
+
 def copy_ceiling(pf, st, nbytes=2 ** 31, reps=10):
     """Read + write bandwidth (GB/s) of a plain device copy of nbytes: torch's copy of float32
     elements and the library's 16-byte streaming copy (phasefield_device_copy)."""
@@ -501,7 +535,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", metavar="PARTS",
                     help="comma-separated subset of {adjoint, batch, velocity, vortex, rollout, "
-                         "deformation}: "
+                         "deformation, nonuniform}: "
                          "run only those measurements and print their JSON (for profiling "
                          "them)")
     ap.add_argument("--batch-steps", type=int, default=300)
@@ -535,7 +569,8 @@ def main():
     st = torch.cuda.Stream()
     if args.only:
         parts = {x.strip() for x in args.only.split(",") if x.strip()}
-        unknown = parts - {"adjoint", "batch", "velocity", "vortex", "rollout", "deformation"}
+        unknown = parts - {"adjoint", "batch", "velocity", "vortex", "rollout", "deformation",
+                           "nonuniform"}
         if unknown:
             print(f"--only: unknown parts {sorted(unknown)}", file=sys.stderr)
             sys.exit(2)
@@ -558,6 +593,9 @@ def main():
         if "velocity" in parts:
             res[f"velocity_{args.n}_{args.dtype}"] = velocity_timing(pf, fx, st, n=args.n,
                                                                    dtype=args.dtype)
+        if "nonuniform" in parts:
+            for dt_ in ("f32", "f64"):
+                res[f"nonuniform_{args.n}_{dt_}"] = nonuniform_timing(pf, fx, st, dt_, n=args.n)
         print(json.dumps(res), flush=True)
         return
     if args.copy_probe:
@@ -648,6 +686,8 @@ def main():
         extras["vortex64_f64"] = vortex_timing(pf, fx, st)
         log("timing velocity synthesis")
         extras[f"velocity_{n}_{args.dtype}"] = velocity_timing(pf, fx, st, n=n, dtype=args.dtype)
+        log("timing the non-uniform mesh")
+        extras[f"nonuniform_{n}_{args.dtype}"] = nonuniform_timing(pf, fx, st, args.dtype, n=n)
         log("timing adjoint")
         extras["adjoint_128_f64"] = adjoint_ratio(pf, fx, "f64", st)
         extras["adjoint_128_f32"] = adjoint_ratio(pf, fx, "f32", st)

@@ -162,6 +162,28 @@ pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);
 
+/* Non-uniform rectilinear mesh for a handle. The paper (Sec. 3.3.3, the list that closes the
+ * comparison with Chiu and Lin) notes that the method extends to non-uniform anisotropic
+ * Cartesian grids, with eps chosen for the worst case or tuned to the local mesh, and gives no
+ * discrete form; this library reads it as follows. hx, hy, hz are HOST arrays of n[0], n[1],
+ * n[2] cell widths (copied; each positive and finite; they need not sum to n dx). The width
+ * index wraps on a periodic axis and mirrors across walls. With d(i) = (h(i-1) + h(i))/2 the
+ * distance between the centres across the low face of cell i: the central gradient divides by
+ * d(i) + d(i+1), the diffusive flux by d of its face, the divergence by h(i); the face values of
+ * phi and of the sharpening product stay the means of the two cells. eps_mode 0: p->eps
+ * everywhere (the worst-case choice: eps on the crossover line of Eq. 17 for the largest width);
+ * 1: per cell p->eps * max(hx_i, hy_j, hz_k) / p->dx (p->dx the reference spacing p->eps belongs
+ * to; the maximum over the axes longer than one cell), averaged onto each face. From then on phasefield_step runs every scheme through the
+ * per-stage kernel in its non-uniform form (no fused sweeps), phasefield_reduce returns
+ * sum(phi * cell volume) (axes of one cell carry no volume), and phasefield_adjoint_step and
+ * phasefield_autotune return PF_ERR_UNSUPPORTED. The velocity on the faces must be discretely
+ * divergence-free on this mesh, sum_a (u_a[+] - u_a[-]) / h_a = 0. All three NULL returns the
+ * handle to the uniform mesh of p->dx. Synchronises the device (queued work may still read the
+ * previous tables). Errors: PF_ERR_INVALID (NULL handle, some but not all widths NULL, a width
+ * that is not positive and finite, eps_mode not 0 or 1), PF_ERR_OOM, PF_ERR_DEVICE. */
+pf_status phasefield_set_spacing(pf_solver *s, const double *hx, const double *hy,
+                                 const double *hz, int32_t eps_mode);
+
 /* How phasefield_adjoint_step runs the four reverse stages of RK4 (other schemes always take
  * one per launch): 0 one stage per launch; 1 two per launch (a kernel that keeps the later
  * stage's adjoint and flux-Jacobian terms in LDS and hands them to the earlier stage of the same

@@ -20,7 +20,8 @@ from ._capi import (EXPORTED, PF_BC_PERIODIC, PF_BC_WALL, PF_ERR_DEVICE, PF_ERR_
                     phasefield_batch_step, phasefield_batch_set_persistent,
                     phasefield_check_params, phasefield_create,
                     phasefield_default_params, phasefield_destroy, phasefield_last_error,
-                    phasefield_reduce, phasefield_set_adjoint_form, phasefield_solver_variant, phasefield_step,
+                    phasefield_reduce, phasefield_set_adjoint_form, phasefield_set_spacing,
+                    phasefield_solver_variant, phasefield_step,
                     phasefield_step_noalloc, phasefield_noalloc_scratch_bytes, phasefield_device_copy,
                     phasefield_variant_count, phasefield_variant_name,
                     phasefield_velocity_coeffs_grad, phasefield_velocity_from_coeffs)
@@ -62,6 +63,12 @@ class Solver:
         phasefield_adjoint_step(self.handle, self.params, phi_n, u, v, w, t_n, lam, gu, gv, gw,
                                 stream)
         return lam
+
+    def set_spacing(self, hx=None, hy=None, hz=None, eps_mode: int = 0) -> None:
+        """Non-uniform rectilinear mesh: cell widths per axis (x: nx values, ...), or all None
+        for the uniform mesh; eps_mode 0 keeps eps, 1 scales it with each cell's largest width
+        (relative to dx)."""
+        phasefield_set_spacing(self.handle, self.params, hx, hy, hz, eps_mode)
 
     def set_adjoint_form(self, form: int) -> None:
         """Reverse RK4 stages of adjoint_step: -1 chosen per grid, 0 one per launch, 1 two."""

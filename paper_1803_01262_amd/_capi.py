@@ -84,6 +84,7 @@ def _load():
         "phasefield_autotune": (i32, [vp, i32, P(i32), P(d), vp]),
         "phasefield_solver_variant": (i32, [vp]),
         "phasefield_set_adjoint_form": (i32, [vp, i32]),
+        "phasefield_set_spacing": (i32, [vp, vp, vp, vp, i32]),
         "phasefield_batch_create": (i32, [P(Params), i32, P(vp)]),
         "phasefield_batch_step": (i32, [vp, P(vp), P(vp), P(vp), P(vp), P(d), i32, vp]),
         "phasefield_batch_destroy": (i32, [vp]),
@@ -107,7 +108,7 @@ EXPORTED = ("phasefield_default_params", "phasefield_check_params", "phasefield_
             "phasefield_reduce", "phasefield_velocity_from_coeffs",
             "phasefield_velocity_coeffs_grad", "phasefield_variant_count",
             "phasefield_variant_name", "phasefield_autotune", "phasefield_solver_variant",
-            "phasefield_set_adjoint_form",
+            "phasefield_set_adjoint_form", "phasefield_set_spacing",
             "phasefield_batch_create", "phasefield_batch_step", "phasefield_batch_destroy",
             "phasefield_batch_set_persistent",
             "phasefield_last_error", "phasefield_step_noalloc",
@@ -290,6 +291,23 @@ def phasefield_batch_step(h, params_list, phis, us, vs, ws, t0s=None, nsteps=1, 
     t0 = None if t0s is None else (ctypes.c_double * B)(*[float(x) for x in t0s])
     _check(lib.phasefield_batch_step(h, arr(phis, "phi"), arr(us, "u"), arr(vs, "v"),
                                      arr(ws, "w"), t0, int(nsteps), _stream(stream)))
+
+
+def phasefield_set_spacing(h, params, hx, hy, hz, eps_mode: int = 0) -> None:
+    """Cell widths per axis (host sequences of n[0], n[1], n[2] floats), or all None."""
+    if hx is None and hy is None and hz is None:
+        _check(lib.phasefield_set_spacing(h, None, None, None, int(eps_mode)))
+        return
+    arrs = []
+    for w, n, name in ((hx, params.n[0], "hx"), (hy, params.n[1], "hy"), (hz, params.n[2], "hz")):
+        if w is None:
+            raise ValueError("give hx, hy and hz, or none")
+        vals = [float(x) for x in w]
+        if len(vals) != n:
+            raise ValueError(f"{name} must hold {n} widths, not {len(vals)}")
+        arrs.append((ctypes.c_double * n)(*vals))
+    _check(lib.phasefield_set_spacing(h, *[ctypes.cast(a, ctypes.c_void_p) for a in arrs],
+                                      int(eps_mode)))
 
 
 def phasefield_set_adjoint_form(h, form: int) -> None:

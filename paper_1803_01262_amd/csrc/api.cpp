@@ -247,6 +247,8 @@ extern "C" pf_status phasefield_create(const pf_params* p, pf_solver** out)
     return PF_OK;
 }
 
+static void free_mesh(NuMesh& m);
+
 extern "C" pf_status phasefield_destroy(pf_solver* s)
 {
     if (!s) return PF_OK;
@@ -260,7 +262,92 @@ extern "C" pf_status phasefield_destroy(pf_solver* s)
     free_dev(ro);
     if (s->red_host) (void)hipHostFree(s->red_host);
     free_dev(s->vel_scratch);
+    free_mesh(s->nu);
     delete s;
+    return PF_OK;
+}
+
+// ------------------------------------------------------------------ non-uniform meshes
+static void free_mesh(NuMesh& m)
+{
+    for (int a = 0; a < 3; ++a) {
+        free_dev(m.tab[a]);
+        void* w = m.width[a];
+        free_dev(w);
+        m.width[a] = nullptr;
+    }
+    m.eps_mode = 0;
+}
+
+// One axis: the kNuCols columns per cell index (NuCol) in the storage dtype, and the widths for
+// the volume weights. The width index wraps on a periodic axis and mirrors across walls.
+template <typename T>
+static hipError_t upload_axis(const double* h, int n, bool walled, void** tab, double** width)
+{
+    auto wid = [&](long idx) {
+        long m;
+        if (walled) {
+            const long p2 = 2L * n;
+            long r = idx % p2;
+            if (r < 0) r += p2;
+            m = r < n ? r : p2 - 1 - r;
+        } else {
+            m = idx % n;
+            if (m < 0) m += n;
+        }
+        return h[m];
+    };
+    auto dist = [&](long idx) { return 0.5 * (wid(idx - 1) + wid(idx)); };
+    std::vector<T> t((size_t)n * kNuCols);
+    for (long i = 0; i < n; ++i) {
+        T* r = t.data() + (size_t)i * kNuCols;
+        r[kNuInvW] = (T)(1.0 / h[i]);
+        r[kNuInvSpan] = (T)(1.0 / (dist(i) + dist(i + 1)));
+        r[kNuInvDist] = (T)(1.0 / dist(i));
+        r[kNuWidth] = n == 1 ? T(0) : (T)h[i];  // a one-cell axis is left out of the local eps
+    }
+    // an axis of one cell carries no volume
+    std::vector<double> w(h, h + n);
+    if (n == 1) w[0] = 1.0;
+    hipError_t e = hipMalloc(tab, t.size() * sizeof(T));
+    if (e == hipSuccess) e = hipMemcpy(*tab, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)width, w.size() * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemcpy(*width, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice);
+    return e;
+}
+
+extern "C" pf_status phasefield_set_spacing(pf_solver* s, const double* hx, const double* hy,
+                                            const double* hz, int32_t eps_mode)
+{
+    if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
+    const double* h[3] = {hx, hy, hz};
+    const int given = (hx != nullptr) + (hy != nullptr) + (hz != nullptr);
+    if (given != 0 && given != 3) return fail(PF_ERR_INVALID, "give hx, hy and hz, or none");
+    if (eps_mode != 0 && eps_mode != 1) return fail(PF_ERR_INVALID, "eps_mode %d is not 0 or 1", (int)eps_mode);
+    if (given == 3)
+        for (int a = 0; a < 3; ++a)
+            for (int i = 0; i < s->p.n[a]; ++i)
+                if (!(std::isfinite(h[a][i]) && h[a][i] > 0.0))
+                    return fail(PF_ERR_INVALID, "width %d of axis %c is not positive and finite", i,
+                                "xyz"[a]);
+    // queued work may still read the old tables
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "phasefield_set_spacing: synchronize");
+    release_graph(s->graph);
+    free_mesh(s->nu);
+    if (given == 0) return PF_OK;
+    const int wm = wall_mask(s->p);
+    for (int a = 0; a < 3 && e == hipSuccess; ++a)
+        e = s->p.dtype == PF_F32
+                ? upload_axis<float>(h[a], s->p.n[a], (wm >> a) & 1, &s->nu.tab[a], &s->nu.width[a])
+                : upload_axis<double>(h[a], s->p.n[a], (wm >> a) & 1, &s->nu.tab[a], &s->nu.width[a]);
+    if (e != hipSuccess) {
+        free_mesh(s->nu);
+        return e == hipErrorOutOfMemory ? fail(PF_ERR_OOM, "phasefield_set_spacing: out of memory")
+                                        : hip_fail(e, "phasefield_set_spacing: upload");
+    }
+    s->nu.eps_mode = eps_mode;
     return PF_OK;
 }
 
@@ -281,7 +368,7 @@ double pf::time_factor(const pf_params& p, double t)
 template <typename T>
 StageArgs<T> pf::make_stage(const pf_params& p, double svel, const T* y, const T* base1,
                             const T* base2, T* out1, T* out2, double c1, double c2, const T* U,
-                            const T* V, const T* W)
+                            const T* V, const T* W, const NuMesh* nu)
 {
     StageArgs<T> a;
     a.y = y;
@@ -303,21 +390,29 @@ StageArgs<T> pf::make_stage(const pf_params& p, double svel, const T* y, const T
     a.c1 = (T)c1;
     a.c2 = (T)c2;
     a.walls = wall_mask(p);
+    if (nu && nu->on()) {
+        for (int ax = 0; ax < 3; ++ax) a.nu[ax] = (const T*)nu->tab[ax];
+        a.nu_ge = (T)(nu->eps_mode == 1 ? p.gamma * p.eps / p.dx : p.gamma * p.eps);
+        a.nu_hg = (T)(0.5 * p.gamma);
+        a.nu_nhs = (T)(-0.5 * svel);
+        a.nu_eps_mode = nu->eps_mode;
+    }
     return a;
 }
 template StageArgs<float> pf::make_stage<float>(const pf_params&, double, const float*,
                                                 const float*, const float*, float*, float*,
                                                 double, double, const float*, const float*,
-                                                const float*);
+                                                const float*, const NuMesh*);
 template StageArgs<double> pf::make_stage<double>(const pf_params&, double, const double*,
                                                   const double*, const double*, double*,
                                                   double*, double, double, const double*,
-                                                  const double*, const double*);
+                                                  const double*, const double*, const NuMesh*);
 
 template <typename T>
 hipError_t pf::run_stage(int variant, const StageArgs<T>& a, hipStream_t st)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
+    if (a.nu[0]) return launch_stage_nu<T>(a, st);
     const int v = variant_is_fused(dtype, variant) ? per_stage_variant(a.nx, a.ny, a.nz, dtype) : variant;
     const StageVariant& sv = stage_variant(dtype, v);
     if constexpr (sizeof(T) == 4)
@@ -347,13 +442,14 @@ template hipError_t pf::run_stage<double>(int, const StageArgs<double>&, hipStre
 // the cell being written). RK2's S2 likewise reads phi only at the cell it writes.
 template <typename T>
 hipError_t pf::enqueue_step(const pf_params& p, int variant, T* phi, const T* U, const T* V,
-                            const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st)
+                            const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st,
+                            const NuMesh* nu)
 {
     const double dt = p.dt;
     hipError_t e;
     if (p.scheme == PF_EULER) {
         e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, nullptr, phi, nullptr,
-                                                acc, 0.0, dt, U, V, W), st);
+                                                acc, 0.0, dt, U, V, W, nu), st);
         if (e != hipSuccess) return e;
         return launch_copy<T>(phi, acc, (size_t)p.n[0] * p.n[1] * p.n[2], st);
     }
@@ -362,41 +458,40 @@ hipError_t pf::enqueue_step(const pf_params& p, int variant, T* phi, const T* U,
         constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0,
                          z3 = -5.0 / 12.0;
         e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, phi, ya, acc,
-                                                dt * g1, dt * (g1 + z2), U, V, W), st);
+                                                dt * g1, dt * (g1 + z2), U, V, W, nu), st);
         if (e != hipSuccess) return e;
         static_assert(g2 + z3 == 0.0, "acc already holds u2 + dt z3 k2 after S2");
         e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t + g1 * dt), ya, acc, nullptr,
-                                                yb, nullptr, dt * g2, 0.0, U, V, W), st);
+                                                yb, nullptr, dt * g2, 0.0, U, V, W, nu), st);
         if (e != hipSuccess) return e;
         return run_stage<T>(variant, make_stage<T>(p, time_factor(p, t + (g1 + g2 + z2) * dt), yb,
-                                                   nullptr, acc, nullptr, phi, 0.0, dt * g3, U, V, W),
+                                                   nullptr, acc, nullptr, phi, 0.0, dt * g3, U, V, W, nu),
                             st);
     }
     if (p.scheme == PF_RK2) {
         e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, nullptr, ya,
-                                                nullptr, 0.5 * dt, 0.0, U, V, W), st);
+                                                nullptr, 0.5 * dt, 0.0, U, V, W, nu), st);
         if (e != hipSuccess) return e;
         return run_stage<T>(variant, make_stage<T>(p, sh, ya, nullptr, phi, nullptr, phi, 0.0, dt,
-                                                   U, V, W), st);
+                                                   U, V, W, nu), st);
     }
     e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), phi, phi, phi, ya, acc,
-                                            0.5 * dt, dt / 6.0, U, V, W), st);
+                                            0.5 * dt, dt / 6.0, U, V, W, nu), st);
     if (e != hipSuccess) return e;
-    e = run_stage<T>(variant, make_stage<T>(p, sh, ya, phi, acc, yb, acc, 0.5 * dt, dt / 3.0, U,
-                                            V, W), st);
+    e = run_stage<T>(variant, make_stage<T>(p, sh, ya, phi, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W, nu), st);
     if (e != hipSuccess) return e;
-    e = run_stage<T>(variant, make_stage<T>(p, sh, yb, phi, acc, ya, acc, dt, dt / 3.0, U, V, W),
+    e = run_stage<T>(variant, make_stage<T>(p, sh, yb, phi, acc, ya, acc, dt, dt / 3.0, U, V, W, nu),
                      st);
     if (e != hipSuccess) return e;
     return run_stage<T>(variant, make_stage<T>(p, time_factor(p, t + dt), ya, nullptr, acc,
-                                               nullptr, phi, 0.0, dt / 6.0, U, V, W), st);
+                                               nullptr, phi, 0.0, dt / 6.0, U, V, W, nu), st);
 }
 template hipError_t pf::enqueue_step<float>(const pf_params&, int, float*, const float*,
                                             const float*, const float*, float*, float*, float*,
-                                            double, hipStream_t);
+                                            double, hipStream_t, const NuMesh*);
 template hipError_t pf::enqueue_step<double>(const pf_params&, int, double*, const double*,
                                              const double*, const double*, double*, double*,
-                                             double*, double, hipStream_t);
+                                             double*, double, hipStream_t, const NuMesh*);
 
 // Arguments of one fused sweep of the RK4 step at time t (pf_fused_body.h): sweep A runs stages
 // 1-2 from phi_cur (writing yb and the accumulator into phi_next), sweep B runs stages 3-4 from
@@ -502,15 +597,16 @@ static hipError_t enqueue_step_fused(const pf_params& p, int variant, const T* p
 template <typename T>
 hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U, const T* V,
                              const T* W, T* ya, T* yb, T* acc, double t0, int nsteps,
-                             hipStream_t st)
+                             hipStream_t st, const NuMesh* nu)
 {
     constexpr int dtype = sizeof(T) == 4 ? PF_F32 : PF_F64;
-    // the fused sweeps run RK4 and RK2 with periodic or walled x and y axes (arrays below 4 GiB
-    // when walled); otherwise their variants run the per-stage kernel
+    // the fused sweeps run RK4 and RK2 on uniform meshes with periodic or walled x and y axes
+    // (arrays below 4 GiB when walled); otherwise their variants run the per-stage kernel
     const int wm = wall_mask(p);
     const bool fused = (p.scheme == PF_RK4 || p.scheme == PF_RK2) && variant_is_fused(dtype, variant) &&
                        (wm & 4) == 0 &&
-                       !(wm != 0 && field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T)));
+                       !(wm != 0 && field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T))) &&
+                       !(nu && nu->on());
     T* cur = phi;
     for (int m = 0; m < nsteps; ++m) {
         const double t = t0 + (double)m * p.dt;
@@ -520,7 +616,7 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
             // (phi, acc); no copy per step
             T* next = cur == phi ? acc : phi;
             e = run_stage<T>(variant, make_stage<T>(p, time_factor(p, t), cur, nullptr, cur, nullptr,
-                                                    next, 0.0, p.dt, U, V, W), st);
+                                                    next, 0.0, p.dt, U, V, W, nu), st);
             cur = next;
         } else if (fused) {
             if (m == nsteps - 1 && cur == phi && p.scheme == PF_RK4) {
@@ -531,7 +627,7 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
                 cur = next;
             }
         } else {
-            e = enqueue_step<T>(p, variant, phi, U, V, W, ya, yb, acc, t, st);
+            e = enqueue_step<T>(p, variant, phi, U, V, W, ya, yb, acc, t, st, nu);
         }
         if (e != hipSuccess) return e;
     }
@@ -540,10 +636,10 @@ hipError_t pf::enqueue_steps(const pf_params& p, int variant, T* phi, const T* U
 }
 template hipError_t pf::enqueue_steps<float>(const pf_params&, int, float*, const float*,
                                              const float*, const float*, float*, float*, float*,
-                                             double, int, hipStream_t);
+                                             double, int, hipStream_t, const NuMesh*);
 template hipError_t pf::enqueue_steps<double>(const pf_params&, int, double*, const double*,
                                               const double*, const double*, double*, double*,
-                                              double*, double, int, hipStream_t);
+                                              double*, double, int, hipStream_t, const NuMesh*);
 
 // Capture `nsteps` steps from t0 on stream st into the handle's graph (replacing what it held)
 // and instantiate it.
@@ -556,7 +652,7 @@ static pf_status capture_steps(pf_solver* s, T* phi, const T* U, const T* V, con
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "phasefield_step: begin capture");
     const hipError_t le = enqueue_steps<T>(s->p, s->variant, phi, U, V, W, (T*)s->ya, (T*)s->yb,
-                                           (T*)s->acc, t0, nsteps, st);
+                                           (T*)s->acc, t0, nsteps, st, &s->nu);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);
     if (le != hipSuccess) {
@@ -620,7 +716,8 @@ static pf_status step_impl(pf_solver* s, T* phi, const T* U, const T* V, const T
     }
     if (done < nsteps) {
         hipError_t e = enqueue_steps<T>(p, s->variant, phi, U, V, W, (T*)s->ya, (T*)s->yb,
-                                        (T*)s->acc, t0 + (double)done * p.dt, nsteps - done, st);
+                                        (T*)s->acc, t0 + (double)done * p.dt, nsteps - done, st,
+                                        &s->nu);
         if (e != hipSuccess) return hip_fail(e, "phasefield_step: launch");
     }
     return PF_OK;
@@ -654,9 +751,19 @@ extern "C" pf_status phasefield_reduce(pf_solver* s, const void* phi, double out
     if (st != PF_OK) return st;
     if (!out4) return fail(PF_ERR_INVALID, "out4 is NULL");
     hipStream_t hs = (hipStream_t)hip_stream;
-    hipError_t e = s->p.dtype == PF_F32
-                       ? launch_reduce<float>((const float*)phi, s->N, s->red_part, s->red_out, hs)
-                       : launch_reduce<double>((const double*)phi, s->N, s->red_part, s->red_out, hs);
+    const NuMesh& m = s->nu;
+    const int* n = s->p.n;
+    hipError_t e;
+    if (m.on())
+        e = s->p.dtype == PF_F32
+                ? launch_reduce_weighted<float>((const float*)phi, n[0], n[1], n[2], m.width[0],
+                                                m.width[1], m.width[2], s->red_part, s->red_out, hs)
+                : launch_reduce_weighted<double>((const double*)phi, n[0], n[1], n[2], m.width[0],
+                                                 m.width[1], m.width[2], s->red_part, s->red_out, hs);
+    else
+        e = s->p.dtype == PF_F32
+                ? launch_reduce<float>((const float*)phi, s->N, s->red_part, s->red_out, hs)
+                : launch_reduce<double>((const double*)phi, s->N, s->red_part, s->red_out, hs);
     if (e != hipSuccess) return hip_fail(e, "phasefield_reduce: launch");
     e = hipMemcpyAsync(s->red_host, s->red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, hs);
     if (e != hipSuccess) return hip_fail(e, "phasefield_reduce: copy");
@@ -664,7 +771,7 @@ extern "C" pf_status phasefield_reduce(pf_solver* s, const void* phi, double out
     if (e != hipSuccess) return hip_fail(e, "phasefield_reduce: synchronize");
     const int D = active_dims(s->p.n);
     double dV = 1.0;
-    for (int d = 0; d < D; ++d) dV *= s->p.dx;
+    for (int d = 0; d < D && !m.on(); ++d) dV *= s->p.dx;  // the weighted sum holds the volumes
     out4[0] = s->red_host[0] * dV;
     out4[1] = s->red_host[1];
     out4[2] = s->red_host[2];
@@ -748,6 +855,8 @@ extern "C" pf_status phasefield_autotune(pf_solver* s, int32_t reps, int32_t* be
 {
     if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
     if (reps < 1) return fail(PF_ERR_INVALID, "reps < 1");
+    if (s->nu.on())
+        return fail(PF_ERR_UNSUPPORTED, "a non-uniform mesh runs one kernel form: nothing to tune");
     hipStream_t hs = (hipStream_t)hip_stream;
     return s->p.dtype == PF_F32 ? autotune_impl<float>(s, reps, best, times_ms, hs)
                                 : autotune_impl<double>(s, reps, best, times_ms, hs);

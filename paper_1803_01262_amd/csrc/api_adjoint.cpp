@@ -263,6 +263,8 @@ extern "C" pf_status phasefield_adjoint_step(pf_solver* s, const void* phi_n, co
     if (!std::isfinite(t_n)) return fail(PF_ERR_INVALID, "t_n is not finite");
     if (wall_mask(s->p) != 0)
         return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint is provided for periodic axes only");
+    if (s->nu.on())
+        return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint is provided for uniform meshes only");
     hipStream_t hs = (hipStream_t)hip_stream;
     if (s->p.dtype == PF_F32)
         return adjoint_impl<float>(s, (const float*)phi_n, (const float*)u, (const float*)v,

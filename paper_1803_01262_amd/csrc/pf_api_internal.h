@@ -32,6 +32,16 @@ struct StepGraph {
     int nsteps = 0;
 };
 
+// A handle's non-uniform mesh (phasefield_set_spacing): per axis a device table of kNuCols
+// storage-dtype values per cell index, the cell widths as doubles for the volume-weighted mass
+// (1 on an axis of one cell), and the eps rule.
+struct NuMesh {
+    void* tab[3] = {nullptr, nullptr, nullptr};
+    double* width[3] = {nullptr, nullptr, nullptr};
+    int eps_mode = 0;
+    bool on() const { return tab[0] != nullptr; }
+};
+
 pf_status fail(pf_status st, const char* fmt, ...);
 pf_status hip_fail(hipError_t e, const char* what);
 pf_status validate_params(const pf_params* p);
@@ -41,19 +51,21 @@ int tuned_variant(int dtype, const int32_t n[3]);
 void release_graph(StepGraph& g);
 double time_factor(const pf_params& p, double t);
 
+// nu: a non-uniform mesh (null or off: the uniform mesh of p)
 template <typename T>
 StageArgs<T> make_stage(const pf_params& p, double svel, const T* y, const T* base1,
                         const T* base2, T* out1, T* out2, double c1, double c2, const T* U,
-                        const T* V, const T* W);
+                        const T* V, const T* W, const NuMesh* nu = nullptr);
 
 template <typename T>
 hipError_t enqueue_step(const pf_params& p, int variant, T* phi, const T* U, const T* V,
-                        const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st);
+                        const T* W, T* ya, T* yb, T* acc, double t, hipStream_t st,
+                        const NuMesh* nu = nullptr);
 
 template <typename T>
 hipError_t enqueue_steps(const pf_params& p, int variant, T* phi, const T* U, const T* V,
                          const T* W, T* ya, T* yb, T* acc, double t0, int nsteps,
-                         hipStream_t st);
+                         hipStream_t st, const NuMesh* nu = nullptr);
 
 template <typename T>
 FusedArgs<T> make_fused(const pf_params& p, bool sweep_b, double t, const T* phi_cur, T* phi_next,
@@ -85,4 +97,5 @@ struct pf_solver {
     double* red_host = nullptr;  // pinned
     void* vel_scratch = nullptr;
     pf::StepGraph graph;
+    pf::NuMesh nu;
 };

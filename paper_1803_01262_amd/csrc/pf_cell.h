@@ -27,10 +27,14 @@ __device__ __forceinline__ float inv_mag(float gx, float gy, float gz, float del
     const float m2 = fmaf(gx, gx, fmaf(gy, gy, fmaf(gz, gz, delta2)));
     return __builtin_amdgcn_rsqf(fmaxf(m2, 1.17549435e-38f));
 }
+// FP64 computes the reciprocal square root on every lane and then selects: with a branch around
+// it, waves over flat regions (g = 0) skip it, tiles there march ahead of their neighbours, and
+// the halo rows the neighbours share are fetched from HBM twice instead of once from L2.
 __device__ __forceinline__ double inv_mag(double gx, double gy, double gz, double delta2)
 {
     const double m2 = fma(gx, gx, fma(gy, gy, fma(gz, gz, delta2)));
-    return m2 > 0.0 ? rsq(m2) : 0.0;
+    const double r = rsq(m2);
+    return m2 > 0.0 ? r : 0.0;
 }
 
 // Sharpening product at a cell centre (step 2), pre-scaled for the flux: returns
@@ -72,6 +76,27 @@ __device__ __forceinline__ T cell_rhs(T sxm, T sxp, T sym, T syp, T szm, T szp,
     const T dif = ((dxp - dxm) + (dyp - dym)) + (dzp - dzm);
     const T shp = ((qxp - qxm) + (qyp - qym)) + (qzp - qzm);
     return fma(nhs, adv, fma(ge, dif, -shp));
+}
+
+// f on a non-uniform rectilinear mesh: per axis the flux difference of the cell's two faces over
+// the cell's width,
+//   f = sum_a iw_a [ nhs (u_a+ S_a+ - u_a- S_a-) + (g_a+ D_a+ - g_a- D_a-) - (q'_a+ - q'_a-) ]
+// with nhs = -s/2, g_a-/+ = gamma eps_face / (centre distance across the low/high face), q' the
+// sharpening products pre-scaled by gamma/2 (the face mean stays the arithmetic mean, so the
+// cell's own q cancels as on the uniform mesh) and iw_a = 1 / h_a.
+template <typename T>
+__device__ __forceinline__ T cell_rhs_nu(T sxm, T sxp, T sym, T syp, T szm, T szp,
+                                         T dxm, T dxp, T dym, T dyp, T dzm, T dzp,
+                                         T qxm, T qxp, T qym, T qyp, T qzm, T qzp,
+                                         T u0, T u1, T v0, T v1, T w0, T w1, T nhs,
+                                         T gxm, T gxp, T gym, T gyp, T gzm, T gzp,
+                                         T iwx, T iwy, T iwz)
+{
+    const T ax = fma(-u0, sxm, u1 * sxp), ay = fma(-v0, sym, v1 * syp), az = fma(-w0, szm, w1 * szp);
+    const T fx = fma(nhs, ax, fma(gxp, dxp, -(gxm * dxm))) - (qxp - qxm);
+    const T fy = fma(nhs, ay, fma(gyp, dyp, -(gym * dym))) - (qyp - qym);
+    const T fz = fma(nhs, az, fma(gzp, dzp, -(gzm * dzm))) - (qzp - qzm);
+    return fma(iwx, fx, fma(iwy, fy, iwz * fz));
 }
 
 // ---------------------------------------------------------------- adjoint (transpose) helpers

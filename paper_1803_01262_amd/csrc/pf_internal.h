@@ -37,7 +37,23 @@ struct StageArgs {
     // indices (reflectn) and the face velocity stored at index 0 (the wall faces, low and, by
     // periodic storage, high) counts as zero, which makes every flux through a wall face zero.
     int walls;
+    // Non-uniform rectilinear mesh (null: the uniform mesh above). Per axis a table of kNuCols
+    // values per cell index (see NuCol); the kernel reads it at the wrapped index on a periodic
+    // axis and at the mirrored one on a walled axis. The uniform coefficients above are then
+    // unused.
+    const T* nu[3] = {nullptr, nullptr, nullptr};
+    T nu_ge = T(0);   // gamma eps (eps mode 0) or gamma eps / dx (mode 1: times the face's mean
+                      // of its two cells' largest widths)
+    T nu_hg = T(0);   // gamma / 2, the face mean of q, folded into q
+    T nu_nhs = T(0);  // -s(t) / 2, the face mean of phi
+    int nu_eps_mode = 0;
 };
+
+// Columns of a non-uniform mesh table, per cell index along one axis: 1/h (divergence),
+// 1/(distance between the centres of the two neighbours) (central gradient), 1/(distance
+// between the centres across the cell's low face) (diffusive flux), h (local eps; 0 on an axis of
+// one cell, which the local eps leaves out).
+enum NuCol { kNuInvW = 0, kNuInvSpan = 1, kNuInvDist = 2, kNuWidth = 3, kNuCols = 4 };
 
 // Adjoint of one stage: given the cotangent kap of the stage's f (a field), accumulate
 //   lam_out = lam_base + a_lam * ybar        (ybar = (df/dy)^T kap at y)
@@ -227,6 +243,12 @@ template <typename T>
 hipError_t launch_reduce(const T* phi, size_t n, double* partial /*4*kReduceBlocks*/,
                          double* out4 /*device, 4*/, hipStream_t st);
 
+// The same on a non-uniform mesh: the sum weights cell (i, j, k) by wx[i] wy[j] wz[k] (device).
+template <typename T>
+hipError_t launch_reduce_weighted(const T* phi, int nx, int ny, int nz, const double* wx,
+                                  const double* wy, const double* wz, double* partial,
+                                  double* out4, hipStream_t st);
+
 // ------------------------------------------------------------------ velocity (velocity.hip)
 // Scratch needs (doubles) for synthesis / projection of an n grid with M modes.
 size_t velocity_scratch_doubles(int nx, int ny, int nz, int M);
@@ -243,6 +265,10 @@ hipError_t launch_velocity_grad(int nx, int ny, int nz, double dx, int M, const 
 int device_compute_units();  // of the current device; 0 on error (cached per device)
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t st);
+
+// One stage on a non-uniform mesh (a.nu set): stage_tiled.hip.
+template <typename T>
+hipError_t launch_stage_nu(const StageArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T* dst, T value, size_t n, hipStream_t st);
 

@@ -17,7 +17,10 @@
 // selects the per-plane descriptor form needed for arrays of 4 GiB or more. WALLS selects the
 // form with solid walls on the axes flagged in a.walls: the stage input is read through mirror
 // indices there (so the diffusive and sharpening fluxes through a wall face vanish) and the face
-// velocity at index 0 of a walled axis counts as zero.
+// velocity at index 0 of a walled axis counts as zero. NU selects the non-uniform rectilinear
+// mesh (a.nu): the gradient, the diffusive fluxes and the divergence take their coefficients from
+// the per-axis tables (this thread's column and row once, the planes' per iteration), and eps
+// mode 1 scales the diffusive flux of each face by the mean of its two cells' largest widths.
 #pragma once
 
 #include "pf_cell.h"
@@ -25,7 +28,8 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, bool BIG, bool WALLS = false, bool PREFETCH = false>
+template <typename T, int TX, int TY, bool BIG, bool WALLS = false, bool PREFETCH = false,
+          bool NU = false>
 __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, int tj, int k0, int k1)
 {
     constexpr int NT = TX * TY;
@@ -106,8 +110,48 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         h_axis = 1;
     }
 
-    const T inv_2dx = a.inv_2dx, d2 = a.delta2, hg = a.hg, nhs = a.nhs, ge = a.ge;
+    const T inv_2dx = a.inv_2dx, d2 = a.delta2, hg = NU ? a.nu_hg : a.hg, nhs = a.nhs, ge = a.ge;
     const int o = (ty + 2) * PW + (tx + 2);  // this thread's cell in a plane of sp
+
+    // non-uniform mesh: gradient spans of this thread's cell and of its halo cell, the column's
+    // and row's divergence and face coefficients, and the widths around the cell (eps mode 1)
+    T sgx = inv_2dx, sgy = inv_2dx, hsgx = inv_2dx, hsgy = inv_2dx;
+    T iwx = T(0), iwy = T(0), dxl = T(0), dxh = T(0), dyl = T(0), dyh = T(0);
+    T hxm = T(0), hxc = T(0), hxp = T(0), hym = T(0), hyc = T(0), hyp = T(0);
+    if constexpr (NU) {
+        const T* X = a.nu[0];
+        const T* Y = a.nu[1];
+        const int cx = mapx(i) * kNuCols, cxm = mapx(i - 1) * kNuCols, cxp = mapx(i + 1) * kNuCols;
+        const int cy = mapy(j) * kNuCols, cym = mapy(j - 1) * kNuCols, cyp = mapy(j + 1) * kNuCols;
+        sgx = X[cx + kNuInvSpan];
+        sgy = Y[cy + kNuInvSpan];
+        iwx = X[cx + kNuInvW];
+        iwy = Y[cy + kNuInvW];
+        dxl = X[cx + kNuInvDist];
+        dxh = X[cxp + kNuInvDist];  // the high face is the low face of cell i+1
+        dyl = Y[cy + kNuInvDist];
+        dyh = Y[cyp + kNuInvDist];
+        hxm = X[cxm + kNuWidth];
+        hxc = X[cx + kNuWidth];
+        hxp = X[cxp + kNuWidth];
+        hym = Y[cym + kNuWidth];
+        hyc = Y[cy + kNuWidth];
+        hyp = Y[cyp + kNuWidth];
+        if (h_o >= 0) {  // the halo cell: column i0-1 / i0+TX on a tile row, or row j0-1 / j0+TY
+            int hi, hj;
+            if (h_axis == 0) {
+                const int side = tid / TY;
+                hi = side ? i0 + TX : i0 - 1;
+                hj = j0 + (tid - side * TY);
+            } else {
+                const int t2 = tid - 2 * TY, side = t2 / TX;
+                hi = i0 + (t2 - side * TX);
+                hj = side ? j0 + TY : j0 - 1;
+            }
+            hsgx = X[mapx(hi) * kNuCols + kNuInvSpan];
+            hsgy = Y[mapy(hj) * kNuCols + kNuInvSpan];
+        }
+    }
 
     fetch(k0 - 2);
     commit(0);
@@ -159,6 +203,19 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
         if constexpr (!PREFETCH) load_ops(k);
         const T w1 = nw1, u0 = nu0, u1 = nu1, v0 = nv0, v1 = nv1, b1 = nb1, b2 = nb2;
         if constexpr (PREFETCH) load_ops(k + 1);
+        // non-uniform mesh: the z coefficients of planes k and k+1 (scalar loads)
+        T sgz = inv_2dx, iwz = T(0), dzl = T(0), dzh = T(0), hzm = T(0), hzc = T(0), hzp = T(0);
+        if constexpr (NU) {
+            const T* Z = a.nu[2];
+            const int zc = mapz(k) * kNuCols, zp = mapz(k + 1) * kNuCols;
+            sgz = Z[zp + kNuInvSpan];  // the gradient of plane k+1
+            iwz = Z[zc + kNuInvW];
+            dzl = Z[zc + kNuInvDist];
+            dzh = Z[zp + kNuInvDist];
+            hzm = Z[mapz(k - 1) * kNuCols + kNuWidth];
+            hzc = Z[zc + kNuWidth];
+            hzp = Z[zp + kNuWidth];
+        }
         __syncthreads();
 
         const T* P0 = sp + s0 * PS;  // plane k
@@ -167,18 +224,18 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
 
         // sharpening product at plane k+1 for this thread's cell
         const T pc1 = P1[o];
-        const T gx = grad1(P1[o + 1], P1[o - 1], inv_2dx);
-        const T gy = grad1(P1[o + PW], P1[o - PW], inv_2dx);
-        const T gz = grad1(P2[o], P0[o], inv_2dx);
+        const T gx = grad1(P1[o + 1], P1[o - 1], sgx);
+        const T gy = grad1(P1[o + PW], P1[o - PW], sgy);
+        const T gz = grad1(P2[o], P0[o], sgz);
         const T fac = sharpen_factor(pc1, gx, gy, gz, d2, hg);
         sqx[q1 * QXS + ty * QXW + tx + 1] = fac * gx;
         sqy[q1 * QYS + (ty + 1) * TX + tx] = fac * gy;
         const T qz_next = fac * gz;
         // ... and on the halo ring
         if (h_o >= 0) {
-            const T hgx = grad1(P1[h_o + 1], P1[h_o - 1], inv_2dx);
-            const T hgy = grad1(P1[h_o + PW], P1[h_o - PW], inv_2dx);
-            const T hgz = grad1(P2[h_o], P0[h_o], inv_2dx);
+            const T hgx = grad1(P1[h_o + 1], P1[h_o - 1], hsgx);
+            const T hgy = grad1(P1[h_o + PW], P1[h_o - PW], hsgy);
+            const T hgz = grad1(P2[h_o], P0[h_o], sgz);
             const T hf = sharpen_factor(P1[h_o], hgx, hgy, hgz, d2, hg);
             if (h_axis == 0)
                 sqx[q1 * QXS + h_dst] = hf * hgx;
@@ -193,10 +250,33 @@ __device__ __forceinline__ void tiled_stage_body(const StageArgs<T>& a, int ti, 
             const T* QX = sqx + q0 * QXS + ty * QXW + tx;  // q_x at i-1, i, i+1
             const T* QY = sqy + q0 * QYS + ty * TX + tx;   // q_y at j-1, j, j+1 (stride TX)
             const T pxm = P0[o - 1], pxp = P0[o + 1], pym = P0[o - PW], pyp = P0[o + PW];
-            const T f = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc),
-                                 face_sum(pc, pyp), szm, szp, face_diff(pxm, pc), face_diff(pc, pxp),
-                                 face_diff(pym, pc), face_diff(pc, pyp), dzm, dzp, QX[0], QX[2],
-                                 QY[0], QY[2 * TX], qz_m1, qz_next, u0, u1, v0, v1, w0, w1, nhs, ge);
+            T f;
+            if constexpr (NU) {
+                // diffusive coefficients of the six faces: gamma eps_face / centre distance
+                T exl = a.nu_ge, exh = a.nu_ge, eyl = a.nu_ge, eyh = a.nu_ge, ezl = a.nu_ge,
+                  ezh = a.nu_ge;
+                if (a.nu_eps_mode == 1) {  // eps of a cell ~ its largest width
+                    const T mc = fmax(hxc, fmax(hyc, hzc));
+                    const T hh = a.nu_ge * T(0.5);
+                    exl = hh * (fmax(hxm, fmax(hyc, hzc)) + mc);
+                    exh = hh * (fmax(hxp, fmax(hyc, hzc)) + mc);
+                    eyl = hh * (fmax(hxc, fmax(hym, hzc)) + mc);
+                    eyh = hh * (fmax(hxc, fmax(hyp, hzc)) + mc);
+                    ezl = hh * (fmax(hxc, fmax(hyc, hzm)) + mc);
+                    ezh = hh * (fmax(hxc, fmax(hyc, hzp)) + mc);
+                }
+                f = cell_rhs_nu(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc),
+                                face_sum(pc, pyp), szm, szp, face_diff(pxm, pc), face_diff(pc, pxp),
+                                face_diff(pym, pc), face_diff(pc, pyp), dzm, dzp, QX[0], QX[2],
+                                QY[0], QY[2 * TX], qz_m1, qz_next, u0, u1, v0, v1, w0, w1,
+                                a.nu_nhs, exl * dxl, exh * dxh, eyl * dyl, eyh * dyh, ezl * dzl,
+                                ezh * dzh, iwx, iwy, iwz);
+            } else {
+                f = cell_rhs(face_sum(pxm, pc), face_sum(pc, pxp), face_sum(pym, pc),
+                             face_sum(pc, pyp), szm, szp, face_diff(pxm, pc), face_diff(pc, pxp),
+                             face_diff(pym, pc), face_diff(pc, pyp), dzm, dzp, QX[0], QX[2],
+                             QY[0], QY[2 * TX], qz_m1, qz_next, u0, u1, v0, v1, w0, w1, nhs, ge);
+            }
             if (a.out1) fo1.store(k, col, fma(a.c1, f, b1));
             if (a.out2) fo2.store(k, col, fma(a.c2, f, b2));
         }

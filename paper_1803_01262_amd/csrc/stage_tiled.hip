@@ -16,7 +16,7 @@
 
 namespace pf {
 
-template <typename T, int TX, int TY, bool BIG, bool WALLS, bool PREFETCH>
+template <typename T, int TX, int TY, bool BIG, bool WALLS, bool PREFETCH, bool NU = false>
 __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int tiles_x,
                                                              int tiles_y, int kz)
 {
@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(TX* TY) stage_tiled_kernel(StageArgs<T> a, int
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int k0 = (b / tiles_y) * kz;
-    tiled_stage_body<T, TX, TY, BIG, WALLS, PREFETCH>(a, ti, tj, k0, min(k0 + kz, a.nz));
+    tiled_stage_body<T, TX, TY, BIG, WALLS, PREFETCH, NU>(a, ti, tj, k0, min(k0 + kz, a.nz));
 }
 
 // The same stage on a grid of one plane (nz = 1): the z-neighbours of every cell are the cell
@@ -129,14 +129,15 @@ __global__ void __launch_bounds__(TX* TY) stage_plane_kernel(StageArgs<T> a, int
 // KZ: planes per z-chunk; KZ = 0 chooses it per launch (launch_chunk_planes).
 // FORCE_BIG selects the per-plane descriptor form even for small arrays (it is what arrays of
 // 4 GiB or more take), so that form can be checked against the default one at any size.
-template <typename T, int TX, int TY, int KZ, bool FORCE_BIG>
+// NU: the non-uniform mesh form (a.nu set), which marches one-plane grids too.
+template <typename T, int TX, int TY, int KZ, bool FORCE_BIG, bool NU = false>
 hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
 {
     const int tiles_x = (a.nx + TX - 1) / TX;
     const int tiles_y = (a.ny + TY - 1) / TY;
     if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0) return hipErrorInvalidValue;
     const bool walls = a.walls != 0;
-    if (a.nz == 1) {  // one plane: no march (a plane is below 2^28 cells, plain addressing)
+    if (a.nz == 1 && !NU) {  // one plane: no march (a plane is below 2^28 cells, plain addressing)
         const long long blocks = (long long)tiles_x * tiles_y;
         if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
         hipLaunchKernelGGL((walls ? stage_plane_kernel<T, TX, TY, true> : stage_plane_kernel<T, TX, TY, false>),
@@ -150,14 +151,14 @@ hipError_t launch_stage_tiled(const StageArgs<T>& a, hipStream_t st)
     constexpr int kPrefetchPlanes = 48;
     auto pick = [&](bool prefetch) -> Kernel {
         if (prefetch)
-            return big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true, true>
-                                : stage_tiled_kernel<T, TX, TY, true, false, true>)
-                       : (walls ? stage_tiled_kernel<T, TX, TY, false, true, true>
-                                : stage_tiled_kernel<T, TX, TY, false, false, true>);
-        return big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true, false>
-                            : stage_tiled_kernel<T, TX, TY, true, false, false>)
-                   : (walls ? stage_tiled_kernel<T, TX, TY, false, true, false>
-                            : stage_tiled_kernel<T, TX, TY, false, false, false>);
+            return big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true, true, NU>
+                                : stage_tiled_kernel<T, TX, TY, true, false, true, NU>)
+                       : (walls ? stage_tiled_kernel<T, TX, TY, false, true, true, NU>
+                                : stage_tiled_kernel<T, TX, TY, false, false, true, NU>);
+        return big ? (walls ? stage_tiled_kernel<T, TX, TY, true, true, false, NU>
+                            : stage_tiled_kernel<T, TX, TY, true, false, false, NU>)
+                   : (walls ? stage_tiled_kernel<T, TX, TY, false, true, false, NU>
+                            : stage_tiled_kernel<T, TX, TY, false, false, false, NU>);
     };
     int kz = KZ;
     bool prefetch = KZ >= kPrefetchPlanes;
@@ -285,6 +286,17 @@ static bool prefer_x64(int nx)
 {
     return (nx + 63) / 64 * 64 <= (nx + 31) / 32 * 32;
 }
+
+// A stage on a non-uniform mesh: the tiled per-stage kernel in its NU form on 64x4 tiles (32x4
+// where 64-wide tiles pad more columns), chunk length chosen per launch.
+template <typename T>
+hipError_t launch_stage_nu(const StageArgs<T>& a, hipStream_t st)
+{
+    return prefer_x64(a.nx) ? launch_stage_tiled<T, 64, 4, 0, false, true>(a, st)
+                            : launch_stage_tiled<T, 32, 4, 0, false, true>(a, st);
+}
+template hipError_t launch_stage_nu<float>(const StageArgs<float>&, hipStream_t);
+template hipError_t launch_stage_nu<double>(const StageArgs<double>&, hipStream_t);
 
 // Grids from this many cells up take the fused sweeps by default, smaller ones the per-stage
 // kernels (MI355X, 32^3-256^3: FP32 per-stage leads to 64^3, fused from 96^3; FP64 per-stage leads

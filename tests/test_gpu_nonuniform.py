@@ -1,0 +1,210 @@
+"""GPU parity of the non-uniform rectilinear mesh (phasefield_set_spacing) against the oracle.
+
+The oracle's reading of the paper's remark on non-uniform anisotropic Cartesian grids (Sec.
+3.3.3, closing list) is pinned on the CPU in test_oracle_nonuniform.py. Here the per-stage kernel
+in its non-uniform form runs RK4, RK3, RK2 and Euler on randomly and smoothly stretched meshes,
+periodic and walled, with eps fixed or tuned to the local mesh, steady and time-varying
+velocity, ragged multi-tile and one-plane grids, against oracle.step_nu: FP64 within 1e-12
+relative L-inf, FP32 storage within 1e-5 of the oracle's FP32-storage mode. Also: equal widths
+agree with the uniform kernels, the volume-weighted mass, graph replay, and the refusals.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pf_fixtures as fx
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+SCH = {"euler": 1, "rk2": 2, "rk3": 3, "rk4": 4}
+
+
+def rel_linf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def nu_case(seed, shape, ratio=2.5, smooth=False, walls=(False, False, False)):
+    """Drops on a stretched mesh with a solenoidal face velocity (largest component 1); on a
+    walled axis the velocity through the wall faces is zero."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    if smooth:
+        h = [fx.smooth_widths(n, 1.0, ratio, 0.7 * a) for a, n in enumerate((nx, ny, nz))]
+    else:
+        h = [fx.random_widths(rng, n, 1.0, ratio) for n in (nx, ny, nz)]
+    A = [rng.standard_normal(shape) for _ in range(3)]
+    if nz == 1:
+        A[0][:] = 0.0
+        A[1][:] = 0.0
+    # zero potential on the edges that bound a wall face keeps the wall faces closed
+    if walls[0]:
+        A[1][:, :, 0] = 0.0
+        A[2][:, :, 0] = 0.0
+    if walls[1]:
+        A[0][:, 0, :] = 0.0
+        A[2][:, 0, :] = 0.0
+    if walls[2]:
+        A[0][0] = 0.0
+        A[1][0] = 0.0
+    U, V, W = fx.edge_curl_nu(*A, *h)
+    s = 1.0 / fx.max_face_speed(U, V, W)
+    xc, yc = fx.cell_centres(h[0]), fx.cell_centres(h[1])
+    zc = fx.cell_centres(h[2]) if nz > 1 else np.array([0.5])
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    r = np.sqrt((X - 0.45) ** 2 + (Y - 0.5) ** 2 + ((Z - 0.55) ** 2 if nz > 1 else 0.0))
+    hmax = max(float(np.max(a)) for a in h[:2 if nz == 1 else 3])
+    phi = 0.5 * (1.0 + np.tanh((0.3 - r) / (2.0 * hmax)))
+    return phi, U * s, V * s, W * s, h, hmax
+
+
+def stable_dt(h, eps, eps_mode, dxref, gamma=1.0, nz=2):
+    """0.08 of the smallest width (advection) and at most 0.1 h_min^2 / (gamma eps_max), the
+    explicit diffusion limit on the finest axis with the largest eps of the mesh (local eps
+    grows with the coarsest width of a cell)."""
+    axes = h if nz > 1 else h[:2]
+    hmin = min(float(np.min(a)) for a in axes)
+    hmax = max(float(np.max(a)) for a in axes)
+    eps_max = eps * hmax / dxref if eps_mode == 1 else eps
+    return min(0.08 * hmin, 0.1 * hmin * hmin / (gamma * eps_max))
+
+
+def run(pf, phi, U, V, W, h, *, dtype, dx, eps, gamma, dt, nsteps, scheme="rk4", eps_mode=0,
+        walls=(False, False, False), vel_mode=0, vel_T=1.0, t0=0.0, stream=True, variant=-1):
+    nz, ny, nx = phi.shape
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    s = pf.Solver((nx, ny, nz), dx, eps, gamma, dt, dtype=dtype, scheme=scheme, walls=walls,
+                  vel_mode=vel_mode, vel_T=vel_T, variant=variant)
+    if h is not None:
+        s.set_spacing(*h, eps_mode=eps_mode)
+    g = [torch.tensor(a, dtype=tdt, device="cuda") for a in (phi, U, V, W)]
+    st = torch.cuda.Stream() if stream else None
+    if st is not None:
+        with torch.cuda.stream(st):
+            s.step(*g, t0=t0, nsteps=nsteps, stream=st)
+    else:
+        s.step(*g, t0=t0, nsteps=nsteps)
+    torch.cuda.synchronize()
+    out = g[0].cpu().numpy().astype(np.float64)
+    return out, s
+
+
+CASES = [
+    # dtype, shape, walls, eps_mode, scheme, smooth
+    ("f64", (12, 20, 70), (False, False, False), 0, "rk4", False),
+    ("f64", (12, 20, 70), (False, False, False), 1, "rk4", True),
+    ("f32", (12, 20, 70), (False, False, False), 1, "rk4", False),
+    ("f64", (10, 16, 128), (False, False, False), 1, "rk4", False),   # 64-wide tiles
+    ("f64", (1, 36, 50), (False, False, False), 1, "rk4", False),     # one plane
+    ("f32", (1, 36, 50), (True, True, False), 0, "rk4", True),
+    ("f64", (14, 18, 40), (True, False, True), 1, "rk4", False),
+    ("f64", (14, 18, 40), (False, True, False), 0, "rk3", False),
+    ("f64", (14, 18, 40), (False, False, False), 1, "rk2", False),
+    ("f64", (14, 18, 40), (True, True, True), 1, "euler", False),
+    ("f32", (20, 9, 33), (False, False, False), 0, "rk3", False),
+]
+
+
+@pytest.mark.parametrize("dtype,shape,walls,eps_mode,scheme,smooth", CASES)
+def test_nonuniform_matches_oracle(lib, dtype, shape, walls, eps_mode, scheme, smooth):
+    phi, U, V, W, h, hmax = nu_case(sum(shape), shape, smooth=smooth, walls=walls)
+    if dtype == "f32":
+        phi, U, V, W = (a.astype(np.float32).astype(np.float64) for a in (phi, U, V, W))
+    dxref = 1.0 / max(shape)
+    eps = 1.1 * (dxref if eps_mode else hmax)
+    kw = dict(dx=dxref, eps=eps, gamma=1.0, dt=stable_dt(h, eps, eps_mode, dxref, nz=shape[0]),
+              nsteps=7)
+    print("case", dtype, shape, walls, eps_mode, scheme, flush=True)
+    ref = oracle.step_nu(phi, U, V, W, hx=h[0], hy=h[1], hz=h[2], scheme=SCH[scheme],
+                         eps_mode=eps_mode, walls=walls, fp32=dtype == "f32", **kw)
+    got, s = run(lib, phi, U, V, W, h, dtype=dtype, scheme=scheme, eps_mode=eps_mode,
+                 walls=walls, **kw)
+    s.close()
+    err = rel_linf(got, ref)
+    print("error", err, flush=True)
+    assert err <= (TOL64 if dtype == "f64" else TOL32), err
+    assert np.abs(got - phi).max() > 1e-3  # the run moved the field
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_nonuniform_time_varying_velocity_and_graph_replay(lib, dtype):
+    """cos(pi t/T) velocity (whole-loop graph of 20 steps from t0) and steady velocity replayed
+    from the 8-step graphs (20 steps), each against the oracle and against launches on the NULL
+    stream (no graph)."""
+    shape = (10, 24, 36)
+    phi, U, V, W, h, hmax = nu_case(3, shape)
+    if dtype == "f32":
+        phi, U, V, W = (a.astype(np.float32).astype(np.float64) for a in (phi, U, V, W))
+    kw = dict(dx=1.0 / 36, eps=1.1 / 36, gamma=1.0, dt=stable_dt(h, 1.1 / 36, 1, 1.0 / 36),
+              nsteps=20)
+    for vel_mode in (1, 0):
+        ref = oracle.step_nu(phi, U, V, W, hx=h[0], hy=h[1], hz=h[2], eps_mode=1, vel_mode=vel_mode,
+                             vel_T=0.2, t0=0.05, fp32=dtype == "f32", **kw)
+        got, s1 = run(lib, phi, U, V, W, h, dtype=dtype, eps_mode=1, vel_mode=vel_mode, vel_T=0.2,
+                      t0=0.05, **kw)
+        eager, s2 = run(lib, phi, U, V, W, h, dtype=dtype, eps_mode=1, vel_mode=vel_mode,
+                        vel_T=0.2, t0=0.05, stream=False, **kw)
+        s1.close()
+        s2.close()
+        assert np.array_equal(got, eager)
+        assert rel_linf(got, ref) <= (TOL64 if dtype == "f64" else TOL32)
+
+
+def test_equal_widths_agree_with_the_uniform_kernels(lib):
+    """Equal widths through the non-uniform form agree with the uniform per-stage and fused
+    kernels to rounding; clearing the widths returns the handle to the uniform kernels
+    bit for bit."""
+    pf = lib
+    shape = (12, 20, 40)
+    phi, U, V, W, _, _ = nu_case(5, shape, ratio=1.0)
+    dx = 1.0 / 40
+    U, V, W = fx.random_edge_faces(np.random.default_rng(5), shape, dx)
+    s = 1.0 / fx.max_face_speed(U, V, W)
+    U, V, W = U * s, V * s, W * s
+    h = [np.full(n, dx) for n in (40, 20, 12)]
+    kw = dict(dx=dx, eps=dx, gamma=1.0, dt=0.1 * dx, nsteps=6)
+    uni, s0 = run(pf, phi, U, V, W, None, dtype="f64", **kw)
+    s0.close()
+    nu, s1 = run(pf, phi, U, V, W, h, dtype="f64", eps_mode=1, **kw)
+    assert rel_linf(nu, uni) <= 1e-13
+    s1.set_spacing(None, None, None)
+    g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi, U, V, W)]
+    s1.step(*g, nsteps=6)
+    torch.cuda.synchronize()
+    assert np.array_equal(g[0].cpu().numpy(), uni)
+    s1.close()
+
+
+def test_nonuniform_mass_and_refusals(lib):
+    pf = lib
+    shape = (16, 18, 20)
+    phi, U, V, W, h, hmax = nu_case(9, shape, walls=(True, False, False))
+    nz, ny, nx = shape
+    s = pf.Solver((nx, ny, nz), 1.0 / 20, 1.1 / 20, 1.0, stable_dt(h, 1.1 / 20, 1, 1.0 / 20),
+                  dtype="f64", walls=(True, False, False))
+    s.set_spacing(*h, eps_mode=1)
+    g = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (phi, U, V, W)]
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        m0 = s.reduce(g[0], stream=st)
+        s.step(*g, nsteps=40, stream=st)
+        m1 = s.reduce(g[0], stream=st)
+    want = oracle.reduce_nu(phi, hx=h[0], hy=h[1], hz=h[2])
+    assert abs(m0[0] - want[0]) <= 1e-13 * want[0] and m0[1:] == want[1:]
+    assert abs(m1[0] - m0[0]) <= 1e-13 * m0[0]
+    lam = torch.ones_like(g[0])
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        s.adjoint_step(*g, 0.0, lam)
+    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        s.autotune(reps=1)
+    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+    bad = [np.array(h[0]), h[1], h[2]]
+    bad[0][3] = 0.0
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        s.set_spacing(*bad)
+    assert ei.value.status == pf.PF_ERR_INVALID
+    with pytest.raises(pf.PhaseFieldError):
+        s.set_spacing(*h, eps_mode=2)
+    s.close()
