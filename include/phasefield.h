@@ -252,7 +252,9 @@ int32_t phasefield_solver_variant(const pf_solver *s);
  * same dtype, RK4, steady velocity) advanced together. Each sweep is ONE launch over a global
  * tile list that covers every instance (one workgroup per tile): two fused two-stage sweeps per
  * step, or four single-stage sweeps. per_instance[0].variant selects the mode by its kind (a "fused_*" variant
- * or a per-stage one); with variant -1, FP32 runs fused and FP64 per-stage. The step sequence
+ * or a per-stage one); with variant -1, FP32 runs fused and FP64 per-stage. Instances may have
+ * walls on any axes (each its own); a walled z axis in any instance puts the batch in per-stage
+ * mode (the fused sweeps take walls on x and y only). The step sequence
  * is replayed from a captured HIP graph. Results are bit-identical to running each instance
  * alone with phasefield_step.
  * ------------------------------------------------------------------------------------- */
@@ -260,8 +262,8 @@ typedef struct pf_batch pf_batch;
 
 /* per_instance: HOST array of count parameter sets (all with the same dtype).
  * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtypes), PF_ERR_UNSUPPORTED (a set
- * with a scheme other than RK4, a time-varying velocity, walls, or a field of 4 GiB or more:
- * such grids take a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * with a scheme other than RK4, a time-varying velocity, or a field of 4 GiB or more: such grids
+ * take a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_batch_create(const pf_params *per_instance, int32_t count, pf_batch **out);
 
 /* Advance every instance b by nsteps steps: phi[b], u[b], v[b], w[b] are HOST arrays of count

@@ -30,6 +30,7 @@ struct pf_batch {
     int num_tiles = 0;
     bool persistent = false;  // launch form: resident-slot grid looping over the list
     bool wide = false;  // every instance's nx allows 16-byte plane loads
+    bool walls = false;  // some instance has walls
     BatchTile* tiles = nullptr;  // device: the global tile list (8 equal per-XCD ranges)
     // device per-instance argument arrays: per-stage mode S1..S4 (StageArgs);
     // fused mode A_even, B_even, A_odd, B_odd (FusedArgs)
@@ -66,8 +67,11 @@ extern "C" pf_status phasefield_batch_destroy(pf_batch* b)
 static size_t padded(size_t n) { return (n + 63) / 64 * 64; }  // keeps buffers 256-byte aligned
 
 // Mode: the kind (fused or per-stage) of the variant named by instance 0, else by dtype.
-static bool B_mode_fused(const pf_params* per_instance)
+// Fused mode unless an instance has a z wall (the fused sweeps take walls on x and y only).
+static bool B_mode_fused(const pf_params* per_instance, int count)
 {
+    for (int b = 0; b < count; ++b)
+        if (wall_mask(per_instance[b]) & 4) return false;
     const int dtype = per_instance[0].dtype, v0 = per_instance[0].variant;
     if (v0 >= 0 && v0 < stage_variant_count(dtype)) return variant_is_fused(dtype, v0);
     return dtype == PF_F32;
@@ -131,20 +135,18 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
             return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver runs RK4 only", b);
         if (per_instance[b].vel_mode != PF_VEL_STEADY)
             return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver needs a steady velocity", b);
-        if (wall_mask(per_instance[b]) != 0)
-            return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver needs periodic axes", b);
         const pf_params& q = per_instance[b];
         if (field_needs_big(q.n[0], q.n[1], q.n[2], q.dtype == PF_F32 ? 4 : 8))
             return fail(PF_ERR_UNSUPPORTED,
                         "instance %d: a field of 4 GiB or more; use a single-grid solver", b);
     }
     std::vector<BatchTile> list;
-    if (!build_tile_list(per_instance, count, B_mode_fused(per_instance), list))
+    if (!build_tile_list(per_instance, count, B_mode_fused(per_instance, count), list))
         return fail(PF_ERR_INVALID, "the batch has too many tiles for one launch");
     auto* B = new pf_batch();
     B->count = count;
     B->dtype = per_instance[0].dtype;
-    B->fused = B_mode_fused(per_instance);
+    B->fused = B_mode_fused(per_instance, count);
     B->p.assign(per_instance, per_instance + count);
     const size_t esz = B->dtype == PF_F32 ? sizeof(float) : sizeof(double);
     size_t total = 0;
@@ -155,7 +157,9 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
         total += 3 * padded(n);
     }
     B->num_tiles = (int)list.size();
-    B->wide = true;
+    B->walls = false;
+    for (int b = 0; b < count; ++b) B->walls = B->walls || wall_mask(B->p[b]) != 0;
+    B->wide = !B->walls;  // mirror reads are element-wise
     for (int b = 0; b < count; ++b)
         B->wide = B->wide && B->p[b].n[0] % (int)(16 / esz) == 0;
     hipError_t e = hipMalloc(&B->pool, total * esz);
@@ -234,14 +238,14 @@ static hipError_t enqueue_batch_step(pf_batch* B, bool odd, hipStream_t st)
         for (int s = 0; s < 2; ++s) {
             hipError_t e = launch_batch_fused<T>((const FusedArgs<T>*)B->tables[(odd ? 2 : 0) + s],
                                                  s == 1, B->wide, B->tiles, B->num_tiles,
-                                                 B->persistent, st);
+                                                 B->persistent, B->walls, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
     for (int s = 0; s < 4; ++s) {
         hipError_t e = launch_batch_stage<T>((const StageArgs<T>*)B->tables[s], B->tiles,
-                                             B->num_tiles, B->persistent, st);
+                                             B->num_tiles, B->persistent, B->walls, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -35,7 +35,7 @@ __device__ __forceinline__ void for_batch_tiles(const BatchTile* __restrict__ ti
     }
 }
 
-template <typename T, bool PERSIST>
+template <typename T, bool PERSIST, bool WALLS>
 __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs<T>* __restrict__ args,
                                                                   const BatchTile* __restrict__ tiles,
                                                                   int len)
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs
         const int k0 = tl.tk * kBKZ;
         // 64-plane chunks: the form that loads per-cell operands one iteration ahead (1.6-1.8 %
         // faster)
-        tiled_stage_body<T, kBTX, kBTY, false, false, true>(args[tl.b], tl.ti, tl.tj, k0,
+        tiled_stage_body<T, kBTX, kBTY, false, WALLS, true>(args[tl.b], tl.ti, tl.tj, k0,
                                                             min(k0 + kBKZ, args[tl.b].nz));
     });
 }
@@ -52,14 +52,15 @@ __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs
 // Fused mode: one launch per two-stage sweep, with the register budget of the single-grid fused
 // kernel (FP32: four waves per SIMD).
 // WIDE: every instance's rows are a whole number of 16-byte pieces (16-byte plane loads).
-template <typename T, bool SWEEP_B, bool WIDE, bool PERSIST>
+// WALLS: walls on x and/or y in some instance (element-wise loads, WIDE off).
+template <typename T, bool SWEEP_B, bool WIDE, bool PERSIST, bool WALLS = false>
 __global__ void __launch_bounds__(kFTX* kFTY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __restrict__ tiles, int len)
 {
     for_batch_tiles<PERSIST>(tiles, len, [&](const BatchTile& tl) {
         const int k0 = tl.tk * kFKZ;
-        fused_body<T, kFTX, kFTY, SWEEP_B, false, WIDE>(args[tl.b], tl.ti, tl.tj, k0,
-                                                        min(k0 + kFKZ, args[tl.b].nz));
+        fused_body<T, kFTX, kFTY, SWEEP_B, false, WIDE, false, WALLS>(args[tl.b], tl.ti, tl.tj, k0,
+                                                                     min(k0 + kFKZ, args[tl.b].nz));
     });
 }
 
@@ -90,19 +91,19 @@ static int persistent_grid(const void* kernel, int threads, int num_tiles)
     return g > num_tiles ? num_tiles : g;
 }
 
-template <typename T, bool SWEEP_B, bool WIDE>
+template <typename T, bool SWEEP_B, bool WIDE, bool WALLS = false>
 static hipError_t launch_batch_fused_form(const FusedArgs<T>* args_dev, const BatchTile* tiles_dev,
                                           int num_tiles, bool persistent, hipStream_t st)
 {
     const int len = num_tiles / 8;
     if (persistent) {
-        const void* k = (const void*)batch_fused_kernel<T, SWEEP_B, WIDE, true>;
+        const void* k = (const void*)batch_fused_kernel<T, SWEEP_B, WIDE, true, WALLS>;
         const int g = persistent_grid(k, kFTX * kFTY, num_tiles);
         if (g < 8) return hipErrorInvalidDevice;
-        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, true>), dim3(g), dim3(kFTX * kFTY),
-                           0, st, args_dev, tiles_dev, len);
+        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, true, WALLS>), dim3(g),
+                           dim3(kFTX * kFTY), 0, st, args_dev, tiles_dev, len);
     } else {
-        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, false>), dim3(num_tiles),
+        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, false, WALLS>), dim3(num_tiles),
                            dim3(kFTX * kFTY), 0, st, args_dev, tiles_dev, len);
     }
     return hipGetLastError();
@@ -111,9 +112,14 @@ static hipError_t launch_batch_fused_form(const FusedArgs<T>* args_dev, const Ba
 template <typename T>
 hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
                               const BatchTile* tiles_dev, int num_tiles, bool persistent,
-                              hipStream_t st)
+                              bool walls, hipStream_t st)
 {
     if (num_tiles <= 0 || num_tiles % 8) return hipErrorInvalidValue;
+    if (walls) {
+        if (wide) return hipErrorInvalidValue;
+        return sweep_b ? launch_batch_fused_form<T, true, false, true>(args_dev, tiles_dev, num_tiles, persistent, st)
+                       : launch_batch_fused_form<T, false, false, true>(args_dev, tiles_dev, num_tiles, persistent, st);
+    }
     if (wide)
         return sweep_b ? launch_batch_fused_form<T, true, true>(args_dev, tiles_dev, num_tiles, persistent, st)
                        : launch_batch_fused_form<T, false, true>(args_dev, tiles_dev, num_tiles, persistent, st);
@@ -128,30 +134,39 @@ hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, bool, const BatchTile*, int, bool, hipStream_t);
-template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, bool, const BatchTile*, int, bool, hipStream_t);
+template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, bool, const BatchTile*, int, bool, bool, hipStream_t);
+template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, bool, const BatchTile*, int, bool, bool, hipStream_t);
 template hipError_t launch_batch_copy<float>(const BatchCopy<float>*, int, hipStream_t);
 template hipError_t launch_batch_copy<double>(const BatchCopy<double>*, int, hipStream_t);
 
-template <typename T>
-hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* tiles_dev, int num_tiles,
-                              bool persistent, hipStream_t st)
+template <typename T, bool WALLS>
+static hipError_t launch_batch_stage_form(const StageArgs<T>* args_dev, const BatchTile* tiles_dev,
+                                          int num_tiles, bool persistent, hipStream_t st)
 {
-    if (num_tiles <= 0 || num_tiles % 8) return hipErrorInvalidValue;
     const int len = num_tiles / 8;
     if (persistent) {
-        const int g = persistent_grid((const void*)batch_stage_kernel<T, true>, kBTX * kBTY, num_tiles);
+        const int g = persistent_grid((const void*)batch_stage_kernel<T, true, WALLS>, kBTX * kBTY,
+                                      num_tiles);
         if (g < 8) return hipErrorInvalidDevice;
-        hipLaunchKernelGGL((batch_stage_kernel<T, true>), dim3(g), dim3(kBTX * kBTY), 0, st, args_dev,
-                           tiles_dev, len);
-    } else {
-        hipLaunchKernelGGL((batch_stage_kernel<T, false>), dim3(num_tiles), dim3(kBTX * kBTY), 0, st,
+        hipLaunchKernelGGL((batch_stage_kernel<T, true, WALLS>), dim3(g), dim3(kBTX * kBTY), 0, st,
                            args_dev, tiles_dev, len);
+    } else {
+        hipLaunchKernelGGL((batch_stage_kernel<T, false, WALLS>), dim3(num_tiles), dim3(kBTX * kBTY),
+                           0, st, args_dev, tiles_dev, len);
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_stage<float>(const StageArgs<float>*, const BatchTile*, int, bool, hipStream_t);
-template hipError_t launch_batch_stage<double>(const StageArgs<double>*, const BatchTile*, int, bool, hipStream_t);
+template <typename T>
+hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* tiles_dev, int num_tiles,
+                              bool persistent, bool walls, hipStream_t st)
+{
+    if (num_tiles <= 0 || num_tiles % 8) return hipErrorInvalidValue;
+    return walls ? launch_batch_stage_form<T, true>(args_dev, tiles_dev, num_tiles, persistent, st)
+                 : launch_batch_stage_form<T, false>(args_dev, tiles_dev, num_tiles, persistent, st);
+}
+
+template hipError_t launch_batch_stage<float>(const StageArgs<float>*, const BatchTile*, int, bool, bool, hipStream_t);
+template hipError_t launch_batch_stage<double>(const StageArgs<double>*, const BatchTile*, int, bool, bool, hipStream_t);
 
 }  // namespace pf

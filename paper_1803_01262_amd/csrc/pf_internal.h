@@ -209,14 +209,17 @@ struct BatchCopy {
 // The list holds 8 equal per-XCD ranges (num_tiles a multiple of 8). persistent: a grid of the
 // kernel's resident slots whose workgroups loop over their XCD's range, instead of one workgroup
 // per entry.
+// walls: some instance has walls (the form that reads through mirror indices where an
+// instance's args flag them; periodic instances read as before).
 template <typename T>
 hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* tiles_dev,
-                              int num_tiles, bool persistent, hipStream_t st);
-// wide: every instance's nx is a multiple of 16 bytes' worth of elements (16-byte plane loads)
+                              int num_tiles, bool persistent, bool walls, hipStream_t st);
+// wide: every instance's nx is a multiple of 16 bytes' worth of elements (16-byte plane loads;
+// never with walls, whose mirror reads are element-wise)
 template <typename T>
 hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
                               const BatchTile* tiles_dev, int num_tiles, bool persistent,
-                              hipStream_t st);
+                              bool walls, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream_t st);
 // Tile shape of a batch mode: x, y extent and z-chunk.

@@ -64,14 +64,12 @@ def test_invalid_sizes_and_bcs(pf):
     with pytest.raises(pf.PhaseFieldError) as ei:
         pf.phasefield_create(p)
     assert ei.value.status == pf.PF_ERR_INVALID
-    # walls validate (a single-grid solver runs them) but the batched driver declines them
+    # walls validate (the single-grid solver and the batched driver run them); the batched
+    # driver declines schemes other than RK4 before any device work
     pw = pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01, walls=(False, False, True))
     assert pw.bc[2] == pf.PF_BC_WALL
     r = pf.phasefield_check_params(pw, 1.0)
     assert r.dt_max_scheme > 0
-    with pytest.raises(pf.PhaseFieldError) as ei:
-        pf.phasefield_batch_create([pw])
-    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
     for scheme in ("euler", "rk2", "rk3"):
         with pytest.raises(pf.PhaseFieldError) as ei:
             pf.phasefield_batch_create([pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01,

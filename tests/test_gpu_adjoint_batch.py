@@ -377,6 +377,61 @@ def test_batch_matches_oracle(lib, dtype):
         assert err <= (1e-12 if dtype == "f64" else 1e-5), (n, err)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("mode,zwall", [("default", False), ("fused", False), ("per-stage", False),
+                                        ("fused-persistent", False), ("default", True)])
+def test_batch_with_walls(lib, dtype, mode, zwall):
+    """Instances with walls on x, on x and y, on y, and periodic ones, in one batch: every
+    instance equals its own single solve bit for bit, and two of them match the oracle with the
+    same walls (FP64 1e-12, FP32 1e-5 against the FP32-storage mode). A walled z axis in any
+    instance puts the batch in per-stage mode."""
+    pf = lib
+    sizes = [(32, 32, 32), (48, 40, 24), (17, 9, 33), (40, 24, 30)]
+    walls = [(True, False, False), (True, True, False), (False, False, False), (False, True, False)]
+    if zwall:
+        sizes.append((24, 20, 28))
+        walls.append((True, True, True))
+    cases = _batch_instances(sizes, seed=31)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
+    names = [pf.phasefield_variant_name(kd, v) for v in range(pf.phasefield_variant_count(kd))]
+    pick = {"default": -1, "fused": names.index("fused_32x16x32"),
+            "per-stage": names.index("tiled_64x8x16")}[mode.replace("-persistent", "")]
+    params = []
+    ins = []
+    for (n, dx, phi, U, V, W), wl in zip(cases, walls):
+        params.append(pf.make_params(n, dx, dx, 1.0, fx.rk4_dt_3d(dx, 1.0, dx), dtype=dtype, walls=wl))
+        arrs = (phi, U, V, W)
+        if dtype == "f32":
+            arrs = tuple(a.astype(np.float32).astype(np.float64) for a in arrs)
+        ins.append(arrs)
+    params[0].variant = pick
+    bs = pf.BatchSolver(params)
+    if mode.endswith("persistent"):
+        bs.set_persistent(True)
+    bt = [[dev(a, tdt) for a in arrs] for arrs in ins]
+    st = torch.cuda.Stream()
+    nsteps = 11
+    with torch.cuda.stream(st):
+        bs.step(*zip(*bt), nsteps=nsteps, stream=st)
+    st.synchronize()
+    bs.close()
+    for p, arrs, b, wl in zip(params, ins, bt, walls):
+        s = pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype=dtype, walls=wl)
+        g = [dev(a, tdt) for a in arrs]
+        s.step(*g, nsteps=nsteps)
+        torch.cuda.synchronize()
+        assert torch.equal(g[0], b[0]), (p.n[:], wl)
+        s.close()
+    for k in (1, len(sizes) - 1):
+        (n, dx, *_rest), arrs, b = cases[k], ins[k], bt[k]
+        ref = oracle.step(*arrs, dx=dx, eps=dx, gamma=1.0, dt=fx.rk4_dt_3d(dx, 1.0, dx),
+                          nsteps=nsteps, fp32=(dtype == "f32"), walls=walls[k])
+        err = rel_linf(host(b[0]), ref)
+        print(dtype, n, walls[k], "batched vs oracle", err, flush=True)
+        assert err <= (1e-12 if dtype == "f64" else 1e-5), (n, err)
+
+
 def test_batch_workload_full_size_bitwise(lib):
     """The batched workload at its full size (96 FP32 instances of 32^3-128^3, seeded drops and
     8-mode fields, 62.7M cells), in the configuration the benchmark times (default mode, steps
