@@ -156,24 +156,24 @@ def reduce(phi, *, dx) -> tuple[float, float, float, float]:
     return tuple(float(v) for v in out)
 
 
-def rhs_vjp(phi, U, V, W, lam, *, dx, eps, gamma, delta=0.0, s=1.0):
-    """(J^T lam, dU, dV, dW): vector-Jacobian product of rhs() at phi."""
+def rhs_vjp(phi, U, V, W, lam, *, dx, eps, gamma, delta=0.0, s=1.0, walls=(False, False, False)):
+    """(J^T lam, dU, dV, dW): vector-Jacobian product of rhs() at phi (walls as in rhs())."""
     phi, U, V, W, lam = map(_f64, (phi, U, V, W, lam))
     pb, ub, vb, wb = (np.zeros_like(phi) for _ in range(4))
-    g = _grid(phi.shape, dx, eps, gamma, delta)
+    g = _grid(phi.shape, dx, eps, gamma, delta, walls)
     _l().orc_rhs_vjp(ctypes.byref(g), s, _ptr(phi), _ptr(U), _ptr(V), _ptr(W), _ptr(lam),
                      _ptr(pb), _ptr(ub), _ptr(vb), _ptr(wb))
     return pb, ub, vb, wb
 
 
 def adjoint_step(phi, U, V, W, lam, *, dx, eps, gamma, dt, delta=0.0, t=0.0, scheme=4,
-                 vel_mode=0, vel_T=1.0):
+                 vel_mode=0, vel_T=1.0, walls=(False, False, False)):
     """Adjoint of one step at phi_n: returns (lam_n, dU, dV, dW) given lam = dL/dphi_{n+1}."""
     _check_scheme(scheme)
     phi, U, V, W = map(_f64, (phi, U, V, W))
     lam = _f64(lam).copy()
     ub, vb, wb = (np.zeros_like(phi) for _ in range(3))
-    g = _grid(phi.shape, dx, eps, gamma, delta)
+    g = _grid(phi.shape, dx, eps, gamma, delta, walls)
     _l().orc_adjoint_step(ctypes.byref(g), int(scheme), dt, t, int(vel_mode), float(vel_T),
                           _ptr(phi), _ptr(U), _ptr(V), _ptr(W), _ptr(lam), _ptr(ub), _ptr(vb),
                           _ptr(wb))

@@ -38,7 +38,8 @@
  *    through a wall face is zero (no normal velocity, no diffusive or sharpening flux), and the
  *    central gradient of a cell next to a wall takes the wall-side value from a mirror ghost
  *    (ghost of cell 0 = cell 0, of cell n-1 = cell n-1). The velocity stored on a wall face is
- *    ignored. Forward step only (the adjoint is for periodic grids).
+ *    ignored. The adjoint transposes exactly this: a wall face contributes nothing, and the
+ *    gradient's read of a mirror ghost scatters back into the cell itself.
  *  - Non-uniform rectilinear meshes (the closing remarks say the method extends to non-uniform
  *    anisotropic Cartesian grids, with eps either fixed by the worst case or tuned to the local
  *    mesh, and give no discrete form; orc_rhs_nu and the functions after it): cell widths
@@ -542,6 +543,8 @@ void orc_rhs_vjp(const orc_grid *g, double s, const double *phi, const double *U
             for (int64_t i = 0; i < g->nx; ++i) {
                 const int64_t c = at(g, i, j, k);
                 for (int a = 0; a < 3; ++a) {
+                    /* a wall face carries the constant flux zero: nothing to transpose */
+                    if (low_face_is_wall(g, i, j, k, a)) continue;
                     const int64_t m = nb(g, i, j, k, a, -1);
                     /* F_a[c] enters f[m] with +1/dx and f[c] with -1/dx */
                     const double Fbar = (lam[m] - lam[c]) / g->dx;
@@ -572,8 +575,9 @@ void orc_rhs_vjp(const orc_grid *g, double s, const double *phi, const double *U
                 for (int a = 0; a < 3; ++a) {
                     /* n_a = g_a / mag:  d n_a / d g_b = delta_ab / mag - g_a g_b / mag^3 */
                     const double gbar = nbar[a] / mag - gr[3 * c + a] * gn / (mag * mag * mag);
-                    phibar[nb(g, i, j, k, a, +1)] += gbar / (2.0 * g->dx);
-                    phibar[nb(g, i, j, k, a, -1)] -= gbar / (2.0 * g->dx);
+                    /* the gradient read the mirror ghost (the cell itself) across a wall */
+                    phibar[nb_grad(g, i, j, k, a, +1)] += gbar / (2.0 * g->dx);
+                    phibar[nb_grad(g, i, j, k, a, -1)] -= gbar / (2.0 * g->dx);
                 }
             }
     free(gr);

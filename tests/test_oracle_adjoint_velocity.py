@@ -94,6 +94,42 @@ def test_adjoint_step_matches_finite_differences(scheme):
         assert np.sum(grads[a] * v) == pytest.approx(fd, rel=2e-7, abs=1e-9)
 
 
+@pytest.mark.parametrize("scheme,walls", [(4, (True, False, False)), (4, (False, True, True)),
+                                          (1, (True, True, True)), (2, (False, False, True)),
+                                          (3, (True, True, False))])
+def test_adjoint_step_with_walls_matches_finite_differences(scheme, walls):
+    """The adjoint on walled axes against central differences of the walled forward (16
+    directions in phi, and in each face array: the wall faces' velocity has no effect, so its
+    gradient is zero there)."""
+    rng, phi, vel, kw = setup(9, delta=0.2)
+    U, V, W = vel
+    step_kw = dict(dt=0.05 * kw["dx"], scheme=scheme, vel_mode=1, vel_T=0.9, t0=0.2,
+                   walls=walls, **kw)
+    adj_kw = dict(dt=step_kw["dt"], scheme=scheme, vel_mode=1, vel_T=0.9, t=0.2, walls=walls,
+                  **kw)
+    lam = rng.standard_normal(phi.shape)
+    lam_n, ub, vb, wb = oracle.adjoint_step(phi, U, V, W, lam, **adj_kw)
+    grads = (ub, vb, wb)
+    for a, w in enumerate(walls):  # no gradient on the wall faces (index 0 of a walled axis)
+        if w:
+            sl = [slice(None)] * 3
+            sl[2 - a] = 0
+            assert not grads[a][tuple(sl)].any()
+    for d in range(16):
+        v = rng.standard_normal(phi.shape)
+        fd = _fd_check(lambda p: oracle.step(p, U, V, W, **step_kw), phi, v, lam, 1e-6)
+        assert np.sum(lam_n * v) == pytest.approx(fd, rel=2e-7, abs=1e-9)
+        a = d % 3
+
+        def with_vel(x, a=a):
+            vv = [U, V, W]
+            vv[a] = x
+            return oracle.step(phi, *vv, **step_kw)
+
+        fd = _fd_check(with_vel, (U, V, W)[a], v, lam, 1e-6)
+        assert np.sum(grads[a] * v) == pytest.approx(fd, rel=2e-7, abs=1e-9)
+
+
 def test_adjoint_two_steps_chain():
     """Two adjoint steps in sequence equal the adjoint of the two-step map (by FD)."""
     rng, phi, vel, kw = setup(3)
