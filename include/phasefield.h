@@ -49,8 +49,8 @@ extern "C" {
 typedef enum {
     PF_OK = 0,
     PF_ERR_INVALID = 1,     /* bad argument: size, spacing, parameter, null/misaligned pointer */
-    PF_ERR_UNSUPPORTED = 2, /* valid request the library does not provide (e.g. walls in an  */
-                            /* adjoint or batched run)                                        */
+    PF_ERR_UNSUPPORTED = 2, /* valid request the library does not provide (e.g. the adjoint  */
+                            /* on a non-uniform mesh)                                         */
     PF_ERR_DEVICE = 3,      /* a HIP call failed                                              */
     PF_ERR_OOM = 4,         /* device allocation failed                                       */
     PF_ERR_NONFINITE = 5    /* phasefield_reduce found NaN or Inf                             */
@@ -76,8 +76,8 @@ typedef struct {
                         /* central gradient; the face velocity stored at index 0 of a walled  */
                         /* axis (the wall face) is ignored. Walls on x and y run on every      */
                         /* kernel (the fused sweeps included); with a walled z axis a fused   */
-                        /* variant runs the per-stage kernel. Forward step only (the adjoint  */
-                        /* and the batched driver take periodic axes).                        */
+                        /* variant runs the per-stage kernel. The adjoint and the batched     */
+                        /* driver take walls too.                                             */
     int32_t dtype;      /* pf_dtype                                                            */
     int32_t scheme;     /* pf_scheme                                                           */
     int32_t vel_mode;   /* pf_velmode: velocity u0(x) * s(t), s = 1 or cos(pi t / vel_T)       */
@@ -154,10 +154,11 @@ size_t phasefield_noalloc_scratch_bytes(void);
 /* Discrete adjoint of ONE step (the transpose of the derivative of phasefield_step with
  * nsteps = 1, taken at phi_n and time t_n). On entry lam = dL/dphi_{n+1}; on exit
  * lam = dL/dphi_n (in place). gu, gv, gw (may each be NULL to skip) ACCUMULATE
- * dL/du0 etc. (+=). The stage inputs of the forward step are recomputed from phi_n.
- * Allocates three more field-sized scratch buffers on first use.
+ * dL/du0 etc. (+=); on a walled axis the wall face's entry (index 0) gets nothing, since the
+ * step ignores the velocity stored there. The stage inputs of the forward step are recomputed
+ * from phi_n. Allocates three more field-sized scratch buffers on first use.
  * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_UNSUPPORTED (a handle with
- * walls), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * a non-uniform mesh), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);
@@ -189,7 +190,8 @@ pf_status phasefield_set_spacing(pf_solver *s, const double *hx, const double *h
  * stage's adjoint and flux-Jacobian terms in LDS and hands them to the earlier stage of the same
  * tile: fewer field passes, but more registers per thread); -1 (the default) two per launch for
  * FP64 on grids of 192^3 cells and more when the handle's variant is a fused one, else one.
- * Every form gives bit-identical results. Fields of 4 GiB or more always take one per launch.
+ * Every form gives bit-identical results. Fields of 4 GiB or more and handles with walls always
+ * take one per launch.
  * Errors: PF_ERR_INVALID (NULL handle, form outside -1..1). */
 pf_status phasefield_set_adjoint_form(pf_solver *s, int32_t form);
 

@@ -22,8 +22,12 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
     const int k = blockIdx.z;
     if (i >= a.nx || j >= a.ny) return;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    // periodic wrap, or the mirror across the walls of a walled axis
+    auto mx = [&](int v) { return (a.walls & 1) ? reflectn(v, nx) : wrapn(v, nx); };
+    auto my = [&](int v) { return (a.walls & 2) ? reflectn(v, ny) : wrapn(v, ny); };
+    auto mz = [&](int v) { return (a.walls & 4) ? reflectn(v, nz) : wrapn(v, nz); };
     auto idx = [&](int di, int dj, int dk) -> size_t {
-        return ((size_t)wrapn(k + dk, nz) * ny + wrapn(j + dj, ny)) * nx + wrapn(i + di, nx);
+        return ((size_t)mz(k + dk) * ny + my(j + dj)) * nx + mx(i + di);
     };
     auto Y = [&](int di, int dj, int dk) -> T { return a.y[idx(di, dj, dk)]; };
     auto K = [&](int di, int dj, int dk) -> T { return a.kap_scale * a.kap_in[idx(di, dj, dk)]; };
@@ -82,7 +86,9 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
 // arithmetic, in the same order, as the plain kernel above, so the two agree bitwise. Memory
 // access, ring slots and the march in whole groups of six iterations follow the forward tiled
 // kernel (buffer descriptors; BIG for arrays of 4 GiB or more).
-template <typename T, int TX, int TY, bool BIG>
+// WALLS: the form that reads the stage input and the cotangent through mirror indices on the
+// walled axes of a.walls.
+template <typename T, int TX, int TY, bool BIG, bool WALLS = false>
 __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int tiles_x, int tiles_y,
                                                                int kz)
 {
@@ -114,6 +120,11 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     const unsigned col = (unsigned)(jw * nx + iw) * ES;
     const unsigned col_xp = (unsigned)(jw * nx + wrapn(i + 1, nx)) * ES;
     const unsigned col_yp = (unsigned)(wrapn(j + 1, ny) * nx + iw) * ES;
+    // plane-load index maps: periodic wrap, or the mirror across walls
+    const bool wx = WALLS && (a.walls & 1), wy = WALLS && (a.walls & 2), wz = WALLS && (a.walls & 4);
+    auto mapx = [&](int v) { return WALLS && wx ? reflectn(v, nx) : wrapn(v, nx); };
+    auto mapy = [&](int v) { return WALLS && wy ? reflectn(v, ny) : wrapn(v, ny); };
+    auto mapz = [&](int v) { return WALLS && wz ? reflectz(v, nz) : wrapz(v, nz); };
 
     unsigned loff[NL];
     int lpos[NL];
@@ -122,7 +133,7 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         const int e = tid + s * NT;
         lpos[s] = e < PS ? e : -1;
         const int r = e / PW, c = e - r * PW;
-        loff[s] = e < PS ? (unsigned)(wrapn(j0 - 2 + r, ny) * nx + wrapn(i0 - 2 + c, nx)) * ES : 0u;
+        loff[s] = e < PS ? (unsigned)(mapy(j0 - 2 + r) * nx + mapx(i0 - 2 + c)) * ES : 0u;
     }
     // buffer descriptors for the stencil and velocity arrays; the cotangent and gradient arrays,
     // touched once per cell, go through a scalar plane pointer and a vector byte offset (which
@@ -133,7 +144,7 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
 
     T pre_y[NL], pre_k[NL];
     auto fetch = [&](int kk) {
-        const int kw = wrapz(kk, nz);
+        const int kw = mapz(kk);
 #pragma unroll
         for (int s = 0; s < NL; ++s)
             if (lpos[s] >= 0) {
@@ -300,20 +311,18 @@ static hipError_t launch_adjoint_tiled(const AdjArgs<T>& a, int kz, bool big, hi
     const int tiles_y = (a.ny + TY - 1) / TY;
     if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0 || kz < 0) return hipErrorInvalidValue;
     big = big || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
+    using Kernel = void (*)(AdjArgs<T>, int, int, int);
+    const Kernel kern = a.walls ? (big ? adjoint_tiled_kernel<T, TX, TY, true, true>
+                                       : adjoint_tiled_kernel<T, TX, TY, false, true>)
+                                : (big ? adjoint_tiled_kernel<T, TX, TY, true, false>
+                                       : adjoint_tiled_kernel<T, TX, TY, false, false>);
     if (kz == 0) {
-        const void* k = big ? (const void*)adjoint_tiled_kernel<T, TX, TY, true>
-                            : (const void*)adjoint_tiled_kernel<T, TX, TY, false>;
-        kz = launch_chunk_planes(k, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
+        kz = launch_chunk_planes((const void*)kern, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
         if (kz <= 0) return hipErrorInvalidDevice;
     }
     const long long blocks = (long long)tiles_x * tiles_y * ((a.nz + kz - 1) / kz);
     if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (big)
-        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, true>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
-    else
-        hipLaunchKernelGGL((adjoint_tiled_kernel<T, TX, TY, false>), dim3((unsigned)blocks),
-                           dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     return hipGetLastError();
 }
 

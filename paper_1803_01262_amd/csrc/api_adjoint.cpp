@@ -34,6 +34,7 @@ static AdjArgs<T> make_adj(const pf_params& p, double svel, const T* y, const T*
     a.nx = p.n[0];
     a.ny = p.n[1];
     a.nz = p.n[2];
+    a.walls = wall_mask(p);
     a.inv_dx = (T)(1.0 / p.dx);
     a.inv_2dx = (T)(1.0 / (2.0 * p.dx));
     a.ge = (T)(p.gamma * p.eps / p.dx);
@@ -185,7 +186,7 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     // alike). A fused FP32 variant produces y2 and y3 in one sweep (sweep A with its y_mid output
     // and no accumulator output); in FP64 three per-stage launches on 64x8 tiles are faster at
     // 128^3-320^3 (at 128^3 0.244 against 0.261 ms per adjoint step).
-    const bool fused_rc = variant_is_fused(p.dtype, v) && p.dtype == PF_F32;
+    const bool fused_rc = variant_is_fused(p.dtype, v) && p.dtype == PF_F32 && wall_mask(p) == 0;
     const int vs = variant_is_fused(p.dtype, v) && !fused_rc ? stage_variant_index(p.dtype, "tiled_64x8") : v;
     if (fused_rc) {
         FusedArgs<T> a = make_fused<T>(p, false, t, phi, y4, U, V, W, y3);
@@ -211,7 +212,7 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     const bool pair_auto = variant_is_fused(p.dtype, v) && p.dtype == PF_F64 &&
                            cells >= (size_t)192 * 192 * 192;
     const bool pair = (s->adjoint_form == 1 || (s->adjoint_form < 0 && pair_auto)) &&
-                      !field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T));
+                      !field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T)) && wall_mask(p) == 0;
     if (pair) {
         // a fused forward variant lends its tile shape (64x8 or 32x16) and fixed chunk length, if
         // it names one; otherwise 64x8 unless 64-wide tiles pad more columns, chunks per launch
@@ -261,8 +262,6 @@ extern "C" pf_status phasefield_adjoint_step(pf_solver* s, const void* phi_n, co
     for (const void* g : {(const void*)gu, (const void*)gv, (const void*)gw})
         if (g && (((uintptr_t)g) & 15)) return fail(PF_ERR_INVALID, "gradient not 16-byte aligned");
     if (!std::isfinite(t_n)) return fail(PF_ERR_INVALID, "t_n is not finite");
-    if (wall_mask(s->p) != 0)
-        return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint is provided for periodic axes only");
     if (s->nu.on())
         return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint is provided for uniform meshes only");
     hipStream_t hs = (hipStream_t)hip_stream;

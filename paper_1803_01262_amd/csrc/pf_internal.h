@@ -77,6 +77,11 @@ struct AdjArgs {
     const T* W;
     int nx, ny, nz;
     T inv_dx, inv_2dx, ge, hg, hs, delta2;
+    // Walls (bit 0: x, 1: y, 2: z): the stage input and the cotangent are read through mirror
+    // indices on a walled axis. The cotangent of a wall face's flux is then exactly zero, and a
+    // mirror ghost's gradient cotangent the exact negative of its partner's along the wall
+    // normal, which is what the gather needs for the gradient's mirror read of the cell itself.
+    int walls = 0;
 };
 
 // Two reverse RK4 stages in one sweep (adjoint_fused.hip): stage H then stage L.
