@@ -349,7 +349,8 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
         bs.set_persistent(persistent)
         bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
         with torch.cuda.stream(st):
-            bs.step(*zip(*bf), nsteps=8, stream=st)
+            # 50 untimed steps: capture, and the first replays after the mode switch
+            bs.step(*zip(*bf), nsteps=50, stream=st)
             modes[mode] = cuda_timer(st, lambda: bs.step(*zip(*bf), nsteps=nsteps, stream=st))
         bs.close()
     params[0].variant = -1
@@ -486,9 +487,14 @@ def write_traffic(args):
     esz = 4 if args.dtype == "f32" else 8
     n = args.n
     cells = n ** 3
-    # the timed steps' kernels: the plain sweeps (the fused form with the optional outputs,
-    # XOUT, only ends odd step counts) or the per-stage kernel
-    stage = sorted(k for k in fetch if ("fused_kernel" in k and not k.split(">")[0].endswith("true"))
+    # the timed steps' kernels: the plain sweeps (fused_kernel<T, TX, TY, SWEEP_B, BIG, WIDE,
+    # XOUT, WALLS>; the form with the optional outputs, XOUT, only ends odd step counts) or the
+    # per-stage kernel
+    def plain_sweep(k):
+        targs = [t.strip() for t in k.split("<", 1)[1].split(">")[0].split(",")]
+        return targs[6] == "false" and targs[7] == "false"
+
+    stage = sorted(k for k in fetch if ("fused_kernel" in k and plain_sweep(k))
                    or "stage_kernel" in k)
     sweeps = {}
     for k in stage:
