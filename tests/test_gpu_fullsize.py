@@ -77,46 +77,49 @@ def test_fullsize_sampled_parity(lib, case512, dtype, nsteps, tol, scheme):
     assert worst <= tol * np.abs(out).max()
 
 
-def _drops_f32(n, dx, centres, radii, eps):
-    """The fixture's drop union, built window by window straight into float32 (the union of
-    tanh profiles is the profile of the union, and rounding to float32 commutes with max)."""
-    phi = np.zeros((n, n, n), dtype=np.float32)
+def _drops_f32(n, dx, centres, radii, eps, dtype=np.float32):
+    """The fixture's drop union, built window by window straight into the storage dtype (the
+    union of tanh profiles is the profile of the union, and rounding commutes with max)."""
+    phi = np.zeros((n, n, n), dtype=dtype)
     for c, r in zip(centres, radii):
         reach = r + 60.0 * eps
         ix, ox = fx._axis_offsets(n, dx, c[0], n * dx, reach)
         iy, oy = fx._axis_offsets(n, dx, c[1], n * dx, reach)
         iz, oz = fx._axis_offsets(n, dx, c[2], n * dx, reach)
         dist = np.sqrt(oz[:, None, None] ** 2 + oy[None, :, None] ** 2 + ox[None, None, :] ** 2)
-        prof = fx.tanh_profile(r - dist, eps).astype(np.float32)
+        prof = fx.tanh_profile(r - dist, eps).astype(dtype)
         sel = np.ix_(iz, iy, ix)
         phi[sel] = np.maximum(phi[sel], prof)
     return phi
 
 
-def test_4gib_fields_switch_to_per_plane_addressing(lib):
-    """At 1024^3 FP32 every field is 4 GiB, past the 32-bit offsets of one buffer descriptor,
-    and the z-marches switch to per-plane descriptors by themselves. Two RK4 steps of the
-    default (fused) variant, checked against the oracle on sampled patches as above. Velocity:
-    U(y, z), V(z, x), W(x, y), products of sines; each component is constant along its own axis,
-    so the discrete divergence vanishes exactly."""
+@pytest.mark.parametrize("dtype,n", [("f32", 1024), ("f64", 816)])
+def test_4gib_fields_switch_to_per_plane_addressing(lib, dtype, n):
+    """At 1024^3 FP32 (4 GiB) and 816^3 FP64 (4.35 GB, ragged against the 32x16 tiles) every
+    field is past the 32-bit offsets of one buffer descriptor, and the z-marches switch to
+    per-plane descriptors by themselves. Two RK4 steps of the default (fused) variant, checked
+    against the oracle on sampled patches as above (FP32 1e-5 against the FP32-storage mode,
+    FP64 1e-12). Velocity: U(y, z), V(z, x), W(x, y), products of sines; each component is
+    constant along its own axis, so the discrete divergence vanishes exactly."""
     pf = lib
-    n = 1024
+    np_dt = np.float32 if dtype == "f32" else np.float64
     dx = 1.0 / n
     eps, gamma, nsteps = dx, 1.1, 2
     dt = fx.rk4_dt_3d(dx, gamma, eps)
     rng = np.random.default_rng(29)
     centres, radii = rng.uniform(0.2, 0.8, size=(3, 3)), np.array([0.12, 0.08, 0.1])
-    print("building 1024^3 inputs", flush=True)
-    phi = _drops_f32(n, dx, centres, radii, eps)
+    print(f"building {n}^3 {dtype} inputs", flush=True)
+    phi = _drops_f32(n, dx, centres, radii, eps, np_dt)
     x = ((np.arange(n) + 0.5) * dx).astype(np.float64)
     s1, c2 = np.sin(2 * np.pi * x + 0.3), np.cos(4 * np.pi * x + 1.1)
     full = (n, n, n)
-    U = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(c2, s1).astype(np.float32)[:, :, None], full))
-    V = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(s1, c2).astype(np.float32)[:, None, :], full))
-    W = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(c2, s1).astype(np.float32)[None, :, :], full))
+    U = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(c2, s1).astype(np_dt)[:, :, None], full))
+    V = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(s1, c2).astype(np_dt)[:, None, :], full))
+    W = np.ascontiguousarray(np.broadcast_to(np.multiply.outer(c2, s1).astype(np_dt)[None, :, :], full))
     inputs = (phi, U, V, W)
+    assert phi.nbytes >= 4 * 2 ** 30 or phi.nbytes > 2 ** 32 - 1
     st = torch.cuda.Stream()
-    s = pf.Solver((n, n, n), dx, eps, gamma, dt, dtype="f32")
+    s = pf.Solver((n, n, n), dx, eps, gamma, dt, dtype=dtype)
     print("variant", s.variant_name, flush=True)
     g = [torch.from_numpy(a).cuda() for a in inputs]
     m0 = s.reduce(g[0], stream=st)
@@ -129,16 +132,17 @@ def test_4gib_fields_switch_to_per_plane_addressing(lib):
     torch.cuda.empty_cache()
     drift = abs(m1[0] - m0[0]) / m0[0]
     print("mass drift", drift, flush=True)
-    assert drift <= 1e-6
+    assert drift <= (1e-6 if dtype == "f32" else 1e-13)
     R = 8 * nsteps + 2
     worst = 0.0
     samples = sample_cells(phi, np.random.default_rng(31), 16)
     for (k, j, i) in samples:
         pp = [patch(a, k, j, i, R).astype(np.float64) for a in inputs]
-        ref = oracle.step(*pp, dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=nsteps, fp32=True)
+        ref = oracle.step(*pp, dx=dx, eps=eps, gamma=gamma, dt=dt, nsteps=nsteps,
+                          fp32=dtype == "f32")
         worst = max(worst, abs(float(out[k, j, i]) - ref[R, R, R]))
     print("worst sampled |gpu - oracle| =", worst, flush=True)
-    assert worst <= 1e-5
+    assert worst <= (1e-5 if dtype == "f32" else 1e-12)
 
 
 @pytest.mark.parametrize("form", [-1, 1])
