@@ -513,12 +513,13 @@ def write_traffic(args):
                                  "bytes": args.traffic_copy_bytes, "write_kib": write[copy_name][0]},
            "bytes_per_launch": int(per_launch), "moved_bytes_per_launch": int(moved),
            "counter_over_moved": round(per_launch / moved, 4),
-           "commands": [f"rocprofv3 --pmc {c} -d gpurun_out/pmc_{c}_{args.dtype} -o bench "
+           "commands": [f"rocprofv3 --pmc {c} -d {d} -o bench "
                         f"--output-format csv -- python3 bench.py --steps 3 --warmup 1 --quick "
                         f"--no-cpu-baseline --no-autotune --dtype {args.dtype} "
-                        f"--copy-probe {args.traffic_copy_bytes}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
-                       + [f"python3 bench.py --traffic-from gpurun_out/pmc_FETCH_SIZE_{args.dtype} "
-                          f"gpurun_out/pmc_WRITE_SIZE_{args.dtype} --dtype {args.dtype} "
+                        f"--copy-probe {args.traffic_copy_bytes}"
+                        for c, d in zip(("FETCH_SIZE", "WRITE_SIZE"), args.traffic_from)]
+                       + [f"python3 bench.py --traffic-from {args.traffic_from[0]} "
+                          f"{args.traffic_from[1]} --dtype {args.dtype} "
                           f"--traffic-variant {args.traffic_variant}"],
            "note": "means over the dispatches of each sweep; factors scale the raw KiB counters "
                    "to bytes by the library copy of known size"}
