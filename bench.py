@@ -426,9 +426,41 @@ def cpu_baseline(fx, n=128, budget_s=12.0, n1=64, budget1_s=8.0):
         el = time.perf_counter() - t0
         return c.cells * steps / el / 1e9, steps, el, used
 
+    def thr(k):
+        return f"{k} thread" + ("s" if k != 1 else "")
+
+    def fixed(c, U, V, W, threads, nsteps, scheme=4, vel_mode=0, vel_T=1.0, fp32=False):
+        oracle.set_threads(threads)
+        used = oracle.max_threads()
+        t0 = time.perf_counter()
+        oracle.step(c.phi0, U, V, W, dx=c.dx, eps=c.eps, gamma=c.gamma, dt=c.dt, nsteps=nsteps,
+                    scheme=scheme, vel_mode=vel_mode, vel_T=vel_T, fp32=fp32)
+        el = time.perf_counter() - t0
+        return round(c.cells * nsteps / el / 1e9, 6), round(el, 2), used
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     v_all, steps, el, used = rate(n, cores, budget_s)
     v_one, steps1, el1, _ = rate(n1, 1, budget1_s)
+    # the other sizes of the same recipe, FP64 oracle arithmetic in FP32-storage mode: 64^3 on
+    # every core (as many steps as the one-thread run took), 256^3 for 10 steps on every core;
+    # and the 2D reversing vortex (64 x 64, FP64, RK4, its whole run) on every core and one thread
+    runs = {}
+    c64 = fx.roofline512(n1, seed=3)
+    f64 = fx.fourier_faces(c64.shape, c64.dx, *c64.modes)
+    fx.set_speed(c64, fx.max_face_speed(*f64))
+    r = fixed(c64, *f64, cores, max(steps1, 1), fp32=True)
+    runs[f"{n1}^3, {thr(r[2])}"] = {"gcell_s": r[0], "steps": max(steps1, 1), "seconds": r[1]}
+    c256 = fx.roofline512(256, seed=3)
+    f256 = fx.fourier_faces(c256.shape, c256.dx, *c256.modes)
+    fx.set_speed(c256, fx.max_face_speed(*f256))
+    r = fixed(c256, *f256, cores, 10, fp32=True)
+    runs[f"256^3, {thr(r[2])}"] = {"gcell_s": r[0], "steps": 10, "seconds": r[1]}
+    del c256, f256
+    cv = fx.vortex2d(64)
+    for th in (cores, 1):
+        r = fixed(cv, cv.U, cv.V, cv.W, th, cv.nsteps, vel_mode=1, vel_T=cv.vel_T)
+        runs[f"vortex 64^2 FP64, {thr(r[2])}"] = {"gcell_s": r[0], "steps": cv.nsteps,
+                                                     "seconds": r[1]}
     oracle.set_threads(cores)
     return {"value": round(v_all, 5), "unit": "Gcell-updates/s", "cores": used, "kind": "oracle",
             "sample": f"{n}^3 instance of the same recipe (64 drops, 16 modes, eps=0.75dx, "
@@ -437,7 +469,8 @@ def cpu_baseline(fx, n=128, budget_s=12.0, n1=64, budget1_s=8.0):
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "single_thread": {"value": round(v_one, 6), "unit": "Gcell-updates/s",
                               "sample": f"{n1}^3 instance, {steps1} steps in {el1:.1f} s, "
-                                        "1 thread"}}
+                                        "1 thread"},
+            "other_runs": runs}
 
 
 def stored_traffic(khash: str, vname: str, n: int = 512, dtype: str = "f32"):
