@@ -220,6 +220,9 @@ def deformation_timing(pf, fx, st, dtype, n=256, steps=100):
             "frac_of_8tbs": round(ALG_WORDS * e * cells / ms / 1e6 / HBM_PEAK_GBS, 4),
             "moved_words_per_cell_update": words,
             "moved_frac_of_8tbs": round(words * e * cells / ms / 1e6 / HBM_PEAK_GBS, 4),
+            # phi, the accumulator, the middle stage and three face arrays: beside the 256 MB
+            # last-level cache, these fractions are partly cache-resident rather than HBM figures
+            "working_set_mb": round(6 * e * cells / 2 ** 20, 1),
             "kernel": name}
 
 
