@@ -323,8 +323,9 @@ def rollout_timing(pf, fx, dtype, n=128):
 
 
 def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
-    """The batched driver (default mode, and both modes forced) against a loop of single
-    solves (each its own handle, one stream, no graphs), on the same uneven FP32 instances."""
+    """The batched driver (default mode, both modes forced, and the autotuned shape and launch
+    form, the figure of record) against a loop of single solves (each its own handle, one
+    stream, no graphs), on the same uneven FP32 instances."""
     import torch
     cases = fx.batch_cases(count=count, nsteps=nsteps)
     params, fields = [], []
@@ -357,7 +358,16 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
             modes[mode] = cuda_timer(st, lambda: bs.step(*zip(*bf), nsteps=nsteps, stream=st))
         bs.close()
     params[0].variant = -1
-    t_batch = modes["default"]
+    # the shape and launch form the batch autotuner picks (every combination timed on private
+    # fields), then timed like the modes above: the batched figure of record
+    bs = pf.BatchSolver(params)
+    pick_shape, pick_pers, tune_times = bs.autotune(reps=2, stream=st)
+    bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+    with torch.cuda.stream(st):
+        bs.step(*zip(*bf), nsteps=50, stream=st)
+        modes["autotuned"] = cuda_timer(st, lambda: bs.step(*zip(*bf), nsteps=nsteps, stream=st))
+    bs.close()
+    t_batch = modes["autotuned"]
     # looped single solves, uncaptured
     solvers = [pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype="f32", use_graph=False)
                for p in params]
@@ -389,6 +399,9 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
             "looped_graph_ms": round(t_gloop, 2),
             "batched_gcell_s": round(cells * nsteps / t_batch / 1e6, 2),
             "batched_mode_ms": {k: round(v, 2) for k, v in modes.items()},
+            "autotune": {"shape": pick_shape, "persistent": pick_pers,
+                         "ms_per_step": {f"{k[0]}{'_persistent' if k[1] else ''}": round(v, 4)
+                                         for k, v in tune_times.items()}},
             "looped_gcell_s": round(cells * nsteps / t_loop / 1e6, 2),
             "speedup_vs_looped": round(t_loop / t_batch, 2),
             "speedup_vs_looped_graph": round(t_gloop / t_batch, 2)}

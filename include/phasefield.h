@@ -283,6 +283,28 @@ pf_status phasefield_batch_step(pf_batch *b, void *const *phi, const void *const
  * (NULL), PF_ERR_DEVICE. */
 pf_status phasefield_batch_set_persistent(pf_batch *b, int32_t persistent);
 
+/* Tile shape of the batched sweeps: 0 fused two-stage sweeps on 32x16 tiles (the fused mode's
+ * default), 1 fused sweeps on 64x8 tiles (fewer halo columns; instances whose rows are not a
+ * multiple of 64 pad their last tile column), 2 one launch per RK stage on 32x8 tiles (the
+ * per-stage mode). Every shape gives bit-identical results. The tile list is rebuilt; the next
+ * step re-uploads the per-instance tables and re-captures its graph (work queued on the batch's
+ * last stream is synchronised first). Errors: PF_ERR_INVALID (NULL, shape outside 0..2),
+ * PF_ERR_UNSUPPORTED (a fused shape while some instance has a walled z axis), PF_ERR_OOM,
+ * PF_ERR_DEVICE. */
+pf_status phasefield_batch_set_shape(pf_batch *b, int32_t shape);
+
+/* Time every tile shape (phasefield_batch_set_shape) in both launch forms
+ * (phasefield_batch_set_persistent) on private fields of the batch's instances (a uniform field
+ * and velocity; caller data is untouched), reps x 8 graph-replayed steps each after one
+ * untimed 8-step run, and leave the batch in the fastest combination, returned in *best_shape
+ * and *best_persistent (HOST, may be NULL). times_ms (HOST, may be NULL) receives 6 per-step
+ * times, index 2 * shape + persistent (-1 for a combination that does not apply). Allocates
+ * 4 fields per instance for the duration of the call; synchronises hip_stream, which must not be
+ * the NULL stream. Errors: PF_ERR_INVALID (NULL batch or stream, reps < 1), PF_ERR_OOM,
+ * PF_ERR_DEVICE. */
+pf_status phasefield_batch_autotune(pf_batch *b, int32_t reps, int32_t *best_shape,
+                                    int32_t *best_persistent, double *times_ms, void *hip_stream);
+
 pf_status phasefield_batch_destroy(pf_batch *b);
 
 /* Copy `bytes` bytes (a multiple of 4) from src to dst, both device pointers, asynchronously

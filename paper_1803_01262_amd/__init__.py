@@ -18,6 +18,7 @@ from ._capi import (EXPORTED, PF_BC_PERIODIC, PF_BC_WALL, PF_ERR_DEVICE, PF_ERR_
                     PhaseFieldError, Report, cells, lib, make_params, phasefield_adjoint_step,
                     phasefield_autotune, phasefield_batch_create, phasefield_batch_destroy,
                     phasefield_batch_step, phasefield_batch_set_persistent,
+                    phasefield_batch_set_shape, phasefield_batch_autotune,
                     phasefield_check_params, phasefield_create,
                     phasefield_default_params, phasefield_destroy, phasefield_last_error,
                     phasefield_reduce, phasefield_set_adjoint_form, phasefield_set_spacing,
@@ -116,6 +117,22 @@ class BatchSolver:
     def set_persistent(self, persistent: bool = True):
         """Launch form of the sweeps: a persistent resident grid, or one workgroup per tile."""
         phasefield_batch_set_persistent(self.handle, persistent)
+
+    SHAPES = ("fused_32x16", "fused_64x8", "stage_32x8")
+
+    def set_shape(self, shape):
+        """Tile shape of the sweeps: index into SHAPES or its name."""
+        phasefield_batch_set_shape(self.handle, self.SHAPES.index(shape) if isinstance(shape, str) else shape)
+
+    def autotune(self, reps=2, stream=None):
+        """Time every shape and launch form on private fields, keep the fastest; returns
+        (shape name, persistent, {(shape name, persistent): ms per step})."""
+        if stream is None:  # graphs are captured: not on the NULL stream
+            stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        bs, bp, times = phasefield_batch_autotune(self.handle, reps, stream)
+        table = {(self.SHAPES[k // 2], bool(k % 2)): t for k, t in enumerate(times) if t >= 0}
+        return self.SHAPES[bs], bool(bp), table
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -89,6 +89,8 @@ def _load():
         "phasefield_batch_step": (i32, [vp, P(vp), P(vp), P(vp), P(vp), P(d), i32, vp]),
         "phasefield_batch_destroy": (i32, [vp]),
         "phasefield_batch_set_persistent": (i32, [vp, i32]),
+        "phasefield_batch_set_shape": (i32, [vp, i32]),
+        "phasefield_batch_autotune": (i32, [vp, i32, P(i32), P(i32), P(d), vp]),
         "phasefield_last_error": (ctypes.c_char_p, []),
         "phasefield_step_noalloc": (i32, [P(Params), vp, vp, vp, vp, d, i32, vp]),
         "phasefield_noalloc_scratch_bytes": (ctypes.c_size_t, []),
@@ -110,7 +112,8 @@ EXPORTED = ("phasefield_default_params", "phasefield_check_params", "phasefield_
             "phasefield_variant_name", "phasefield_autotune", "phasefield_solver_variant",
             "phasefield_set_adjoint_form", "phasefield_set_spacing",
             "phasefield_batch_create", "phasefield_batch_step", "phasefield_batch_destroy",
-            "phasefield_batch_set_persistent",
+            "phasefield_batch_set_persistent", "phasefield_batch_set_shape",
+            "phasefield_batch_autotune",
             "phasefield_last_error", "phasefield_step_noalloc",
             "phasefield_noalloc_scratch_bytes", "phasefield_device_copy")
 
@@ -316,6 +319,19 @@ def phasefield_set_adjoint_form(h, form: int) -> None:
 
 def phasefield_batch_set_persistent(h, persistent: bool) -> None:
     _check(lib.phasefield_batch_set_persistent(h, int(bool(persistent))))
+
+
+def phasefield_batch_set_shape(h, shape: int) -> None:
+    _check(lib.phasefield_batch_set_shape(h, int(shape)))
+
+
+def phasefield_batch_autotune(h, reps, stream):
+    """(best shape, best persistent flag, list of 6 per-step times in ms, -1 where n/a)."""
+    bs, bp = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    times = (ctypes.c_double * 6)()
+    _check(lib.phasefield_batch_autotune(h, int(reps), ctypes.byref(bs), ctypes.byref(bp), times,
+                                         _stream(stream)))
+    return int(bs.value), int(bp.value), list(times)
 
 
 def phasefield_batch_destroy(h) -> None:

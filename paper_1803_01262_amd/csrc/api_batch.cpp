@@ -8,7 +8,9 @@
 //              buffer from step to step; tables for even and odd steps are kept, and after an
 //              odd step count one batched copy returns phi to the caller's buffers.
 //   per-stage: four launches per step, fixed buffers.
-// Either way every instance is bit-identical to its own single solve.
+// Either way every instance is bit-identical to its own single solve. The tile shape (fused
+// 32x16 or 64x8, per-stage 32x8) and the launch form can be set, or chosen by timing them all
+// (phasefield_batch_autotune).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +33,7 @@ struct pf_batch {
     bool persistent = false;  // launch form: resident-slot grid looping over the list
     bool wide = false;  // every instance's nx allows 16-byte plane loads
     bool walls = false;  // some instance has walls
+    int shape = kBatchStage32x8;  // BatchShape of the tile list
     BatchTile* tiles = nullptr;  // device: the global tile list (8 equal per-XCD ranges)
     // device per-instance argument arrays: per-stage mode S1..S4 (StageArgs);
     // fused mode A_even, B_even, A_odd, B_odd (FusedArgs)
@@ -81,11 +84,11 @@ static bool B_mode_fused(const pf_params* per_instance, int count)
 // first, each onto the least-loaded XCD), so the tiles of one instance share one L2; within an
 // XCD's range the tiles run longest z-chunk first, so short tiles fill the end; the ranges are
 // padded to one length with empty entries (the launch maps workgroup ids onto the ranges).
-static bool build_tile_list(const pf_params* p, int count, bool fused, std::vector<BatchTile>& out)
+static bool build_tile_list(const pf_params* p, int count, int shape, std::vector<BatchTile>& out)
 {
     int TX, TY, KZ;
-    batch_tile_shape(fused, &TX, &TY, &KZ);
-    const int warm = fused ? 6 : 2;  // warm-up planes per z-chunk
+    batch_tile_shape(shape, &TX, &TY, &KZ);
+    const int warm = shape != kBatchStage32x8 ? 6 : 2;  // warm-up planes per z-chunk
     std::vector<double> work(count);
     std::vector<int> order(count);
     for (int b = 0; b < count; ++b) {
@@ -141,12 +144,14 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
                         "instance %d: a field of 4 GiB or more; use a single-grid solver", b);
     }
     std::vector<BatchTile> list;
-    if (!build_tile_list(per_instance, count, B_mode_fused(per_instance, count), list))
+    const int shape = B_mode_fused(per_instance, count) ? kBatchFused32x16 : kBatchStage32x8;
+    if (!build_tile_list(per_instance, count, shape, list))
         return fail(PF_ERR_INVALID, "the batch has too many tiles for one launch");
     auto* B = new pf_batch();
     B->count = count;
     B->dtype = per_instance[0].dtype;
-    B->fused = B_mode_fused(per_instance, count);
+    B->shape = shape;
+    B->fused = shape != kBatchStage32x8;
     B->p.assign(per_instance, per_instance + count);
     const size_t esz = B->dtype == PF_F32 ? sizeof(float) : sizeof(double);
     size_t total = 0;
@@ -166,11 +171,10 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
     if (e == hipSuccess) e = hipMalloc((void**)&B->tiles, list.size() * sizeof(BatchTile));
     if (e == hipSuccess)
         e = hipMemcpy(B->tiles, list.data(), list.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
-    size_t tsz;
-    if (B->fused)
-        tsz = B->dtype == PF_F32 ? sizeof(FusedArgs<float>) : sizeof(FusedArgs<double>);
-    else
-        tsz = B->dtype == PF_F32 ? sizeof(StageArgs<float>) : sizeof(StageArgs<double>);
+    // room for either mode's per-instance arguments (the shape can change later)
+    const size_t tsz = B->dtype == PF_F32
+                           ? std::max(sizeof(FusedArgs<float>), sizeof(StageArgs<float>))
+                           : std::max(sizeof(FusedArgs<double>), sizeof(StageArgs<double>));
     for (int s = 0; s < 4 && e == hipSuccess; ++s) e = hipMalloc(&B->tables[s], tsz * count);
     if (e == hipSuccess)
         e = hipMalloc(&B->copies, (B->dtype == PF_F32 ? sizeof(BatchCopy<float>) : sizeof(BatchCopy<double>)) * count);
@@ -238,7 +242,7 @@ static hipError_t enqueue_batch_step(pf_batch* B, bool odd, hipStream_t st)
         for (int s = 0; s < 2; ++s) {
             hipError_t e = launch_batch_fused<T>((const FusedArgs<T>*)B->tables[(odd ? 2 : 0) + s],
                                                  s == 1, B->wide, B->tiles, B->num_tiles,
-                                                 B->persistent, B->walls, st);
+                                                 B->persistent, B->walls, B->shape, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -338,4 +342,152 @@ extern "C" pf_status phasefield_batch_step(pf_batch* b, void* const* phi, const 
     hipStream_t hs = (hipStream_t)hip_stream;
     return b->dtype == PF_F32 ? batch_step_impl<float>(b, phi, u, v, w, nsteps, hs)
                               : batch_step_impl<double>(b, phi, u, v, w, nsteps, hs);
+}
+
+// Rebuild the tile list for another shape. Queued work on the batch's last stream may still read
+// the old list and tables, so that stream is synchronised first; the next step re-uploads the
+// tables and re-captures the graph.
+static pf_status batch_apply_shape(pf_batch* b, int shape)
+{
+    if (shape == b->shape) return PF_OK;
+    std::vector<BatchTile> list;
+    if (!build_tile_list(b->p.data(), b->count, shape, list))
+        return fail(PF_ERR_INVALID, "the batch has too many tiles for one launch");
+    hipError_t e = b->key_stream ? hipStreamSynchronize(b->key_stream) : hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "phasefield_batch_set_shape: synchronize");
+    batch_release_graph(b);
+    BatchTile* tiles = nullptr;
+    e = hipMalloc((void**)&tiles, list.size() * sizeof(BatchTile));
+    if (e == hipSuccess)
+        e = hipMemcpy(tiles, list.data(), list.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (tiles) (void)hipFree(tiles);
+        return e == hipErrorOutOfMemory ? fail(PF_ERR_OOM, "phasefield_batch_set_shape: out of memory")
+                                        : hip_fail(e, "phasefield_batch_set_shape: tile list");
+    }
+    if (b->tiles) (void)hipFree(b->tiles);
+    b->tiles = tiles;
+    b->num_tiles = (int)list.size();
+    b->shape = shape;
+    b->fused = shape != kBatchStage32x8;
+    b->key.clear();  // the tables of the new mode are uploaded by the next step
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_batch_set_shape(pf_batch* b, int32_t shape)
+{
+    if (!b) return fail(PF_ERR_INVALID, "batch is NULL");
+    if (shape < 0 || shape >= kNumBatchShapes)
+        return fail(PF_ERR_INVALID, "batch shape %d is not 0, 1 or 2", (int)shape);
+    if (shape != kBatchStage32x8)
+        for (int i = 0; i < b->count; ++i)
+            if (wall_mask(b->p[i]) & 4)
+                return fail(PF_ERR_UNSUPPORTED, "instance %d has a z wall: per-stage shape only", i);
+    return batch_apply_shape(b, shape);
+}
+
+template <typename T>
+static pf_status batch_autotune_impl(pf_batch* B, int reps, int32_t* best_shape,
+                                     int32_t* best_persistent, double* times_ms, hipStream_t st)
+{
+    // private operands for every instance: a smooth bounded field and a uniform velocity (the
+    // timing does not depend on the values)
+    size_t total = 0;
+    for (int b = 0; b < B->count; ++b) total += 4 * padded(B->N[b]);
+    T* pool = nullptr;
+    hipError_t e = hipMalloc((void**)&pool, total * sizeof(T));
+    if (e != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(PF_ERR_OOM, "phasefield_batch_autotune: out of memory")
+                                        : hip_fail(e, "phasefield_batch_autotune: allocation");
+    std::vector<void*> phi(B->count);
+    std::vector<const void*> u(B->count), v(B->count), w(B->count);
+    size_t off = 0;
+    for (int b = 0; b < B->count && e == hipSuccess; ++b) {
+        const size_t n = B->N[b], pn = padded(n);
+        T* base = pool + off;
+        off += 4 * pn;
+        phi[b] = base;
+        u[b] = base + pn;
+        v[b] = base + 2 * pn;
+        w[b] = base + 3 * pn;
+        e = launch_fill<T>(base, (T)0.5, n, st);
+        for (int k = 1; k < 4 && e == hipSuccess; ++k) e = launch_fill<T>(base + k * pn, (T)0.1, n, st);
+    }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    pf_status ret = e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_batch_autotune: set-up");
+    const int start_shape = B->shape;
+    const bool start_persistent = B->persistent;
+    double best_t = INFINITY;
+    int bs = start_shape, bp = start_persistent ? 1 : 0;
+    bool zwall = false;
+    for (int b = 0; b < B->count; ++b) zwall = zwall || (wall_mask(B->p[b]) & 4) != 0;
+    const int steps = kGraphSteps * std::max(reps, 1);
+    for (int shape = 0; shape < kNumBatchShapes && ret == PF_OK; ++shape) {
+        for (int pers = 0; pers < 2 && ret == PF_OK; ++pers) {
+            const int slot = 2 * shape + pers;
+            if (times_ms) times_ms[slot] = -1.0;
+            if (zwall && shape != kBatchStage32x8) continue;  // fused shapes take no z walls
+            ret = batch_apply_shape(B, shape);
+            if (ret != PF_OK) break;
+            if (B->persistent != (pers != 0)) {
+                batch_release_graph(B);
+                B->persistent = pers != 0;
+            }
+            // one graph-length run first: table upload and capture stay out of the timing
+            ret = batch_step_impl<T>(B, phi.data(), u.data(), v.data(), w.data(), kGraphSteps, st);
+            if (ret != PF_OK) break;
+            e = hipEventRecord(ev0, st);
+            if (e == hipSuccess) {
+                ret = batch_step_impl<T>(B, phi.data(), u.data(), v.data(), w.data(), steps, st);
+                if (ret != PF_OK) break;
+                e = hipEventRecord(ev1, st);
+            }
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (e != hipSuccess) {
+                ret = hip_fail(e, "phasefield_batch_autotune: timing");
+                break;
+            }
+            const double per = ms / steps;
+            if (times_ms) times_ms[slot] = per;
+            if (per < best_t) {
+                best_t = per;
+                bs = shape;
+                bp = pers;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    // the private pointers must not be mistaken for a caller's set later
+    batch_release_graph(B);
+    B->key.clear();
+    (void)hipFree(pool);
+    if (ret != PF_OK) {
+        (void)batch_apply_shape(B, start_shape);
+        B->persistent = start_persistent;
+        return ret;
+    }
+    ret = batch_apply_shape(B, bs);
+    if (ret != PF_OK) return ret;
+    B->persistent = bp != 0;
+    if (best_shape) *best_shape = bs;
+    if (best_persistent) *best_persistent = bp;
+    return PF_OK;
+}
+
+extern "C" pf_status phasefield_batch_autotune(pf_batch* b, int32_t reps, int32_t* best_shape,
+                                               int32_t* best_persistent, double* times_ms,
+                                               void* hip_stream)
+{
+    if (!b) return fail(PF_ERR_INVALID, "batch is NULL");
+    if (reps < 1) return fail(PF_ERR_INVALID, "reps < 1");
+    hipStream_t hs = (hipStream_t)hip_stream;
+    if (!hs) return fail(PF_ERR_INVALID, "the batch autotuner needs a stream (graphs are captured)");
+    return b->dtype == PF_F32 ? batch_autotune_impl<float>(b, reps, best_shape, best_persistent, times_ms, hs)
+                              : batch_autotune_impl<double>(b, reps, best_shape, best_persistent, times_ms, hs);
 }

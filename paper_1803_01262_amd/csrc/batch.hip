@@ -7,10 +7,11 @@
 
 namespace pf {
 
-// Tile shapes: 32 wide (instances down to 32 cells), 64-plane z-chunks (a whole number of the
-// six-iteration groups of the marches, and little warm-up per chunk).
-constexpr int kBTX = 32, kBTY = 8, kBKZ = 64;   // per-stage mode tile shape
-constexpr int kFTX = 32, kFTY = 16, kFKZ = 64;  // fused mode tile shape
+// Tile shapes (BatchShape): fused 32x16 (instances down to 32 cells wide), fused 64x8 (fewer
+// halo columns where rows are whole multiples of 64), per-stage 32x8; 64-plane z-chunks (little
+// warm-up per chunk; 96 and 128 planes measured no faster).
+constexpr int kBTX = 32, kBTY = 8, kBKZ = 64;   // per-stage tile
+constexpr int kFKZ = 64;                        // fused tiles' z-chunk
 
 // Workgroup -> tile-list entry: the list holds 8 equal ranges of `len` entries, one per XCD.
 // One workgroup per entry: xcd_tile_order lets each XCD walk its own range in order.
@@ -53,14 +54,14 @@ __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs
 // kernel (FP32: four waves per SIMD).
 // WIDE: every instance's rows are a whole number of 16-byte pieces (16-byte plane loads).
 // WALLS: walls on x and/or y in some instance (element-wise loads, WIDE off).
-template <typename T, bool SWEEP_B, bool WIDE, bool PERSIST, bool WALLS = false>
-__global__ void __launch_bounds__(kFTX* kFTY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+template <typename T, int TX, int TY, bool SWEEP_B, bool WIDE, bool PERSIST, bool WALLS = false>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __restrict__ tiles, int len)
 {
     for_batch_tiles<PERSIST>(tiles, len, [&](const BatchTile& tl) {
         const int k0 = tl.tk * kFKZ;
-        fused_body<T, kFTX, kFTY, SWEEP_B, false, WIDE, false, WALLS>(args[tl.b], tl.ti, tl.tj, k0,
-                                                                     min(k0 + kFKZ, args[tl.b].nz));
+        fused_body<T, TX, TY, SWEEP_B, false, WIDE, false, WALLS>(args[tl.b], tl.ti, tl.tj, k0,
+                                                                 min(k0 + kFKZ, args[tl.b].nz));
     });
 }
 
@@ -73,11 +74,11 @@ __global__ void batch_copy_kernel(const BatchCopy<T>* __restrict__ e)
         c.dst[i] = c.src[i];
 }
 
-void batch_tile_shape(bool fused, int* tx, int* ty, int* kz)
+void batch_tile_shape(int shape, int* tx, int* ty, int* kz)
 {
-    *tx = fused ? kFTX : kBTX;
-    *ty = fused ? kFTY : kBTY;
-    *kz = fused ? kFKZ : kBKZ;
+    *tx = shape == kBatchFused64x8 ? 64 : 32;
+    *ty = shape == kBatchFused32x16 ? 16 : 8;
+    *kz = shape == kBatchStage32x8 ? kBKZ : kFKZ;
 }
 
 // Grid of the persistent form: the resident slots of the kernel (compute units x workgroups per
@@ -91,40 +92,54 @@ static int persistent_grid(const void* kernel, int threads, int num_tiles)
     return g > num_tiles ? num_tiles : g;
 }
 
-template <typename T, bool SWEEP_B, bool WIDE, bool WALLS = false>
+template <typename T, int TX, int TY, bool SWEEP_B, bool WIDE, bool WALLS = false>
 static hipError_t launch_batch_fused_form(const FusedArgs<T>* args_dev, const BatchTile* tiles_dev,
                                           int num_tiles, bool persistent, hipStream_t st)
 {
     const int len = num_tiles / 8;
     if (persistent) {
-        const void* k = (const void*)batch_fused_kernel<T, SWEEP_B, WIDE, true, WALLS>;
-        const int g = persistent_grid(k, kFTX * kFTY, num_tiles);
+        const void* k = (const void*)batch_fused_kernel<T, TX, TY, SWEEP_B, WIDE, true, WALLS>;
+        const int g = persistent_grid(k, TX * TY, num_tiles);
         if (g < 8) return hipErrorInvalidDevice;
-        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, true, WALLS>), dim3(g),
-                           dim3(kFTX * kFTY), 0, st, args_dev, tiles_dev, len);
+        hipLaunchKernelGGL((batch_fused_kernel<T, TX, TY, SWEEP_B, WIDE, true, WALLS>), dim3(g),
+                           dim3(TX * TY), 0, st, args_dev, tiles_dev, len);
     } else {
-        hipLaunchKernelGGL((batch_fused_kernel<T, SWEEP_B, WIDE, false, WALLS>), dim3(num_tiles),
-                           dim3(kFTX * kFTY), 0, st, args_dev, tiles_dev, len);
+        hipLaunchKernelGGL((batch_fused_kernel<T, TX, TY, SWEEP_B, WIDE, false, WALLS>),
+                           dim3(num_tiles), dim3(TX * TY), 0, st, args_dev, tiles_dev, len);
     }
     return hipGetLastError();
+}
+
+template <typename T, int TX, int TY>
+static hipError_t launch_batch_fused_shape(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
+                                           const BatchTile* tiles_dev, int num_tiles,
+                                           bool persistent, bool walls, hipStream_t st)
+{
+    if (walls) {
+        if (wide) return hipErrorInvalidValue;
+        return sweep_b ? launch_batch_fused_form<T, TX, TY, true, false, true>(args_dev, tiles_dev, num_tiles, persistent, st)
+                       : launch_batch_fused_form<T, TX, TY, false, false, true>(args_dev, tiles_dev, num_tiles, persistent, st);
+    }
+    if (wide)
+        return sweep_b ? launch_batch_fused_form<T, TX, TY, true, true>(args_dev, tiles_dev, num_tiles, persistent, st)
+                       : launch_batch_fused_form<T, TX, TY, false, true>(args_dev, tiles_dev, num_tiles, persistent, st);
+    return sweep_b ? launch_batch_fused_form<T, TX, TY, true, false>(args_dev, tiles_dev, num_tiles, persistent, st)
+                   : launch_batch_fused_form<T, TX, TY, false, false>(args_dev, tiles_dev, num_tiles, persistent, st);
 }
 
 template <typename T>
 hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
                               const BatchTile* tiles_dev, int num_tiles, bool persistent,
-                              bool walls, hipStream_t st)
+                              bool walls, int shape, hipStream_t st)
 {
     if (num_tiles <= 0 || num_tiles % 8) return hipErrorInvalidValue;
-    if (walls) {
-        if (wide) return hipErrorInvalidValue;
-        return sweep_b ? launch_batch_fused_form<T, true, false, true>(args_dev, tiles_dev, num_tiles, persistent, st)
-                       : launch_batch_fused_form<T, false, false, true>(args_dev, tiles_dev, num_tiles, persistent, st);
-    }
-    if (wide)
-        return sweep_b ? launch_batch_fused_form<T, true, true>(args_dev, tiles_dev, num_tiles, persistent, st)
-                       : launch_batch_fused_form<T, false, true>(args_dev, tiles_dev, num_tiles, persistent, st);
-    return sweep_b ? launch_batch_fused_form<T, true, false>(args_dev, tiles_dev, num_tiles, persistent, st)
-                   : launch_batch_fused_form<T, false, false>(args_dev, tiles_dev, num_tiles, persistent, st);
+    if (shape == kBatchFused32x16)
+        return launch_batch_fused_shape<T, 32, 16>(args_dev, sweep_b, wide, tiles_dev, num_tiles,
+                                                   persistent, walls, st);
+    if (shape == kBatchFused64x8)
+        return launch_batch_fused_shape<T, 64, 8>(args_dev, sweep_b, wide, tiles_dev, num_tiles,
+                                                  persistent, walls, st);
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -134,8 +149,8 @@ hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, bool, const BatchTile*, int, bool, bool, hipStream_t);
-template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, bool, const BatchTile*, int, bool, bool, hipStream_t);
+template hipError_t launch_batch_fused<float>(const FusedArgs<float>*, bool, bool, const BatchTile*, int, bool, bool, int, hipStream_t);
+template hipError_t launch_batch_fused<double>(const FusedArgs<double>*, bool, bool, const BatchTile*, int, bool, bool, int, hipStream_t);
 template hipError_t launch_batch_copy<float>(const BatchCopy<float>*, int, hipStream_t);
 template hipError_t launch_batch_copy<double>(const BatchCopy<double>*, int, hipStream_t);
 

@@ -224,11 +224,13 @@ hipError_t launch_batch_stage(const StageArgs<T>* args_dev, const BatchTile* til
 template <typename T>
 hipError_t launch_batch_fused(const FusedArgs<T>* args_dev, bool sweep_b, bool wide,
                               const BatchTile* tiles_dev, int num_tiles, bool persistent,
-                              bool walls, hipStream_t st);
+                              bool walls, int shape, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_copy(const BatchCopy<T>* table_dev, int count, hipStream_t st);
-// Tile shape of a batch mode: x, y extent and z-chunk.
-void batch_tile_shape(bool fused, int* tx, int* ty, int* kz);
+// Tile shapes of the batched sweeps (the values of phasefield_batch_set_shape).
+enum BatchShape { kBatchFused32x16 = 0, kBatchFused64x8 = 1, kBatchStage32x8 = 2, kNumBatchShapes = 3 };
+// Tile of a batch shape: x, y extent and z-chunk.
+void batch_tile_shape(int shape, int* tx, int* ty, int* kz);
 
 // ------------------------------------------------------------------ adjoint (adjoint.hip)
 // Tiled z-march with tile shape `tile` (an index from adjoint_tile_index or

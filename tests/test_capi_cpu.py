@@ -118,3 +118,11 @@ def test_noalloc_step_refuses_oversized_grid_on_the_host(pf):
 def test_adjoint_form_setter_checks_its_arguments(pf):
     assert pf.lib.phasefield_set_adjoint_form(None, 0) == pf.PF_ERR_INVALID
     assert "NULL" in pf.phasefield_last_error()
+
+
+def test_batch_shape_and_autotune_check_their_arguments(pf):
+    import ctypes
+    assert pf.lib.phasefield_batch_set_shape(None, 0) == pf.PF_ERR_INVALID
+    bs, bp = ctypes.c_int32(), ctypes.c_int32()
+    assert pf.lib.phasefield_batch_autotune(None, 1, ctypes.byref(bs), ctypes.byref(bp), None,
+                                            None) == pf.PF_ERR_INVALID

@@ -307,11 +307,12 @@ def _batch_instances(sizes, seed=4):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("mode", ["default", "fused", "per-stage", "fused-persistent",
-                                  "per-stage-persistent"])
+                                  "per-stage-persistent", "shape64", "shape64-persistent"])
 def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
     """Both batched modes (chosen through instance 0's variant), each in both launch forms (one
-    workgroup per tile entry, or a persistent resident grid), give every instance exactly its
-    own single solve, over uneven, ragged and degenerate grids."""
+    workgroup per tile entry, or a persistent resident grid), and the fused sweeps on 64x8 tiles
+    (set_shape), give every instance exactly its own single solve, over uneven, ragged and
+    degenerate grids."""
     pf = lib
     sizes = [(32, 32, 32), (48, 40, 24), (17, 9, 33), (64, 64, 8), (5, 70, 3), (96, 1, 1),
              (40, 24, 130)]
@@ -319,7 +320,7 @@ def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
     names = [pf.phasefield_variant_name(kd, v) for v in range(pf.phasefield_variant_count(kd))]
-    pick = {"default": -1, "fused": names.index("fused_32x16x32"),
+    pick = {"default": -1, "fused": names.index("fused_32x16x32"), "shape64": -1,
             "per-stage": names.index("tiled_64x8x16")}[mode.replace("-persistent", "")]
     params, singles = [], []
     for (n, dx, phi, U, V, W) in cases:
@@ -327,6 +328,8 @@ def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
     params[0].variant = pick
     st = torch.cuda.Stream()
     bs = pf.BatchSolver(params)
+    if mode.startswith("shape64"):
+        bs.set_shape("fused_64x8")
     if mode.endswith("persistent"):
         bs.set_persistent(True)
     bt = [[dev(a, tdt) for a in cs[2:]] for cs in cases]
@@ -342,6 +345,49 @@ def test_batch_bitwise_equals_single_solves(lib, dtype, mode):
         assert torch.equal(g[0], b[0]), p.n[:]
         s.close()
     bs.close()
+
+
+@pytest.mark.parametrize("dtype,zwall", [("f32", False), ("f64", False), ("f32", True)])
+def test_batch_autotune(lib, dtype, zwall):
+    """The batch autotuner times every tile shape in both launch forms on private fields, leaves
+    the batch in the fastest combination (the minimum of the reported times) and the caller's
+    fields untouched; the tuned batch then gives every instance its single solve bit for bit. A
+    walled z axis leaves only the per-stage shape (the fused shapes are reported as n/a and
+    refused by set_shape)."""
+    pf = lib
+    sizes = [(32, 32, 32), (48, 40, 24), (64, 64, 8), (17, 9, 33)]
+    cases = _batch_instances(sizes, seed=41)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    walls = [(False, False, True) if (zwall and k == 1) else (False, False, False)
+             for k in range(len(sizes))]
+    params = [pf.make_params(n, dx, dx, 1.0, fx.rk4_dt_3d(dx, 1.0, dx), dtype=dtype, walls=wl)
+              for (n, dx, *_r), wl in zip(cases, walls)]
+    bs = pf.BatchSolver(params)
+    bt = [[dev(a, tdt) for a in cs[2:]] for cs in cases]
+    keep = [b[0].clone() for b in bt]
+    st = torch.cuda.Stream()
+    shape, persistent, times = bs.autotune(reps=1, stream=st)
+    print(dtype, "zwall" if zwall else "", "autotune", shape, persistent, times, flush=True)
+    assert all(torch.equal(b[0], k) for b, k in zip(bt, keep))  # caller data untouched
+    expect = 2 if zwall else 6
+    assert len(times) == expect and all(t > 0 for t in times.values())
+    assert times[(shape, persistent)] == min(times.values())
+    if zwall:
+        assert shape == "stage_32x8"
+        with pytest.raises(pf.PhaseFieldError) as ei:
+            bs.set_shape("fused_32x16")
+        assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+    with torch.cuda.stream(st):
+        bs.step(*zip(*bt), nsteps=11, stream=st)
+    st.synchronize()
+    bs.close()
+    for p, cs, b, wl in zip(params, cases, bt, walls):
+        s = pf.Solver(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype=dtype, walls=wl)
+        g = [dev(a, tdt) for a in cs[2:]]
+        s.step(*g, nsteps=11)
+        torch.cuda.synchronize()
+        assert torch.equal(g[0], b[0]), p.n[:]
+        s.close()
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
