@@ -60,8 +60,8 @@ batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __res
 {
     for_batch_tiles<PERSIST>(tiles, len, [&](const BatchTile& tl) {
         const int k0 = tl.tk * kFKZ;
-        fused_body<T, TX, TY, SWEEP_B, false, WIDE, false, WALLS>(args[tl.b], tl.ti, tl.tj, k0,
-                                                                 min(k0 + kFKZ, args[tl.b].nz));
+        fused_body<T, TX, TY, SWEEP_B, false, WIDE, false, WALLS, fused_lag<T, TX, TY>()>(
+            args[tl.b], tl.ti, tl.tj, k0, min(k0 + kFKZ, args[tl.b].nz));
     });
 }
 

@@ -40,6 +40,12 @@
 // main loop, which runs E1 and E2 in whole groups of six unconditional iterations so that the
 // values handed from plane to plane stay in place; iterations past the chunk end compute on
 // wrapped planes and store nothing. Two barriers per iteration.
+// LAG (the one-barrier march): E2 trails E1 by one more plane (q2 at plane t, outputs of plane
+// t-1) and each iteration commits the planes of the next one, so that within an iteration every
+// LDS read is of data written in earlier iterations and every write goes to a slot nobody reads
+// in it; one barrier ends the iteration. The cost is deeper rings (four stage-input and four
+// middle-stage planes, two of each staged plane, a fourth own-cell queue entry), five warm-up
+// iterations and groups of four. Same arithmetic in the same order: bit-identical results.
 // Global memory goes through FieldRef buffer descriptors (BIG: arrays of 4 GiB or more). With
 // WIDE (nx a multiple of 16 bytes' worth of elements), the planes of the stage input and of phi
 // are read in 16-byte pieces: groups of consecutive x-columns that start at a multiple of the
@@ -61,9 +67,18 @@
 
 namespace pf {
 
+// The one-barrier march wherever its deeper rings fit in LDS: every FP32 tile (64 x 8: 55-62 KB
+// per workgroup, two per compute unit) and 32-wide FP64 tiles (32 x 16: 136-148 KB, one per
+// compute unit); FP64 64 x 8 tiles would need 166 KB and keep the two-barrier march.
+template <typename T, int TX, int TY>
+constexpr bool fused_lag()
+{
+    return sizeof(T) == 4 || TX == 32;
+}
+
 // The workgroup owns the TX x TY column tile (ti, tj) and the output planes [k0, k1).
 template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT = false,
-          bool WALLS = false>
+          bool WALLS = false, bool LAG = false>
 __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int k0, int k1)
 {
     static_assert(!(XOUT && SWEEP_B), "the optional outputs belong to sweep A");
@@ -91,20 +106,23 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     constexpr int NLB = SWEEP_B ? (WIDE ? (INGW * MH + NT - 1) / NT : (MS + NT - 1) / NT) : 0;
     static_assert(OUT0 + NOUT <= NT, "tile too small for the E1 halo assignment");
     static_assert(NH2 <= NT, "tile too small for the E2 halo assignment");
+    // ring depths: stage input and middle-stage planes, staged planes (velocities, phi on MID),
+    // own-cell queue from E1 to E2
+    constexpr int NIN = LAG ? 4 : 3, NMID = LAG ? 4 : 3, NSTG = LAG ? 2 : 1, NQ = LAG ? 4 : 3;
 
     // separate arrays, so that the compiler knows the regions do not overlap
-    __shared__ __align__(16) T s_in[3 * INS];
-    __shared__ T s_mid[3 * MS];
+    __shared__ __align__(16) T s_in[NIN * INS];
+    __shared__ T s_mid[NMID * MS];
     __shared__ T s_q1x[2 * Q1XS];
     __shared__ T s_q1y[2 * Q1YS];
     __shared__ T s_q2x[2 * Q2XS];
     __shared__ T s_q2y[2 * Q2YS];
-    __shared__ __align__(16) T s_pb[SWEEP_B ? PBS : 1];
+    __shared__ __align__(16) T s_pb[SWEEP_B ? NSTG * PBS : 1];
     // velocity staging (x from i0-4 at the IN width, rows from j0-2): U on MH rows, V on MH+1
     // rows (its +y neighbour), W on MH rows
     constexpr bool STAGE = sizeof(T) == 8;  // velocity staging (FP64)
     constexpr int VSU = 0, VSV = MH * INW, VSW = (2 * MH + 1) * INW, VSS = (3 * MH + 1) * INW;
-    __shared__ __align__(16) T s_vel[STAGE ? VSS : 1];
+    __shared__ __align__(16) T s_vel[STAGE ? NSTG * VSS : 1];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * ny;
@@ -297,17 +315,17 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 pre_v[s] = load_piece(fW, kw1, lv_off[s]);
         }
     };
-    auto commit_vel = [&]() {
+    auto commit_vel = [&](int slot) {
 #pragma unroll
         for (int s = 0; s < NLV; ++s) {
             const int e = tid + s * NT;
-            if (e < NGVEL) put_piece(s_vel + e * PV, pre_v[s]);
+            if (e < NGVEL) put_piece(s_vel + slot * VSS + e * PV, pre_v[s]);
         }
     };
-    auto commit_b = [&]() {
+    auto commit_b = [&](int slot) {
 #pragma unroll
         for (int s = 0; s < NLB; ++s)
-            if (lb_pos[s] >= 0) put_piece(s_pb + lb_pos[s], pre_b[s]);
+            if (lb_pos[s] >= 0) put_piece(s_pb + slot * PBS + lb_pos[s], pre_b[s]);
     };
 
     // per-slot z state of E1 (q1_z and the z-face flux) and of E2
@@ -316,35 +334,72 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     T e_qzm[2] = {T(0), T(0)}, e_qz[2] = {T(0), T(0)}, e_sz[2] = {T(0), T(0)};
     T e_dz[2] = {T(0), T(0)}, e_w0[2] = {T(0), T(0)};
     T q2zm = T(0), q2z = T(0), sz2 = T(0), dz2 = T(0), w2 = T(0);
-    // own-cell queues from E1 (plane p) to E2 (plane p, two iterations later): after E1 of
-    // iteration t they hold planes t, t+1, t+2 in entries 0, 1, 2
-    T qa_phi[3] = {T(0), T(0), T(0)}, qa_acc[3] = {T(0), T(0), T(0)};
-    T qa_u0[3] = {T(0), T(0), T(0)}, qa_u1[3] = {T(0), T(0), T(0)};
-    T qa_v0[3] = {T(0), T(0), T(0)}, qa_v1[3] = {T(0), T(0), T(0)};
-    T qa_w1[3] = {T(0), T(0), T(0)};
+    // own-cell queues from E1 (plane p) to E2 (plane p, NQ-1 iterations later): after E1 of
+    // iteration t they hold planes t+3-NQ .. t+2 in entries 0 .. NQ-1
+    T qa_phi[NQ] = {}, qa_acc[NQ] = {}, qa_u0[NQ] = {}, qa_u1[NQ] = {}, qa_v0[NQ] = {};
+    T qa_v1[NQ] = {}, qa_w1[NQ] = {};
 
     const int tbeg = k0 - 6;
-    fetch_in(tbeg + 2);
-    commit_in(0);
-    fetch_in(tbeg + 3);
-    commit_in(1);
-    fetch_in(tbeg + 4);
-    if (STAGE) fetch_vel(tbeg + 2);
-    if (SWEEP_B) fetch_b(tbeg + 2);
+    T eacc_pre = T(0);  // LAG, sweep B: acc at the own cell of the next E1 plane
+    if constexpr (LAG) {
+        // planes p = tbeg+2 .. tbeg+4 committed to slots (p - tbeg) mod 4, plane tbeg+5 in
+        // flight; the staged planes of tbeg+2 committed to slot 0, tbeg+3 in flight
+        fetch_in(tbeg + 2);
+        commit_in(2);
+        fetch_in(tbeg + 3);
+        commit_in(3);
+        fetch_in(tbeg + 4);
+        commit_in(0);
+        if (STAGE) {
+            fetch_vel(tbeg + 2);
+            commit_vel(0);
+        }
+        if (SWEEP_B) {
+            fetch_b(tbeg + 2);
+            commit_b(0);
+            eacc_pre = facc.load(wrapz(tbeg + 2, nz), e_col[0]);
+        }
+        fetch_in(tbeg + 5);
+        if (STAGE) fetch_vel(tbeg + 3);
+        if (SWEEP_B) fetch_b(tbeg + 3);
+        __syncthreads();
+    } else {
+        fetch_in(tbeg + 2);
+        commit_in(0);
+        fetch_in(tbeg + 3);
+        commit_in(1);
+        fetch_in(tbeg + 4);
+        if (STAGE) fetch_vel(tbeg + 2);
+        if (SWEEP_B) fetch_b(tbeg + 2);
+    }
 
-    // One iteration of the march; R = (t - tbeg) mod 6 fixes every ring slot at compile time,
-    // WITH_E2 whether the second evaluation runs.
+    // One iteration of the march; R = (t - tbeg) mod 6 (LAG: mod 4) fixes every ring slot at
+    // compile time, WITH_E2 whether the second evaluation runs.
     auto iteration = [&](auto RC, auto E2C, int t) {
         constexpr int R = decltype(RC)::value;
         constexpr bool WITH_E2 = decltype(E2C)::value != 0;
-        constexpr int sa = R % 3, sb = (R + 1) % 3, sc = (R + 2) % 3;  // planes t+2, t+3, t+4
+        // slots of the stage input planes t+2, t+3, t+4 (and of ya at plane t+2)
+        constexpr int sa = LAG ? (R + 2) % 4 : R % 3;
+        constexpr int sb = LAG ? (R + 3) % 4 : (R + 1) % 3;
+        constexpr int sc = LAG ? R % 4 : (R + 2) % 3;
         constexpr int q1new = (R + 1) & 1, q1old = R & 1;
-        commit_in(sc);
-        if (STAGE) commit_vel();  // velocities of plane t+2 (W: t+3)
-        if (SWEEP_B) commit_b();
-        fetch_in(t + 5);
-        if (STAGE) fetch_vel(t + 3);
-        if (SWEEP_B) fetch_b(t + 3);
+        constexpr int vs = LAG ? R % 2 : 0;  // slot of the staged planes of t+2
+        if constexpr (LAG) {
+            // the planes of the next iteration into the slots this one does not read
+            commit_in((R + 1) % 4);  // plane t+5
+            if (STAGE) commit_vel((R + 1) % 2);  // velocities of plane t+3 (W: t+4)
+            if (SWEEP_B) commit_b((R + 1) % 2);
+            fetch_in(t + 6);
+            if (STAGE) fetch_vel(t + 4);
+            if (SWEEP_B) fetch_b(t + 4);
+        } else {
+            commit_in(sc);
+            if (STAGE) commit_vel(0);  // velocities of plane t+2 (W: t+3)
+            if (SWEEP_B) commit_b(0);
+            fetch_in(t + 5);
+            if (STAGE) fetch_vel(t + 3);
+            if (SWEEP_B) fetch_b(t + 3);
+        }
         // E1 operands from global memory (plane p = t+2), issued before the barrier
         const int pw = wrapz(t + 2, nz), pw1 = wrapz(t + 3, nz);
         T eu0[2], eu1[2], ev0[2], ev1[2], ew1[2], eacc = T(0);
@@ -359,18 +414,28 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 ew1[s] = fW.load(pw1, e_col[s]);
             }
         }
-        if (SWEEP_B) eacc = facc.load(pw, e_col[0]);
-        __syncthreads();  // input plane t+4, phi (and staged velocities) of plane t+2 visible
+        if (SWEEP_B) {
+            if constexpr (LAG) {  // loaded one iteration ahead
+                eacc = eacc_pre;
+                eacc_pre = facc.load(pw1, e_col[0]);
+            } else {
+                eacc = facc.load(pw, e_col[0]);
+            }
+        }
+        // input plane t+4, phi (and staged velocities) of plane t+2 visible (LAG: since the
+        // barrier that ended the previous iteration)
+        if constexpr (!LAG) __syncthreads();
         if (STAGE) {
+            const T* SV = s_vel + vs * VSS;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 // the slot's IN offset (e_lx + 2) + (e_ly + 2) INW, two rows up: same pitch
                 const int vo = (e_lx[s] + 2) + (e_ly[s] + 2) * INW - 2 * INW;
-                eu0[s] = s_vel[VSU + vo];
-                eu1[s] = s_vel[VSU + vo + 1];
-                ev0[s] = s_vel[VSV + vo];
-                ev1[s] = s_vel[VSV + vo + INW];
-                ew1[s] = s_vel[VSW + vo];
+                eu0[s] = SV[VSU + vo];
+                eu1[s] = SV[VSU + vo + 1];
+                ev0[s] = SV[VSV + vo];
+                ev1[s] = SV[VSV + vo + INW];
+                ew1[s] = SV[VSW + vo];
             }
         }
 
@@ -438,7 +503,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                                   face_diff(pc, pxp), face_diff(pym, pc), face_diff(pc, pyp), e_dz[s],
                                   dzp, qx[0], qx[2], qy[0], qy[2 * MW], e_qzm[s], qzn[s], eu0[s],
                                   eu1[s], ev0[s], ev1[s], e_w0[s], ew1[s], a.nhs1, ge);
-            const T base = SWEEP_B ? s_pb[(WIDE ? lx + 2 : lx) + ly * PBW] : pc;
+            const T base = SWEEP_B ? s_pb[vs * PBS + (WIDE ? lx + 2 : lx) + ly * PBW] : pc;
             const T ym = fma(a.c_mid, f1, base);
             YM[lx + ly * MW] = ym;
             if (s == 0) {
@@ -448,7 +513,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 }
                 // own cell: hand plane p's values to E2 (used two iterations later)
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < NQ - 1; ++q) {
                     qa_phi[q] = qa_phi[q + 1];
                     qa_acc[q] = qa_acc[q + 1];
                     qa_u0[q] = qa_u0[q + 1];
@@ -457,13 +522,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                     qa_v1[q] = qa_v1[q + 1];
                     qa_w1[q] = qa_w1[q + 1];
                 }
-                qa_phi[2] = pc;
-                qa_acc[2] = SWEEP_B ? fma(a.c_acc1, f1, eacc) : fma(a.c_acc1, f1, pc);
-                qa_u0[2] = eu0[0];
-                qa_u1[2] = eu1[0];
-                qa_v0[2] = ev0[0];
-                qa_v1[2] = ev1[0];
-                qa_w1[2] = ew1[0];
+                qa_phi[NQ - 1] = pc;
+                qa_acc[NQ - 1] = SWEEP_B ? fma(a.c_acc1, f1, eacc) : fma(a.c_acc1, f1, pc);
+                qa_u0[NQ - 1] = eu0[0];
+                qa_u1[NQ - 1] = eu1[0];
+                qa_v0[NQ - 1] = ev0[0];
+                qa_v1[NQ - 1] = ev1[0];
+                qa_w1[NQ - 1] = ew1[0];
             }
             e_sz[s] = szp;
             e_dz[s] = dzp;
@@ -483,15 +548,19 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 YM[e_lx[s] + e_ly[s] * MW] = YM[(mx - (i0 - 2)) + (my - (j0 - 2)) * MW];
             }
         }
-        __syncthreads();  // ya at plane t+2 visible
+        if constexpr (!LAG) __syncthreads();  // ya at plane t+2 visible
 
         if constexpr (WITH_E2) {
-            // E2: q2 at plane t+1, outputs of plane t
-            constexpr int m0 = (R + 1) % 3, m1 = (R + 2) % 3;  // planes t, t+1
+            // E2: q2 at plane to+1, outputs of plane to (to = t; LAG: to = t-1, so that E2 reads
+            // only the planes of earlier iterations)
+            const int to = LAG ? t - 1 : t;
+            constexpr int m0 = LAG ? (R + 3) % 4 : (R + 1) % 3;  // plane to
+            constexpr int m1 = LAG ? R % 4 : (R + 2) % 3;        // plane to+1
+            constexpr int m2 = LAG ? (R + 1) % 4 : R % 3;        // plane to+2
             const T* M0 = s_mid + m0 * MS;
             const T* M1 = s_mid + m1 * MS;
-            const T* M2 = YM;  // plane t+2
-            constexpr int q2new = (R + 1) & 1, q2old = R & 1;
+            const T* M2 = s_mid + m2 * MS;
+            constexpr int q2new = LAG ? R & 1 : (R + 1) & 1, q2old = LAG ? (R + 1) & 1 : R & 1;
             const int om = (tx + 2) + (ty + 2) * MW;
             const T pc1 = M1[om];
             const T gx = grad1(M1[om + 1], M1[om - 1], inv_2dx);
@@ -513,7 +582,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             }
             const T pc = M0[om];
             const T szp = face_sum(pc, pc1), dzp = face_diff(pc, pc1);
-            if (t >= k0 && t < k1 && active) {
+            if (to >= k0 && to < k1 && active) {
                 const T* qx = s_q2x + q2old * Q2XS + tx + ty * Q2XW;
                 const T* qy = s_q2y + q2old * Q2YS + tx + ty * TX;
                 const T pxm = M0[om - 1], pxp = M0[om + 1], pym = M0[om - MW], pyp = M0[om + MW];
@@ -524,10 +593,10 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                                       qa_u0[0], qa_u1[0], qa_v0[0], qa_v1[0], w2, qa_w1[0], a.nhs2,
                                       ge);
                 const unsigned c = e_col[0];  // own cell (i0+tx, j0+ty): no wrap when active
-                if (!SWEEP_B) foy.store(t, c, fma(a.c_y2, f2, qa_phi[0]));
+                if (!SWEEP_B) foy.store(to, c, fma(a.c_y2, f2, qa_phi[0]));
                 if constexpr (XOUT)
-                    if (a.out_phi) fophi.store(t, c, qa_phi[0]);
-                if (SWEEP_B || a.out_acc) foacc.store(t, c, fma(a.c_acc2, f2, qa_acc[0]));
+                    if (a.out_phi) fophi.store(to, c, qa_phi[0]);
+                if (SWEEP_B || a.out_acc) foacc.store(to, c, fma(a.c_acc2, f2, qa_acc[0]));
             }
             sz2 = szp;
             dz2 = dzp;
@@ -535,20 +604,38 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             q2z = q2zn;
             w2 = qa_w1[0];
         }
+        if constexpr (LAG) __syncthreads();  // the iteration's LDS writes visible to the next
     };
 
-    iteration(IntC<0>(), IntC<0>(), tbeg);
-    iteration(IntC<1>(), IntC<0>(), tbeg + 1);
-    iteration(IntC<2>(), IntC<0>(), tbeg + 2);
-    iteration(IntC<3>(), IntC<0>(), tbeg + 3);
-    const int tend = k0 - 2 + 6 * ((k1 - k0 + 7) / 6);  // k0-2 .. k1-1, in groups of six
-    for (int t = k0 - 2; t < tend; t += 6) {
-        iteration(IntC<4>(), IntC<1>(), t);
-        iteration(IntC<5>(), IntC<1>(), t + 1);
-        iteration(IntC<0>(), IntC<1>(), t + 2);
-        iteration(IntC<1>(), IntC<1>(), t + 3);
-        iteration(IntC<2>(), IntC<1>(), t + 4);
-        iteration(IntC<3>(), IntC<1>(), t + 5);
+    if constexpr (LAG) {
+        // five iterations of E1 alone (ya from plane k0-2 on), then E2 from t = k0-1 (q2 at
+        // k0-1) to t = k1 (outputs of plane k1-1)
+        iteration(IntC<0>(), IntC<0>(), tbeg);
+        iteration(IntC<1>(), IntC<0>(), tbeg + 1);
+        iteration(IntC<2>(), IntC<0>(), tbeg + 2);
+        iteration(IntC<3>(), IntC<0>(), tbeg + 3);
+        iteration(IntC<0>(), IntC<0>(), tbeg + 4);
+        const int tend = k0 - 1 + 4 * ((k1 - k0 + 5) / 4);  // k0-1 .. k1, in groups of four
+        for (int t = k0 - 1; t < tend; t += 4) {
+            iteration(IntC<1>(), IntC<1>(), t);
+            iteration(IntC<2>(), IntC<1>(), t + 1);
+            iteration(IntC<3>(), IntC<1>(), t + 2);
+            iteration(IntC<0>(), IntC<1>(), t + 3);
+        }
+    } else {
+        iteration(IntC<0>(), IntC<0>(), tbeg);
+        iteration(IntC<1>(), IntC<0>(), tbeg + 1);
+        iteration(IntC<2>(), IntC<0>(), tbeg + 2);
+        iteration(IntC<3>(), IntC<0>(), tbeg + 3);
+        const int tend = k0 - 2 + 6 * ((k1 - k0 + 7) / 6);  // k0-2 .. k1-1, in groups of six
+        for (int t = k0 - 2; t < tend; t += 6) {
+            iteration(IntC<4>(), IntC<1>(), t);
+            iteration(IntC<5>(), IntC<1>(), t + 1);
+            iteration(IntC<0>(), IntC<1>(), t + 2);
+            iteration(IntC<1>(), IntC<1>(), t + 3);
+            iteration(IntC<2>(), IntC<1>(), t + 4);
+            iteration(IntC<3>(), IntC<1>(), t + 5);
+        }
     }
 }
 

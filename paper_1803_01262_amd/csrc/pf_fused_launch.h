@@ -21,7 +21,8 @@ fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y, int kz)
     b /= tiles_x;
     const int tj = b % tiles_y;
     const int k0 = (b / tiles_y) * kz;
-    fused_body<T, TX, TY, SWEEP_B, BIG, WIDE, XOUT, WALLS>(a, ti, tj, k0, min(k0 + kz, a.nz));
+    fused_body<T, TX, TY, SWEEP_B, BIG, WIDE, XOUT, WALLS, fused_lag<T, TX, TY>()>(a, ti, tj, k0,
+                                                                            min(k0 + kz, a.nz));
 }
 
 template <typename T, int TX, int TY, bool BIG, bool WIDE, bool WALLS = false>
