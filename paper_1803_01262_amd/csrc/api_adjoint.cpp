@@ -183,10 +183,11 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
                  s4 = time_factor(p, t + dt);
     const int v = s->variant;
     // recompute the stage inputs exactly as the forward step stores them (every variant rounds
-    // alike). A fused FP32 variant produces y2 and y3 in one sweep (sweep A with its y_mid output
-    // and no accumulator output); in FP64 three per-stage launches on 64x8 tiles are faster at
-    // 128^3-320^3 (at 128^3 0.244 against 0.261 ms per adjoint step).
-    const bool fused_rc = variant_is_fused(p.dtype, v) && p.dtype == PF_F32 && wall_mask(p) == 0;
+    // alike). A fused variant produces y2 and y3 in one sweep (sweep A with its y_mid output and
+    // no accumulator output; FP64 adjoint step against three per-stage launches on 64x8 tiles:
+    // 128^3 0.259 / 0.259 ms, 256^3 1.90 / 1.95, 512^3 14.98 / 15.38); on walled grids three
+    // per-stage launches.
+    const bool fused_rc = variant_is_fused(p.dtype, v) && wall_mask(p) == 0;
     const int vs = variant_is_fused(p.dtype, v) && !fused_rc ? stage_variant_index(p.dtype, "tiled_64x8") : v;
     if (fused_rc) {
         FusedArgs<T> a = make_fused<T>(p, false, t, phi, y4, U, V, W, y3);

@@ -299,10 +299,11 @@ template hipError_t launch_stage_nu<float>(const StageArgs<float>&, hipStream_t)
 template hipError_t launch_stage_nu<double>(const StageArgs<double>&, hipStream_t);
 
 // Grids from this many cells up take the fused sweeps by default, smaller ones the per-stage
-// kernels (MI355X, 32^3-256^3: FP32 per-stage leads to 64^3, fused from 96^3; FP64 per-stage leads
-// to 96^3 and ties at 128^3).
-constexpr long long kFusedMinCellsF32 = 80LL * 80 * 80;
-constexpr long long kFusedMinCellsF64 = 128LL * 128 * 128;
+// kernels (MI355X, ms per step, best per-stage / best fused: FP32 80^3 0.036 / 0.044, 96^3
+// 0.041 / 0.045, 112^3 0.058 / 0.057, 128^3 0.066 / 0.058; FP64 128^3 0.094 / 0.099, 160^3
+// 0.152 / 0.155, 192^3 0.325 / 0.272).
+constexpr long long kFusedMinCellsF32 = 104LL * 104 * 104;
+constexpr long long kFusedMinCellsF64 = 176LL * 176 * 176;
 constexpr long long kX64MinCellsF32 = 256LL * 256 * 256;
 
 // Default variant before (or without) autotuning, from MI355X measurements at 32^3-640^3, all with
