@@ -240,7 +240,7 @@ const char *phasefield_variant_name(int32_t dtype, int32_t variant);
  * used by later phasefield_create calls with variant -1; if the environment variable
  * PF_TUNE_CACHE names a file, the cache is also read from and written to it (one line per
  * entry: dtype nx ny nz variant-name). Without a cached choice, create picks a default from
- * the grid size and dtype (fused sweeps from about 104^3 cells in FP32 and 176^3 in FP64,
+ * the grid size and dtype (fused sweeps from about 104^3 cells in FP32 and 128^3 in FP64,
  * per-stage kernels below and on every grid of one plane; both with per-launch chunk
  * lengths). */
 pf_status phasefield_autotune(pf_solver *s, int32_t reps, int32_t *best, double *times_ms,

@@ -301,9 +301,11 @@ template hipError_t launch_stage_nu<double>(const StageArgs<double>&, hipStream_
 // Grids from this many cells up take the fused sweeps by default, smaller ones the per-stage
 // kernels (MI355X, ms per step, best per-stage / best fused: FP32 80^3 0.036 / 0.044, 96^3
 // 0.041 / 0.045, 112^3 0.058 / 0.057, 128^3 0.066 / 0.058; FP64 128^3 0.094 / 0.099, 160^3
-// 0.152 / 0.155, 192^3 0.325 / 0.272).
+// 0.152 / 0.155, 192^3 0.325 / 0.272). FP64 takes the fused sweeps from 128^3 all the same: a
+// per-stage forward variant lends its tile to the adjoint, and at 128^3 the adjoint step on 32x4
+// tiles took 0.284 ms against 0.259 after a fused forward variant (64x8 tiles).
 constexpr long long kFusedMinCellsF32 = 104LL * 104 * 104;
-constexpr long long kFusedMinCellsF64 = 176LL * 176 * 176;
+constexpr long long kFusedMinCellsF64 = 128LL * 128 * 128;
 constexpr long long kX64MinCellsF32 = 256LL * 256 * 256;
 
 // Default variant before (or without) autotuning, from MI355X measurements at 32^3-640^3, all with
@@ -332,13 +334,15 @@ int default_stage_variant(int nx, int ny, int nz, int dtype)
                                       : per_stage_variant(nx, ny, nz, dtype);
 }
 
-// FP32 on 64x4 tiles unless those pad more columns than 32x4; FP64 on 32x4 (as fast or faster at
-// every measured size).
+// FP32 on 64x4 tiles unless those pad more columns than 32x4 (512^3: 3.36 ms per RK4 step against
+// 3.49 on 64x8); FP64 on 32x4 below 176^3 cells (128^3: 0.094 ms, 160^3: 0.152 against 0.162 on
+// 64x8) and on 64x8 from there unless those pad more columns (192^3: 64x8 0.325, 32x4 slower;
+// 512^3: 6.16 against 7.12 ms).
 int per_stage_variant(int nx, int ny, int nz, int dtype)
 {
-    (void)ny;
-    (void)nz;
-    return variant_by_name(dtype, dtype == PF_F32 && prefer_x64(nx) ? "tiled_64x4" : "tiled_32x4");
+    if (dtype == PF_F32) return variant_by_name(dtype, prefer_x64(nx) ? "tiled_64x4" : "tiled_32x4");
+    const long long cells = (long long)nx * ny * nz;
+    return variant_by_name(dtype, cells >= 176LL * 176 * 176 && prefer_x64(nx) ? "tiled_64x8" : "tiled_32x4");
 }
 
 }  // namespace pf

@@ -354,13 +354,13 @@ def test_default_variant_on_one_plane_grids(lib):
     """Grids of one plane take the per-stage (march-free plane) kernel at every size, never a
     fused sweep; 64x8 tiles from 256^2 cells, the per-stage rule's tiles below. Thicker grids
     take the fused sweeps from 104^3 cells (FP32; on 32x16 tiles below 256^3 cells and 64x8 from
-    there) and from 176^3 cells (FP64, 32x16), the per-stage kernels below."""
+    there) and from 128^3 cells (FP64, 32x16), the per-stage kernels below."""
     pf = lib
     cases = [((1024, 1024, 1), "f32", "tiled_64x8"), ((512, 512, 1), "f64", "tiled_64x8"),
              ((64, 64, 1), "f64", "tiled_32x4"), ((96, 4000, 1), "f32", "tiled_32x4"),
              ((1024, 1024, 2), "f32", "fused_32x16"), ((256, 256, 256), "f32", "fused_64x8"),
              ((96, 96, 96), "f32", "tiled_32x4"), ((112, 112, 112), "f32", "fused_32x16"),
-             ((128, 128, 128), "f64", "tiled_32x4"), ((192, 192, 192), "f64", "fused_32x16")]
+             ((120, 120, 120), "f64", "tiled_32x4"), ((128, 128, 128), "f64", "fused_32x16")]
     for n, dtype, want in cases:
         s = pf.Solver(n, 1.0 / n[0], 1.0 / n[0], 1.0, 0.1 / n[0], dtype=dtype)
         assert s.variant_name == want, (n, dtype, s.variant_name)
