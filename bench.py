@@ -286,8 +286,9 @@ def rollout_timing(pf, fx, dtype, n=128):
     """The full differentiable rollout of the adjoint workload: 400 steps with a checkpoint
     every 20, loss 0.5 ||phi_T - target||^2, gradients for phi_0 and the 8^3 x 3 velocity
     coefficients. Times the forward (velocity synthesis, steps, checkpoint copies) and the
-    backward (segment re-forward, 400 adjoint steps, projection onto the coefficients), on the
-    current stream."""
+    backward (segment re-runs, 400 adjoint steps, projection onto the coefficients), on the
+    current stream: the default backward, whose re-runs keep the stage inputs for the adjoint
+    steps, and the one whose adjoint steps recompute them."""
     import torch
     c = fx.adjoint_case(n)
     tdt = torch.float32 if dtype == "f32" else torch.float64
@@ -300,26 +301,34 @@ def rollout_timing(pf, fx, dtype, n=128):
     phi0 = torch.tensor(c.phi0, dtype=tdt, device="cuda").requires_grad_(True)
     cf = coeffs.clone().requires_grad_(True)
     target = torch.tensor(c.extra["target"], dtype=tdt, device="cuda")
-    # warm-up: one short rollout (first launches of every kernel, graph capture)
-    w0 = pf.Rollout.apply(phi0, cf, s, phases, 20, 20, 0.0)
-    (0.5 * ((w0 - target) ** 2).sum()).backward()
-    phi0.grad = None
-    cf.grad = None
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    torch.cuda.synchronize()
-    ev[0].record()
-    phiT = pf.Rollout.apply(phi0, cf, s, phases, c.nsteps, 20, 0.0)
-    loss = 0.5 * ((phiT - target) ** 2).sum()
-    ev[1].record()
-    loss.backward()
-    ev[2].record()
-    torch.cuda.synchronize()
-    fwd, bwd = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+
+    def run(nsteps, cache):
+        phi0.grad = None
+        cf.grad = None
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        phiT = pf.Rollout.apply(phi0, cf, s, phases, nsteps, 20, 0.0, cache)
+        loss = 0.5 * ((phiT - target) ** 2).sum()
+        ev[1].record()
+        loss.backward()
+        ev[2].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+
+    # warm-up: one short rollout each way (first launches of every kernel, graph capture)
+    run(20, True)
+    run(20, False)
+    fwd_r, bwd_r = run(c.nsteps, False)
+    fwd, bwd = run(c.nsteps, True)
+    out = {"grid": n, "dtype": dtype, "steps": c.nsteps, "checkpoint_every": 20,
+           "forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
+           "backward_over_forward": round(bwd / fwd, 3),
+           "backward_ms_recomputing_stages": round(bwd_r, 2),
+           "backward_over_forward_recomputing_stages": round(bwd_r / fwd_r, 3),
+           "grad_finite": bool(torch.isfinite(phi0.grad).all() and torch.isfinite(cf.grad).all())}
     s.close()
-    return {"grid": n, "dtype": dtype, "steps": c.nsteps, "checkpoint_every": 20,
-            "forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
-            "backward_over_forward": round(bwd / fwd, 3),
-            "grad_finite": bool(torch.isfinite(phi0.grad).all() and torch.isfinite(cf.grad).all())}
+    return out
 
 
 def batch_vs_loop(pf, fx, st, count=96, nsteps=300):

@@ -22,12 +22,14 @@ from ._capi import (EXPORTED, PF_BC_PERIODIC, PF_BC_WALL, PF_ERR_DEVICE, PF_ERR_
                     phasefield_check_params, phasefield_create,
                     phasefield_default_params, phasefield_destroy, phasefield_last_error,
                     phasefield_reduce, phasefield_set_adjoint_form, phasefield_set_spacing,
-                    phasefield_solver_variant, phasefield_step,
+                    phasefield_solver_variant, phasefield_step, phasefield_step_stages,
+                    phasefield_adjoint_step_stages,
                     phasefield_step_noalloc, phasefield_noalloc_scratch_bytes, phasefield_device_copy,
                     phasefield_variant_count, phasefield_variant_name,
                     phasefield_velocity_coeffs_grad, phasefield_velocity_from_coeffs)
 
 TORCH_DTYPE = {PF_F32: torch.float32, PF_F64: torch.float64}
+STAGE_COUNT = {PF_RK4: 3, PF_RK3: 2, PF_RK2: 1, PF_EULER: 0}  # stage inputs kept for the adjoint
 
 
 class Solver:
@@ -63,6 +65,27 @@ class Solver:
         """lam <- dL/dphi_n given lam = dL/dphi_{n+1}; gu/gv/gw accumulate dL/du0 (in place)."""
         phasefield_adjoint_step(self.handle, self.params, phi_n, u, v, w, t_n, lam, gu, gv, gw,
                                 stream)
+        return lam
+
+    @property
+    def stage_count(self) -> int:
+        """Stage inputs one step keeps for its adjoint (RK4 3, RK3 2, RK2 1, Euler 0)."""
+        return STAGE_COUNT[self.params.scheme]
+
+    def step_stages(self, phi, u, v, w, t, *stages, stream=None):
+        """One step from time t (phi in place) that also writes its stage inputs into the
+        stage_count tensors given (y2, y3, y4 as the scheme uses them)."""
+        ys = list(stages) + [None] * (3 - len(stages))
+        phasefield_step_stages(self.handle, self.params, phi, u, v, w, t, *ys[:3], stream)
+        return phi
+
+    def adjoint_step_stages(self, phi_n, stages, u, v, w, t_n, lam, gu=None, gv=None, gw=None,
+                            stream=None):
+        """adjoint_step with the stage inputs kept by step_stages at (phi_n, t_n): no
+        recompute, the same results bit for bit."""
+        ys = list(stages) + [None] * (3 - len(stages))
+        phasefield_adjoint_step_stages(self.handle, self.params, phi_n, *ys[:3], u, v, w, t_n,
+                                       lam, gu, gv, gw, stream)
         return lam
 
     def set_spacing(self, hx=None, hy=None, hz=None, eps_mode: int = 0) -> None:
@@ -169,17 +192,21 @@ def velocity_coeffs_grad(params: Params, phases, gu, gv, gw, stream=None):
 class Rollout(torch.autograd.Function):
     """phi_T = (nsteps steps of the solver)(phi_0) in the velocity synthesised from coeffs.
 
-    Backward: discrete adjoint with checkpoints every ``ckpt`` steps. Each segment is
-    recomputed from its checkpoint (states held on the GPU), then swept backwards with
-    phasefield_adjoint_step; the accumulated face-velocity gradient is projected onto the mode
-    coefficients once. Returns gradients for phi_0 and coeffs.
+    Backward: discrete adjoint with checkpoints every ``ckpt`` steps. Each segment is re-run
+    from its checkpoint (states held on the GPU), then swept backwards step by step; the
+    accumulated face-velocity gradient is projected onto the mode coefficients once. With
+    ``cache_stages`` (default) the re-run keeps every step's stage inputs as well
+    (phasefield_step_stages; (1 + stage_count) fields per step of a segment) and the sweep takes
+    them (phasefield_adjoint_step_stages) instead of recomputing them; without it, each adjoint
+    step recomputes its stage inputs (phasefield_adjoint_step; one field per step). Both give the
+    same gradients bit for bit. Returns gradients for phi_0 and coeffs.
 
-    Usage: Rollout.apply(phi0, coeffs, solver, phases, nsteps, ckpt, t0)
+    Usage: Rollout.apply(phi0, coeffs, solver, phases, nsteps, ckpt, t0, cache_stages)
     """
 
     @staticmethod
     def forward(ctx, phi0, coeffs, solver: Solver, phases, nsteps: int, ckpt: int = 20,
-                t0: float = 0.0):
+                t0: float = 0.0, cache_stages: bool = True):
         p = solver.params
         u, v, w = velocity_from_coeffs(p, phases, coeffs.detach().to(torch.float64))
         phi = phi0.detach().clone().contiguous()
@@ -192,6 +219,7 @@ class Rollout(torch.autograd.Function):
             _advance(solver, phi, u, v, w, t0, n, m, single)
             n += m
         ctx.solver, ctx.phases, ctx.nsteps, ctx.ckpt, ctx.t0 = solver, phases, nsteps, ckpt, t0
+        ctx.cache_stages = bool(cache_stages)
         ctx.ckpts = ckpts
         ctx.vel = (u, v, w)
         return phi
@@ -206,9 +234,22 @@ class Rollout(torch.autograd.Function):
         lam = grad_out.detach().to(solver.dtype).contiguous().clone()
         gu, gv, gw = (torch.zeros_like(u) for _ in range(3))
         nseg = len(ctx.ckpts)
+        ns = solver.stage_count
         for s in reversed(range(nseg)):
             n0 = s * ckpt
             m = min(ckpt, nsteps - n0)
+            if ctx.cache_stages:
+                phi = ctx.ckpts[s].clone()
+                states, stages = [], []
+                for j in range(m):
+                    states.append(phi.clone())
+                    ys = [torch.empty_like(phi) for _ in range(ns)]
+                    solver.step_stages(phi, u, v, w, t0 + (n0 + j) * dt, *ys)
+                    stages.append(ys)
+                for j in reversed(range(m)):
+                    solver.adjoint_step_stages(states[j], stages[j], u, v, w, t0 + (n0 + j) * dt,
+                                               lam, gu, gv, gw)
+                continue
             states = [ctx.ckpts[s]]
             phi = ctx.ckpts[s].clone()
             for j in range(m - 1):
@@ -218,7 +259,7 @@ class Rollout(torch.autograd.Function):
                 solver.adjoint_step(states[j], u, v, w, t0 + (n0 + j) * dt, lam, gu, gv, gw)
         cg = velocity_coeffs_grad(p, ctx.phases, gu, gv, gw)
         ctx.ckpts = None
-        return lam, cg, None, None, None, None, None
+        return lam, cg, None, None, None, None, None, None
 
 
 def _advance(solver, phi, u, v, w, t0, n0, m, single):

@@ -76,6 +76,9 @@ def _load():
         "phasefield_destroy": (i32, [vp]),
         "phasefield_step": (i32, [vp, vp, vp, vp, vp, d, i32, vp]),
         "phasefield_adjoint_step": (i32, [vp, vp, vp, vp, vp, d, vp, vp, vp, vp, vp]),
+        "phasefield_step_stages": (i32, [vp, vp, vp, vp, vp, d, vp, vp, vp, vp]),
+        "phasefield_adjoint_step_stages": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, d, vp, vp, vp,
+                                                 vp, vp]),
         "phasefield_reduce": (i32, [vp, vp, P(d), vp]),
         "phasefield_velocity_from_coeffs": (i32, [P(Params), i32, vp, vp, vp, vp, vp, vp]),
         "phasefield_velocity_coeffs_grad": (i32, [P(Params), i32, vp, vp, vp, vp, vp, vp]),
@@ -107,6 +110,7 @@ lib = _load()
 
 EXPORTED = ("phasefield_default_params", "phasefield_check_params", "phasefield_create",
             "phasefield_destroy", "phasefield_step", "phasefield_adjoint_step",
+            "phasefield_step_stages", "phasefield_adjoint_step_stages",
             "phasefield_reduce", "phasefield_velocity_from_coeffs",
             "phasefield_velocity_coeffs_grad", "phasefield_variant_count",
             "phasefield_variant_name", "phasefield_autotune", "phasefield_solver_variant",
@@ -225,6 +229,26 @@ def phasefield_adjoint_step(h, p: Params, phi_n, u, v, w, t_n, lam, gu=None, gv=
         _ptr(w, p.dtype, n, "w"), float(t_n), _ptr(lam, p.dtype, n, "lam"),
         _ptr(gu, p.dtype, n, "gu"), _ptr(gv, p.dtype, n, "gv"), _ptr(gw, p.dtype, n, "gw"),
         _stream(stream)))
+
+
+def phasefield_step_stages(h, p: Params, phi, u, v, w, t, y2=None, y3=None, y4=None,
+                           stream=None) -> None:
+    n = cells(p)
+    _check(lib.phasefield_step_stages(
+        h, _ptr(phi, p.dtype, n, "phi"), _ptr(u, p.dtype, n, "u"), _ptr(v, p.dtype, n, "v"),
+        _ptr(w, p.dtype, n, "w"), float(t), _ptr(y2, p.dtype, n, "y2"),
+        _ptr(y3, p.dtype, n, "y3"), _ptr(y4, p.dtype, n, "y4"), _stream(stream)))
+
+
+def phasefield_adjoint_step_stages(h, p: Params, phi_n, y2, y3, y4, u, v, w, t_n, lam, gu=None,
+                                   gv=None, gw=None, stream=None) -> None:
+    n = cells(p)
+    _check(lib.phasefield_adjoint_step_stages(
+        h, _ptr(phi_n, p.dtype, n, "phi_n"), _ptr(y2, p.dtype, n, "y2"),
+        _ptr(y3, p.dtype, n, "y3"), _ptr(y4, p.dtype, n, "y4"), _ptr(u, p.dtype, n, "u"),
+        _ptr(v, p.dtype, n, "v"), _ptr(w, p.dtype, n, "w"), float(t_n),
+        _ptr(lam, p.dtype, n, "lam"), _ptr(gu, p.dtype, n, "gu"), _ptr(gv, p.dtype, n, "gv"),
+        _ptr(gw, p.dtype, n, "gw"), _stream(stream)))
 
 
 def phasefield_reduce(h, p: Params, phi, stream=None):

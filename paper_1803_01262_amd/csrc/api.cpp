@@ -743,6 +743,80 @@ extern "C" pf_status phasefield_step(pf_solver* s, void* phi, const void* u, con
                              (const double*)w, t0, nsteps, hs);
 }
 
+// One step of the handle's scheme from time t (phi in place) that also stores the stage inputs
+// the adjoint step reads (scheme_stage_count): the per-stage launches with the stage outputs
+// directed into the caller's buffers; an RK4 step of a fused variant (no walls) gets y2 and y3
+// from one sweep A that stores its middle value, then y4 and phi from two per-stage launches.
+// Every form rounds alike, so phi and the stages are bit-identical to those of phasefield_step
+// and of the adjoint's own recompute.
+template <typename T>
+static hipError_t step_stages_impl(pf_solver* s, T* phi, const T* U, const T* V, const T* W,
+                                   double t, T* y2, T* y3, T* y4, hipStream_t st)
+{
+    const pf_params& p = s->p;
+    const double dt = p.dt;
+    T* acc = (T*)s->acc;
+    const int v = s->variant;
+    if (p.scheme == PF_EULER)
+        return enqueue_step<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, acc, t, st, nullptr);
+    if (p.scheme != PF_RK4)  // RK3 and RK2 keep their stage inputs in ya (y2) and yb (y3)
+        return enqueue_step<T>(p, v, phi, U, V, W, y2, y3 ? y3 : (T*)s->yb, acc, t, st, nullptr);
+    const double sh = time_factor(p, t + 0.5 * dt);
+    hipError_t e;
+    if (variant_is_fused(p.dtype, v) && wall_mask(p) == 0) {
+        FusedArgs<T> a = make_fused<T>(p, false, t, phi, acc, U, V, W, y3);
+        a.out_mid = y2;
+        e = run_fused_sweep<T>(v, a, false, st);
+    } else {
+        e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, phi, phi, y2, acc, 0.5 * dt,
+                                          dt / 6.0, U, V, W), st);
+        if (e == hipSuccess)
+            e = run_stage<T>(v, make_stage<T>(p, sh, y2, phi, acc, y3, acc, 0.5 * dt, dt / 3.0, U, V,
+                                              W), st);
+    }
+    if (e == hipSuccess)
+        e = run_stage<T>(v, make_stage<T>(p, sh, y3, phi, acc, y4, acc, dt, dt / 3.0, U, V, W), st);
+    if (e == hipSuccess)
+        e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t + dt), y4, nullptr, acc, nullptr, phi,
+                                          0.0, dt / 6.0, U, V, W), st);
+    return e;
+}
+
+extern "C" pf_status phasefield_step_stages(pf_solver* s, void* phi, const void* u, const void* v,
+                                            const void* w, double t, void* y2, void* y3, void* y4,
+                                            void* hip_stream)
+{
+    if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
+    pf_status st;
+    if ((st = check_field_ptr(phi, "phi")) != PF_OK) return st;
+    if ((st = check_field_ptr(u, "u")) != PF_OK) return st;
+    if ((st = check_field_ptr(v, "v")) != PF_OK) return st;
+    if ((st = check_field_ptr(w, "w")) != PF_OK) return st;
+    if (!std::isfinite(t)) return fail(PF_ERR_INVALID, "t is not finite");
+    if (s->nu.on())
+        return fail(PF_ERR_UNSUPPORTED, "stage inputs are kept for uniform meshes only (no adjoint)");
+    void* stages[3] = {y2, y3, y4};
+    const int ns = scheme_stage_count(s->p.scheme);
+    for (int k = 0; k < ns; ++k) {
+        if ((st = check_field_ptr(stages[k], k == 0 ? "y2" : k == 1 ? "y3" : "y4")) != PF_OK)
+            return st;
+        if (stages[k] == phi) return fail(PF_ERR_INVALID, "a stage buffer is phi");
+        for (int j = 0; j < k; ++j)
+            if (stages[j] == stages[k]) return fail(PF_ERR_INVALID, "stage buffers coincide");
+    }
+    hipStream_t hs = (hipStream_t)hip_stream;
+    hipError_t e =
+        s->p.dtype == PF_F32
+            ? step_stages_impl<float>(s, (float*)phi, (const float*)u, (const float*)v,
+                                      (const float*)w, t, (float*)(ns > 0 ? y2 : nullptr),
+                                      (float*)(ns > 1 ? y3 : nullptr), (float*)(ns > 2 ? y4 : nullptr), hs)
+            : step_stages_impl<double>(s, (double*)phi, (const double*)u, (const double*)v,
+                                       (const double*)w, t, (double*)(ns > 0 ? y2 : nullptr),
+                                       (double*)(ns > 1 ? y3 : nullptr),
+                                       (double*)(ns > 2 ? y4 : nullptr), hs);
+    return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_step_stages");
+}
+
 extern "C" pf_status phasefield_reduce(pf_solver* s, const void* phi, double out4[4],
                                        void* hip_stream)
 {

@@ -91,10 +91,13 @@ static AdjPairArgs<T> make_pair(const pf_params& p, double svelH, double svelL, 
 //   kap2 = dt/3 lam' + dt/2 ybar3          gU += sum_s (df/dU at y_s)^T kap_s.
 //   kap1 = dt/6 lam' + dt/2 ybar2
 // Buffers: y2, y3, y4 reuse the forward stage buffers; Ka/Kb ping-pong the stage cotangent
-// (it is read with a stencil), L accumulates lam' + sum ybar.
+// (it is read with a stencil), L accumulates lam' + sum ybar. With stages (the caller's copies of
+// the stage inputs, from phasefield_step_stages) nothing is recomputed: y2, y3, y4 are read from
+// there (RK3: y2, y3; RK2: y2).
 template <typename T>
 static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V, const T* W,
-                              double t, T* lam, T* gU, T* gV, T* gW, hipStream_t st)
+                              double t, T* lam, T* gU, T* gV, T* gW, hipStream_t st,
+                              const T* const* stages = nullptr)
 {
     const pf_params& p = s->p;
     for (int b = 0; b < 3; ++b)
@@ -139,16 +142,22 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         //   L += ybar2;  lam_n = L + ybar1
         constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, z2 = -17.0 / 60.0;
         static_assert(g1 + z2 == 0.25, "a31 must equal b1 for the folded kap1");
-        T* y2 = (T*)s->ya;
-        T* y3 = (T*)s->yb;
+        const T* y2 = (T*)s->ya;
+        const T* y3 = (T*)s->yb;
         T* A = (T*)s->acc;  // u1 + dt z2 k1, the base of y3
         const double s1 = time_factor(p, t), s2 = time_factor(p, t + g1 * dt),
                      s3 = time_factor(p, t + (g1 + g2 + z2) * dt);
-        e = run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, phi, y2, A, dt * g1,
-                                                   dt * (g1 + z2), U, V, W), st);
-        if (e == hipSuccess)
-            e = run_stage<T>(s->variant, make_stage<T>(p, s2, y2, A, nullptr, y3, nullptr, dt * g2,
-                                                       0.0, U, V, W), st);
+        if (stages) {
+            y2 = stages[0];
+            y3 = stages[1];
+            e = hipSuccess;
+        } else {
+            e = run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, phi, (T*)y2, A, dt * g1,
+                                                       dt * (g1 + z2), U, V, W), st);
+            if (e == hipSuccess)
+                e = run_stage<T>(s->variant, make_stage<T>(p, s2, y2, A, nullptr, (T*)y3, nullptr,
+                                                           dt * g2, 0.0, U, V, W), st);
+        }
         if (e == hipSuccess)
             e = adj(make_adj<T>(p, s3, y3, lam, 0.75 * dt, lam, L, lam, Ka, 0.0, g2 * dt, gU, gV,
                                 gW, U, V, W), st);
@@ -164,10 +173,11 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         // phi' = phi + dt k2,  k2 = f(y2, t + dt/2),  y2 = phi + dt/2 k1:
         //   kap2 = dt lam';  ybar2 = (df/dy at y2)^T kap2;  kap1 = dt/2 ybar2;
         //   lam_n = lam' + ybar2 + (df/dy at phi)^T kap1
-        T* y2 = (T*)s->ya;
+        const T* y2 = stages ? stages[0] : (T*)s->ya;
         const double s1 = time_factor(p, t), s2 = time_factor(p, t + 0.5 * dt);
-        e = run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt,
-                                                   0.0, U, V, W), st);
+        e = stages ? hipSuccess
+                   : run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, nullptr, (T*)y2, nullptr,
+                                                            0.5 * dt, 0.0, U, V, W), st);
         if (e == hipSuccess)
             e = adj(make_adj<T>(p, s2, y2, lam, dt, lam, L, lam, Ka, 0.0, 0.5 * dt, gU, gV, gW, U,
                                 V, W), st);
@@ -189,7 +199,12 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     // per-stage launches.
     const bool fused_rc = variant_is_fused(p.dtype, v) && wall_mask(p) == 0;
     const int vs = variant_is_fused(p.dtype, v) && !fused_rc ? stage_variant_index(p.dtype, "tiled_64x8") : v;
-    if (fused_rc) {
+    if (stages) {
+        y2 = (T*)stages[0];
+        y3 = (T*)stages[1];
+        y4 = (T*)stages[2];
+        e = hipSuccess;
+    } else if (fused_rc) {
         FusedArgs<T> a = make_fused<T>(p, false, t, phi, y4, U, V, W, y3);
         a.out_mid = y2;
         a.out_acc = nullptr;
@@ -199,7 +214,7 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         if (e == hipSuccess)
             e = run_stage<T>(vs, make_stage<T>(p, s2, y2, phi, nullptr, y3, nullptr, 0.5 * dt, 0.0, U, V, W), st);
     }
-    if (e == hipSuccess)
+    if (e == hipSuccess && !stages)
         e = run_stage<T>(vs, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W), st);
     // reverse stages: one per launch, or two per launch (adjoint_fused.hip, the same
     // arithmetic as the single stages below, bit for bit): (4, 3) writes L = lam' + ybar4 +
@@ -249,9 +264,15 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
 }
 
-extern "C" pf_status phasefield_adjoint_step(pf_solver* s, const void* phi_n, const void* u,
-                                             const void* v, const void* w, double t_n, void* lam,
-                                             void* gu, void* gv, void* gw, void* hip_stream)
+// Stage inputs an RK step keeps for its adjoint: RK4 y2, y3, y4; RK3 y2, y3; RK2 y2; Euler none.
+int pf::scheme_stage_count(int scheme)
+{
+    return scheme == PF_RK4 ? 3 : scheme == PF_RK3 ? 2 : scheme == PF_RK2 ? 1 : 0;
+}
+
+static pf_status adjoint_checks(pf_solver* s, const void* phi_n, const void* u, const void* v,
+                                const void* w, double t_n, const void* lam, const void* gu,
+                                const void* gv, const void* gw)
 {
     if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
     pf_status st;
@@ -260,19 +281,51 @@ extern "C" pf_status phasefield_adjoint_step(pf_solver* s, const void* phi_n, co
     if ((st = check_field_ptr(v, "v")) != PF_OK) return st;
     if ((st = check_field_ptr(w, "w")) != PF_OK) return st;
     if ((st = check_field_ptr(lam, "lam")) != PF_OK) return st;
-    for (const void* g : {(const void*)gu, (const void*)gv, (const void*)gw})
+    for (const void* g : {gu, gv, gw})
         if (g && (((uintptr_t)g) & 15)) return fail(PF_ERR_INVALID, "gradient not 16-byte aligned");
     if (!std::isfinite(t_n)) return fail(PF_ERR_INVALID, "t_n is not finite");
     if (s->nu.on())
         return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint is provided for uniform meshes only");
+    return PF_OK;
+}
+
+static pf_status adjoint_dispatch(pf_solver* s, const void* phi_n, const void* u, const void* v,
+                                  const void* w, double t_n, void* lam, void* gu, void* gv,
+                                  void* gw, void* hip_stream, const void* const* stages)
+{
     hipStream_t hs = (hipStream_t)hip_stream;
     if (s->p.dtype == PF_F32)
         return adjoint_impl<float>(s, (const float*)phi_n, (const float*)u, (const float*)v,
                                    (const float*)w, t_n, (float*)lam, (float*)gu, (float*)gv,
-                                   (float*)gw, hs);
+                                   (float*)gw, hs, (const float* const*)stages);
     return adjoint_impl<double>(s, (const double*)phi_n, (const double*)u, (const double*)v,
                                 (const double*)w, t_n, (double*)lam, (double*)gu, (double*)gv,
-                                (double*)gw, hs);
+                                (double*)gw, hs, (const double* const*)stages);
+}
+
+extern "C" pf_status phasefield_adjoint_step(pf_solver* s, const void* phi_n, const void* u,
+                                             const void* v, const void* w, double t_n, void* lam,
+                                             void* gu, void* gv, void* gw, void* hip_stream)
+{
+    pf_status st = adjoint_checks(s, phi_n, u, v, w, t_n, lam, gu, gv, gw);
+    if (st != PF_OK) return st;
+    return adjoint_dispatch(s, phi_n, u, v, w, t_n, lam, gu, gv, gw, hip_stream, nullptr);
+}
+
+extern "C" pf_status phasefield_adjoint_step_stages(pf_solver* s, const void* phi_n,
+                                                    const void* y2, const void* y3,
+                                                    const void* y4, const void* u, const void* v,
+                                                    const void* w, double t_n, void* lam,
+                                                    void* gu, void* gv, void* gw, void* hip_stream)
+{
+    pf_status st = adjoint_checks(s, phi_n, u, v, w, t_n, lam, gu, gv, gw);
+    if (st != PF_OK) return st;
+    const void* stages[3] = {y2, y3, y4};
+    const int ns = scheme_stage_count(s->p.scheme);
+    for (int k = 0; k < ns; ++k)
+        if ((st = check_field_ptr(stages[k], k == 0 ? "y2" : k == 1 ? "y3" : "y4")) != PF_OK)
+            return st;
+    return adjoint_dispatch(s, phi_n, u, v, w, t_n, lam, gu, gv, gw, hip_stream, stages);
 }
 
 // ------------------------------------------------------------------------------ velocity

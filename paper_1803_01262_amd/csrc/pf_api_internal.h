@@ -47,6 +47,7 @@ pf_status hip_fail(hipError_t e, const char* what);
 pf_status validate_params(const pf_params* p);
 int wall_mask(const pf_params& p);  // bit a set: walls on axis a
 pf_status check_field_ptr(const void* ptr, const char* name);
+int scheme_stage_count(int scheme);  // stage inputs an RK step keeps for its adjoint
 int tuned_variant(int dtype, const int32_t n[3]);
 void release_graph(StepGraph& g);
 double time_factor(const pf_params& p, double t);

@@ -120,6 +120,14 @@ def test_adjoint_form_setter_checks_its_arguments(pf):
     assert "NULL" in pf.phasefield_last_error()
 
 
+def test_stage_entry_points_check_the_handle(pf):
+    assert pf.lib.phasefield_step_stages(None, None, None, None, None, 0.0, None, None, None,
+                                         None) == pf.PF_ERR_INVALID
+    assert pf.lib.phasefield_adjoint_step_stages(None, None, None, None, None, None, None, None,
+                                                 0.0, None, None, None, None,
+                                                 None) == pf.PF_ERR_INVALID
+
+
 def test_batch_shape_and_autotune_check_their_arguments(pf):
     import ctypes
     assert pf.lib.phasefield_batch_set_shape(None, 0) == pf.PF_ERR_INVALID
