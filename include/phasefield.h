@@ -163,21 +163,23 @@ pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);
 
-/* One step of the handle's scheme from time t (phi in place, as phasefield_step with nsteps = 1)
- * that also stores the stage inputs its discrete adjoint reads (the Runge-Kutta stage values of
- * Sec. 2.3: RK4 y2 = phi + dt/2 k1, y3 = phi + dt/2 k2, y4 = phi + dt k3; RK3 the first two of its
- * low-storage stages, y2 and y3; RK2 the midpoint value y2; Euler none). y2, y3, y4: DEVICE
- * arrays of the field's size and storage type, owned by the caller, written completely; those
- * the scheme does not use may be NULL and are not touched; they must not coincide with phi or
- * with each other. phi and the stage values are bit-identical to phasefield_step's and to what
- * phasefield_adjoint_step recomputes. For checkpointed adjoints that keep the stage values of a
- * re-run segment instead of recomputing them (phasefield_adjoint_step_stages). Stream-ordered on
- * hip_stream, no synchronisation, no graph. Errors: PF_ERR_INVALID (null or misaligned phi, u,
- * v, w or a stage buffer the scheme needs, coinciding buffers, non-finite t),
+/* One step of the handle's scheme from time t (as phasefield_step with nsteps = 1) that also
+ * stores the stage inputs its discrete adjoint reads (the Runge-Kutta stage values of Sec. 2.3:
+ * RK4 y2 = phi + dt/2 k1, y3 = phi + dt/2 k2, y4 = phi + dt k3; RK3 the first two of its
+ * low-storage stages, y2 and y3; RK2 the midpoint value y2; Euler none). The new phi goes to
+ * phi_next (DEVICE, the field's size and type); phi_next NULL or equal to phi steps in place,
+ * otherwise phi is left unchanged. y2, y3, y4: DEVICE arrays of the field's size and storage
+ * type, owned by the caller, written completely; those the scheme does not use may be NULL and
+ * are not touched; they must not coincide with phi, phi_next or each other. The new phi and the
+ * stage values are bit-identical to phasefield_step's and to what phasefield_adjoint_step
+ * recomputes. For checkpointed adjoints that keep the stage values of a re-run segment instead
+ * of recomputing them (phasefield_adjoint_step_stages). Stream-ordered on hip_stream, no
+ * synchronisation, no graph. Errors: PF_ERR_INVALID (null or misaligned phi, u, v, w or a stage
+ * buffer the scheme needs, misaligned phi_next, coinciding buffers, non-finite t),
  * PF_ERR_UNSUPPORTED (a handle with a non-uniform mesh), PF_ERR_DEVICE. */
-pf_status phasefield_step_stages(pf_solver *s, void *phi, const void *u, const void *v,
-                                 const void *w, double t, void *y2, void *y3, void *y4,
-                                 void *hip_stream);
+pf_status phasefield_step_stages(pf_solver *s, void *phi, void *phi_next, const void *u,
+                                 const void *v, const void *w, double t, void *y2, void *y3,
+                                 void *y4, void *hip_stream);
 
 /* phasefield_adjoint_step with the stage inputs supplied: y2, y3, y4 (DEVICE, read only; those
  * the scheme does not use may be NULL) as phasefield_step_stages stored them for the same phi_n,

@@ -72,12 +72,14 @@ class Solver:
         """Stage inputs one step keeps for its adjoint (RK4 3, RK3 2, RK2 1, Euler 0)."""
         return STAGE_COUNT[self.params.scheme]
 
-    def step_stages(self, phi, u, v, w, t, *stages, stream=None):
-        """One step from time t (phi in place) that also writes its stage inputs into the
-        stage_count tensors given (y2, y3, y4 as the scheme uses them)."""
+    def step_stages(self, phi, u, v, w, t, *stages, phi_next=None, stream=None):
+        """One step from time t that also writes its stage inputs into the stage_count tensors
+        given (y2, y3, y4 as the scheme uses them); the new phi into phi_next (None: phi in
+        place). Returns the new phi."""
         ys = list(stages) + [None] * (3 - len(stages))
-        phasefield_step_stages(self.handle, self.params, phi, u, v, w, t, *ys[:3], stream)
-        return phi
+        phasefield_step_stages(self.handle, self.params, phi, u, v, w, t, *ys[:3], stream,
+                               phi_next)
+        return phi if phi_next is None else phi_next
 
     def adjoint_step_stages(self, phi_n, stages, u, v, w, t_n, lam, gu=None, gv=None, gw=None,
                             stream=None):
@@ -235,28 +237,58 @@ class Rollout(torch.autograd.Function):
         gu, gv, gw = (torch.zeros_like(u) for _ in range(3))
         nseg = len(ctx.ckpts)
         ns = solver.stage_count
-        for s in reversed(range(nseg)):
-            n0 = s * ckpt
-            m = min(ckpt, nsteps - n0)
-            if ctx.cache_stages:
-                phi = ctx.ckpts[s].clone()
+        if ctx.cache_stages:
+            main = torch.cuda.current_stream()
+            side = torch.cuda.Stream()
+
+            def rerun(si, st):
+                """Segment si re-run on stream st, keeping phi and the stage inputs of every
+                step (out of place: the checkpoint stays intact)."""
+                n0, m = si * ckpt, min(ckpt, nsteps - si * ckpt)
                 states, stages = [], []
-                for j in range(m):
-                    states.append(phi.clone())
-                    ys = [torch.empty_like(phi) for _ in range(ns)]
-                    solver.step_stages(phi, u, v, w, t0 + (n0 + j) * dt, *ys)
-                    stages.append(ys)
-                for j in reversed(range(m)):
+                with torch.cuda.stream(st):
+                    cur = ctx.ckpts[si]
+                    for j in range(m):
+                        states.append(cur)
+                        ys = [torch.empty_like(cur) for _ in range(ns)]
+                        nxt = torch.empty_like(cur)
+                        solver.step_stages(cur, u, v, w, t0 + (n0 + j) * dt, *ys, phi_next=nxt,
+                                           stream=st)
+                        stages.append(ys)
+                        cur = nxt
+                    done = torch.cuda.Event()
+                    done.record(st)
+                if st is not main:  # consumed on the main stream
+                    for t in states[1:] + [y for ys in stages for y in ys]:
+                        t.record_stream(main)
+                return states, stages, done
+
+            # the last segment's re-run on the main stream; each earlier one on the side stream,
+            # after the previous re-run (both use the handle's accumulator) and beside the
+            # reverse sweep of the segment after it (which uses the adjoint buffers only)
+            pending = rerun(nseg - 1, main)
+            for si in reversed(range(nseg)):
+                states, stages, done = pending
+                if si > 0:
+                    side.wait_event(done)
+                    pending = rerun(si - 1, side)
+                main.wait_event(done)
+                n0 = si * ckpt
+                for j in reversed(range(len(states))):
                     solver.adjoint_step_stages(states[j], stages[j], u, v, w, t0 + (n0 + j) * dt,
-                                               lam, gu, gv, gw)
-                continue
-            states = [ctx.ckpts[s]]
-            phi = ctx.ckpts[s].clone()
-            for j in range(m - 1):
-                _advance(solver, phi, u, v, w, t0, n0 + j, 1, single)
-                states.append(phi.clone())
-            for j in reversed(range(m)):
-                solver.adjoint_step(states[j], u, v, w, t0 + (n0 + j) * dt, lam, gu, gv, gw)
+                                               lam, gu, gv, gw, stream=main)
+                del states, stages
+        else:
+            for s in reversed(range(nseg)):
+                n0 = s * ckpt
+                m = min(ckpt, nsteps - n0)
+                states = [ctx.ckpts[s]]
+                phi = ctx.ckpts[s].clone()
+                for j in range(m - 1):
+                    _advance(solver, phi, u, v, w, t0, n0 + j, 1, single)
+                    states.append(phi.clone())
+                for j in reversed(range(m)):
+                    solver.adjoint_step(states[j], u, v, w, t0 + (n0 + j) * dt, lam, gu, gv, gw)
         cg = velocity_coeffs_grad(p, ctx.phases, gu, gv, gw)
         ctx.ckpts = None
         return lam, cg, None, None, None, None, None, None

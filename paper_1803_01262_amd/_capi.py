@@ -76,7 +76,7 @@ def _load():
         "phasefield_destroy": (i32, [vp]),
         "phasefield_step": (i32, [vp, vp, vp, vp, vp, d, i32, vp]),
         "phasefield_adjoint_step": (i32, [vp, vp, vp, vp, vp, d, vp, vp, vp, vp, vp]),
-        "phasefield_step_stages": (i32, [vp, vp, vp, vp, vp, d, vp, vp, vp, vp]),
+        "phasefield_step_stages": (i32, [vp, vp, vp, vp, vp, vp, d, vp, vp, vp, vp]),
         "phasefield_adjoint_step_stages": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, d, vp, vp, vp,
                                                  vp, vp]),
         "phasefield_reduce": (i32, [vp, vp, P(d), vp]),
@@ -232,12 +232,13 @@ def phasefield_adjoint_step(h, p: Params, phi_n, u, v, w, t_n, lam, gu=None, gv=
 
 
 def phasefield_step_stages(h, p: Params, phi, u, v, w, t, y2=None, y3=None, y4=None,
-                           stream=None) -> None:
+                           stream=None, phi_next=None) -> None:
     n = cells(p)
     _check(lib.phasefield_step_stages(
-        h, _ptr(phi, p.dtype, n, "phi"), _ptr(u, p.dtype, n, "u"), _ptr(v, p.dtype, n, "v"),
-        _ptr(w, p.dtype, n, "w"), float(t), _ptr(y2, p.dtype, n, "y2"),
-        _ptr(y3, p.dtype, n, "y3"), _ptr(y4, p.dtype, n, "y4"), _stream(stream)))
+        h, _ptr(phi, p.dtype, n, "phi"), _ptr(phi_next, p.dtype, n, "phi_next"),
+        _ptr(u, p.dtype, n, "u"), _ptr(v, p.dtype, n, "v"), _ptr(w, p.dtype, n, "w"), float(t),
+        _ptr(y2, p.dtype, n, "y2"), _ptr(y3, p.dtype, n, "y3"), _ptr(y4, p.dtype, n, "y4"),
+        _stream(stream)))
 
 
 def phasefield_adjoint_step_stages(h, p: Params, phi_n, y2, y3, y4, u, v, w, t_n, lam, gu=None,

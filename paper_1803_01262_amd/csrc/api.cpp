@@ -743,27 +743,53 @@ extern "C" pf_status phasefield_step(pf_solver* s, void* phi, const void* u, con
                              (const double*)w, t0, nsteps, hs);
 }
 
-// One step of the handle's scheme from time t (phi in place) that also stores the stage inputs
-// the adjoint step reads (scheme_stage_count): the per-stage launches with the stage outputs
-// directed into the caller's buffers; an RK4 step of a fused variant (no walls) gets y2 and y3
-// from one sweep A that stores its middle value, then y4 and phi from two per-stage launches.
-// Every form rounds alike, so phi and the stages are bit-identical to those of phasefield_step
-// and of the adjoint's own recompute.
+// One step of the handle's scheme from time t that also stores the stage inputs the adjoint step
+// reads (scheme_stage_count), the new phi into phi_next (phi itself: in place): the per-stage
+// launches with the stage outputs directed into the caller's buffers; an RK4 step of a fused
+// variant (no walls; FP64 from 176^3 cells, where the fused sweep overtakes the per-stage
+// launches) gets y2 and y3 from one sweep A that stores its middle value, then y4 and the new phi
+// from two per-stage launches. Every form rounds alike, so the new phi and the stages are
+// bit-identical to those of phasefield_step and of the adjoint's own recompute.
 template <typename T>
-static hipError_t step_stages_impl(pf_solver* s, T* phi, const T* U, const T* V, const T* W,
-                                   double t, T* y2, T* y3, T* y4, hipStream_t st)
+static hipError_t step_stages_impl(pf_solver* s, const T* phi, T* phi_next, const T* U,
+                                   const T* V, const T* W, double t, T* y2, T* y3, T* y4,
+                                   hipStream_t st)
 {
     const pf_params& p = s->p;
     const double dt = p.dt;
     T* acc = (T*)s->acc;
     const int v = s->variant;
-    if (p.scheme == PF_EULER)
-        return enqueue_step<T>(p, v, phi, U, V, W, (T*)s->ya, (T*)s->yb, acc, t, st, nullptr);
-    if (p.scheme != PF_RK4)  // RK3 and RK2 keep their stage inputs in ya (y2) and yb (y3)
-        return enqueue_step<T>(p, v, phi, U, V, W, y2, y3 ? y3 : (T*)s->yb, acc, t, st, nullptr);
     const double sh = time_factor(p, t + 0.5 * dt);
     hipError_t e;
-    if (variant_is_fused(p.dtype, v) && wall_mask(p) == 0) {
+    if (p.scheme == PF_EULER) {
+        if (phi_next == phi)  // in place: through the accumulator, as the step does
+            return enqueue_step<T>(p, v, phi_next, U, V, W, (T*)s->ya, (T*)s->yb, acc, t, st,
+                                   nullptr);
+        return run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, nullptr, phi, nullptr,
+                                             phi_next, 0.0, dt, U, V, W), st);
+    }
+    if (p.scheme == PF_RK2) {
+        e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, phi, nullptr, y2, nullptr,
+                                          0.5 * dt, 0.0, U, V, W), st);
+        if (e != hipSuccess) return e;
+        return run_stage<T>(v, make_stage<T>(p, sh, y2, nullptr, phi, nullptr, phi_next, 0.0, dt,
+                                             U, V, W), st);
+    }
+    if (p.scheme == PF_RK3) {
+        constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0;
+        e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, phi, phi, y2, acc, dt * g1,
+                                          dt * (g1 + z2), U, V, W), st);
+        if (e != hipSuccess) return e;
+        e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t + g1 * dt), y2, acc, nullptr, y3,
+                                          nullptr, dt * g2, 0.0, U, V, W), st);
+        if (e != hipSuccess) return e;
+        return run_stage<T>(v, make_stage<T>(p, time_factor(p, t + (g1 + g2 + z2) * dt), y3,
+                                             nullptr, acc, nullptr, phi_next, 0.0, dt * g3, U, V, W),
+                            st);
+    }
+    const long long cells = (long long)p.n[0] * p.n[1] * p.n[2];
+    if (variant_is_fused(p.dtype, v) && wall_mask(p) == 0 &&
+        (p.dtype == PF_F32 || cells >= 176LL * 176 * 176)) {
         FusedArgs<T> a = make_fused<T>(p, false, t, phi, acc, U, V, W, y3);
         a.out_mid = y2;
         e = run_fused_sweep<T>(v, a, false, st);
@@ -777,14 +803,14 @@ static hipError_t step_stages_impl(pf_solver* s, T* phi, const T* U, const T* V,
     if (e == hipSuccess)
         e = run_stage<T>(v, make_stage<T>(p, sh, y3, phi, acc, y4, acc, dt, dt / 3.0, U, V, W), st);
     if (e == hipSuccess)
-        e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t + dt), y4, nullptr, acc, nullptr, phi,
-                                          0.0, dt / 6.0, U, V, W), st);
+        e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t + dt), y4, nullptr, acc, nullptr,
+                                          phi_next, 0.0, dt / 6.0, U, V, W), st);
     return e;
 }
 
-extern "C" pf_status phasefield_step_stages(pf_solver* s, void* phi, const void* u, const void* v,
-                                            const void* w, double t, void* y2, void* y3, void* y4,
-                                            void* hip_stream)
+extern "C" pf_status phasefield_step_stages(pf_solver* s, void* phi, void* phi_next, const void* u,
+                                            const void* v, const void* w, double t, void* y2,
+                                            void* y3, void* y4, void* hip_stream)
 {
     if (!s) return fail(PF_ERR_INVALID, "solver is NULL");
     pf_status st;
@@ -792,6 +818,8 @@ extern "C" pf_status phasefield_step_stages(pf_solver* s, void* phi, const void*
     if ((st = check_field_ptr(u, "u")) != PF_OK) return st;
     if ((st = check_field_ptr(v, "v")) != PF_OK) return st;
     if ((st = check_field_ptr(w, "w")) != PF_OK) return st;
+    if (!phi_next) phi_next = phi;
+    if ((st = check_field_ptr(phi_next, "phi_next")) != PF_OK) return st;
     if (!std::isfinite(t)) return fail(PF_ERR_INVALID, "t is not finite");
     if (s->nu.on())
         return fail(PF_ERR_UNSUPPORTED, "stage inputs are kept for uniform meshes only (no adjoint)");
@@ -800,18 +828,21 @@ extern "C" pf_status phasefield_step_stages(pf_solver* s, void* phi, const void*
     for (int k = 0; k < ns; ++k) {
         if ((st = check_field_ptr(stages[k], k == 0 ? "y2" : k == 1 ? "y3" : "y4")) != PF_OK)
             return st;
-        if (stages[k] == phi) return fail(PF_ERR_INVALID, "a stage buffer is phi");
+        if (stages[k] == phi || stages[k] == phi_next)
+            return fail(PF_ERR_INVALID, "a stage buffer is phi or phi_next");
         for (int j = 0; j < k; ++j)
             if (stages[j] == stages[k]) return fail(PF_ERR_INVALID, "stage buffers coincide");
     }
     hipStream_t hs = (hipStream_t)hip_stream;
     hipError_t e =
         s->p.dtype == PF_F32
-            ? step_stages_impl<float>(s, (float*)phi, (const float*)u, (const float*)v,
-                                      (const float*)w, t, (float*)(ns > 0 ? y2 : nullptr),
-                                      (float*)(ns > 1 ? y3 : nullptr), (float*)(ns > 2 ? y4 : nullptr), hs)
-            : step_stages_impl<double>(s, (double*)phi, (const double*)u, (const double*)v,
-                                       (const double*)w, t, (double*)(ns > 0 ? y2 : nullptr),
+            ? step_stages_impl<float>(s, (const float*)phi, (float*)phi_next, (const float*)u,
+                                      (const float*)v, (const float*)w, t,
+                                      (float*)(ns > 0 ? y2 : nullptr), (float*)(ns > 1 ? y3 : nullptr),
+                                      (float*)(ns > 2 ? y4 : nullptr), hs)
+            : step_stages_impl<double>(s, (const double*)phi, (double*)phi_next, (const double*)u,
+                                       (const double*)v, (const double*)w, t,
+                                       (double*)(ns > 0 ? y2 : nullptr),
                                        (double*)(ns > 1 ? y3 : nullptr),
                                        (double*)(ns > 2 ? y4 : nullptr), hs);
     return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_step_stages");

@@ -121,8 +121,8 @@ def test_adjoint_form_setter_checks_its_arguments(pf):
 
 
 def test_stage_entry_points_check_the_handle(pf):
-    assert pf.lib.phasefield_step_stages(None, None, None, None, None, 0.0, None, None, None,
-                                         None) == pf.PF_ERR_INVALID
+    assert pf.lib.phasefield_step_stages(None, None, None, None, None, None, 0.0, None, None,
+                                         None, None) == pf.PF_ERR_INVALID
     assert pf.lib.phasefield_adjoint_step_stages(None, None, None, None, None, None, None, None,
                                                  0.0, None, None, None, None,
                                                  None) == pf.PF_ERR_INVALID

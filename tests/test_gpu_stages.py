@@ -3,12 +3,13 @@ of one step (Sec. 2.3: RK4 y2, y3, y4; RK3 its first two low-storage stages; RK2
 value) and phasefield_adjoint_step_stages takes them instead of recomputing them.
 
 Checked for RK4, RK3, RK2 and Euler, FP64 and FP32, per-stage and fused variants, periodic and
-walled grids, one-plane grids, steady and time-varying velocity: the new phi bitwise equal to
-phasefield_step's, lam and the velocity gradients bitwise equal to phasefield_adjoint_step's
-(which the adjoint tests hold to the oracle), every stage buffer written completely, and in FP64
-each stored stage against its definition evaluated with the oracle's right-hand side from the
-previously stored stage (1e-12 relative L-inf); the checkpointed Rollout with and without stage
-caching bitwise equal; the argument refusals.
+walled grids, one-plane grids, steady and time-varying velocity: the new phi, in place and into
+a separate buffer (phi then untouched), bitwise equal to phasefield_step's; lam and the velocity
+gradients bitwise equal to phasefield_adjoint_step's (which the adjoint tests hold to the
+oracle); every stage buffer written completely; in FP64 each stored stage against its definition
+evaluated with the oracle's right-hand side from the previously stored stage (1e-12 relative
+L-inf); the checkpointed Rollout with and without stage caching bitwise equal; the argument
+refusals.
 """
 import numpy as np
 import pytest
@@ -89,12 +90,20 @@ def test_stages_match_step_and_adjoint_bitwise(lib, scheme, dtype, shape, vname,
     ys = [torch.full_like(g[0], float("nan")) for _ in range(ns)]
     phi1 = g[0].clone()
     s.step_stages(phi1, *g[1:], t, *ys)
+    # out of place: phi untouched, the same new phi and stages
+    ys2 = [torch.full_like(g[0], float("nan")) for _ in range(ns)]
+    phi_in = g[0].clone()
+    phi2 = torch.full_like(g[0], float("nan"))
+    s.step_stages(phi_in, *g[1:], t, *ys2, phi_next=phi2)
     lam1 = dev(lam, tdt)
     grad1 = [torch.zeros_like(g[0]) for _ in range(3)]
     s.adjoint_step_stages(g[0], ys, *g[1:], t, lam1, *grad1)
     torch.cuda.synchronize()
     s.close()
     assert torch.equal(phi1, ref_phi)
+    assert torch.equal(phi2, ref_phi) and torch.equal(phi_in, g[0])
+    for a, b in zip(ys, ys2):
+        assert torch.equal(a, b)
     assert torch.equal(lam1, lam_ref)
     for a, b in zip(grad1, grad_ref):
         assert torch.equal(a, b)
@@ -169,6 +178,9 @@ def test_stage_argument_refusals(lib):
     assert ei.value.status == pf.PF_ERR_INVALID
     with pytest.raises(pf.PhaseFieldError) as ei:  # a stage buffer is phi
         s.step_stages(g[0], *g[1:], 0.0, g[0], y[1], y[2])
+    assert ei.value.status == pf.PF_ERR_INVALID
+    with pytest.raises(pf.PhaseFieldError) as ei:  # a stage buffer is phi_next
+        s.step_stages(g[0], *g[1:], 0.0, *y, phi_next=y[2])
     assert ei.value.status == pf.PF_ERR_INVALID
     with pytest.raises(pf.PhaseFieldError) as ei:
         s.step_stages(g[0], *g[1:], float("nan"), *y)
