@@ -28,7 +28,11 @@
  *
  * Streams: hip_stream is a hipStream_t (NULL = the legacy default stream). Work is enqueued
  * asynchronously on it unless a function says it synchronises. A handle serves one stream at a
- * time; calls on one handle from several host threads must be serialised by the caller.
+ * time; calls on one handle from several host threads must be serialised by the caller. One
+ * exception: phasefield_step_stages (which uses the handle's accumulator buffer alone) and
+ * phasefield_adjoint_step_stages (its adjoint buffers alone) may run at the same time on two
+ * streams, e.g. a checkpointed backward re-running one segment while it sweeps the next one
+ * backwards; each of the two still serves one stream at a time.
  *
  * Errors: every function returns pf_status; none aborts. On failure nothing has been enqueued
  * (argument errors) or the HIP error is reported as PF_ERR_DEVICE; phasefield_last_error()
