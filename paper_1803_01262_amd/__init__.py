@@ -197,18 +197,21 @@ class Rollout(torch.autograd.Function):
     Backward: discrete adjoint with checkpoints every ``ckpt`` steps. Each segment is re-run
     from its checkpoint (states held on the GPU), then swept backwards step by step; the
     accumulated face-velocity gradient is projected onto the mode coefficients once. With
-    ``cache_stages`` (default) the re-run keeps every step's stage inputs as well
-    (phasefield_step_stages; (1 + stage_count) fields per step of a segment) and the sweep takes
-    them (phasefield_adjoint_step_stages) instead of recomputing them; without it, each adjoint
-    step recomputes its stage inputs (phasefield_adjoint_step; one field per step). Both give the
-    same gradients bit for bit. Returns gradients for phi_0 and coeffs.
+    ``cache_stages`` the re-run keeps every step's stage inputs as well (phasefield_step_stages;
+    (2 + stage_count) fields per step, for two segments at a time: each earlier segment is re-run
+    on a side stream while the later one is swept) and the sweep takes them
+    (phasefield_adjoint_step_stages) instead of recomputing them; without it, each adjoint step
+    recomputes its stage inputs (phasefield_adjoint_step; one field per step of one segment).
+    ``cache_stages=None`` (the default) caches when that memory is below half of what the device
+    has available. Both give the same gradients bit for bit. Returns gradients for phi_0 and
+    coeffs.
 
     Usage: Rollout.apply(phi0, coeffs, solver, phases, nsteps, ckpt, t0, cache_stages)
     """
 
     @staticmethod
     def forward(ctx, phi0, coeffs, solver: Solver, phases, nsteps: int, ckpt: int = 20,
-                t0: float = 0.0, cache_stages: bool = True):
+                t0: float = 0.0, cache_stages: bool | None = None):
         p = solver.params
         u, v, w = velocity_from_coeffs(p, phases, coeffs.detach().to(torch.float64))
         phi = phi0.detach().clone().contiguous()
@@ -221,6 +224,12 @@ class Rollout(torch.autograd.Function):
             _advance(solver, phi, u, v, w, t0, n, m, single)
             n += m
         ctx.solver, ctx.phases, ctx.nsteps, ctx.ckpt, ctx.t0 = solver, phases, nsteps, ckpt, t0
+        if cache_stages is None:
+            m = min(ckpt, nsteps)
+            need = 2 * m * (2 + solver.stage_count) * phi.numel() * phi.element_size()
+            free, _ = torch.cuda.mem_get_info(phi.device)
+            free += torch.cuda.memory_reserved(phi.device) - torch.cuda.memory_allocated(phi.device)
+            cache_stages = need < free // 2
         ctx.cache_stages = bool(cache_stages)
         ctx.ckpts = ckpts
         ctx.vel = (u, v, w)
