@@ -288,7 +288,8 @@ def rollout_timing(pf, fx, dtype, n=128):
     coefficients. Times the forward (velocity synthesis, steps, checkpoint copies) and the
     backward (segment re-runs, 400 adjoint steps, projection onto the coefficients), on the
     current stream: the default backward, whose re-runs keep the stage inputs for the adjoint
-    steps, and the one whose adjoint steps recompute them."""
+    steps, the one whose adjoint steps recompute them, and (keep_all) a forward that keeps every
+    state and stage input so that the backward is the reverse sweep alone."""
     import torch
     c = fx.adjoint_case(n)
     tdt = torch.float32 if dtype == "f32" else torch.float64
@@ -302,13 +303,13 @@ def rollout_timing(pf, fx, dtype, n=128):
     cf = coeffs.clone().requires_grad_(True)
     target = torch.tensor(c.extra["target"], dtype=tdt, device="cuda")
 
-    def run(nsteps, cache):
+    def run(nsteps, cache, keep_all=False):
         phi0.grad = None
         cf.grad = None
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         torch.cuda.synchronize()
         ev[0].record()
-        phiT = pf.Rollout.apply(phi0, cf, s, phases, nsteps, 20, 0.0, cache)
+        phiT = pf.Rollout.apply(phi0, cf, s, phases, nsteps, 20, 0.0, cache, keep_all)
         loss = 0.5 * ((phiT - target) ** 2).sum()
         ev[1].record()
         loss.backward()
@@ -319,7 +320,9 @@ def rollout_timing(pf, fx, dtype, n=128):
     # warm-up: one short rollout each way (first launches of every kernel, graph capture)
     run(20, True)
     run(20, False)
+    run(20, None, True)
     fwd_r, bwd_r = run(c.nsteps, False)
+    fwd_k, bwd_k = run(c.nsteps, None, True)
     fwd, bwd = run(c.nsteps, True)
     # a forward whose state buffer landed at a new address re-captures its step graph; the
     # faster of the two forwards is the denominator of both ratios (the larger ratios)
@@ -329,6 +332,10 @@ def rollout_timing(pf, fx, dtype, n=128):
            "backward_over_forward": round(bwd / fwd, 3),
            "backward_ms_recomputing_stages": round(bwd_r, 2),
            "backward_over_forward_recomputing_stages": round(bwd_r / fwd, 3),
+           # the forward keeping every state and stage input (no checkpoints, no re-run)
+           "keep_all": {"forward_ms": round(fwd_k, 2), "backward_ms": round(bwd_k, 2),
+                        "backward_over_checkpointed_forward": round(bwd_k / fwd, 3),
+                        "total_over_checkpointed_total": round((fwd_k + bwd_k) / (fwd + bwd), 3)},
            "grad_finite": bool(torch.isfinite(phi0.grad).all() and torch.isfinite(cf.grad).all())}
     s.close()
     return out

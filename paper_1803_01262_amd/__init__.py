@@ -203,18 +203,40 @@ class Rollout(torch.autograd.Function):
     (phasefield_adjoint_step_stages) instead of recomputing them; without it, each adjoint step
     recomputes its stage inputs (phasefield_adjoint_step; one field per step of one segment).
     ``cache_stages=None`` (the default) caches when that memory is below half of what the device
-    has available. Both give the same gradients bit for bit. Returns gradients for phi_0 and
-    coeffs.
+    has available. With ``keep_all`` the forward itself keeps every step's state and stage inputs
+    ((1 + stage_count) fields per step for the whole rollout, one allocation; ckpt and
+    cache_stages are then unused) and the backward is the reverse sweep alone. All forms give the same gradients bit
+    for bit. Returns gradients for phi_0 and coeffs.
 
-    Usage: Rollout.apply(phi0, coeffs, solver, phases, nsteps, ckpt, t0, cache_stages)
+    Usage: Rollout.apply(phi0, coeffs, solver, phases, nsteps, ckpt, t0, cache_stages, keep_all)
     """
 
     @staticmethod
     def forward(ctx, phi0, coeffs, solver: Solver, phases, nsteps: int, ckpt: int = 20,
-                t0: float = 0.0, cache_stages: bool | None = None):
+                t0: float = 0.0, cache_stages: bool | None = None, keep_all: bool = False):
         p = solver.params
         u, v, w = velocity_from_coeffs(p, phases, coeffs.detach().to(torch.float64))
         phi = phi0.detach().clone().contiguous()
+        ctx.solver, ctx.phases, ctx.nsteps, ctx.ckpt, ctx.t0 = solver, phases, nsteps, ckpt, t0
+        ctx.vel = (u, v, w)
+        ctx.keep_all = bool(keep_all)
+        if ctx.keep_all:
+            # every state and stage input of the rollout, in one allocation: field k of step n at
+            # row n (1 + stage_count) + k (0: the state), rows padded to 256 bytes
+            ns = solver.stage_count
+            esz, numel = phi.element_size(), phi.numel()
+            row = -(-numel * esz // 256) * 256 // esz
+            pool = torch.empty(((nsteps + 1) * (1 + ns), row), dtype=phi.dtype, device=phi.device)
+
+            def field(n, k):
+                return pool[n * (1 + ns) + k, :numel].view(phi.shape)
+
+            field(0, 0).copy_(phi)
+            for n in range(nsteps):
+                solver.step_stages(field(n, 0), u, v, w, t0 + n * solver.dt,
+                                   *[field(n, 1 + k) for k in range(ns)], phi_next=field(n + 1, 0))
+            ctx.pool, ctx.field = pool, field
+            return field(nsteps, 0).clone()
         single = p.vel_mode != PF_VEL_STEADY  # time-varying: one call per step, t = t0 + n dt
         ckpts = []
         n = 0
@@ -223,7 +245,6 @@ class Rollout(torch.autograd.Function):
             m = min(ckpt, nsteps - n)
             _advance(solver, phi, u, v, w, t0, n, m, single)
             n += m
-        ctx.solver, ctx.phases, ctx.nsteps, ctx.ckpt, ctx.t0 = solver, phases, nsteps, ckpt, t0
         if cache_stages is None:
             m = min(ckpt, nsteps)
             need = 2 * m * (2 + solver.stage_count) * phi.numel() * phi.element_size()
@@ -232,7 +253,6 @@ class Rollout(torch.autograd.Function):
             cache_stages = need < free // 2
         ctx.cache_stages = bool(cache_stages)
         ctx.ckpts = ckpts
-        ctx.vel = (u, v, w)
         return phi
 
     @staticmethod
@@ -244,8 +264,16 @@ class Rollout(torch.autograd.Function):
         single = p.vel_mode != PF_VEL_STEADY
         lam = grad_out.detach().to(solver.dtype).contiguous().clone()
         gu, gv, gw = (torch.zeros_like(u) for _ in range(3))
-        nseg = len(ctx.ckpts)
         ns = solver.stage_count
+        if ctx.keep_all:
+            f = ctx.field
+            for n in reversed(range(nsteps)):
+                solver.adjoint_step_stages(f(n, 0), [f(n, 1 + k) for k in range(ns)], u, v, w,
+                                           t0 + n * dt, lam, gu, gv, gw)
+            cg = velocity_coeffs_grad(p, ctx.phases, gu, gv, gw)
+            ctx.pool = ctx.field = None
+            return lam, cg, None, None, None, None, None, None, None
+        nseg = len(ctx.ckpts)
         if ctx.cache_stages:
             main = torch.cuda.current_stream()
             side = torch.cuda.Stream()
@@ -300,7 +328,7 @@ class Rollout(torch.autograd.Function):
                     solver.adjoint_step(states[j], u, v, w, t0 + (n0 + j) * dt, lam, gu, gv, gw)
         cg = velocity_coeffs_grad(p, ctx.phases, gu, gv, gw)
         ctx.ckpts = None
-        return lam, cg, None, None, None, None, None, None
+        return lam, cg, None, None, None, None, None, None, None
 
 
 def _advance(solver, phi, u, v, w, t0, n0, m, single):

@@ -8,8 +8,8 @@ a separate buffer (phi then untouched), bitwise equal to phasefield_step's; lam 
 gradients bitwise equal to phasefield_adjoint_step's (which the adjoint tests hold to the
 oracle); every stage buffer written completely; in FP64 each stored stage against its definition
 evaluated with the oracle's right-hand side from the previously stored stage (1e-12 relative
-L-inf); the checkpointed Rollout with and without stage caching bitwise equal; the argument
-refusals.
+L-inf); the Rollout with stage caching, without it and keeping every step bitwise equal; the
+argument refusals.
 """
 import numpy as np
 import pytest
@@ -136,8 +136,9 @@ def test_stages_match_step_and_adjoint_bitwise(lib, scheme, dtype, shape, vname,
 @pytest.mark.parametrize("dtype,vel_mode", [("f64", 0), ("f32", 1)])
 def test_rollout_with_and_without_stage_caching_bitwise(lib, dtype, vel_mode):
     """The checkpointed Rollout (24 steps of 24^3, checkpoint 10: segments 10, 10, 4) gives the
-    same gradients bit for bit whether the re-run segments keep their stage inputs or each
-    adjoint step recomputes them."""
+    same gradients and final state bit for bit whether the re-run segments keep their stage
+    inputs, each adjoint step recomputes them, or the forward keeps every state and stage input
+    (keep_all)."""
     pf = lib
     n = 24
     c = fx.adjoint_case(n)
@@ -150,17 +151,18 @@ def test_rollout_with_and_without_stage_caching_bitwise(lib, dtype, vel_mode):
     s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, c.dt, dtype=dtype, delta=c.delta,
                   vel_mode=vel_mode, vel_T=40 * c.dt)
     out = []
-    for cache in (True, False):
+    for cache, keep_all in ((True, False), (False, False), (None, True)):
         phi0 = dev(c.phi0, tdt).requires_grad_(True)
         cc = dev(c.modes[1]).requires_grad_(True)
-        phiT = pf.Rollout.apply(phi0, cc, s, th, 24, 10, 0.0, cache)
+        phiT = pf.Rollout.apply(phi0, cc, s, th, 24, 10, 0.0, cache, keep_all)
         L = 0.5 * ((phiT - dev(c.extra["target"], tdt)) ** 2).sum()
         L.backward()
         torch.cuda.synchronize()
-        out.append((phi0.grad.clone(), cc.grad.clone()))
+        out.append((phi0.grad.clone(), cc.grad.clone(), phiT.detach().clone()))
     s.close()
-    assert torch.equal(out[0][0], out[1][0])
-    assert torch.equal(out[0][1], out[1][1])
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert torch.equal(a, b)
     assert float(out[0][0].abs().max()) > 0.0 and float(out[0][1].abs().max()) > 0.0
 
 
