@@ -746,9 +746,9 @@ extern "C" pf_status phasefield_step(pf_solver* s, void* phi, const void* u, con
 // One step of the handle's scheme from time t that also stores the stage inputs the adjoint step
 // reads (scheme_stage_count), the new phi into phi_next (phi itself: in place): the per-stage
 // launches with the stage outputs directed into the caller's buffers; an RK4 step of a fused
-// variant (no walls; FP64 from 176^3 cells, where the fused sweep overtakes the per-stage
-// launches) gets y2 and y3 from one sweep A that stores its middle value, then y4 and the new phi
-// from two per-stage launches. Every form rounds alike, so the new phi and the stages are
+// variant (no walls; FP64 from 176^3 cells, where the fused sweeps overtake the per-stage
+// launches) runs its two sweeps, each storing its middle value (y2, y4; sweep A also writes y3),
+// when out of place, and in place sweep A then two per-stage launches for y4 and the new phi. Every form rounds alike, so the new phi and the stages are
 // bit-identical to those of phasefield_step and of the adjoint's own recompute.
 template <typename T>
 static hipError_t step_stages_impl(pf_solver* s, const T* phi, T* phi_next, const T* U,
@@ -788,8 +788,20 @@ static hipError_t step_stages_impl(pf_solver* s, const T* phi, T* phi_next, cons
                             st);
     }
     const long long cells = (long long)p.n[0] * p.n[1] * p.n[2];
-    if (variant_is_fused(p.dtype, v) && wall_mask(p) == 0 &&
-        (p.dtype == PF_F32 || cells >= 176LL * 176 * 176)) {
+    const bool fused = variant_is_fused(p.dtype, v) && wall_mask(p) == 0 &&
+                       (p.dtype == PF_F32 || cells >= 176LL * 176 * 176);
+    if (fused && phi_next != phi) {
+        // out of place: the two sweeps of the step, the accumulator in phi_next (sweep B writes
+        // the new phi over it at the cell), sweep A storing y2, sweep B y4
+        FusedArgs<T> a = make_fused<T>(p, false, t, phi, phi_next, U, V, W, y3);
+        a.out_mid = y2;
+        e = run_fused_sweep<T>(v, a, false, st);
+        if (e != hipSuccess) return e;
+        FusedArgs<T> b = make_fused<T>(p, true, t, phi, phi_next, U, V, W, y3);
+        b.out_mid = y4;
+        return run_fused_sweep<T>(v, b, true, st);
+    }
+    if (fused) {
         FusedArgs<T> a = make_fused<T>(p, false, t, phi, acc, U, V, W, y3);
         a.out_mid = y2;
         e = run_fused_sweep<T>(v, a, false, st);

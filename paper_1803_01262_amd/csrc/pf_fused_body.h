@@ -17,10 +17,12 @@
 //
 // The explicit midpoint rule (RK2) is sweep A alone: with c_mid = dt/2 and c_y2 = dt its out_y
 // is the new phi (into the other buffer of the pair), and a null out_acc skips the accumulator.
-// Two more optional outputs of sweep A (XOUT, a separate instantiation so that the descriptors
-// cost the plain sweeps no registers): out_mid receives y_mid on the tile (so the adjoint can
-// recompute two stage inputs in one sweep), and out_phi a copy of phi (then sweep B may read that
-// copy and write the new phi into phi's own buffer, which ends an odd step count in place).
+// Optional outputs (XOUT, a separate instantiation so that the descriptors cost the plain sweeps
+// no registers): out_mid receives y_mid on the tile (sweep A: the RK4 stage value y2, so that the
+// adjoint can recompute two stage inputs in one sweep; sweep B: y4, so that a step can keep all
+// its stage values in two sweeps), and, in sweep A only, out_phi a copy of phi (then sweep B may
+// read that copy and write the new phi into phi's own buffer, which ends an odd step count in
+// place).
 //
 // Regions, for a TX x TY tile at (i0, j0), as (x range) x (y range):
 //   IN   stage input, ring of 3 planes       [i0-4, i0+TX+4) x [j0-4, j0+TY+4)
@@ -83,7 +85,6 @@ template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XO
           bool WALLS = false, bool LAG = false>
 __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj, int k0, int k1)
 {
-    static_assert(!(XOUT && SWEEP_B), "the optional outputs belong to sweep A");
     static_assert(!(WALLS && WIDE), "mirror reads are element-wise");
     constexpr int NT = TX * TY;
     constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte piece
@@ -596,7 +597,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                                       ge);
                 const unsigned c = e_col[0];  // own cell (i0+tx, j0+ty): no wrap when active
                 if (!SWEEP_B) foy.store(to, c, fma(a.c_y2, f2, qa_phi[0]));
-                if constexpr (XOUT)
+                if constexpr (XOUT && !SWEEP_B)
                     if (a.out_phi) fophi.store(to, c, qa_phi[0]);
                 if (SWEEP_B || a.out_acc) foacc.store(to, c, fma(a.c_acc2, f2, qa_acc[0]));
             }

@@ -10,8 +10,8 @@ namespace pf {
 // One workgroup per (tile, z-chunk of kz planes); the chunk length is a launch argument.
 // FP32: at least four waves per SIMD (at most 128 VGPRs), two workgroups of eight waves per CU.
 // FP64 needs more registers than that and runs at two waves per SIMD.
-// XOUT: sweep A with its optional outputs (out_mid, out_phi). WALLS: x and/or y walled
-// (a.walls), element-wise plane loads, single-descriptor addressing.
+// XOUT: the optional outputs (out_mid; sweep A also out_phi). WALLS: x and/or y walled (a.walls),
+// element-wise plane loads, single-descriptor addressing.
 template <typename T, int TX, int TY, bool SWEEP_B, bool BIG, bool WIDE, bool XOUT, bool WALLS = false>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 fused_kernel(FusedArgs<T> a, int tiles_x, int tiles_y, int kz)
@@ -29,10 +29,18 @@ template <typename T, int TX, int TY, bool BIG, bool WIDE, bool WALLS = false>
 hipError_t launch_fused_sweep(const FusedArgs<T>& a, bool sweep_b, unsigned blocks, int tiles_x,
                               int tiles_y, int kz, hipStream_t st)
 {
-    if (sweep_b)
+    if (sweep_b) {
+        if constexpr (!WALLS) {  // sweep B with out_mid: periodic x and y only
+            if (a.out_mid) {
+                hipLaunchKernelGGL((fused_kernel<T, TX, TY, true, BIG, WIDE, true, false>),
+                                   dim3(blocks), dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
+                return hipGetLastError();
+            }
+        }
+        if (a.out_mid || a.out_phi) return hipErrorInvalidValue;
         hipLaunchKernelGGL((fused_kernel<T, TX, TY, true, BIG, WIDE, false, WALLS>), dim3(blocks),
                            dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
-    else if (a.out_mid || a.out_phi)
+    } else if (a.out_mid || a.out_phi)
         hipLaunchKernelGGL((fused_kernel<T, TX, TY, false, BIG, WIDE, true, WALLS>), dim3(blocks),
                            dim3(TX * TY), 0, st, a, tiles_x, tiles_y, kz);
     else

@@ -56,6 +56,7 @@ CASES = [
     ("rk4", "f64", (14, 18, 40), "fused_32x16", (T, F, T), 0),
     ("rk4", "f32", (14, 18, 40), "fused_32x16x32", (F, T, F), 1),
     ("rk4", "f64", (1, 20, 18), None, (F, F, F), 0),
+    ("rk4", "f64", (176, 176, 176), "fused_32x16", (F, F, F), 1),  # FP64 fused from 176^3
     ("rk3", "f64", (12, 10, 14), None, (F, F, F), 1),
     ("rk3", "f32", (20, 18, 40), "fused_32x16", (F, F, F), 0),
     ("rk2", "f64", (12, 10, 14), None, (F, F, F), 1),
