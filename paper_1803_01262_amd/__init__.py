@@ -205,8 +205,8 @@ class Rollout(torch.autograd.Function):
     ``cache_stages=None`` (the default) caches when that memory is below half of what the device
     has available. With ``keep_all`` the forward itself keeps every step's state and stage inputs
     ((1 + stage_count) fields per step for the whole rollout, one allocation; ckpt and
-    cache_stages are then unused) and the backward is the reverse sweep alone. All forms give the same gradients bit
-    for bit. Returns gradients for phi_0 and coeffs.
+    cache_stages are then unused) and the backward is the reverse sweep alone. All forms give
+    the same gradients bit for bit. Returns gradients for phi_0 and coeffs.
 
     Usage: Rollout.apply(phi0, coeffs, solver, phases, nsteps, ckpt, t0, cache_stages, keep_all)
     """
