@@ -208,8 +208,9 @@ pf_status phasefield_adjoint_step_stages(pf_solver *s, const void *phi_n, const 
  * phi and of the sharpening product stay the means of the two cells. eps_mode 0: p->eps
  * everywhere (the worst-case choice: eps on the crossover line of Eq. 17 for the largest width);
  * 1: per cell p->eps * max(hx_i, hy_j, hz_k) / p->dx (p->dx the reference spacing p->eps belongs
- * to; the maximum over the axes longer than one cell), averaged onto each face. From then on phasefield_step runs every scheme through the
- * per-stage kernel in its non-uniform form (no fused sweeps), phasefield_reduce returns
+ * to; the maximum over the axes longer than one cell), averaged onto each face. From then on
+ * phasefield_step runs every scheme through the per-stage kernel in its non-uniform form (no
+ * fused sweeps), phasefield_reduce returns
  * sum(phi * cell volume) (axes of one cell carry no volume), and phasefield_adjoint_step and
  * phasefield_autotune return PF_ERR_UNSUPPORTED. The velocity on the faces must be discretely
  * divergence-free on this mesh, sum_a (u_a[+] - u_a[-]) / h_a = 0. All three NULL returns the
@@ -287,8 +288,8 @@ int32_t phasefield_solver_variant(const pf_solver *s);
  * Batched driver: many independent simulations (each its own pf_params, uneven grid sizes,
  * same dtype, RK4, steady velocity) advanced together. Each sweep is ONE launch over a global
  * tile list that covers every instance (one workgroup per tile): two fused two-stage sweeps per
- * step, or four single-stage sweeps. per_instance[0].variant selects the mode by its kind (a "fused_*" variant
- * or a per-stage one); with variant -1, FP32 runs fused and FP64 per-stage. Instances may have
+ * step, or four single-stage sweeps. per_instance[0].variant selects the mode by its kind (a
+ * "fused_*" variant or a per-stage one); with variant -1, FP32 runs fused and FP64 per-stage. Instances may have
  * walls on any axes (each its own); a walled z axis in any instance puts the batch in per-stage
  * mode (the fused sweeps take walls on x and y only). The step sequence
  * is replayed from a captured HIP graph. Results are bit-identical to running each instance

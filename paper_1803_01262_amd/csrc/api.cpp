@@ -748,8 +748,9 @@ extern "C" pf_status phasefield_step(pf_solver* s, void* phi, const void* u, con
 // launches with the stage outputs directed into the caller's buffers; an RK4 step of a fused
 // variant (no walls; FP64 from 176^3 cells, where the fused sweeps overtake the per-stage
 // launches) runs its two sweeps, each storing its middle value (y2, y4; sweep A also writes y3),
-// when out of place, and in place sweep A then two per-stage launches for y4 and the new phi. Every form rounds alike, so the new phi and the stages are
-// bit-identical to those of phasefield_step and of the adjoint's own recompute.
+// when out of place, and in place sweep A then two per-stage launches for y4 and the new phi.
+// Every form rounds alike, so the new phi and the stages are bit-identical to those of
+// phasefield_step and of the adjoint's own recompute.
 template <typename T>
 static hipError_t step_stages_impl(pf_solver* s, const T* phi, T* phi_next, const T* U,
                                    const T* V, const T* W, double t, T* y2, T* y3, T* y4,
