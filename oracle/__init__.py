@@ -70,6 +70,9 @@ def _l():
         _lib.orc_step_nu.argtypes = [gp, p, p, p, ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d,
                                      ctypes.c_int, d, i64, p, p, p, p]
         _lib.orc_reduce_nu.argtypes = [gp, p, p, p, p, p]
+        _lib.orc_rhs_vjp_nu.argtypes = [gp, p, p, p, ctypes.c_int, d, p, p, p, p, p, p, p, p, p]
+        _lib.orc_adjoint_step_nu.argtypes = [gp, p, p, p, ctypes.c_int, ctypes.c_int, d, d,
+                                             ctypes.c_int, d, p, p, p, p, p, p, p, p]
         _lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib.orc_max_threads.restype = ctypes.c_int
     return _lib
@@ -246,6 +249,34 @@ def step_nu(phi, U, V, W, *, hx, hy, hz, dx, eps, gamma, dt, nsteps=1, delta=0.0
                      int(bool(fp32)), dt, t0, int(vel_mode), float(vel_T), int(nsteps), _ptr(out),
                      _ptr(U), _ptr(V), _ptr(W))
     return out
+
+
+def rhs_vjp_nu(phi, U, V, W, lam, *, hx, hy, hz, dx, eps, gamma, delta=0.0, s=1.0, eps_mode=0,
+               walls=(False, False, False)):
+    """(J^T lam, dU, dV, dW): vector-Jacobian product of rhs_nu() at phi."""
+    phi, U, V, W, lam = map(_f64, (phi, U, V, W, lam))
+    pb, ub, vb, wb = (np.zeros_like(phi) for _ in range(4))
+    h = _widths(phi.shape, hx, hy, hz)
+    g = _grid(phi.shape, dx, eps, gamma, delta, walls)
+    _l().orc_rhs_vjp_nu(ctypes.byref(g), *(_ptr(a) for a in h), int(eps_mode), s, _ptr(phi),
+                        _ptr(U), _ptr(V), _ptr(W), _ptr(lam), _ptr(pb), _ptr(ub), _ptr(vb),
+                        _ptr(wb))
+    return pb, ub, vb, wb
+
+
+def adjoint_step_nu(phi, U, V, W, lam, *, hx, hy, hz, dx, eps, gamma, dt, delta=0.0, t=0.0,
+                    scheme=4, vel_mode=0, vel_T=1.0, eps_mode=0, walls=(False, False, False)):
+    """adjoint_step() on a non-uniform mesh (widths and eps_mode as rhs_nu)."""
+    _check_scheme(scheme)
+    phi, U, V, W = map(_f64, (phi, U, V, W))
+    lam = _f64(lam).copy()
+    ub, vb, wb = (np.zeros_like(phi) for _ in range(3))
+    h = _widths(phi.shape, hx, hy, hz)
+    g = _grid(phi.shape, dx, eps, gamma, delta, walls)
+    _l().orc_adjoint_step_nu(ctypes.byref(g), *(_ptr(a) for a in h), int(eps_mode), int(scheme),
+                             dt, t, int(vel_mode), float(vel_T), _ptr(phi), _ptr(U), _ptr(V),
+                             _ptr(W), _ptr(lam), _ptr(ub), _ptr(vb), _ptr(wb))
+    return lam, ub, vb, wb
 
 
 def reduce_nu(phi, *, hx, hy, hz) -> tuple[float, float, float, float]:

@@ -586,11 +586,128 @@ void orc_rhs_vjp(const orc_grid *g, double s, const double *phi, const double *U
     free(qbar);
 }
 
+/* The same vector-Jacobian product for rhs_nu (the non-uniform mesh m): rhs_nu's steps run
+ * backwards with the mesh's coefficients, each scattered to the values it read. */
+static void rhs_vjp_nu(const orc_grid *g, const orc_mesh *m, double s, const double *phi,
+                       const double *U, const double *V, const double *W, const double *lam,
+                       double *phibar, double *Ubar, double *Vbar, double *Wbar)
+{
+    const int64_t N = ncell(g);
+    double *gr = malloc(sizeof(double) * 3 * N);
+    double *qbar = calloc(3 * N, sizeof(double));
+    const double *vel[3] = {U, V, W};
+    double *velbar[3] = {Ubar, Vbar, Wbar};
+    /* the forward's gradient (over the distance between the two neighbours' centres) */
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                const int64_t c = at(g, i, j, k);
+                const int64_t idx[3] = {i, j, k};
+                for (int a = 0; a < 3; ++a) {
+                    const double span = centre_dist(g, m, a, idx[a]) + centre_dist(g, m, a, idx[a] + 1);
+                    gr[3 * c + a] =
+                        (phi[nb_grad(g, i, j, k, a, +1)] - phi[nb_grad(g, i, j, k, a, -1)]) / span;
+                }
+            }
+    /* reverse of steps 5 and 4 */
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                const int64_t c = at(g, i, j, k);
+                const int64_t idx[3] = {i, j, k};
+                for (int a = 0; a < 3; ++a) {
+                    if (low_face_is_wall(g, i, j, k, a)) continue;
+                    const int64_t mc = nb(g, i, j, k, a, -1);
+                    /* F_a[c] enters f[mc] with +1/h(mc) and f[c] with -1/h(c) */
+                    const double Fbar = lam[mc] / width(g, m, a, idx[a] - 1) - lam[c] / width(g, m, a, idx[a]);
+                    const double eps_f = 0.5 * (eps_cell(g, m, i - (a == 0), j - (a == 1), k - (a == 2)) +
+                                                eps_cell(g, m, i, j, k));
+                    const double dcoef = g->gamma * eps_f / centre_dist(g, m, a, idx[a]);
+                    if (velbar[a]) velbar[a][c] += -s * 0.5 * (phi[mc] + phi[c]) * Fbar;
+                    phibar[c] += Fbar * (-s * vel[a][c] * 0.5 + dcoef);
+                    phibar[mc] += Fbar * (-s * vel[a][c] * 0.5 - dcoef);
+                    qbar[3 * c + a] += -g->gamma * 0.5 * Fbar;
+                    qbar[3 * mc + a] += -g->gamma * 0.5 * Fbar;
+                }
+            }
+    /* reverse of steps 3, 2 and 1 */
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                const int64_t c = at(g, i, j, k);
+                const int64_t idx[3] = {i, j, k};
+                const double p = phi[c];
+                double mag2 = 0.0;
+                for (int a = 0; a < 3; ++a) mag2 += gr[3 * c + a] * gr[3 * c + a];
+                const double mag = sqrt(mag2 + g->delta * g->delta);
+                double nbar[3], wbar = 0.0, gn = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double n_a = mag > 0.0 ? gr[3 * c + a] / mag : 0.0;
+                    wbar += n_a * qbar[3 * c + a];
+                    nbar[a] = p * (1.0 - p) * qbar[3 * c + a];
+                    gn += gr[3 * c + a] * nbar[a];
+                }
+                phibar[c] += (1.0 - 2.0 * p) * wbar;
+                if (!(mag > 0.0)) continue;
+                for (int a = 0; a < 3; ++a) {
+                    const double gbar = nbar[a] / mag - gr[3 * c + a] * gn / (mag * mag * mag);
+                    const double span = centre_dist(g, m, a, idx[a]) + centre_dist(g, m, a, idx[a] + 1);
+                    phibar[nb_grad(g, i, j, k, a, +1)] += gbar / span;
+                    phibar[nb_grad(g, i, j, k, a, -1)] -= gbar / span;
+                }
+            }
+    free(gr);
+    free(qbar);
+}
+
+static void rhs_vjp_any(const orc_grid *g, const orc_mesh *m, double s, const double *phi,
+                        const double *U, const double *V, const double *W, const double *lam,
+                        double *phibar, double *Ubar, double *Vbar, double *Wbar)
+{
+    if (m)
+        rhs_vjp_nu(g, m, s, phi, U, V, W, lam, phibar, Ubar, Vbar, Wbar);
+    else
+        orc_rhs_vjp(g, s, phi, U, V, W, lam, phibar, Ubar, Vbar, Wbar);
+}
+
+/* orc_rhs_vjp on a non-uniform mesh (widths and eps_mode as orc_rhs_nu) */
+void orc_rhs_vjp_nu(const orc_grid *g, const double *hx, const double *hy, const double *hz,
+                    int eps_mode, double s, const double *phi, const double *U, const double *V,
+                    const double *W, const double *lam, double *phibar, double *Ubar,
+                    double *Vbar, double *Wbar)
+{
+    const orc_mesh m = {{hx, hy, hz}, eps_mode};
+    rhs_vjp_nu(g, &m, s, phi, U, V, W, lam, phibar, Ubar, Vbar, Wbar);
+}
+
+static void adjoint_impl(const orc_grid *g, const orc_mesh *mesh, int scheme, double dt,
+                         double t, int vel_mode, double vel_T, const double *phi, const double *U,
+                         const double *V, const double *W, double *lam, double *Ubar, double *Vbar,
+                         double *Wbar);
+
 /* Adjoint of one step of orc_step (FP64): on entry lam holds dL/dphi_{n+1}; on exit dL/dphi_n.
  * Ubar/Vbar/Wbar (may be NULL) accumulate dL/dU0 etc. for u = u0 s(t). */
 void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int vel_mode,
                       double vel_T, const double *phi, const double *U, const double *V,
                       const double *W, double *lam, double *Ubar, double *Vbar, double *Wbar)
+{
+    adjoint_impl(g, NULL, scheme, dt, t, vel_mode, vel_T, phi, U, V, W, lam, Ubar, Vbar, Wbar);
+}
+
+/* orc_adjoint_step on a non-uniform mesh (widths and eps_mode as orc_rhs_nu) */
+void orc_adjoint_step_nu(const orc_grid *g, const double *hx, const double *hy, const double *hz,
+                         int eps_mode, int scheme, double dt, double t, int vel_mode,
+                         double vel_T, const double *phi, const double *U, const double *V,
+                         const double *W, double *lam, double *Ubar, double *Vbar, double *Wbar)
+{
+    const orc_mesh m = {{hx, hy, hz}, eps_mode};
+    adjoint_impl(g, &m, scheme, dt, t, vel_mode, vel_T, phi, U, V, W, lam, Ubar, Vbar, Wbar);
+}
+
+static void adjoint_impl(const orc_grid *g, const orc_mesh *mesh, int scheme, double dt,
+                         double t, int vel_mode, double vel_T, const double *phi, const double *U,
+                         const double *V, const double *W, double *lam, double *Ubar, double *Vbar,
+                         double *Wbar)
 {
     const int64_t N = ncell(g);
     double *kb = malloc(sizeof(double) * N);
@@ -598,7 +715,8 @@ void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int ve
     double *out = malloc(sizeof(double) * N);
     if (scheme == 1) {
         for (int64_t c = 0; c < N; ++c) kb[c] = dt * lam[c];
-        orc_rhs_vjp(g, time_factor(vel_mode, vel_T, t), phi, U, V, W, kb, yb, Ubar, Vbar, Wbar);
+        rhs_vjp_any(g, mesh, time_factor(vel_mode, vel_T, t), phi, U, V, W, kb, yb, Ubar, Vbar,
+                    Wbar);
         for (int64_t c = 0; c < N; ++c) lam[c] += yb[c];
         free(kb);
         free(yb);
@@ -651,7 +769,7 @@ void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int ve
             y[s][c] = v;
         }
         if (s < ns - 1) /* the last slope enters no stage input */
-            orc_rhs(g, time_factor(vel_mode, vel_T, t + cs[s] * dt), y[s], U, V, W, kk[s]);
+            rhs_any(g, mesh, time_factor(vel_mode, vel_T, t + cs[s] * dt), y[s], U, V, W, kk[s]);
     }
     /* reverse sweep over the stages, newest first */
     for (int64_t c = 0; c < N; ++c) out[c] = lam[c];
@@ -663,8 +781,8 @@ void orc_adjoint_step(const orc_grid *g, int scheme, double dt, double t, int ve
             for (int i = s + 1; i < ns; ++i) v += a[i][s] * ybar[i][c];
             kb[c] = dt * v;
         }
-        orc_rhs_vjp(g, time_factor(vel_mode, vel_T, t + cs[s] * dt), y[s], U, V, W, kb, ybar[s],
-                    Ubar, Vbar, Wbar);
+        rhs_vjp_any(g, mesh, time_factor(vel_mode, vel_T, t + cs[s] * dt), y[s], U, V, W, kb,
+                    ybar[s], Ubar, Vbar, Wbar);
     }
     /* every stage input is phi + (something), so phibar collects all the ybar */
     for (int64_t c = 0; c < N; ++c) {
