@@ -160,9 +160,10 @@ size_t phasefield_noalloc_scratch_bytes(void);
  * lam = dL/dphi_n (in place). gu, gv, gw (may each be NULL to skip) ACCUMULATE
  * dL/du0 etc. (+=); on a walled axis the wall face's entry (index 0) gets nothing, since the
  * step ignores the velocity stored there. The stage inputs of the forward step are recomputed
- * from phi_n. Allocates three more field-sized scratch buffers on first use.
- * Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned), PF_ERR_UNSUPPORTED (a handle with
- * a non-uniform mesh), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * from phi_n. Allocates three more field-sized scratch buffers on first use. On a non-uniform
+ * mesh (phasefield_set_spacing) it is the transpose of that mesh's step, one thread per cell
+ * (one reverse stage per launch). Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned),
+ * PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
                                   const void *w, double t_n, void *lam, void *gu, void *gv,
                                   void *gw, void *hip_stream);
@@ -180,7 +181,7 @@ pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u
  * of recomputing them (phasefield_adjoint_step_stages). Stream-ordered on hip_stream, no
  * synchronisation, no graph. Errors: PF_ERR_INVALID (null or misaligned phi, u, v, w or a stage
  * buffer the scheme needs, misaligned phi_next, coinciding buffers, non-finite t),
- * PF_ERR_UNSUPPORTED (a handle with a non-uniform mesh), PF_ERR_DEVICE. */
+ * PF_ERR_DEVICE. */
 pf_status phasefield_step_stages(pf_solver *s, void *phi, void *phi_next, const void *u,
                                  const void *v, const void *w, double t, void *y2, void *y3,
                                  void *y4, void *hip_stream);
@@ -211,8 +212,9 @@ pf_status phasefield_adjoint_step_stages(pf_solver *s, const void *phi_n, const 
  * to; the maximum over the axes longer than one cell), averaged onto each face. From then on
  * phasefield_step runs every scheme through the per-stage kernel in its non-uniform form (no
  * fused sweeps), phasefield_reduce returns
- * sum(phi * cell volume) (axes of one cell carry no volume), and phasefield_adjoint_step and
- * phasefield_autotune return PF_ERR_UNSUPPORTED. The velocity on the faces must be discretely
+ * sum(phi * cell volume) (axes of one cell carry no volume), phasefield_adjoint_step (and the
+ * stage-keeping pair) take the transpose of this mesh's step, and phasefield_autotune returns
+ * PF_ERR_UNSUPPORTED. The velocity on the faces must be discretely
  * divergence-free on this mesh, sum_a (u_a[+] - u_a[-]) / h_a = 0. All three NULL returns the
  * handle to the uniform mesh of p->dx. Synchronises the device (queued work may still read the
  * previous tables). Errors: PF_ERR_INVALID (NULL handle, some but not all widths NULL, a width

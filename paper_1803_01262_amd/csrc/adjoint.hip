@@ -296,6 +296,106 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     }
 }
 
+// Non-uniform mesh form of the gather above (a.nu set), one thread per cell: the same steps with
+// the mesh's per-axis coefficients, read from the forward's tables at the wrapped or mirrored
+// index of each cell: the flux cotangent on the low face of cell X is kap[X-e] / h[X-e] -
+// kap[X] / h[X]; the diffusive coefficient of that face gamma eps_face / (distance between the
+// two cells' centres), eps_face the mean of the two cells' eps (mode 1: eps of a cell ~ its
+// largest width over the axes longer than one cell); the gradient of cell X divides by the
+// distance between its two neighbours' centres, and its transpose gathers
+// gbar[c - e] / span[c - e] - gbar[c + e] / span[c + e]. Across a wall the mirror reads make the
+// wall face's flux cotangent vanish and a ghost's gradient cotangent the negative of its
+// partner's, as in the uniform form (the tables are mirror-symmetric).
+template <typename T>
+__global__ void __launch_bounds__(256) adjoint_stage_nu_kernel(AdjArgs<T> a)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= a.nx || j >= a.ny) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    auto mx = [&](int v) { return (a.walls & 1) ? reflectn(v, nx) : wrapn(v, nx); };
+    auto my = [&](int v) { return (a.walls & 2) ? reflectn(v, ny) : wrapn(v, ny); };
+    auto mz = [&](int v) { return (a.walls & 4) ? reflectn(v, nz) : wrapn(v, nz); };
+    auto idx = [&](int di, int dj, int dk) -> size_t {
+        return ((size_t)mz(k + dk) * ny + my(j + dj)) * nx + mx(i + di);
+    };
+    auto Y = [&](int di, int dj, int dk) -> T { return a.y[idx(di, dj, dk)]; };
+    auto K = [&](int di, int dj, int dk) -> T { return a.kap_scale * a.kap_in[idx(di, dj, dk)]; };
+    // column col of the table of axis ax at the cell (di, dj, dk)
+    auto tab = [&](int ax, int di, int dj, int dk, int col) -> T {
+        const int m = ax == 0 ? mx(i + di) : (ax == 1 ? my(j + dj) : mz(k + dk));
+        return a.nu[ax][(size_t)m * kNuCols + col];
+    };
+    // largest width of a cell over the axes longer than one cell (a one-cell axis has width 0)
+    auto wmax = [&](int di, int dj, int dk) -> T {
+        return fmax(tab(0, di, dj, dk, kNuWidth), fmax(tab(1, di, dj, dk, kNuWidth), tab(2, di, dj, dk, kNuWidth)));
+    };
+    // cotangent of the flux on the low ax-face of cell (di, dj, dk)
+    auto Fb = [&](int di, int dj, int dk, int ax) -> T {
+        const int ex = ax == 0, ey = ax == 1, ez = ax == 2;
+        return K(di - ex, dj - ey, dk - ez) * tab(ax, di - ex, dj - ey, dk - ez, kNuInvW) -
+               K(di, dj, dk) * tab(ax, di, dj, dk, kNuInvW);
+    };
+    // diffusive coefficient of the low ax-face of cell (di, dj, dk)
+    auto gef = [&](int di, int dj, int dk, int ax) -> T {
+        const int ex = ax == 0, ey = ax == 1, ez = ax == 2;
+        const T d = tab(ax, di, dj, dk, kNuInvDist);
+        if (a.nu_eps_mode == 1)
+            return a.nu_ge * T(0.5) * (wmax(di - ex, dj - ey, dk - ez) + wmax(di, dj, dk)) * d;
+        return a.nu_ge * d;
+    };
+    auto cell = [&](int di, int dj, int dk, T gb[3], T& local) {
+        const T p = Y(di, dj, dk);
+        T g[3];
+        g[0] = (Y(di + 1, dj, dk) - Y(di - 1, dj, dk)) * tab(0, di, dj, dk, kNuInvSpan);
+        g[1] = (Y(di, dj + 1, dk) - Y(di, dj - 1, dk)) * tab(1, di, dj, dk, kNuInvSpan);
+        g[2] = (Y(di, dj, dk + 1) - Y(di, dj, dk - 1)) * tab(2, di, dj, dk, kNuInvSpan);
+        T qb[3];
+        qb[0] = -a.nu_hg * (Fb(di, dj, dk, 0) + Fb(di + 1, dj, dk, 0));
+        qb[1] = -a.nu_hg * (Fb(di, dj, dk, 1) + Fb(di, dj + 1, dk, 1));
+        qb[2] = -a.nu_hg * (Fb(di, dj, dk, 2) + Fb(di, dj, dk + 1, 2));
+        local = adj_cell(p, g, qb, a.delta2, gb);
+    };
+
+    const size_t c = idx(0, 0, 0);
+    const T yc = a.y[c];
+    T gbc[3], local;
+    cell(0, 0, 0, gbc, local);
+    T ybar = local;
+    const T* vel[3] = {a.U, a.V, a.W};
+    T* velbar[3] = {a.gU, a.gV, a.gW};
+    for (int ax = 0; ax < 3; ++ax) {
+        const int ex = ax == 0, ey = ax == 1, ez = ax == 2;
+        const T fb_lo = Fb(0, 0, 0, ax);
+        const T fb_hi = Fb(ex, ey, ez, ax);
+        const T u_lo = vel[ax][c];
+        const T u_hi = vel[ax][idx(ex, ey, ez)];
+        ybar = fma(fb_lo, fma(-a.hs, u_lo, gef(0, 0, 0, ax)), ybar);
+        ybar = fma(fb_hi, fma(-a.hs, u_hi, -gef(ex, ey, ez, ax)), ybar);
+        if (velbar[ax]) velbar[ax][c] = fma(-a.hs * (Y(-ex, -ey, -ez) + yc), fb_lo, velbar[ax][c]);
+        T gbm[3], gbp[3], dummy;
+        cell(-ex, -ey, -ez, gbm, dummy);
+        cell(ex, ey, ez, gbp, dummy);
+        ybar = fma(gbm[ax], tab(ax, -ex, -ey, -ez, kNuInvSpan), ybar);
+        ybar = fma(-gbp[ax], tab(ax, ex, ey, ez, kNuInvSpan), ybar);
+    }
+    const T lb = a.lam_out ? a.lam_base[c] : T(0), lp = a.kap_out ? a.lamp[c] : T(0);
+    if (a.lam_out) a.lam_out[c] = lb + ybar;
+    if (a.kap_out) a.kap_out[c] = fma(a.ka, ybar, a.kb * lp);
+}
+
+template <typename T>
+hipError_t launch_adjoint_stage_nu(const AdjArgs<T>& a, hipStream_t st)
+{
+    if (!a.nu[0] || !a.nu[1] || !a.nu[2]) return hipErrorInvalidValue;
+    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.nz);
+    hipLaunchKernelGGL(adjoint_stage_nu_kernel<T>, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+template hipError_t launch_adjoint_stage_nu<float>(const AdjArgs<float>&, hipStream_t);
+template hipError_t launch_adjoint_stage_nu<double>(const AdjArgs<double>&, hipStream_t);
+
 template <typename T>
 hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st)
 {

@@ -748,8 +748,8 @@ extern "C" pf_status phasefield_step(pf_solver* s, void* phi, const void* u, con
 // launches with the stage outputs directed into the caller's buffers; an RK4 step of a fused
 // variant (no walls; FP64 from 176^3 cells, where the fused sweeps overtake the per-stage
 // launches) runs its two sweeps, each storing its middle value (y2, y4; sweep A also writes y3),
-// when out of place, and in place sweep A then two per-stage launches for y4 and the new phi.
-// Every form rounds alike, so the new phi and the stages are bit-identical to those of
+// when out of place, and in place sweep A then two per-stage launches for y4 and the new phi;
+// on a non-uniform mesh the per-stage launches of that mesh's kernel. Every form rounds alike, so the new phi and the stages are bit-identical to those of
 // phasefield_step and of the adjoint's own recompute.
 template <typename T>
 static hipError_t step_stages_impl(pf_solver* s, const T* phi, T* phi_next, const T* U,
@@ -761,35 +761,36 @@ static hipError_t step_stages_impl(pf_solver* s, const T* phi, T* phi_next, cons
     T* acc = (T*)s->acc;
     const int v = s->variant;
     const double sh = time_factor(p, t + 0.5 * dt);
+    const NuMesh* nu = s->nu.on() ? &s->nu : nullptr;
     hipError_t e;
     if (p.scheme == PF_EULER) {
         if (phi_next == phi)  // in place: through the accumulator, as the step does
             return enqueue_step<T>(p, v, phi_next, U, V, W, (T*)s->ya, (T*)s->yb, acc, t, st,
-                                   nullptr);
+                                   nu);
         return run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, nullptr, phi, nullptr,
-                                             phi_next, 0.0, dt, U, V, W), st);
+                                             phi_next, 0.0, dt, U, V, W, nu), st);
     }
     if (p.scheme == PF_RK2) {
         e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, phi, nullptr, y2, nullptr,
-                                          0.5 * dt, 0.0, U, V, W), st);
+                                          0.5 * dt, 0.0, U, V, W, nu), st);
         if (e != hipSuccess) return e;
         return run_stage<T>(v, make_stage<T>(p, sh, y2, nullptr, phi, nullptr, phi_next, 0.0, dt,
-                                             U, V, W), st);
+                                             U, V, W, nu), st);
     }
     if (p.scheme == PF_RK3) {
         constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0;
         e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, phi, phi, y2, acc, dt * g1,
-                                          dt * (g1 + z2), U, V, W), st);
+                                          dt * (g1 + z2), U, V, W, nu), st);
         if (e != hipSuccess) return e;
         e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t + g1 * dt), y2, acc, nullptr, y3,
-                                          nullptr, dt * g2, 0.0, U, V, W), st);
+                                          nullptr, dt * g2, 0.0, U, V, W, nu), st);
         if (e != hipSuccess) return e;
         return run_stage<T>(v, make_stage<T>(p, time_factor(p, t + (g1 + g2 + z2) * dt), y3,
-                                             nullptr, acc, nullptr, phi_next, 0.0, dt * g3, U, V, W),
+                                             nullptr, acc, nullptr, phi_next, 0.0, dt * g3, U, V, W, nu),
                             st);
     }
     const long long cells = (long long)p.n[0] * p.n[1] * p.n[2];
-    const bool fused = variant_is_fused(p.dtype, v) && wall_mask(p) == 0 &&
+    const bool fused = !nu && variant_is_fused(p.dtype, v) && wall_mask(p) == 0 &&
                        (p.dtype == PF_F32 || cells >= 176LL * 176 * 176);
     if (fused && phi_next != phi) {
         // out of place: the two sweeps of the step, the accumulator in phi_next (sweep B writes
@@ -808,16 +809,16 @@ static hipError_t step_stages_impl(pf_solver* s, const T* phi, T* phi_next, cons
         e = run_fused_sweep<T>(v, a, false, st);
     } else {
         e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t), phi, phi, phi, y2, acc, 0.5 * dt,
-                                          dt / 6.0, U, V, W), st);
+                                          dt / 6.0, U, V, W, nu), st);
         if (e == hipSuccess)
             e = run_stage<T>(v, make_stage<T>(p, sh, y2, phi, acc, y3, acc, 0.5 * dt, dt / 3.0, U, V,
-                                              W), st);
+                                              W, nu), st);
     }
     if (e == hipSuccess)
-        e = run_stage<T>(v, make_stage<T>(p, sh, y3, phi, acc, y4, acc, dt, dt / 3.0, U, V, W), st);
+        e = run_stage<T>(v, make_stage<T>(p, sh, y3, phi, acc, y4, acc, dt, dt / 3.0, U, V, W, nu), st);
     if (e == hipSuccess)
         e = run_stage<T>(v, make_stage<T>(p, time_factor(p, t + dt), y4, nullptr, acc, nullptr,
-                                          phi_next, 0.0, dt / 6.0, U, V, W), st);
+                                          phi_next, 0.0, dt / 6.0, U, V, W, nu), st);
     return e;
 }
 
@@ -834,8 +835,6 @@ extern "C" pf_status phasefield_step_stages(pf_solver* s, void* phi, void* phi_n
     if (!phi_next) phi_next = phi;
     if ((st = check_field_ptr(phi_next, "phi_next")) != PF_OK) return st;
     if (!std::isfinite(t)) return fail(PF_ERR_INVALID, "t is not finite");
-    if (s->nu.on())
-        return fail(PF_ERR_UNSUPPORTED, "stage inputs are kept for uniform meshes only (no adjoint)");
     void* stages[3] = {y2, y3, y4};
     const int ns = scheme_stage_count(s->p.scheme);
     for (int k = 0; k < ns; ++k) {

@@ -13,7 +13,7 @@ template <typename T>
 static AdjArgs<T> make_adj(const pf_params& p, double svel, const T* y, const T* kap_in,
                            double kap_scale, const T* lam_base, T* lam_out, const T* lamp,
                            T* kap_out, double kb, double ka, T* gU, T* gV, T* gW, const T* U,
-                           const T* V, const T* W)
+                           const T* V, const T* W, const NuMesh* nu)
 {
     AdjArgs<T> a;
     a.y = y;
@@ -41,6 +41,12 @@ static AdjArgs<T> make_adj(const pf_params& p, double svel, const T* y, const T*
     a.hg = (T)(0.5 * p.gamma);
     a.hs = (T)(0.5 * svel);
     a.delta2 = (T)(p.delta * p.delta);
+    if (nu) {  // the forward's coefficients of the mesh (make_stage)
+        for (int ax = 0; ax < 3; ++ax) a.nu[ax] = (const T*)nu->tab[ax];
+        a.nu_ge = (T)(nu->eps_mode == 1 ? p.gamma * p.eps / p.dx : p.gamma * p.eps);
+        a.nu_hg = (T)(0.5 * p.gamma);
+        a.nu_eps_mode = nu->eps_mode;
+    }
     return a;
 }
 
@@ -122,7 +128,10 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     if (tile < 0) tile = adjoint_default_tile(p.n[0], p.n[1], p.n[2]);
     const size_t vlen = std::strlen(vname);
     const bool big = vlen > 4 && std::strcmp(vname + vlen - 4, "_big") == 0;
+    // a non-uniform mesh: its own forward and adjoint kernels (one form each)
+    const NuMesh* nu = s->nu.on() ? &s->nu : nullptr;
     auto adj = [&](const AdjArgs<T>& a, hipStream_t hs) {
+        if (nu) return launch_adjoint_stage_nu<T>(a, hs);
         return plain ? launch_adjoint_stage_global<T>(a, hs)
                      : launch_adjoint_stage<T>(a, tile, kz, big, hs);
     };
@@ -130,7 +139,7 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     if (p.scheme == PF_EULER) {
         // phi' = phi + dt f(phi):  lam_n = lam' + (df/dphi)^T (dt lam')
         e = adj(make_adj<T>(p, time_factor(p, t), phi, lam, dt, lam, L, nullptr,
-                                                nullptr, 0.0, 0.0, gU, gV, gW, U, V, W), st);
+                                                nullptr, 0.0, 0.0, gU, gV, gW, U, V, W, nu), st);
         if (e == hipSuccess) e = launch_copy<T>(lam, L, s->N, st);
         return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
     }
@@ -153,20 +162,20 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
             e = hipSuccess;
         } else {
             e = run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, phi, (T*)y2, A, dt * g1,
-                                                       dt * (g1 + z2), U, V, W), st);
+                                                       dt * (g1 + z2), U, V, W, nu), st);
             if (e == hipSuccess)
                 e = run_stage<T>(s->variant, make_stage<T>(p, s2, y2, A, nullptr, (T*)y3, nullptr,
-                                                           dt * g2, 0.0, U, V, W), st);
+                                                           dt * g2, 0.0, U, V, W, nu), st);
         }
         if (e == hipSuccess)
             e = adj(make_adj<T>(p, s3, y3, lam, 0.75 * dt, lam, L, lam, Ka, 0.0, g2 * dt, gU, gV,
-                                gW, U, V, W), st);
+                                gW, U, V, W, nu), st);
         if (e == hipSuccess)
             e = adj(make_adj<T>(p, s2, y2, Ka, 1.0, L, L, L, Kb, 0.25 * dt, g1 * dt, gU, gV, gW, U,
-                                V, W), st);
+                                V, W, nu), st);
         if (e == hipSuccess)
             e = adj(make_adj<T>(p, s1, phi, Kb, 1.0, L, lam, nullptr, nullptr, 0.0, 0.0, gU, gV,
-                                gW, U, V, W), st);
+                                gW, U, V, W, nu), st);
         return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
     }
     if (p.scheme == PF_RK2) {
@@ -177,13 +186,13 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         const double s1 = time_factor(p, t), s2 = time_factor(p, t + 0.5 * dt);
         e = stages ? hipSuccess
                    : run_stage<T>(s->variant, make_stage<T>(p, s1, phi, phi, nullptr, (T*)y2, nullptr,
-                                                            0.5 * dt, 0.0, U, V, W), st);
+                                                            0.5 * dt, 0.0, U, V, W, nu), st);
         if (e == hipSuccess)
             e = adj(make_adj<T>(p, s2, y2, lam, dt, lam, L, lam, Ka, 0.0, 0.5 * dt, gU, gV, gW, U,
-                                V, W), st);
+                                V, W, nu), st);
         if (e == hipSuccess)
             e = adj(make_adj<T>(p, s1, phi, Ka, 1.0, L, lam, nullptr, nullptr, 0.0, 0.0, gU, gV,
-                                gW, U, V, W), st);
+                                gW, U, V, W, nu), st);
         return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
     }
     T* y2 = (T*)s->ya;
@@ -197,7 +206,7 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     // no accumulator output; FP64 adjoint step against three per-stage launches on 64x8 tiles:
     // 128^3 0.259 / 0.259 ms, 256^3 1.90 / 1.95, 512^3 14.98 / 15.38); on walled grids three
     // per-stage launches.
-    const bool fused_rc = variant_is_fused(p.dtype, v) && wall_mask(p) == 0;
+    const bool fused_rc = !nu && variant_is_fused(p.dtype, v) && wall_mask(p) == 0;
     const int vs = variant_is_fused(p.dtype, v) && !fused_rc ? stage_variant_index(p.dtype, "tiled_64x8") : v;
     if (stages) {
         y2 = (T*)stages[0];
@@ -210,12 +219,12 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
         a.out_acc = nullptr;
         e = run_fused_sweep<T>(v, a, false, st);
     } else {
-        e = run_stage<T>(vs, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt, 0.0, U, V, W), st);
+        e = run_stage<T>(vs, make_stage<T>(p, s1, phi, phi, nullptr, y2, nullptr, 0.5 * dt, 0.0, U, V, W, nu), st);
         if (e == hipSuccess)
-            e = run_stage<T>(vs, make_stage<T>(p, s2, y2, phi, nullptr, y3, nullptr, 0.5 * dt, 0.0, U, V, W), st);
+            e = run_stage<T>(vs, make_stage<T>(p, s2, y2, phi, nullptr, y3, nullptr, 0.5 * dt, 0.0, U, V, W, nu), st);
     }
     if (e == hipSuccess && !stages)
-        e = run_stage<T>(vs, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W), st);
+        e = run_stage<T>(vs, make_stage<T>(p, s2, y3, phi, nullptr, y4, nullptr, dt, 0.0, U, V, W, nu), st);
     // reverse stages: one per launch, or two per launch (adjoint_fused.hip, the same
     // arithmetic as the single stages below, bit for bit): (4, 3) writes L = lam' + ybar4 +
     // ybar3, kap2 into Kb and a copy of lam' into Ka (so that (2, 1) can write lam in place while
@@ -228,7 +237,8 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     const bool pair_auto = variant_is_fused(p.dtype, v) && p.dtype == PF_F64 &&
                            cells >= (size_t)192 * 192 * 192;
     const bool pair = (s->adjoint_form == 1 || (s->adjoint_form < 0 && pair_auto)) &&
-                      !field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T)) && wall_mask(p) == 0;
+                      !field_needs_big(p.n[0], p.n[1], p.n[2], sizeof(T)) && wall_mask(p) == 0 &&
+                      !nu;
     if (pair) {
         // a fused forward variant lends its tile shape (64x8 or 32x16) and fixed chunk length, if
         // it names one; otherwise 64x8 unless 64-wide tiles pad more columns, chunks per launch
@@ -250,16 +260,16 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     }
     if (e == hipSuccess)
         e = adj(make_adj<T>(p, s4, y4, lam, dt / 6.0, lam, L, lam, Ka, dt / 3.0,
-                                                dt, gU, gV, gW, U, V, W), st);
+                                                dt, gU, gV, gW, U, V, W, nu), st);
     if (e == hipSuccess)
         e = adj(make_adj<T>(p, s2, y3, Ka, 1.0, L, L, lam, Kb, dt / 3.0,
-                                                0.5 * dt, gU, gV, gW, U, V, W), st);
+                                                0.5 * dt, gU, gV, gW, U, V, W, nu), st);
     if (e == hipSuccess)
         e = adj(make_adj<T>(p, s2, y2, Kb, 1.0, L, L, lam, Ka, dt / 6.0,
-                                                0.5 * dt, gU, gV, gW, U, V, W), st);
+                                                0.5 * dt, gU, gV, gW, U, V, W, nu), st);
     if (e == hipSuccess)
         e = adj(make_adj<T>(p, s1, phi, Ka, 1.0, L, lam, nullptr, nullptr, 0.0,
-                                                0.0, gU, gV, gW, U, V, W), st);
+                                                0.0, gU, gV, gW, U, V, W, nu), st);
     // the forward graph (if any) captured the stage buffers' old contents only; nothing to redo
     return e == hipSuccess ? PF_OK : hip_fail(e, "phasefield_adjoint_step");
 }
@@ -284,8 +294,6 @@ static pf_status adjoint_checks(pf_solver* s, const void* phi_n, const void* u, 
     for (const void* g : {gu, gv, gw})
         if (g && (((uintptr_t)g) & 15)) return fail(PF_ERR_INVALID, "gradient not 16-byte aligned");
     if (!std::isfinite(t_n)) return fail(PF_ERR_INVALID, "t_n is not finite");
-    if (s->nu.on())
-        return fail(PF_ERR_UNSUPPORTED, "the discrete adjoint is provided for uniform meshes only");
     return PF_OK;
 }
 

@@ -82,6 +82,12 @@ struct AdjArgs {
     // mirror ghost's gradient cotangent the exact negative of its partner's along the wall
     // normal, which is what the gather needs for the gradient's mirror read of the cell itself.
     int walls = 0;
+    // Non-uniform mesh (nu[0] set; the per-axis coefficient tables of the forward's NU form,
+    // NuCol columns per cell index): nu_ge = gamma eps (eps mode 0) or gamma eps / dx (mode 1,
+    // eps of a cell ~ its largest width), nu_hg = gamma / 2.
+    const T* nu[3] = {nullptr, nullptr, nullptr};
+    T nu_ge = 0, nu_hg = 0;
+    int nu_eps_mode = 0;
 };
 
 // Two reverse RK4 stages in one sweep (adjoint_fused.hip): stage H then stage L.
@@ -242,6 +248,8 @@ int adjoint_tile_index(int tx, int ty);               // -1 if that shape has no
 int adjoint_default_tile(int nx, int ny, int nz);
 template <typename T>
 hipError_t launch_adjoint_stage_global(const AdjArgs<T>& a, hipStream_t st);  // one thread per cell
+template <typename T>
+hipError_t launch_adjoint_stage_nu(const AdjArgs<T>& a, hipStream_t st);  // non-uniform mesh
 // Two reverse stages per launch (tile 0: 64x8, 1: 32x16; kz 0: chosen per launch). Arrays of
 // 4 GiB or more are refused (hipErrorInvalidValue): the caller runs single stages then.
 template <typename T>

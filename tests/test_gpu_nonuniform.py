@@ -7,6 +7,14 @@ periodic and walled, with eps fixed or tuned to the local mesh, steady and time-
 velocity, ragged multi-tile and one-plane grids, against oracle.step_nu: FP64 within 1e-12
 relative L-inf, FP32 storage within 1e-5 of the oracle's FP32-storage mode. Also: equal widths
 agree with the uniform kernels, the volume-weighted mass, graph replay, and the refusals.
+
+The adjoint step on these meshes (the plain vector-Jacobian product of the non-uniform step,
+pinned on the CPU in test_oracle_adjoint_nonuniform.py) against oracle.adjoint_step_nu for every
+scheme, periodic and walled axes, both eps rules, steady and time-varying velocity, one-plane
+grids and a fused handle: FP64 within 1e-12 relative L-inf for lambda and the three face
+gradients, FP32 storage within 1e-3 of the FP64 oracle; with the stage inputs kept by
+phasefield_step_stages bit for bit the recomputing adjoint's results, and the stored new phi bit
+for bit phasefield_step's.
 """
 import numpy as np
 import pytest
@@ -193,10 +201,6 @@ def test_nonuniform_mass_and_refusals(lib):
     want = oracle.reduce_nu(phi, hx=h[0], hy=h[1], hz=h[2])
     assert abs(m0[0] - want[0]) <= 1e-13 * want[0] and m0[1:] == want[1:]
     assert abs(m1[0] - m0[0]) <= 1e-13 * m0[0]
-    lam = torch.ones_like(g[0])
-    with pytest.raises(pf.PhaseFieldError) as ei:
-        s.adjoint_step(*g, 0.0, lam)
-    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
     with pytest.raises(pf.PhaseFieldError) as ei:
         s.autotune(reps=1)
     assert ei.value.status == pf.PF_ERR_UNSUPPORTED
@@ -208,3 +212,75 @@ def test_nonuniform_mass_and_refusals(lib):
     with pytest.raises(pf.PhaseFieldError):
         s.set_spacing(*h, eps_mode=2)
     s.close()
+
+
+F, T = False, True
+ADJ_CASES = [
+    # dtype, shape (nz, ny, nx), walls (x, y, z), eps_mode, scheme, vel_mode, variant (None: default)
+    ("f64", (12, 20, 70), (F, F, F), 0, "rk4", 0, None),
+    ("f64", (12, 20, 70), (F, F, F), 1, "rk4", 1, "fused_32x16"),  # per-stage on a fused handle
+    ("f64", (14, 18, 40), (T, F, T), 1, "rk4", 1, None),
+    ("f64", (14, 18, 40), (F, T, F), 0, "rk3", 1, None),
+    ("f64", (14, 18, 40), (T, T, T), 1, "rk2", 0, None),
+    ("f64", (9, 11, 7), (F, F, T), 1, "euler", 1, None),
+    ("f64", (1, 36, 50), (T, F, F), 1, "rk4", 1, None),            # one plane
+    ("f64", (10, 16, 130), (F, F, F), 1, "rk3", 0, "global"),
+    ("f32", (12, 20, 70), (F, F, F), 1, "rk4", 1, None),
+    ("f32", (14, 18, 40), (T, F, T), 0, "rk2", 0, None),
+]
+
+
+@pytest.mark.parametrize("dtype,shape,walls,eps_mode,scheme,vel_mode,vname", ADJ_CASES)
+def test_nonuniform_adjoint_matches_oracle(lib, dtype, shape, walls, eps_mode, scheme, vel_mode,
+                                           vname):
+    pf = lib
+    phi, U, V, W, h, hmax = nu_case(sum(shape) + 11, shape, walls=walls)
+    if dtype == "f32":
+        phi, U, V, W = (a.astype(np.float32).astype(np.float64) for a in (phi, U, V, W))
+    nz, ny, nx = shape
+    rng = np.random.default_rng(sum(shape))
+    lam = rng.standard_normal(shape)
+    dxref = 1.0 / max(shape)
+    eps = 1.1 * (dxref if eps_mode else hmax)
+    t, vel_T = 0.1, 0.7
+    kw = dict(dx=dxref, eps=eps, gamma=1.2, dt=stable_dt(h, eps, eps_mode, dxref, 1.2, nz),
+              delta=0.05 / dxref)
+    print("case", dtype, shape, walls, eps_mode, scheme, vel_mode, vname, flush=True)
+    ref = oracle.adjoint_step_nu(phi, U, V, W, lam, hx=h[0], hy=h[1], hz=h[2], t=t,
+                                 scheme=SCH[scheme], vel_mode=vel_mode, vel_T=vel_T,
+                                 eps_mode=eps_mode, walls=walls, **kw)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
+    names = [pf.phasefield_variant_name(kd, k) for k in range(pf.phasefield_variant_count(kd))]
+    s = pf.Solver((nx, ny, nz), scheme=scheme, walls=walls, dtype=dtype, vel_mode=vel_mode,
+                  vel_T=vel_T, variant=-1 if vname is None else names.index(vname), **kw)
+    s.set_spacing(*h, eps_mode=eps_mode)
+    g = [torch.tensor(a, dtype=tdt, device="cuda") for a in (phi, U, V, W)]
+    L = torch.tensor(lam, dtype=tdt, device="cuda")
+    grads = [torch.zeros_like(L) for _ in range(3)]
+    s.adjoint_step(*g, t, L, *grads)
+    # the same step keeping its stage inputs, and the adjoint reading them
+    ns = s.stage_count
+    ys = [torch.full_like(g[0], float("nan")) for _ in range(ns)]
+    phi1 = torch.full_like(g[0], float("nan"))
+    s.step_stages(g[0], *g[1:], t, *ys, phi_next=phi1)
+    phi_ref = g[0].clone()
+    s.step(phi_ref, *g[1:], t0=t, nsteps=1)
+    L1 = torch.tensor(lam, dtype=tdt, device="cuda")
+    grads1 = [torch.zeros_like(L) for _ in range(3)]
+    s.adjoint_step_stages(g[0], ys, *g[1:], t, L1, *grads1)
+    torch.cuda.synchronize()
+    s.close()
+    tol = TOL64 if dtype == "f64" else 1e-3
+    for k, (got, want) in enumerate(zip([L] + grads, ref)):
+        err = rel_linf(got.cpu().numpy().astype(np.float64), want)
+        print("output", k, "error", err, flush=True)
+        assert err <= tol, (k, err)
+    for a, w in enumerate(walls):  # the wall faces' velocity entries stay untouched
+        if w:
+            sl = [slice(None)] * 3
+            sl[2 - a] = 0
+            assert not grads[a][tuple(sl)].any()
+    assert torch.equal(phi1, phi_ref)
+    for x, y in zip([L] + grads, [L1] + grads1):
+        assert torch.equal(x, y)

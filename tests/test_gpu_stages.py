@@ -193,11 +193,4 @@ def test_stage_argument_refusals(lib):
         pf.phasefield_adjoint_step_stages(s.handle, s.params, g[0], y[0], None, y[2], *g[1:], 0.0,
                                           lam_t)
     assert ei.value.status == pf.PF_ERR_INVALID
-    s.set_spacing(np.full(8, dx), np.full(8, dx), np.full(8, dx))
-    with pytest.raises(pf.PhaseFieldError) as ei:
-        s.step_stages(g[0], *g[1:], 0.0, *y)
-    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
-    with pytest.raises(pf.PhaseFieldError) as ei:
-        s.adjoint_step_stages(g[0], y, *g[1:], 0.0, lam_t)
-    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
     s.close()
