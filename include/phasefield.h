@@ -161,8 +161,8 @@ size_t phasefield_noalloc_scratch_bytes(void);
  * dL/du0 etc. (+=); on a walled axis the wall face's entry (index 0) gets nothing, since the
  * step ignores the velocity stored there. The stage inputs of the forward step are recomputed
  * from phi_n. Allocates three more field-sized scratch buffers on first use. On a non-uniform
- * mesh (phasefield_set_spacing) it is the transpose of that mesh's step, one thread per cell
- * (one reverse stage per launch). Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned),
+ * mesh (phasefield_set_spacing) it is the transpose of that mesh's step (one reverse stage per
+ * launch). Errors: PF_ERR_INVALID (null phi_n/u/v/w/lam, misaligned),
  * PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_adjoint_step(pf_solver *s, const void *phi_n, const void *u, const void *v,
                                   const void *w, double t_n, void *lam, void *gu, void *gv,

@@ -14,6 +14,15 @@
 
 namespace pf {
 
+// Cotangent of a face's flux on a non-uniform mesh: kap of the low cell over its width minus kap
+// of the high cell over its width, both products rounded (no contraction in this build), so that
+// across a wall, where the mirror makes the two products equal, it is exactly zero.
+template <typename T>
+__device__ __forceinline__ T nu_face(T k_lo, T iw_lo, T k_hi, T iw_hi)
+{
+    return k_lo * iw_lo - k_hi * iw_hi;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
 {
@@ -88,7 +97,10 @@ __global__ void __launch_bounds__(256) adjoint_stage_kernel(AdjArgs<T> a)
 // kernel (buffer descriptors; BIG for arrays of 4 GiB or more).
 // WALLS: the form that reads the stage input and the cotangent through mirror indices on the
 // walled axes of a.walls.
-template <typename T, int TX, int TY, bool BIG, bool WALLS = false>
+// NU: the non-uniform mesh form (a.nu set; arrays under 4 GiB), the steps of
+// adjoint_stage_nu_kernel in the same order: the coefficients of the tile's columns and rows sit
+// in LDS (mapped like the loads), those of the z planes are uniform loads per iteration.
+template <typename T, int TX, int TY, bool BIG, bool WALLS = false, bool NU = false>
 __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int tiles_x, int tiles_y,
                                                                int kz)
 {
@@ -98,10 +110,14 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     constexpr int GYS = TX * (TY + 2);
     constexpr int NL = (PS + NT - 1) / NT;
     static_assert(NT >= 2 * TX + 2 * TY, "halo ring needs one thread per halo cell");
+    static_assert(!NU || NT >= PW + PH, "one thread per coefficient column and row");
+    static_assert(!(NU && BIG), "the non-uniform form takes arrays under 4 GiB");
     __shared__ T sy[3 * PS];
     __shared__ T sk[3 * PS];
     __shared__ T sgx[2 * GXS];
     __shared__ T sgy[2 * GYS];
+    __shared__ T scx[NU ? kNuCols * PW : 1];  // column-major per coefficient
+    __shared__ T scy[NU ? kNuCols * PH : 1];
 
     int b = xcd_tile_order(blockIdx.x, gridDim.x);
     const int ti = b % tiles_x;
@@ -125,6 +141,22 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     auto mapx = [&](int v) { return WALLS && wx ? reflectn(v, nx) : wrapn(v, nx); };
     auto mapy = [&](int v) { return WALLS && wy ? reflectn(v, ny) : wrapn(v, ny); };
     auto mapz = [&](int v) { return WALLS && wz ? reflectz(v, nz) : wrapz(v, nz); };
+
+    if constexpr (NU) {  // read by the first iteration, after its barriers
+        if (tid < PW) {
+            const T* r = a.nu[0] + (size_t)mapx(i0 - 2 + tid) * kNuCols;
+#pragma unroll
+            for (int c = 0; c < kNuCols; ++c) scx[c * PW + tid] = r[c];
+        } else if (tid < PW + PH) {
+            const int t = tid - PW;
+            const T* r = a.nu[1] + (size_t)mapy(j0 - 2 + t) * kNuCols;
+#pragma unroll
+            for (int c = 0; c < kNuCols; ++c) scy[c * PH + t] = r[c];
+        }
+    }
+    auto CX = [&](int col, int c) -> T { return scx[col * PW + c]; };
+    auto CY = [&](int col, int r) -> T { return scy[col * PH + r]; };
+    auto CZ = [&](int col, int kk) -> T { return a.nu[2][(size_t)mapz(kk) * kNuCols + col]; };
 
     unsigned loff[NL];
     int lpos[NL];
@@ -188,6 +220,23 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         qb[2] = -hg * (adj_face(K0[q], K1[q], inv_dx) + adj_face(K1[q], K2[q], inv_dx));
         return adj_cell(Y1[q], g, qb, d2, gb);
     };
+    // the same on a non-uniform mesh: the cell at LDS row r, column c; sz1 the inverse gradient
+    // span of plane k+1, iz0..iz2 the inverse widths of planes k, k+1, k+2
+    auto cell_nu = [&](const T* Y0, const T* Y1, const T* Y2, const T* K0, const T* K1,
+                       const T* K2, int q, int r, int c, T sz1, T iz0, T iz1, T iz2, T gb[3]) -> T {
+        T g[3], qb[3];
+        g[0] = (Y1[q + 1] - Y1[q - 1]) * CX(kNuInvSpan, c);
+        g[1] = (Y1[q + PW] - Y1[q - PW]) * CY(kNuInvSpan, r);
+        g[2] = (Y2[q] - Y0[q]) * sz1;
+        const T wxm = CX(kNuInvW, c - 1), wxc = CX(kNuInvW, c), wxp = CX(kNuInvW, c + 1);
+        const T wym = CY(kNuInvW, r - 1), wyc = CY(kNuInvW, r), wyp = CY(kNuInvW, r + 1);
+        qb[0] = -a.nu_hg * (nu_face(K1[q - 1], wxm, K1[q], wxc) + nu_face(K1[q], wxc, K1[q + 1], wxp));
+        qb[1] = -a.nu_hg *
+                (nu_face(K1[q - PW], wym, K1[q], wyc) + nu_face(K1[q], wyc, K1[q + PW], wyp));
+        qb[2] = -a.nu_hg * (nu_face(K0[q], iz0, K1[q], iz1) + nu_face(K1[q], iz1, K2[q], iz2));
+        return adj_cell(Y1[q], g, qb, d2, gb);
+    };
+    const int h_r = h_o >= 0 ? h_o / PW : 0, h_c = h_o >= 0 ? h_o - h_r * PW : 0;
 
     fetch(k0 - 2);
     commit(0);
@@ -241,21 +290,87 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         const T *Y0 = sy + s0 * PS, *Y1 = sy + s1 * PS, *Y2 = sy + s2 * PS;
         const T *K0 = sk + s0 * PS, *K1 = sk + s1 * PS, *K2 = sk + s2 * PS;
         T gb[3];
-        const T loc_next = cell(Y0, Y1, Y2, K0, K1, K2, o, gb);
+        T loc_next, fbz_next;  // fbz_next: the z-face between planes k and k+1
+        T iz0 = T(0), iz1 = T(0), iz2 = T(0), sz1 = T(0);
+        if constexpr (NU) {
+            iz0 = CZ(kNuInvW, k);
+            iz1 = CZ(kNuInvW, k + 1);
+            iz2 = CZ(kNuInvW, k + 2);
+            sz1 = CZ(kNuInvSpan, k + 1);
+            loc_next = cell_nu(Y0, Y1, Y2, K0, K1, K2, o, ty + 2, tx + 2, sz1, iz0, iz1, iz2, gb);
+            fbz_next = nu_face(K0[o], iz0, K1[o], iz1);
+        } else {
+            loc_next = cell(Y0, Y1, Y2, K0, K1, K2, o, gb);
+            fbz_next = adj_face(K0[o], K1[o], inv_dx);
+        }
         sgx[q1 * GXS + ty * GXW + tx + 1] = gb[0];
         sgy[q1 * GYS + (ty + 1) * TX + tx] = gb[1];
         const T gz_next = gb[2];
         if (h_o >= 0) {
             T hb[3];
-            (void)cell(Y0, Y1, Y2, K0, K1, K2, h_o, hb);
+            if constexpr (NU)
+                (void)cell_nu(Y0, Y1, Y2, K0, K1, K2, h_o, h_r, h_c, sz1, iz0, iz1, iz2, hb);
+            else
+                (void)cell(Y0, Y1, Y2, K0, K1, K2, h_o, hb);
             if (h_axis == 0)
                 sgx[q1 * GXS + h_dst] = hb[0];
             else
                 sgy[q1 * GYS + h_dst] = hb[1];
         }
-        const T fbz_next = adj_face(K0[o], K1[o], inv_dx);  // z-face between planes k and k+1
         if (zplane && active && a.gW) stg<T>(a.gW + ok1, col, fma(-hs * (Y0[o] + Y1[o]), fbz_next, gw));
-        if (out_plane && active) {
+        if constexpr (NU) {
+            if (out_plane && active) {
+                const int r = ty + 2, c = tx + 2;
+                // diffusive coefficients of the six faces: gamma eps_face / centre distance
+                const T dzl = CZ(kNuInvDist, k), dzh = CZ(kNuInvDist, k + 1);
+                T exl, exh, eyl, eyh, ezl, ezh;
+                if (a.nu_eps_mode == 1) {  // eps of a cell ~ its largest width
+                    const T wx = CX(kNuWidth, c), wy = CY(kNuWidth, r), wz = CZ(kNuWidth, k);
+                    const T mc = fmax(wx, fmax(wy, wz));
+                    const T hh = a.nu_ge * T(0.5);
+                    exl = hh * (fmax(CX(kNuWidth, c - 1), fmax(wy, wz)) + mc) * CX(kNuInvDist, c);
+                    exh = hh * (mc + fmax(CX(kNuWidth, c + 1), fmax(wy, wz))) * CX(kNuInvDist, c + 1);
+                    eyl = hh * (fmax(wx, fmax(CY(kNuWidth, r - 1), wz)) + mc) * CY(kNuInvDist, r);
+                    eyh = hh * (mc + fmax(wx, fmax(CY(kNuWidth, r + 1), wz))) * CY(kNuInvDist, r + 1);
+                    ezl = hh * (fmax(wx, fmax(wy, CZ(kNuWidth, k - 1))) + mc) * dzl;
+                    ezh = hh * (mc + fmax(wx, fmax(wy, CZ(kNuWidth, k + 1)))) * dzh;
+                } else {
+                    exl = a.nu_ge * CX(kNuInvDist, c);
+                    exh = a.nu_ge * CX(kNuInvDist, c + 1);
+                    eyl = a.nu_ge * CY(kNuInvDist, r);
+                    eyh = a.nu_ge * CY(kNuInvDist, r + 1);
+                    ezl = a.nu_ge * dzl;
+                    ezh = a.nu_ge * dzh;
+                }
+                T ybar = loc_cur;
+                // x faces
+                const T wxm = CX(kNuInvW, c - 1), wxc = CX(kNuInvW, c), wxp = CX(kNuInvW, c + 1);
+                T lo = nu_face(K0[o - 1], wxm, K0[o], wxc), hi = nu_face(K0[o], wxc, K0[o + 1], wxp);
+                ybar = fma(lo, fma(-hs, u0, exl), ybar);
+                ybar = fma(hi, fma(-hs, u1, -exh), ybar);
+                if (a.gU) stg<T>(a.gU + ok, col, fma(-hs * (Y0[o - 1] + Y0[o]), lo, gu));
+                const T* GX = sgx + q0 * GXS + ty * GXW + tx;
+                ybar = fma(GX[0], CX(kNuInvSpan, c - 1), ybar);
+                ybar = fma(-GX[2], CX(kNuInvSpan, c + 1), ybar);
+                // y faces
+                const T wym = CY(kNuInvW, r - 1), wyc = CY(kNuInvW, r), wyp = CY(kNuInvW, r + 1);
+                lo = nu_face(K0[o - PW], wym, K0[o], wyc);
+                hi = nu_face(K0[o], wyc, K0[o + PW], wyp);
+                ybar = fma(lo, fma(-hs, v0, eyl), ybar);
+                ybar = fma(hi, fma(-hs, v1, -eyh), ybar);
+                if (a.gV) stg<T>(a.gV + ok, col, fma(-hs * (Y0[o - PW] + Y0[o]), lo, gv));
+                const T* GY = sgy + q0 * GYS + ty * TX + tx;
+                ybar = fma(GY[0], CY(kNuInvSpan, r - 1), ybar);
+                ybar = fma(-GY[2 * TX], CY(kNuInvSpan, r + 1), ybar);
+                // z faces
+                ybar = fma(fbz_cur, fma(-hs, w0, ezl), ybar);
+                ybar = fma(fbz_next, fma(-hs, w1, -ezh), ybar);
+                ybar = fma(gz_prev, CZ(kNuInvSpan, k - 1), ybar);
+                ybar = fma(-gz_next, CZ(kNuInvSpan, k + 1), ybar);
+                if (a.lam_out) stg<T>(a.lam_out + ok, col, lb + ybar);
+                if (a.kap_out) stg<T>(a.kap_out + ok, col, fma(a.ka, ybar, a.kb * lp));
+            }
+        } else if (out_plane && active) {
             T ybar = loc_cur;
             // x faces
             T lo = adj_face(K0[o - 1], K0[o], inv_dx), hi = adj_face(K0[o], K0[o + 1], inv_dx);
@@ -334,8 +449,8 @@ __global__ void __launch_bounds__(256) adjoint_stage_nu_kernel(AdjArgs<T> a)
     // cotangent of the flux on the low ax-face of cell (di, dj, dk)
     auto Fb = [&](int di, int dj, int dk, int ax) -> T {
         const int ex = ax == 0, ey = ax == 1, ez = ax == 2;
-        return K(di - ex, dj - ey, dk - ez) * tab(ax, di - ex, dj - ey, dk - ez, kNuInvW) -
-               K(di, dj, dk) * tab(ax, di, dj, dk, kNuInvW);
+        return nu_face(K(di - ex, dj - ey, dk - ez), tab(ax, di - ex, dj - ey, dk - ez, kNuInvW),
+                       K(di, dj, dk), tab(ax, di, dj, dk, kNuInvW));
     };
     // diffusive coefficient of the low ax-face of cell (di, dj, dk)
     auto gef = [&](int di, int dj, int dk, int ax) -> T {
@@ -412,10 +527,17 @@ static hipError_t launch_adjoint_tiled(const AdjArgs<T>& a, int kz, bool big, hi
     if (a.nz <= 0 || tiles_x <= 0 || tiles_y <= 0 || kz < 0) return hipErrorInvalidValue;
     big = big || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
     using Kernel = void (*)(AdjArgs<T>, int, int, int);
-    const Kernel kern = a.walls ? (big ? adjoint_tiled_kernel<T, TX, TY, true, true>
-                                       : adjoint_tiled_kernel<T, TX, TY, false, true>)
-                                : (big ? adjoint_tiled_kernel<T, TX, TY, true, false>
-                                       : adjoint_tiled_kernel<T, TX, TY, false, false>);
+    Kernel kern;
+    if (a.nu[0]) {
+        if (big) return launch_adjoint_stage_nu<T>(a, st);  // the plain form indexes 64-bit
+        kern = a.walls ? adjoint_tiled_kernel<T, TX, TY, false, true, true>
+                       : adjoint_tiled_kernel<T, TX, TY, false, false, true>;
+    } else {
+        kern = a.walls ? (big ? adjoint_tiled_kernel<T, TX, TY, true, true>
+                              : adjoint_tiled_kernel<T, TX, TY, false, true>)
+                       : (big ? adjoint_tiled_kernel<T, TX, TY, true, false>
+                              : adjoint_tiled_kernel<T, TX, TY, false, false>);
+    }
     if (kz == 0) {
         kz = launch_chunk_planes((const void*)kern, TX * TY, (long long)tiles_x * tiles_y, a.nz, 1);
         if (kz <= 0) return hipErrorInvalidDevice;

@@ -128,12 +128,12 @@ static pf_status adjoint_impl(pf_solver* s, const T* phi, const T* U, const T* V
     if (tile < 0) tile = adjoint_default_tile(p.n[0], p.n[1], p.n[2]);
     const size_t vlen = std::strlen(vname);
     const bool big = vlen > 4 && std::strcmp(vname + vlen - 4, "_big") == 0;
-    // a non-uniform mesh: its own forward and adjoint kernels (one form each)
+    // a non-uniform mesh: the forward's per-stage NU kernel for the recompute, the NU forms of the
+    // plain and tiled adjoint kernels for the reverse stages
     const NuMesh* nu = s->nu.on() ? &s->nu : nullptr;
     auto adj = [&](const AdjArgs<T>& a, hipStream_t hs) {
-        if (nu) return launch_adjoint_stage_nu<T>(a, hs);
-        return plain ? launch_adjoint_stage_global<T>(a, hs)
-                     : launch_adjoint_stage<T>(a, tile, kz, big, hs);
+        if (plain) return nu ? launch_adjoint_stage_nu<T>(a, hs) : launch_adjoint_stage_global<T>(a, hs);
+        return launch_adjoint_stage<T>(a, tile, kz, big, hs);
     };
     hipError_t e;
     if (p.scheme == PF_EULER) {

@@ -14,7 +14,8 @@ scheme, periodic and walled axes, both eps rules, steady and time-varying veloci
 grids and a fused handle: FP64 within 1e-12 relative L-inf for lambda and the three face
 gradients, FP32 storage within 1e-3 of the FP64 oracle; with the stage inputs kept by
 phasefield_step_stages bit for bit the recomputing adjoint's results, and the stored new phi bit
-for bit phasefield_step's.
+for bit phasefield_step's. The tiled form of the non-uniform adjoint (three tile shapes, fixed
+and per-launch chunks) bit for bit its one-thread-per-cell form.
 """
 import numpy as np
 import pytest
@@ -284,3 +285,44 @@ def test_nonuniform_adjoint_matches_oracle(lib, dtype, shape, walls, eps_mode, s
     assert torch.equal(phi1, phi_ref)
     for x, y in zip([L] + grads, [L1] + grads1):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("dtype,walls,eps_mode,scheme", [("f64", (F, F, F), 1, "rk4"),
+                                                         ("f64", (T, F, T), 0, "rk4"),
+                                                         ("f32", (F, T, F), 1, "rk4"),
+                                                         ("f64", (F, F, F), 1, "rk3")])
+def test_nonuniform_adjoint_tiled_equals_plain(lib, dtype, walls, eps_mode, scheme):
+    """On a ragged grid (13 x 21 x 70): the adjoint through the tiled NU kernel (64x8 with
+    16-plane chunks, 64x4 with 32, 32x4 with per-launch chunks, the default handle) and through
+    the large-array variant (which takes the one-thread-per-cell form) bit for bit the
+    one-thread-per-cell form."""
+    pf = lib
+    shape = (13, 21, 70)
+    phi, U, V, W, h, hmax = nu_case(77, shape, walls=walls)
+    nz, ny, nx = shape
+    lam = np.random.default_rng(7).standard_normal(shape)
+    dxref = 1.0 / 70
+    eps = 1.1 * (dxref if eps_mode else hmax)
+    kw = dict(dx=dxref, eps=eps, gamma=1.2, dt=stable_dt(h, eps, eps_mode, dxref, 1.2, nz),
+              delta=0.05 / dxref)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    kd = pf.PF_F64 if dtype == "f64" else pf.PF_F32
+    names = [pf.phasefield_variant_name(kd, k) for k in range(pf.phasefield_variant_count(kd))]
+    outs = []
+    for vname in ("global", "tiled_64x8x16", "tiled_64x4x32", "tiled_32x4", "tiled_64x8x16_big",
+                  None):
+        print("case", dtype, walls, eps_mode, scheme, vname, flush=True)
+        s = pf.Solver((nx, ny, nz), scheme=scheme, walls=walls, dtype=dtype, vel_mode=1,
+                      vel_T=0.6, variant=-1 if vname is None else names.index(vname), **kw)
+        s.set_spacing(*h, eps_mode=eps_mode)
+        g = [torch.tensor(a, dtype=tdt, device="cuda") for a in (phi, U, V, W)]
+        L = torch.tensor(lam, dtype=tdt, device="cuda")
+        grads = [torch.zeros_like(L) for _ in range(3)]
+        s.adjoint_step(*g, 0.05, L, *grads)
+        torch.cuda.synchronize()
+        s.close()
+        outs.append([L] + grads)
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert torch.equal(x, y)
+    assert float(outs[0][0].abs().max()) > 0.0 and float(outs[0][1].abs().max()) > 0.0
