@@ -118,8 +118,10 @@ def time_forward(pf, c, phi, u, v, w, dtype, steps, warmup, st, autotune=True, v
 def nonuniform_timing(pf, fx, st, dtype, n=512, steps=20):
     """RK4 on a smoothly stretched n^3 mesh (widths varying 2x along every axis, eps tuned to the
     local mesh): the per-stage kernel's non-uniform form against its uniform form (tiled_64x4)
-    on the same grid. Fields and velocity of the roofline workload (timing does not depend on
-    the velocity's divergence on the stretched mesh)."""
+    on the same grid; and the adjoint step (stage recompute and four reverse stages, velocity
+    gradients accumulated) of a handle with the default variant, whose tile shape the tiled
+    adjoint takes, on both meshes. Fields and velocity of the roofline workload (timing does not
+    depend on the velocity's divergence on the stretched mesh)."""
     import torch
     c, phi, u, v, w = setup_roofline(pf, fx, n, dtype, st)
     h = [fx.smooth_widths(n, 1.0, 2.0, 0.9 * a) for a in range(3)]
@@ -139,11 +141,26 @@ def nonuniform_timing(pf, fx, st, dtype, n=512, steps=20):
             phi.copy_(keep)
             del keep
         s.close()
+        s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, dt, dtype=dtype)
+        if widths is not None:
+            s.set_spacing(*widths, eps_mode=1)
+        with torch.cuda.stream(st):
+            lam = torch.ones_like(phi)
+            grads = [torch.zeros_like(phi) for _ in range(3)]
+            s.adjoint_step(phi, u, v, w, 0.0, lam, *grads, stream=st)
+            ms_adj = cuda_timer(st, lambda: s.adjoint_step(phi, u, v, w, 0.0, lam, *grads,
+                                                           stream=st), 5)
+            del lam, grads
+        s.close()
         esz = 4 if dtype == "f32" else 8
         res[label] = {"ms_per_step": round(ms, 4), "gcell_s": round(c.cells / ms / 1e6, 2),
-                      "frac_of_8tbs_28_words": round(ALG_WORDS * esz * c.cells / ms / 1e6 / HBM_PEAK_GBS, 4)}
+                      "frac_of_8tbs_28_words": round(ALG_WORDS * esz * c.cells / ms / 1e6 / HBM_PEAK_GBS, 4),
+                      "adjoint_ms_default_variant": round(ms_adj, 4)}
     res["nonuniform_over_uniform"] = round(res["nonuniform"]["ms_per_step"] /
                                            res["uniform_tiled_64x4"]["ms_per_step"], 3)
+    res["adjoint_nonuniform_over_uniform"] = round(
+        res["nonuniform"]["adjoint_ms_default_variant"] /
+        res["uniform_tiled_64x4"]["adjoint_ms_default_variant"], 3)
     del phi, u, v, w
     torch.cuda.empty_cache()
     return res

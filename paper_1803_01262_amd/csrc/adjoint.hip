@@ -156,7 +156,38 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     }
     auto CX = [&](int col, int c) -> T { return scx[col * PW + c]; };
     auto CY = [&](int col, int r) -> T { return scy[col * PH + r]; };
-    auto CZ = [&](int col, int kk) -> T { return a.nu[2][(size_t)mapz(kk) * kNuCols + col]; };
+    // FP64 on 64x8 tiles keeps the coefficients of the thread's own column and row, and those of
+    // planes k-1 .. k+2, in registers along the march (it runs two waves per SIMD either way;
+    // 512^3 NU adjoint 19.2 against 21.6 ms reading them per iteration); FP32, and the smaller
+    // FP64 tiles (where 256 registers would leave one wave per SIMD), read them per iteration
+    // (LDS and uniform loads), which keeps FP32 at four waves per SIMD (10.9 against 13.1 ms)
+    constexpr bool HOIST = NU && sizeof(T) == 8 && TX * TY >= 512;
+    struct NuRow {
+        T v[kNuCols];
+    };
+    auto load_row = [&](const T* tab, int m) -> NuRow {
+        NuRow r;
+#pragma unroll
+        for (int c = 0; c < kNuCols; ++c) r.v[c] = tab[(size_t)m * kNuCols + c];
+        return r;
+    };
+    NuRow ox[3], oy[3];  // columns i-1, i, i+1 and rows j-1, j, j+1
+    if constexpr (HOIST) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ox[d] = load_row(a.nu[0], mapx(i0 + tid % TX - 1 + d));
+            oy[d] = load_row(a.nu[1], mapy(j0 + tid / TX - 1 + d));
+        }
+    }
+    // coefficient col of the thread's own column i-1+d, row j-1+d
+    auto OX = [&](int col, int d) -> T {
+        if constexpr (HOIST) return ox[d].v[col];
+        else return CX(col, tid % TX + 1 + d);
+    };
+    auto OY = [&](int col, int d) -> T {
+        if constexpr (HOIST) return oy[d].v[col];
+        else return CY(col, tid / TX + 1 + d);
+    };
 
     unsigned loff[NL];
     int lpos[NL];
@@ -220,16 +251,16 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         qb[2] = -hg * (adj_face(K0[q], K1[q], inv_dx) + adj_face(K1[q], K2[q], inv_dx));
         return adj_cell(Y1[q], g, qb, d2, gb);
     };
-    // the same on a non-uniform mesh: the cell at LDS row r, column c; sz1 the inverse gradient
-    // span of plane k+1, iz0..iz2 the inverse widths of planes k, k+1, k+2
+    // the same on a non-uniform mesh, the cell at LDS offset q: sx, sy, sz1 the inverse gradient
+    // spans of its column, row and plane k+1; wxm..wxp, wym..wyp the inverse widths of the
+    // columns and rows around it, iz0..iz2 those of planes k, k+1, k+2
     auto cell_nu = [&](const T* Y0, const T* Y1, const T* Y2, const T* K0, const T* K1,
-                       const T* K2, int q, int r, int c, T sz1, T iz0, T iz1, T iz2, T gb[3]) -> T {
+                       const T* K2, int q, T sx, T sy, T wxm, T wxc, T wxp, T wym, T wyc, T wyp,
+                       T sz1, T iz0, T iz1, T iz2, T gb[3]) -> T {
         T g[3], qb[3];
-        g[0] = (Y1[q + 1] - Y1[q - 1]) * CX(kNuInvSpan, c);
-        g[1] = (Y1[q + PW] - Y1[q - PW]) * CY(kNuInvSpan, r);
+        g[0] = (Y1[q + 1] - Y1[q - 1]) * sx;
+        g[1] = (Y1[q + PW] - Y1[q - PW]) * sy;
         g[2] = (Y2[q] - Y0[q]) * sz1;
-        const T wxm = CX(kNuInvW, c - 1), wxc = CX(kNuInvW, c), wxp = CX(kNuInvW, c + 1);
-        const T wym = CY(kNuInvW, r - 1), wyc = CY(kNuInvW, r), wyp = CY(kNuInvW, r + 1);
         qb[0] = -a.nu_hg * (nu_face(K1[q - 1], wxm, K1[q], wxc) + nu_face(K1[q], wxc, K1[q + 1], wxp));
         qb[1] = -a.nu_hg *
                 (nu_face(K1[q - PW], wym, K1[q], wyc) + nu_face(K1[q], wyc, K1[q + PW], wyp));
@@ -243,6 +274,12 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
     fetch(k0 - 1);
     commit(1);
     fetch(k0);
+    // FP64: the z-plane coefficients of planes k-1 .. k+2 of iteration k, handed down the march
+    NuRow zr[4];
+    if constexpr (HOIST) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) zr[d] = load_row(a.nu[2], mapz(k0 - 3 + d));
+    }
     // handed from plane to plane: gbar_z at k-1 and k, the local term and z-face cotangent of
     // plane k, W at k
     T gz_prev = T(0), gz_cur = T(0), loc_cur = T(0), fbz_cur = T(0), w0 = T(0);
@@ -291,13 +328,23 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         const T *K0 = sk + s0 * PS, *K1 = sk + s1 * PS, *K2 = sk + s2 * PS;
         T gb[3];
         T loc_next, fbz_next;  // fbz_next: the z-face between planes k and k+1
+        // coefficient col of plane k+dk (dk = -1 .. 2)
+        auto ZC = [&](int col, int dk) -> T {
+            if constexpr (HOIST) return zr[dk + 1].v[col];
+            else return a.nu[2][(size_t)mapz(k + dk) * kNuCols + col];
+        };
+        NuRow z3;
+        if constexpr (HOIST) z3 = load_row(a.nu[2], mapz(k + 3));  // for the next iteration
+        // inverse widths of planes k, k+1, k+2 and inverse gradient span of plane k+1
         T iz0 = T(0), iz1 = T(0), iz2 = T(0), sz1 = T(0);
         if constexpr (NU) {
-            iz0 = CZ(kNuInvW, k);
-            iz1 = CZ(kNuInvW, k + 1);
-            iz2 = CZ(kNuInvW, k + 2);
-            sz1 = CZ(kNuInvSpan, k + 1);
-            loc_next = cell_nu(Y0, Y1, Y2, K0, K1, K2, o, ty + 2, tx + 2, sz1, iz0, iz1, iz2, gb);
+            iz0 = ZC(kNuInvW, 0);
+            iz1 = ZC(kNuInvW, 1);
+            iz2 = ZC(kNuInvW, 2);
+            sz1 = ZC(kNuInvSpan, 1);
+            loc_next = cell_nu(Y0, Y1, Y2, K0, K1, K2, o, OX(kNuInvSpan, 1), OY(kNuInvSpan, 1),
+                               OX(kNuInvW, 0), OX(kNuInvW, 1), OX(kNuInvW, 2), OY(kNuInvW, 0),
+                               OY(kNuInvW, 1), OY(kNuInvW, 2), sz1, iz0, iz1, iz2, gb);
             fbz_next = nu_face(K0[o], iz0, K1[o], iz1);
         } else {
             loc_next = cell(Y0, Y1, Y2, K0, K1, K2, o, gb);
@@ -309,7 +356,10 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         if (h_o >= 0) {
             T hb[3];
             if constexpr (NU)
-                (void)cell_nu(Y0, Y1, Y2, K0, K1, K2, h_o, h_r, h_c, sz1, iz0, iz1, iz2, hb);
+                (void)cell_nu(Y0, Y1, Y2, K0, K1, K2, h_o, CX(kNuInvSpan, h_c), CY(kNuInvSpan, h_r),
+                              CX(kNuInvW, h_c - 1), CX(kNuInvW, h_c), CX(kNuInvW, h_c + 1),
+                              CY(kNuInvW, h_r - 1), CY(kNuInvW, h_r), CY(kNuInvW, h_r + 1),
+                              sz1, iz0, iz1, iz2, hb);
             else
                 (void)cell(Y0, Y1, Y2, K0, K1, K2, h_o, hb);
             if (h_axis == 0)
@@ -320,53 +370,52 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         if (zplane && active && a.gW) stg<T>(a.gW + ok1, col, fma(-hs * (Y0[o] + Y1[o]), fbz_next, gw));
         if constexpr (NU) {
             if (out_plane && active) {
-                const int r = ty + 2, c = tx + 2;
                 // diffusive coefficients of the six faces: gamma eps_face / centre distance
-                const T dzl = CZ(kNuInvDist, k), dzh = CZ(kNuInvDist, k + 1);
+                const T dzl = ZC(kNuInvDist, 0), dzh = ZC(kNuInvDist, 1);
                 T exl, exh, eyl, eyh, ezl, ezh;
                 if (a.nu_eps_mode == 1) {  // eps of a cell ~ its largest width
-                    const T wx = CX(kNuWidth, c), wy = CY(kNuWidth, r), wz = CZ(kNuWidth, k);
+                    const T wx = OX(kNuWidth, 1), wy = OY(kNuWidth, 1), wz = ZC(kNuWidth, 0);
                     const T mc = fmax(wx, fmax(wy, wz));
                     const T hh = a.nu_ge * T(0.5);
-                    exl = hh * (fmax(CX(kNuWidth, c - 1), fmax(wy, wz)) + mc) * CX(kNuInvDist, c);
-                    exh = hh * (mc + fmax(CX(kNuWidth, c + 1), fmax(wy, wz))) * CX(kNuInvDist, c + 1);
-                    eyl = hh * (fmax(wx, fmax(CY(kNuWidth, r - 1), wz)) + mc) * CY(kNuInvDist, r);
-                    eyh = hh * (mc + fmax(wx, fmax(CY(kNuWidth, r + 1), wz))) * CY(kNuInvDist, r + 1);
-                    ezl = hh * (fmax(wx, fmax(wy, CZ(kNuWidth, k - 1))) + mc) * dzl;
-                    ezh = hh * (mc + fmax(wx, fmax(wy, CZ(kNuWidth, k + 1)))) * dzh;
+                    exl = hh * (fmax(OX(kNuWidth, 0), fmax(wy, wz)) + mc) * OX(kNuInvDist, 1);
+                    exh = hh * (mc + fmax(OX(kNuWidth, 2), fmax(wy, wz))) * OX(kNuInvDist, 2);
+                    eyl = hh * (fmax(wx, fmax(OY(kNuWidth, 0), wz)) + mc) * OY(kNuInvDist, 1);
+                    eyh = hh * (mc + fmax(wx, fmax(OY(kNuWidth, 2), wz))) * OY(kNuInvDist, 2);
+                    ezl = hh * (fmax(wx, fmax(wy, ZC(kNuWidth, -1))) + mc) * dzl;
+                    ezh = hh * (mc + fmax(wx, fmax(wy, ZC(kNuWidth, 1)))) * dzh;
                 } else {
-                    exl = a.nu_ge * CX(kNuInvDist, c);
-                    exh = a.nu_ge * CX(kNuInvDist, c + 1);
-                    eyl = a.nu_ge * CY(kNuInvDist, r);
-                    eyh = a.nu_ge * CY(kNuInvDist, r + 1);
+                    exl = a.nu_ge * OX(kNuInvDist, 1);
+                    exh = a.nu_ge * OX(kNuInvDist, 2);
+                    eyl = a.nu_ge * OY(kNuInvDist, 1);
+                    eyh = a.nu_ge * OY(kNuInvDist, 2);
                     ezl = a.nu_ge * dzl;
                     ezh = a.nu_ge * dzh;
                 }
                 T ybar = loc_cur;
                 // x faces
-                const T wxm = CX(kNuInvW, c - 1), wxc = CX(kNuInvW, c), wxp = CX(kNuInvW, c + 1);
+                const T wxm = OX(kNuInvW, 0), wxc = OX(kNuInvW, 1), wxp = OX(kNuInvW, 2);
                 T lo = nu_face(K0[o - 1], wxm, K0[o], wxc), hi = nu_face(K0[o], wxc, K0[o + 1], wxp);
                 ybar = fma(lo, fma(-hs, u0, exl), ybar);
                 ybar = fma(hi, fma(-hs, u1, -exh), ybar);
                 if (a.gU) stg<T>(a.gU + ok, col, fma(-hs * (Y0[o - 1] + Y0[o]), lo, gu));
                 const T* GX = sgx + q0 * GXS + ty * GXW + tx;
-                ybar = fma(GX[0], CX(kNuInvSpan, c - 1), ybar);
-                ybar = fma(-GX[2], CX(kNuInvSpan, c + 1), ybar);
+                ybar = fma(GX[0], OX(kNuInvSpan, 0), ybar);
+                ybar = fma(-GX[2], OX(kNuInvSpan, 2), ybar);
                 // y faces
-                const T wym = CY(kNuInvW, r - 1), wyc = CY(kNuInvW, r), wyp = CY(kNuInvW, r + 1);
+                const T wym = OY(kNuInvW, 0), wyc = OY(kNuInvW, 1), wyp = OY(kNuInvW, 2);
                 lo = nu_face(K0[o - PW], wym, K0[o], wyc);
                 hi = nu_face(K0[o], wyc, K0[o + PW], wyp);
                 ybar = fma(lo, fma(-hs, v0, eyl), ybar);
                 ybar = fma(hi, fma(-hs, v1, -eyh), ybar);
                 if (a.gV) stg<T>(a.gV + ok, col, fma(-hs * (Y0[o - PW] + Y0[o]), lo, gv));
                 const T* GY = sgy + q0 * GYS + ty * TX + tx;
-                ybar = fma(GY[0], CY(kNuInvSpan, r - 1), ybar);
-                ybar = fma(-GY[2 * TX], CY(kNuInvSpan, r + 1), ybar);
+                ybar = fma(GY[0], OY(kNuInvSpan, 0), ybar);
+                ybar = fma(-GY[2 * TX], OY(kNuInvSpan, 2), ybar);
                 // z faces
                 ybar = fma(fbz_cur, fma(-hs, w0, ezl), ybar);
                 ybar = fma(fbz_next, fma(-hs, w1, -ezh), ybar);
-                ybar = fma(gz_prev, CZ(kNuInvSpan, k - 1), ybar);
-                ybar = fma(-gz_next, CZ(kNuInvSpan, k + 1), ybar);
+                ybar = fma(gz_prev, ZC(kNuInvSpan, -1), ybar);
+                ybar = fma(-gz_next, ZC(kNuInvSpan, 1), ybar);
                 if (a.lam_out) stg<T>(a.lam_out + ok, col, lb + ybar);
                 if (a.kap_out) stg<T>(a.kap_out + ok, col, fma(a.ka, ybar, a.kb * lp));
             }
@@ -399,6 +448,12 @@ __global__ void __launch_bounds__(TX* TY) adjoint_tiled_kernel(AdjArgs<T> a, int
         loc_cur = loc_next;
         fbz_cur = fbz_next;
         w0 = w1;
+        if constexpr (HOIST) {
+            zr[0] = zr[1];
+            zr[1] = zr[2];
+            zr[2] = zr[3];
+            zr[3] = z3;
+        }
     };
     const int kend = k0 - 2 + 6 * ((k1 - k0 + 7) / 6);  // k0-2 .. k1-1, in groups of six
     for (int k = k0 - 2; k < kend; k += 6) {
