@@ -6,6 +6,8 @@ configuration (tuned tile variant, FP32 storage). The oracle cannot step 134M ce
 but a cell's value after m RK4 steps depends only on the input within 8m cells of it (four
 stages, each reaching two cells along an axis; 4m for RK2's two stages), so the oracle runs on a
 periodic patch of that radius plus 2 around each sampled cell and its centre value is exact.
+The non-uniform mesh at the same size is sampled the same way (its widths sliced with the patch),
+for a step and for an adjoint step. The adjoint workload (128^3) is compared on every cell.
 """
 import numpy as np
 import pytest
@@ -192,3 +194,69 @@ def test_adjoint_workload_full_grid(lib, dtype, tol, form):
         resp = float(np.abs(ref_p[k] - want).max() / scale)
         print("output", k, "error", err, "oracle response to unit roundoff", resp, flush=True)
         assert err <= tol, (k, err, tol)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fullsize_nonuniform_sampled_parity(lib, case512, dtype):
+    """The non-uniform leg at its benchmark size: 512^3 with widths varying 2x smoothly along
+    every axis and eps tuned to the local mesh, delta = 1e-3/dx, a default-variant handle (the
+    per-stage NU kernel, the tiled NU reverse stages). One RK4 step and one adjoint step on the
+    whole grid; sampled cells against the oracle on periodic patches whose widths are sliced
+    alike. A step's output reaches 8 cells of input; the adjoint's lambda and face gradients reach
+    8 cells of the cotangent and 16 of phi (through the stage inputs), so patches of radius 10 and
+    18 make the centre values exact. FP64 within 1e-12 of each output's largest sampled value;
+    FP32 storage: the step within 1e-5 of the oracle's FP32-storage mode, the adjoint within 1e-3
+    of the FP64 oracle."""
+    pf = lib
+    c, U, V, W = case512
+    n = c.shape[0]
+    h = [fx.smooth_widths(n, 1.0, 2.0, 0.9 * a) for a in range(3)]
+    dt = min(c.dt, 0.1 * min(map(min, h)) ** 2 / (c.gamma * c.eps * max(map(max, h)) / c.dx))
+    delta = 1e-3 / c.dx
+    np_dt = np.float32 if dtype == "f32" else np.float64
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    inputs = [a.astype(np_dt).astype(np.float64) for a in (c.phi0, U, V, W)]
+    lam = np.random.default_rng(23).standard_normal(c.shape).astype(np_dt).astype(np.float64)
+    s = pf.Solver((n, n, n), c.dx, c.eps, c.gamma, dt, dtype=dtype, delta=delta)
+    s.set_spacing(*h, eps_mode=1)
+    print(dtype, "variant", s.variant_name, flush=True)
+    g = [torch.tensor(a, dtype=tdt, device="cuda") for a in inputs]
+    phi1 = g[0].clone()
+    s.step(phi1, *g[1:], nsteps=1)
+    out = phi1.cpu().numpy().astype(np.float64)
+    del phi1
+    L = torch.tensor(lam, dtype=tdt, device="cuda")
+    grads = [torch.zeros_like(L) for _ in range(3)]
+    s.adjoint_step(*g, 0.0, L, *grads)
+    adj = [t.cpu().numpy().astype(np.float64) for t in [L] + grads]
+    del g, L, grads
+    s.close()
+    kw = dict(dx=c.dx, eps=c.eps, gamma=c.gamma, dt=dt, delta=delta, eps_mode=1)
+    cells = sample_cells(inputs[0], np.random.default_rng(29), 12)
+
+    def widths(k, j, i, R):
+        return dict(hx=h[0][(i + np.arange(-R, R + 1)) % n], hy=h[1][(j + np.arange(-R, R + 1)) % n],
+                    hz=h[2][(k + np.arange(-R, R + 1)) % n])
+
+    worst, scale = 0.0, 0.0
+    for (k, j, i) in cells:
+        R = 10
+        pp = [patch(a, k, j, i, R) for a in inputs]
+        ref = oracle.step_nu(*pp, **widths(k, j, i, R), fp32=(dtype == "f32"), **kw)
+        worst = max(worst, abs(out[k, j, i] - ref[R, R, R]))
+        scale = max(scale, abs(ref[R, R, R]))
+    print(dtype, "step: worst sampled |gpu - oracle|", worst, "of", scale, flush=True)
+    assert worst <= (1e-12 if dtype == "f64" else 1e-5) * max(scale, 1.0)
+    worst, scale = [0.0] * 4, [0.0] * 4
+    for (k, j, i) in cells:
+        R = 18
+        pp = [patch(a, k, j, i, R) for a in inputs]
+        ref = oracle.adjoint_step_nu(*pp, patch(lam, k, j, i, R), **widths(k, j, i, R), t=0.0, **kw)
+        for q in range(4):
+            worst[q] = max(worst[q], abs(adj[q][k, j, i] - ref[q][R, R, R]))
+            scale[q] = max(scale[q], abs(ref[q][R, R, R]))
+    print(dtype, "adjoint: worst sampled |gpu - oracle|", worst, "of", scale, flush=True)
+    tol = 1e-12 if dtype == "f64" else 1e-3
+    for q in range(4):
+        assert scale[q] > 0.0, q
+        assert worst[q] <= tol * scale[q], (q, worst[q], scale[q])
