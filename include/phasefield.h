@@ -227,8 +227,8 @@ pf_status phasefield_set_spacing(pf_solver *s, const double *hx, const double *h
  * stage's adjoint and flux-Jacobian terms in LDS and hands them to the earlier stage of the same
  * tile: fewer field passes, but more registers per thread); -1 (the default) two per launch for
  * FP64 on grids of 192^3 cells and more when the handle's variant is a fused one, else one.
- * Every form gives bit-identical results. Fields of 4 GiB or more and handles with walls always
- * take one per launch.
+ * Every form gives bit-identical results. Fields of 4 GiB or more, handles with walls and
+ * handles with a non-uniform mesh always take one per launch.
  * Errors: PF_ERR_INVALID (NULL handle, form outside -1..1). */
 pf_status phasefield_set_adjoint_form(pf_solver *s, int32_t form);
 
