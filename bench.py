@@ -365,7 +365,8 @@ def rollout_timing(pf, fx, dtype, n=128):
 def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
     """The batched driver (default mode, both modes forced, and the autotuned shape and launch
     form, the figure of record) against a loop of single solves (each its own handle, one
-    stream, no graphs), on the same uneven FP32 instances."""
+    stream, no graphs), on the same uneven FP32 instances; then RK3, RK2 and Euler batches of
+    the same instances against their loops."""
     import torch
     cases = fx.batch_cases(count=count, nsteps=nsteps)
     params, fields = [], []
@@ -434,6 +435,38 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
         t_gloop = cuda_timer(st, lambda: gloop(nsteps))
     for s in solvers + gsolvers:
         s.close()
+    # the other schemes (per-stage sweeps, one launch per stage), 100 steps at 0.9 of each
+    # instance's stability limit for that scheme, against the uncaptured loop
+    other = {}
+    for scheme in ("rk3", "rk2", "euler"):
+        sp = []
+        for c, p in zip(cases, params):
+            q = pf.make_params(tuple(p.n), p.dx, p.eps, p.gamma, p.dt, dtype="f32", scheme=scheme)
+            q.dt = 0.9 * min(c.dt, pf.phasefield_check_params(q, c.extra["umax"]).dt_max_scheme)
+            sp.append(q)
+        steps = 100
+        bs = pf.BatchSolver(sp)
+        bf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+        with torch.cuda.stream(st):
+            bs.step(*zip(*bf), nsteps=16, stream=st)
+            tb = cuda_timer(st, lambda: bs.step(*zip(*bf), nsteps=steps, stream=st))
+        bs.close()
+        ss = [pf.Solver(tuple(q.n), q.dx, q.eps, q.gamma, q.dt, dtype="f32", scheme=scheme,
+                        use_graph=False) for q in sp]
+        sf = [[f[0].clone(), f[1], f[2], f[3]] for f in fields]
+
+        def sloop(k):
+            for s, f in zip(ss, sf):
+                s.step(*f, nsteps=k, stream=st)
+
+        with torch.cuda.stream(st):
+            sloop(2)
+            tl = cuda_timer(st, lambda: sloop(steps))
+        for s in ss:
+            s.close()
+        other[scheme] = {"steps": steps, "batched_ms": round(tb, 2), "looped_ms": round(tl, 2),
+                         "batched_gcell_s": round(cells * steps / tb / 1e6, 2),
+                         "speedup_vs_looped": round(tl / tb, 2)}
     return {"instances": count, "cells": cells, "steps": nsteps,
             "batched_ms": round(t_batch, 2), "looped_ms": round(t_loop, 2),
             "looped_graph_ms": round(t_gloop, 2),
@@ -444,7 +477,8 @@ def batch_vs_loop(pf, fx, st, count=96, nsteps=300):
                                          for k, v in tune_times.items()}},
             "looped_gcell_s": round(cells * nsteps / t_loop / 1e6, 2),
             "speedup_vs_looped": round(t_loop / t_batch, 2),
-            "speedup_vs_looped_graph": round(t_gloop / t_batch, 2)}
+            "speedup_vs_looped_graph": round(t_gloop / t_batch, 2),
+            "other_schemes": other}
 
 
 def cpu_model() -> str:

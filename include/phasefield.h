@@ -288,21 +288,24 @@ int32_t phasefield_solver_variant(const pf_solver *s);
 
 /* ----------------------------------------------------------------------------------------
  * Batched driver: many independent simulations (each its own pf_params, uneven grid sizes,
- * same dtype, RK4, steady velocity) advanced together. Each sweep is ONE launch over a global
- * tile list that covers every instance (one workgroup per tile): two fused two-stage sweeps per
- * step, or four single-stage sweeps. per_instance[0].variant selects the mode by its kind (a
- * "fused_*" variant or a per-stage one); with variant -1, FP32 runs fused and FP64 per-stage. Instances may have
- * walls on any axes (each its own); a walled z axis in any instance puts the batch in per-stage
- * mode (the fused sweeps take walls on x and y only). The step sequence
+ * same dtype, same scheme, steady velocity) advanced together. Each sweep is ONE launch over a
+ * global tile list that covers every instance (one workgroup per tile): for RK4 two fused
+ * two-stage sweeps per step, or four single-stage sweeps; for RK3, RK2 and Euler one
+ * single-stage sweep per stage (Euler then one batched copy of the accumulator into phi).
+ * per_instance[0].variant selects the RK4 mode by its kind (a "fused_*" variant or a per-stage
+ * one); with variant -1, FP32 runs fused and FP64 per-stage. Instances may have walls on any
+ * axes (each its own); a walled z axis in any instance, or a scheme other than RK4, puts the
+ * batch in per-stage mode (the fused sweeps pair RK4's stages and take walls on x and y only).
+ * The step sequence
  * is replayed from a captured HIP graph. Results are bit-identical to running each instance
  * alone with phasefield_step.
  * ------------------------------------------------------------------------------------- */
 typedef struct pf_batch pf_batch;
 
 /* per_instance: HOST array of count parameter sets (all with the same dtype).
- * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtypes), PF_ERR_UNSUPPORTED (a set
- * with a scheme other than RK4, a time-varying velocity, or a field of 4 GiB or more: such grids
- * take a single-grid solver), PF_ERR_OOM, PF_ERR_DEVICE. */
+ * Errors: PF_ERR_INVALID (count < 1, any invalid set, mixed dtypes), PF_ERR_UNSUPPORTED (mixed
+ * schemes, a time-varying velocity, or a field of 4 GiB or more: such grids take a single-grid
+ * solver), PF_ERR_OOM, PF_ERR_DEVICE. */
 pf_status phasefield_batch_create(const pf_params *per_instance, int32_t count, pf_batch **out);
 
 /* Advance every instance b by nsteps steps: phi[b], u[b], v[b], w[b] are HOST arrays of count
@@ -326,7 +329,8 @@ pf_status phasefield_batch_set_persistent(pf_batch *b, int32_t persistent);
  * per-stage mode). Every shape gives bit-identical results. The tile list is rebuilt; the next
  * step re-uploads the per-instance tables and re-captures its graph (work queued on the batch's
  * last stream is synchronised first). Errors: PF_ERR_INVALID (NULL, shape outside 0..2),
- * PF_ERR_UNSUPPORTED (a fused shape while some instance has a walled z axis), PF_ERR_OOM,
+ * PF_ERR_UNSUPPORTED (a fused shape while some instance has a walled z axis, or for a scheme
+ * other than RK4), PF_ERR_OOM,
  * PF_ERR_DEVICE. */
 pf_status phasefield_batch_set_shape(pf_batch *b, int32_t shape);
 

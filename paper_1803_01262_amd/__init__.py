@@ -129,8 +129,9 @@ class Solver:
 
 
 class BatchSolver:
-    """Many independent RK4 simulations (uneven grids, one storage dtype, steady velocity)
-    advanced together: one launch per sweep over a global tile list, graph-replayed steps."""
+    """Many independent simulations (uneven grids, one storage dtype, one scheme, steady
+    velocity) advanced together: one launch per sweep over a global tile list, graph-replayed
+    steps (RK4 in fused or per-stage sweeps, RK3, RK2 and Euler in per-stage sweeps)."""
 
     def __init__(self, params_list):
         self.params = list(params_list)

@@ -7,8 +7,11 @@
 //   fused:     two-stage sweeps (two launches per step). phi alternates with the accumulator
 //              buffer from step to step; tables for even and odd steps are kept, and after an
 //              odd step count one batched copy returns phi to the caller's buffers.
-//   per-stage: four launches per step, fixed buffers.
-// Either way every instance is bit-identical to its own single solve. The tile shape (fused
+//   per-stage: one launch per RK stage (RK4 four, RK3 three, RK2 two, Euler one and a batched
+//              copy of the accumulator into phi), fixed buffers; the only mode of the schemes
+//              other than RK4 (the fused sweeps pair RK4's stages).
+// Every instance of a batch runs the same scheme. Either way every instance is bit-identical to
+// its own single solve. The tile shape (fused
 // 32x16 or 64x8, per-stage 32x8) and the launch form can be set, or chosen by timing them all
 // (phasefield_batch_autotune).
 #include <hip/hip_runtime.h>
@@ -24,6 +27,7 @@ using namespace pf;
 struct pf_batch {
     int count = 0;
     int dtype = PF_F64;
+    int scheme = PF_RK4;  // every instance's
     bool fused = false;
     std::vector<pf_params> p;
     std::vector<size_t> N;
@@ -35,7 +39,8 @@ struct pf_batch {
     bool walls = false;  // some instance has walls
     int shape = kBatchStage32x8;  // BatchShape of the tile list
     BatchTile* tiles = nullptr;  // device: the global tile list (8 equal per-XCD ranges)
-    // device per-instance argument arrays: per-stage mode S1..S4 (StageArgs);
+    // device per-instance argument arrays: per-stage mode S1..S4 (StageArgs; RK3 S1..S3, RK2
+    // S1..S2, Euler S1);
     // fused mode A_even, B_even, A_odd, B_odd (FusedArgs)
     void* tables[4] = {nullptr, nullptr, nullptr, nullptr};
     void* copies = nullptr;        // device BatchCopy<T>[count]: acc -> phi after an odd count
@@ -69,12 +74,20 @@ extern "C" pf_status phasefield_batch_destroy(pf_batch* b)
 
 static size_t padded(size_t n) { return (n + 63) / 64 * 64; }  // keeps buffers 256-byte aligned
 
-// Mode: the kind (fused or per-stage) of the variant named by instance 0, else by dtype.
-// Fused mode unless an instance has a z wall (the fused sweeps take walls on x and y only).
-static bool B_mode_fused(const pf_params* per_instance, int count)
+// Whether the fused shapes apply: RK4 with no walled z axis (the fused sweeps pair RK4's
+// stages and take walls on x and y only); 0 if they do, else the first instance that stops them.
+static int B_stage_only(const pf_params* per_instance, int count)
 {
     for (int b = 0; b < count; ++b)
-        if (wall_mask(per_instance[b]) & 4) return false;
+        if ((wall_mask(per_instance[b]) & 4) || per_instance[b].scheme != PF_RK4) return b + 1;
+    return 0;
+}
+
+// Mode: the kind (fused or per-stage) of the variant named by instance 0, else by dtype.
+// Per-stage whenever the fused shapes do not apply (B_stage_only).
+static bool B_mode_fused(const pf_params* per_instance, int count)
+{
+    if (B_stage_only(per_instance, count)) return false;
     const int dtype = per_instance[0].dtype, v0 = per_instance[0].variant;
     if (v0 >= 0 && v0 < stage_variant_count(dtype)) return variant_is_fused(dtype, v0);
     return dtype == PF_F32;
@@ -134,8 +147,8 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
         if (st != PF_OK) return fail(st, "instance %d: %s", b, phasefield_last_error());
         if (per_instance[b].dtype != per_instance[0].dtype)
             return fail(PF_ERR_INVALID, "instance %d: mixed dtypes", b);
-        if (per_instance[b].scheme != PF_RK4)
-            return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver runs RK4 only", b);
+        if (per_instance[b].scheme != per_instance[0].scheme)
+            return fail(PF_ERR_UNSUPPORTED, "instance %d: mixed schemes in one batch", b);
         if (per_instance[b].vel_mode != PF_VEL_STEADY)
             return fail(PF_ERR_UNSUPPORTED, "instance %d: the batched driver needs a steady velocity", b);
         const pf_params& q = per_instance[b];
@@ -150,6 +163,7 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
     auto* B = new pf_batch();
     B->count = count;
     B->dtype = per_instance[0].dtype;
+    B->scheme = per_instance[0].scheme;
     B->shape = shape;
     B->fused = shape != kBatchStage32x8;
     B->p.assign(per_instance, per_instance + count);
@@ -186,9 +200,19 @@ extern "C" pf_status phasefield_batch_create(const pf_params* per_instance, int3
     return PF_OK;
 }
 
-// Build the device tables for one pointer set.
-//   per-stage: S1 ya = phi + dt/2 k1, acc = phi + dt/6 k1;  S2 yb = phi + dt/2 k2, acc += dt/3 k2;
-//              S3 ya = phi + dt k3, acc += dt/3 k3;        S4 phi = acc + dt/6 k4.
+// Stage launches per step in per-stage mode.
+static int batch_stage_count(int scheme)
+{
+    return scheme == PF_RK4 ? 4 : scheme == PF_RK3 ? 3 : scheme == PF_RK2 ? 2 : 1;
+}
+
+// Build the device tables for one pointer set. Per-stage mode, the single-grid step's stages:
+//   RK4:   S1 ya = phi + dt/2 k1, acc = phi + dt/6 k1;  S2 yb = phi + dt/2 k2, acc += dt/3 k2;
+//          S3 ya = phi + dt k3, acc += dt/3 k3;        S4 phi = acc + dt/6 k4.
+//   RK3:   S1 ya = phi + dt g1 k1, acc = phi + dt (g1 + z2) k1;  S2 yb = acc + dt g2 k2;
+//          S3 phi = acc + dt g3 k3.
+//   RK2:   S1 ya = phi + dt/2 k1;  S2 phi = phi + dt k2.
+//   Euler: S1 acc = phi + dt k1, then the batched copy acc -> phi.
 //   fused:     even steps run from phi into acc, odd steps from acc back into phi.
 template <typename T>
 static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const* u,
@@ -212,16 +236,28 @@ static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const*
             for (int s = 0; s < 4; ++s) fu_tab[s].push_back(f[s]);
         } else {
             const double dt = p.dt;
-            const StageArgs<T> sa[4] = {
-                make_stage<T>(p, 1.0, ph, ph, ph, ya, acc, 0.5 * dt, dt / 6.0, U, V, W),
-                make_stage<T>(p, 1.0, ya, ph, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W),
-                make_stage<T>(p, 1.0, yb, ph, acc, ya, acc, dt, dt / 3.0, U, V, W),
-                make_stage<T>(p, 1.0, ya, nullptr, acc, nullptr, ph, 0.0, dt / 6.0, U, V, W)};
-            for (int s = 0; s < 4; ++s) st_tab[s].push_back(sa[s]);
+            constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0;
+            StageArgs<T> sa[4];
+            if (p.scheme == PF_RK4) {
+                sa[0] = make_stage<T>(p, 1.0, ph, ph, ph, ya, acc, 0.5 * dt, dt / 6.0, U, V, W);
+                sa[1] = make_stage<T>(p, 1.0, ya, ph, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W);
+                sa[2] = make_stage<T>(p, 1.0, yb, ph, acc, ya, acc, dt, dt / 3.0, U, V, W);
+                sa[3] = make_stage<T>(p, 1.0, ya, nullptr, acc, nullptr, ph, 0.0, dt / 6.0, U, V, W);
+            } else if (p.scheme == PF_RK3) {
+                sa[0] = make_stage<T>(p, 1.0, ph, ph, ph, ya, acc, dt * g1, dt * (g1 + z2), U, V, W);
+                sa[1] = make_stage<T>(p, 1.0, ya, acc, nullptr, yb, nullptr, dt * g2, 0.0, U, V, W);
+                sa[2] = make_stage<T>(p, 1.0, yb, nullptr, acc, nullptr, ph, 0.0, dt * g3, U, V, W);
+            } else if (p.scheme == PF_RK2) {
+                sa[0] = make_stage<T>(p, 1.0, ph, ph, nullptr, ya, nullptr, 0.5 * dt, 0.0, U, V, W);
+                sa[1] = make_stage<T>(p, 1.0, ya, nullptr, ph, nullptr, ph, 0.0, dt, U, V, W);
+            } else {
+                sa[0] = make_stage<T>(p, 1.0, ph, nullptr, ph, nullptr, acc, 0.0, dt, U, V, W);
+            }
+            for (int s = 0; s < batch_stage_count(p.scheme); ++s) st_tab[s].push_back(sa[s]);
         }
         copies.push_back({acc, ph, B->N[b]});
     }
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < (B->fused ? 4 : batch_stage_count(B->scheme)); ++s) {
         hipError_t e = B->fused ? hipMemcpy(B->tables[s], fu_tab[s].data(),
                                             sizeof(FusedArgs<T>) * B->count, hipMemcpyHostToDevice)
                                 : hipMemcpy(B->tables[s], st_tab[s].data(),
@@ -247,11 +283,13 @@ static hipError_t enqueue_batch_step(pf_batch* B, bool odd, hipStream_t st)
         }
         return hipSuccess;
     }
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < batch_stage_count(B->scheme); ++s) {
         hipError_t e = launch_batch_stage<T>((const StageArgs<T>*)B->tables[s], B->tiles,
                                              B->num_tiles, B->persistent, B->walls, st);
         if (e != hipSuccess) return e;
     }
+    if (B->scheme == PF_EULER)  // the step's new phi is in the accumulator
+        return launch_batch_copy<T>((const BatchCopy<T>*)B->copies, B->count, st);
     return hipSuccess;
 }
 
@@ -379,10 +417,14 @@ extern "C" pf_status phasefield_batch_set_shape(pf_batch* b, int32_t shape)
     if (!b) return fail(PF_ERR_INVALID, "batch is NULL");
     if (shape < 0 || shape >= kNumBatchShapes)
         return fail(PF_ERR_INVALID, "batch shape %d is not 0, 1 or 2", (int)shape);
-    if (shape != kBatchStage32x8)
-        for (int i = 0; i < b->count; ++i)
-            if (wall_mask(b->p[i]) & 4)
-                return fail(PF_ERR_UNSUPPORTED, "instance %d has a z wall: per-stage shape only", i);
+    if (shape != kBatchStage32x8) {
+        const int i = B_stage_only(b->p.data(), b->count) - 1;
+        if (i >= 0)
+            return fail(PF_ERR_UNSUPPORTED, b->p[i].scheme != PF_RK4
+                                                ? "instance %d runs a scheme other than RK4: per-stage shape only"
+                                                : "instance %d has a z wall: per-stage shape only",
+                        i);
+    }
     return batch_apply_shape(b, shape);
 }
 
@@ -421,14 +463,13 @@ static pf_status batch_autotune_impl(pf_batch* B, int reps, int32_t* best_shape,
     const bool start_persistent = B->persistent;
     double best_t = INFINITY;
     int bs = start_shape, bp = start_persistent ? 1 : 0;
-    bool zwall = false;
-    for (int b = 0; b < B->count; ++b) zwall = zwall || (wall_mask(B->p[b]) & 4) != 0;
+    const bool stage_only = B_stage_only(B->p.data(), B->count) != 0;
     const int steps = kGraphSteps * std::max(reps, 1);
     for (int shape = 0; shape < kNumBatchShapes && ret == PF_OK; ++shape) {
         for (int pers = 0; pers < 2 && ret == PF_OK; ++pers) {
             const int slot = 2 * shape + pers;
             if (times_ms) times_ms[slot] = -1.0;
-            if (zwall && shape != kBatchStage32x8) continue;  // fused shapes take no z walls
+            if (stage_only && shape != kBatchStage32x8) continue;  // fused shapes do not apply
             ret = batch_apply_shape(B, shape);
             if (ret != PF_OK) break;
             if (B->persistent != (pers != 0)) {

@@ -65,16 +65,21 @@ def test_invalid_sizes_and_bcs(pf):
         pf.phasefield_create(p)
     assert ei.value.status == pf.PF_ERR_INVALID
     # walls validate (the single-grid solver and the batched driver run them); the batched
-    # driver declines schemes other than RK4 before any device work
+    # driver declines mixed schemes and a time-varying velocity before any device work
     pw = pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01, walls=(False, False, True))
     assert pw.bc[2] == pf.PF_BC_WALL
     r = pf.phasefield_check_params(pw, 1.0)
     assert r.dt_max_scheme > 0
     for scheme in ("euler", "rk2", "rk3"):
         with pytest.raises(pf.PhaseFieldError) as ei:
-            pf.phasefield_batch_create([pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01,
+            pf.phasefield_batch_create([pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01),
+                                        pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01,
                                                        scheme=scheme)])
         assert ei.value.status == pf.PF_ERR_UNSUPPORTED
+        assert "mixed schemes" in pf.phasefield_last_error()
+    with pytest.raises(pf.PhaseFieldError) as ei:
+        pf.phasefield_batch_create([pf.make_params((8, 8, 8), 0.1, 0.1, 1.0, 0.01, vel_mode=1)])
+    assert ei.value.status == pf.PF_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("n,scheme", [((64, 64, 1), "rk4"), ((32, 32, 32), "rk4"),
