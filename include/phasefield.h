@@ -78,9 +78,8 @@ typedef struct {
     int32_t bc[3];      /* pf_bc per axis. PF_BC_WALL: solid walls at x_a = 0 and n dx, with   */
                         /* zero total flux through the wall faces and mirror ghosts for the   */
                         /* central gradient; the face velocity stored at index 0 of a walled  */
-                        /* axis (the wall face) is ignored. Walls on x and y run on every      */
-                        /* kernel (the fused sweeps included); with a walled z axis a fused   */
-                        /* variant runs the per-stage kernel. The adjoint and the batched     */
+                        /* axis (the wall face) is ignored. Walls on any axes run on every    */
+                        /* kernel (the fused sweeps included). The adjoint and the batched    */
                         /* driver take walls too.                                             */
     int32_t dtype;      /* pf_dtype                                                            */
     int32_t scheme;     /* pf_scheme                                                           */
@@ -273,13 +272,14 @@ const char *phasefield_variant_name(int32_t dtype, int32_t variant);
 /* Time every variant on the handle's grid (using the handle's scratch and temporary buffers
  * only; caller data is untouched), store the fastest as the handle's variant and return it in
  * *best; times_ms (HOST, may be NULL) receives phasefield_variant_count(dtype) per-step times.
- * Synchronises. The choice is cached per (dtype, grid shape) for the life of the process and
- * used by later phasefield_create calls with variant -1; if the environment variable
- * PF_TUNE_CACHE names a file, the cache is also read from and written to it (one line per
- * entry: dtype nx ny nz variant-name). Without a cached choice, create picks a default from
+ * Synchronises. The choice for a periodic grid is cached per (dtype, grid shape) for the life
+ * of the process and used by later phasefield_create calls with variant -1; if the environment
+ * variable PF_TUNE_CACHE names a file, the cache is also read from and written to it (one line
+ * per entry: dtype nx ny nz variant-name). Without a cached choice, create picks a default from
  * the grid size and dtype (fused sweeps from about 104^3 cells in FP32 and 128^3 in FP64,
  * per-stage kernels below and on every grid of one plane; both with per-launch chunk
- * lengths). */
+ * lengths); a grid with walls takes the per-stage kernel in FP64 and, in FP32, the fused 32x16
+ * sweeps from about 320^3 cells (per-stage below). */
 pf_status phasefield_autotune(pf_solver *s, int32_t reps, int32_t *best, double *times_ms,
                               void *hip_stream);
 
@@ -294,8 +294,8 @@ int32_t phasefield_solver_variant(const pf_solver *s);
  * single-stage sweep per stage (Euler then one batched copy of the accumulator into phi).
  * per_instance[0].variant selects the RK4 mode by its kind (a "fused_*" variant or a per-stage
  * one); with variant -1, FP32 runs fused and FP64 per-stage. Instances may have walls on any
- * axes (each its own); a walled z axis in any instance, or a scheme other than RK4, puts the
- * batch in per-stage mode (the fused sweeps pair RK4's stages and take walls on x and y only).
+ * axes (each its own), in either mode; a scheme other than RK4 puts the batch in per-stage mode
+ * (the fused sweeps pair RK4's stages).
  * The step sequence
  * is replayed from a captured HIP graph. Results are bit-identical to running each instance
  * alone with phasefield_step.
@@ -329,8 +329,7 @@ pf_status phasefield_batch_set_persistent(pf_batch *b, int32_t persistent);
  * per-stage mode). Every shape gives bit-identical results. The tile list is rebuilt; the next
  * step re-uploads the per-instance tables and re-captures its graph (work queued on the batch's
  * last stream is synchronised first). Errors: PF_ERR_INVALID (NULL, shape outside 0..2),
- * PF_ERR_UNSUPPORTED (a fused shape while some instance has a walled z axis, or for a scheme
- * other than RK4), PF_ERR_OOM,
+ * PF_ERR_UNSUPPORTED (a fused shape for a scheme other than RK4), PF_ERR_OOM,
  * PF_ERR_DEVICE. */
 pf_status phasefield_batch_set_shape(pf_batch *b, int32_t shape);
 

@@ -74,12 +74,12 @@ extern "C" pf_status phasefield_batch_destroy(pf_batch* b)
 
 static size_t padded(size_t n) { return (n + 63) / 64 * 64; }  // keeps buffers 256-byte aligned
 
-// Whether the fused shapes apply: RK4 with no walled z axis (the fused sweeps pair RK4's
-// stages and take walls on x and y only); 0 if they do, else the first instance that stops them.
+// Whether the fused shapes apply: RK4 (the fused sweeps pair RK4's stages); 0 if they do, else
+// the first instance that stops them.
 static int B_stage_only(const pf_params* per_instance, int count)
 {
     for (int b = 0; b < count; ++b)
-        if ((wall_mask(per_instance[b]) & 4) || per_instance[b].scheme != PF_RK4) return b + 1;
+        if (per_instance[b].scheme != PF_RK4) return b + 1;
     return 0;
 }
 
@@ -420,10 +420,8 @@ extern "C" pf_status phasefield_batch_set_shape(pf_batch* b, int32_t shape)
     if (shape != kBatchStage32x8) {
         const int i = B_stage_only(b->p.data(), b->count) - 1;
         if (i >= 0)
-            return fail(PF_ERR_UNSUPPORTED, b->p[i].scheme != PF_RK4
-                                                ? "instance %d runs a scheme other than RK4: per-stage shape only"
-                                                : "instance %d has a z wall: per-stage shape only",
-                        i);
+            return fail(PF_ERR_UNSUPPORTED,
+                        "instance %d runs a scheme other than RK4: per-stage shape only", i);
     }
     return batch_apply_shape(b, shape);
 }

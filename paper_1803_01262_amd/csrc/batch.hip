@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(kBTX* kBTY) batch_stage_kernel(const StageArgs
 // Fused mode: one launch per two-stage sweep, with the register budget of the single-grid fused
 // kernel (FP32: four waves per SIMD).
 // WIDE: every instance's rows are a whole number of 16-byte pieces (16-byte plane loads).
-// WALLS: walls on x and/or y in some instance (element-wise loads, WIDE off).
+// WALLS: walls in some instance, on any axes (element-wise loads, WIDE off).
 template <typename T, int TX, int TY, bool SWEEP_B, bool WIDE, bool PERSIST, bool WALLS = false>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 batch_fused_kernel(const FusedArgs<T>* __restrict__ args, const BatchTile* __restrict__ tiles, int len)

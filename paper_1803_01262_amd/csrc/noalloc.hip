@@ -94,7 +94,7 @@ extern "C" pf_status phasefield_step_noalloc(const pf_params* p, void* phi, cons
     if (nsteps == 0) return PF_OK;
     void* base = scratch_on_current_device(&st);
     if (!base) return st;
-    const int variant = p->variant >= 0 ? p->variant : tuned_variant(p->dtype, p->n);
+    const int variant = p->variant >= 0 ? p->variant : default_variant(*p);
     hipStream_t hs = (hipStream_t)hip_stream;
     hipError_t e =
         p->dtype == PF_F32

@@ -49,6 +49,7 @@ int wall_mask(const pf_params& p);  // bit a set: walls on axis a
 pf_status check_field_ptr(const void* ptr, const char* name);
 int scheme_stage_count(int scheme);  // stage inputs an RK step keeps for its adjoint
 int tuned_variant(int dtype, const int32_t n[3]);
+int default_variant(const pf_params& p);  // variant -1: walled grids by rule, else tuned_variant
 void release_graph(StepGraph& g);
 double time_factor(const pf_params& p, double t);
 

@@ -52,14 +52,18 @@
 // WIDE (nx a multiple of 16 bytes' worth of elements), the planes of the stage input and of phi
 // are read in 16-byte pieces: groups of consecutive x-columns that start at a multiple of the
 // group size never straddle the periodic wrap, so each group is one aligned load.
-// WALLS (x and/or y walled, a.walls bits 0 and 1; a walled z axis runs on the per-stage kernel):
-// the stage input and phi are read through mirror indices, so the sharpening products of the
-// ghost cells are the exact mirror images of their partners' (the normal component flips sign)
-// and the diffusive and sharpening fluxes through a wall face vanish; the face velocity on a
-// wall face counts as zero. E1 evaluates only cells inside the domain; after it, each ghost cell
-// of the middle-stage ring takes the value of its mirror partner (one more barrier), which is
-// exactly what the per-stage kernel reads there, so the walled sweeps stay bit-identical to the
-// per-stage launches.
+// WALLS (walls on any axes, a.walls bits 0-2): the stage input and phi are read through mirror
+// indices, so the sharpening products of the ghost cells are the exact mirror images of their
+// partners' (the normal component flips sign) and the diffusive and sharpening fluxes through a
+// wall face vanish; the face velocity on a wall face counts as zero. In x and y, E1 evaluates
+// only cells inside the domain; after it, each ghost cell of the middle-stage ring takes the
+// value of its mirror partner (one more barrier), which is exactly what the per-stage kernel
+// reads there. In z, E1 also evaluates the ghost planes, with U and V mirrored and W on a face
+// beyond the wall the partner face's with its sign flipped: the plane next to a wall then comes
+// out as its partner bit for bit (the two z-advection terms swap places with one of them zero),
+// and the sharpening product of E2 on that ghost plane is set to the negated partner's (the
+// plane two beyond, whose terms do not swap exactly, feeds nothing else that is stored). So the
+// walled sweeps stay bit-identical to the per-stage launches.
 #pragma once
 
 #include <type_traits>
@@ -135,9 +139,28 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     const bool active = (i0 + tx < nx) && (j0 + ty < ny);
     const T inv_2dx = a.inv_2dx, d2 = a.delta2, hg = a.hg, ge = a.ge;
     // index maps of the stage input and phi: periodic wrap, or the mirror across walls
-    const bool wx = WALLS && (a.walls & 1), wy = WALLS && (a.walls & 2);
+    const bool wx = WALLS && (a.walls & 1), wy = WALLS && (a.walls & 2), wz = WALLS && (a.walls & 4);
     auto mapx = [&](int v) { return WALLS && wx ? reflectn(v, nx) : wrapn(v, nx); };
     auto mapy = [&](int v) { return WALLS && wy ? reflectn(v, ny) : wrapn(v, ny); };
+    auto mapz = [&](int v) { return WALLS && wz ? reflectz(v, nz) : wrapz(v, nz); };
+    // W on face p (between planes p-1 and p): the plane to read and the sign. Along a walled z
+    // axis (seen as a periodic one of 2 nz planes) the wall faces 0 and nz carry no velocity
+    // (sign 0) and a face beyond a wall is its mirror partner with the normal component flipped.
+    auto wface = [&](int p, int& kw) -> int {
+        if (!(WALLS && wz)) {
+            kw = wrapz(p, nz);
+            return 1;
+        }
+        int m = p % (2 * nz);
+        if (m < 0) m += 2 * nz;
+        kw = m < nz ? m : 2 * nz - m;
+        if (m == 0 || m == nz) {
+            kw = 0;
+            return 0;
+        }
+        return m < nz ? 1 : -1;
+    };
+    auto wval = [](int sg, T v) -> T { return sg == 0 ? T(0) : (sg < 0 ? -v : v); };
 
     // ---- E1 cell slots: slot 0 = own cell, slot 1 = a MID ring cell (tid < NRING)
     int e_lx[2], e_ly[2];
@@ -288,7 +311,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             *dst = v;
     };
     auto fetch_in = [&](int kk) {
-        const int kw = wrapz(kk, nz);
+        const int kw = mapz(kk);
 #pragma unroll
         for (int s = 0; s < NLI; ++s)
             if (li_pos[s] >= 0) pre_in[s] = load_piece(fy, kw, li_off[s]);
@@ -299,14 +322,16 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             if (li_pos[s] >= 0) put_piece(s_in + slot * INS + li_pos[s], pre_in[s]);
     };
     auto fetch_b = [&](int kk) {
-        const int kw = wrapz(kk, nz);
+        const int kw = mapz(kk);
 #pragma unroll
         for (int s = 0; s < NLB; ++s)
             if (lb_pos[s] >= 0) pre_b[s] = load_piece(fphi, kw, lb_off[s]);
     };
     piece_t pre_v[NLV > 0 ? NLV : 1];
     auto fetch_vel = [&](int p) {  // U, V at plane p, W at plane p+1
-        const int kw = wrapz(p, nz), kw1 = wrapz(p + 1, nz);
+        const int kw = mapz(p);
+        int kw1;
+        const int sg1 = wface(p + 1, kw1);
 #pragma unroll
         for (int s = 0; s < NLV; ++s) {
             const int e = tid + s * NT;
@@ -314,8 +339,12 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 pre_v[s] = load_piece(fU, kw, lv_off[s]);
             else if (e < NGU + NGV)
                 pre_v[s] = load_piece(fV, kw, lv_off[s]);
-            else if (e < NGVEL)
-                pre_v[s] = load_piece(fW, kw1, lv_off[s]);
+            else if (e < NGVEL) {
+                if constexpr (WALLS)
+                    pre_v[s] = wval(sg1, load_piece(fW, kw1, lv_off[s]));
+                else
+                    pre_v[s] = load_piece(fW, kw1, lv_off[s]);
+            }
         }
     };
     auto commit_vel = [&](int slot) {
@@ -403,8 +432,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             if (STAGE) fetch_vel(t + 3);
             if (SWEEP_B) fetch_b(t + 3);
         }
-        // E1 operands from global memory (plane p = t+2), issued before the barrier
-        const int pw = wrapz(t + 2, nz), pw1 = wrapz(t + 3, nz);
+        // E1 operands from global memory (plane p = t+2), issued before the barrier; the
+        // accumulator is read at the wrapped plane (it is used on the domain's planes only)
+        const int pw = mapz(t + 2), pa = wrapz(t + 2, nz), pa1 = wrapz(t + 3, nz);
+        int pw1;
+        const int sgw = wface(t + 3, pw1);
         T eu0[2], eu1[2], ev0[2], ev1[2], ew1[2], eacc = T(0);
         if (!STAGE) {
 #pragma unroll
@@ -414,15 +446,18 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
                 eu1[s] = fU.load(pw, e_colx[s]);
                 ev0[s] = fV.load(pw, e_col[s]);
                 ev1[s] = fV.load(pw, e_coly[s]);
-                ew1[s] = fW.load(pw1, e_col[s]);
+                if constexpr (WALLS)
+                    ew1[s] = wval(sgw, fW.load(pw1, e_col[s]));
+                else
+                    ew1[s] = fW.load(pw1, e_col[s]);
             }
         }
         if (SWEEP_B) {
             if constexpr (LAG) {  // loaded one iteration ahead
                 eacc = eacc_pre;
-                eacc_pre = facc.load(pw1, e_col[0]);
+                eacc_pre = facc.load(pa1, e_col[0]);
             } else {
-                eacc = facc.load(pw, e_col[0]);
+                eacc = facc.load(pa, e_col[0]);
             }
         }
         // input plane t+4, phi (and staged velocities) of plane t+2 visible (LAG: since the
@@ -572,7 +607,11 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             const T fac = sharpen_factor(pc1, gx, gy, gz, d2, hg);
             s_q2x[q2new * Q2XS + (tx + 1) + ty * Q2XW] = fac * gx;
             s_q2y[q2new * Q2YS + tx + (ty + 1) * TX] = fac * gy;
-            const T q2zn = fac * gz;
+            T q2zn = fac * gz;
+            if constexpr (WALLS) {  // walled z: the ghost planes next to the walls mirror exactly
+                if (wz && to + 1 == 0) q2z = -q2zn;   // plane -1, from plane 0
+                if (wz && to + 1 == nz) q2zn = -q2z;  // plane nz, from plane nz-1
+            }
             if (has_h2) {
                 const T hgx = grad1(M1[h_om + 1], M1[h_om - 1], inv_2dx);
                 const T hgy = grad1(M1[h_om + MW], M1[h_om - MW], inv_2dx);

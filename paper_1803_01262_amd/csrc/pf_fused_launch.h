@@ -62,7 +62,7 @@ hipError_t launch_fused(const FusedArgs<T>& a, bool sweep_b, hipStream_t st)
     const bool wide = a.nx % (16 / (int)sizeof(T)) == 0;
     const bool big = FORCE_BIG || field_needs_big(a.nx, a.ny, a.nz, sizeof(T));
     if (a.walls) {
-        // walled x/y: one form (mirror reads element by element, single-descriptor addressing:
+        // walled axes: one form (mirror reads element by element, single-descriptor addressing:
         // arrays below 4 GiB, also for the variants that force the large-array form)
         if (field_needs_big(a.nx, a.ny, a.nz, sizeof(T))) return hipErrorInvalidValue;
         int kzw = KZ;

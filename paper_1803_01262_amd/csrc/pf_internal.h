@@ -138,7 +138,7 @@ struct FusedArgs {
     T inv_2dx, ge, hg, delta2;  // as in StageArgs
     T nhs1, nhs2;               // -s / (2 dx) at the stage time of E1 and of E2
     T c_mid, c_acc1, c_y2, c_acc2;
-    int walls;                  // bit 0: x walled, bit 1: y walled (z walls: per-stage kernel)
+    int walls;                  // bit a: axis a walled
 };
 
 // An array of nx*ny*nz elements of `es` bytes needs the per-plane buffer descriptors of the

@@ -352,8 +352,7 @@ def test_batch_autotune(lib, dtype, zwall):
     """The batch autotuner times every tile shape in both launch forms on private fields, leaves
     the batch in the fastest combination (the minimum of the reported times) and the caller's
     fields untouched; the tuned batch then gives every instance its single solve bit for bit. A
-    walled z axis leaves only the per-stage shape (the fused shapes are reported as n/a and
-    refused by set_shape)."""
+    walled z axis keeps every shape (the fused sweeps take walls on every axis)."""
     pf = lib
     sizes = [(32, 32, 32), (48, 40, 24), (64, 64, 8), (17, 9, 33)]
     cases = _batch_instances(sizes, seed=41)
@@ -369,14 +368,8 @@ def test_batch_autotune(lib, dtype, zwall):
     shape, persistent, times = bs.autotune(reps=1, stream=st)
     print(dtype, "zwall" if zwall else "", "autotune", shape, persistent, times, flush=True)
     assert all(torch.equal(b[0], k) for b, k in zip(bt, keep))  # caller data untouched
-    expect = 2 if zwall else 6
-    assert len(times) == expect and all(t > 0 for t in times.values())
+    assert len(times) == 6 and all(t > 0 for t in times.values())
     assert times[(shape, persistent)] == min(times.values())
-    if zwall:
-        assert shape == "stage_32x8"
-        with pytest.raises(pf.PhaseFieldError) as ei:
-            bs.set_shape("fused_32x16")
-        assert ei.value.status == pf.PF_ERR_UNSUPPORTED
     with torch.cuda.stream(st):
         bs.step(*zip(*bt), nsteps=11, stream=st)
     st.synchronize()
@@ -425,12 +418,13 @@ def test_batch_matches_oracle(lib, dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("mode,zwall", [("default", False), ("fused", False), ("per-stage", False),
-                                        ("fused-persistent", False), ("default", True)])
+                                        ("fused-persistent", False), ("default", True),
+                                        ("fused", True), ("per-stage", True)])
 def test_batch_with_walls(lib, dtype, mode, zwall):
     """Instances with walls on x, on x and y, on y, and periodic ones, in one batch: every
     instance equals its own single solve bit for bit, and two of them match the oracle with the
-    same walls (FP64 1e-12, FP32 1e-5 against the FP32-storage mode). A walled z axis in any
-    instance puts the batch in per-stage mode."""
+    same walls (FP64 1e-12, FP32 1e-5 against the FP32-storage mode); with an instance walled on
+    all three axes as well, in each mode."""
     pf = lib
     sizes = [(32, 32, 32), (48, 40, 24), (17, 9, 33), (40, 24, 30)]
     walls = [(True, False, False), (True, True, False), (False, False, False), (False, True, False)]

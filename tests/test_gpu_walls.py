@@ -1,9 +1,10 @@
 """GPU parity of the solid-wall boundaries (through the C ABI).
 
-Walls on x and y run on every kernel: per-stage (tiled, one-plane, one-thread-per-cell) and the
-fused two-stage sweeps (mirror reads, ghost cells of the middle stage copied from their mirror
-partners); a walled z axis runs on the per-stage kernels (fused variants fall back to the
-per-stage default). Bars as for the periodic grids: FP64 <= 1e-12 relative L-inf against the
+Walls on any axes run on every kernel: per-stage (tiled, one-plane, one-thread-per-cell) and the
+fused two-stage sweeps (mirror reads; in x and y the ghost cells of the middle stage copied from
+their mirror partners, in z the ghost planes evaluated from mirrored inputs and velocities). A
+handle with walls and variant -1 takes the walled default (per-stage in FP64, fused 32x16 in
+FP32 from about 320^3 cells). Bars as for the periodic grids: FP64 <= 1e-12 relative L-inf against the
 oracle with the same walls, FP32 <= 1e-5 against its FP32-storage mode, every variant bitwise
 equal to every other. The face velocity on the wall faces is random (it must be ignored).
 """
@@ -162,3 +163,25 @@ def test_walls_adjoint_matches_oracle(lib, scheme, walls, shape):
     for k, (got, want) in enumerate(zip([L] + grads, ref)):
         err = rel_linf(got.cpu().numpy().astype(np.float64), want)
         assert err <= 1e-3, (k, err)
+
+
+@pytest.mark.parametrize("dtype,shape,walls,want", [
+    ("f64", (20, 20, 20), (False, False, True), "tiled_32x4"),
+    ("f64", (200, 200, 192), (True, False, False), "tiled_64x8"),
+    ("f32", (40, 36, 128), (False, True, False), "tiled_64x8"),
+    ("f32", (40, 36, 96), (False, True, False), "tiled_32x4"),
+    ("f32", (320, 320, 336), (True, True, True), "fused_32x16"),
+    ("f32", (320, 320, 336), (False, False, False), None)])
+def test_walled_default_variant(lib, dtype, shape, walls, want):
+    """variant -1 on a grid with walls takes the walled default (the tuning cache is for periodic
+    grids); a periodic grid keeps the periodic default."""
+    pf = lib
+    nz, ny, nx = shape
+    s = pf.Solver((nx, ny, nz), 1.0 / nx, 1.0 / nx, 1.0, 0.1 / nx, dtype=dtype, walls=walls)
+    name = s.variant_name
+    s.close()
+    print(dtype, shape, walls, name, flush=True)
+    if want is None:
+        assert name.startswith("fused_")
+    else:
+        assert name == want
