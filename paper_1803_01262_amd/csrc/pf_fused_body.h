@@ -151,6 +151,18 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             kw = wrapz(p, nz);
             return 1;
         }
+        if (p > 0 && p < nz) {
+            kw = p;
+            return 1;
+        }
+        if (p == 0 || p == nz) {
+            kw = 0;
+            return 0;
+        }
+        if (nz >= 16) {  // the march reaches at most 10 planes beyond the domain
+            kw = p < 0 ? -p : 2 * nz - p;
+            return -1;
+        }
         int m = p % (2 * nz);
         if (m < 0) m += 2 * nz;
         kw = m < nz ? m : 2 * nz - m;
@@ -191,6 +203,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
     // WALLS: per slot, bit 0/1: its low/high x-face is a wall face, bit 2/3 likewise in y; bit 4:
     // the cell is a ghost (outside the domain along a walled axis)
     int e_wall[2] = {0, 0};
+    int e_gsrc[2] = {0, 0};
     for (int s = 0; s < 2; ++s) {
         const int gx = wrapn(i0 - 2 + e_lx[s], nx), gy = wrapn(j0 - 2 + e_ly[s], ny);
         e_col[s] = (unsigned)(gy * nx + gx) * ES;
@@ -201,6 +214,9 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             e_wall[s] = (wx && ux == 0 ? 1 : 0) | (wx && ux == nx - 1 ? 2 : 0) |
                         (wy && uy == 0 ? 4 : 0) | (wy && uy == ny - 1 ? 8 : 0) |
                         ((wx && (ux < 0 || ux >= nx)) || (wy && (uy < 0 || uy >= ny)) ? 16 : 0);
+            // a ghost slot's mirror partner in the middle-stage ring (fixed along the march)
+            const int mx = wx ? reflectn(ux, nx) : ux, my = wy ? reflectn(uy, ny) : uy;
+            e_gsrc[s] = (mx - (i0 - 2)) + (my - (j0 - 2)) * MW;
         }
     }
     // ---- q1-only cell (x-outer: Q1X columns 0 and TX+5; y-outer: Q1Y rows 0 and TY+5)
@@ -574,16 +590,14 @@ __device__ __forceinline__ void fused_body(const FusedArgs<T>& a, int ti, int tj
             e_qz[s] = qzn[s];
             e_w0[s] = ew1[s];
         }
-        if constexpr (WALLS) {
+        if constexpr (WALLS) if (wx || wy) {
             __syncthreads();  // every E1 value of plane t+2 is in YM
             // ghost cells of the ring take their mirror partner's value
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 if (s == 1 && !has_ring) continue;
                 if (!(e_wall[s] & 16)) continue;
-                const int ux = i0 - 2 + e_lx[s], uy = j0 - 2 + e_ly[s];
-                const int mx = wx ? reflectn(ux, nx) : ux, my = wy ? reflectn(uy, ny) : uy;
-                YM[e_lx[s] + e_ly[s] * MW] = YM[(mx - (i0 - 2)) + (my - (j0 - 2)) * MW];
+                YM[e_lx[s] + e_ly[s] * MW] = YM[e_gsrc[s]];
             }
         }
         if constexpr (!LAG) __syncthreads();  // ya at plane t+2 visible
