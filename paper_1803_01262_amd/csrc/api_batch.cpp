@@ -237,7 +237,7 @@ static pf_status upload_tables(pf_batch* B, void* const* phi, const void* const*
         } else {
             const double dt = p.dt;
             constexpr double g1 = 8.0 / 15.0, g2 = 5.0 / 12.0, g3 = 0.75, z2 = -17.0 / 60.0;
-            StageArgs<T> sa[4];
+            StageArgs<T> sa[4] = {};
             if (p.scheme == PF_RK4) {
                 sa[0] = make_stage<T>(p, 1.0, ph, ph, ph, ya, acc, 0.5 * dt, dt / 6.0, U, V, W);
                 sa[1] = make_stage<T>(p, 1.0, ya, ph, acc, yb, acc, 0.5 * dt, dt / 3.0, U, V, W);
