@@ -279,7 +279,7 @@ const char *phasefield_variant_name(int32_t dtype, int32_t variant);
  * the grid size and dtype (fused sweeps from about 104^3 cells in FP32 and 128^3 in FP64,
  * per-stage kernels below and on every grid of one plane; both with per-launch chunk
  * lengths); a grid with walls takes the per-stage kernel in FP64 and, in FP32, the fused 32x16
- * sweeps from about 320^3 cells (per-stage below). */
+ * sweeps from about 144^3 cells (per-stage below). */
 pf_status phasefield_autotune(pf_solver *s, int32_t reps, int32_t *best, double *times_ms,
                               void *hip_stream);
 

@@ -186,17 +186,17 @@ int pf::tuned_variant(int dtype, const int32_t n[3])
 }
 
 // Default variant of a grid with walls (the tuning cache is kept for periodic grids). Walls cost
-// the fused sweeps their 16-byte plane loads and one barrier per plane (walls on x and z, per
-// step: FP64 512^3 fused_32x16 7.08 ms against tiled_64x8 6.09, 128^3 0.162 against 0.105 on
-// tiled_32x4; FP32 512^3 fused_32x16 2.78 against fused_64x8 3.04 and tiled_64x8 3.29, 384^3
-// 1.42 against 1.46, 192^3 0.178 against 0.166): FP64 takes the per-stage kernel, FP32 the
-// fused 32x16 sweeps from 320^3 cells and per-stage 64x8 tiles below (32x4 where 64-wide tiles
-// pad more columns).
+// the fused sweeps their 16-byte plane loads and scalar registers (walls on x and z, per step:
+// FP64 512^3 fused_32x16 7.08 ms against tiled_64x8 6.09, 128^3 0.162 against 0.105 on
+// tiled_32x4; FP32 512^3 fused_32x16 2.78 against fused_64x8 3.04 and tiled_64x8 3.29, 256^3
+// 0.352 against 0.436, 160^3 0.106 against 0.124, 128^3 0.082 against 0.077 on tiled_32x4):
+// FP64 takes the per-stage kernel, FP32 the fused 32x16 sweeps from 144^3 cells and per-stage
+// 64x8 tiles below (32x4 where 64-wide tiles pad more columns).
 static int walled_default_variant(int dtype, const int32_t n[3])
 {
     if (dtype == PF_F64) return per_stage_variant(n[0], n[1], n[2], dtype);
     const long long cells = (long long)n[0] * n[1] * n[2];
-    if (cells >= 320LL * 320 * 320) return stage_variant_index(dtype, "fused_32x16");
+    if (cells >= 144LL * 144 * 144) return stage_variant_index(dtype, "fused_32x16");
     const bool x64 = (n[0] + 63) / 64 * 64 <= (n[0] + 31) / 32 * 32;
     return stage_variant_index(dtype, x64 ? "tiled_64x8" : "tiled_32x4");
 }

@@ -4,7 +4,7 @@ Walls on any axes run on every kernel: per-stage (tiled, one-plane, one-thread-p
 fused two-stage sweeps (mirror reads; in x and y the ghost cells of the middle stage copied from
 their mirror partners, in z the ghost planes evaluated from mirrored inputs and velocities). A
 handle with walls and variant -1 takes the walled default (per-stage in FP64, fused 32x16 in
-FP32 from about 320^3 cells). Bars as for the periodic grids: FP64 <= 1e-12 relative L-inf against the
+FP32 from about 144^3 cells). Bars as for the periodic grids: FP64 <= 1e-12 relative L-inf against the
 oracle with the same walls, FP32 <= 1e-5 against its FP32-storage mode, every variant bitwise
 equal to every other. The face velocity on the wall faces is random (it must be ignored).
 """
@@ -170,8 +170,8 @@ def test_walls_adjoint_matches_oracle(lib, scheme, walls, shape):
     ("f64", (200, 200, 192), (True, False, False), "tiled_64x8"),
     ("f32", (40, 36, 128), (False, True, False), "tiled_64x8"),
     ("f32", (40, 36, 96), (False, True, False), "tiled_32x4"),
-    ("f32", (320, 320, 336), (True, True, True), "fused_32x16"),
-    ("f32", (320, 320, 336), (False, False, False), None)])
+    ("f32", (150, 150, 160), (True, True, True), "fused_32x16"),
+    ("f32", (150, 150, 160), (False, False, False), None)])
 def test_walled_default_variant(lib, dtype, shape, walls, want):
     """variant -1 on a grid with walls takes the walled default (the tuning cache is for periodic
     grids); a periodic grid keeps the periodic default."""
